@@ -1,0 +1,112 @@
+/*
+ * burr_oracle.h - plain sequential CPU oracle for Bumped Ribbon Retrieval
+ * (BuRR) with the parallel scheme of bumping keys at range boundaries.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library links, loads or
+ * calls this code: only tests/, the smoke check and the benchmark's CPU
+ * baseline leg may use it. It shares no code, header, table or constant
+ * generator with the HIP path.
+ *
+ * Source: Becht, Lehmann, Sanders, "Brief Announcement: Parallel Construction
+ * of Bumped Ribbon Retrieval" (arXiv 2411.12365). The paper defines the method
+ * at concept level (Sec. 2 "Preliminaries", Sec. 3 "Parallelization"); every
+ * detail it leaves open is fixed by the readings listed in each function's
+ * comment in burr_oracle.c.
+ *
+ * Parity pins: thresholds, solution words and bump sets are pinned by dense
+ * GF(2) brute force on tiny inputs, the query invariant, range independence
+ * and closed-form bounds (tests/test_oracle_*.py). The hash is a reading of
+ * ours (the paper does not define one): parity unpinned against the paper;
+ * its structure is pinned against the published MurmurHash3 finalizer and
+ * Lemire's multiply-shift range reduction by independent computations.
+ */
+#ifndef BURR_ORACLE_H
+#define BURR_ORACLE_H
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  REF_OK = 0,
+  REF_E_INVALID = -1,
+  REF_E_NOMEM = -2,
+  REF_E_UNSOLVABLE = -3,
+};
+
+typedef struct ref_params {
+  uint32_t bucket;          /* b: slots per bucket, a multiple of 64 */
+  uint32_t load_num;        /* BuRR layer slots per key = load_num/load_den */
+  uint32_t load_den;
+  uint32_t final_num;       /* final plain ribbon slots per key */
+  uint32_t final_den;
+  uint32_t layers;          /* BuRR layers before the final plain layer */
+  uint32_t t_lo;            /* middle 2-bit threshold values, 0<t_lo<t_hi<b */
+  uint32_t t_hi;
+  uint32_t ranges;          /* maximum number of independent ranges per layer */
+  uint32_t minbpt;          /* minimum buckets per range */
+  uint32_t final_attempts;  /* scale-up attempts of the final layer */
+  uint32_t filter_mode;     /* 1: stored value is an r-bit key fingerprint */
+  uint64_t seed;
+} ref_params;
+
+/* per-layer statistics, index 0..layers_built-1; the final layer is
+ * reported by ref_final_info */
+typedef struct ref_layer_info {
+  uint64_t n;          /* keys entering the layer */
+  uint64_t m;          /* slots */
+  uint64_t nbuckets;   /* m / b */
+  uint64_t nranges;    /* independent ranges */
+  uint64_t bumped;     /* keys sent to the next layer */
+  uint64_t forced;     /* keys bumped because they cross a range boundary */
+  uint64_t pivots;     /* rows placed */
+  uint64_t redundant;  /* equations that reduced to 0 = 0 */
+  uint64_t steps;      /* XOR-and-shift elimination steps (statistics) */
+} ref_layer_info;
+
+typedef struct ref_final_info {
+  uint64_t n;
+  uint64_t m;
+  uint64_t attempt;    /* index of the successful scale-up attempt */
+  uint64_t steps;
+} ref_final_info;
+
+typedef struct ref_burr ref_burr;
+
+/* hash primitives, exported so tests can check them against independent
+ * computations */
+uint64_t ref_fmix64(uint64_t k);
+uint64_t ref_fastrange(uint64_t h, uint64_t n);
+void ref_hash(uint64_t key, uint32_t layer, uint64_t m, uint64_t seed,
+              uint64_t* start, uint64_t* coeff);
+uint32_t ref_fingerprint(uint64_t key, uint32_t r, uint64_t seed);
+
+/* Build. keys: n host u64; values: host u8 (r<=8) / u16 (r<=16) / u32
+ * (r<=32), ignored in filter mode. On success *out owns everything. */
+int ref_build(const uint64_t* keys, const void* values, uint64_t n, uint32_t r,
+              const ref_params* p, ref_burr** out);
+void ref_free(ref_burr* h);
+
+/* Query n keys; out has the value width of r (u8/u16/u32). */
+int ref_query(const ref_burr* h, const uint64_t* keys, uint64_t n, void* out);
+
+/* Canonical little-endian serialisation; *needed receives the size. */
+int ref_export(const ref_burr* h, uint8_t* buf, uint64_t cap, uint64_t* needed);
+
+uint32_t ref_layers_built(const ref_burr* h);
+int ref_get_layer_info(const ref_burr* h, uint32_t layer, ref_layer_info* out);
+int ref_get_final_info(const ref_burr* h, ref_final_info* out);
+/* Keys entering layer `layer` (layer == layers_built: the final layer), in
+ * the oracle's own order; copy at most cap keys, return the count. */
+uint64_t ref_layer_keys(const ref_burr* h, uint32_t layer, uint64_t* out, uint64_t cap);
+/* 2-bit threshold codes of layer `layer`, one byte per bucket. */
+uint64_t ref_layer_codes(const ref_burr* h, uint32_t layer, uint8_t* out, uint64_t cap);
+/* Solution Z of layer `layer` (layer == layers_built: final), one u32 per slot. */
+uint64_t ref_layer_solution(const ref_burr* h, uint32_t layer, uint32_t* out, uint64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
