@@ -1,0 +1,153 @@
+/*
+ * burr.h - C ABI of the MI355X Bumped Ribbon Retrieval (BuRR) library.
+ *
+ * A retrieval structure stores a static function f: S -> {0,1}^r for a set S
+ * of distinct 64-bit keys; a query of x in S returns f(x), a query of any
+ * other key returns an arbitrary r-bit value (Becht, Lehmann, Sanders,
+ * arXiv 2411.12365, Sec. 1). Construction solves a banded GF(2) system in
+ * layers: keys that cannot be placed, or whose row would cross the end of an
+ * independently solved slot range, are bumped to the next layer (Sec. 2
+ * "bumping", Sec. 3 "Bumping"); the last layer is a plain ribbon scaled up
+ * until it solves (Sec. 3).
+ *
+ * Conventions for every entry point:
+ *   - pointers named keys/values/out are DEVICE pointers (HIP global memory)
+ *     unless the name says host_; they stay owned by the caller and must
+ *     remain valid until the call returns (or, for the *_async calls, until
+ *     the given stream has passed the call);
+ *   - keys are u64; values and query outputs are u8 for r <= 8, u16 for
+ *     r <= 16, u32 for r <= 32 (only the low r bits are used);
+ *   - return codes: BURR_OK (0) or a negative BURR_E_* code; functions that
+ *     return a handle return NULL on error. burr_last_error() gives the code
+ *     of the calling thread's last failed call.
+ *   - the library never calls PyTorch; it allocates device memory through
+ *     the allocator callbacks in burr_params, or through HIP's stream-ordered
+ *     allocator when they are NULL.
+ */
+#ifndef BURR_H
+#define BURR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BURR_ABI_VERSION 1u
+
+enum {
+  BURR_OK = 0,
+  BURR_E_INVALID = -1,    /* bad argument or parameter */
+  BURR_E_NOMEM = -2,      /* device or host allocation failed */
+  BURR_E_UNSOLVABLE = -3, /* final layer failed every scale-up attempt
+                             (in practice: one key given two values) */
+  BURR_E_DEVICE = -4,     /* a HIP call failed */
+  BURR_E_BUDGET = -5      /* request larger than a server's memory budget */
+};
+
+/* Keep the device copy of every layer's input keys (debugging, parity tests);
+ * read them with burr_debug_layer_keys. */
+#define BURR_FLAG_KEEP_LAYER_KEYS 1u
+
+typedef void* (*burr_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*burr_free_fn)(void* ptr, void* stream, void* ctx);
+
+/* Construction parameters. Every field that changes the structure is stored
+ * in the handle and in its export. */
+typedef struct burr_params {
+  uint32_t abi_version;    /* BURR_ABI_VERSION */
+  uint32_t bucket;         /* b, slots per bucket; the HIP path supports 64 */
+  uint32_t load_num;       /* BuRR layer: m = b*ceil(n*load_num/(load_den*b)) */
+  uint32_t load_den;       /*   (overloaded table, Sec. 2; default 97/100) */
+  uint32_t final_num;      /* final plain ribbon slots per key, >= 1 */
+  uint32_t final_den;      /*   (default 110/100; +1/10 per failed attempt) */
+  uint32_t layers;         /* BuRR layers before the final one (default 3) */
+  uint32_t t_lo;           /* middle 2-bit threshold values, 0<t_lo<t_hi<b */
+  uint32_t t_hi;           /*   (Sec. 2 "2-bit" thresholds; default 16, 32) */
+  uint32_t ranges;         /* max independent ranges per layer (Sec. 3) */
+  uint32_t minbpt;         /* min buckets per range (Sec. 3 "minbpt") */
+  uint32_t final_attempts; /* scale-up attempts of the final layer */
+  uint32_t filter_mode;    /* 1: values ignored, store an r-bit fingerprint */
+  uint32_t flags;          /* BURR_FLAG_* */
+  uint64_t seed;           /* hash seed */
+  void* stream;            /* hipStream_t for all work; NULL = null stream */
+  burr_alloc_fn alloc;     /* device workspace allocator; NULL = HIP pool */
+  burr_free_fn free;
+  void* alloc_ctx;
+} burr_params;
+
+typedef struct burr_handle burr_handle;
+
+typedef struct burr_layer_stats {
+  uint64_t n;        /* keys entering the layer */
+  uint64_t m;        /* slots */
+  uint64_t nbuckets; /* m / b */
+  uint64_t nranges;  /* independently solved ranges */
+  uint64_t bumped;   /* keys passed to the next layer */
+} burr_layer_stats;
+
+typedef struct burr_stats {
+  uint64_t n;                     /* keys stored */
+  uint32_t r;                     /* value bits */
+  uint32_t layers_built;          /* BuRR layers with keys */
+  burr_layer_stats layer[32];
+  uint64_t final_n, final_m, final_attempt;
+  uint64_t table_bytes;           /* device bytes of codes + solution words */
+  double ms_sort, ms_solve, ms_final, ms_total; /* device time of the build */
+} burr_stats;
+
+/* Fills *p with the defaults above (one range, seed 0, no callbacks). */
+void burr_default_params(burr_params* p);
+
+/* Builds a structure for n keys (device u64[n]) with r-bit values (device
+ * array, see conventions; may be NULL in filter mode). Keys must be
+ * distinct; a key repeated with the same value is harmless. The build runs on
+ * p->stream and returns when it is complete (it reads one counter per layer
+ * back to the host). Returns NULL on error (see burr_last_error). The handle
+ * owns one device allocation per layer; free it with burr_free.
+ * Method: Sec. 2 (ribbon insertion, 2-bit thresholds, overloading) and
+ * Sec. 3 (ranges made independent by bumping keys at range ends, minimum
+ * buckets per range, sequential final layer). */
+burr_handle* burr_build(const uint64_t* keys, const void* values, uint64_t n, uint32_t r,
+                        const burr_params* p);
+
+/* Queries n keys (device u64[n]) into out (device, value width of r): for
+ * each layer, skip it if the key's offset is below its bucket's threshold,
+ * else return the parity of the key's row AND the table window, per column
+ * (Sec. 2, Fig. 1a). Enqueued on `stream` (NULL: the build's stream) and
+ * returns without waiting. */
+int burr_query(const burr_handle* h, const uint64_t* keys, uint64_t n, void* out, void* stream);
+
+/* Filter mode only: out[i] = 1 if the stored value of keys[i] equals its
+ * fingerprint (always 1 for stored keys; 2^-r false positive rate). */
+int burr_contains(const burr_handle* h, const uint64_t* keys, uint64_t n, uint8_t* out,
+                  void* stream);
+
+void burr_free(burr_handle* h);
+
+int burr_get_stats(const burr_handle* h, burr_stats* s);
+
+/* Canonical little-endian serialisation (layout in the library's export
+ * code): header, then per BuRR layer n, m, ranges, packed 2-bit codes and
+ * column-interleaved solution words, then the final layer. Copies to host
+ * memory; *needed receives the size (pass host_buf = NULL to query it). */
+int burr_export(const burr_handle* h, void* host_buf, size_t cap, size_t* needed);
+
+/* Rebuilds a handle from export bytes (host memory); p supplies only the
+ * stream and allocator (may be NULL). */
+burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* p);
+
+/* With BURR_FLAG_KEEP_LAYER_KEYS: copies up to cap keys that entered layer
+ * `layer` (layers_built = the final layer) to host memory, in an unspecified
+ * order; returns their number (or a negative code). */
+int64_t burr_debug_layer_keys(const burr_handle* h, uint32_t layer, uint64_t* host_out,
+                              uint64_t cap);
+
+int burr_last_error(void);
+const char* burr_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BURR_H */

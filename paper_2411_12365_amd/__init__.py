@@ -1,0 +1,281 @@
+"""MI355X Bumped Ribbon Retrieval (BuRR) - Python binding of libburr.so.
+
+Argument marshalling only: every step of construction and query runs in the
+HIP kernels behind the C ABI declared in include/burr.h. Tensors must live
+on the GPU; PyTorch supplies device memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import asdict, dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libburr.so")
+
+BURR_OK = 0
+BURR_E_INVALID = -1
+BURR_E_NOMEM = -2
+BURR_E_UNSOLVABLE = -3
+BURR_E_DEVICE = -4
+BURR_E_BUDGET = -5
+BURR_FLAG_KEEP_LAYER_KEYS = 1
+ABI_VERSION = 1
+
+_EXPORTS = ("burr_default_params", "burr_build", "burr_query", "burr_contains", "burr_free",
+            "burr_get_stats", "burr_export", "burr_import", "burr_debug_layer_keys",
+            "burr_last_error", "burr_error_string")
+
+
+class BurrError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        msg = _lib_error_string(code)
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+        self.code = code
+
+
+class _CParams(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_uint32), ("bucket", ctypes.c_uint32),
+        ("load_num", ctypes.c_uint32), ("load_den", ctypes.c_uint32),
+        ("final_num", ctypes.c_uint32), ("final_den", ctypes.c_uint32),
+        ("layers", ctypes.c_uint32), ("t_lo", ctypes.c_uint32), ("t_hi", ctypes.c_uint32),
+        ("ranges", ctypes.c_uint32), ("minbpt", ctypes.c_uint32),
+        ("final_attempts", ctypes.c_uint32), ("filter_mode", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p),
+        ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p), ("alloc_ctx", ctypes.c_void_p),
+    ]
+
+
+class _CLayerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("n", "m", "nbuckets", "nranges", "bumped")]
+
+
+class _CStats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint64), ("r", ctypes.c_uint32), ("layers_built", ctypes.c_uint32),
+        ("layer", _CLayerStats * 32), ("final_n", ctypes.c_uint64), ("final_m", ctypes.c_uint64),
+        ("final_attempt", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
+        ("ms_sort", ctypes.c_double), ("ms_solve", ctypes.c_double),
+        ("ms_final", ctypes.c_double), ("ms_total", ctypes.c_double),
+    ]
+
+
+@dataclass
+class Params:
+    """burr_params without the stream/allocator fields."""
+    bucket: int = 64
+    load_num: int = 97
+    load_den: int = 100
+    final_num: int = 110
+    final_den: int = 100
+    layers: int = 3
+    t_lo: int = 16
+    t_hi: int = 32
+    ranges: int = 1
+    minbpt: int = 16
+    final_attempts: int = 16
+    filter_mode: int = 0
+    flags: int = 0
+    seed: int = 0
+
+    def c(self, stream: int | None = None) -> _CParams:
+        return _CParams(abi_version=ABI_VERSION, stream=stream, alloc=None, free=None,
+                        alloc_ctx=None, **asdict(self))
+
+
+_lib = None
+
+
+def lib():
+    """Load libburr.so; raises if it has not been built (no CPU fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() or "
+                               "python paper_2411_12365_amd/build_lib.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+        L.burr_default_params.argtypes = [ctypes.POINTER(_CParams)]
+        L.burr_default_params.restype = None
+        L.burr_build.argtypes = [vp, vp, u64, u32, ctypes.POINTER(_CParams)]
+        L.burr_build.restype = vp
+        L.burr_query.argtypes = [vp, vp, u64, vp, vp]
+        L.burr_query.restype = i32
+        L.burr_contains.argtypes = [vp, vp, u64, vp, vp]
+        L.burr_contains.restype = i32
+        L.burr_free.argtypes = [vp]
+        L.burr_free.restype = None
+        L.burr_get_stats.argtypes = [vp, ctypes.POINTER(_CStats)]
+        L.burr_get_stats.restype = i32
+        L.burr_export.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+        L.burr_export.restype = i32
+        L.burr_import.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(_CParams)]
+        L.burr_import.restype = vp
+        L.burr_debug_layer_keys.argtypes = [vp, u32, vp, u64]
+        L.burr_debug_layer_keys.restype = ctypes.c_int64
+        L.burr_last_error.argtypes = []
+        L.burr_last_error.restype = i32
+        L.burr_error_string.argtypes = [i32]
+        L.burr_error_string.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _lib_error_string(code: int) -> str:
+    try:
+        return lib().burr_error_string(code).decode()
+    except Exception:  # library missing: still report the code
+        return "error"
+
+
+def _stream_of(stream) -> int:
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _check_tensor(t, name: str, dtypes):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+
+
+def value_dtype(r: int):
+    import torch
+    return torch.uint8 if r <= 8 else (torch.uint16 if r <= 16 else torch.uint32)
+
+
+class Handle:
+    """A structure built on the GPU; owns its device memory until free()."""
+
+    def __init__(self, ptr: int, r: int, params: Params):
+        self._h = ptr
+        self.r = r
+        self.params = params
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().burr_free(self._h)
+            self._h = None
+
+    def query(self, keys, out=None, stream=None):
+        return burr_query(self, keys, out, stream)
+
+    def contains(self, keys, out=None, stream=None):
+        return burr_contains(self, keys, out, stream)
+
+    def export(self) -> bytes:
+        return burr_export(self)
+
+    def stats(self) -> dict:
+        return burr_get_stats(self)
+
+    def layer_keys(self, layer: int):
+        return burr_debug_layer_keys(self, layer)
+
+
+def burr_build(keys, values, r: int, params: Params | None = None, stream=None) -> Handle:
+    """keys: int64/uint64 GPU tensor (bit pattern of u64 keys); values: GPU
+    tensor of uint8/uint16/uint32 (by r) or None in filter mode."""
+    import torch
+    params = params or Params()
+    _check_tensor(keys, "keys", (torch.int64, torch.uint64))
+    vptr = None
+    if values is not None:
+        _check_tensor(values, "values", (value_dtype(r),))
+        if values.numel() != keys.numel():
+            raise ValueError("keys and values differ in length")
+        vptr = values.data_ptr()
+    cp = params.c(_stream_of(stream))
+    h = lib().burr_build(keys.data_ptr() if keys.numel() else None, vptr, keys.numel(), r,
+                         ctypes.byref(cp))
+    if not h:
+        raise BurrError(lib().burr_last_error(), "burr_build")
+    return Handle(h, r, params)
+
+
+def burr_query(h: Handle, keys, out=None, stream=None):
+    import torch
+    _check_tensor(keys, "keys", (torch.int64, torch.uint64))
+    if out is None:
+        out = torch.empty(keys.numel(), dtype=value_dtype(h.r), device=keys.device)
+    _check_tensor(out, "out", (value_dtype(h.r),))
+    rc = lib().burr_query(h._h, keys.data_ptr() if keys.numel() else None, keys.numel(),
+                          out.data_ptr() if out.numel() else None, _stream_of(stream))
+    if rc != BURR_OK:
+        raise BurrError(rc, "burr_query")
+    return out
+
+
+def burr_contains(h: Handle, keys, out=None, stream=None):
+    import torch
+    _check_tensor(keys, "keys", (torch.int64, torch.uint64))
+    if out is None:
+        out = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+    rc = lib().burr_contains(h._h, keys.data_ptr() if keys.numel() else None, keys.numel(),
+                             out.data_ptr() if out.numel() else None, _stream_of(stream))
+    if rc != BURR_OK:
+        raise BurrError(rc, "burr_contains")
+    return out
+
+
+def burr_free(h: Handle):
+    h.free()
+
+
+def burr_get_stats(h: Handle) -> dict:
+    st = _CStats()
+    rc = lib().burr_get_stats(h._h, ctypes.byref(st))
+    if rc != BURR_OK:
+        raise BurrError(rc, "burr_get_stats")
+    layers = [{f: int(getattr(st.layer[i], f)) for f, _ in _CLayerStats._fields_}
+              for i in range(st.layers_built)]
+    return dict(n=st.n, r=st.r, layers_built=st.layers_built, layers=layers,
+                final_n=st.final_n, final_m=st.final_m, final_attempt=st.final_attempt,
+                table_bytes=st.table_bytes, ms_sort=st.ms_sort, ms_solve=st.ms_solve,
+                ms_final=st.ms_final, ms_total=st.ms_total)
+
+
+def burr_export(h: Handle) -> bytes:
+    need = ctypes.c_size_t(0)
+    rc = lib().burr_export(h._h, None, 0, ctypes.byref(need))
+    if rc != BURR_OK:
+        raise BurrError(rc, "burr_export")
+    buf = (ctypes.c_uint8 * need.value)()
+    rc = lib().burr_export(h._h, buf, need.value, ctypes.byref(need))
+    if rc != BURR_OK:
+        raise BurrError(rc, "burr_export")
+    return bytes(buf)
+
+
+def burr_import(data: bytes, stream=None) -> Handle:
+    cp = Params().c(_stream_of(stream))
+    h = lib().burr_import(data, len(data), ctypes.byref(cp))
+    if not h:
+        raise BurrError(lib().burr_last_error(), "burr_import")
+    r = int.from_bytes(data[20:24], "little")
+    return Handle(h, r, Params())
+
+
+def burr_debug_layer_keys(h: Handle, layer: int):
+    import numpy as np
+    n = lib().burr_debug_layer_keys(h._h, layer, None, 0)
+    if n < 0:
+        raise BurrError(int(n), "burr_debug_layer_keys")
+    out = np.zeros(n, dtype=np.uint64)
+    if n:
+        lib().burr_debug_layer_keys(h._h, layer, out.ctypes.data, n)
+    return out
+
+
+# short aliases
+build = burr_build
+import_ = burr_import

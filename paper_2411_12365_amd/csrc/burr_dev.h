@@ -1,0 +1,84 @@
+// burr_dev.h - device-side definitions shared by the HIP kernels of the
+// BuRR library (hash, layer geometry, record layout). Host code of the
+// library includes it for the launch structs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace burr {
+
+constexpr uint32_t kWidth = 64;           // ribbon width w (Sec. 2)
+constexpr uint32_t kBucket = 64;          // bucket size b handled by the kernels
+constexpr uint32_t kRing = 128;           // LDS ring rows per range: bucket q touches slots [64q, 64q+126]
+constexpr uint32_t kBucketsPerBin = 2048; // coarse sort bin = 2048 consecutive buckets
+constexpr uint32_t kDigitsPerBin = 3 * kBucketsPerBin; // (bucket, chunk) digits inside a bin
+constexpr uint32_t kMaxBins = 32768;      // level-1 histogram fits in LDS
+
+// MurmurHash3's 64-bit finalizer (public domain), used as the key mixer.
+__host__ __device__ inline uint64_t mix64(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ull;
+  x ^= x >> 33;
+  return x;
+}
+
+// Geometry and hash salts of one layer, passed by value to kernels.
+struct LayerGeom {
+  uint64_t salt_s;   // start-position salt of the layer
+  uint64_t salt_c;   // coefficient-row salt of the layer
+  uint64_t span;     // m - w + 1: number of possible start slots
+  uint64_t m;        // slots
+  uint64_t nbuckets; // m / 64
+  uint64_t nranges;  // independent ranges
+  uint32_t t_lo, t_hi;
+  uint32_t plain;    // 1: final plain ribbon (one chunk, conflicts fail)
+  uint32_t r;        // value bits
+};
+
+// start slot in [0, m-64]: high word of mix64(key^salt) * span
+__device__ inline uint64_t start_of(uint64_t key, const LayerGeom& g) {
+  return __umul64hi(mix64(key ^ g.salt_s), g.span);
+}
+// coefficient row; bit j <-> slot s+j, bit 0 always set
+__device__ inline uint64_t row_of(uint64_t key, const LayerGeom& g) {
+  return mix64(key ^ g.salt_c) | 1ull;
+}
+// position of a key's chunk in the insertion order of its bucket:
+// 0 = offsets [t_hi,64) (chunk 3, inserted first), 1 = [t_lo,t_hi), 2 = [0,t_lo)
+__device__ inline uint32_t rank_of(uint32_t o, const LayerGeom& g) {
+  if (g.plain) return 0;
+  return o >= g.t_hi ? 0u : (o >= g.t_lo ? 1u : 2u);
+}
+
+// Sorted record of one key: the row and a meta word
+//   meta bits  0..31: value, 32..37: offset in bucket, 40..41: rank
+struct alignas(16) Rec {
+  uint64_t c;
+  uint64_t meta;
+};
+
+__device__ inline uint32_t meta_value(uint64_t meta) { return (uint32_t)meta; }
+__device__ inline uint32_t meta_offset(uint64_t meta) { return (uint32_t)(meta >> 32) & 63u; }
+__device__ inline uint32_t meta_rank(uint64_t meta) { return (uint32_t)(meta >> 40) & 3u; }
+
+// Query-side description of one layer (BuRR layers and the final one).
+struct QueryLayer {
+  uint64_t salt_s, salt_c, span;
+  const uint64_t* codes; // packed 2-bit codes, bucket beta at bits 2*(beta%32) of word beta/32
+  const uint64_t* W;     // column-interleaved solution words, W[k*r + col]
+  uint32_t t_lo, t_hi;
+  uint32_t plain;        // final layer: no threshold check
+  uint32_t empty;        // final layer without keys: answer 0
+};
+
+constexpr int kMaxQueryLayers = 33;
+struct QueryPlan {
+  QueryLayer layer[kMaxQueryLayers];
+  uint32_t nlayers; // BuRR layers + 1 (final)
+  uint32_t r;
+};
+
+}  // namespace burr

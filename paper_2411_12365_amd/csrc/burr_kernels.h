@@ -1,0 +1,73 @@
+// burr_kernels.h - host-side launchers of the HIP kernels (internal to the
+// library; the public interface is include/burr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "burr_dev.h"
+
+namespace burr {
+
+// Exclusive prefix sum of n u32 values in place; `tmp` needs scan_tmp_words(n) u32.
+size_t scan_tmp_words(size_t n);
+hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s);
+
+// Sorting of one layer's keys by (bucket, chunk) - two passes:
+//   level 1: partition keys into coarse bins of kBucketsPerBin buckets
+//   level 2: one workgroup per bin orders its keys by (bucket, chunk) and
+//            writes records + bucket start offsets.
+struct SortArgs {
+  const uint64_t* keys;   // input keys (n)
+  const void* vals;       // input values (n) or nullptr (filter fingerprints)
+  uint32_t vbytes;        // 1, 2 or 4
+  uint32_t mask_values;   // layer 0: mask to r bits / compute fingerprints
+  uint64_t fp_salt;       // fingerprint salt (filter mode)
+  uint32_t filter;        // values are fingerprints
+  uint64_t n;
+  LayerGeom g;
+  uint32_t nbins;         // ceil(B / kBucketsPerBin)
+  uint32_t groups;        // level-1 workgroups
+  uint32_t* counts;       // nbins * groups (+1) u32, scanned in place
+  uint32_t* scan_tmp;
+  uint64_t* tmp_keys;     // level-1 output (n)
+  uint32_t* tmp_vals;     // level-1 output values widened to u32 (n)
+  uint64_t* out_keys;     // level-2 output keys (n)
+  Rec* out_rec;           // level-2 output records (n)
+  uint32_t* bstart;       // B + 1 bucket start offsets
+};
+hipError_t sort_layer(const SortArgs& a, hipStream_t s);
+
+// Per-range insertion with 2-bit thresholds and boundary bumping: one lane
+// per range, ring of 128 rows per lane in LDS.
+struct SolveArgs {
+  const Rec* rec;
+  const uint32_t* bstart;
+  LayerGeom g;
+  uint64_t* rowsC;     // m rows, written through at placement
+  uint32_t* rowsV;     // m values
+  uint64_t* occ;       // m/64 occupancy words
+  uint8_t* code8;      // B codes (not in plain mode)
+  uint32_t* bump;      // B bumped-key counts (not in plain mode)
+  uint32_t* fail;      // plain mode: set to 1 on an inconsistent equation
+  uint64_t* steps;     // optional: total elimination steps (statistics)
+  uint32_t nrec;       // number of records (prefetch bound)
+};
+hipError_t solve_layer(const SolveArgs& a, hipStream_t s);
+
+// Back-substitution per range into column-interleaved words W[k*r+col].
+hipError_t back_substitute(const uint64_t* rowsC, const uint32_t* rowsV, const uint64_t* occ,
+                           const LayerGeom& g, uint64_t* W, hipStream_t s);
+
+// code8[B] -> packed 2-bit code words
+hipError_t pack_codes(const uint8_t* code8, uint64_t B, uint64_t* words, hipStream_t s);
+
+// Copy the bumped suffix of every bucket into the next layer's input.
+hipError_t gather_bumped(const uint64_t* sorted_keys, const Rec* rec, const uint32_t* bstart,
+                         const uint32_t* off /* scanned bump counts, B+1 */, uint64_t B,
+                         uint64_t* next_keys, uint32_t* next_vals, hipStream_t s);
+
+hipError_t query(const QueryPlan& plan, const uint64_t* keys, uint64_t n, void* out,
+                 uint32_t out_bytes, uint32_t contains, uint64_t fp_salt, hipStream_t s);
+
+}  // namespace burr

@@ -1,0 +1,625 @@
+// burr_kernels.hip - HIP kernels of the BuRR library for gfx950 (CDNA4).
+//
+// Per layer (Sec. 2 and Sec. 3 of the paper):
+//   sort      : two-level partition of the keys by (bucket, chunk); level 1
+//               scatters into coarse bins of 2048 buckets through LDS
+//               histograms, level 2 orders one bin per workgroup in LDS and
+//               writes 16-byte records (row + value/offset/chunk)
+//   solve     : one lane per range; banded GF(2) insertion against a ring of
+//               128 rows in LDS, bucket by bucket, chunks of decreasing
+//               offset, 2-bit thresholds, forced bumps at the range end
+//   backsub   : one lane per range, column-interleaved output words
+//   gather    : bumped keys (a suffix of every bucket) -> next layer input
+//   query     : one lane per key, layer walk, two-word window, popcount parity
+#include "burr_kernels.h"
+
+namespace burr {
+
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scan (wave scan with cross-lane shuffles + LDS totals)
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t* wsum, uint32_t* total) {
+  constexpr int NW = NT / 64;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wid = threadIdx.x >> 6;
+  uint32_t inc = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(inc, d, 64);
+    if (lane >= (uint32_t)d) inc += y;
+  }
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  if (wid == 0) {
+    uint32_t w = lane < (uint32_t)NW ? wsum[lane] : 0u;
+    uint32_t wi = w;
+#pragma unroll
+    for (int d = 1; d < NW; d <<= 1) {
+      uint32_t y = __shfl_up(wi, d, 64);
+      if (lane >= (uint32_t)d) wi += y;
+    }
+    if (lane < (uint32_t)NW) wsum[lane] = wi - w;
+    if (lane == (uint32_t)NW - 1 && total) *total = wi;
+  }
+  __syncthreads();
+  uint32_t res = wsum[wid] + inc - x;
+  __syncthreads();
+  return res;
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan of u32 (tiles of 2048, recursive on tile sums)
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 8;
+constexpr size_t kScanTile = (size_t)kScanThreads * kScanPer;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile(uint32_t* data, size_t n,
+                                                             uint32_t* sums) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  __shared__ uint32_t total;
+  const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanPer;
+  uint32_t v[kScanPer];
+  uint32_t tot = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = (base + k < n) ? data[base + k] : 0u;
+    tot += v[k];
+  }
+  uint32_t run = block_exclusive_scan<kScanThreads>(tot, wsum, &total);
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < n) data[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0 && sums) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(uint32_t* data, size_t n,
+                                                            const uint32_t* sums) {
+  const uint32_t add = sums[blockIdx.x];
+  const size_t base = (size_t)blockIdx.x * kScanTile;
+  for (size_t k = threadIdx.x; k < kScanTile; k += kScanThreads)
+    if (base + k < n) data[base + k] += add;
+}
+
+size_t scan_tmp_words(size_t n) {
+  size_t w = 0;
+  while (n > kScanTile) {
+    n = (n + kScanTile - 1) / kScanTile;
+    w += n;
+  }
+  return w + 1;
+}
+
+hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t tiles = (n + kScanTile - 1) / kScanTile;
+  if (tiles == 1) {
+    k_scan_tile<<<1, kScanThreads, 0, s>>>(data, n, nullptr);
+    return hipGetLastError();
+  }
+  k_scan_tile<<<(unsigned)tiles, kScanThreads, 0, s>>>(data, n, tmp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = scan_exclusive(tmp, tiles, tmp + tiles, s);
+  if (e != hipSuccess) return e;
+  k_scan_add<<<(unsigned)tiles, kScanThreads, 0, s>>>(data, n, tmp);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sorting
+// ---------------------------------------------------------------------------
+constexpr int kL1Threads = 256;
+constexpr int kL2Threads = 512;
+
+__device__ inline uint32_t coarse_bin(uint64_t s) {
+  return (uint32_t)((s >> 6) / kBucketsPerBin);
+}
+
+__global__ __launch_bounds__(kL1Threads) void k_l1_hist(const uint64_t* __restrict__ keys,
+                                                         uint64_t n, LayerGeom g, uint32_t nbins,
+                                                         uint32_t groups, uint64_t per_group,
+                                                         uint32_t* __restrict__ counts) {
+  extern __shared__ uint32_t hist[];
+  for (uint32_t i = threadIdx.x; i < nbins; i += kL1Threads) hist[i] = 0;
+  __syncthreads();
+  const uint64_t lo = (uint64_t)blockIdx.x * per_group;
+  const uint64_t hi = lo + per_group < n ? lo + per_group : n;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kL1Threads)
+    atomicAdd(&hist[coarse_bin(start_of(keys[i], g))], 1u);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nbins; i += kL1Threads)
+    counts[(size_t)i * groups + blockIdx.x] = hist[i];
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kL1Threads) void k_l1_scatter(
+    const uint64_t* __restrict__ keys, const VT* __restrict__ vals, uint64_t n, LayerGeom g,
+    uint32_t nbins, uint32_t groups, uint64_t per_group, const uint32_t* __restrict__ offs,
+    uint32_t mask_values, uint32_t filter, uint64_t fp_salt, uint64_t* __restrict__ tk,
+    uint32_t* __restrict__ tv) {
+  extern __shared__ uint32_t cur[];
+  for (uint32_t i = threadIdx.x; i < nbins; i += kL1Threads)
+    cur[i] = offs[(size_t)i * groups + blockIdx.x];
+  __syncthreads();
+  const uint64_t lo = (uint64_t)blockIdx.x * per_group;
+  const uint64_t hi = lo + per_group < n ? lo + per_group : n;
+  const uint32_t vmask = g.r >= 32 ? 0xffffffffu : ((1u << g.r) - 1u);
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kL1Threads) {
+    const uint64_t key = keys[i];
+    uint32_t v;
+    if (filter && mask_values)
+      v = (uint32_t)(mix64(key ^ fp_salt) >> (64 - g.r));
+    else
+      v = mask_values ? ((uint32_t)vals[i] & vmask) : (uint32_t)vals[i];
+    const uint32_t pos = atomicAdd(&cur[coarse_bin(start_of(key, g))], 1u);
+    tk[pos] = key;
+    tv[pos] = v;
+  }
+}
+
+__global__ __launch_bounds__(kL2Threads) void k_l2_sort(
+    const uint64_t* __restrict__ tk, const uint32_t* __restrict__ tv, uint64_t n, LayerGeom g,
+    uint32_t nbins, uint32_t groups, const uint32_t* __restrict__ offs,
+    uint64_t* __restrict__ ok, Rec* __restrict__ orec, uint32_t* __restrict__ bstart) {
+  __shared__ uint32_t hist[kDigitsPerBin];
+  __shared__ uint32_t wsum[kL2Threads / 64];
+  const uint32_t bin = blockIdx.x;
+  const uint64_t lo = offs[(size_t)bin * groups];
+  const uint64_t hi = bin + 1 < nbins ? offs[(size_t)(bin + 1) * groups] : n;
+  const uint64_t bbase = (uint64_t)bin * kBucketsPerBin;
+  for (uint32_t i = threadIdx.x; i < kDigitsPerBin; i += kL2Threads) hist[i] = 0;
+  __syncthreads();
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kL2Threads) {
+    const uint64_t s = start_of(tk[i], g);
+    const uint32_t d = (uint32_t)((s >> 6) - bbase) * 3u + rank_of((uint32_t)s & 63u, g);
+    atomicAdd(&hist[d], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of the 6144 digit counts, 12 per thread
+  constexpr int kPer = kDigitsPerBin / kL2Threads;
+  uint32_t loc[kPer];
+  uint32_t tot = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    loc[k] = hist[threadIdx.x * kPer + k];
+    tot += loc[k];
+  }
+  uint32_t run = block_exclusive_scan<kL2Threads>(tot, wsum, nullptr);
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    hist[threadIdx.x * kPer + k] = run;
+    run += loc[k];
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < kBucketsPerBin; b += kL2Threads) {
+    const uint64_t beta = bbase + b;
+    if (beta < g.nbuckets) bstart[beta] = (uint32_t)(lo + hist[3 * b]);
+  }
+  if (bin + 1 == nbins && threadIdx.x == 0) bstart[g.nbuckets] = (uint32_t)hi;
+  __syncthreads();
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kL2Threads) {
+    const uint64_t key = tk[i];
+    const uint64_t s = start_of(key, g);
+    const uint32_t o = (uint32_t)s & 63u;
+    const uint32_t rk = rank_of(o, g);
+    const uint32_t d = (uint32_t)((s >> 6) - bbase) * 3u + rk;
+    const uint64_t pos = lo + atomicAdd(&hist[d], 1u);
+    ok[pos] = key;
+    Rec rc;
+    rc.c = row_of(key, g);
+    rc.meta = (uint64_t)tv[i] | ((uint64_t)o << 32) | ((uint64_t)rk << 40);
+    orec[pos] = rc;
+  }
+}
+
+hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
+  const uint64_t per_group = (a.n + a.groups - 1) / a.groups;
+  const size_t hist_bytes = (size_t)a.nbins * sizeof(uint32_t);
+  k_l1_hist<<<a.groups, kL1Threads, hist_bytes, s>>>(a.keys, a.n, a.g, a.nbins, a.groups,
+                                                     per_group, a.counts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = scan_exclusive(a.counts, (size_t)a.nbins * a.groups, a.scan_tmp, s);
+  if (e != hipSuccess) return e;
+  switch (a.vbytes) {
+    case 1:
+      k_l1_scatter<uint8_t><<<a.groups, kL1Threads, hist_bytes, s>>>(
+          a.keys, (const uint8_t*)a.vals, a.n, a.g, a.nbins, a.groups, per_group, a.counts,
+          a.mask_values, a.filter, a.fp_salt, a.tmp_keys, a.tmp_vals);
+      break;
+    case 2:
+      k_l1_scatter<uint16_t><<<a.groups, kL1Threads, hist_bytes, s>>>(
+          a.keys, (const uint16_t*)a.vals, a.n, a.g, a.nbins, a.groups, per_group, a.counts,
+          a.mask_values, a.filter, a.fp_salt, a.tmp_keys, a.tmp_vals);
+      break;
+    default:
+      k_l1_scatter<uint32_t><<<a.groups, kL1Threads, hist_bytes, s>>>(
+          a.keys, (const uint32_t*)a.vals, a.n, a.g, a.nbins, a.groups, per_group, a.counts,
+          a.mask_values, a.filter, a.fp_salt, a.tmp_keys, a.tmp_vals);
+      break;
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_l2_sort<<<a.nbins, kL2Threads, 0, s>>>(a.tmp_keys, a.tmp_vals, a.n, a.g, a.nbins, a.groups,
+                                           a.counts, a.out_keys, a.out_rec, a.bstart);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Solve: one lane per range
+// ---------------------------------------------------------------------------
+enum : uint32_t {
+  ST_ELIM = 0,      // eliminating the current equation
+  ST_PLACE = 1,     // found an empty slot at i
+  ST_REDUNDANT = 2, // reduced to 0 = 0
+  ST_CONFLICT = 3,  // reduced to 0 = v with v != 0
+  ST_NEXT = 4,      // fetch the next record of the bucket
+  ST_BEND = 5,      // finish the current bucket
+  ST_BSTART = 6,    // start the next bucket
+  ST_DONE = 7
+};
+
+template <typename VT, int K>
+__global__ __launch_bounds__(64) void k_solve(SolveArgs a, uint32_t total) {
+  extern __shared__ uint64_t lds[];
+  uint64_t* ringC = lds;                                  // [kRing][64]
+  VT* ringV = reinterpret_cast<VT*>(lds + kRing * 64);    // [kRing][64]
+  const LayerGeom g = a.g;
+  const uint32_t lane = threadIdx.x;
+  const uint64_t rho = (uint64_t)blockIdx.x * 64 + lane;
+
+  uint32_t state = ST_DONE;
+  uint64_t fb = 0;
+  uint32_t nq = 0;
+  bool last_range = true;
+  if (rho < g.nranges) {
+    fb = rho * g.nbuckets / g.nranges;
+    nq = (uint32_t)((rho + 1) * g.nbuckets / g.nranges - fb);
+    last_range = (rho + 1 == g.nranges);
+    state = ST_BSTART;
+  }
+  const uint64_t P0 = fb * 64;
+  uint32_t q = 0;                 // bucket index inside the range
+  uint32_t t = 0, lo = 0, hi = 0; // record cursor, bucket record interval
+  uint32_t nbs = 0;               // prefetched bstart of the bucket after next
+  uint32_t kf = 0, code = 0, curk = 4, chunk_start = 0, split_at = 0;
+  uint32_t i = 0, v = 0;
+  uint64_t c = 0;
+  uint64_t vm0 = 0, vm1 = 0;      // valid ring rows (bit p <-> ring position p)
+  uint64_t pm0 = 0, pm1 = 0;      // rows placed by the current chunk
+  Rec nrec = {0, 0};
+  uint32_t nidx = 0xffffffffu;
+  uint64_t steps = 0;
+
+  while (true) {
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      if (state == ST_ELIM) {
+        const uint32_t p = i & (kRing - 1);
+        const uint64_t row = ringC[p * 64 + lane];
+        const uint32_t rv = ringV[p * 64 + lane];
+        const uint64_t vmw = (p & 64) ? vm1 : vm0;
+        if (((vmw >> (p & 63)) & 1ull) == 0) {
+          state = ST_PLACE;
+        } else {
+          ++steps;
+          c ^= row;
+          v ^= rv;
+          if (c == 0) {
+            state = (v == 0) ? ST_REDUNDANT : ST_CONFLICT;
+          } else {
+            const uint32_t j = (uint32_t)__builtin_ctzll(c);
+            c >>= j;
+            i += j;
+          }
+        }
+      }
+    }
+
+    if (state == ST_PLACE && i >= 64u * nq) {
+      // unreachable for kept keys (their rows end inside the range); stop
+      // the lane instead of writing outside it
+      *a.fail = 2u;
+      state = ST_DONE;
+    }
+    if (state == ST_PLACE) {
+      const uint32_t p = i & (kRing - 1);
+      ringC[p * 64 + lane] = c;
+      ringV[p * 64 + lane] = (VT)v;
+      const uint64_t bit = 1ull << (p & 63);
+      if (p & 64) {
+        vm1 |= bit;
+        pm1 |= bit;
+      } else {
+        vm0 |= bit;
+        pm0 |= bit;
+      }
+      a.rowsC[P0 + i] = c;
+      a.rowsV[P0 + i] = v;
+      state = ST_NEXT;
+    } else if (state == ST_REDUNDANT) {
+      state = ST_NEXT;
+    } else if (state == ST_CONFLICT) {
+      if (g.plain) {
+        *a.fail = 1u;
+        state = ST_DONE;
+      } else {
+        vm0 &= ~pm0;  // undo the chunk
+        vm1 &= ~pm1;
+        code = curk;
+        split_at = chunk_start;
+        state = ST_BEND;
+      }
+    }
+
+    while (state >= ST_NEXT && state != ST_DONE) {
+      if (state == ST_NEXT) {
+        ++t;
+        if (t >= hi) {
+          split_at = hi;
+          state = ST_BEND;
+        } else {
+          const Rec rc = (t == nidx) ? nrec : a.rec[t];
+          if (t + 1 < total) {
+            nrec = a.rec[t + 1];
+            nidx = t + 1;
+          }
+          const uint32_t k = 3u - meta_rank(rc.meta);
+          if (k <= kf) {
+            split_at = t;
+            state = ST_BEND;
+          } else {
+            if (k != curk) {
+              pm0 = 0;
+              pm1 = 0;
+              curk = k;
+              chunk_start = t;
+            }
+            c = rc.c;
+            v = meta_value(rc.meta);
+            i = 64u * q + meta_offset(rc.meta);
+            state = ST_ELIM;
+          }
+        }
+      }
+      if (state == ST_BEND) {
+        const uint64_t beta = fb + q;
+        if (!g.plain) {
+          a.code8[beta] = (uint8_t)code;
+          a.bump[beta] = hi - split_at;
+        }
+        ++q;
+        if (q == nq) {
+          a.occ[beta] = ((q - 1) & 1) ? vm1 : vm0;
+          state = ST_DONE;
+        } else {
+          state = ST_BSTART;
+        }
+      }
+      if (state == ST_BSTART) {
+        const uint64_t beta = fb + q;
+        if (q == 0) {
+          lo = a.bstart[beta];
+          hi = a.bstart[beta + 1];
+        } else {
+          lo = hi;
+          hi = nbs;
+          // bucket q-1 is final: publish its occupancy and free its ring half
+          if ((q - 1) & 1) {
+            a.occ[beta - 1] = vm1;
+            vm1 = 0;
+          } else {
+            a.occ[beta - 1] = vm0;
+            vm0 = 0;
+          }
+        }
+        if (q + 1 < nq) nbs = a.bstart[beta + 2];
+        kf = 0;
+        if (!g.plain && !last_range && q + 1 == nq && lo < hi) {
+          // The last bucket of a range: keys starting past its first slot
+          // would cross the range end (b = w = 64) and must be bumped; the
+          // threshold is the smallest value above the largest such offset.
+          const uint32_t rk = meta_rank(a.rec[lo].meta);
+          if (rk == 0) {
+            kf = 3;
+          } else if (rk == 1) {
+            kf = 2;
+          } else {
+            for (uint32_t x = lo; x < hi; ++x)
+              if (meta_offset(a.rec[x].meta) >= 1) kf = 1;
+          }
+        }
+        code = kf;
+        curk = 4;
+        pm0 = 0;
+        pm1 = 0;
+        chunk_start = lo;
+        t = lo - 1u;
+        state = ST_NEXT;
+      }
+    }
+    if (!__any(state != ST_DONE)) break;
+  }
+  if (a.steps) atomicAdd((unsigned long long*)a.steps, (unsigned long long)steps);
+}
+
+hipError_t solve_layer(const SolveArgs& a, hipStream_t s) {
+  const unsigned blocks = (unsigned)((a.g.nranges + 63) / 64);
+  if (a.g.r <= 8) {
+    const size_t lds = kRing * 64 * (sizeof(uint64_t) + 1);
+    (void)hipFuncSetAttribute((const void*)k_solve<uint8_t, 4>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_solve<uint8_t, 4><<<blocks, 64, lds, s>>>(a, a.nrec);
+  } else if (a.g.r <= 16) {
+    const size_t lds = kRing * 64 * (sizeof(uint64_t) + 2);
+    (void)hipFuncSetAttribute((const void*)k_solve<uint16_t, 4>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_solve<uint16_t, 4><<<blocks, 64, lds, s>>>(a, a.nrec);
+  } else {
+    const size_t lds = kRing * 64 * (sizeof(uint64_t) + 4);
+    (void)hipFuncSetAttribute((const void*)k_solve<uint32_t, 4>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_solve<uint32_t, 4><<<blocks, 64, lds, s>>>(a, a.nrec);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Back-substitution: one lane per range, from the range end down
+// ---------------------------------------------------------------------------
+template <int RMAX>
+__global__ __launch_bounds__(256) void k_backsub(const uint64_t* __restrict__ rowsC,
+                                                 const uint32_t* __restrict__ rowsV,
+                                                 const uint64_t* __restrict__ occ, LayerGeom g,
+                                                 uint64_t* __restrict__ W) {
+  const uint64_t rho = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (rho >= g.nranges) return;
+  const uint64_t fb = rho * g.nbuckets / g.nranges;
+  const uint64_t lb = (rho + 1) * g.nbuckets / g.nranges;
+  const uint32_t r = g.r;
+  uint64_t win[RMAX];  // bit j of win[col] = column col of Z[i+1+j]
+#pragma unroll
+  for (int col = 0; col < RMAX; ++col) win[col] = 0;
+  for (uint64_t k = lb; k-- > fb;) {
+    const uint64_t oc = occ[k];
+    uint64_t out[RMAX];
+#pragma unroll
+    for (int col = 0; col < RMAX; ++col) out[col] = 0;
+    for (int tt = 63; tt >= 0; --tt) {
+      uint32_t z = 0;
+      if ((oc >> tt) & 1ull) {
+        const uint64_t slot = k * 64 + (uint64_t)tt;
+        const uint64_t C = rowsC[slot] >> 1;
+        const uint32_t V = rowsV[slot];
+#pragma unroll
+        for (int col = 0; col < RMAX; ++col)
+          if ((uint32_t)col < r)
+            z |= ((V >> col) ^ (uint32_t)__popcll(C & win[col])) & 1u ? (1u << col) : 0u;
+      }
+#pragma unroll
+      for (int col = 0; col < RMAX; ++col) {
+        if ((uint32_t)col < r) {
+          const uint64_t b = (z >> col) & 1u;
+          win[col] = (win[col] << 1) | b;
+          out[col] |= b << tt;
+        }
+      }
+    }
+    for (uint32_t col = 0; col < r && col < (uint32_t)RMAX; ++col) W[k * r + col] = out[col];
+  }
+}
+
+hipError_t back_substitute(const uint64_t* rowsC, const uint32_t* rowsV, const uint64_t* occ,
+                           const LayerGeom& g, uint64_t* W, hipStream_t s) {
+  const unsigned blocks = (unsigned)((g.nranges + 255) / 256);
+  if (g.r <= 8)
+    k_backsub<8><<<blocks, 256, 0, s>>>(rowsC, rowsV, occ, g, W);
+  else if (g.r <= 16)
+    k_backsub<16><<<blocks, 256, 0, s>>>(rowsC, rowsV, occ, g, W);
+  else
+    k_backsub<32><<<blocks, 256, 0, s>>>(rowsC, rowsV, occ, g, W);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Codes and bumped keys
+// ---------------------------------------------------------------------------
+__global__ void k_pack_codes(const uint8_t* __restrict__ code8, uint64_t B,
+                             uint64_t* __restrict__ words) {
+  const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= (B + 31) / 32) return;
+  uint64_t word = 0;
+  for (uint64_t j = 0; j < 32; ++j) {
+    const uint64_t beta = w * 32 + j;
+    if (beta < B) word |= (uint64_t)(code8[beta] & 3u) << (2 * j);
+  }
+  words[w] = word;
+}
+
+hipError_t pack_codes(const uint8_t* code8, uint64_t B, uint64_t* words, hipStream_t s) {
+  const uint64_t nw = (B + 31) / 32;
+  if (nw == 0) return hipSuccess;
+  k_pack_codes<<<(unsigned)((nw + 255) / 256), 256, 0, s>>>(code8, B, words);
+  return hipGetLastError();
+}
+
+__global__ void k_gather(const uint64_t* __restrict__ sorted_keys, const Rec* __restrict__ rec,
+                         const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ off,
+                         uint64_t B, uint64_t* __restrict__ nk, uint32_t* __restrict__ nv) {
+  const uint64_t beta = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (beta >= B) return;
+  const uint32_t o = off[beta];
+  const uint32_t cnt = off[beta + 1] - o;
+  const uint32_t src = bstart[beta + 1] - cnt;
+  for (uint32_t j = 0; j < cnt; ++j) {
+    nk[o + j] = sorted_keys[src + j];
+    nv[o + j] = meta_value(rec[src + j].meta);
+  }
+}
+
+hipError_t gather_bumped(const uint64_t* sorted_keys, const Rec* rec, const uint32_t* bstart,
+                         const uint32_t* off, uint64_t B, uint64_t* next_keys,
+                         uint32_t* next_vals, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  k_gather<<<(unsigned)((B + 255) / 256), 256, 0, s>>>(sorted_keys, rec, bstart, off, B,
+                                                       next_keys, next_vals);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Query: one lane per key
+// ---------------------------------------------------------------------------
+template <typename OT>
+__global__ __launch_bounds__(256) void k_query(QueryPlan plan, const uint64_t* __restrict__ keys,
+                                               uint64_t n, OT* __restrict__ out,
+                                               uint32_t contains, uint64_t fp_salt) {
+  const uint64_t idx = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n) return;
+  const uint64_t key = keys[idx];
+  const uint32_t r = plan.r;
+  uint32_t res = 0;
+  for (uint32_t l = 0; l < plan.nlayers; ++l) {
+    const QueryLayer& L = plan.layer[l];
+    if (L.empty) break;
+    const uint64_t s = __umul64hi(mix64(key ^ L.salt_s), L.span);
+    if (!L.plain) {
+      const uint64_t beta = s >> 6;
+      const uint32_t o = (uint32_t)s & 63u;
+      const uint32_t code = (uint32_t)(L.codes[beta >> 5] >> (2 * (beta & 31))) & 3u;
+      const uint32_t th = code == 0 ? 0u : (code == 1 ? L.t_lo : (code == 2 ? L.t_hi : 64u));
+      if (o < th) continue;
+    }
+    const uint64_t c = mix64(key ^ L.salt_c) | 1ull;
+    const uint32_t sh = (uint32_t)s & 63u;
+    const uint64_t* w = L.W + (s >> 6) * r;
+    for (uint32_t col = 0; col < r; ++col) {
+      uint64_t win = w[col] >> sh;
+      if (sh) win |= w[r + col] << (64 - sh);
+      res |= ((uint32_t)__popcll(win & c) & 1u) << col;
+    }
+    break;
+  }
+  if (contains)
+    out[idx] = (OT)(res == (uint32_t)(mix64(key ^ fp_salt) >> (64 - r)));
+  else
+    out[idx] = (OT)res;
+}
+
+hipError_t query(const QueryPlan& plan, const uint64_t* keys, uint64_t n, void* out,
+                 uint32_t out_bytes, uint32_t contains, uint64_t fp_salt, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (out_bytes == 1)
+    k_query<uint8_t><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
+  else if (out_bytes == 2)
+    k_query<uint16_t><<<blocks, 256, 0, s>>>(plan, keys, n, (uint16_t*)out, contains, fp_salt);
+  else
+    k_query<uint32_t><<<blocks, 256, 0, s>>>(plan, keys, n, (uint32_t*)out, contains, fp_salt);
+  return hipGetLastError();
+}
+
+}  // namespace burr

@@ -1,0 +1,127 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Bit-exact comparison of the whole exported structure (per-layer sizes,
+2-bit codes, solution words, final layer), of the per-layer key sets, and of
+query results for members and non-members.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_12365_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _burr():
+    import paper_2411_12365_amd as burr
+    return burr
+
+
+def _compare(keys, vals, r, kw, label=""):
+    burr = _burr()
+    filt = kw.get("filter_mode", 0)
+    print(f"[parity] {label} n={len(keys)} r={r} {kw}", flush=True)
+    ref = oracle.build(keys, None if filt else vals, r, oracle.Params(**kw))
+    h = burr.build(_dev(keys), None if filt else _dev(vals), r,
+                   burr.Params(flags=burr.BURR_FLAG_KEEP_LAYER_KEYS, **kw))
+    st = h.stats()
+    assert st["layers_built"] == ref.layers_built
+    for li in range(ref.layers_built):
+        info = ref.layer_info(li)
+        gl = st["layers"][li]
+        assert (gl["n"], gl["m"], gl["nranges"], gl["bumped"]) == \
+            (info["n"], info["m"], info["nranges"], info["bumped"]), f"layer {li} sizes"
+        assert np.array_equal(np.sort(h.layer_keys(li)), np.sort(ref.layer_keys(li))), \
+            f"layer {li} key set"
+    fin = ref.final_info()
+    assert (st["final_n"], st["final_m"], st["final_attempt"]) == \
+        (fin["n"], fin["m"], fin["attempt"])
+    assert h.export() == ref.export()
+    n = len(keys)
+    q = np.concatenate([keys[: min(n, 20000)], W.non_members(n, 20000, 99)])
+    got = h.query(_dev(q)).cpu().numpy()
+    assert np.array_equal(got, ref.query(q))
+    if filt:
+        cont = h.contains(_dev(q)).cpu().numpy()
+        assert cont[: min(n, 20000)].all()
+    return h, ref
+
+
+CASES = [
+    (1, 8, dict(ranges=4)),
+    (64, 2, dict(ranges=1)),
+    (200, 8, dict(ranges=1)),
+    (1000, 8, dict(ranges=4, minbpt=2)),
+    (5000, 1, dict(ranges=8, minbpt=2, seed=77)),
+    (20000, 8, dict(ranges=64)),
+    (30000, 16, dict(ranges=16)),
+    (30000, 32, dict(ranges=8, seed=5)),
+    (25000, 13, dict(ranges=100, minbpt=2, load_num=90, load_den=100, layers=5)),
+    (20000, 5, dict(ranges=37, minbpt=3, filter_mode=1, seed=9)),
+    (8000, 8, dict(layers=0)),
+    (20000, 8, dict(ranges=16, t_lo=8, t_hi=40, seed=123)),
+    (3000, 4, dict(ranges=6, minbpt=2, load_num=60, load_den=100, layers=4)),
+    (200000, 8, dict(ranges=4096, minbpt=4)),
+]
+
+
+@pytest.mark.parametrize("n,r,kw", CASES)
+def test_structure_matches_oracle(n, r, kw):
+    keys = W.keys(n, 1000 + n)
+    vals = W.values(n, r, 2000 + n)
+    _compare(keys, vals, r, kw, "case")
+
+
+def test_empty_build():
+    burr = _burr()
+    h = burr.build(_dev(np.zeros(0, np.uint64)), _dev(np.zeros(0, np.uint8)), 8, burr.Params())
+    ref = oracle.build(np.zeros(0, np.uint64), np.zeros(0, np.uint8), 8, oracle.Params())
+    assert h.export() == ref.export()
+    q = W.keys(100, 5)
+    assert (h.query(_dev(q)).cpu().numpy() == 0).all()
+
+
+def test_equal_duplicates_and_conflicts():
+    burr = _burr()
+    keys = W.keys(5000, 8)
+    vals = W.values(5000, 8, 9)
+    dk = np.concatenate([keys, keys[::11]])
+    dv = np.concatenate([vals, vals[::11]])
+    _compare(dk, dv, 8, dict(ranges=8, minbpt=2), "dups")
+    bad = dv.copy()
+    bad[-1] ^= 1
+    with pytest.raises(burr.BurrError) as e:
+        burr.build(_dev(dk), _dev(bad), 8, burr.Params(ranges=8, minbpt=2))
+    assert e.value.code == burr.BURR_E_UNSOLVABLE
+
+
+def test_import_roundtrip():
+    burr = _burr()
+    keys = W.keys(30000, 3)
+    vals = W.values(30000, 8, 4)
+    h, ref = _compare(keys, vals, 8, dict(ranges=32), "import")
+    h2 = burr.import_(h.export())
+    assert h2.export() == ref.export()
+    assert np.array_equal(h2.query(_dev(keys)).cpu().numpy(), vals)
+
+
+def test_one_million_keys_one_range():
+    # 1M keys, r = 8, one range (no boundary bumping)
+    keys = W.keys(1_000_000, 1)
+    vals = W.values(1_000_000, 8, 1001)
+    _compare(keys, vals, 8, dict(ranges=1), "1M")
+
+
+def test_ten_million_keys_many_ranges():
+    keys = W.keys(10_000_000, 2)
+    vals = W.values(10_000_000, 8, 1002)
+    _compare(keys, vals, 8, dict(ranges=1 << 16), "10M")

@@ -1,0 +1,56 @@
+"""The HIP library loads on the CPU and exports every entry point that
+include/burr.h declares (no compute calls: there may be no GPU)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "burr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(burr_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    import paper_2411_12365_amd as burr
+    lib = burr.lib()
+    names = declared()
+    assert "burr_build" in names and "burr_query" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_default_params_and_error_strings():
+    import paper_2411_12365_amd as burr
+    lib = burr.lib()
+    p = burr._CParams()
+    lib.burr_default_params(ctypes.byref(p))
+    assert (p.abi_version, p.bucket, p.load_num, p.load_den, p.layers, p.t_lo, p.t_hi) == \
+        (1, 64, 97, 100, 3, 16, 32)
+    assert lib.burr_error_string(burr.BURR_E_UNSOLVABLE).startswith(b"final layer")
+
+
+def test_invalid_arguments_fail_without_touching_the_device():
+    import paper_2411_12365_amd as burr
+    lib = burr.lib()
+    p = burr.Params(bucket=128).c(None)
+    assert lib.burr_build(None, None, 10, 8, ctypes.byref(p)) is None
+    assert lib.burr_last_error() == burr.BURR_E_INVALID
+    p = burr.Params().c(None)
+    assert lib.burr_build(None, None, 10, 0, ctypes.byref(p)) is None
+    assert lib.burr_import(b"not an export", 13, None) is None
+    assert lib.burr_last_error() == burr.BURR_E_INVALID
+
+
+def test_python_binding_fails_loudly_without_library(monkeypatch):
+    import paper_2411_12365_amd as burr
+    monkeypatch.setattr(burr, "_lib", None)
+    monkeypatch.setattr(burr, "LIB_PATH", "/nonexistent/libburr.so")
+    try:
+        burr.lib()
+    except RuntimeError as e:
+        assert "missing" in str(e)
+    else:
+        raise AssertionError("expected a failure")
