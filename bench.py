@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Benchmark: BuRR construction of 100M keys on one MI355X.
+
+One step = one complete burr_build of 100M uniform random 64-bit keys with
+uniform 8-bit values, w = 64, bucket 64, 0.97 slots per key per layer,
+2-bit thresholds, 2^16 equal ranges with boundary bumping, 3 BuRR layers and
+the final plain ribbon layer (every kernel of the path: hash, sort,
+insertion, back-substitution, bumped-key compaction, final layer). Inputs are
+resident in HBM before the timed region. Prints one JSON line.
+
+Also reported (not the headline value): query throughput of 100M mixed
+member/non-member keys, per-kernel device times (hipEvents recorded by the
+library on the build stream), and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+N_KEYS = 100_000_000
+R_BITS = 8
+RANGES = 1 << 16
+
+
+def algorithmic_build_bytes(stats, r):
+    """Bytes the method has to move per build: per layer, read the input
+    keys+values, one grouping pass (read + write), write the solution
+    (m*r/8), the codes (2 bits per bucket) and the bumped keys."""
+    kv = 8 + (1 if r <= 8 else 2 if r <= 16 else 4)
+    total = 0
+    for L in stats["layers"]:
+        total += kv * L["n"] * 3 + L["m"] * r // 8 + L["nbuckets"] // 4 + kv * L["bumped"]
+    total += kv * stats["final_n"] * 3 + stats["final_m"] * r // 8
+    return total
+
+
+def solve_kernel_bytes(L, r):
+    """Algorithmic bytes of one insertion launch: read the 16-byte sorted
+    records and the bucket starts, write every placed row (u64 row + u32
+    value), the occupancy bits, one code byte and one bump count per bucket."""
+    pivots = L["n"] - L["bumped"]
+    return 16 * L["n"] + 4 * (L["nbuckets"] + 1) + 12 * pivots + L["m"] // 8 + 5 * L["nbuckets"]
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes of one launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    runs (profiles/traffic_*.json), or None when the kernel source changed
+    since those counters were taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2411_12365_amd", "csrc", "burr_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
+        rec = json.load(open(path))
+        if rec.get("source_sha256_prefix") == sha and kernel_key in rec.get("kernels", {}):
+            k = rec["kernels"][kernel_key]
+            return k["fetch_bytes"] + k["write_bytes"]
+    return None
+
+
+def cpu_baseline(n_sample):
+    import numpy as np  # noqa: F401
+    import oracle
+    from paper_2411_12365_amd import workload as W
+    keys = W.keys(n_sample, 2)
+    vals = W.values(n_sample, R_BITS, 1002)
+    ranges = max(1, round(RANGES * n_sample / N_KEYS))
+    t0 = time.perf_counter()
+    ref = oracle.build(keys, vals, R_BITS, oracle.Params(ranges=ranges))
+    dt = time.perf_counter() - t0
+    del ref
+    return {
+        "value": round(n_sample / dt / 1e6, 3),
+        "unit": "Mkeys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"first {n_sample:,} keys of the same key/value streams, {ranges} ranges "
+                  f"(same ~23 buckets per range), full build incl. all layers; {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=N_KEYS)
+    ap.add_argument("--queries", type=int, default=N_KEYS)
+    ap.add_argument("--cpu-sample", type=int, default=10_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="after the run, copy this many MiB once (a plain copy kernel of "
+                         "known size, for scaling hardware byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2411_12365_amd as burr
+    from paper_2411_12365_amd import workload as W
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    ranges = max(1, round(RANGES * n / N_KEYS))
+    params = burr.Params(ranges=ranges)
+    keys_np = W.keys(n, 2)
+    vals_np = W.values(n, R_BITS, 1002)
+    keys = torch.from_numpy(keys_np.view(np.int64)).to(dev)
+    vals = torch.from_numpy(vals_np).to(dev)
+    q_np, is_mem, q_idx = W.query_mix(n, args.queries, 2002, 2)
+    qkeys = torch.from_numpy(q_np.view(np.int64)).to(dev)
+    del q_np
+    torch.cuda.synchronize()
+    print(f"# inputs ready: {n} keys, {args.queries} queries", file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        h = burr.build(keys, vals, R_BITS, params)
+        h.free()
+        print(f"# warmup {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+
+    step_s, stats = [], []
+    h = None
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        if h is not None:
+            h.free()
+        ts = time.perf_counter()
+        h = burr.build(keys, vals, R_BITS, params)
+        step_s.append(time.perf_counter() - ts)
+        stats.append(h.stats())
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t0
+    print(f"# timed {args.steps} builds in {total_s:.3f} s", file=sys.stderr, flush=True)
+
+    # correctness spot check of the last build (members retrieve their value)
+    sample = torch.arange(0, n, max(1, n // 1_000_000), device=dev)
+    got = h.query(keys[sample])
+    if not torch.equal(got, vals[sample]):
+        raise SystemExit("member query mismatch")
+
+    # query throughput (events on the stream the library launches on)
+    out = torch.empty(qkeys.numel(), dtype=torch.uint8, device=dev)
+    for _ in range(2):
+        h.query(qkeys, out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    qreps = 5
+    e0.record()
+    for _ in range(qreps):
+        h.query(qkeys, out)
+    e1.record()
+    torch.cuda.synchronize()
+    q_ms = e0.elapsed_time(e1) / qreps
+    mem_idx = torch.from_numpy(q_idx[is_mem]).to(dev)
+    member_ok = bool(torch.equal(out[torch.from_numpy(is_mem).to(dev)], vals[mem_idx]))
+    del mem_idx
+
+    ms = np.array(step_s) * 1e3
+    ms_per_step = total_s * 1e3 / args.steps
+    value = n / (ms_per_step / 1e3) / 1e6
+
+    # per-kernel breakdown (mean over timed steps)
+    def mean(f):
+        return float(np.mean([f(s) for s in stats]))
+    last = stats[-1]
+    nl = last["layers_built"]
+    kernels = {}
+    for li in range(nl):
+        for k in ("ms_sort", "ms_solve", "ms_backsub", "ms_gather"):
+            kernels[f"layer{li}_{k[3:]}_ms"] = round(mean(lambda s: s["layers"][li][k]), 4)
+    kernels["final_layer_ms"] = round(mean(lambda s: s["ms_final"]), 4)
+    kernels["device_total_ms"] = round(mean(lambda s: s["ms_total"]), 4)
+
+    # dominant launch: the layer-0 insertion kernel
+    L0 = last["layers"][0]
+    solve_ms = mean(lambda s: s["layers"][0]["ms_solve"])
+    solve_bytes = solve_kernel_bytes(L0, R_BITS)
+    solve_gbs = solve_bytes / (solve_ms / 1e3) / 1e9
+    roofline = {
+        "kernel": "k_solve (layer 0 insertion)",
+        "bound": "hbm",
+        "achieved": round(solve_gbs, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(solve_gbs / HBM_PEAK_GBS, 4),
+        "traffic": measured_traffic("k_solve_layer0") if n == N_KEYS else None,
+        "bytes_per_launch": solve_bytes,
+        "ms_per_launch": round(solve_ms, 4),
+    }
+    build_bytes = algorithmic_build_bytes(last, R_BITS)
+    build_gbs = build_bytes / (ms_per_step / 1e3) / 1e9
+
+    res = {
+        "metric": "BuRR build Mkeys/s @100M keys r=8 (%HBM peak); batched builds/s; p99 build ms",
+        "value": round(value, 2),
+        "unit": "Mkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"BuRR build, {n:,} uniform random u64 keys (SplitMix64 stream), "
+                        f"r={R_BITS}, w=64, bucket 64, m=0.97n per layer, 2-bit thresholds, "
+                        f"{ranges} ranges with boundary bumping, 3 layers + final plain "
+                        f"ribbon at 1.1n",
+            "n_keys": n, "r": R_BITS, "ranges": ranges, "minbpt": params.minbpt,
+        },
+        "build_ms_p50": round(float(np.percentile(ms, 50)), 3),
+        "build_ms_p99": round(float(np.percentile(ms, 99)), 3),
+        "build_hbm_frac": round(build_gbs / HBM_PEAK_GBS, 4),
+        "build_algorithmic_bytes": build_bytes,
+        "query_Mq_per_s": round(args.queries / (q_ms / 1e3) / 1e6, 1),
+        "query_ms": round(q_ms, 3),
+        "query_members_ok": member_ok,
+        "layers": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in L.items()}
+                   for L in last["layers"]],
+        "final": {"n": last["final_n"], "m": last["final_m"], "attempt": last["final_attempt"]},
+        "kernels": kernels,
+        "roofline": roofline,
+        "cpu_baseline": None,
+        "context": {"paper_cpu_Mkeys_s_100M_64threads": 67.8,
+                    "paper_hw": "AMD EPYC 7551P 32C/64T, b=128, minbpt=1000, 8-bit filter"},
+    }
+    h.free()
+    del keys, vals, qkeys, out
+    if args.calibration_copy_mib:
+        src = torch.ones(args.calibration_copy_mib << 18, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["calibration_copy_bytes"] = 2 * src.numel() * 4
+        del src, dst
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(min(args.cpu_sample, n))
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -85,6 +85,11 @@ typedef struct burr_layer_stats {
   uint64_t nbuckets; /* m / b */
   uint64_t nranges;  /* independently solved ranges */
   uint64_t bumped;   /* keys passed to the next layer */
+  uint64_t steps;    /* XOR-and-shift elimination steps */
+  double ms_sort;    /* device time of the sort kernels (hipEvents) */
+  double ms_solve;   /* device time of the insertion kernel */
+  double ms_backsub; /* device time of back-substitution + code packing */
+  double ms_gather;  /* device time of bumped-key compaction */
 } burr_layer_stats;
 
 typedef struct burr_stats {

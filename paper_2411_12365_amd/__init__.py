@@ -48,7 +48,9 @@ class _CParams(ctypes.Structure):
 
 
 class _CLayerStats(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_uint64) for f in ("n", "m", "nbuckets", "nranges", "bumped")]
+    _fields_ = [(f, ctypes.c_uint64) for f in ("n", "m", "nbuckets", "nranges", "bumped",
+                                                "steps")] + \
+               [(f, ctypes.c_double) for f in ("ms_sort", "ms_solve", "ms_backsub", "ms_gather")]
 
 
 class _CStats(ctypes.Structure):
@@ -236,7 +238,7 @@ def burr_get_stats(h: Handle) -> dict:
     rc = lib().burr_get_stats(h._h, ctypes.byref(st))
     if rc != BURR_OK:
         raise BurrError(rc, "burr_get_stats")
-    layers = [{f: int(getattr(st.layer[i], f)) for f, _ in _CLayerStats._fields_}
+    layers = [{f: getattr(st.layer[i], f) for f, _ in _CLayerStats._fields_}
               for i in range(st.layers_built)]
     return dict(n=st.n, r=st.r, layers_built=st.layers_built, layers=layers,
                 final_n=st.final_n, final_m=st.final_m, final_attempt=st.final_attempt,

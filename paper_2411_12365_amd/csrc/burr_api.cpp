@@ -67,6 +67,7 @@ void keep_pool_memory(int dev) {
 
 struct DevLayer {
   uint64_t n = 0, m = 0, B = 0, R = 0, bumped = 0;
+  double ms_sort = 0, ms_solve = 0, ms_backsub = 0, ms_gather = 0;
   uint64_t ncode = 0, nW = 0;  // words
   uint64_t* codes = nullptr;
   uint64_t* W = nullptr;
@@ -181,7 +182,13 @@ struct Workspace {
     if (n <= cap_keys && keysA) return true;
     cap_keys = std::max<uint64_t>(n, 1);
     return alloc(keysA, cap_keys) && alloc(keysT, cap_keys) && alloc(keysS, cap_keys) &&
-           alloc(valsA, cap_keys) && alloc(valsT, cap_keys) && alloc(rec, cap_keys);
+           alloc(valsA, cap_keys) && alloc(valsT, cap_keys);
+  }
+  uint64_t cap_items = 0;
+  bool reserve_items(uint64_t count) {  // item stream: one record per key + one header per bucket
+    if (count <= cap_items && rec) return true;
+    cap_items = count;
+    return alloc(rec, count);
   }
   bool reserve_slots(uint64_t m) {
     if (m <= cap_m && rowsC) return true;
@@ -251,6 +258,7 @@ int run_sort(Workspace& ws, const uint64_t* keys, const void* vals, uint32_t vby
   a.tmp_keys = ws.keysT;
   a.tmp_vals = ws.valsT;
   a.out_keys = ws.keysS;
+  if (!ws.reserve_items(n + g.nbuckets)) return set_error(BURR_E_NOMEM);
   a.out_rec = ws.rec;
   a.bstart = ws.bstart;
   HIP_TRY(sort_layer(a, s));
@@ -270,12 +278,12 @@ int build_impl(burr_handle* h, const uint64_t* keys, const void* values) {
   const uint64_t fp_salt = mix64(~p.seed);
   Workspace ws(&h->al);
   if (!ws.misc()) return set_error(BURR_E_NOMEM);
-  hipEvent_t ev[4];
+  hipEvent_t ev[6];
   for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
   struct EvGuard {
     hipEvent_t* e;
     ~EvGuard() {
-      for (int i = 0; i < 4; i++) (void)hipEventDestroy(e[i]);
+      for (int i = 0; i < 6; i++) (void)hipEventDestroy(e[i]);
     }
   } evg{ev};
   HIP_TRY(hipEventRecord(ev[0], s));
@@ -306,7 +314,6 @@ int build_impl(burr_handle* h, const uint64_t* keys, const void* values) {
     int rc = run_sort(ws, cur_keys, cur_vals, cur_vbytes, first, p.filter_mode != 0, fp_salt,
                       cur_n, g, s);
     if (rc != BURR_OK) return rc;
-    HIP_TRY(hipEventRecord(ev[2], s));
 
     SolveArgs sa{};
     sa.rec = ws.rec;
@@ -319,10 +326,12 @@ int build_impl(burr_handle* h, const uint64_t* keys, const void* values) {
     sa.bump = ws.bump;
     sa.fail = ws.fail;
     sa.steps = ws.steps;
-    sa.nrec = (uint32_t)cur_n;
+    sa.nrec = (uint32_t)(cur_n + g.nbuckets);
     HIP_TRY(hipMemsetAsync(ws.steps, 0, 8, s));
     HIP_TRY(hipMemsetAsync(ws.fail, 0, 4, s));
+    HIP_TRY(hipEventRecord(ev[2], s));
     HIP_TRY(solve_layer(sa, s));
+    HIP_TRY(hipEventRecord(ev[4], s));
 
     L.ncode = (g.nbuckets + 31) / 32;
     L.nW = (g.m / 64) * r;
@@ -343,13 +352,18 @@ int build_impl(burr_handle* h, const uint64_t* keys, const void* values) {
     HIP_TRY(hipMemcpyAsync(&steps, ws.steps, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(gather_bumped(ws.keysS, ws.rec, ws.bstart, ws.bump, g.nbuckets, ws.keysA, ws.valsA,
                           s));
+    HIP_TRY(hipEventRecord(ev[5], s));
     HIP_TRY(hipStreamSynchronize(s));
     if (failed) {
       fprintf(stderr, "burr: internal error: a row left its range in layer %u\n", li);
       return set_error(BURR_E_DEVICE);
     }
-    ms_sort += elapsed_ms(ev[1], ev[2]);
-    ms_solve += elapsed_ms(ev[2], ev[3]);
+    L.ms_sort = elapsed_ms(ev[1], ev[2]);
+    L.ms_solve = elapsed_ms(ev[2], ev[4]);
+    L.ms_backsub = elapsed_ms(ev[4], ev[3]);
+    L.ms_gather = elapsed_ms(ev[3], ev[5]);
+    ms_sort += L.ms_sort;
+    ms_solve += L.ms_solve + L.ms_backsub;
     L.bumped = nnext;
     L.steps = steps;
     cur_n = nnext;
@@ -393,7 +407,7 @@ int build_impl(burr_handle* h, const uint64_t* keys, const void* values) {
       sa.occ = ws.occ;
       sa.fail = ws.fail;
       sa.steps = ws.steps;
-      sa.nrec = (uint32_t)cur_n;
+      sa.nrec = (uint32_t)(cur_n + g.nbuckets);
       HIP_TRY(solve_layer(sa, s));
       uint32_t failed = 0;
       uint64_t steps = 0;
@@ -428,6 +442,11 @@ int build_impl(burr_handle* h, const uint64_t* keys, const void* values) {
     st.layer[i].nbuckets = h->layer[i].B;
     st.layer[i].nranges = h->layer[i].R;
     st.layer[i].bumped = h->layer[i].bumped;
+    st.layer[i].steps = h->layer[i].steps;
+    st.layer[i].ms_sort = h->layer[i].ms_sort;
+    st.layer[i].ms_solve = h->layer[i].ms_solve;
+    st.layer[i].ms_backsub = h->layer[i].ms_backsub;
+    st.layer[i].ms_gather = h->layer[i].ms_gather;
     bytes += (h->layer[i].ncode + h->layer[i].nW) * 8;
   }
   st.final_n = F.n;

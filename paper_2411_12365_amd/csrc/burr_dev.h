@@ -53,12 +53,19 @@ __device__ inline uint32_t rank_of(uint32_t o, const LayerGeom& g) {
   return o >= g.t_hi ? 0u : (o >= g.t_lo ? 1u : 2u);
 }
 
-// Sorted record of one key: the row and a meta word
-//   meta bits  0..31: value, 32..37: offset in bucket, 40..41: rank
+// One 16-byte element of a layer's item stream. The stream holds, for every
+// bucket in order, a header item followed by the bucket's records:
+//   header : c = number of records | (forced threshold index << 32), meta = 0
+//   record : c = coefficient row, meta = value (bits 0..31) | offset in the
+//            bucket (bits 32..37) | rank (bits 40..41)
+// The record of sorted key position p in bucket beta sits at item p+beta+1,
+// the header of bucket beta at item bstart[beta]+beta.
 struct alignas(16) Rec {
   uint64_t c;
   uint64_t meta;
 };
+__device__ inline uint32_t head_count(const Rec& h) { return (uint32_t)h.c; }
+__device__ inline uint32_t head_kf(const Rec& h) { return (uint32_t)(h.c >> 32) & 3u; }
 
 __device__ inline uint32_t meta_value(uint64_t meta) { return (uint32_t)meta; }
 __device__ inline uint32_t meta_offset(uint64_t meta) { return (uint32_t)(meta >> 32) & 63u; }

@@ -161,22 +161,39 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_scatter(
   }
 }
 
+// Forced threshold index of bucket beta: the last bucket of a range that is
+// not the last one must bump every key that starts past its first slot
+// (b = w = 64), so its threshold is the smallest 2-bit value above the largest
+// offset of such a key (Sec. 3 "Bumping").
+__device__ inline uint32_t forced_kf(uint64_t beta, uint32_t maxoff, uint32_t count,
+                                     const LayerGeom& g) {
+  if (g.plain || count == 0 || maxoff == 0) return 0;
+  const uint64_t rho = ((beta + 1) * g.nranges - 1) / g.nbuckets;
+  if (rho + 1 >= g.nranges) return 0;
+  if ((rho + 1) * g.nbuckets / g.nranges != beta + 1) return 0;
+  return maxoff >= g.t_hi ? 3u : (maxoff >= g.t_lo ? 2u : 1u);
+}
+
 __global__ __launch_bounds__(kL2Threads) void k_l2_sort(
     const uint64_t* __restrict__ tk, const uint32_t* __restrict__ tv, uint64_t n, LayerGeom g,
     uint32_t nbins, uint32_t groups, const uint32_t* __restrict__ offs,
-    uint64_t* __restrict__ ok, Rec* __restrict__ orec, uint32_t* __restrict__ bstart) {
+    uint64_t* __restrict__ ok, Rec* __restrict__ items, uint32_t* __restrict__ bstart) {
   __shared__ uint32_t hist[kDigitsPerBin];
+  __shared__ uint32_t maxoff[kBucketsPerBin];
   __shared__ uint32_t wsum[kL2Threads / 64];
   const uint32_t bin = blockIdx.x;
   const uint64_t lo = offs[(size_t)bin * groups];
   const uint64_t hi = bin + 1 < nbins ? offs[(size_t)(bin + 1) * groups] : n;
   const uint64_t bbase = (uint64_t)bin * kBucketsPerBin;
   for (uint32_t i = threadIdx.x; i < kDigitsPerBin; i += kL2Threads) hist[i] = 0;
+  for (uint32_t i = threadIdx.x; i < kBucketsPerBin; i += kL2Threads) maxoff[i] = 0;
   __syncthreads();
   for (uint64_t i = lo + threadIdx.x; i < hi; i += kL2Threads) {
     const uint64_t s = start_of(tk[i], g);
-    const uint32_t d = (uint32_t)((s >> 6) - bbase) * 3u + rank_of((uint32_t)s & 63u, g);
-    atomicAdd(&hist[d], 1u);
+    const uint32_t b = (uint32_t)((s >> 6) - bbase);
+    const uint32_t o = (uint32_t)s & 63u;
+    atomicAdd(&hist[b * 3u + rank_of(o, g)], 1u);
+    atomicMax(&maxoff[b], o);
   }
   __syncthreads();
   // exclusive scan of the 6144 digit counts, 12 per thread
@@ -195,9 +212,18 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_sort(
     run += loc[k];
   }
   __syncthreads();
+  // bucket starts and bucket headers
   for (uint32_t b = threadIdx.x; b < kBucketsPerBin; b += kL2Threads) {
     const uint64_t beta = bbase + b;
-    if (beta < g.nbuckets) bstart[beta] = (uint32_t)(lo + hist[3 * b]);
+    if (beta >= g.nbuckets) continue;
+    const uint32_t first = hist[3 * b];
+    const uint32_t next = (b + 1 < kBucketsPerBin) ? hist[3 * b + 3] : (uint32_t)(hi - lo);
+    const uint32_t count = next - first;
+    bstart[beta] = (uint32_t)(lo + first);
+    Rec hd;
+    hd.c = (uint64_t)count | ((uint64_t)forced_kf(beta, maxoff[b], count, g) << 32);
+    hd.meta = 0;
+    items[lo + first + beta] = hd;
   }
   if (bin + 1 == nbins && threadIdx.x == 0) bstart[g.nbuckets] = (uint32_t)hi;
   __syncthreads();
@@ -206,13 +232,14 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_sort(
     const uint64_t s = start_of(key, g);
     const uint32_t o = (uint32_t)s & 63u;
     const uint32_t rk = rank_of(o, g);
-    const uint32_t d = (uint32_t)((s >> 6) - bbase) * 3u + rk;
+    const uint64_t beta = s >> 6;
+    const uint32_t d = (uint32_t)(beta - bbase) * 3u + rk;
     const uint64_t pos = lo + atomicAdd(&hist[d], 1u);
     ok[pos] = key;
     Rec rc;
     rc.c = row_of(key, g);
     rc.meta = (uint64_t)tv[i] | ((uint64_t)o << 32) | ((uint64_t)rk << 40);
-    orec[pos] = rc;
+    items[pos + beta + 1] = rc;
   }
 }
 
@@ -252,22 +279,36 @@ hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Solve: one lane per range
 // ---------------------------------------------------------------------------
+// Every lane owns one range and walks its item stream bucket by bucket. The
+// hot loop touches LDS only: the 128-row ring (coefficient rows and values)
+// and a FIFO of the next kFifo items per lane. Global loads are issued once
+// per round of kRoundIters iterations into registers and written to the FIFO
+// at the next round, so no wave waits on a global load inside a round.
 enum : uint32_t {
   ST_ELIM = 0,      // eliminating the current equation
   ST_PLACE = 1,     // found an empty slot at i
   ST_REDUNDANT = 2, // reduced to 0 = 0
   ST_CONFLICT = 3,  // reduced to 0 = v with v != 0
-  ST_NEXT = 4,      // fetch the next record of the bucket
-  ST_BEND = 5,      // finish the current bucket
-  ST_BSTART = 6,    // start the next bucket
+  ST_NEXT = 4,      // take the next record of the bucket, or end the bucket
+  ST_BEND = 5,      // publish the bucket's threshold code and bump count
+  ST_BHEAD = 6,     // take the next bucket header
   ST_DONE = 7
 };
 
+constexpr int kFifo = 8;  // must match the 8 staged registers below
+constexpr int kRoundIters = 16;
+
+template <typename VT>
+constexpr size_t solve_lds_bytes() {
+  return kRing * 64 * sizeof(uint64_t) + kFifo * 64 * sizeof(Rec) + kRing * 64 * sizeof(VT);
+}
+
 template <typename VT, int K>
-__global__ __launch_bounds__(64) void k_solve(SolveArgs a, uint32_t total) {
+__global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
   extern __shared__ uint64_t lds[];
   uint64_t* ringC = lds;                                  // [kRing][64]
-  VT* ringV = reinterpret_cast<VT*>(lds + kRing * 64);    // [kRing][64]
+  Rec* fifo = reinterpret_cast<Rec*>(lds + kRing * 64);   // [kFifo][64]
+  VT* ringV = reinterpret_cast<VT*>(fifo + kFifo * 64);   // [kRing][64]
   const LayerGeom g = a.g;
   const uint32_t lane = threadIdx.x;
   const uint64_t rho = (uint64_t)blockIdx.x * 64 + lane;
@@ -275,173 +316,190 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a, uint32_t total) {
   uint32_t state = ST_DONE;
   uint64_t fb = 0;
   uint32_t nq = 0;
-  bool last_range = true;
+  uint32_t x = 0, xend = 0;  // item cursor and end of the range's items
   if (rho < g.nranges) {
     fb = rho * g.nbuckets / g.nranges;
     nq = (uint32_t)((rho + 1) * g.nbuckets / g.nranges - fb);
-    last_range = (rho + 1 == g.nranges);
-    state = ST_BSTART;
+    x = a.bstart[fb] + (uint32_t)fb;
+    xend = a.bstart[fb + nq] + (uint32_t)(fb + nq);
+    state = ST_BHEAD;
   }
   const uint64_t P0 = fb * 64;
-  uint32_t q = 0;                 // bucket index inside the range
-  uint32_t t = 0, lo = 0, hi = 0; // record cursor, bucket record interval
-  uint32_t nbs = 0;               // prefetched bstart of the bucket after next
+  uint32_t q = 0xffffffffu;  // bucket index inside the range
+  uint32_t rend = 0;         // item index past the current bucket's records
   uint32_t kf = 0, code = 0, curk = 4, chunk_start = 0, split_at = 0;
   uint32_t i = 0, v = 0;
   uint64_t c = 0;
-  uint64_t vm0 = 0, vm1 = 0;      // valid ring rows (bit p <-> ring position p)
-  uint64_t pm0 = 0, pm1 = 0;      // rows placed by the current chunk
-  Rec nrec = {0, 0};
-  uint32_t nidx = 0xffffffffu;
+  uint64_t vm0 = 0, vm1 = 0;  // valid ring rows (bit p <-> ring position p)
+  uint64_t pm0 = 0, pm1 = 0;  // rows placed by the current chunk
   uint64_t steps = 0;
 
+  // FIFO state: items [x, written) are in LDS. Each round loads the next
+  // items into registers and commits them to LDS at the end of the round, so
+  // the loads have a whole round to land.
+  uint32_t written = x;
+  const uint32_t last_item = a.nrec - 1;
+  const uint4* rec4 = reinterpret_cast<const uint4*>(a.rec);
+  uint4* fifo4 = reinterpret_cast<uint4*>(fifo);
+
   while (true) {
+    const uint32_t ld0 = written > x ? written : x;
+    const uint32_t ld1 = (x + kFifo < xend) ? x + kFifo : xend;
+    const uint32_t ldn = ld1 > ld0 ? ld1 - ld0 : 0;
+    // unconditional loads (clamped index) into named registers: a
+    // conditional load, or an array, makes the compiler copy or spill the
+    // value and wait for it at once
+#define BURR_STAGE_LOAD(j) \
+    const uint4 st##j = rec4[ld0 + j < last_item ? ld0 + j : last_item];
+    BURR_STAGE_LOAD(0) BURR_STAGE_LOAD(1) BURR_STAGE_LOAD(2) BURR_STAGE_LOAD(3)
+    BURR_STAGE_LOAD(4) BURR_STAGE_LOAD(5) BURR_STAGE_LOAD(6) BURR_STAGE_LOAD(7)
+#undef BURR_STAGE_LOAD
+
+    for (int it = 0; it < kRoundIters; ++it) {
 #pragma unroll
-    for (int u = 0; u < K; ++u) {
-      if (state == ST_ELIM) {
-        const uint32_t p = i & (kRing - 1);
-        const uint64_t row = ringC[p * 64 + lane];
-        const uint32_t rv = ringV[p * 64 + lane];
-        const uint64_t vmw = (p & 64) ? vm1 : vm0;
-        if (((vmw >> (p & 63)) & 1ull) == 0) {
-          state = ST_PLACE;
-        } else {
-          ++steps;
-          c ^= row;
-          v ^= rv;
-          if (c == 0) {
-            state = (v == 0) ? ST_REDUNDANT : ST_CONFLICT;
+      for (int u = 0; u < K; ++u) {
+        if (state == ST_ELIM) {
+          const uint32_t p = i & (kRing - 1);
+          const uint64_t row = ringC[p * 64 + lane];
+          const uint32_t rv = ringV[p * 64 + lane];
+          const uint64_t vmw = (p & 64) ? vm1 : vm0;
+          if (((vmw >> (p & 63)) & 1ull) == 0) {
+            state = ST_PLACE;
           } else {
-            const uint32_t j = (uint32_t)__builtin_ctzll(c);
-            c >>= j;
-            i += j;
-          }
-        }
-      }
-    }
-
-    if (state == ST_PLACE && i >= 64u * nq) {
-      // unreachable for kept keys (their rows end inside the range); stop
-      // the lane instead of writing outside it
-      *a.fail = 2u;
-      state = ST_DONE;
-    }
-    if (state == ST_PLACE) {
-      const uint32_t p = i & (kRing - 1);
-      ringC[p * 64 + lane] = c;
-      ringV[p * 64 + lane] = (VT)v;
-      const uint64_t bit = 1ull << (p & 63);
-      if (p & 64) {
-        vm1 |= bit;
-        pm1 |= bit;
-      } else {
-        vm0 |= bit;
-        pm0 |= bit;
-      }
-      a.rowsC[P0 + i] = c;
-      a.rowsV[P0 + i] = v;
-      state = ST_NEXT;
-    } else if (state == ST_REDUNDANT) {
-      state = ST_NEXT;
-    } else if (state == ST_CONFLICT) {
-      if (g.plain) {
-        *a.fail = 1u;
-        state = ST_DONE;
-      } else {
-        vm0 &= ~pm0;  // undo the chunk
-        vm1 &= ~pm1;
-        code = curk;
-        split_at = chunk_start;
-        state = ST_BEND;
-      }
-    }
-
-    while (state >= ST_NEXT && state != ST_DONE) {
-      if (state == ST_NEXT) {
-        ++t;
-        if (t >= hi) {
-          split_at = hi;
-          state = ST_BEND;
-        } else {
-          const Rec rc = (t == nidx) ? nrec : a.rec[t];
-          if (t + 1 < total) {
-            nrec = a.rec[t + 1];
-            nidx = t + 1;
-          }
-          const uint32_t k = 3u - meta_rank(rc.meta);
-          if (k <= kf) {
-            split_at = t;
-            state = ST_BEND;
-          } else {
-            if (k != curk) {
-              pm0 = 0;
-              pm1 = 0;
-              curk = k;
-              chunk_start = t;
+            ++steps;
+            c ^= row;
+            v ^= rv;
+            if (c == 0) {
+              state = (v == 0) ? ST_REDUNDANT : ST_CONFLICT;
+            } else {
+              const uint32_t j = (uint32_t)__builtin_ctzll(c);
+              c >>= j;
+              i += j;
             }
-            c = rc.c;
-            v = meta_value(rc.meta);
-            i = 64u * q + meta_offset(rc.meta);
-            state = ST_ELIM;
           }
         }
       }
-      if (state == ST_BEND) {
-        const uint64_t beta = fb + q;
-        if (!g.plain) {
-          a.code8[beta] = (uint8_t)code;
-          a.bump[beta] = hi - split_at;
+
+      if (state == ST_PLACE && i >= 64u * nq) {
+        // unreachable for kept keys (their rows end inside the range); stop
+        // the lane instead of writing outside it
+        *a.fail = 2u;
+        state = ST_DONE;
+      }
+      if (state == ST_PLACE) {
+        const uint32_t p = i & (kRing - 1);
+        ringC[p * 64 + lane] = c;
+        ringV[p * 64 + lane] = (VT)v;
+        const uint64_t bit = 1ull << (p & 63);
+        if (p & 64) {
+          vm1 |= bit;
+          pm1 |= bit;
+        } else {
+          vm0 |= bit;
+          pm0 |= bit;
         }
-        ++q;
-        if (q == nq) {
-          a.occ[beta] = ((q - 1) & 1) ? vm1 : vm0;
+        a.rowsC[P0 + i] = c;
+        a.rowsV[P0 + i] = v;
+        state = ST_NEXT;
+      } else if (state == ST_REDUNDANT) {
+        state = ST_NEXT;
+      } else if (state == ST_CONFLICT) {
+        if (g.plain) {
+          *a.fail = 1u;
           state = ST_DONE;
         } else {
-          state = ST_BSTART;
+          vm0 &= ~pm0;  // undo the chunk
+          vm1 &= ~pm1;
+          code = curk;
+          split_at = chunk_start;
+          state = ST_BEND;
         }
       }
-      if (state == ST_BSTART) {
-        const uint64_t beta = fb + q;
-        if (q == 0) {
-          lo = a.bstart[beta];
-          hi = a.bstart[beta + 1];
+
+      // transitions; a lane whose next item has not reached the FIFO waits
+      bool go = true;
+#pragma unroll 1
+      for (int tr = 0; tr < 6 && go; ++tr) {
+        if (state == ST_NEXT) {
+          if (x == rend) {
+            split_at = rend;
+            state = ST_BEND;
+          } else if (x < written) {
+            const Rec rc = fifo[(x % kFifo) * 64 + lane];
+            const uint32_t y = x++;
+            const uint32_t k = 3u - meta_rank(rc.meta);
+            if (k <= kf) {
+              split_at = y;
+              state = ST_BEND;
+            } else {
+              if (k != curk) {
+                pm0 = 0;
+                pm1 = 0;
+                curk = k;
+                chunk_start = y;
+              }
+              c = rc.c;
+              v = meta_value(rc.meta);
+              i = 64u * q + meta_offset(rc.meta);
+              state = ST_ELIM;
+              go = false;
+            }
+          } else {
+            go = false;
+          }
+        } else if (state == ST_BEND) {
+          const uint64_t beta = fb + q;
+          if (!g.plain) {
+            a.code8[beta] = (uint8_t)code;
+            a.bump[beta] = rend - split_at;
+          }
+          x = rend;  // skip the bumped rest of the bucket
+          if (q + 1 == nq) {
+            a.occ[beta] = (q & 1) ? vm1 : vm0;
+            state = ST_DONE;
+            go = false;
+          } else {
+            state = ST_BHEAD;
+          }
+        } else if (state == ST_BHEAD) {
+          if (x < written) {
+            const Rec hd = fifo[(x % kFifo) * 64 + lane];
+            ++q;
+            if (q >= 1) {
+              // bucket q-1 is final: publish its occupancy, free its ring half
+              const uint64_t beta = fb + q - 1;
+              if ((q - 1) & 1) {
+                a.occ[beta] = vm1;
+                vm1 = 0;
+              } else {
+                a.occ[beta] = vm0;
+                vm0 = 0;
+              }
+            }
+            kf = head_kf(hd);
+            code = kf;
+            curk = 4;
+            pm0 = 0;
+            pm1 = 0;
+            rend = x + 1 + head_count(hd);
+            ++x;
+            chunk_start = x;
+            state = ST_NEXT;
+          } else {
+            go = false;
+          }
         } else {
-          lo = hi;
-          hi = nbs;
-          // bucket q-1 is final: publish its occupancy and free its ring half
-          if ((q - 1) & 1) {
-            a.occ[beta - 1] = vm1;
-            vm1 = 0;
-          } else {
-            a.occ[beta - 1] = vm0;
-            vm0 = 0;
-          }
+          go = false;
         }
-        if (q + 1 < nq) nbs = a.bstart[beta + 2];
-        kf = 0;
-        if (!g.plain && !last_range && q + 1 == nq && lo < hi) {
-          // The last bucket of a range: keys starting past its first slot
-          // would cross the range end (b = w = 64) and must be bumped; the
-          // threshold is the smallest value above the largest such offset.
-          const uint32_t rk = meta_rank(a.rec[lo].meta);
-          if (rk == 0) {
-            kf = 3;
-          } else if (rk == 1) {
-            kf = 2;
-          } else {
-            for (uint32_t x = lo; x < hi; ++x)
-              if (meta_offset(a.rec[x].meta) >= 1) kf = 1;
-          }
-        }
-        code = kf;
-        curk = 4;
-        pm0 = 0;
-        pm1 = 0;
-        chunk_start = lo;
-        t = lo - 1u;
-        state = ST_NEXT;
       }
     }
+    // ---- round end: commit this round's loads to the FIFO ----
+#define BURR_STAGE_COMMIT(j) \
+    if (j < ldn) fifo4[((ld0 + j) % kFifo) * 64 + lane] = st##j;
+    BURR_STAGE_COMMIT(0) BURR_STAGE_COMMIT(1) BURR_STAGE_COMMIT(2) BURR_STAGE_COMMIT(3)
+    BURR_STAGE_COMMIT(4) BURR_STAGE_COMMIT(5) BURR_STAGE_COMMIT(6) BURR_STAGE_COMMIT(7)
+#undef BURR_STAGE_COMMIT
+    if (ldn) written = ld0 + ldn;
     if (!__any(state != ST_DONE)) break;
   }
   if (a.steps) atomicAdd((unsigned long long*)a.steps, (unsigned long long)steps);
@@ -450,20 +508,20 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a, uint32_t total) {
 hipError_t solve_layer(const SolveArgs& a, hipStream_t s) {
   const unsigned blocks = (unsigned)((a.g.nranges + 63) / 64);
   if (a.g.r <= 8) {
-    const size_t lds = kRing * 64 * (sizeof(uint64_t) + 1);
+    const size_t lds = solve_lds_bytes<uint8_t>();
     (void)hipFuncSetAttribute((const void*)k_solve<uint8_t, 4>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_solve<uint8_t, 4><<<blocks, 64, lds, s>>>(a, a.nrec);
+    k_solve<uint8_t, 4><<<blocks, 64, lds, s>>>(a);
   } else if (a.g.r <= 16) {
-    const size_t lds = kRing * 64 * (sizeof(uint64_t) + 2);
+    const size_t lds = solve_lds_bytes<uint16_t>();
     (void)hipFuncSetAttribute((const void*)k_solve<uint16_t, 4>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_solve<uint16_t, 4><<<blocks, 64, lds, s>>>(a, a.nrec);
+    k_solve<uint16_t, 4><<<blocks, 64, lds, s>>>(a);
   } else {
-    const size_t lds = kRing * 64 * (sizeof(uint64_t) + 4);
+    const size_t lds = solve_lds_bytes<uint32_t>();
     (void)hipFuncSetAttribute((const void*)k_solve<uint32_t, 4>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_solve<uint32_t, 4><<<blocks, 64, lds, s>>>(a, a.nrec);
+    k_solve<uint32_t, 4><<<blocks, 64, lds, s>>>(a);
   }
   return hipGetLastError();
 }
@@ -557,7 +615,7 @@ __global__ void k_gather(const uint64_t* __restrict__ sorted_keys, const Rec* __
   const uint32_t src = bstart[beta + 1] - cnt;
   for (uint32_t j = 0; j < cnt; ++j) {
     nk[o + j] = sorted_keys[src + j];
-    nv[o + j] = meta_value(rec[src + j].meta);
+    nv[o + j] = meta_value(rec[src + j + beta + 1].meta);
   }
 }
 

@@ -51,9 +51,10 @@ def non_members(n_members: int, q: int, seed: int) -> np.ndarray:
 
 
 def query_mix(n_members: int, q: int, seed: int, key_seed: int,
-              member_frac: float = 0.5) -> tuple[np.ndarray, np.ndarray]:
+              member_frac: float = 0.5) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
     """q queries, each a member (uniform index, with replacement) with
-    probability member_frac, else a non-member. Returns (keys, is_member)."""
+    probability member_frac, else a non-member. Returns (keys, is_member,
+    member index or -1)."""
     rng = np.random.default_rng(seed)
     is_mem = rng.random(q) < member_frac
     idx = rng.integers(0, max(n_members, 1), size=q, dtype=np.int64)
@@ -64,7 +65,8 @@ def query_mix(n_members: int, q: int, seed: int, key_seed: int,
         is_mem[:] = False
     nm = int((~is_mem).sum())
     out[~is_mem] = splitmix64(key_seed, n_members, nm)
-    return out, is_mem
+    idx[~is_mem] = -1
+    return out, is_mem, idx
 
 
 def _gather_stream(seed: int, idx: np.ndarray) -> np.ndarray:
