@@ -327,7 +327,7 @@ int build_impl(burr_handle* h, const uint64_t* keys, const void* values) {
     sa.fail = ws.fail;
     sa.steps = ws.steps;
     sa.nrec = (uint32_t)(cur_n + g.nbuckets);
-    HIP_TRY(hipMemsetAsync(ws.steps, 0, 8, s));
+    HIP_TRY(hipMemsetAsync(ws.steps, 0, 64, s));
     HIP_TRY(hipMemsetAsync(ws.fail, 0, 4, s));
     HIP_TRY(hipEventRecord(ev[2], s));
     HIP_TRY(solve_layer(sa, s));
@@ -354,8 +354,17 @@ int build_impl(burr_handle* h, const uint64_t* keys, const void* values) {
                           s));
     HIP_TRY(hipEventRecord(ev[5], s));
     HIP_TRY(hipStreamSynchronize(s));
+#ifdef BURR_SOLVE_DEBUG
+    {
+      uint64_t d[4];
+      if (hipMemcpy(d, ws.steps, 32, hipMemcpyDeviceToHost) == hipSuccess)
+        fprintf(stderr, "solve-debug layer %u: steps %llu lane-iters %llu elim-iters %llu want-iters %llu\n",
+                li, (unsigned long long)d[0], (unsigned long long)d[1], (unsigned long long)d[2],
+                (unsigned long long)d[3]);
+    }
+#endif
     if (failed) {
-      fprintf(stderr, "burr: internal error: a row left its range in layer %u\n", li);
+      fprintf(stderr, "burr: internal error %u in the insertion kernel, layer %u\n", failed, li);
       return set_error(BURR_E_DEVICE);
     }
     L.ms_sort = elapsed_ms(ev[1], ev[2]);
@@ -415,7 +424,10 @@ int build_impl(burr_handle* h, const uint64_t* keys, const void* values) {
       HIP_TRY(hipMemcpyAsync(&steps, ws.steps, 8, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       F.steps += steps;
-      if (failed == 2) return set_error(BURR_E_DEVICE);
+      if (failed >= 2) {
+        fprintf(stderr, "burr: internal error %u in the final layer\n", failed);
+        return set_error(BURR_E_DEVICE);
+      }
       if (failed) continue;
       F.m = g.m;
       F.nW = (g.m / 64) * r;

@@ -279,24 +279,35 @@ hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Solve: one lane per range
 // ---------------------------------------------------------------------------
-// Every lane owns one range and walks its item stream bucket by bucket. The
-// hot loop touches LDS only: the 128-row ring (coefficient rows and values)
-// and a FIFO of the next kFifo items per lane. Global loads are issued once
-// per round of kRoundIters iterations into registers and written to the FIFO
-// at the next round, so no wave waits on a global load inside a round.
+// Every lane owns one range and walks its item stream (a header per bucket,
+// then the bucket's records). The hot loop touches LDS only: the 128-row ring
+// (coefficient rows and values) and a FIFO of the lane's next kFifo items.
+// Global loads are issued once per round of kRoundIters iterations into
+// registers and committed to the FIFO at the end of the round, so no wave
+// waits on a global load inside a round.
+//
+// One iteration = K elimination steps for every lane still eliminating, then
+// the outcome of finished equations, then the lanes that need their next item
+// take it (usually the next record of the same bucket; bucket ends and
+// headers are the rare path).
 enum : uint32_t {
   ST_ELIM = 0,      // eliminating the current equation
   ST_PLACE = 1,     // found an empty slot at i
   ST_REDUNDANT = 2, // reduced to 0 = 0
   ST_CONFLICT = 3,  // reduced to 0 = v with v != 0
-  ST_NEXT = 4,      // take the next record of the bucket, or end the bucket
-  ST_BEND = 5,      // publish the bucket's threshold code and bump count
-  ST_BHEAD = 6,     // take the next bucket header
-  ST_DONE = 7
+  ST_WANT = 4,      // needs item x
+  ST_DONE = 5
 };
 
+#ifndef BURR_ROUND_ITERS
+#define BURR_ROUND_ITERS 4
+#endif
+#ifndef BURR_SOLVE_K
+#define BURR_SOLVE_K 8
+#endif
 constexpr int kFifo = 8;  // must match the 8 staged registers below
-constexpr int kRoundIters = 16;
+constexpr int kRoundIters = BURR_ROUND_ITERS;
+constexpr uint32_t kNoSplit = 0xffffffffu;
 
 template <typename VT>
 constexpr size_t solve_lds_bytes() {
@@ -322,22 +333,28 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     nq = (uint32_t)((rho + 1) * g.nbuckets / g.nranges - fb);
     x = a.bstart[fb] + (uint32_t)fb;
     xend = a.bstart[fb + nq] + (uint32_t)(fb + nq);
-    state = ST_BHEAD;
+    state = ST_WANT;
   }
   const uint64_t P0 = fb * 64;
-  uint32_t q = 0xffffffffu;  // bucket index inside the range
-  uint32_t rend = 0;         // item index past the current bucket's records
-  uint32_t kf = 0, code = 0, curk = 4, chunk_start = 0, split_at = 0;
+  const uint32_t limit = 64u * nq;  // rows of kept keys end inside the range
+  uint32_t q = 0xffffffffu;   // bucket index inside the range
+  uint32_t rend = x;          // item index past the current bucket's records
+  bool open = false;          // a bucket is being processed
+  uint32_t kf = 0, code = 0, curk = 4, chunk_start = 0, split_at = kNoSplit;
   uint32_t i = 0, v = 0;
   uint64_t c = 0;
   uint64_t vm0 = 0, vm1 = 0;  // valid ring rows (bit p <-> ring position p)
   uint64_t pm0 = 0, pm1 = 0;  // rows placed by the current chunk
   uint64_t steps = 0;
+#ifdef BURR_SOLVE_DEBUG
+  uint64_t dbg_active = 0, dbg_elim = 0, dbg_stall = 0;
+#endif
 
-  // FIFO state: items [x, written) are in LDS. Each round loads the next
-  // items into registers and commits them to LDS at the end of the round, so
-  // the loads have a whole round to land.
-  uint32_t written = x;
+  // Each item needs at most 64 elimination steps, so a lane is done after
+  // far fewer iterations than this cap; reaching it means a logic error, and
+  // the lane stops (fail = 3) instead of keeping the wave alive.
+  uint64_t iter_left = (uint64_t)(xend - x) * 80u + 4096u;
+  uint32_t written = x;  // items [x, written) are in the FIFO
   const uint32_t last_item = a.nrec - 1;
   const uint4* rec4 = reinterpret_cast<const uint4*>(a.rec);
   uint4* fifo4 = reinterpret_cast<uint4*>(fifo);
@@ -356,140 +373,157 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
 #undef BURR_STAGE_LOAD
 
     for (int it = 0; it < kRoundIters; ++it) {
-#pragma unroll
-      for (int u = 0; u < K; ++u) {
-        if (state == ST_ELIM) {
-          const uint32_t p = i & (kRing - 1);
-          const uint64_t row = ringC[p * 64 + lane];
-          const uint32_t rv = ringV[p * 64 + lane];
-          const uint64_t vmw = (p & 64) ? vm1 : vm0;
-          if (((vmw >> (p & 63)) & 1ull) == 0) {
-            state = ST_PLACE;
-          } else {
-            ++steps;
-            c ^= row;
-            v ^= rv;
-            if (c == 0) {
-              state = (v == 0) ? ST_REDUNDANT : ST_CONFLICT;
-            } else {
-              const uint32_t j = (uint32_t)__builtin_ctzll(c);
-              c >>= j;
-              i += j;
-            }
-          }
-        }
-      }
-
-      if (state == ST_PLACE && i >= 64u * nq) {
-        // unreachable for kept keys (their rows end inside the range); stop
-        // the lane instead of writing outside it
-        *a.fail = 2u;
+      if (state != ST_DONE && iter_left-- == 0) {
+        *a.fail = 3u;
         state = ST_DONE;
       }
-      if (state == ST_PLACE) {
+#ifdef BURR_SOLVE_DEBUG
+      dbg_active += state != ST_DONE;
+      dbg_elim += state == ST_ELIM;
+      dbg_stall += state == ST_WANT;
+#endif
+      // ---- K elimination steps ----
+      // branch-free: every lane reads its ring row; selects keep the state
+      // of lanes that are not eliminating
+#pragma unroll
+      for (int u = 0; u < K; ++u) {
         const uint32_t p = i & (kRing - 1);
-        ringC[p * 64 + lane] = c;
-        ringV[p * 64 + lane] = (VT)v;
-        const uint64_t bit = 1ull << (p & 63);
-        if (p & 64) {
-          vm1 |= bit;
-          pm1 |= bit;
+        const uint64_t row = ringC[p * 64 + lane];
+        const uint32_t rv = ringV[p * 64 + lane];
+        const uint64_t vmw = (p & 64) ? vm1 : vm0;
+        const bool elim = state == ST_ELIM;
+        const bool valid = ((vmw >> (p & 63)) & 1ull) != 0;
+        const uint64_t cx = c ^ row;
+        const uint32_t vx = v ^ rv;
+        const bool cont = elim && valid && cx != 0;
+        const uint32_t j = (uint32_t)__builtin_ctzg(cx, 64);  // defined for cx == 0
+        const uint32_t fin = !valid ? ST_PLACE : (vx == 0 ? ST_REDUNDANT : ST_CONFLICT);
+        steps += (elim && valid) ? 1u : 0u;
+        c = cont ? (cx >> j) : c;
+        v = cont ? vx : v;
+        i = cont ? i + j : i;
+        state = (elim && !cont) ? fin : state;
+      }
+
+      // ---- outcome of finished equations (common path) ----
+      if (state == ST_PLACE) {
+        if (i >= limit) {
+          // unreachable for kept keys; stop instead of writing outside the range
+          *a.fail = 2u;
+          state = ST_DONE;
         } else {
-          vm0 |= bit;
-          pm0 |= bit;
+          const uint32_t p = i & (kRing - 1);
+          ringC[p * 64 + lane] = c;
+          ringV[p * 64 + lane] = (VT)v;
+          const uint64_t bit = 1ull << (p & 63);
+          const bool hi_half = (p & 64) != 0;
+          vm1 |= hi_half ? bit : 0;
+          pm1 |= hi_half ? bit : 0;
+          vm0 |= hi_half ? 0 : bit;
+          pm0 |= hi_half ? 0 : bit;
+          a.rowsC[P0 + i] = c;
+          a.rowsV[P0 + i] = v;
+          state = ST_WANT;
         }
-        a.rowsC[P0 + i] = c;
-        a.rowsV[P0 + i] = v;
-        state = ST_NEXT;
-      } else if (state == ST_REDUNDANT) {
-        state = ST_NEXT;
-      } else if (state == ST_CONFLICT) {
+      }
+      state = state == ST_REDUNDANT ? ST_WANT : state;
+      // next record of the same bucket straight from the FIFO
+      if (state == ST_WANT && x != rend && x < written) {
+        const Rec rc = fifo[(x % kFifo) * 64 + lane];
+        const uint32_t k = 3u - meta_rank(rc.meta);
+        if (k > kf) {
+          const bool newk = k != curk;
+          pm0 = newk ? 0 : pm0;
+          pm1 = newk ? 0 : pm1;
+          chunk_start = newk ? x : chunk_start;
+          curk = k;
+          c = rc.c;
+          v = meta_value(rc.meta);
+          i = 64u * q + meta_offset(rc.meta);
+          ++x;
+          state = ST_ELIM;
+        }
+      }
+      // ---- rare paths: conflicts, bucket ends, headers, forced bumps ----
+      if (!__any(state == ST_CONFLICT ||
+                 (state == ST_WANT && (x == rend ? (open || x < written) : x < written))))
+        continue;
+      if (state == ST_CONFLICT) {
         if (g.plain) {
           *a.fail = 1u;
           state = ST_DONE;
         } else {
-          vm0 &= ~pm0;  // undo the chunk
+          vm0 &= ~pm0;  // undo the chunk; the rest of the bucket is bumped
           vm1 &= ~pm1;
           code = curk;
           split_at = chunk_start;
-          state = ST_BEND;
+          x = rend;
+          state = ST_WANT;
         }
       }
-
-      // transitions; a lane whose next item has not reached the FIFO waits
-      bool go = true;
-#pragma unroll 1
-      for (int tr = 0; tr < 6 && go; ++tr) {
-        if (state == ST_NEXT) {
-          if (x == rend) {
-            split_at = rend;
-            state = ST_BEND;
-          } else if (x < written) {
-            const Rec rc = fifo[(x % kFifo) * 64 + lane];
-            const uint32_t y = x++;
-            const uint32_t k = 3u - meta_rank(rc.meta);
-            if (k <= kf) {
-              split_at = y;
-              state = ST_BEND;
-            } else {
-              if (k != curk) {
-                pm0 = 0;
-                pm1 = 0;
-                curk = k;
-                chunk_start = y;
-              }
-              c = rc.c;
-              v = meta_value(rc.meta);
-              i = 64u * q + meta_offset(rc.meta);
-              state = ST_ELIM;
-              go = false;
-            }
-          } else {
-            go = false;
-          }
-        } else if (state == ST_BEND) {
+      // ---- lanes take their next item ----
+      // Up to three flat passes; each pass may end a bucket, open the next
+      // one from its header and take a record. A lane whose next item has not
+      // reached the FIFO waits for the next round.
+#pragma unroll
+      for (int pass = 0; pass < 3; ++pass) {
+        if (pass > 0 && !__any(state == ST_WANT && (x == rend ? (open || x < written) : x < written)))
+          break;
+        if (state == ST_WANT && x == rend && open) {
+          // end of the current bucket: publish code and bump count
           const uint64_t beta = fb + q;
           if (!g.plain) {
             a.code8[beta] = (uint8_t)code;
-            a.bump[beta] = rend - split_at;
+            a.bump[beta] = rend - (split_at == kNoSplit ? rend : split_at);
           }
-          x = rend;  // skip the bumped rest of the bucket
+          open = false;
           if (q + 1 == nq) {
             a.occ[beta] = (q & 1) ? vm1 : vm0;
             state = ST_DONE;
-            go = false;
-          } else {
-            state = ST_BHEAD;
           }
-        } else if (state == ST_BHEAD) {
-          if (x < written) {
-            const Rec hd = fifo[(x % kFifo) * 64 + lane];
-            ++q;
-            if (q >= 1) {
-              // bucket q-1 is final: publish its occupancy, free its ring half
-              const uint64_t beta = fb + q - 1;
-              if ((q - 1) & 1) {
-                a.occ[beta] = vm1;
-                vm1 = 0;
-              } else {
-                a.occ[beta] = vm0;
-                vm0 = 0;
-              }
-            }
-            kf = head_kf(hd);
-            code = kf;
-            curk = 4;
-            pm0 = 0;
-            pm1 = 0;
-            rend = x + 1 + head_count(hd);
+        }
+        if (state == ST_WANT && x == rend && !open && x < written) {
+          // header of the next bucket; bucket q-1 is final: publish its
+          // occupancy and free its ring half
+          const Rec hd = fifo[(x % kFifo) * 64 + lane];
+          ++q;
+          if (q >= 1) {
+            const uint64_t beta = fb + q - 1;
+            const bool odd = ((q - 1) & 1) != 0;
+            a.occ[beta] = odd ? vm1 : vm0;
+            vm1 = odd ? 0 : vm1;
+            vm0 = odd ? vm0 : 0;
+          }
+          kf = head_kf(hd);
+          code = kf;
+          curk = 4;
+          pm0 = 0;
+          pm1 = 0;
+          split_at = kNoSplit;
+          rend = x + 1 + head_count(hd);
+          ++x;
+          open = true;
+        }
+        if (state == ST_WANT && x != rend && x < written) {
+          // a record of the current bucket
+          const Rec rc = fifo[(x % kFifo) * 64 + lane];
+          const uint32_t k = 3u - meta_rank(rc.meta);
+          if (k <= kf) {
+            // forced part of a range's last bucket: the rest is bumped
+            split_at = x;
+            x = rend;
+          } else {
+            const bool newk = k != curk;
+            pm0 = newk ? 0 : pm0;
+            pm1 = newk ? 0 : pm1;
+            chunk_start = newk ? x : chunk_start;
+            curk = k;
+            c = rc.c;
+            v = meta_value(rc.meta);
+            i = 64u * q + meta_offset(rc.meta);
             ++x;
-            chunk_start = x;
-            state = ST_NEXT;
-          } else {
-            go = false;
+            state = ST_ELIM;
           }
-        } else {
-          go = false;
         }
       }
     }
@@ -503,27 +537,29 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     if (!__any(state != ST_DONE)) break;
   }
   if (a.steps) atomicAdd((unsigned long long*)a.steps, (unsigned long long)steps);
+#ifdef BURR_SOLVE_DEBUG
+  if (a.steps) {
+    atomicAdd((unsigned long long*)a.steps + 1, (unsigned long long)dbg_active);
+    atomicAdd((unsigned long long*)a.steps + 2, (unsigned long long)dbg_elim);
+    atomicAdd((unsigned long long*)a.steps + 3, (unsigned long long)dbg_stall);
+  }
+#endif
+}
+
+template <typename VT, int K>
+static hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
+  const unsigned blocks = (unsigned)((a.g.nranges + 63) / 64);
+  const size_t lds = solve_lds_bytes<VT>();
+  (void)hipFuncSetAttribute((const void*)k_solve<VT, K>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  k_solve<VT, K><<<blocks, 64, lds, s>>>(a);
+  return hipGetLastError();
 }
 
 hipError_t solve_layer(const SolveArgs& a, hipStream_t s) {
-  const unsigned blocks = (unsigned)((a.g.nranges + 63) / 64);
-  if (a.g.r <= 8) {
-    const size_t lds = solve_lds_bytes<uint8_t>();
-    (void)hipFuncSetAttribute((const void*)k_solve<uint8_t, 4>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_solve<uint8_t, 4><<<blocks, 64, lds, s>>>(a);
-  } else if (a.g.r <= 16) {
-    const size_t lds = solve_lds_bytes<uint16_t>();
-    (void)hipFuncSetAttribute((const void*)k_solve<uint16_t, 4>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_solve<uint16_t, 4><<<blocks, 64, lds, s>>>(a);
-  } else {
-    const size_t lds = solve_lds_bytes<uint32_t>();
-    (void)hipFuncSetAttribute((const void*)k_solve<uint32_t, 4>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_solve<uint32_t, 4><<<blocks, 64, lds, s>>>(a);
-  }
-  return hipGetLastError();
+  if (a.g.r <= 8) return launch_solve<uint8_t, BURR_SOLVE_K>(a, s);
+  if (a.g.r <= 16) return launch_solve<uint16_t, BURR_SOLVE_K>(a, s);
+  return launch_solve<uint32_t, BURR_SOLVE_K>(a, s);
 }
 
 // ---------------------------------------------------------------------------
