@@ -214,6 +214,16 @@ struct Workspace {
     return alloc(scan_tmp, need);
   }
   bool misc() { return alloc(fail, 64) && alloc(steps, 8); }
+  // final layer segments
+  uint64_t cap_seg = 0;
+  uint64_t *spillC = nullptr, *spill_occ = nullptr, *xfirst = nullptr;
+  uint32_t *spillV = nullptr, *z0first = nullptr, *bnd = nullptr;
+  bool reserve_segments(uint64_t P) {
+    if (P <= cap_seg && spillC) return true;
+    cap_seg = P;
+    return alloc(spillC, P * 64) && alloc(spillV, P * 64) && alloc(spill_occ, P) &&
+           alloc(xfirst, P * 64) && alloc(z0first, P * 64) && alloc(bnd, P * 64);
+  }
 };
 
 #define HIP_TRY(expr)                                     \
@@ -225,6 +235,9 @@ struct Workspace {
       return set_error(BURR_E_DEVICE);                    \
     }                                                     \
   } while (0)
+
+// final layer: buckets per independently solved segment
+constexpr uint64_t kFinalSegBuckets = 4;
 
 uint32_t sort_groups(uint64_t n, uint32_t nbins) {
   // level-1 workgroups: enough to fill the chip, few enough that the
@@ -405,19 +418,41 @@ int build_impl(burr_handle* h, const uint64_t* keys, const void* values) {
       int rc = run_sort(ws, cur_keys, cur_vals, cur_vbytes, first, p.filter_mode != 0, fp_salt,
                         cur_n, g, s);
       if (rc != BURR_OK) return rc;
+      // The table is cut into segments of kFinalSegBuckets buckets solved in
+      // parallel; rows crossing a segment end are merged afterwards.
+      LayerGeom gs = g;
+      gs.nranges = std::max<uint64_t>(1, g.nbuckets / kFinalSegBuckets);
+      if (!ws.reserve_segments(gs.nranges)) return set_error(BURR_E_NOMEM);
       HIP_TRY(hipMemsetAsync(ws.fail, 0, 4, s));
-      HIP_TRY(hipMemsetAsync(ws.steps, 0, 8, s));
+      HIP_TRY(hipMemsetAsync(ws.steps, 0, 64, s));
+      HIP_TRY(hipMemsetAsync(ws.spill_occ, 0, gs.nranges * 8, s));
       SolveArgs sa{};
       sa.rec = ws.rec;
       sa.bstart = ws.bstart;
-      sa.g = g;
+      sa.g = gs;
       sa.rowsC = ws.rowsC;
       sa.rowsV = ws.rowsV;
       sa.occ = ws.occ;
       sa.fail = ws.fail;
       sa.steps = ws.steps;
       sa.nrec = (uint32_t)(cur_n + g.nbuckets);
+      sa.spillC = ws.spillC;
+      sa.spillV = ws.spillV;
+      sa.spill_occ = ws.spill_occ;
       HIP_TRY(solve_layer(sa, s));
+      FinalArgs fa{};
+      fa.g = gs;
+      fa.rowsC = ws.rowsC;
+      fa.rowsV = ws.rowsV;
+      fa.occ = ws.occ;
+      fa.spillC = ws.spillC;
+      fa.spillV = ws.spillV;
+      fa.spill_occ = ws.spill_occ;
+      fa.fail = ws.fail;
+      fa.z0first = ws.z0first;
+      fa.xfirst = ws.xfirst;
+      fa.bnd = ws.bnd;
+      HIP_TRY(final_merge(fa, s));
       uint32_t failed = 0;
       uint64_t steps = 0;
       HIP_TRY(hipMemcpyAsync(&failed, ws.fail, 4, hipMemcpyDeviceToHost, s));
@@ -433,7 +468,8 @@ int build_impl(burr_handle* h, const uint64_t* keys, const void* values) {
       F.nW = (g.m / 64) * r;
       F.W = (uint64_t*)h->al.get(F.nW * 8);
       if (!F.W) return set_error(BURR_E_NOMEM);
-      HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, ws.occ, g, F.W, s));
+      HIP_TRY(final_boundaries(fa, s));
+      HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, ws.occ, gs, F.W, s, ws.bnd));
       h->fin_attempt = a;
       solved = true;
     }

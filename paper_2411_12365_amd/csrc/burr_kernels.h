@@ -52,12 +52,39 @@ struct SolveArgs {
   uint32_t* fail;      // plain mode: set to 1 on an inconsistent equation
   uint64_t* steps;     // optional: total elimination steps (statistics)
   uint32_t nrec;       // number of records (prefetch bound)
+  // final-layer segments: rows that land past a segment's end go to its
+  // spill buffer (64 rows + occupancy word per segment) instead of failing
+  uint64_t* spillC;
+  uint32_t* spillV;
+  uint64_t* spill_occ;
 };
 hipError_t solve_layer(const SolveArgs& a, hipStream_t s);
 
 // Back-substitution per range into column-interleaved words W[k*r+col].
+// bnd (optional, 64 u32 per range): solution values of the 63 slots after
+// each range's end (final-layer segments, whose rows cross segment ends).
 hipError_t back_substitute(const uint64_t* rowsC, const uint32_t* rowsV, const uint64_t* occ,
-                           const LayerGeom& g, uint64_t* W, hipStream_t s);
+                           const LayerGeom& g, uint64_t* W, hipStream_t s,
+                           const uint32_t* bnd = nullptr);
+
+// Final plain layer, after the per-segment solve (g.nranges = segments):
+// merge the segments' spill rows pairwise over log2(segments) levels, then
+// compute each segment's boundary values.
+struct FinalArgs {
+  LayerGeom g;
+  uint64_t* rowsC;
+  uint32_t* rowsV;
+  uint64_t* occ;
+  uint64_t* spillC;
+  uint32_t* spillV;
+  uint64_t* spill_occ;
+  uint32_t* fail;
+  uint32_t* z0first;  // segments x 64: values of a segment's first 63 slots with a zero boundary
+  uint64_t* xfirst;   // segments x 64: their dependence on the 63 boundary values
+  uint32_t* bnd;      // segments x 64: true values of the 63 slots after each segment
+};
+hipError_t final_merge(const FinalArgs& a, hipStream_t s);
+hipError_t final_boundaries(const FinalArgs& a, hipStream_t s);
 
 // code8[B] -> packed 2-bit code words
 hipError_t pack_codes(const uint8_t* code8, uint64_t B, uint64_t* words, hipStream_t s);

@@ -406,12 +406,28 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
       }
 
       // ---- outcome of finished equations (common path) ----
-      if (state == ST_PLACE) {
-        if (i >= limit) {
-          // unreachable for kept keys; stop instead of writing outside the range
+      if (state == ST_PLACE && i >= limit) {
+        if (a.spillC && i < limit + 64u) {
+          // final-layer segment: the row belongs past the segment end; keep it
+          // in the ring (its half is free during the last bucket) and in the
+          // segment's spill buffer
+          const uint32_t p = i & (kRing - 1);
+          ringC[p * 64 + lane] = c;
+          ringV[p * 64 + lane] = (VT)v;
+          const uint64_t bit = 1ull << (p & 63);
+          if (p & 64) vm1 |= bit; else vm0 |= bit;
+          a.spillC[rho * 64 + (i - limit)] = c;
+          a.spillV[rho * 64 + (i - limit)] = v;
+          state = ST_WANT;
+        } else {
+          // unreachable for kept keys of a BuRR layer; stop instead of
+          // writing outside the range
           *a.fail = 2u;
           state = ST_DONE;
-        } else {
+        }
+      }
+      if (state == ST_PLACE) {
+        {
           const uint32_t p = i & (kRing - 1);
           ringC[p * 64 + lane] = c;
           ringV[p * 64 + lane] = (VT)v;
@@ -479,6 +495,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
           open = false;
           if (q + 1 == nq) {
             a.occ[beta] = (q & 1) ? vm1 : vm0;
+            if (a.spill_occ) a.spill_occ[rho] = (q & 1) ? vm0 : vm1;
             state = ST_DONE;
           }
         }
@@ -569,7 +586,8 @@ template <int RMAX>
 __global__ __launch_bounds__(256) void k_backsub(const uint64_t* __restrict__ rowsC,
                                                  const uint32_t* __restrict__ rowsV,
                                                  const uint64_t* __restrict__ occ, LayerGeom g,
-                                                 uint64_t* __restrict__ W) {
+                                                 uint64_t* __restrict__ W,
+                                                 const uint32_t* __restrict__ bnd) {
   const uint64_t rho = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   if (rho >= g.nranges) return;
   const uint64_t fb = rho * g.nbuckets / g.nranges;
@@ -578,6 +596,14 @@ __global__ __launch_bounds__(256) void k_backsub(const uint64_t* __restrict__ ro
   uint64_t win[RMAX];  // bit j of win[col] = column col of Z[i+1+j]
 #pragma unroll
   for (int col = 0; col < RMAX; ++col) win[col] = 0;
+  if (bnd) {
+    // rows near the end may reach the 63 slots after it: start from their values
+    for (uint32_t t = 0; t < 63; ++t) {
+      const uint32_t z = bnd[rho * 64 + t];
+#pragma unroll
+      for (int col = 0; col < RMAX; ++col) win[col] |= (uint64_t)((z >> col) & 1u) << t;
+    }
+  }
   for (uint64_t k = lb; k-- > fb;) {
     const uint64_t oc = occ[k];
     uint64_t out[RMAX];
@@ -608,14 +634,239 @@ __global__ __launch_bounds__(256) void k_backsub(const uint64_t* __restrict__ ro
 }
 
 hipError_t back_substitute(const uint64_t* rowsC, const uint32_t* rowsV, const uint64_t* occ,
-                           const LayerGeom& g, uint64_t* W, hipStream_t s) {
+                           const LayerGeom& g, uint64_t* W, hipStream_t s, const uint32_t* bnd) {
   const unsigned blocks = (unsigned)((g.nranges + 255) / 256);
   if (g.r <= 8)
-    k_backsub<8><<<blocks, 256, 0, s>>>(rowsC, rowsV, occ, g, W);
+    k_backsub<8><<<blocks, 256, 0, s>>>(rowsC, rowsV, occ, g, W, bnd);
   else if (g.r <= 16)
-    k_backsub<16><<<blocks, 256, 0, s>>>(rowsC, rowsV, occ, g, W);
+    k_backsub<16><<<blocks, 256, 0, s>>>(rowsC, rowsV, occ, g, W, bnd);
   else
-    k_backsub<32><<<blocks, 256, 0, s>>>(rowsC, rowsV, occ, g, W);
+    k_backsub<32><<<blocks, 256, 0, s>>>(rowsC, rowsV, occ, g, W, bnd);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Final plain layer across segments
+// ---------------------------------------------------------------------------
+// The final layer cannot bump, so its segments are not independent: a row may
+// end past its segment's end. After the per-segment solve those rows wait in
+// the segment's spill buffer. Merging inserts a left group's spill rows into
+// the right group (the usual elimination, starting at the right group's first
+// slots), so after log2(segments) levels the whole layer is one echelon
+// system - the same row space, hence the same solution with free slots 0.
+
+__device__ inline uint64_t seg_first_slot(uint64_t p, const LayerGeom& g) {
+  return 64 * (p * g.nbuckets / g.nranges);
+}
+
+constexpr uint32_t kMergeWin = 384;  // slots of the right group staged in LDS
+
+__global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
+  __shared__ uint64_t wc[kMergeWin];
+  __shared__ uint32_t wv[kMergeWin];
+  __shared__ uint64_t wocc[kMergeWin / 64];
+  const LayerGeom g = a.g;
+  const uint64_t P = g.nranges;
+  const uint64_t L0 = (uint64_t)blockIdx.x * 2 * G;
+  const uint64_t R0 = L0 + G;
+  if (R0 >= P) return;
+  const uint64_t lastL = R0 - 1;
+  const uint64_t lastR = (L0 + 2 * G < P ? L0 + 2 * G : P) - 1;
+  const uint64_t start = seg_first_slot(R0, g);
+  const uint64_t endR = seg_first_slot(lastR + 1, g);  // slot after the right group
+  // window: slots [start, start + win); slots >= endR are the right group's
+  // spill zone, which the window holds either completely or not at all
+  const uint64_t span = endR + 64 - start;
+  const uint64_t body = endR - start;
+  const uint32_t win = (uint32_t)(span <= kMergeWin ? span : (body < kMergeWin ? body : kMergeWin));
+  const uint32_t lane = threadIdx.x;
+  for (uint32_t t = lane; t < win; t += 64) {
+    const uint64_t slot = start + t;
+    if (slot < endR) {
+      wc[t] = a.rowsC[slot];
+      wv[t] = a.rowsV[slot];
+    } else {
+      wc[t] = a.spillC[lastR * 64 + (slot - endR)];
+      wv[t] = a.spillV[lastR * 64 + (slot - endR)];
+    }
+  }
+  for (uint32_t b = lane; b < win / 64; b += 64) {
+    const uint64_t slot = start + 64ull * b;
+    wocc[b] = slot < endR ? a.occ[slot / 64] : a.spill_occ[lastR];
+  }
+  __syncthreads();
+  if (lane == 0) {
+    uint64_t pend = a.spill_occ[lastL];
+    bool bad = false, internal = false;
+    while (pend && !bad) {
+      const uint32_t t0 = (uint32_t)__builtin_ctzll(pend);
+      pend &= pend - 1;
+      uint64_t c = a.spillC[lastL * 64 + t0];
+      uint32_t v = a.spillV[lastL * 64 + t0];
+      uint32_t i = t0;  // relative to start (the left group ends where the right one begins)
+      while (true) {
+        bool occupied;
+        uint64_t row;
+        uint32_t rv;
+        if (i < win) {
+          occupied = (wocc[i / 64] >> (i % 64)) & 1ull;
+          row = wc[i];
+          rv = wv[i];
+        } else {
+          // beyond the staged window: read the right group in global memory
+          const uint64_t slot = start + i;
+          if (slot < endR) {
+            occupied = (a.occ[slot / 64] >> (slot % 64)) & 1ull;
+            row = a.rowsC[slot];
+            rv = a.rowsV[slot];
+          } else {
+            const uint64_t t = slot - endR;
+            if (t >= 64) {  // unreachable: rows end at most 62 slots past the group
+              bad = true;
+              internal = true;
+              break;
+            }
+            occupied = (a.spill_occ[lastR] >> t) & 1ull;
+            row = a.spillC[lastR * 64 + t];
+            rv = a.spillV[lastR * 64 + t];
+          }
+        }
+        if (!occupied) {
+          if (i < win) {
+            wc[i] = c;
+            wv[i] = v;
+            wocc[i / 64] |= 1ull << (i % 64);
+          } else {
+            const uint64_t slot = start + i;
+            if (slot < endR) {
+              a.rowsC[slot] = c;
+              a.rowsV[slot] = v;
+              a.occ[slot / 64] |= 1ull << (slot % 64);
+            } else {
+              const uint64_t t = slot - endR;
+              a.spillC[lastR * 64 + t] = c;
+              a.spillV[lastR * 64 + t] = v;
+              a.spill_occ[lastR] |= 1ull << t;
+            }
+          }
+          break;
+        }
+        c ^= row;
+        v ^= rv;
+        if (c == 0) {
+          if (v != 0) bad = true;  // inconsistent: this table size fails
+          break;
+        }
+        const uint32_t j = (uint32_t)__builtin_ctzll(c);
+        c >>= j;
+        i += j;
+      }
+    }
+    if (bad) *a.fail = internal ? 2u : 1u;
+    a.spill_occ[lastL] = 0;
+  }
+  __syncthreads();
+  for (uint32_t t = lane; t < win; t += 64) {
+    const uint64_t slot = start + t;
+    if (slot < endR) {
+      a.rowsC[slot] = wc[t];
+      a.rowsV[slot] = wv[t];
+    } else {
+      a.spillC[lastR * 64 + (slot - endR)] = wc[t];
+      a.spillV[lastR * 64 + (slot - endR)] = wv[t];
+    }
+  }
+  for (uint32_t b = lane; b < win / 64; b += 64) {
+    const uint64_t slot = start + 64ull * b;
+    if (slot < endR)
+      a.occ[slot / 64] = wocc[b];
+    else
+      a.spill_occ[lastR] = wocc[b];
+  }
+}
+
+hipError_t final_merge(const FinalArgs& a, hipStream_t s) {
+  const uint64_t P = a.g.nranges;
+  for (uint64_t G = 1; G < P; G *= 2) {
+    const uint64_t pairs = (P + 2 * G - 1) / (2 * G);
+    k_merge<<<(unsigned)pairs, 64, 0, s>>>(a, (uint32_t)G);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Per segment, back-substitute with the 63 values after the segment unknown:
+// every slot's value is z0 (zero boundary) xor the boundary values selected
+// by a 63-bit dependence word X. Only the first 63 slots' (z0, X) are kept.
+__global__ __launch_bounds__(64) void k_final_partial(FinalArgs a) {
+  __shared__ uint32_t zwin[64 * 64];
+  __shared__ uint64_t xwin[64 * 64];
+  const LayerGeom g = a.g;
+  const uint32_t lane = threadIdx.x;
+  const uint64_t p = (uint64_t)blockIdx.x * 64 + lane;
+  if (p >= g.nranges) return;
+  const uint64_t start = seg_first_slot(p, g);
+  const uint64_t end = seg_first_slot(p + 1, g);
+  for (uint64_t i = end; i-- > start;) {
+    uint32_t z = 0;
+    uint64_t X = 0;
+    if ((a.occ[i / 64] >> (i % 64)) & 1ull) {
+      z = a.rowsV[i];
+      uint64_t bits = a.rowsC[i] >> 1;
+      while (bits) {
+        const uint32_t k = (uint32_t)__builtin_ctzll(bits) + 1;
+        bits &= bits - 1;
+        const uint64_t slot = i + k;
+        if (slot < end) {
+          z ^= zwin[(slot % 64) * 64 + lane];
+          X ^= xwin[(slot % 64) * 64 + lane];
+        } else {
+          X ^= 1ull << (slot - end);
+        }
+      }
+    }
+    zwin[(i % 64) * 64 + lane] = z;
+    xwin[(i % 64) * 64 + lane] = X;
+    if (i - start < 63) {
+      a.z0first[p * 64 + (i - start)] = z;
+      a.xfirst[p * 64 + (i - start)] = X;
+    }
+  }
+}
+
+// From the last segment down: the boundary of segment p-1 is the true value
+// of segment p's first 63 slots = z0 xor (X applied to segment p's boundary).
+__global__ __launch_bounds__(64) void k_final_scan(FinalArgs a) {
+  __shared__ uint32_t b[64];
+  const uint32_t t = threadIdx.x;
+  const uint64_t P = a.g.nranges;
+  b[t] = 0;  // nothing lies past the last segment
+  __syncthreads();
+  for (uint64_t p = P; p-- > 0;) {
+    a.bnd[p * 64 + t] = b[t];
+    uint32_t z = 0;
+    if (t < 63) {
+      z = a.z0first[p * 64 + t];
+      uint64_t X = a.xfirst[p * 64 + t];
+      while (X) {
+        const uint32_t k = (uint32_t)__builtin_ctzll(X);
+        X &= X - 1;
+        z ^= b[k];
+      }
+    }
+    __syncthreads();
+    b[t] = z;
+    __syncthreads();
+  }
+}
+
+hipError_t final_boundaries(const FinalArgs& a, hipStream_t s) {
+  const uint64_t P = a.g.nranges;
+  k_final_partial<<<(unsigned)((P + 63) / 64), 64, 0, s>>>(a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_final_scan<<<1, 64, 0, s>>>(a);
   return hipGetLastError();
 }
 

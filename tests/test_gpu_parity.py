@@ -71,6 +71,15 @@ CASES = [
     (20000, 8, dict(ranges=16, t_lo=8, t_hi=40, seed=123)),
     (3000, 4, dict(ranges=6, minbpt=2, load_num=60, load_den=100, layers=4)),
     (200000, 8, dict(ranges=4096, minbpt=4)),
+    # the final plain layer is the whole structure: thousands of segments,
+    # log2 merge levels, boundary propagation across all of them
+    (200000, 8, dict(layers=0)),
+    (150000, 32, dict(layers=0, seed=11)),
+    (100000, 3, dict(layers=1, ranges=64)),
+    # a tight final layer (1.0 slots per key) fails its first attempts,
+    # some of them only when segments are merged
+    (60000, 8, dict(layers=0, final_num=100, final_den=100, seed=4)),
+    (60000, 8, dict(layers=0, final_num=100, final_den=100, seed=5)),
 ]
 
 
