@@ -78,6 +78,7 @@ typedef struct burr_params {
 } burr_params;
 
 typedef struct burr_handle burr_handle;
+typedef struct burr_batch burr_batch;
 
 typedef struct burr_layer_stats {
   uint64_t n;        /* keys entering the layer */
@@ -107,7 +108,8 @@ void burr_default_params(burr_params* p);
 
 /* Builds a structure for n keys (device u64[n]) with r-bit values (device
  * array, see conventions; may be NULL in filter mode). Keys must be
- * distinct; a key repeated with the same value is harmless. The build runs on
+ * distinct; a key repeated with the same value is harmless; n < 0xF0000000
+ * (item indices are 32-bit; the same bound holds for a batch's total). The build runs on
  * p->stream and returns when it is complete (it reads one counter per layer
  * back to the host). Returns NULL on error (see burr_last_error). The handle
  * owns one device allocation per layer; free it with burr_free.
@@ -129,9 +131,39 @@ int burr_query(const burr_handle* h, const uint64_t* keys, uint64_t n, void* out
 int burr_contains(const burr_handle* h, const uint64_t* keys, uint64_t n, uint8_t* out,
                   void* stream);
 
+/* Frees a handle returned by burr_build or burr_import. A batch member's
+ * handle is not freed this way (BURR_E_INVALID): free its batch. */
 void burr_free(burr_handle* h);
 
+/* Sizes and device times of h's build. For a batch member the per-layer and
+ * total times are those of the whole batch (its layers were built together). */
 int burr_get_stats(const burr_handle* h, burr_stats* s);
+
+/* Builds `count` independent structures at once (many small sets, e.g. one per
+ * shard or per document). Structure i stores keys[host_offsets[i],
+ * host_offsets[i+1]) (device keys, host offsets, host_offsets[0] = 0, non-
+ * decreasing; an empty range gives an empty structure) with host_r[i] value
+ * bits (1..32); values (device) are laid out like keys, in elements of the
+ * value width of the LARGEST host_r[i]. Each structure is the one burr_build
+ * would make from its own keys and p: same layers, tables, export bytes and
+ * query results (Sec. 2 and 3 per structure; keys of different structures
+ * never meet). The layers of all structures are built together, one launch
+ * per kernel and layer, so a batch of small structures fills the GPU like
+ * one large build. Runs on p->stream and returns when done; NULL on error. */
+burr_batch* burr_build_batch(const uint64_t* keys, const void* values,
+                             const uint64_t* host_offsets, const uint32_t* host_r,
+                             uint32_t count, const burr_params* p);
+
+/* Number of structures in a batch (0 for NULL). */
+uint32_t burr_batch_size(const burr_batch* b);
+
+/* Handle of structure i (NULL if out of range). It is valid until the batch
+ * is freed and works with burr_query, burr_contains, burr_get_stats,
+ * burr_export and burr_debug_layer_keys. */
+const burr_handle* burr_batch_member(const burr_batch* b, uint32_t i);
+
+/* Frees a batch and every member's tables. */
+void burr_batch_free(burr_batch* b);
 
 /* Canonical little-endian serialisation (layout in the library's export
  * code): header, then per BuRR layer n, m, ranges, packed 2-bit codes and

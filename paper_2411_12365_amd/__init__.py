@@ -24,7 +24,8 @@ ABI_VERSION = 1
 
 _EXPORTS = ("burr_default_params", "burr_build", "burr_query", "burr_contains", "burr_free",
             "burr_get_stats", "burr_export", "burr_import", "burr_debug_layer_keys",
-            "burr_last_error", "burr_error_string")
+            "burr_last_error", "burr_error_string", "burr_build_batch", "burr_batch_size",
+            "burr_batch_member", "burr_batch_free")
 
 
 class BurrError(RuntimeError):
@@ -116,6 +117,14 @@ def lib():
         L.burr_import.restype = vp
         L.burr_debug_layer_keys.argtypes = [vp, u32, vp, u64]
         L.burr_debug_layer_keys.restype = ctypes.c_int64
+        L.burr_build_batch.argtypes = [vp, vp, vp, vp, u32, ctypes.POINTER(_CParams)]
+        L.burr_build_batch.restype = vp
+        L.burr_batch_size.argtypes = [vp]
+        L.burr_batch_size.restype = u32
+        L.burr_batch_member.argtypes = [vp, u32]
+        L.burr_batch_member.restype = vp
+        L.burr_batch_free.argtypes = [vp]
+        L.burr_batch_free.restype = None
         L.burr_last_error.argtypes = []
         L.burr_last_error.restype = i32
         L.burr_error_string.argtypes = [i32]
@@ -153,20 +162,24 @@ def value_dtype(r: int):
 
 
 class Handle:
-    """A structure built on the GPU; owns its device memory until free()."""
+    """A structure built on the GPU; owns its device memory until free().
+    A batch member's handle owns nothing: it keeps its batch alive."""
 
-    def __init__(self, ptr: int, r: int, params: Params):
+    def __init__(self, ptr: int, r: int, params: Params, batch: "Batch | None" = None):
         self._h = ptr
         self.r = r
         self.params = params
+        self._batch = batch
 
     def __del__(self):
         self.free()
 
     def free(self):
         if getattr(self, "_h", None):
-            lib().burr_free(self._h)
+            if self._batch is None:
+                lib().burr_free(self._h)
             self._h = None
+            self._batch = None
 
     def query(self, keys, out=None, stream=None):
         return burr_query(self, keys, out, stream)
@@ -202,6 +215,75 @@ def burr_build(keys, values, r: int, params: Params | None = None, stream=None) 
     if not h:
         raise BurrError(lib().burr_last_error(), "burr_build")
     return Handle(h, r, params)
+
+
+class Batch:
+    """Independent structures built together by burr_build_batch."""
+
+    def __init__(self, ptr: int, rs, params: Params):
+        self._b = ptr
+        self.rs = list(rs)
+        self.params = params
+
+    def __del__(self):
+        self.free()
+
+    def __len__(self):
+        return lib().burr_batch_size(self._b) if self._b else 0
+
+    def member(self, i: int) -> Handle:
+        return burr_batch_member(self, i)
+
+    def free(self):
+        if getattr(self, "_b", None):
+            lib().burr_batch_free(self._b)
+            self._b = None
+
+
+def burr_build_batch(keys, values, offsets, rs, params: Params | None = None,
+                     stream=None) -> Batch:
+    """keys: GPU int64/uint64 tensor holding every structure's keys back to
+    back; offsets: host sequence of len(rs)+1 key offsets (offsets[0] = 0);
+    rs: value bits per structure; values: GPU tensor laid out like keys with
+    the value dtype of max(rs), or None in filter mode."""
+    import numpy as np
+    import torch
+    params = params or Params()
+    _check_tensor(keys, "keys", (torch.int64, torch.uint64))
+    rs = [int(r) for r in rs]
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    rr = np.ascontiguousarray(np.asarray(rs, dtype=np.uint32))
+    if len(rr) == 0 or off.shape != (len(rr) + 1,):
+        raise ValueError("offsets must hold len(rs)+1 entries")
+    if int(off[-1]) != keys.numel():
+        raise ValueError("offsets[-1] must equal the number of keys")
+    vptr = None
+    if values is not None:
+        _check_tensor(values, "values", (value_dtype(max(rs)),))
+        if values.numel() != keys.numel():
+            raise ValueError("keys and values differ in length")
+        vptr = values.data_ptr() if values.numel() else None
+    cp = params.c(_stream_of(stream))
+    b = lib().burr_build_batch(keys.data_ptr() if keys.numel() else None, vptr,
+                               off.ctypes.data, rr.ctypes.data, len(rr), ctypes.byref(cp))
+    if not b:
+        raise BurrError(lib().burr_last_error(), "burr_build_batch")
+    return Batch(b, rs, params)
+
+
+def burr_batch_size(b: Batch) -> int:
+    return len(b)
+
+
+def burr_batch_member(b: Batch, i: int) -> Handle:
+    h = lib().burr_batch_member(b._b, i)
+    if not h:
+        raise BurrError(lib().burr_last_error(), "burr_batch_member")
+    return Handle(h, b.rs[i], b.params, batch=b)
+
+
+def burr_batch_free(b: Batch):
+    b.free()
 
 
 def burr_query(h: Handle, keys, out=None, stream=None):
@@ -280,4 +362,5 @@ def burr_debug_layer_keys(h: Handle, layer: int):
 
 # short aliases
 build = burr_build
+build_batch = burr_build_batch
 import_ = burr_import

@@ -1,10 +1,15 @@
 // burr_api.cpp - C ABI of the BuRR library (include/burr.h): parameter
 // checks, layer planning, workspace, the per-layer launch sequence, export
 // and import.
+//
+// Every build is a batch: one or more independent structures whose layers
+// are built together - each kernel launch covers the same layer of every
+// structure that still has keys (a single build is a batch of one). The
+// members share one device allocation per layer for their threshold codes
+// and solution words; a handle is a view of one member.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -27,6 +32,9 @@ int set_error(int code) {
 constexpr uint64_t kExportMagic = 0x3170786552527542ull;  // "BuRRexp1"
 constexpr uint32_t kExportVersion = 1;
 constexpr uint32_t kMaxLayers = 32;
+constexpr uint64_t kFinalSegBuckets = 4;  // final layer: buckets per segment
+// item indices (one per key plus one per bucket) are 32-bit
+constexpr uint64_t kMaxKeys = 0xf0000000ull;
 
 uint32_t value_bytes(uint32_t r) { return r <= 8 ? 1 : (r <= 16 ? 2 : 4); }
 
@@ -65,98 +73,127 @@ void keep_pool_memory(int dev) {
   done[dev] = true;
 }
 
-struct DevLayer {
-  uint64_t n = 0, m = 0, B = 0, R = 0, bumped = 0;
-  double ms_sort = 0, ms_solve = 0, ms_backsub = 0, ms_gather = 0;
-  uint64_t ncode = 0, nW = 0;  // words
+// one layer of one member
+struct MemberLayer {
+  uint64_t n = 0, m = 0, R = 0, bumped = 0;
+  uint64_t code_off = 0, ncode = 0;  // words of the layer's shared code array
+  uint64_t word_off = 0, nW = 0;     // words of the layer's shared solution array
+  uint64_t key_off = 0;              // debug: first key in the layer's kept key array
+};
+
+// storage shared by all members of a batch for one layer
+struct LayerStore {
   uint64_t* codes = nullptr;
   uint64_t* W = nullptr;
-  uint64_t* keys = nullptr;    // kept input keys (debug flag)
+  uint64_t* keys = nullptr;  // kept input keys (debug flag)
   uint64_t steps = 0;
+  double ms_sort = 0, ms_solve = 0, ms_backsub = 0, ms_gather = 0;
+};
+
+struct Member {
+  uint64_t n = 0;
+  uint32_t r = 0;
+  uint32_t built = 0;  // BuRR layers with keys
+  MemberLayer layer[kMaxLayers];
+  MemberLayer fin;
+  uint64_t fin_attempt = 0;
+  const uint64_t* fin_W = nullptr;
+  const uint64_t* fin_keys = nullptr;  // debug
 };
 
 }  // namespace
 
 struct burr_handle {
+  struct burr_batch* b = nullptr;
+  uint32_t idx = 0;
+  bool owner = false;  // a single build: freeing the handle frees the batch
+};
+
+struct burr_batch {
   burr_params p{};
-  uint32_t r = 0;
-  uint64_t n = 0;
-  uint32_t built = 0;
-  DevLayer layer[kMaxLayers];
-  DevLayer fin;
-  uint64_t fin_attempt = 0;
   hipStream_t stream = nullptr;
   Allocator al;
-  burr_stats st{};
+  std::vector<Member> members;
+  std::vector<burr_handle> views;
+  LayerStore layers[kMaxLayers];
+  std::vector<void*> owned;  // final-layer tables and debug key arrays
+  double ms_total = 0, ms_final = 0;
 };
 
 namespace {
 
-bool params_ok(const burr_params* p, uint32_t r, const void* values, uint64_t n) {
+bool params_ok(const burr_params* p) {
   if (!p || p->abi_version != BURR_ABI_VERSION) return false;
-  if (r < 1 || r > 32) return false;
   if (p->bucket != kBucket) return false;  // the kernels handle b = w = 64
   if (!(p->t_lo > 0 && p->t_lo < p->t_hi && p->t_hi < p->bucket)) return false;
   if (!p->load_num || !p->load_den || !p->final_num || !p->final_den) return false;
   if (p->final_num < p->final_den) return false;
   if (p->layers > kMaxLayers - 1) return false;
   if (!p->ranges || !p->final_attempts) return false;
-  if (!p->filter_mode && !values && n > 0) return false;
-  if (n >= 0xfff00000ull) return false;  // record indices are 32-bit
   return true;
 }
 
 uint64_t ceil_div(unsigned __int128 a, unsigned __int128 b) { return (uint64_t)((a + b - 1) / b); }
 
-// BuRR layer geometry: m = b * max(1, ceil(load * n / b)) slots, B = m/b
-// buckets, R = min(ranges, B / max(minbpt, 2)) ranges (at least 1).
-LayerGeom plan_layer(const burr_params& p, uint64_t n, uint32_t layer, uint32_t r) {
-  LayerGeom g{};
+// BuRR layer: m = b * max(1, ceil(load * n / b)) slots, B = m/b buckets,
+// R = min(ranges, B / max(minbpt, 2)) ranges, at least 1.
+void plan_layer(const burr_params& p, uint64_t n, uint64_t* m, uint64_t* R) {
   uint64_t nb = ceil_div((unsigned __int128)n * p.load_num, (unsigned __int128)p.load_den * kBucket);
   if (nb < 1) nb = 1;
-  g.m = nb * kBucket;
-  g.nbuckets = nb;
-  uint64_t per = p.minbpt < 2 ? 2 : p.minbpt;
-  uint64_t R = nb / per;
-  if (R > p.ranges) R = p.ranges;
-  if (R < 1) R = 1;
-  g.nranges = R;
-  g.salt_s = mix64(p.seed ^ (2ull * layer + 1ull));
-  g.salt_c = mix64(p.seed ^ (2ull * layer + 2ull));
-  g.span = g.m - kWidth + 1;
-  g.t_lo = p.t_lo;
-  g.t_hi = p.t_hi;
-  g.plain = 0;
-  g.r = r;
-  return g;
+  const uint64_t per = p.minbpt < 2 ? 2 : p.minbpt;
+  uint64_t r = nb / per;
+  if (r > p.ranges) r = p.ranges;
+  if (r < 1) r = 1;
+  *m = nb * kBucket;
+  *R = r;
 }
 
-// Final plain ribbon: m = 64 * max(1, ceil(n * (final + a/10) / 64)).
-LayerGeom plan_final(const burr_params& p, uint64_t n, uint32_t attempt, uint32_t r) {
-  LayerGeom g{};
-  unsigned __int128 num =
+// Final plain ribbon, attempt a: m = 64 * max(1, ceil(n * (final + a/10) / 64)).
+uint64_t plan_final(const burr_params& p, uint64_t n, uint32_t attempt) {
+  const unsigned __int128 num =
       (unsigned __int128)n * ((uint64_t)p.final_num * 10u + (uint64_t)attempt * p.final_den);
   uint64_t nb = ceil_div(num, (unsigned __int128)p.final_den * 10u * kWidth);
   if (nb < 1) nb = 1;
-  g.m = nb * kWidth;
-  g.nbuckets = nb;
-  g.nranges = 1;
-  g.salt_s = mix64(p.seed ^ (2ull * p.layers + 1ull));
-  g.salt_c = mix64(p.seed ^ (2ull * p.layers + 2ull));
-  g.span = g.m - kWidth + 1;
-  g.t_lo = p.t_lo;
-  g.t_hi = p.t_hi;
-  g.plain = 1;
-  g.r = r;
-  return g;
+  return nb * kWidth;
 }
 
-// Reusable device workspace of one build; grows on demand.
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess) {                                                            \
+      fprintf(stderr, "burr: %s failed: %s (%s:%d)\n", #expr, hipGetErrorString(_e), \
+              __FILE__, __LINE__);                                                     \
+      return set_error(BURR_E_DEVICE);                                                 \
+    }                                                                                  \
+  } while (0)
+
+// Host copy of a layer's per-structure table (see LayerGeom).
+struct Table {
+  std::vector<uint64_t> key_off{0}, span, bucket_base{0}, range_base{0}, word_base{0},
+      code_base{0};
+  std::vector<uint32_t> rbits;
+  // next structure: n keys, m slots, R ranges (final layer: segments), r value bits
+  void add(uint64_t n, uint64_t m, uint64_t R, uint32_t r) {
+    const uint64_t B = m / 64;
+    key_off.push_back(key_off.back() + n);
+    span.push_back(m - kWidth + 1);
+    bucket_base.push_back(bucket_base.back() + B);
+    range_base.push_back(range_base.back() + R);
+    word_base.push_back(word_base.back() + B * r);
+    code_base.push_back(code_base.back() + (B + 31) / 32);
+    rbits.push_back(r);
+  }
+  uint32_t J() const { return (uint32_t)rbits.size(); }
+};
+
+// Reusable device workspace of one build; grows on demand (outgrown buffers
+// are released with the workspace, after every launch that used them).
 struct Workspace {
   Allocator* al;
   std::vector<void*> owned;
-  uint64_t cap_keys = 0, cap_m = 0, cap_B = 0, cap_counts = 0;
-  uint64_t *keysA = nullptr, *keysT = nullptr, *keysS = nullptr;
+  uint64_t cap_keys = 0, cap_m = 0, cap_B = 0, cap_counts = 0, cap_items = 0, cap_scan = 0;
+  uint64_t cap_seg = 0, cap_tab = 0, cap_J = 0;
+  uint64_t *keysA = nullptr, *keysT = nullptr, *keysS = nullptr, *slotT = nullptr;
   uint32_t *valsA = nullptr, *valsT = nullptr;
   Rec* rec = nullptr;
   uint64_t* rowsC = nullptr;
@@ -164,8 +201,12 @@ struct Workspace {
   uint64_t* occ = nullptr;
   uint8_t* code8 = nullptr;
   uint32_t *bump = nullptr, *bstart = nullptr, *counts = nullptr, *scan_tmp = nullptr;
-  uint32_t* fail = nullptr;
+  uint32_t* fail = nullptr;  // per structure
+  uint32_t* soff = nullptr;  // per structure: first bumped key
   uint64_t* steps = nullptr;
+  uint64_t* tab = nullptr;   // layer table
+  uint64_t *spillC = nullptr, *spill_occ = nullptr, *xfirst = nullptr;
+  uint32_t *spillV = nullptr, *z0first = nullptr, *bnd = nullptr;
 
   explicit Workspace(Allocator* a) : al(a) {}
   ~Workspace() {
@@ -182,10 +223,9 @@ struct Workspace {
     if (n <= cap_keys && keysA) return true;
     cap_keys = std::max<uint64_t>(n, 1);
     return alloc(keysA, cap_keys) && alloc(keysT, cap_keys) && alloc(keysS, cap_keys) &&
-           alloc(valsA, cap_keys) && alloc(valsT, cap_keys);
+           alloc(slotT, cap_keys) && alloc(valsA, cap_keys) && alloc(valsT, cap_keys);
   }
-  uint64_t cap_items = 0;
-  bool reserve_items(uint64_t count) {  // item stream: one record per key + one header per bucket
+  bool reserve_items(uint64_t count) {  // one record per key + one header per bucket
     if (count <= cap_items && rec) return true;
     cap_items = count;
     return alloc(rec, count);
@@ -194,6 +234,12 @@ struct Workspace {
     if (m <= cap_m && rowsC) return true;
     cap_m = m;
     return alloc(rowsC, m) && alloc(rowsV, m) && alloc(occ, m / 64 + 1);
+  }
+  bool reserve_scan(uint64_t n) {
+    const uint64_t need = scan_tmp_words(n) + 64;
+    if (need <= cap_scan && scan_tmp) return true;
+    cap_scan = need;
+    return alloc(scan_tmp, need);
   }
   bool reserve_buckets(uint64_t B) {
     if (B <= cap_B && bump) return reserve_scan(B + 1);
@@ -206,18 +252,16 @@ struct Workspace {
     cap_counts = c;
     return alloc(counts, c + 1) && reserve_scan(c + 1);
   }
-  uint64_t cap_scan = 0;
-  bool reserve_scan(uint64_t n) {
-    const uint64_t need = scan_tmp_words(n) + 64;
-    if (need <= cap_scan && scan_tmp) return true;
-    cap_scan = need;
-    return alloc(scan_tmp, need);
+  bool reserve_structs(uint64_t J) {
+    if (J <= cap_J && fail) return true;
+    cap_J = J;
+    return alloc(fail, J + 1) && alloc(soff, J + 1);
   }
-  bool misc() { return alloc(fail, 64) && alloc(steps, 8); }
-  // final layer segments
-  uint64_t cap_seg = 0;
-  uint64_t *spillC = nullptr, *spill_occ = nullptr, *xfirst = nullptr;
-  uint32_t *spillV = nullptr, *z0first = nullptr, *bnd = nullptr;
+  bool reserve_table(uint64_t words) {
+    if (words <= cap_tab && tab) return true;
+    cap_tab = words;
+    return alloc(tab, words);
+  }
   bool reserve_segments(uint64_t P) {
     if (P <= cap_seg && spillC) return true;
     cap_seg = P;
@@ -226,32 +270,51 @@ struct Workspace {
   }
 };
 
-#define HIP_TRY(expr)                                     \
-  do {                                                    \
-    hipError_t _e = (expr);                               \
-    if (_e != hipSuccess) {                               \
-      fprintf(stderr, "burr: %s failed: %s (%s:%d)\n", #expr, hipGetErrorString(_e), \
-              __FILE__, __LINE__);                        \
-      return set_error(BURR_E_DEVICE);                    \
-    }                                                     \
-  } while (0)
-
-// final layer: buckets per independently solved segment
-constexpr uint64_t kFinalSegBuckets = 4;
+// Uploads a table (one device buffer) and fills the geometry's pointers and totals.
+int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s) {
+  const uint64_t J = t.J();
+  const uint64_t words = 6 * (J + 1) + (J + 1) / 2 + 1;
+  if (!ws.reserve_table(words)) return set_error(BURR_E_NOMEM);
+  std::vector<uint64_t> host(words, 0);
+  uint64_t* h = host.data();
+  memcpy(h, t.key_off.data(), (J + 1) * 8);
+  memcpy(h + (J + 1), t.span.data(), J * 8);
+  memcpy(h + 2 * (J + 1), t.bucket_base.data(), (J + 1) * 8);
+  memcpy(h + 3 * (J + 1), t.range_base.data(), (J + 1) * 8);
+  memcpy(h + 4 * (J + 1), t.word_base.data(), (J + 1) * 8);
+  memcpy(h + 5 * (J + 1), t.code_base.data(), (J + 1) * 8);
+  memcpy(h + 6 * (J + 1), t.rbits.data(), J * 4);
+  HIP_TRY(hipMemcpyAsync(ws.tab, h, words * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));  // the host copy dies with this function
+  g.key_off = ws.tab;
+  g.span = ws.tab + (J + 1);
+  g.bucket_base = ws.tab + 2 * (J + 1);
+  g.range_base = ws.tab + 3 * (J + 1);
+  g.word_base = ws.tab + 4 * (J + 1);
+  g.code_base = ws.tab + 5 * (J + 1);
+  g.rbits = (const uint32_t*)(ws.tab + 6 * (J + 1));
+  g.J = (uint32_t)J;
+  g.nkeys = t.key_off.back();
+  g.nbuckets = t.bucket_base.back();
+  g.m = 64 * g.nbuckets;
+  g.nranges = t.range_base.back();
+  g.r = *std::max_element(t.rbits.begin(), t.rbits.end());
+  return BURR_OK;
+}
 
 uint32_t sort_groups(uint64_t n, uint32_t nbins) {
   // level-1 workgroups: enough to fill the chip, few enough that the
   // bins x groups count matrix stays small
   uint64_t g = (n + 4095) / 4096;
-  uint64_t cap = nbins > 4096 ? 1024 : 2048;
+  const uint64_t cap = nbins > 4096 ? 1024 : 2048;
   if (g > cap) g = cap;
   if (g < 1) g = 1;
   return (uint32_t)g;
 }
 
-// Sort one layer's n keys (device) by (bucket, chunk) into ws.keysS / ws.rec / ws.bstart.
+// Sorts one layer's keys by (bucket, chunk) into ws.keysS / ws.rec / ws.bstart.
 int run_sort(Workspace& ws, const uint64_t* keys, const void* vals, uint32_t vbytes,
-             bool first_layer, bool filter, uint64_t fp_salt, uint64_t n, const LayerGeom& g,
+             bool first_layer, bool filter, uint64_t fp_salt, const LayerGeom& g,
              hipStream_t s) {
   SortArgs a{};
   a.keys = keys;
@@ -260,18 +323,18 @@ int run_sort(Workspace& ws, const uint64_t* keys, const void* vals, uint32_t vby
   a.mask_values = first_layer ? 1u : 0u;
   a.filter = filter ? 1u : 0u;
   a.fp_salt = fp_salt;
-  a.n = n;
   a.g = g;
   a.nbins = (uint32_t)((g.nbuckets + kBucketsPerBin - 1) / kBucketsPerBin);
   if (a.nbins > kMaxBins) return set_error(BURR_E_INVALID);
-  a.groups = sort_groups(n, a.nbins);
+  a.groups = sort_groups(g.nkeys, a.nbins);
   if (!ws.reserve_counts((uint64_t)a.nbins * a.groups)) return set_error(BURR_E_NOMEM);
+  if (!ws.reserve_items(g.nkeys + g.nbuckets)) return set_error(BURR_E_NOMEM);
   a.counts = ws.counts;
   a.scan_tmp = ws.scan_tmp;
   a.tmp_keys = ws.keysT;
   a.tmp_vals = ws.valsT;
+  a.tmp_slot = ws.slotT;
   a.out_keys = ws.keysS;
-  if (!ws.reserve_items(n + g.nbuckets)) return set_error(BURR_E_NOMEM);
   a.out_rec = ws.rec;
   a.bstart = ws.bstart;
   HIP_TRY(sort_layer(a, s));
@@ -284,48 +347,157 @@ double elapsed_ms(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
-int build_impl(burr_handle* h, const uint64_t* keys, const void* values) {
-  const burr_params& p = h->p;
-  const uint32_t r = h->r;
-  hipStream_t s = h->stream;
-  const uint64_t fp_salt = mix64(~p.seed);
-  Workspace ws(&h->al);
-  if (!ws.misc()) return set_error(BURR_E_NOMEM);
-  hipEvent_t ev[6];
-  for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
-  struct EvGuard {
-    hipEvent_t* e;
-    ~EvGuard() {
-      for (int i = 0; i < 6; i++) (void)hipEventDestroy(e[i]);
-    }
-  } evg{ev};
-  HIP_TRY(hipEventRecord(ev[0], s));
+struct Events {
+  hipEvent_t e[6] = {};
+  bool ok = true;
+  Events() {
+    for (auto& x : e) ok = hipEventCreate(&x) == hipSuccess && ok;
+  }
+  ~Events() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
 
-  uint64_t cur_n = h->n;
+// Final plain layer of the listed members at one attempt index each. Their
+// final keys lie contiguously at `keys`, in list order. The table is cut
+// into segments of kFinalSegBuckets buckets that are solved in parallel;
+// rows crossing a segment end are merged afterwards. fails[i] = 1 if member
+// list[i]'s system was inconsistent at this size (then it keeps no table).
+int final_attempt(burr_batch* b, Workspace& ws, const std::vector<uint32_t>& list,
+                  const std::vector<uint32_t>& attempt, const uint64_t* keys, const void* vals,
+                  uint32_t vbytes, bool first_layer, std::vector<uint32_t>& fails) {
+  const burr_params& p = b->p;
+  hipStream_t s = b->stream;
+  Table t;
+  uint64_t max_seg = 1;
+  for (size_t i = 0; i < list.size(); ++i) {
+    const Member& mb = b->members[list[i]];
+    const uint64_t m = plan_final(p, mb.fin.n, attempt[i]);
+    const uint64_t P = std::max<uint64_t>(1, (m / 64) / kFinalSegBuckets);
+    max_seg = std::max(max_seg, P);
+    t.add(mb.fin.n, m, P, mb.r);
+  }
+  LayerGeom g{};
+  g.salt_s = mix64(p.seed ^ (2ull * p.layers + 1ull));
+  g.salt_c = mix64(p.seed ^ (2ull * p.layers + 2ull));
+  g.t_lo = p.t_lo;
+  g.t_hi = p.t_hi;
+  g.plain = 1;
+  int rc = upload_table(ws, t, g, s);
+  if (rc != BURR_OK) return rc;
+  if (!ws.reserve_slots(g.m) || !ws.reserve_buckets(g.nbuckets) || !ws.reserve_structs(g.J) ||
+      !ws.reserve_segments(g.nranges))
+    return set_error(BURR_E_NOMEM);
+  rc = run_sort(ws, keys, vals, vbytes, first_layer, p.filter_mode != 0, mix64(~p.seed), g, s);
+  if (rc != BURR_OK) return rc;
+  HIP_TRY(hipMemsetAsync(ws.fail, 0, (g.J + 1) * 4, s));
+  HIP_TRY(hipMemsetAsync(ws.spill_occ, 0, g.nranges * 8, s));
+  SolveArgs sa{};
+  sa.rec = ws.rec;
+  sa.bstart = ws.bstart;
+  sa.g = g;
+  sa.rowsC = ws.rowsC;
+  sa.rowsV = ws.rowsV;
+  sa.occ = ws.occ;
+  sa.fail = ws.fail;
+  sa.nrec = (uint32_t)(g.nkeys + g.nbuckets);
+  sa.spillC = ws.spillC;
+  sa.spillV = ws.spillV;
+  sa.spill_occ = ws.spill_occ;
+  HIP_TRY(solve_layer(sa, s));
+  FinalArgs fa{};
+  fa.g = g;
+  fa.rowsC = ws.rowsC;
+  fa.rowsV = ws.rowsV;
+  fa.occ = ws.occ;
+  fa.spillC = ws.spillC;
+  fa.spillV = ws.spillV;
+  fa.spill_occ = ws.spill_occ;
+  fa.fail = ws.fail;
+  fa.z0first = ws.z0first;
+  fa.xfirst = ws.xfirst;
+  fa.bnd = ws.bnd;
+  HIP_TRY(final_merge(fa, max_seg, s));
+  // boundaries and back-substitution run for every listed member; the
+  // words of a member that failed are never referenced
+  HIP_TRY(final_boundaries(fa, s));
+  uint64_t* W = (uint64_t*)b->al.get(t.word_base.back() * 8 + 8);
+  if (!W) return set_error(BURR_E_NOMEM);
+  b->owned.push_back(W);
+  HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, ws.occ, g, W, s, ws.bnd));
+  fails.assign(g.J, 0);
+  HIP_TRY(hipMemcpyAsync(fails.data(), ws.fail, g.J * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (size_t i = 0; i < list.size(); ++i) {
+    if (fails[i] >= 2) {
+      fprintf(stderr, "burr: internal error %u in the final layer\n", fails[i]);
+      return set_error(BURR_E_DEVICE);
+    }
+    if (fails[i]) continue;
+    Member& mb = b->members[list[i]];
+    mb.fin.m = 64 * (t.bucket_base[i + 1] - t.bucket_base[i]);
+    mb.fin.nW = t.word_base[i + 1] - t.word_base[i];
+    mb.fin_W = W + t.word_base[i];
+    mb.fin_attempt = attempt[i];
+  }
+  return BURR_OK;
+}
+
+// Builds every member of b. Member i's keys are keys[off[i], off[i+1]), its
+// values the same range of `values` (elements of value_bytes(max r) bytes).
+int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
+                const std::vector<uint64_t>& off) {
+  const burr_params& p = b->p;
+  hipStream_t s = b->stream;
+  const uint64_t fp_salt = mix64(~p.seed);
+  const uint32_t M = (uint32_t)b->members.size();
+  uint32_t rmax = 1;
+  for (const Member& mb : b->members) rmax = std::max(rmax, mb.r);
+  Workspace ws(&b->al);
+  Events ev;
+  if (!ev.ok) return set_error(BURR_E_DEVICE);
+  if (!ws.reserve_keys(off.back()) || !ws.alloc(ws.steps, 8)) return set_error(BURR_E_NOMEM);
+  HIP_TRY(hipEventRecord(ev.e[0], s));
+
+  // members with keys in the current layer, in key order, and their key counts
+  std::vector<uint32_t> active;
+  std::vector<uint64_t> cur_n;
+  for (uint32_t i = 0; i < M; ++i)
+    if (off[i + 1] > off[i]) {
+      active.push_back(i);
+      cur_n.push_back(off[i + 1] - off[i]);
+    }
   const uint64_t* cur_keys = keys;
   const void* cur_vals = values;
-  uint32_t cur_vbytes = value_bytes(r);
+  uint32_t cur_vbytes = value_bytes(rmax);
   bool first = true;
-  double ms_sort = 0, ms_solve = 0;
-  if (!ws.reserve_keys(cur_n)) return set_error(BURR_E_NOMEM);
 
-  uint32_t li = 0;
-  while (li < p.layers && cur_n > 0) {
-    DevLayer& L = h->layer[li];
-    const LayerGeom g = plan_layer(p, cur_n, li, r);
-    L.n = cur_n;
-    L.m = g.m;
-    L.B = g.nbuckets;
-    L.R = g.nranges;
-    if (p.flags & BURR_FLAG_KEEP_LAYER_KEYS) {
-      L.keys = (uint64_t*)h->al.get(cur_n * 8);
-      if (!L.keys) return set_error(BURR_E_NOMEM);
-      HIP_TRY(hipMemcpyAsync(L.keys, cur_keys, cur_n * 8, hipMemcpyDeviceToDevice, s));
+  for (uint32_t li = 0; li < p.layers && !active.empty(); ++li) {
+    LayerStore& LS = b->layers[li];
+    Table t;
+    for (size_t a = 0; a < active.size(); ++a) {
+      uint64_t m, R;
+      plan_layer(p, cur_n[a], &m, &R);
+      t.add(cur_n[a], m, R, b->members[active[a]].r);
     }
-    if (!ws.reserve_slots(g.m) || !ws.reserve_buckets(g.nbuckets)) return set_error(BURR_E_NOMEM);
-    HIP_TRY(hipEventRecord(ev[1], s));
-    int rc = run_sort(ws, cur_keys, cur_vals, cur_vbytes, first, p.filter_mode != 0, fp_salt,
-                      cur_n, g, s);
+    LayerGeom g{};
+    g.salt_s = mix64(p.seed ^ (2ull * li + 1ull));
+    g.salt_c = mix64(p.seed ^ (2ull * li + 2ull));
+    g.t_lo = p.t_lo;
+    g.t_hi = p.t_hi;
+    g.plain = 0;
+    int rc = upload_table(ws, t, g, s);
+    if (rc != BURR_OK) return rc;
+    if (!ws.reserve_slots(g.m) || !ws.reserve_buckets(g.nbuckets) || !ws.reserve_structs(g.J))
+      return set_error(BURR_E_NOMEM);
+    if (p.flags & BURR_FLAG_KEEP_LAYER_KEYS) {
+      LS.keys = (uint64_t*)b->al.get(g.nkeys * 8);
+      if (!LS.keys) return set_error(BURR_E_NOMEM);
+      HIP_TRY(hipMemcpyAsync(LS.keys, cur_keys, g.nkeys * 8, hipMemcpyDeviceToDevice, s));
+    }
+    HIP_TRY(hipEventRecord(ev.e[1], s));
+    rc = run_sort(ws, cur_keys, cur_vals, cur_vbytes, first, p.filter_mode != 0, fp_salt, g, s);
     if (rc != BURR_OK) return rc;
 
     SolveArgs sa{};
@@ -339,223 +511,180 @@ int build_impl(burr_handle* h, const uint64_t* keys, const void* values) {
     sa.bump = ws.bump;
     sa.fail = ws.fail;
     sa.steps = ws.steps;
-    sa.nrec = (uint32_t)(cur_n + g.nbuckets);
+    sa.nrec = (uint32_t)(g.nkeys + g.nbuckets);
     HIP_TRY(hipMemsetAsync(ws.steps, 0, 64, s));
-    HIP_TRY(hipMemsetAsync(ws.fail, 0, 4, s));
-    HIP_TRY(hipEventRecord(ev[2], s));
+    HIP_TRY(hipMemsetAsync(ws.fail, 0, (g.J + 1) * 4, s));
+    HIP_TRY(hipEventRecord(ev.e[2], s));
     HIP_TRY(solve_layer(sa, s));
-    HIP_TRY(hipEventRecord(ev[4], s));
+    HIP_TRY(hipEventRecord(ev.e[3], s));
 
-    L.ncode = (g.nbuckets + 31) / 32;
-    L.nW = (g.m / 64) * r;
-    L.codes = (uint64_t*)h->al.get(L.ncode * 8);
-    L.W = (uint64_t*)h->al.get(L.nW * 8);
-    if (!L.codes || !L.W) return set_error(BURR_E_NOMEM);
-    HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, ws.occ, g, L.W, s));
-    HIP_TRY(pack_codes(ws.code8, g.nbuckets, L.codes, s));
-    HIP_TRY(hipEventRecord(ev[3], s));
+    LS.codes = (uint64_t*)b->al.get(t.code_base.back() * 8);
+    LS.W = (uint64_t*)b->al.get(t.word_base.back() * 8);
+    if (!LS.codes || !LS.W) return set_error(BURR_E_NOMEM);
+    HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, ws.occ, g, LS.W, s));
+    HIP_TRY(pack_codes(ws.code8, g, t.code_base.back(), LS.codes, s));
+    HIP_TRY(hipEventRecord(ev.e[4], s));
 
-    // bumped keys: exclusive scan of per-bucket counts, then gather
+    // bumped keys: exclusive scan of per-bucket counts, then gather; the
+    // next layer's keys stay grouped by structure in structure order
     HIP_TRY(hipMemsetAsync(ws.bump + g.nbuckets, 0, 4, s));
     HIP_TRY(scan_exclusive(ws.bump, g.nbuckets + 1, ws.scan_tmp, s));
-    uint32_t nnext = 0, failed = 0;
+    HIP_TRY(struct_offsets(ws.bump, g, ws.soff, s));
+    std::vector<uint32_t> soff(g.J + 1), fails(g.J);
     uint64_t steps = 0;
-    HIP_TRY(hipMemcpyAsync(&failed, ws.fail, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&nnext, ws.bump + g.nbuckets, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(soff.data(), ws.soff, (g.J + 1) * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(fails.data(), ws.fail, g.J * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&steps, ws.steps, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(gather_bumped(ws.keysS, ws.rec, ws.bstart, ws.bump, g.nbuckets, ws.keysA, ws.valsA,
                           s));
-    HIP_TRY(hipEventRecord(ev[5], s));
+    HIP_TRY(hipEventRecord(ev.e[5], s));
     HIP_TRY(hipStreamSynchronize(s));
 #ifdef BURR_SOLVE_DEBUG
     {
       uint64_t d[4];
       if (hipMemcpy(d, ws.steps, 32, hipMemcpyDeviceToHost) == hipSuccess)
-        fprintf(stderr, "solve-debug layer %u: steps %llu lane-iters %llu elim-iters %llu want-iters %llu\n",
-                li, (unsigned long long)d[0], (unsigned long long)d[1], (unsigned long long)d[2],
-                (unsigned long long)d[3]);
+        fprintf(stderr, "solve-debug layer %u: steps %llu lane-iters %llu elim-iters %llu "
+                "want-iters %llu\n", li, (unsigned long long)d[0], (unsigned long long)d[1],
+                (unsigned long long)d[2], (unsigned long long)d[3]);
     }
 #endif
-    if (failed) {
-      fprintf(stderr, "burr: internal error %u in the insertion kernel, layer %u\n", failed, li);
-      return set_error(BURR_E_DEVICE);
+    for (uint32_t f : fails)
+      if (f) {
+        fprintf(stderr, "burr: internal error %u in the insertion kernel, layer %u\n", f, li);
+        return set_error(BURR_E_DEVICE);
+      }
+    LS.ms_sort = elapsed_ms(ev.e[1], ev.e[2]);
+    LS.ms_solve = elapsed_ms(ev.e[2], ev.e[3]);
+    LS.ms_backsub = elapsed_ms(ev.e[3], ev.e[4]);
+    LS.ms_gather = elapsed_ms(ev.e[4], ev.e[5]);
+    LS.steps = steps;
+
+    std::vector<uint32_t> next_active;
+    std::vector<uint64_t> next_n;
+    for (size_t a = 0; a < active.size(); ++a) {
+      Member& mb = b->members[active[a]];
+      MemberLayer& L = mb.layer[li];
+      L.n = cur_n[a];
+      L.m = t.span[a] + kWidth - 1;
+      L.R = t.range_base[a + 1] - t.range_base[a];
+      L.bumped = soff[a + 1] - soff[a];
+      L.code_off = t.code_base[a];
+      L.ncode = t.code_base[a + 1] - t.code_base[a];
+      L.word_off = t.word_base[a];
+      L.nW = t.word_base[a + 1] - t.word_base[a];
+      L.key_off = t.key_off[a];
+      mb.built = li + 1;
+      if (L.bumped) {
+        next_active.push_back(active[a]);
+        next_n.push_back(L.bumped);
+      }
     }
-    L.ms_sort = elapsed_ms(ev[1], ev[2]);
-    L.ms_solve = elapsed_ms(ev[2], ev[4]);
-    L.ms_backsub = elapsed_ms(ev[4], ev[3]);
-    L.ms_gather = elapsed_ms(ev[3], ev[5]);
-    ms_sort += L.ms_sort;
-    ms_solve += L.ms_solve + L.ms_backsub;
-    L.bumped = nnext;
-    L.steps = steps;
-    cur_n = nnext;
+    active.swap(next_active);
+    cur_n.swap(next_n);
     cur_keys = ws.keysA;
     cur_vals = ws.valsA;
     cur_vbytes = 4;
     first = false;
-    ++li;
   }
-  h->built = li;
 
-  // final plain ribbon layer
-  DevLayer& F = h->fin;
-  F.n = cur_n;
-  HIP_TRY(hipEventRecord(ev[1], s));
-  if (p.flags & BURR_FLAG_KEEP_LAYER_KEYS) {
-    F.keys = (uint64_t*)h->al.get(cur_n * 8 + 8);
-    if (!F.keys) return set_error(BURR_E_NOMEM);
-    if (cur_n) HIP_TRY(hipMemcpyAsync(F.keys, cur_keys, cur_n * 8, hipMemcpyDeviceToDevice, s));
+  // final plain layer of every member that still has keys
+  HIP_TRY(hipEventRecord(ev.e[1], s));
+  std::vector<uint64_t> fin_off(active.size() + 1, 0);
+  for (size_t a = 0; a < active.size(); ++a) {
+    b->members[active[a]].fin.n = cur_n[a];
+    fin_off[a + 1] = fin_off[a] + cur_n[a];
   }
-  if (cur_n == 0) {
-    F.m = 0;
-    F.nW = 0;
-    h->fin_attempt = 0;
-  } else {
-    bool solved = false;
-    for (uint32_t a = 0; a < p.final_attempts && !solved; ++a) {
-      const LayerGeom g = plan_final(p, cur_n, a, r);
-      if (!ws.reserve_slots(g.m) || !ws.reserve_buckets(g.nbuckets)) return set_error(BURR_E_NOMEM);
-      int rc = run_sort(ws, cur_keys, cur_vals, cur_vbytes, first, p.filter_mode != 0, fp_salt,
-                        cur_n, g, s);
-      if (rc != BURR_OK) return rc;
-      // The table is cut into segments of kFinalSegBuckets buckets solved in
-      // parallel; rows crossing a segment end are merged afterwards.
-      LayerGeom gs = g;
-      gs.nranges = std::max<uint64_t>(1, g.nbuckets / kFinalSegBuckets);
-      if (!ws.reserve_segments(gs.nranges)) return set_error(BURR_E_NOMEM);
-      HIP_TRY(hipMemsetAsync(ws.fail, 0, 4, s));
-      HIP_TRY(hipMemsetAsync(ws.steps, 0, 64, s));
-      HIP_TRY(hipMemsetAsync(ws.spill_occ, 0, gs.nranges * 8, s));
-      SolveArgs sa{};
-      sa.rec = ws.rec;
-      sa.bstart = ws.bstart;
-      sa.g = gs;
-      sa.rowsC = ws.rowsC;
-      sa.rowsV = ws.rowsV;
-      sa.occ = ws.occ;
-      sa.fail = ws.fail;
-      sa.steps = ws.steps;
-      sa.nrec = (uint32_t)(cur_n + g.nbuckets);
-      sa.spillC = ws.spillC;
-      sa.spillV = ws.spillV;
-      sa.spill_occ = ws.spill_occ;
-      HIP_TRY(solve_layer(sa, s));
-      FinalArgs fa{};
-      fa.g = gs;
-      fa.rowsC = ws.rowsC;
-      fa.rowsV = ws.rowsV;
-      fa.occ = ws.occ;
-      fa.spillC = ws.spillC;
-      fa.spillV = ws.spillV;
-      fa.spill_occ = ws.spill_occ;
-      fa.fail = ws.fail;
-      fa.z0first = ws.z0first;
-      fa.xfirst = ws.xfirst;
-      fa.bnd = ws.bnd;
-      HIP_TRY(final_merge(fa, s));
-      uint32_t failed = 0;
-      uint64_t steps = 0;
-      HIP_TRY(hipMemcpyAsync(&failed, ws.fail, 4, hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(&steps, ws.steps, 8, hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      F.steps += steps;
-      if (failed >= 2) {
-        fprintf(stderr, "burr: internal error %u in the final layer\n", failed);
-        return set_error(BURR_E_DEVICE);
+  if ((p.flags & BURR_FLAG_KEEP_LAYER_KEYS) && !active.empty()) {
+    uint64_t* kk = (uint64_t*)b->al.get(fin_off.back() * 8);
+    if (!kk) return set_error(BURR_E_NOMEM);
+    b->owned.push_back(kk);
+    HIP_TRY(hipMemcpyAsync(kk, cur_keys, fin_off.back() * 8, hipMemcpyDeviceToDevice, s));
+    for (size_t a = 0; a < active.size(); ++a) b->members[active[a]].fin_keys = kk + fin_off[a];
+  }
+  if (!active.empty()) {
+    std::vector<uint32_t> zero(active.size(), 0), fails;
+    int rc = final_attempt(b, ws, active, zero, cur_keys, cur_vals, cur_vbytes, first, fails);
+    if (rc != BURR_OK) return rc;
+    // rare: a member whose final system was inconsistent retries alone with
+    // larger tables (Sec. 3: the last layer grows until it succeeds)
+    for (size_t a = 0; a < active.size(); ++a) {
+      if (!fails[a]) continue;
+      const void* v = cur_vals ? (const void*)((const uint8_t*)cur_vals + fin_off[a] * cur_vbytes)
+                               : nullptr;
+      bool solved = false;
+      for (uint32_t att = 1; att < p.final_attempts && !solved; ++att) {
+        std::vector<uint32_t> one(1, active[a]), at(1, att), f1;
+        rc = final_attempt(b, ws, one, at, cur_keys + fin_off[a], v, cur_vbytes, first, f1);
+        if (rc != BURR_OK) return rc;
+        solved = f1[0] == 0;
       }
-      if (failed) continue;
-      F.m = g.m;
-      F.nW = (g.m / 64) * r;
-      F.W = (uint64_t*)h->al.get(F.nW * 8);
-      if (!F.W) return set_error(BURR_E_NOMEM);
-      HIP_TRY(final_boundaries(fa, s));
-      HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, ws.occ, gs, F.W, s, ws.bnd));
-      h->fin_attempt = a;
-      solved = true;
+      if (!solved) return set_error(BURR_E_UNSOLVABLE);
     }
-    if (!solved) return set_error(BURR_E_UNSOLVABLE);
   }
-  HIP_TRY(hipEventRecord(ev[2], s));
+  HIP_TRY(hipEventRecord(ev.e[2], s));
   HIP_TRY(hipStreamSynchronize(s));
-
-  burr_stats& st = h->st;
-  memset(&st, 0, sizeof(st));
-  st.n = h->n;
-  st.r = r;
-  st.layers_built = h->built;
-  uint64_t bytes = 0;
-  for (uint32_t i = 0; i < h->built; ++i) {
-    st.layer[i].n = h->layer[i].n;
-    st.layer[i].m = h->layer[i].m;
-    st.layer[i].nbuckets = h->layer[i].B;
-    st.layer[i].nranges = h->layer[i].R;
-    st.layer[i].bumped = h->layer[i].bumped;
-    st.layer[i].steps = h->layer[i].steps;
-    st.layer[i].ms_sort = h->layer[i].ms_sort;
-    st.layer[i].ms_solve = h->layer[i].ms_solve;
-    st.layer[i].ms_backsub = h->layer[i].ms_backsub;
-    st.layer[i].ms_gather = h->layer[i].ms_gather;
-    bytes += (h->layer[i].ncode + h->layer[i].nW) * 8;
-  }
-  st.final_n = F.n;
-  st.final_m = F.m;
-  st.final_attempt = h->fin_attempt;
-  st.table_bytes = bytes + F.nW * 8;
-  st.ms_sort = ms_sort;
-  st.ms_solve = ms_solve;
-  st.ms_final = elapsed_ms(ev[1], ev[2]);
-  st.ms_total = elapsed_ms(ev[0], ev[2]);
+  b->ms_final = elapsed_ms(ev.e[1], ev.e[2]);
+  b->ms_total = elapsed_ms(ev.e[0], ev.e[2]);
   return BURR_OK;
 }
 
-void free_layer(Allocator& al, DevLayer& L) {
-  al.put(L.codes);
-  al.put(L.W);
-  al.put(L.keys);
-  L.codes = nullptr;
-  L.W = nullptr;
-  L.keys = nullptr;
-}
-
-burr_handle* new_handle(const burr_params* p) {
-  burr_handle* h = new (std::nothrow) burr_handle();
-  if (!h) return nullptr;
-  h->p = *p;
-  h->stream = (hipStream_t)p->stream;
-  h->al.fn = p->alloc;
-  h->al.ffn = p->free;
-  h->al.ctx = p->alloc_ctx;
-  h->al.s = h->stream;
+burr_batch* new_batch(const burr_params* p, uint32_t count) {
+  burr_batch* b = new (std::nothrow) burr_batch();
+  if (!b) return nullptr;
+  b->p = *p;
+  b->stream = (hipStream_t)p->stream;
+  b->al.fn = p->alloc;
+  b->al.ffn = p->free;
+  b->al.ctx = p->alloc_ctx;
+  b->al.s = b->stream;
+  b->members.resize(count);
+  b->views.resize(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    b->views[i].b = b;
+    b->views[i].idx = i;
+  }
   int dev = 0;
   if (hipGetDevice(&dev) == hipSuccess) keep_pool_memory(dev);
-  return h;
+  return b;
 }
 
-QueryPlan make_plan(const burr_handle* h) {
+void free_batch(burr_batch* b) {
+  if (!b) return;
+  for (uint32_t i = 0; i < kMaxLayers; ++i) {
+    b->al.put(b->layers[i].codes);
+    b->al.put(b->layers[i].W);
+    b->al.put(b->layers[i].keys);
+  }
+  for (void* q : b->owned) b->al.put(q);
+  (void)hipStreamSynchronize(b->stream);
+  delete b;
+}
+
+QueryPlan make_plan(const burr_batch* b, const Member& mb) {
   QueryPlan plan{};
-  plan.r = h->r;
+  plan.r = mb.r;
   uint32_t l = 0;
-  for (; l < h->built; ++l) {
-    const DevLayer& L = h->layer[l];
+  for (; l < mb.built; ++l) {
+    const MemberLayer& L = mb.layer[l];
     QueryLayer& q = plan.layer[l];
-    q.salt_s = mix64(h->p.seed ^ (2ull * l + 1ull));
-    q.salt_c = mix64(h->p.seed ^ (2ull * l + 2ull));
+    q.salt_s = mix64(b->p.seed ^ (2ull * l + 1ull));
+    q.salt_c = mix64(b->p.seed ^ (2ull * l + 2ull));
     q.span = L.m - kWidth + 1;
-    q.codes = L.codes;
-    q.W = L.W;
-    q.t_lo = h->p.t_lo;
-    q.t_hi = h->p.t_hi;
+    q.codes = b->layers[l].codes + L.code_off;
+    q.W = b->layers[l].W + L.word_off;
+    q.t_lo = b->p.t_lo;
+    q.t_hi = b->p.t_hi;
     q.plain = 0;
     q.empty = 0;
   }
   QueryLayer& f = plan.layer[l];
-  f.salt_s = mix64(h->p.seed ^ (2ull * h->p.layers + 1ull));
-  f.salt_c = mix64(h->p.seed ^ (2ull * h->p.layers + 2ull));
-  f.span = h->fin.m ? h->fin.m - kWidth + 1 : 1;
+  f.salt_s = mix64(b->p.seed ^ (2ull * b->p.layers + 1ull));
+  f.salt_c = mix64(b->p.seed ^ (2ull * b->p.layers + 2ull));
+  f.span = mb.fin.m ? mb.fin.m - kWidth + 1 : 1;
   f.codes = nullptr;
-  f.W = h->fin.W;
+  f.W = mb.fin_W;
   f.plain = 1;
-  f.empty = h->fin.m == 0;
+  f.empty = mb.fin.m == 0;
   plan.nlayers = l + 1;
   return plan;
 }
@@ -593,6 +722,11 @@ struct In {
   }
 };
 
+const Member* member_of(const burr_handle* h) {
+  if (!h || !h->b || h->idx >= h->b->members.size()) return nullptr;
+  return &h->b->members[h->idx];
+}
+
 }  // namespace
 
 extern "C" {
@@ -619,72 +753,162 @@ void burr_default_params(burr_params* p) {
 
 burr_handle* burr_build(const uint64_t* keys, const void* values, uint64_t n, uint32_t r,
                         const burr_params* p) {
-  if (!params_ok(p, r, values, n) || (n > 0 && !keys)) {
+  if (!params_ok(p) || r < 1 || r > 32 || (n > 0 && !keys) ||
+      (!p->filter_mode && !values && n > 0) || n >= kMaxKeys) {
     set_error(BURR_E_INVALID);
     return nullptr;
   }
-  burr_handle* h = new_handle(p);
-  if (!h) {
+  burr_batch* b = new_batch(p, 1);
+  if (!b) {
     set_error(BURR_E_NOMEM);
     return nullptr;
   }
-  h->r = r;
-  h->n = n;
-  int rc = build_impl(h, keys, values);
+  b->members[0].n = n;
+  b->members[0].r = r;
+  b->views[0].owner = true;
+  const std::vector<uint64_t> off = {0, n};
+  const int rc = build_batch(b, keys, values, off);
   if (rc != BURR_OK) {
-    burr_free(h);
+    free_batch(b);
     set_error(rc);
     return nullptr;
   }
   set_error(BURR_OK);
-  return h;
+  return &b->views[0];
 }
 
+burr_batch* burr_build_batch(const uint64_t* keys, const void* values,
+                             const uint64_t* host_offsets, const uint32_t* host_r,
+                             uint32_t count, const burr_params* p) {
+  if (!params_ok(p) || !host_offsets || !host_r || count == 0) {
+    set_error(BURR_E_INVALID);
+    return nullptr;
+  }
+  const std::vector<uint64_t> off(host_offsets, host_offsets + count + 1);
+  for (uint32_t i = 0; i < count; ++i)
+    if (off[i + 1] < off[i] || host_r[i] < 1 || host_r[i] > 32) {
+      set_error(BURR_E_INVALID);
+      return nullptr;
+    }
+  const uint64_t total = off.back();
+  if (off[0] != 0 || total >= kMaxKeys || (total > 0 && !keys) ||
+      (!p->filter_mode && !values && total > 0)) {
+    set_error(BURR_E_INVALID);
+    return nullptr;
+  }
+  burr_batch* b = new_batch(p, count);
+  if (!b) {
+    set_error(BURR_E_NOMEM);
+    return nullptr;
+  }
+  for (uint32_t i = 0; i < count; ++i) {
+    b->members[i].n = off[i + 1] - off[i];
+    b->members[i].r = host_r[i];
+  }
+  const int rc = build_batch(b, keys, values, off);
+  if (rc != BURR_OK) {
+    free_batch(b);
+    set_error(rc);
+    return nullptr;
+  }
+  set_error(BURR_OK);
+  return b;
+}
+
+uint32_t burr_batch_size(const burr_batch* b) { return b ? (uint32_t)b->members.size() : 0; }
+
+const burr_handle* burr_batch_member(const burr_batch* b, uint32_t i) {
+  if (!b || i >= b->members.size()) {
+    set_error(BURR_E_INVALID);
+    return nullptr;
+  }
+  return &b->views[i];
+}
+
+void burr_batch_free(burr_batch* b) { free_batch(b); }
+
 int burr_query(const burr_handle* h, const uint64_t* keys, uint64_t n, void* out, void* stream) {
-  if (!h || (n > 0 && (!keys || !out))) return set_error(BURR_E_INVALID);
-  QueryPlan plan = make_plan(h);
-  hipStream_t s = stream ? (hipStream_t)stream : h->stream;
-  if (query(plan, keys, n, out, value_bytes(h->r), 0, 0, s) != hipSuccess)
+  const Member* mb = member_of(h);
+  if (!mb || (n > 0 && (!keys || !out))) return set_error(BURR_E_INVALID);
+  const QueryPlan plan = make_plan(h->b, *mb);
+  hipStream_t s = stream ? (hipStream_t)stream : h->b->stream;
+  if (query(plan, keys, n, out, value_bytes(mb->r), 0, 0, s) != hipSuccess)
     return set_error(BURR_E_DEVICE);
   return BURR_OK;
 }
 
 int burr_contains(const burr_handle* h, const uint64_t* keys, uint64_t n, uint8_t* out,
                   void* stream) {
-  if (!h || !h->p.filter_mode || (n > 0 && (!keys || !out))) return set_error(BURR_E_INVALID);
-  QueryPlan plan = make_plan(h);
-  hipStream_t s = stream ? (hipStream_t)stream : h->stream;
-  if (query(plan, keys, n, out, 1, 1, mix64(~h->p.seed), s) != hipSuccess)
+  const Member* mb = member_of(h);
+  if (!mb || !h->b->p.filter_mode || (n > 0 && (!keys || !out))) return set_error(BURR_E_INVALID);
+  const QueryPlan plan = make_plan(h->b, *mb);
+  hipStream_t s = stream ? (hipStream_t)stream : h->b->stream;
+  if (query(plan, keys, n, out, 1, 1, mix64(~h->b->p.seed), s) != hipSuccess)
     return set_error(BURR_E_DEVICE);
   return BURR_OK;
 }
 
 void burr_free(burr_handle* h) {
-  if (!h) return;
-  for (uint32_t i = 0; i < kMaxLayers; ++i) free_layer(h->al, h->layer[i]);
-  free_layer(h->al, h->fin);
-  (void)hipStreamSynchronize(h->stream);
-  delete h;
+  if (!h || !h->b) return;
+  if (!h->owner) {  // a batch member: its memory belongs to the batch
+    set_error(BURR_E_INVALID);
+    return;
+  }
+  free_batch(h->b);
 }
 
-int burr_get_stats(const burr_handle* h, burr_stats* s) {
-  if (!h || !s) return set_error(BURR_E_INVALID);
-  *s = h->st;
+int burr_get_stats(const burr_handle* h, burr_stats* st) {
+  const Member* mb = member_of(h);
+  if (!mb || !st) return set_error(BURR_E_INVALID);
+  const burr_batch* b = h->b;
+  memset(st, 0, sizeof(*st));
+  st->n = mb->n;
+  st->r = mb->r;
+  st->layers_built = mb->built;
+  uint64_t bytes = 0;
+  double ms_sort = 0, ms_solve = 0;
+  for (uint32_t i = 0; i < mb->built; ++i) {
+    const MemberLayer& L = mb->layer[i];
+    const LayerStore& LS = b->layers[i];
+    st->layer[i].n = L.n;
+    st->layer[i].m = L.m;
+    st->layer[i].nbuckets = L.m / 64;
+    st->layer[i].nranges = L.R;
+    st->layer[i].bumped = L.bumped;
+    st->layer[i].steps = LS.steps;
+    st->layer[i].ms_sort = LS.ms_sort;
+    st->layer[i].ms_solve = LS.ms_solve;
+    st->layer[i].ms_backsub = LS.ms_backsub;
+    st->layer[i].ms_gather = LS.ms_gather;
+    ms_sort += LS.ms_sort;
+    ms_solve += LS.ms_solve + LS.ms_backsub;
+    bytes += (L.ncode + L.nW) * 8;
+  }
+  st->final_n = mb->fin.n;
+  st->final_m = mb->fin.m;
+  st->final_attempt = mb->fin_attempt;
+  st->table_bytes = bytes + mb->fin.nW * 8;
+  st->ms_sort = ms_sort;
+  st->ms_solve = ms_solve;
+  st->ms_final = b->ms_final;
+  st->ms_total = b->ms_total;
   return BURR_OK;
 }
 
 int burr_export(const burr_handle* h, void* host_buf, size_t cap, size_t* needed) {
-  if (!h) return set_error(BURR_E_INVALID);
+  const Member* mb = member_of(h);
+  if (!mb) return set_error(BURR_E_INVALID);
+  const burr_batch* b = h->b;
   Out o{(uint8_t*)host_buf, host_buf ? cap : 0};
-  const burr_params& p = h->p;
+  const burr_params& p = b->p;
   o.put(kExportMagic, 8);
-  const uint32_t hdr[16] = {kExportVersion, kWidth,        p.bucket,  h->r,         p.load_num,
-                            p.load_den,     p.final_num,   p.final_den, p.layers,   p.t_lo,
-                            p.t_hi,         p.ranges,      p.minbpt,  p.final_attempts,
-                            p.filter_mode,  h->built};
+  const uint32_t hdr[16] = {kExportVersion, kWidth,      p.bucket,    mb->r,    p.load_num,
+                            p.load_den,     p.final_num, p.final_den, p.layers, p.t_lo,
+                            p.t_hi,         p.ranges,    p.minbpt,    p.final_attempts,
+                            p.filter_mode,  mb->built};
   for (uint32_t x : hdr) o.put(x, 4);
   o.put(p.seed, 8);
-  o.put(h->n, 8);
+  o.put(mb->n, 8);
   std::vector<uint64_t> tmp;
   auto copy_words = [&](const uint64_t* d, uint64_t nw) -> bool {
     tmp.assign(nw, 0);
@@ -692,28 +916,28 @@ int burr_export(const burr_handle* h, void* host_buf, size_t cap, size_t* needed
     return true;
   };
   const bool fill = host_buf != nullptr;
-  for (uint32_t l = 0; l < h->built; ++l) {
-    const DevLayer& L = h->layer[l];
+  for (uint32_t l = 0; l < mb->built; ++l) {
+    const MemberLayer& L = mb->layer[l];
     o.put(L.n, 8);
     o.put(L.m, 8);
     o.put(L.R, 8);
     if (fill) {
-      if (!copy_words(L.codes, L.ncode)) return set_error(BURR_E_DEVICE);
+      if (!copy_words(b->layers[l].codes + L.code_off, L.ncode)) return set_error(BURR_E_DEVICE);
       o.put_words(tmp);
-      if (!copy_words(L.W, L.nW)) return set_error(BURR_E_DEVICE);
+      if (!copy_words(b->layers[l].W + L.word_off, L.nW)) return set_error(BURR_E_DEVICE);
       o.put_words(tmp);
     } else {
       o.len += (L.ncode + L.nW) * 8;
     }
   }
-  o.put(h->fin.n, 8);
-  o.put(h->fin.m, 8);
-  o.put(h->fin_attempt, 8);
+  o.put(mb->fin.n, 8);
+  o.put(mb->fin.m, 8);
+  o.put(mb->fin_attempt, 8);
   if (fill) {
-    if (!copy_words(h->fin.W, h->fin.nW)) return set_error(BURR_E_DEVICE);
+    if (!copy_words(mb->fin_W, mb->fin.nW)) return set_error(BURR_E_DEVICE);
     o.put_words(tmp);
   } else {
-    o.len += h->fin.nW * 8;
+    o.len += mb->fin.nW * 8;
   }
   if (needed) *needed = o.len;
   if (host_buf && o.len > cap) return set_error(BURR_E_INVALID);
@@ -754,17 +978,19 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
   def.final_attempts = hdr[13];
   def.filter_mode = hdr[14];
   def.seed = in.get(8);
-  burr_handle* h = new_handle(&def);
-  if (!h) {
+  burr_batch* b = new_batch(&def, 1);
+  if (!b) {
     set_error(BURR_E_NOMEM);
     return nullptr;
   }
-  h->r = hdr[3];
-  h->n = in.get(8);
-  h->built = hdr[15];
+  b->views[0].owner = true;
+  Member& mb = b->members[0];
+  mb.r = hdr[3];
+  mb.n = in.get(8);
+  mb.built = hdr[15];
   auto load_words = [&](uint64_t nw, uint64_t** dst) -> bool {
     if (in.off + nw * 8 > in.len) return false;
-    *dst = (uint64_t*)h->al.get(nw * 8 + 8);
+    *dst = (uint64_t*)b->al.get(nw * 8 + 8);
     if (!*dst) return false;
     if (nw && hipMemcpy(*dst, in.buf + in.off, nw * 8, hipMemcpyHostToDevice) != hipSuccess)
       return false;
@@ -772,48 +998,58 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
     return true;
   };
   bool ok = in.ok;
-  for (uint32_t l = 0; ok && l < h->built; ++l) {
-    DevLayer& L = h->layer[l];
+  for (uint32_t l = 0; ok && l < mb.built; ++l) {
+    MemberLayer& L = mb.layer[l];
     L.n = in.get(8);
     L.m = in.get(8);
     L.R = in.get(8);
-    if (!in.ok || L.m % 64 || L.m < 64) { ok = false; break; }
-    L.B = L.m / 64;
-    L.ncode = (L.B + 31) / 32;
-    L.nW = (L.m / 64) * h->r;
-    ok = load_words(L.ncode, &L.codes) && load_words(L.nW, &L.W);
+    if (!in.ok || L.m % 64 || L.m < 64) {
+      ok = false;
+      break;
+    }
+    L.ncode = (L.m / 64 + 31) / 32;
+    L.nW = (L.m / 64) * mb.r;
+    ok = load_words(L.ncode, &b->layers[l].codes) && load_words(L.nW, &b->layers[l].W);
   }
   if (ok) {
-    h->fin.n = in.get(8);
-    h->fin.m = in.get(8);
-    h->fin_attempt = in.get(8);
-    ok = in.ok && h->fin.m % 64 == 0;
+    mb.fin.n = in.get(8);
+    mb.fin.m = in.get(8);
+    mb.fin_attempt = in.get(8);
+    ok = in.ok && mb.fin.m % 64 == 0;
     if (ok) {
-      h->fin.nW = (h->fin.m / 64) * h->r;
-      ok = load_words(h->fin.nW, &h->fin.W);
+      mb.fin.nW = (mb.fin.m / 64) * mb.r;
+      uint64_t* w = nullptr;
+      ok = load_words(mb.fin.nW, &w);
+      if (w) b->owned.push_back(w);
+      mb.fin_W = w;
     }
   }
   if (!ok || in.off != in.len) {
-    burr_free(h);
+    free_batch(b);
     set_error(BURR_E_INVALID);
     return nullptr;
   }
-  h->st.n = h->n;
-  h->st.r = h->r;
-  h->st.layers_built = h->built;
   set_error(BURR_OK);
-  return h;
+  return &b->views[0];
 }
 
 int64_t burr_debug_layer_keys(const burr_handle* h, uint32_t layer, uint64_t* host_out,
                               uint64_t cap) {
-  if (!h || layer > h->built || !(h->p.flags & BURR_FLAG_KEEP_LAYER_KEYS))
+  const Member* mb = member_of(h);
+  if (!mb || layer > mb->built || !(h->b->p.flags & BURR_FLAG_KEEP_LAYER_KEYS))
     return set_error(BURR_E_INVALID);
-  const DevLayer& L = layer < h->built ? h->layer[layer] : h->fin;
-  uint64_t n = L.n;
-  if (host_out && cap) {
-    uint64_t c = std::min(n, cap);
-    if (c && hipMemcpy(host_out, L.keys, c * 8, hipMemcpyDeviceToHost) != hipSuccess)
+  const uint64_t* src;
+  uint64_t n;
+  if (layer < mb->built) {
+    src = h->b->layers[layer].keys + mb->layer[layer].key_off;
+    n = mb->layer[layer].n;
+  } else {
+    src = mb->fin_keys;
+    n = mb->fin.n;
+  }
+  if (host_out && cap && n) {
+    const uint64_t c = std::min(n, cap);
+    if (hipMemcpy(host_out, src, c * 8, hipMemcpyDeviceToHost) != hipSuccess)
       return set_error(BURR_E_DEVICE);
   }
   return (int64_t)n;

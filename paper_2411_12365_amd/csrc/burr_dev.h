@@ -25,22 +25,49 @@ __host__ __device__ inline uint64_t mix64(uint64_t x) {
   return x;
 }
 
-// Geometry and hash salts of one layer, passed by value to kernels.
+// Geometry of one layer of one or more structures built together (a single
+// build is one structure). Passed by value to kernels; the per-structure
+// tables live in device memory. Structure j of the layer owns
+//   keys         [key_off[j],     key_off[j+1])      of the layer's key array
+//   buckets      [bucket_base[j], bucket_base[j+1])  (global bucket space)
+//   ranges       [range_base[j],  range_base[j+1])   (segments in the final layer)
+//   table words  [word_base[j],   word_base[j+1])    solution words
+//   code words   [code_base[j],   code_base[j+1])
+// and hashes its keys into span[j] = m_j - 63 possible start slots.
 struct LayerGeom {
   uint64_t salt_s;   // start-position salt of the layer
   uint64_t salt_c;   // coefficient-row salt of the layer
-  uint64_t span;     // m - w + 1: number of possible start slots
-  uint64_t m;        // slots
-  uint64_t nbuckets; // m / 64
-  uint64_t nranges;  // independent ranges
+  uint64_t m;        // total slots = 64 * nbuckets
+  uint64_t nbuckets; // total buckets
+  uint64_t nranges;  // total ranges (final layer: segments)
+  uint64_t nkeys;    // total keys
   uint32_t t_lo, t_hi;
   uint32_t plain;    // 1: final plain ribbon (one chunk, conflicts fail)
-  uint32_t r;        // value bits
+  uint32_t r;        // largest value width of the structures
+  uint32_t J;        // structures in the layer
+  uint32_t pad;
+  const uint64_t* key_off;
+  const uint64_t* span;
+  const uint64_t* bucket_base;
+  const uint64_t* range_base;
+  const uint64_t* word_base;
+  const uint64_t* code_base;
+  const uint32_t* rbits;
 };
 
-// start slot in [0, m-64]: high word of mix64(key^salt) * span
-__device__ inline uint64_t start_of(uint64_t key, const LayerGeom& g) {
-  return __umul64hi(mix64(key ^ g.salt_s), g.span);
+// largest j < J with base[j] <= x (base strictly increasing, base[0] <= x)
+__device__ inline uint32_t find_struct(const uint64_t* base, uint32_t J, uint64_t x) {
+  uint32_t lo = 0, hi = J;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (base[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// start slot in [0, span-1] = [0, m-64]: high word of mix64(key^salt) * span
+__device__ inline uint64_t start_of(uint64_t key, uint64_t salt, uint64_t span) {
+  return __umul64hi(mix64(key ^ salt), span);
 }
 // coefficient row; bit j <-> slot s+j, bit 0 always set
 __device__ inline uint64_t row_of(uint64_t key, const LayerGeom& g) {

@@ -1,5 +1,6 @@
 // burr_kernels.h - host-side launchers of the HIP kernels (internal to the
-// library; the public interface is include/burr.h).
+// library; the public interface is include/burr.h). Every launcher works on
+// one layer of one or more structures described by a LayerGeom.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,26 +15,27 @@ size_t scan_tmp_words(size_t n);
 hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s);
 
 // Sorting of one layer's keys by (bucket, chunk) - two passes:
-//   level 1: partition keys into coarse bins of kBucketsPerBin buckets
-//   level 2: one workgroup per bin orders its keys by (bucket, chunk) and
-//            writes records + bucket start offsets.
+//   level 1: hash every key, partition into coarse bins of kBucketsPerBin
+//            global buckets; the start slot travels with the key
+//   level 2: one workgroup per bin orders its keys by (bucket, chunk) in LDS
+//            and writes the item stream (bucket headers + records)
 struct SortArgs {
-  const uint64_t* keys;   // input keys (n)
-  const void* vals;       // input values (n) or nullptr (filter fingerprints)
+  const uint64_t* keys;   // input keys (g.nkeys), structure j at g.key_off[j]
+  const void* vals;       // input values or nullptr (filter fingerprints)
   uint32_t vbytes;        // 1, 2 or 4
-  uint32_t mask_values;   // layer 0: mask to r bits / compute fingerprints
+  uint32_t mask_values;   // first layer: mask to r bits / compute fingerprints
   uint64_t fp_salt;       // fingerprint salt (filter mode)
   uint32_t filter;        // values are fingerprints
-  uint64_t n;
   LayerGeom g;
   uint32_t nbins;         // ceil(B / kBucketsPerBin)
   uint32_t groups;        // level-1 workgroups
-  uint32_t* counts;       // nbins * groups (+1) u32, scanned in place
+  uint32_t* counts;       // nbins * groups u32, scanned in place
   uint32_t* scan_tmp;
-  uint64_t* tmp_keys;     // level-1 output (n)
-  uint32_t* tmp_vals;     // level-1 output values widened to u32 (n)
-  uint64_t* out_keys;     // level-2 output keys (n)
-  Rec* out_rec;           // level-2 output records (n)
+  uint64_t* tmp_keys;     // level-1 output (nkeys)
+  uint32_t* tmp_vals;
+  uint64_t* tmp_slot;     // global start slot of each key
+  uint64_t* out_keys;     // level-2 output keys (nkeys), bucket order
+  Rec* out_rec;           // item stream (nkeys + nbuckets)
   uint32_t* bstart;       // B + 1 bucket start offsets
 };
 hipError_t sort_layer(const SortArgs& a, hipStream_t s);
@@ -49,9 +51,9 @@ struct SolveArgs {
   uint64_t* occ;       // m/64 occupancy words
   uint8_t* code8;      // B codes (not in plain mode)
   uint32_t* bump;      // B bumped-key counts (not in plain mode)
-  uint32_t* fail;      // plain mode: set to 1 on an inconsistent equation
+  uint32_t* fail;      // per structure: 1 inconsistent final layer, >= 2 internal error
   uint64_t* steps;     // optional: total elimination steps (statistics)
-  uint32_t nrec;       // number of records (prefetch bound)
+  uint32_t nrec;       // number of items (prefetch bound)
   // final-layer segments: rows that land past a segment's end go to its
   // spill buffer (64 rows + occupancy word per segment) instead of failing
   uint64_t* spillC;
@@ -60,16 +62,29 @@ struct SolveArgs {
 };
 hipError_t solve_layer(const SolveArgs& a, hipStream_t s);
 
-// Back-substitution per range into column-interleaved words W[k*r+col].
-// bnd (optional, 64 u32 per range): solution values of the 63 slots after
-// each range's end (final-layer segments, whose rows cross segment ends).
+// Back-substitution per range into column-interleaved words
+// W[word_base[j] + k*r_j + col]. bnd (optional, 64 u32 per range): solution
+// values of the 63 slots after each range's end (final-layer segments, whose
+// rows cross segment ends).
 hipError_t back_substitute(const uint64_t* rowsC, const uint32_t* rowsV, const uint64_t* occ,
                            const LayerGeom& g, uint64_t* W, hipStream_t s,
                            const uint32_t* bnd = nullptr);
 
+// code8[B] -> packed 2-bit code words of every structure
+hipError_t pack_codes(const uint8_t* code8, const LayerGeom& g, uint64_t ncode_words,
+                      uint64_t* words, hipStream_t s);
+
+// Copy the bumped suffix of every bucket into the next layer's input.
+hipError_t gather_bumped(const uint64_t* sorted_keys, const Rec* rec, const uint32_t* bstart,
+                         const uint32_t* off /* scanned bump counts, B+1 */, uint64_t B,
+                         uint64_t* next_keys, uint32_t* next_vals, hipStream_t s);
+
+// out[j] = off[bucket_base[j]] for j <= J (bumped keys before structure j)
+hipError_t struct_offsets(const uint32_t* off, const LayerGeom& g, uint32_t* out, hipStream_t s);
+
 // Final plain layer, after the per-segment solve (g.nranges = segments):
-// merge the segments' spill rows pairwise over log2(segments) levels, then
-// compute each segment's boundary values.
+// merge each structure's segments' spill rows pairwise over log2 levels,
+// then compute each segment's boundary values.
 struct FinalArgs {
   LayerGeom g;
   uint64_t* rowsC;
@@ -78,21 +93,13 @@ struct FinalArgs {
   uint64_t* spillC;
   uint32_t* spillV;
   uint64_t* spill_occ;
-  uint32_t* fail;
-  uint32_t* z0first;  // segments x 64: values of a segment's first 63 slots with a zero boundary
+  uint32_t* fail;     // per structure
+  uint32_t* z0first;  // segments x 64: a segment's first 63 values with a zero boundary
   uint64_t* xfirst;   // segments x 64: their dependence on the 63 boundary values
   uint32_t* bnd;      // segments x 64: true values of the 63 slots after each segment
 };
-hipError_t final_merge(const FinalArgs& a, hipStream_t s);
+hipError_t final_merge(const FinalArgs& a, uint64_t max_segments, hipStream_t s);
 hipError_t final_boundaries(const FinalArgs& a, hipStream_t s);
-
-// code8[B] -> packed 2-bit code words
-hipError_t pack_codes(const uint8_t* code8, uint64_t B, uint64_t* words, hipStream_t s);
-
-// Copy the bumped suffix of every bucket into the next layer's input.
-hipError_t gather_bumped(const uint64_t* sorted_keys, const Rec* rec, const uint32_t* bstart,
-                         const uint32_t* off /* scanned bump counts, B+1 */, uint64_t B,
-                         uint64_t* next_keys, uint32_t* next_vals, hipStream_t s);
 
 hipError_t query(const QueryPlan& plan, const uint64_t* keys, uint64_t n, void* out,
                  uint32_t out_bytes, uint32_t contains, uint64_t fp_salt, hipStream_t s);

@@ -115,21 +115,47 @@ hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s
 constexpr int kL1Threads = 256;
 constexpr int kL2Threads = 512;
 
-__device__ inline uint32_t coarse_bin(uint64_t s) {
-  return (uint32_t)((s >> 6) / kBucketsPerBin);
-}
+// Threads walk their keys in increasing index order: the structure of the
+// first key is found by binary search, later ones by stepping forward.
+struct KeyWalk {
+  uint32_t j;
+  uint64_t end;   // first key of the next structure
+  uint64_t span;  // start positions of structure j
+  uint64_t bb;    // first global bucket of structure j
+  uint32_t r;     // value bits of structure j
+  __device__ KeyWalk(const LayerGeom& g, uint64_t i) {
+    j = i < g.nkeys ? find_struct(g.key_off, g.J, i) : 0;
+    load(g);
+  }
+  __device__ void load(const LayerGeom& g) {
+    end = g.key_off[j + 1];
+    span = g.span[j];
+    bb = g.bucket_base[j];
+    r = g.rbits[j];
+  }
+  __device__ void advance(const LayerGeom& g, uint64_t i) {
+    while (i >= end) {
+      ++j;
+      load(g);
+    }
+  }
+};
 
 __global__ __launch_bounds__(kL1Threads) void k_l1_hist(const uint64_t* __restrict__ keys,
-                                                         uint64_t n, LayerGeom g, uint32_t nbins,
+                                                         LayerGeom g, uint32_t nbins,
                                                          uint32_t groups, uint64_t per_group,
                                                          uint32_t* __restrict__ counts) {
   extern __shared__ uint32_t hist[];
   for (uint32_t i = threadIdx.x; i < nbins; i += kL1Threads) hist[i] = 0;
   __syncthreads();
   const uint64_t lo = (uint64_t)blockIdx.x * per_group;
-  const uint64_t hi = lo + per_group < n ? lo + per_group : n;
-  for (uint64_t i = lo + threadIdx.x; i < hi; i += kL1Threads)
-    atomicAdd(&hist[coarse_bin(start_of(keys[i], g))], 1u);
+  const uint64_t hi = lo + per_group < g.nkeys ? lo + per_group : g.nkeys;
+  KeyWalk w(g, lo + threadIdx.x);
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kL1Threads) {
+    w.advance(g, i);
+    const uint64_t s = start_of(keys[i], g.salt_s, w.span);
+    atomicAdd(&hist[(uint32_t)((w.bb + (s >> 6)) / kBucketsPerBin)], 1u);
+  }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nbins; i += kL1Threads)
     counts[(size_t)i * groups + blockIdx.x] = hist[i];
@@ -137,61 +163,71 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_hist(const uint64_t* __restri
 
 template <typename VT>
 __global__ __launch_bounds__(kL1Threads) void k_l1_scatter(
-    const uint64_t* __restrict__ keys, const VT* __restrict__ vals, uint64_t n, LayerGeom g,
+    const uint64_t* __restrict__ keys, const VT* __restrict__ vals, LayerGeom g,
     uint32_t nbins, uint32_t groups, uint64_t per_group, const uint32_t* __restrict__ offs,
     uint32_t mask_values, uint32_t filter, uint64_t fp_salt, uint64_t* __restrict__ tk,
-    uint32_t* __restrict__ tv) {
+    uint32_t* __restrict__ tv, uint64_t* __restrict__ ts) {
   extern __shared__ uint32_t cur[];
   for (uint32_t i = threadIdx.x; i < nbins; i += kL1Threads)
     cur[i] = offs[(size_t)i * groups + blockIdx.x];
   __syncthreads();
   const uint64_t lo = (uint64_t)blockIdx.x * per_group;
-  const uint64_t hi = lo + per_group < n ? lo + per_group : n;
-  const uint32_t vmask = g.r >= 32 ? 0xffffffffu : ((1u << g.r) - 1u);
+  const uint64_t hi = lo + per_group < g.nkeys ? lo + per_group : g.nkeys;
+  KeyWalk w(g, lo + threadIdx.x);
   for (uint64_t i = lo + threadIdx.x; i < hi; i += kL1Threads) {
+    w.advance(g, i);
     const uint64_t key = keys[i];
     uint32_t v;
     if (filter && mask_values)
-      v = (uint32_t)(mix64(key ^ fp_salt) >> (64 - g.r));
+      v = (uint32_t)(mix64(key ^ fp_salt) >> (64 - w.r));
+    else if (mask_values)
+      v = (uint32_t)vals[i] & (w.r >= 32 ? 0xffffffffu : ((1u << w.r) - 1u));
     else
-      v = mask_values ? ((uint32_t)vals[i] & vmask) : (uint32_t)vals[i];
-    const uint32_t pos = atomicAdd(&cur[coarse_bin(start_of(key, g))], 1u);
+      v = (uint32_t)vals[i];
+    const uint64_t slot = 64 * w.bb + start_of(key, g.salt_s, w.span);
+    const uint32_t pos = atomicAdd(&cur[(uint32_t)((slot >> 6) / kBucketsPerBin)], 1u);
     tk[pos] = key;
     tv[pos] = v;
+    ts[pos] = slot;
   }
 }
 
-// Forced threshold index of bucket beta: the last bucket of a range that is
-// not the last one must bump every key that starts past its first slot
-// (b = w = 64), so its threshold is the smallest 2-bit value above the largest
-// offset of such a key (Sec. 3 "Bumping").
+// Forced threshold index of global bucket beta: the last bucket of a range
+// that is not its structure's last range must bump every key that starts
+// past its first slot (b = w = 64), so its threshold is the smallest 2-bit
+// value above the largest offset of such a key (Sec. 3 "Bumping").
 __device__ inline uint32_t forced_kf(uint64_t beta, uint32_t maxoff, uint32_t count,
                                      const LayerGeom& g) {
   if (g.plain || count == 0 || maxoff == 0) return 0;
-  const uint64_t rho = ((beta + 1) * g.nranges - 1) / g.nbuckets;
-  if (rho + 1 >= g.nranges) return 0;
-  if ((rho + 1) * g.nbuckets / g.nranges != beta + 1) return 0;
+  const uint32_t j = find_struct(g.bucket_base, g.J, beta);
+  const uint64_t B = g.bucket_base[j + 1] - g.bucket_base[j];
+  const uint64_t R = g.range_base[j + 1] - g.range_base[j];
+  const uint64_t b = beta - g.bucket_base[j];
+  const uint64_t rho = ((b + 1) * R - 1) / B;
+  if (rho + 1 >= R) return 0;
+  if ((rho + 1) * B / R != b + 1) return 0;
   return maxoff >= g.t_hi ? 3u : (maxoff >= g.t_lo ? 2u : 1u);
 }
 
 __global__ __launch_bounds__(kL2Threads) void k_l2_sort(
-    const uint64_t* __restrict__ tk, const uint32_t* __restrict__ tv, uint64_t n, LayerGeom g,
-    uint32_t nbins, uint32_t groups, const uint32_t* __restrict__ offs,
-    uint64_t* __restrict__ ok, Rec* __restrict__ items, uint32_t* __restrict__ bstart) {
+    const uint64_t* __restrict__ tk, const uint32_t* __restrict__ tv,
+    const uint64_t* __restrict__ ts, LayerGeom g, uint32_t nbins, uint32_t groups,
+    const uint32_t* __restrict__ offs, uint64_t* __restrict__ ok, Rec* __restrict__ items,
+    uint32_t* __restrict__ bstart) {
   __shared__ uint32_t hist[kDigitsPerBin];
   __shared__ uint32_t maxoff[kBucketsPerBin];
   __shared__ uint32_t wsum[kL2Threads / 64];
   const uint32_t bin = blockIdx.x;
   const uint64_t lo = offs[(size_t)bin * groups];
-  const uint64_t hi = bin + 1 < nbins ? offs[(size_t)(bin + 1) * groups] : n;
+  const uint64_t hi = bin + 1 < nbins ? offs[(size_t)(bin + 1) * groups] : g.nkeys;
   const uint64_t bbase = (uint64_t)bin * kBucketsPerBin;
   for (uint32_t i = threadIdx.x; i < kDigitsPerBin; i += kL2Threads) hist[i] = 0;
   for (uint32_t i = threadIdx.x; i < kBucketsPerBin; i += kL2Threads) maxoff[i] = 0;
   __syncthreads();
   for (uint64_t i = lo + threadIdx.x; i < hi; i += kL2Threads) {
-    const uint64_t s = start_of(tk[i], g);
-    const uint32_t b = (uint32_t)((s >> 6) - bbase);
-    const uint32_t o = (uint32_t)s & 63u;
+    const uint64_t slot = ts[i];
+    const uint32_t b = (uint32_t)((slot >> 6) - bbase);
+    const uint32_t o = (uint32_t)slot & 63u;
     atomicAdd(&hist[b * 3u + rank_of(o, g)], 1u);
     atomicMax(&maxoff[b], o);
   }
@@ -229,10 +265,10 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_sort(
   __syncthreads();
   for (uint64_t i = lo + threadIdx.x; i < hi; i += kL2Threads) {
     const uint64_t key = tk[i];
-    const uint64_t s = start_of(key, g);
-    const uint32_t o = (uint32_t)s & 63u;
+    const uint64_t slot = ts[i];
+    const uint32_t o = (uint32_t)slot & 63u;
     const uint32_t rk = rank_of(o, g);
-    const uint64_t beta = s >> 6;
+    const uint64_t beta = slot >> 6;
     const uint32_t d = (uint32_t)(beta - bbase) * 3u + rk;
     const uint64_t pos = lo + atomicAdd(&hist[d], 1u);
     ok[pos] = key;
@@ -244,9 +280,9 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_sort(
 }
 
 hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
-  const uint64_t per_group = (a.n + a.groups - 1) / a.groups;
+  const uint64_t per_group = (a.g.nkeys + a.groups - 1) / a.groups;
   const size_t hist_bytes = (size_t)a.nbins * sizeof(uint32_t);
-  k_l1_hist<<<a.groups, kL1Threads, hist_bytes, s>>>(a.keys, a.n, a.g, a.nbins, a.groups,
+  k_l1_hist<<<a.groups, kL1Threads, hist_bytes, s>>>(a.keys, a.g, a.nbins, a.groups,
                                                      per_group, a.counts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -255,24 +291,24 @@ hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
   switch (a.vbytes) {
     case 1:
       k_l1_scatter<uint8_t><<<a.groups, kL1Threads, hist_bytes, s>>>(
-          a.keys, (const uint8_t*)a.vals, a.n, a.g, a.nbins, a.groups, per_group, a.counts,
-          a.mask_values, a.filter, a.fp_salt, a.tmp_keys, a.tmp_vals);
+          a.keys, (const uint8_t*)a.vals, a.g, a.nbins, a.groups, per_group, a.counts,
+          a.mask_values, a.filter, a.fp_salt, a.tmp_keys, a.tmp_vals, a.tmp_slot);
       break;
     case 2:
       k_l1_scatter<uint16_t><<<a.groups, kL1Threads, hist_bytes, s>>>(
-          a.keys, (const uint16_t*)a.vals, a.n, a.g, a.nbins, a.groups, per_group, a.counts,
-          a.mask_values, a.filter, a.fp_salt, a.tmp_keys, a.tmp_vals);
+          a.keys, (const uint16_t*)a.vals, a.g, a.nbins, a.groups, per_group, a.counts,
+          a.mask_values, a.filter, a.fp_salt, a.tmp_keys, a.tmp_vals, a.tmp_slot);
       break;
     default:
       k_l1_scatter<uint32_t><<<a.groups, kL1Threads, hist_bytes, s>>>(
-          a.keys, (const uint32_t*)a.vals, a.n, a.g, a.nbins, a.groups, per_group, a.counts,
-          a.mask_values, a.filter, a.fp_salt, a.tmp_keys, a.tmp_vals);
+          a.keys, (const uint32_t*)a.vals, a.g, a.nbins, a.groups, per_group, a.counts,
+          a.mask_values, a.filter, a.fp_salt, a.tmp_keys, a.tmp_vals, a.tmp_slot);
       break;
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_l2_sort<<<a.nbins, kL2Threads, 0, s>>>(a.tmp_keys, a.tmp_vals, a.n, a.g, a.nbins, a.groups,
-                                           a.counts, a.out_keys, a.out_rec, a.bstart);
+  k_l2_sort<<<a.nbins, kL2Threads, 0, s>>>(a.tmp_keys, a.tmp_vals, a.tmp_slot, a.g, a.nbins,
+                                           a.groups, a.counts, a.out_keys, a.out_rec, a.bstart);
   return hipGetLastError();
 }
 
@@ -328,9 +364,15 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
   uint64_t fb = 0;
   uint32_t nq = 0;
   uint32_t x = 0, xend = 0;  // item cursor and end of the range's items
+  uint32_t js = 0;           // structure of the range
   if (rho < g.nranges) {
-    fb = rho * g.nbuckets / g.nranges;
-    nq = (uint32_t)((rho + 1) * g.nbuckets / g.nranges - fb);
+    js = find_struct(g.range_base, g.J, rho);
+    const uint64_t B = g.bucket_base[js + 1] - g.bucket_base[js];
+    const uint64_t R = g.range_base[js + 1] - g.range_base[js];
+    const uint64_t lr = rho - g.range_base[js];
+    const uint64_t f0 = lr * B / R;
+    fb = g.bucket_base[js] + f0;
+    nq = (uint32_t)((lr + 1) * B / R - f0);
     x = a.bstart[fb] + (uint32_t)fb;
     xend = a.bstart[fb + nq] + (uint32_t)(fb + nq);
     state = ST_WANT;
@@ -374,7 +416,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
 
     for (int it = 0; it < kRoundIters; ++it) {
       if (state != ST_DONE && iter_left-- == 0) {
-        *a.fail = 3u;
+        a.fail[js] = 3u;
         state = ST_DONE;
       }
 #ifdef BURR_SOLVE_DEBUG
@@ -422,7 +464,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         } else {
           // unreachable for kept keys of a BuRR layer; stop instead of
           // writing outside the range
-          *a.fail = 2u;
+          a.fail[js] = 2u;
           state = ST_DONE;
         }
       }
@@ -466,7 +508,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         continue;
       if (state == ST_CONFLICT) {
         if (g.plain) {
-          *a.fail = 1u;
+          a.fail[js] = 1u;
           state = ST_DONE;
         } else {
           vm0 &= ~pm0;  // undo the chunk; the rest of the bucket is bumped
@@ -590,9 +632,14 @@ __global__ __launch_bounds__(256) void k_backsub(const uint64_t* __restrict__ ro
                                                  const uint32_t* __restrict__ bnd) {
   const uint64_t rho = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   if (rho >= g.nranges) return;
-  const uint64_t fb = rho * g.nbuckets / g.nranges;
-  const uint64_t lb = (rho + 1) * g.nbuckets / g.nranges;
-  const uint32_t r = g.r;
+  const uint32_t j = find_struct(g.range_base, g.J, rho);
+  const uint64_t B = g.bucket_base[j + 1] - g.bucket_base[j];
+  const uint64_t R = g.range_base[j + 1] - g.range_base[j];
+  const uint64_t lr = rho - g.range_base[j];
+  const uint64_t fb = g.bucket_base[j] + lr * B / R;
+  const uint64_t lb = g.bucket_base[j] + (lr + 1) * B / R;
+  const uint32_t r = g.rbits[j];
+  const uint64_t wb = g.word_base[j], bb = g.bucket_base[j];  // block k at wb + (k-bb)*r
   uint64_t win[RMAX];  // bit j of win[col] = column col of Z[i+1+j]
 #pragma unroll
   for (int col = 0; col < RMAX; ++col) win[col] = 0;
@@ -629,7 +676,8 @@ __global__ __launch_bounds__(256) void k_backsub(const uint64_t* __restrict__ ro
         }
       }
     }
-    for (uint32_t col = 0; col < r && col < (uint32_t)RMAX; ++col) W[k * r + col] = out[col];
+    for (uint32_t col = 0; col < r && col < (uint32_t)RMAX; ++col)
+      W[wb + (k - bb) * r + col] = out[col];
   }
 }
 
@@ -655,25 +703,43 @@ hipError_t back_substitute(const uint64_t* rowsC, const uint32_t* rowsV, const u
 // slots), so after log2(segments) levels the whole layer is one echelon
 // system - the same row space, hence the same solution with free slots 0.
 
-__device__ inline uint64_t seg_first_slot(uint64_t p, const LayerGeom& g) {
-  return 64 * (p * g.nbuckets / g.nranges);
+// slots [start, end) of global segment p (a "range" of the final layer)
+struct SegBounds {
+  uint32_t j;       // structure
+  uint64_t first;   // first global segment of the structure
+  uint64_t count;   // segments of the structure
+  uint64_t start, end;
+};
+__device__ inline SegBounds seg_bounds(uint64_t p, const LayerGeom& g) {
+  SegBounds sb;
+  sb.j = find_struct(g.range_base, g.J, p);
+  const uint64_t B = g.bucket_base[sb.j + 1] - g.bucket_base[sb.j];
+  sb.first = g.range_base[sb.j];
+  sb.count = g.range_base[sb.j + 1] - sb.first;
+  const uint64_t lp = p - sb.first;
+  sb.start = 64 * (g.bucket_base[sb.j] + lp * B / sb.count);
+  sb.end = 64 * (g.bucket_base[sb.j] + (lp + 1) * B / sb.count);
+  return sb;
 }
 
 constexpr uint32_t kMergeWin = 384;  // slots of the right group staged in LDS
 
+// One workgroup per segment p; it merges at level G when p starts a left
+// group of G segments inside its structure and a right group follows.
 __global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
   __shared__ uint64_t wc[kMergeWin];
   __shared__ uint32_t wv[kMergeWin];
   __shared__ uint64_t wocc[kMergeWin / 64];
   const LayerGeom g = a.g;
-  const uint64_t P = g.nranges;
-  const uint64_t L0 = (uint64_t)blockIdx.x * 2 * G;
-  const uint64_t R0 = L0 + G;
-  if (R0 >= P) return;
+  const uint64_t p = blockIdx.x;
+  const SegBounds sp = seg_bounds(p, g);
+  const uint64_t lp = p - sp.first;
+  if (lp % (2ull * G) != 0 || lp + G >= sp.count) return;
+  const uint64_t R0 = p + G;
   const uint64_t lastL = R0 - 1;
-  const uint64_t lastR = (L0 + 2 * G < P ? L0 + 2 * G : P) - 1;
-  const uint64_t start = seg_first_slot(R0, g);
-  const uint64_t endR = seg_first_slot(lastR + 1, g);  // slot after the right group
+  const uint64_t lastR = (lp + 2ull * G < sp.count ? p + 2ull * G : sp.first + sp.count) - 1;
+  const uint64_t start = seg_bounds(R0, g).start;
+  const uint64_t endR = seg_bounds(lastR, g).end;  // slot after the right group
   // window: slots [start, start + win); slots >= endR are the right group's
   // spill zone, which the window holds either completely or not at all
   const uint64_t span = endR + 64 - start;
@@ -762,7 +828,7 @@ __global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
         i += j;
       }
     }
-    if (bad) *a.fail = internal ? 2u : 1u;
+    if (bad) a.fail[sp.j] = internal ? 2u : 1u;
     a.spill_occ[lastL] = 0;
   }
   __syncthreads();
@@ -785,11 +851,9 @@ __global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
   }
 }
 
-hipError_t final_merge(const FinalArgs& a, hipStream_t s) {
-  const uint64_t P = a.g.nranges;
-  for (uint64_t G = 1; G < P; G *= 2) {
-    const uint64_t pairs = (P + 2 * G - 1) / (2 * G);
-    k_merge<<<(unsigned)pairs, 64, 0, s>>>(a, (uint32_t)G);
+hipError_t final_merge(const FinalArgs& a, uint64_t max_segments, hipStream_t s) {
+  for (uint64_t G = 1; G < max_segments; G *= 2) {
+    k_merge<<<(unsigned)a.g.nranges, 64, 0, s>>>(a, (uint32_t)G);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -806,8 +870,8 @@ __global__ __launch_bounds__(64) void k_final_partial(FinalArgs a) {
   const uint32_t lane = threadIdx.x;
   const uint64_t p = (uint64_t)blockIdx.x * 64 + lane;
   if (p >= g.nranges) return;
-  const uint64_t start = seg_first_slot(p, g);
-  const uint64_t end = seg_first_slot(p + 1, g);
+  const SegBounds sb = seg_bounds(p, g);
+  const uint64_t start = sb.start, end = sb.end;
   for (uint64_t i = end; i-- > start;) {
     uint32_t z = 0;
     uint64_t X = 0;
@@ -835,15 +899,18 @@ __global__ __launch_bounds__(64) void k_final_partial(FinalArgs a) {
   }
 }
 
-// From the last segment down: the boundary of segment p-1 is the true value
-// of segment p's first 63 slots = z0 xor (X applied to segment p's boundary).
+// One workgroup per structure, from its last segment down: the boundary of
+// segment p-1 is the true value of segment p's first 63 slots = z0 xor (X
+// applied to segment p's boundary).
 __global__ __launch_bounds__(64) void k_final_scan(FinalArgs a) {
   __shared__ uint32_t b[64];
   const uint32_t t = threadIdx.x;
-  const uint64_t P = a.g.nranges;
-  b[t] = 0;  // nothing lies past the last segment
+  const LayerGeom g = a.g;
+  const uint32_t j = blockIdx.x;
+  const uint64_t first = g.range_base[j], last = g.range_base[j + 1];
+  b[t] = 0;  // nothing lies past the structure's last segment
   __syncthreads();
-  for (uint64_t p = P; p-- > 0;) {
+  for (uint64_t p = last; p-- > first;) {
     a.bnd[p * 64 + t] = b[t];
     uint32_t z = 0;
     if (t < 63) {
@@ -866,29 +933,44 @@ hipError_t final_boundaries(const FinalArgs& a, hipStream_t s) {
   k_final_partial<<<(unsigned)((P + 63) / 64), 64, 0, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_final_scan<<<1, 64, 0, s>>>(a);
+  k_final_scan<<<a.g.J, 64, 0, s>>>(a);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Codes and bumped keys
 // ---------------------------------------------------------------------------
-__global__ void k_pack_codes(const uint8_t* __restrict__ code8, uint64_t B,
-                             uint64_t* __restrict__ words) {
+__global__ void k_pack_codes(const uint8_t* __restrict__ code8, LayerGeom g,
+                             uint64_t ncode_words, uint64_t* __restrict__ words) {
   const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= (B + 31) / 32) return;
+  if (w >= ncode_words) return;
+  const uint32_t j = find_struct(g.code_base, g.J, w);
+  const uint64_t B = g.bucket_base[j + 1] - g.bucket_base[j];
+  const uint64_t wl = w - g.code_base[j];
   uint64_t word = 0;
-  for (uint64_t j = 0; j < 32; ++j) {
-    const uint64_t beta = w * 32 + j;
-    if (beta < B) word |= (uint64_t)(code8[beta] & 3u) << (2 * j);
+  for (uint64_t t = 0; t < 32; ++t) {
+    const uint64_t b = wl * 32 + t;
+    if (b < B) word |= (uint64_t)(code8[g.bucket_base[j] + b] & 3u) << (2 * t);
   }
   words[w] = word;
 }
 
-hipError_t pack_codes(const uint8_t* code8, uint64_t B, uint64_t* words, hipStream_t s) {
-  const uint64_t nw = (B + 31) / 32;
-  if (nw == 0) return hipSuccess;
-  k_pack_codes<<<(unsigned)((nw + 255) / 256), 256, 0, s>>>(code8, B, words);
+hipError_t pack_codes(const uint8_t* code8, const LayerGeom& g, uint64_t ncode_words,
+                      uint64_t* words, hipStream_t s) {
+  if (ncode_words == 0) return hipSuccess;
+  k_pack_codes<<<(unsigned)((ncode_words + 255) / 256), 256, 0, s>>>(code8, g, ncode_words,
+                                                                     words);
+  return hipGetLastError();
+}
+
+__global__ void k_struct_offsets(const uint32_t* __restrict__ off, LayerGeom g,
+                                 uint32_t* __restrict__ out) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j <= g.J) out[j] = off[g.bucket_base[j]];
+}
+
+hipError_t struct_offsets(const uint32_t* off, const LayerGeom& g, uint32_t* out, hipStream_t s) {
+  k_struct_offsets<<<(g.J + 256) / 256, 256, 0, s>>>(off, g, out);
   return hipGetLastError();
 }
 

@@ -1,0 +1,40 @@
+"""Shared checks of a GPU-built structure against the oracle's (GPU tests)."""
+import numpy as np
+
+from paper_2411_12365_amd import workload as W
+
+
+def to_dev(a):
+    import torch
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def check_handle(h, ref, keys, filt=False, n_queries=20000, layer_keys=True):
+    """Bit-exact: per-layer sizes (and key sets when kept), final layer
+    sizes, export bytes, query results of members and non-members."""
+    st = h.stats()
+    assert st["layers_built"] == ref.layers_built
+    for li in range(ref.layers_built):
+        info = ref.layer_info(li)
+        gl = st["layers"][li]
+        assert (gl["n"], gl["m"], gl["nranges"], gl["bumped"]) == \
+            (info["n"], info["m"], info["nranges"], info["bumped"]), f"layer {li} sizes"
+        if layer_keys:
+            assert np.array_equal(np.sort(h.layer_keys(li)), np.sort(ref.layer_keys(li))), \
+                f"layer {li} key set"
+    fin = ref.final_info()
+    assert (st["final_n"], st["final_m"], st["final_attempt"]) == \
+        (fin["n"], fin["m"], fin["attempt"])
+    if layer_keys:
+        assert np.array_equal(np.sort(h.layer_keys(ref.layers_built)),
+                              np.sort(ref.layer_keys(ref.layers_built))), "final key set"
+    assert h.export() == ref.export()
+    n = len(keys)
+    q = np.concatenate([keys[: min(n, n_queries)], W.non_members(max(n, 1), n_queries, 99)])
+    got = h.query(to_dev(q)).cpu().numpy()
+    assert np.array_equal(got, ref.query(q))
+    if filt:
+        cont = h.contains(to_dev(q)).cpu().numpy()
+        assert cont[: min(n, n_queries)].all()

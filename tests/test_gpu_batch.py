@@ -1,0 +1,125 @@
+"""GPU parity of batched builds: every member of a batch equals the oracle's
+structure built from that member's keys alone (Sec. 2 and 3 per structure),
+bit for bit - sizes, key sets per layer, export bytes and queries."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_12365_amd import workload as W
+from tests.gpu_compare import check_handle, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _burr():
+    import paper_2411_12365_amd as burr
+    return burr
+
+
+def _value_dtype(r):
+    return np.uint8 if r <= 8 else (np.uint16 if r <= 16 else np.uint32)
+
+
+def _make(sizes, rs, seed):
+    """Member i: sizes[i] distinct keys (disjoint streams), values spanning the
+    full width of the batch's value dtype (the library keeps r_i bits)."""
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    keys = W.keys(int(offs[-1]), seed)
+    vt = _value_dtype(max(rs))
+    vals = W.values(int(offs[-1]), 8 * np.dtype(vt).itemsize, seed + 1).astype(vt)
+    return keys, vals, offs
+
+
+def _member_ref(keys, vals, offs, rs, i, kw, filt=False):
+    lo, hi = int(offs[i]), int(offs[i + 1])
+    r = rs[i]
+    mk = keys[lo:hi]
+    mv = (vals[lo:hi].astype(np.uint64) & ((1 << r) - 1)).astype(_value_dtype(r))
+    return mk, oracle.build(mk, None if filt else mv, r, oracle.Params(**kw))
+
+
+def _check_batch(sizes, rs, kw, seed, members=None, filt=False, layer_keys=True):
+    burr = _burr()
+    print(f"[batch] {len(sizes)} structures, {sum(sizes)} keys, {kw}", flush=True)
+    keys, vals, offs = _make(sizes, rs, seed)
+    flags = burr.BURR_FLAG_KEEP_LAYER_KEYS if layer_keys else 0
+    b = burr.build_batch(to_dev(keys), None if filt else to_dev(vals), offs, rs,
+                         burr.Params(flags=flags, **kw))
+    assert len(b) == len(sizes)
+    for i in (range(len(sizes)) if members is None else members):
+        mk, ref = _member_ref(keys, vals, offs, rs, i, kw, filt)
+        h = b.member(i)
+        check_handle(h, ref, mk, filt=filt, n_queries=2000, layer_keys=layer_keys)
+    return b, keys, vals, offs
+
+
+def test_mixed_sizes_and_widths():
+    sizes = [0, 1, 2, 63, 64, 65, 500, 2000, 5000, 0, 17, 30000, 129, 1000]
+    rs = [1, 2, 3, 8, 13, 1, 2, 3, 8, 5, 16, 3, 1, 2]
+    _check_batch(sizes, rs, dict(ranges=8, minbpt=2, seed=3), 41)
+
+
+def test_single_member_batch_equals_single_build():
+    burr = _burr()
+    keys = W.keys(20000, 5)
+    vals = W.values(20000, 8, 6)
+    kw = dict(ranges=16, minbpt=4)
+    b = burr.build_batch(to_dev(keys), to_dev(vals), [0, 20000], [8], burr.Params(**kw))
+    h = burr.build(to_dev(keys), to_dev(vals), 8, burr.Params(**kw))
+    assert b.member(0).export() == h.export()
+
+
+def test_lognormal_batch_sampled_members():
+    # many small structures with the lognormal size mix of the batched workload
+    sizes = W.batch_sizes(600, 77, median=2000)
+    rs = [1 + (i % 3) for i in range(len(sizes))]
+    rng = np.random.default_rng(5)
+    members = sorted(set(rng.choice(len(sizes), 40, replace=False).tolist()) | {0, len(sizes) - 1})
+    b, keys, vals, offs = _check_batch(list(sizes), rs, dict(ranges=1 << 16), 51, members,
+                                       layer_keys=False)
+    # every member retrieves every stored value
+    out = []
+    for i in range(len(sizes)):
+        lo, hi = int(offs[i]), int(offs[i + 1])
+        got = b.member(i).query(to_dev(keys[lo:hi])).cpu().numpy()
+        out.append(np.array_equal(got, (vals[lo:hi] & ((1 << rs[i]) - 1)).astype(got.dtype)))
+    assert all(out)
+
+
+def test_final_layer_retries_per_member():
+    # a tight final plain layer: larger members fail their first attempt and
+    # retry alone with larger tables; small ones succeed at once
+    sizes = [30000, 50, 8000, 1, 20000, 700]
+    rs = [8, 3, 8, 2, 13, 1]
+    _check_batch(sizes, rs, dict(layers=0, final_num=100, final_den=100, seed=4), 61)
+
+
+def test_filter_mode_batch():
+    sizes = [3000, 0, 12000, 77, 500]
+    rs = [8, 4, 3, 16, 1]
+    _check_batch(sizes, rs, dict(ranges=32, minbpt=3, filter_mode=1, seed=9), 71, filt=True)
+
+
+def test_conflicting_duplicate_in_one_member_fails_the_batch():
+    burr = _burr()
+    keys, vals, offs = _make([4000, 4000], [8, 8], 81)
+    keys = keys.copy()
+    vals = vals.copy()
+    keys[4001] = keys[4000 + 2000]
+    vals[4001] = vals[4000 + 2000] ^ 1
+    with pytest.raises(burr.BurrError) as e:
+        burr.build_batch(to_dev(keys), to_dev(vals), offs, [8, 8], burr.Params(ranges=8))
+    assert e.value.code == burr.BURR_E_UNSOLVABLE
+
+
+def test_member_handles_do_not_free_the_batch():
+    burr = _burr()
+    keys, vals, offs = _make([1000, 2000], [8, 8], 91)
+    b = burr.build_batch(to_dev(keys), to_dev(vals), offs, [8, 8], burr.Params())
+    h = b.member(1)
+    h.free()  # no-op for a member
+    got = b.member(1).query(to_dev(keys[1000:])).cpu().numpy()
+    assert np.array_equal(got, vals[1000:])
+    b.free()

@@ -9,16 +9,14 @@ import pytest
 
 import oracle
 from paper_2411_12365_amd import workload as W
+from tests.gpu_compare import check_handle, to_dev
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
 
-def _dev(a):
-    if a.dtype == np.uint64:
-        a = a.view(np.int64)
-    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+_dev = to_dev
 
 
 def _burr():
@@ -33,26 +31,7 @@ def _compare(keys, vals, r, kw, label=""):
     ref = oracle.build(keys, None if filt else vals, r, oracle.Params(**kw))
     h = burr.build(_dev(keys), None if filt else _dev(vals), r,
                    burr.Params(flags=burr.BURR_FLAG_KEEP_LAYER_KEYS, **kw))
-    st = h.stats()
-    assert st["layers_built"] == ref.layers_built
-    for li in range(ref.layers_built):
-        info = ref.layer_info(li)
-        gl = st["layers"][li]
-        assert (gl["n"], gl["m"], gl["nranges"], gl["bumped"]) == \
-            (info["n"], info["m"], info["nranges"], info["bumped"]), f"layer {li} sizes"
-        assert np.array_equal(np.sort(h.layer_keys(li)), np.sort(ref.layer_keys(li))), \
-            f"layer {li} key set"
-    fin = ref.final_info()
-    assert (st["final_n"], st["final_m"], st["final_attempt"]) == \
-        (fin["n"], fin["m"], fin["attempt"])
-    assert h.export() == ref.export()
-    n = len(keys)
-    q = np.concatenate([keys[: min(n, 20000)], W.non_members(n, 20000, 99)])
-    got = h.query(_dev(q)).cpu().numpy()
-    assert np.array_equal(got, ref.query(q))
-    if filt:
-        cont = h.contains(_dev(q)).cpu().numpy()
-        assert cont[: min(n, 20000)].all()
+    check_handle(h, ref, keys, filt=bool(filt))
     return h, ref
 
 

@@ -44,6 +44,33 @@ def test_invalid_arguments_fail_without_touching_the_device():
     assert lib.burr_last_error() == burr.BURR_E_INVALID
 
 
+def test_invalid_batch_arguments_fail_without_touching_the_device():
+    import numpy as np
+    import paper_2411_12365_amd as burr
+    lib = burr.lib()
+    p = burr.Params().c(None)
+    off = np.array([0, 5, 3], dtype=np.uint64)      # decreasing
+    rs = np.array([8, 8], dtype=np.uint32)
+    fake = ctypes.c_void_p(0x1000)                  # never dereferenced
+    assert lib.burr_build_batch(fake, fake, off.ctypes.data, rs.ctypes.data, 2,
+                                ctypes.byref(p)) is None
+    assert lib.burr_last_error() == burr.BURR_E_INVALID
+    off = np.array([0, 3, 5], dtype=np.uint64)
+    rs0 = np.array([8, 0], dtype=np.uint32)         # r = 0
+    assert lib.burr_build_batch(fake, fake, off.ctypes.data, rs0.ctypes.data, 2,
+                                ctypes.byref(p)) is None
+    assert lib.burr_build_batch(fake, fake, off.ctypes.data, rs.ctypes.data, 0,
+                                ctypes.byref(p)) is None
+    off1 = np.array([1, 3, 5], dtype=np.uint64)     # does not start at 0
+    assert lib.burr_build_batch(fake, fake, off1.ctypes.data, rs.ctypes.data, 2,
+                                ctypes.byref(p)) is None
+    assert lib.burr_build_batch(None, fake, off.ctypes.data, rs.ctypes.data, 2,
+                                ctypes.byref(p)) is None
+    assert lib.burr_last_error() == burr.BURR_E_INVALID
+    assert lib.burr_batch_size(None) == 0
+    assert lib.burr_batch_member(None, 0) is None
+
+
 def test_python_binding_fails_loudly_without_library(monkeypatch):
     import paper_2411_12365_amd as burr
     monkeypatch.setattr(burr, "_lib", None)
