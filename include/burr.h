@@ -43,7 +43,8 @@ enum {
   BURR_E_UNSOLVABLE = -3, /* final layer failed every scale-up attempt
                              (in practice: one key given two values) */
   BURR_E_DEVICE = -4,     /* a HIP call failed */
-  BURR_E_BUDGET = -5      /* request larger than a server's memory budget */
+  BURR_E_BUDGET = -5,     /* request larger than a server's memory budget */
+  BURR_E_EVICTED = -6     /* a server evicted or dropped the target structure */
 };
 
 /* Keep the device copy of every layer's input keys (debugging, parity tests);
@@ -180,6 +181,112 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* p)
  * order; returns their number (or a negative code). */
 int64_t burr_debug_layer_keys(const burr_handle* h, uint32_t layer, uint64_t* host_out,
                               uint64_t cap);
+
+/* Device bytes a build of n keys with r-bit values is expected to hold:
+ * *table_bytes for the finished structure (layer 0 exact, deeper layers and
+ * the final one at a bound on the bump rate) and *workspace_bytes for the
+ * build's temporary buffers. Host computation only. */
+int burr_estimate_build_bytes(uint64_t n, uint32_t r, const burr_params* p,
+                              uint64_t* table_bytes, uint64_t* workspace_bytes);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop that keeps built structures resident on the device
+ * and runs build and query requests concurrently under a device-memory
+ * budget (continuous batching). Worker threads inside the library each own
+ * one HIP stream; a request runs as soon as its memory fits and a worker is
+ * free, while earlier requests are still running. Build requests that are
+ * waiting together are packed into one batched build (burr_build_batch), so
+ * small builds share launches; every structure is still the one burr_build
+ * makes from its own keys, and every query result the one burr_query gives.
+ * ------------------------------------------------------------------------- */
+typedef struct burr_server burr_server;
+
+#define BURR_SERVER_EVICT_LRU 1u /* evict least recently used idle structures
+                                    when a build does not fit the budget */
+#define BURR_SERVER_NO_DEVICE 2u /* scheduling only: requests complete without
+                                    device work (tests of the admission
+                                    policy); results are not computed */
+
+typedef struct burr_server_config {
+  uint32_t abi_version;    /* BURR_ABI_VERSION */
+  uint32_t workers;        /* worker threads = HIP streams (default 4, >= 1) */
+  uint64_t budget_bytes;   /* resident tables + in-flight build workspace */
+  uint32_t max_batch;      /* most build requests packed together (default 1024) */
+  uint32_t flags;          /* BURR_SERVER_* */
+  uint64_t max_batch_keys; /* most keys in one packed build (default 2^28) */
+} burr_server_config;
+
+enum { BURR_REQ_BUILD = 1, BURR_REQ_QUERY = 2 };
+
+typedef struct burr_completion {
+  uint64_t req_id;
+  uint64_t struct_id;  /* build: id of the new structure (= its req_id); query: target */
+  uint32_t kind;       /* BURR_REQ_* */
+  int32_t status;      /* BURR_OK or a negative code */
+  uint64_t n;          /* keys of the request */
+  uint64_t batch_id;   /* builds packed into one batched build share it */
+  double t_submit_ms;  /* host steady clock, ms since the server was created */
+  double t_start_ms;   /* dispatched to a worker */
+  double t_end_ms;     /* device work finished */
+} burr_completion;
+
+typedef struct burr_server_info {
+  uint64_t resident_bytes;  /* tables of resident structures */
+  uint64_t inflight_bytes;  /* reserved by running builds */
+  uint64_t peak_bytes;      /* largest resident + inflight seen */
+  uint64_t resident;        /* resident structures */
+  uint64_t pending;         /* submitted, not dispatched */
+  uint64_t running;         /* dispatched, not complete */
+  uint64_t completed;       /* completions produced */
+  uint64_t evictions;       /* structures evicted under pressure */
+  uint64_t batches;         /* batched builds run */
+} burr_server_info;
+
+/* Fills *c with defaults (budget 0 = unlimited). */
+void burr_server_default_config(burr_server_config* c);
+
+/* Creates a server; p gives the construction parameters of every structure
+ * (its stream and allocator fields are ignored: workers use their own
+ * streams and HIP's pool). NULL on error. */
+burr_server* burr_server_create(const burr_server_config* c, const burr_params* p);
+
+/* Enqueues a build of n keys (device) with r-bit values (device, width of r;
+ * NULL in filter mode). The arrays must hold their data when the call is
+ * made and stay valid until the request's completion. *req_id receives the
+ * request id, which is also the structure's id. Returns BURR_E_BUDGET if the
+ * build alone exceeds the budget. Builds are admitted in arrival order. */
+int burr_server_submit_build(burr_server* s, const uint64_t* keys, const void* values,
+                             uint64_t n, uint32_t r, uint64_t* req_id);
+
+/* Enqueues a query of n keys (device) against structure struct_id into out
+ * (device, value width of its r). A query of a structure still being built
+ * waits for it; one of an unknown, dropped or evicted structure completes
+ * with BURR_E_EVICTED. Same lifetime rules as builds. */
+int burr_server_submit_query(burr_server* s, uint64_t struct_id, const uint64_t* keys,
+                             uint64_t n, void* out, uint64_t* req_id);
+
+/* Moves up to max finished requests into out (host); *got receives their
+ * number. With timeout_ms > 0 waits that long for at least one, unless
+ * nothing is outstanding. */
+int burr_server_poll(burr_server* s, burr_completion* out, uint32_t max, uint32_t* got,
+                     int64_t timeout_ms);
+
+/* Waits until every submitted request has finished (completions stay
+ * available to burr_server_poll). */
+int burr_server_drain(burr_server* s);
+
+/* Releases a resident structure (its memory is returned once no query of it
+ * runs). Queries submitted later complete with BURR_E_EVICTED. */
+int burr_server_drop(burr_server* s, uint64_t struct_id);
+
+/* Handle of a resident structure (NULL otherwise); valid until it is
+ * dropped or evicted. Not for use while a drop may race with it. */
+const burr_handle* burr_server_handle(burr_server* s, uint64_t struct_id);
+
+int burr_server_get_info(burr_server* s, burr_server_info* info);
+
+/* Waits for running and pending requests, then frees every structure. */
+void burr_server_destroy(burr_server* s);
 
 int burr_last_error(void);
 const char* burr_error_string(int code);

@@ -19,13 +19,22 @@ BURR_E_NOMEM = -2
 BURR_E_UNSOLVABLE = -3
 BURR_E_DEVICE = -4
 BURR_E_BUDGET = -5
+BURR_E_EVICTED = -6
+BURR_SERVER_EVICT_LRU = 1
+BURR_SERVER_NO_DEVICE = 2
+BURR_REQ_BUILD = 1
+BURR_REQ_QUERY = 2
 BURR_FLAG_KEEP_LAYER_KEYS = 1
 ABI_VERSION = 1
 
 _EXPORTS = ("burr_default_params", "burr_build", "burr_query", "burr_contains", "burr_free",
             "burr_get_stats", "burr_export", "burr_import", "burr_debug_layer_keys",
             "burr_last_error", "burr_error_string", "burr_build_batch", "burr_batch_size",
-            "burr_batch_member", "burr_batch_free")
+            "burr_batch_member", "burr_batch_free", "burr_estimate_build_bytes",
+            "burr_server_default_config", "burr_server_create", "burr_server_submit_build",
+            "burr_server_submit_query", "burr_server_poll", "burr_server_drain",
+            "burr_server_drop", "burr_server_handle", "burr_server_get_info",
+            "burr_server_destroy")
 
 
 class BurrError(RuntimeError):
@@ -62,6 +71,25 @@ class _CStats(ctypes.Structure):
         ("ms_sort", ctypes.c_double), ("ms_solve", ctypes.c_double),
         ("ms_final", ctypes.c_double), ("ms_total", ctypes.c_double),
     ]
+
+
+class _CServerConfig(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("workers", ctypes.c_uint32),
+                ("budget_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("max_batch_keys", ctypes.c_uint64)]
+
+
+class _CCompletion(ctypes.Structure):
+    _fields_ = [("req_id", ctypes.c_uint64), ("struct_id", ctypes.c_uint64),
+                ("kind", ctypes.c_uint32), ("status", ctypes.c_int32), ("n", ctypes.c_uint64),
+                ("batch_id", ctypes.c_uint64), ("t_submit_ms", ctypes.c_double),
+                ("t_start_ms", ctypes.c_double), ("t_end_ms", ctypes.c_double)]
+
+
+class _CServerInfo(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in (
+        "resident_bytes", "inflight_bytes", "peak_bytes", "resident", "pending", "running",
+        "completed", "evictions", "batches")]
 
 
 @dataclass
@@ -125,6 +153,30 @@ def lib():
         L.burr_batch_member.restype = vp
         L.burr_batch_free.argtypes = [vp]
         L.burr_batch_free.restype = None
+        L.burr_estimate_build_bytes.argtypes = [u64, u32, ctypes.POINTER(_CParams),
+                                                ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.burr_estimate_build_bytes.restype = i32
+        L.burr_server_default_config.argtypes = [ctypes.POINTER(_CServerConfig)]
+        L.burr_server_default_config.restype = None
+        L.burr_server_create.argtypes = [ctypes.POINTER(_CServerConfig), ctypes.POINTER(_CParams)]
+        L.burr_server_create.restype = vp
+        L.burr_server_submit_build.argtypes = [vp, vp, vp, u64, u32, ctypes.POINTER(u64)]
+        L.burr_server_submit_build.restype = i32
+        L.burr_server_submit_query.argtypes = [vp, u64, vp, u64, vp, ctypes.POINTER(u64)]
+        L.burr_server_submit_query.restype = i32
+        L.burr_server_poll.argtypes = [vp, ctypes.POINTER(_CCompletion), u32,
+                                       ctypes.POINTER(u32), ctypes.c_int64]
+        L.burr_server_poll.restype = i32
+        L.burr_server_drain.argtypes = [vp]
+        L.burr_server_drain.restype = i32
+        L.burr_server_drop.argtypes = [vp, u64]
+        L.burr_server_drop.restype = i32
+        L.burr_server_handle.argtypes = [vp, u64]
+        L.burr_server_handle.restype = vp
+        L.burr_server_get_info.argtypes = [vp, ctypes.POINTER(_CServerInfo)]
+        L.burr_server_get_info.restype = i32
+        L.burr_server_destroy.argtypes = [vp]
+        L.burr_server_destroy.restype = None
         L.burr_last_error.argtypes = []
         L.burr_last_error.restype = i32
         L.burr_error_string.argtypes = [i32]
@@ -358,6 +410,118 @@ def burr_debug_layer_keys(h: Handle, layer: int):
     if n:
         lib().burr_debug_layer_keys(h._h, layer, out.ctypes.data, n)
     return out
+
+
+def burr_estimate_build_bytes(n: int, r: int, params: Params | None = None):
+    """(table bytes, workspace bytes) the library expects a build to hold."""
+    cp = (params or Params()).c(None)
+    tb, wb = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    rc = lib().burr_estimate_build_bytes(n, r, ctypes.byref(cp), ctypes.byref(tb),
+                                         ctypes.byref(wb))
+    if rc != BURR_OK:
+        raise BurrError(rc, "burr_estimate_build_bytes")
+    return tb.value, wb.value
+
+
+class Server:
+    """Request loop with resident structures (burr_server_* in include/burr.h).
+
+    submit_build/submit_query return request ids at once; poll() returns
+    completions. The tensors of a request are kept referenced here until its
+    completion has been polled, so the library never sees freed memory."""
+
+    def __init__(self, budget_bytes: int = 0, workers: int = 4, max_batch: int = 1024,
+                 max_batch_keys: int = 1 << 28, evict_lru: bool = False,
+                 params: Params | None = None, no_device: bool = False):
+        self.params = params or Params()
+        cfg = _CServerConfig()
+        lib().burr_server_default_config(ctypes.byref(cfg))
+        cfg.workers = workers
+        cfg.budget_bytes = budget_bytes
+        cfg.max_batch = max_batch
+        cfg.max_batch_keys = max_batch_keys
+        cfg.flags = (BURR_SERVER_EVICT_LRU if evict_lru else 0) | \
+            (BURR_SERVER_NO_DEVICE if no_device else 0)
+        cp = self.params.c(None)
+        self._s = lib().burr_server_create(ctypes.byref(cfg), ctypes.byref(cp))
+        if not self._s:
+            raise BurrError(lib().burr_last_error(), "burr_server_create")
+        self._live = {}
+        self._r = {}
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "_s", None):
+            lib().burr_server_destroy(self._s)
+            self._s = None
+            self._live.clear()
+
+    def submit_build(self, keys, values, r: int) -> int:
+        import torch
+        _check_tensor(keys, "keys", (torch.int64, torch.uint64))
+        vptr = None
+        if values is not None and not self.params.filter_mode:
+            _check_tensor(values, "values", (value_dtype(r),))
+            if values.numel() != keys.numel():
+                raise ValueError("keys and values differ in length")
+            vptr = values.data_ptr() if values.numel() else None
+        rid = ctypes.c_uint64(0)
+        rc = lib().burr_server_submit_build(self._s, keys.data_ptr() if keys.numel() else None,
+                                            vptr, keys.numel(), r, ctypes.byref(rid))
+        if rc != BURR_OK:
+            raise BurrError(rc, "burr_server_submit_build")
+        self._live[rid.value] = (keys, values)
+        self._r[rid.value] = r
+        return rid.value
+
+    def submit_query(self, struct_id: int, keys, out=None):
+        """Returns (request id, out tensor); out is valid after completion."""
+        import torch
+        _check_tensor(keys, "keys", (torch.int64, torch.uint64))
+        r = self._r.get(struct_id, 8)
+        if out is None:
+            out = torch.empty(keys.numel(), dtype=value_dtype(r), device=keys.device)
+        rid = ctypes.c_uint64(0)
+        rc = lib().burr_server_submit_query(self._s, struct_id,
+                                            keys.data_ptr() if keys.numel() else None,
+                                            keys.numel(), out.data_ptr() if out.numel() else None,
+                                            ctypes.byref(rid))
+        if rc != BURR_OK:
+            raise BurrError(rc, "burr_server_submit_query")
+        self._live[rid.value] = (keys, out)
+        return rid.value, out
+
+    def poll(self, max_items: int = 4096, timeout_ms: int = 0) -> list:
+        buf = (_CCompletion * max_items)()
+        got = ctypes.c_uint32(0)
+        rc = lib().burr_server_poll(self._s, buf, max_items, ctypes.byref(got), timeout_ms)
+        if rc != BURR_OK:
+            raise BurrError(rc, "burr_server_poll")
+        out = []
+        for i in range(got.value):
+            c = {f: getattr(buf[i], f) for f, _ in _CCompletion._fields_}
+            self._live.pop(c["req_id"], None)
+            out.append(c)
+        return out
+
+    def drain(self):
+        lib().burr_server_drain(self._s)
+
+    def drop(self, struct_id: int):
+        rc = lib().burr_server_drop(self._s, struct_id)
+        if rc != BURR_OK:
+            raise BurrError(rc, "burr_server_drop")
+
+    def handle(self, struct_id: int):
+        h = lib().burr_server_handle(self._s, struct_id)
+        return Handle(h, self._r[struct_id], self.params, batch=self) if h else None
+
+    def info(self) -> dict:
+        st = _CServerInfo()
+        lib().burr_server_get_info(self._s, ctypes.byref(st))
+        return {f: getattr(st, f) for f, _ in _CServerInfo._fields_}
 
 
 # short aliases

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/burr.h"
+#include "burr_internal.h"
 #include "burr_kernels.h"
 
 using namespace burr;
@@ -117,6 +118,7 @@ struct burr_batch {
   std::vector<burr_handle> views;
   LayerStore layers[kMaxLayers];
   std::vector<void*> owned;  // final-layer tables and debug key arrays
+  uint64_t table_bytes = 0;  // device bytes of codes and solution words
   double ms_total = 0, ms_final = 0;
 };
 
@@ -425,6 +427,7 @@ int final_attempt(burr_batch* b, Workspace& ws, const std::vector<uint32_t>& lis
   uint64_t* W = (uint64_t*)b->al.get(t.word_base.back() * 8 + 8);
   if (!W) return set_error(BURR_E_NOMEM);
   b->owned.push_back(W);
+  b->table_bytes += t.word_base.back() * 8 + 8;
   HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, ws.occ, g, W, s, ws.bnd));
   fails.assign(g.J, 0);
   HIP_TRY(hipMemcpyAsync(fails.data(), ws.fail, g.J * 4, hipMemcpyDeviceToHost, s));
@@ -521,6 +524,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     LS.codes = (uint64_t*)b->al.get(t.code_base.back() * 8);
     LS.W = (uint64_t*)b->al.get(t.word_base.back() * 8);
     if (!LS.codes || !LS.W) return set_error(BURR_E_NOMEM);
+    b->table_bytes += (t.code_base.back() + t.word_base.back()) * 8;
     HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, ws.occ, g, LS.W, s));
     HIP_TRY(pack_codes(ws.code8, g, t.code_base.back(), LS.codes, s));
     HIP_TRY(hipEventRecord(ev.e[4], s));
@@ -727,9 +731,64 @@ const Member* member_of(const burr_handle* h) {
   return &h->b->members[h->idx];
 }
 
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// Bound on the fraction of a layer's keys passed to the next layer, for
+// memory estimates only (about 6-7 % at 0.97 slots per key and 2-bit
+// thresholds; small structures see more).
+constexpr double kBumpBound = 0.12;
+
+uint64_t estimate_table(uint64_t n, uint32_t r, const burr_params& p, uint64_t* n_final) {
+  uint64_t bytes = 0, cur = n;
+  for (uint32_t l = 0; l < p.layers && cur > 0; ++l) {
+    uint64_t m, R;
+    plan_layer(p, cur, &m, &R);
+    const uint64_t B = m / 64;
+    bytes += align256((B + 31) / 32 * 8) + align256(B * r * 8);
+    cur = (uint64_t)((double)cur * kBumpBound) + (cur > 0 ? 1 : 0);
+  }
+  if (n_final) *n_final = cur;
+  if (cur > 0) bytes += align256(plan_final(p, cur, 0) / 64 * r * 8 + 8);
+  return bytes;
+}
+
 }  // namespace
 
+uint64_t burr_batch_device_bytes(const burr_batch* b) { return b ? b->table_bytes : 0; }
+
+int burr_set_error(int code) { return set_error(code); }
+
+uint64_t burr_workspace_bytes(uint64_t n, uint32_t rmax, uint32_t count, const burr_params* p,
+                              int staged) {
+  if (!p) return 0;
+  uint64_t m0 = 64, R0;
+  if (p->layers > 0) plan_layer(*p, n, &m0, &R0);
+  uint64_t nf = 0;
+  estimate_table(n, rmax, *p, &nf);
+  const uint64_t mf = nf ? plan_final(*p, nf, 0) : 64;
+  // every structure has at least one bucket per layer
+  const uint64_t m = std::max(m0, mf) + 64ull * count;
+  const uint64_t B = m / 64;
+  uint64_t bytes = 0;
+  bytes += 40 * std::max<uint64_t>(n, 1);              // key and value buffers
+  bytes += 16 * (n + B + 1);                           // item stream
+  bytes += 12 * m + 8 * (B + 1);                       // rows and occupancy
+  bytes += 9 * (B + 1) + 4 * ((B + 2047) / 2048) * 2048 + 4 * (B + 64);  // codes, counts, scans
+  bytes += 8 * (7ull * (count + 1) + 8);               // per-structure tables
+  bytes += 36ull * 64 * (mf / 64 / 4 + count);         // final-layer segments
+  if (staged) bytes += (8 + (rmax <= 8 ? 1 : rmax <= 16 ? 2 : 4)) * n;
+  return bytes + (1u << 20);
+}
+
 extern "C" {
+
+int burr_estimate_build_bytes(uint64_t n, uint32_t r, const burr_params* p,
+                              uint64_t* table_bytes, uint64_t* workspace_bytes) {
+  if (!params_ok(p) || r < 1 || r > 32) return set_error(BURR_E_INVALID);
+  if (table_bytes) *table_bytes = estimate_table(n, r, *p, nullptr);
+  if (workspace_bytes) *workspace_bytes = burr_workspace_bytes(n, r, 1, p, 0);
+  return BURR_OK;
+}
 
 void burr_default_params(burr_params* p) {
   if (!p) return;
@@ -1010,6 +1069,7 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
     L.ncode = (L.m / 64 + 31) / 32;
     L.nW = (L.m / 64) * mb.r;
     ok = load_words(L.ncode, &b->layers[l].codes) && load_words(L.nW, &b->layers[l].W);
+    b->table_bytes += (L.ncode + L.nW) * 8 + 16;
   }
   if (ok) {
     mb.fin.n = in.get(8);
@@ -1021,6 +1081,7 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
       uint64_t* w = nullptr;
       ok = load_words(mb.fin.nW, &w);
       if (w) b->owned.push_back(w);
+      b->table_bytes += mb.fin.nW * 8 + 8;
       mb.fin_W = w;
     }
   }
@@ -1065,6 +1126,7 @@ const char* burr_error_string(int code) {
     case BURR_E_UNSOLVABLE: return "final layer unsolvable (conflicting duplicate keys?)";
     case BURR_E_DEVICE: return "HIP device error";
     case BURR_E_BUDGET: return "request exceeds the memory budget";
+    case BURR_E_EVICTED: return "structure evicted or dropped";
     default: return "unknown error";
   }
 }

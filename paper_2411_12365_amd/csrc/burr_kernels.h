@@ -101,6 +101,13 @@ struct FinalArgs {
 hipError_t final_merge(const FinalArgs& a, uint64_t max_segments, hipStream_t s);
 hipError_t final_boundaries(const FinalArgs& a, hipStream_t s);
 
+// Copies the inputs of J structures, each in its own device arrays, into
+// one key array and one value array of out_vb-byte elements (structure j at
+// off[j]). tab (device): J key pointers, J value pointers (0 in filter mode),
+// J+1 offsets, J input value widths - one u64 each.
+hipError_t concat_inputs(const uint64_t* tab, uint32_t J, uint64_t n, uint64_t* out_keys,
+                         void* out_vals, uint32_t out_vb, hipStream_t s);
+
 hipError_t query(const QueryPlan& plan, const uint64_t* keys, uint64_t n, void* out,
                  uint32_t out_bytes, uint32_t contains, uint64_t fp_salt, hipStream_t s);
 

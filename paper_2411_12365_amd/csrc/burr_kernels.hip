@@ -998,6 +998,45 @@ hipError_t gather_bumped(const uint64_t* sorted_keys, const Rec* rec, const uint
 }
 
 // ---------------------------------------------------------------------------
+// Input concatenation (requests built together)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_concat(const uint64_t* __restrict__ tab, uint32_t J,
+                                                uint64_t n, uint64_t* __restrict__ out_keys,
+                                                void* __restrict__ out_vals, uint32_t out_vb) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t* off = tab + 2 * (uint64_t)J;
+  const uint32_t j = find_struct(off, J, i);
+  const uint64_t k = i - off[j];
+  out_keys[i] = reinterpret_cast<const uint64_t*>(tab[j])[k];
+  if (!out_vals) return;
+  const void* src = reinterpret_cast<const void*>(tab[J + j]);
+  const uint32_t vb = (uint32_t)tab[3 * (uint64_t)J + 1 + j];
+  uint32_t v = 0;
+  if (src) {
+    if (vb == 1)
+      v = reinterpret_cast<const uint8_t*>(src)[k];
+    else if (vb == 2)
+      v = reinterpret_cast<const uint16_t*>(src)[k];
+    else
+      v = reinterpret_cast<const uint32_t*>(src)[k];
+  }
+  if (out_vb == 1)
+    reinterpret_cast<uint8_t*>(out_vals)[i] = (uint8_t)v;
+  else if (out_vb == 2)
+    reinterpret_cast<uint16_t*>(out_vals)[i] = (uint16_t)v;
+  else
+    reinterpret_cast<uint32_t*>(out_vals)[i] = v;
+}
+
+hipError_t concat_inputs(const uint64_t* tab, uint32_t J, uint64_t n, uint64_t* out_keys,
+                         void* out_vals, uint32_t out_vb, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_concat<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(tab, J, n, out_keys, out_vals, out_vb);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Query: one lane per key
 // ---------------------------------------------------------------------------
 template <typename OT>
