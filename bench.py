@@ -10,7 +10,10 @@ resident in HBM before the timed region. Prints one JSON line.
 
 Also reported (not the headline value): query throughput of 100M mixed
 member/non-member keys, per-kernel device times (hipEvents recorded by the
-library on the build stream), and the CPU oracle timed on a bounded sample.
+library on the build stream), the CPU oracle timed on a bounded sample,
+batched builds/s of 200k small structures (one batched build against one
+build per structure), and p50/p99 latencies of the serving loop under
+Poisson arrivals.
 """
 import argparse
 import json
@@ -85,6 +88,217 @@ def cpu_baseline(n_sample):
     }
 
 
+def _device_stream(gen, n, dtype, dev, chunk=100_000_000):
+    """Fill a device tensor from a host generator gen(start, count), chunk by chunk."""
+    import numpy as np
+    import torch
+    out = torch.empty(n, dtype=dtype, device=dev)
+    for lo in range(0, n, chunk):
+        c = min(chunk, n - lo)
+        a = np.ascontiguousarray(gen(lo, c))
+        out[lo:lo + c].copy_(torch.from_numpy(a.view(np.int64) if a.dtype == np.uint64 else a))
+    return out
+
+
+def run_batched(args, dev):
+    """Many small structures: one batched build against one build per structure."""
+    import numpy as np
+    import torch
+    import paper_2411_12365_amd as burr
+    from paper_2411_12365_amd import workload as W
+    count = args.batch_structures
+    sizes = W.batch_sizes(count, 4)
+    rs = np.random.default_rng(4).integers(1, 4, size=count).astype(np.uint32)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    N = int(offs[-1])
+    keys = _device_stream(lambda lo, c: W.keys(c, 4, lo), N, torch.int64, dev)
+    vals = _device_stream(lambda lo, c: (W.splitmix64(1004, lo, c) & np.uint64(0xFF))
+                          .astype(np.uint8), N, torch.uint8, dev)
+    torch.cuda.synchronize()
+    params = burr.Params(ranges=1 << 16)
+    print(f"# batched: {count} structures, {N} keys", file=sys.stderr, flush=True)
+    b = burr.build_batch(keys, vals, offs, rs, params)
+    b.free()
+    times = []
+    for _ in range(args.batch_steps):
+        t0 = time.perf_counter()
+        b = burr.build_batch(keys, vals, offs, rs, params)
+        times.append(time.perf_counter() - t0)
+        if len(times) < args.batch_steps:
+            b.free()
+    # spot check: members of sampled structures retrieve their values
+    ok = True
+    for i in np.linspace(0, count - 1, 64).astype(int):
+        lo, hi = int(offs[i]), int(offs[i + 1])
+        got = b.member(int(i)).query(keys[lo:hi])
+        ok &= bool(torch.equal(got, vals[lo:hi] & ((1 << int(rs[i])) - 1)))
+    st = b.member(0).stats()
+    b.free()
+    # per-structure baseline on the first S structures, and the batch on the same S
+    S = min(args.batch_single_sample, count)
+    t0 = time.perf_counter()
+    for i in range(S):
+        lo, hi = int(offs[i]), int(offs[i + 1])
+        h = burr.build(keys[lo:hi], vals[lo:hi], int(rs[i]), params)
+        h.free()
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    bs = burr.build_batch(keys[:int(offs[S])], vals[:int(offs[S])], offs[:S + 1], rs[:S], params)
+    bs.free()
+    t0 = time.perf_counter()
+    bs = burr.build_batch(keys[:int(offs[S])], vals[:int(offs[S])], offs[:S + 1], rs[:S], params)
+    t_sample = time.perf_counter() - t0
+    bs.free()
+    ms = np.array(times) * 1e3
+    return {
+        "workload": f"{count} structures, log-normal sizes (median 2000, clipped 100..200000), "
+                    f"{N} keys, r uniform in {{1,2,3}}, one batched build, {args.batch_steps} "
+                    f"timed builds",
+        "structures": count, "keys": N,
+        "builds_per_s": round(count / float(np.mean(times)), 1),
+        "Mkeys_per_s": round(N / float(np.mean(times)) / 1e6, 1),
+        "build_ms_p50": round(float(np.percentile(ms, 50)), 2),
+        "build_ms_max": round(float(ms.max()), 2),
+        "members_ok": ok,
+        "layer0_device_ms": {k: round(st["layers"][0][k], 3) for k in
+                             ("ms_sort", "ms_solve", "ms_backsub", "ms_gather")},
+        "device_total_ms": round(st["ms_total"], 2),
+        "per_structure_baseline": {
+            "structures": S, "keys": int(offs[S]),
+            "one_build_per_structure_builds_per_s": round(S / t_single, 1),
+            "batched_same_structures_builds_per_s": round(S / t_sample, 1),
+            "speedup": round(t_single / t_sample, 1),
+        },
+    }
+
+
+def _pct(a, q):
+    import numpy as np
+    return round(float(np.percentile(a, q)), 3) if len(a) else None
+
+
+def run_serving(args, dev):
+    """Poisson arrivals of builds and query batches against resident structures."""
+    import numpy as np
+    import torch
+    import paper_2411_12365_amd as burr
+    from paper_2411_12365_amd import workload as W
+    pool_n = 150_000_000
+    pool_k = _device_stream(lambda lo, c: W.keys(c, 5, lo), pool_n, torch.int64, dev)
+    pool_v = _device_stream(lambda lo, c: (W.splitmix64(1005, lo, c) & np.uint64(0xFF))
+                            .astype(np.uint8), pool_n, torch.uint8, dev)
+    torch.cuda.synchronize()
+    params = burr.Params(ranges=1 << 16)
+    budget = 200 << 30
+    QPB = 8  # query batches per structure before the client drops it
+
+    def one_run(nb, rate, seed, burst=False):
+        srv = burr.Server(workers=4, budget_bytes=budget, params=params)
+        bsz = W.serving_sizes(nb, seed, "build")
+        qsz = W.serving_sizes(nb * QPB, seed + 1, "query")
+        if burst:  # everything at once: each build followed by its query batches
+            events = []
+            for i in range(nb):
+                events.append((0.0, 0, i))
+                events += [(0.0, 1, i * QPB + k) for k in range(QPB)]
+        else:
+            tb = W.poisson_arrivals(nb, rate / (1 + QPB), seed + 2)
+            tq = W.poisson_arrivals(nb * QPB, rate * QPB / (1 + QPB), seed + 3)
+            events = sorted([(t, 0, i) for i, t in enumerate(tb)] +
+                            [(t, 1, i) for i, t in enumerate(tq)])
+        off = 0
+        where = {}      # struct id -> (pool offset, n)
+        resident = []   # built and not yet dropped
+        asked, answered = {}, {}
+        pending_q = []  # queries submitted before any structure was resident
+        checks = []
+        lat = {1: [], 2: []}
+        keys_done = {1: 0, 2: 0}
+        failed = 0
+
+        def handle(cs):
+            nonlocal failed
+            for c in cs:
+                if c["status"] != 0:
+                    failed += 1
+                    continue
+                lat[c["kind"]].append(c["t_end_ms"] - c["t_submit_ms"])
+                keys_done[c["kind"]] += c["n"]
+                if c["kind"] == 1:
+                    resident.append(c["struct_id"])
+                else:
+                    sid = c["struct_id"]
+                    answered[sid] = answered.get(sid, 0) + 1
+                    if answered[sid] == QPB and sid in resident:
+                        resident.remove(sid)
+                        srv.drop(sid)
+
+        rng = np.random.default_rng(seed + 4)
+        last_build = None
+        t0 = time.perf_counter()
+        for t, kind, i in events:
+            while True:
+                handle(srv.poll(timeout_ms=0))
+                if time.perf_counter() - t0 >= t:
+                    break
+                time.sleep(min(0.0005, max(0.0, t - (time.perf_counter() - t0))))
+            if kind == 0:
+                n = int(bsz[i])
+                if off + n > pool_n:
+                    off = 0
+                sid = srv.submit_build(pool_k[off:off + n], pool_v[off:off + n], 8)
+                where[sid] = (off, n)
+                off += n
+                last_build = sid
+            else:
+                cands = [s for s in resident if asked.get(s, 0) < QPB]
+                sid = cands[int(rng.integers(len(cands)))] if cands else last_build
+                if sid is None or asked.get(sid, 0) >= QPB:
+                    continue
+                so, sn = where[sid]
+                q = int(qsz[i])
+                lo = max(0, so + sn - q // 2)
+                hi = min(pool_n, lo + q)
+                rid, out = srv.submit_query(sid, pool_k[lo:hi])
+                asked[sid] = asked.get(sid, 0) + 1
+                if len(checks) < 40:
+                    checks.append((out, lo, max(lo, so), so + sn))
+        srv.drain()
+        handle(srv.poll())
+        wall = time.perf_counter() - t0
+        ok = all(torch.equal(o[m - lo:e - lo], pool_v[m:e]) for o, lo, m, e in checks if e > m)
+        info = srv.info()
+        srv.close()
+        return dict(wall_s=wall, requests=len(lat[1]) + len(lat[2]) + failed, lat=lat, keys=keys_done, ok=ok,
+                    failed=failed, peak_gb=info["peak_bytes"] / 2**30, batches=info["batches"])
+
+    nb = args.serve_builds
+    print(f"# serving: saturation burst", file=sys.stderr, flush=True)
+    sat = one_run(max(20, nb // 4), 0, 50, burst=True)
+    rate_sat = sat["requests"] / sat["wall_s"]
+    levels = []
+    for load in [float(x) for x in args.serve_loads.split(",") if x]:
+        print(f"# serving: load {load}", file=sys.stderr, flush=True)
+        r = one_run(nb, load * rate_sat, 60 + int(load * 100))
+        levels.append({
+            "load": load, "offered_req_per_s": round(load * rate_sat, 1),
+            "requests": r["requests"], "wall_s": round(r["wall_s"], 3),
+            "build_ms_p50": _pct(r["lat"][1], 50), "build_ms_p99": _pct(r["lat"][1], 99),
+            "query_ms_p50": _pct(r["lat"][2], 50), "query_ms_p99": _pct(r["lat"][2], 99),
+            "build_Mkeys_per_s": round(r["keys"][1] / r["wall_s"] / 1e6, 1),
+            "query_Mkeys_per_s": round(r["keys"][2] / r["wall_s"] / 1e6, 1),
+            "batched_builds": r["batches"], "failed": r["failed"],
+            "peak_budget_GiB": round(r["peak_gb"], 2), "results_ok": r["ok"],
+        })
+    return {
+        "workload": "Poisson arrivals: builds log-normal 1e3..1e7 keys (median 1e5, r=8), "
+                    "query batches log-normal 1e4..1e6 keys (median 1e5, half members), 8 query "
+                    "batches per structure then dropped; 4 workers; 200 GiB budget",
+        "saturated_req_per_s": round(rate_sat, 1),
+        "levels": levels,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +308,15 @@ def main():
     ap.add_argument("--queries", type=int, default=N_KEYS)
     ap.add_argument("--cpu-sample", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-structures", type=int, default=200_000)
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--batch-single-sample", type=int, default=2000,
+                    help="structures built one by one for the per-structure baseline")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--serve-builds", type=int, default=200,
+                    help="build requests per load level (8 query batches per build)")
+    ap.add_argument("--serve-loads", type=str, default="0.5,0.8,0.95")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB once (a plain copy kernel of "
                          "known size, for scaling hardware byte counters)")
@@ -246,6 +469,19 @@ def main():
         res["calibration_copy_bytes"] = 2 * src.numel() * 4
         del src, dst
     torch.cuda.empty_cache()
+    # secondary sections: a failure is reported in the JSON line, not raised
+    if not args.no_batch:
+        try:
+            res["batched"] = run_batched(args, dev)
+        except burr.BurrError as e:
+            res["batched"] = {"error": str(e)}
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        try:
+            res["serving"] = run_serving(args, dev)
+        except burr.BurrError as e:
+            res["serving"] = {"error": str(e)}
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(min(args.cpu_sample, n))

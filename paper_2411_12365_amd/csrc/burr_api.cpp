@@ -207,6 +207,7 @@ struct Workspace {
   uint32_t* soff = nullptr;  // per structure: first bumped key
   uint64_t* steps = nullptr;
   uint64_t* tab = nullptr;   // layer table
+  uint64_t* diag = nullptr;  // insertion-kernel diagnostics (16 u64)
   uint64_t *spillC = nullptr, *spill_occ = nullptr, *xfirst = nullptr;
   uint32_t *spillV = nullptr, *z0first = nullptr, *bnd = nullptr;
 
@@ -271,6 +272,20 @@ struct Workspace {
            alloc(xfirst, P * 64) && alloc(z0first, P * 64) && alloc(bnd, P * 64);
   }
 };
+
+void print_diag(const uint64_t* d) {
+  uint64_t h[16] = {0};
+  if (hipMemcpy(h, d, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess || !h[0]) return;
+  fprintf(stderr,
+          "burr: lane state: code %llu range %llu structure %llu x %llu xend %llu q %llu/%llu "
+          "state %llu open %llu written %llu rend %llu kf %llu curk %llu i %llu first bucket "
+          "%llu\n",
+          (unsigned long long)h[1], (unsigned long long)h[2], (unsigned long long)h[3],
+          (unsigned long long)h[4], (unsigned long long)h[5], (unsigned long long)h[6],
+          (unsigned long long)h[7], (unsigned long long)h[8], (unsigned long long)h[9],
+          (unsigned long long)h[10], (unsigned long long)h[11], (unsigned long long)h[12],
+          (unsigned long long)h[13], (unsigned long long)h[14], (unsigned long long)h[15]);
+}
 
 // Uploads a table (one device buffer) and fills the geometry's pointers and totals.
 int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s) {
@@ -407,6 +422,7 @@ int final_attempt(burr_batch* b, Workspace& ws, const std::vector<uint32_t>& lis
   sa.spillC = ws.spillC;
   sa.spillV = ws.spillV;
   sa.spill_occ = ws.spill_occ;
+  sa.diag = ws.diag;
   HIP_TRY(solve_layer(sa, s));
   FinalArgs fa{};
   fa.g = g;
@@ -435,6 +451,7 @@ int final_attempt(burr_batch* b, Workspace& ws, const std::vector<uint32_t>& lis
   for (size_t i = 0; i < list.size(); ++i) {
     if (fails[i] >= 2) {
       fprintf(stderr, "burr: internal error %u in the final layer\n", fails[i]);
+      print_diag(ws.diag);
       return set_error(BURR_E_DEVICE);
     }
     if (fails[i]) continue;
@@ -460,7 +477,9 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   Workspace ws(&b->al);
   Events ev;
   if (!ev.ok) return set_error(BURR_E_DEVICE);
-  if (!ws.reserve_keys(off.back()) || !ws.alloc(ws.steps, 8)) return set_error(BURR_E_NOMEM);
+  if (!ws.reserve_keys(off.back()) || !ws.alloc(ws.steps, 8) || !ws.alloc(ws.diag, 16))
+    return set_error(BURR_E_NOMEM);
+  HIP_TRY(hipMemsetAsync(ws.diag, 0, 16 * 8, s));
   HIP_TRY(hipEventRecord(ev.e[0], s));
 
   // members with keys in the current layer, in key order, and their key counts
@@ -514,6 +533,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     sa.bump = ws.bump;
     sa.fail = ws.fail;
     sa.steps = ws.steps;
+    sa.diag = ws.diag;
     sa.nrec = (uint32_t)(g.nkeys + g.nbuckets);
     HIP_TRY(hipMemsetAsync(ws.steps, 0, 64, s));
     HIP_TRY(hipMemsetAsync(ws.fail, 0, (g.J + 1) * 4, s));
@@ -555,6 +575,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     for (uint32_t f : fails)
       if (f) {
         fprintf(stderr, "burr: internal error %u in the insertion kernel, layer %u\n", f, li);
+        print_diag(ws.diag);
         return set_error(BURR_E_DEVICE);
       }
     LS.ms_sort = elapsed_ms(ev.e[1], ev.e[2]);

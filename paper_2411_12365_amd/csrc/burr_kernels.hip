@@ -345,6 +345,29 @@ constexpr int kFifo = 8;  // must match the 8 staged registers below
 constexpr int kRoundIters = BURR_ROUND_ITERS;
 constexpr uint32_t kNoSplit = 0xffffffffu;
 
+// Records the state of the first lane that stops with an internal error.
+__device__ inline void solve_diag(uint64_t* d, uint32_t code, uint64_t rho, uint32_t js,
+                                  uint32_t x, uint32_t xend, uint32_t q, uint32_t nq,
+                                  uint32_t state, bool open, uint32_t written, uint32_t rend,
+                                  uint32_t kf, uint32_t curk, uint32_t i, uint64_t fb) {
+  if (!d || atomicCAS((unsigned long long*)d, 0ull, 1ull) != 0ull) return;
+  d[1] = code;
+  d[2] = rho;
+  d[3] = js;
+  d[4] = x;
+  d[5] = xend;
+  d[6] = q;
+  d[7] = nq;
+  d[8] = state;
+  d[9] = open;
+  d[10] = written;
+  d[11] = rend;
+  d[12] = kf;
+  d[13] = curk;
+  d[14] = i;
+  d[15] = fb;
+}
+
 template <typename VT>
 constexpr size_t solve_lds_bytes() {
   return kRing * 64 * sizeof(uint64_t) + kFifo * 64 * sizeof(Rec) + kRing * 64 * sizeof(VT);
@@ -417,6 +440,8 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     for (int it = 0; it < kRoundIters; ++it) {
       if (state != ST_DONE && iter_left-- == 0) {
         a.fail[js] = 3u;
+        solve_diag(a.diag, 3, rho, js, x, xend, q, nq, state, open, written, rend, kf, curk, i,
+                   fb);
         state = ST_DONE;
       }
 #ifdef BURR_SOLVE_DEBUG
@@ -465,6 +490,8 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
           // unreachable for kept keys of a BuRR layer; stop instead of
           // writing outside the range
           a.fail[js] = 2u;
+          solve_diag(a.diag, 2, rho, js, x, xend, q, nq, state, open, written, rend, kf, curk,
+                     i, fb);
           state = ST_DONE;
         }
       }

@@ -86,3 +86,21 @@ def batch_sizes(count: int, seed: int, median: float = 2000.0, lo: int = 100,
     rng = np.random.default_rng(seed)
     s = rng.lognormal(mean=np.log(median), sigma=np.sqrt(2 * np.log(2)), size=count)
     return np.clip(np.rint(s), lo, hi).astype(np.int64)
+
+
+def serving_sizes(count: int, seed: int, kind: str) -> np.ndarray:
+    """Request sizes of the serving workload: builds log-normal with median
+    1e5 keys clipped to [1e3, 1e7]; query batches log-normal with median 1e5
+    clipped to [1e4, 1e6] (the clip bounds taken as +-3 sigma)."""
+    rng = np.random.default_rng(seed)
+    if kind == "build":
+        s = rng.lognormal(np.log(1e5), np.log(1e4) / 6, size=count)
+        return np.clip(np.rint(s), 1_000, 10_000_000).astype(np.int64)
+    s = rng.lognormal(np.log(1e5), np.log(100) / 6, size=count)
+    return np.clip(np.rint(s), 10_000, 1_000_000).astype(np.int64)
+
+
+def poisson_arrivals(count: int, rate_per_s: float, seed: int) -> np.ndarray:
+    """Arrival times (s) of a Poisson stream."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=count))
