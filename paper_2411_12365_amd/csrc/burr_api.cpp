@@ -563,15 +563,6 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
                           s));
     HIP_TRY(hipEventRecord(ev.e[5], s));
     HIP_TRY(hipStreamSynchronize(s));
-#ifdef BURR_SOLVE_DEBUG
-    {
-      uint64_t d[4];
-      if (hipMemcpy(d, ws.steps, 32, hipMemcpyDeviceToHost) == hipSuccess)
-        fprintf(stderr, "solve-debug layer %u: steps %llu lane-iters %llu elim-iters %llu "
-                "want-iters %llu\n", li, (unsigned long long)d[0], (unsigned long long)d[1],
-                (unsigned long long)d[2], (unsigned long long)d[3]);
-    }
-#endif
     for (uint32_t f : fails)
       if (f) {
         fprintf(stderr, "burr: internal error %u in the insertion kernel, layer %u\n", f, li);

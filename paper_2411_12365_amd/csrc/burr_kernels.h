@@ -40,8 +40,9 @@ struct SortArgs {
 };
 hipError_t sort_layer(const SortArgs& a, hipStream_t s);
 
-// Per-range insertion with 2-bit thresholds and boundary bumping: one lane
-// per range, ring of 128 rows per lane in LDS.
+// Per-range insertion with 2-bit thresholds and boundary bumping: one wave
+// per range, its 64 lanes insert a bucket's records together against a ring
+// of 128 rows in LDS.
 struct SolveArgs {
   const Rec* rec;
   const uint32_t* bstart;

@@ -5,9 +5,10 @@
 //               scatters into coarse bins of 2048 buckets through LDS
 //               histograms, level 2 orders one bin per workgroup in LDS and
 //               writes 16-byte records (row + value/offset/chunk)
-//   solve     : one lane per range; banded GF(2) insertion against a ring of
-//               128 rows in LDS, bucket by bucket, chunks of decreasing
-//               offset, 2-bit thresholds, forced bumps at the range end
+//   solve     : one wave per range; the lanes insert a bucket's records
+//               together (banded GF(2) elimination against a 128-row ring in
+//               LDS, claims by compare-and-swap), bucket by bucket, 2-bit
+//               thresholds from chunk prefixes, forced bumps at range ends
 //   backsub   : one lane per range, column-interleaved output words
 //   gather    : bumped keys (a suffix of every bucket) -> next layer input
 //   query     : one lane per key, layer walk, two-word window, popcount parity
@@ -258,7 +259,8 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_sort(
     bstart[beta] = (uint32_t)(lo + first);
     Rec hd;
     hd.c = (uint64_t)count | ((uint64_t)forced_kf(beta, maxoff[b], count, g) << 32);
-    hd.meta = 0;
+    // records per chunk: rank 0 (inserted first) and rank 1; rank 2 is the rest
+    hd.meta = (uint64_t)(hist[3 * b + 1] - first) | ((uint64_t)(hist[3 * b + 2] - hist[3 * b + 1]) << 32);
     items[lo + first + beta] = hd;
   }
   if (bin + 1 == nbins && threadIdx.x == 0) bstart[g.nbuckets] = (uint32_t)hi;
@@ -312,39 +314,6 @@ hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Solve: one lane per range
-// ---------------------------------------------------------------------------
-// Every lane owns one range and walks its item stream (a header per bucket,
-// then the bucket's records). The hot loop touches LDS only: the 128-row ring
-// (coefficient rows and values) and a FIFO of the lane's next kFifo items.
-// Global loads are issued once per round of kRoundIters iterations into
-// registers and committed to the FIFO at the end of the round, so no wave
-// waits on a global load inside a round.
-//
-// One iteration = K elimination steps for every lane still eliminating, then
-// the outcome of finished equations, then the lanes that need their next item
-// take it (usually the next record of the same bucket; bucket ends and
-// headers are the rare path).
-enum : uint32_t {
-  ST_ELIM = 0,      // eliminating the current equation
-  ST_PLACE = 1,     // found an empty slot at i
-  ST_REDUNDANT = 2, // reduced to 0 = 0
-  ST_CONFLICT = 3,  // reduced to 0 = v with v != 0
-  ST_WANT = 4,      // needs item x
-  ST_DONE = 5
-};
-
-#ifndef BURR_ROUND_ITERS
-#define BURR_ROUND_ITERS 4
-#endif
-#ifndef BURR_SOLVE_K
-#define BURR_SOLVE_K 8
-#endif
-constexpr int kFifo = 8;  // must match the 8 staged registers below
-constexpr int kRoundIters = BURR_ROUND_ITERS;
-constexpr uint32_t kNoSplit = 0xffffffffu;
-
 // Records the state of the first lane that stops with an internal error.
 __device__ inline void solve_diag(uint64_t* d, uint32_t code, uint64_t rho, uint32_t js,
                                   uint32_t x, uint32_t xend, uint32_t q, uint32_t nq,
@@ -368,284 +337,236 @@ __device__ inline void solve_diag(uint64_t* d, uint32_t code, uint64_t rho, uint
   d[15] = fb;
 }
 
-template <typename VT>
-constexpr size_t solve_lds_bytes() {
-  return kRing * 64 * sizeof(uint64_t) + kFifo * 64 * sizeof(Rec) + kRing * 64 * sizeof(VT);
-}
+// ---------------------------------------------------------------------------
+// Solve: one wave per range, the lanes insert a bucket's records together
+// ---------------------------------------------------------------------------
+// The range's rows live in a ring of 128 slots in LDS shared by the wave
+// (bucket q touches slots [64q, 64q+126]). A pass inserts a set of records of
+// the current bucket: lanes take records from the staged bucket, and every
+// lane repeats one elimination step against the ring - XOR with the row at
+// its leading slot and shift - until its row reduces to zero or reaches an
+// empty slot, which it claims with an LDS compare-and-swap. Claims serialize,
+// so a pass equals sequential insertion in claim order; the pivot set and the
+// solution with free slots 0 do not depend on that order (they are
+// invariants of the row space), nor does the consistency of the inserted set.
+//
+// Per bucket, the first pass inserts every record that is not forced out.
+// If it meets an inconsistency (a row reducing to 0 with a nonzero value),
+// its rows are removed and the shorter chunk prefixes are tried, largest
+// first; the first consistent prefix is kept and the failing chunk sets the
+// bucket's threshold - the outcome of inserting the chunks one after the
+// other in decreasing offset order (Sec. 2, 2-bit thresholds), since a
+// prefix of a consistent set is consistent.
+constexpr uint32_t kStageItems = 128;  // header + 127 records staged in LDS per bucket
 
-template <typename VT, int K>
-__global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
-  extern __shared__ uint64_t lds[];
-  uint64_t* ringC = lds;                                  // [kRing][64]
-  Rec* fifo = reinterpret_cast<Rec*>(lds + kRing * 64);   // [kFifo][64]
-  VT* ringV = reinterpret_cast<VT*>(fifo + kFifo * 64);   // [kRing][64]
-  const LayerGeom g = a.g;
+struct WaveRing {
+  uint64_t c[kRing];
+  uint32_t v[kRing];
+  uint4 stage[kStageItems];
+  uint64_t placed[2];  // slots claimed by the current pass
+};
+
+__device__ inline uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+// Inserts records [r0, r1) of the staged bucket q. Returns 0 if the set was
+// consistent, 1 if an inconsistency was met (its rows are removed again), or
+// 2 on an internal error.
+__device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint4* rec4,
+                                     uint32_t hq, uint32_t q, uint32_t r0, uint32_t r1,
+                                     uint64_t P0, uint32_t limit, uint64_t rho,
+                                     uint64_t& steps) {
   const uint32_t lane = threadIdx.x;
-  const uint64_t rho = (uint64_t)blockIdx.x * 64 + lane;
-
-  uint32_t state = ST_DONE;
-  uint64_t fb = 0;
-  uint32_t nq = 0;
-  uint32_t x = 0, xend = 0;  // item cursor and end of the range's items
-  uint32_t js = 0;           // structure of the range
-  if (rho < g.nranges) {
-    js = find_struct(g.range_base, g.J, rho);
-    const uint64_t B = g.bucket_base[js + 1] - g.bucket_base[js];
-    const uint64_t R = g.range_base[js + 1] - g.range_base[js];
-    const uint64_t lr = rho - g.range_base[js];
-    const uint64_t f0 = lr * B / R;
-    fb = g.bucket_base[js] + f0;
-    nq = (uint32_t)((lr + 1) * B / R - f0);
-    x = a.bstart[fb] + (uint32_t)fb;
-    xend = a.bstart[fb + nq] + (uint32_t)(fb + nq);
-    state = ST_WANT;
-  }
-  const uint64_t P0 = fb * 64;
-  const uint32_t limit = 64u * nq;  // rows of kept keys end inside the range
-  uint32_t q = 0xffffffffu;   // bucket index inside the range
-  uint32_t rend = x;          // item index past the current bucket's records
-  bool open = false;          // a bucket is being processed
-  uint32_t kf = 0, code = 0, curk = 4, chunk_start = 0, split_at = kNoSplit;
-  uint32_t i = 0, v = 0;
+  if (lane < 2) R.placed[lane] = 0;
+  __syncthreads();
+  bool active = false, bad = false;
   uint64_t c = 0;
-  uint64_t vm0 = 0, vm1 = 0;  // valid ring rows (bit p <-> ring position p)
-  uint64_t pm0 = 0, pm1 = 0;  // rows placed by the current chunk
-  uint64_t steps = 0;
-#ifdef BURR_SOLVE_DEBUG
-  uint64_t dbg_active = 0, dbg_elim = 0, dbg_stall = 0;
-#endif
-
-  // Each item needs at most 64 elimination steps, so a lane is done after
-  // far fewer iterations than this cap; reaching it means a logic error, and
-  // the lane stops (fail = 3) instead of keeping the wave alive.
-  uint64_t iter_left = (uint64_t)(xend - x) * 80u + 4096u;
-  uint32_t written = x;  // items [x, written) are in the FIFO
-  const uint32_t last_item = a.nrec - 1;
-  const uint4* rec4 = reinterpret_cast<const uint4*>(a.rec);
-  uint4* fifo4 = reinterpret_cast<uint4*>(fifo);
-
+  uint32_t v = 0, i = 0;
+  uint32_t next = r0;
+  uint32_t guard = (r1 - r0) * 256u + 1024u;  // a lane advances or stops every other step
+  uint32_t result = 0;
   while (true) {
-    const uint32_t ld0 = written > x ? written : x;
-    const uint32_t ld1 = (x + kFifo < xend) ? x + kFifo : xend;
-    const uint32_t ldn = ld1 > ld0 ? ld1 - ld0 : 0;
-    // unconditional loads (clamped index) into named registers: a
-    // conditional load, or an array, makes the compiler copy or spill the
-    // value and wait for it at once
-#define BURR_STAGE_LOAD(j) \
-    const uint4 st##j = rec4[ld0 + j < last_item ? ld0 + j : last_item];
-    BURR_STAGE_LOAD(0) BURR_STAGE_LOAD(1) BURR_STAGE_LOAD(2) BURR_STAGE_LOAD(3)
-    BURR_STAGE_LOAD(4) BURR_STAGE_LOAD(5) BURR_STAGE_LOAD(6) BURR_STAGE_LOAD(7)
-#undef BURR_STAGE_LOAD
-
-    for (int it = 0; it < kRoundIters; ++it) {
-      if (state != ST_DONE && iter_left-- == 0) {
-        a.fail[js] = 3u;
-        solve_diag(a.diag, 3, rho, js, x, xend, q, nq, state, open, written, rend, kf, curk, i,
-                   fb);
-        state = ST_DONE;
-      }
-#ifdef BURR_SOLVE_DEBUG
-      dbg_active += state != ST_DONE;
-      dbg_elim += state == ST_ELIM;
-      dbg_stall += state == ST_WANT;
-#endif
-      // ---- K elimination steps ----
-      // branch-free: every lane reads its ring row; selects keep the state
-      // of lanes that are not eliminating
-#pragma unroll
-      for (int u = 0; u < K; ++u) {
-        const uint32_t p = i & (kRing - 1);
-        const uint64_t row = ringC[p * 64 + lane];
-        const uint32_t rv = ringV[p * 64 + lane];
-        const uint64_t vmw = (p & 64) ? vm1 : vm0;
-        const bool elim = state == ST_ELIM;
-        const bool valid = ((vmw >> (p & 63)) & 1ull) != 0;
-        const uint64_t cx = c ^ row;
-        const uint32_t vx = v ^ rv;
-        const bool cont = elim && valid && cx != 0;
-        const uint32_t j = (uint32_t)__builtin_ctzg(cx, 64);  // defined for cx == 0
-        const uint32_t fin = !valid ? ST_PLACE : (vx == 0 ? ST_REDUNDANT : ST_CONFLICT);
-        steps += (elim && valid) ? 1u : 0u;
-        c = cont ? (cx >> j) : c;
-        v = cont ? vx : v;
-        i = cont ? i + j : i;
-        state = (elim && !cont) ? fin : state;
-      }
-
-      // ---- outcome of finished equations (common path) ----
-      if (state == ST_PLACE && i >= limit) {
-        if (a.spillC && i < limit + 64u) {
-          // final-layer segment: the row belongs past the segment end; keep it
-          // in the ring (its half is free during the last bucket) and in the
-          // segment's spill buffer
-          const uint32_t p = i & (kRing - 1);
-          ringC[p * 64 + lane] = c;
-          ringV[p * 64 + lane] = (VT)v;
-          const uint64_t bit = 1ull << (p & 63);
-          if (p & 64) vm1 |= bit; else vm0 |= bit;
-          a.spillC[rho * 64 + (i - limit)] = c;
-          a.spillV[rho * 64 + (i - limit)] = v;
-          state = ST_WANT;
+    // lanes without a row take the next records
+    const uint64_t freem = wave_ballot(!active);
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(freem >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)freem, 0u));
+    if (!active && next + rank < r1) {
+      const uint32_t t = next + rank;
+      const uint4 r = t + 1 < kStageItems ? R.stage[t + 1] : rec4[hq + 1 + t];
+      c = (uint64_t)r.x | ((uint64_t)r.y << 32);
+      v = r.z;
+      i = 64u * q + (r.w & 63u);
+      active = true;
+    }
+    const uint32_t nfree = (uint32_t)__popcll(freem);
+    next = (r1 - next < nfree) ? r1 : next + nfree;
+    if (!__any(active)) break;
+    if (guard-- == 0) {
+      result = 2;
+      break;
+    }
+    // one elimination step
+    const uint32_t p = i & (kRing - 1);
+    const uint64_t row = R.c[p];
+    const uint32_t rv = R.v[p];
+    bool conflict = false;
+    if (active) {
+      if (row == 0) {
+        if (i >= limit && !(a.spillC && i < limit + 64u)) {
+          active = false;  // unreachable: a kept row crossing the range end
+          result = 2;
         } else {
-          // unreachable for kept keys of a BuRR layer; stop instead of
-          // writing outside the range
-          a.fail[js] = 2u;
-          solve_diag(a.diag, 2, rho, js, x, xend, q, nq, state, open, written, rend, kf, curk,
-                     i, fb);
-          state = ST_DONE;
+          const uint64_t old = atomicCAS((unsigned long long*)&R.c[p], 0ull,
+                                         (unsigned long long)c);
+          if (old == 0) {
+            R.v[p] = v;
+            atomicOr((unsigned long long*)&R.placed[p >> 6], 1ull << (p & 63));
+            if (i < limit) {
+              a.rowsC[P0 + i] = c;
+              a.rowsV[P0 + i] = v;
+            } else {
+              a.spillC[rho * 64 + (i - limit)] = c;
+              a.spillV[rho * 64 + (i - limit)] = v;
+            }
+            active = false;
+          }
+          // otherwise another lane took the slot: step against its row next time
         }
-      }
-      if (state == ST_PLACE) {
-        {
-          const uint32_t p = i & (kRing - 1);
-          ringC[p * 64 + lane] = c;
-          ringV[p * 64 + lane] = (VT)v;
-          const uint64_t bit = 1ull << (p & 63);
-          const bool hi_half = (p & 64) != 0;
-          vm1 |= hi_half ? bit : 0;
-          pm1 |= hi_half ? bit : 0;
-          vm0 |= hi_half ? 0 : bit;
-          pm0 |= hi_half ? 0 : bit;
-          a.rowsC[P0 + i] = c;
-          a.rowsV[P0 + i] = v;
-          state = ST_WANT;
-        }
-      }
-      state = state == ST_REDUNDANT ? ST_WANT : state;
-      // next record of the same bucket straight from the FIFO
-      if (state == ST_WANT && x != rend && x < written) {
-        const Rec rc = fifo[(x % kFifo) * 64 + lane];
-        const uint32_t k = 3u - meta_rank(rc.meta);
-        if (k > kf) {
-          const bool newk = k != curk;
-          pm0 = newk ? 0 : pm0;
-          pm1 = newk ? 0 : pm1;
-          chunk_start = newk ? x : chunk_start;
-          curk = k;
-          c = rc.c;
-          v = meta_value(rc.meta);
-          i = 64u * q + meta_offset(rc.meta);
-          ++x;
-          state = ST_ELIM;
-        }
-      }
-      // ---- rare paths: conflicts, bucket ends, headers, forced bumps ----
-      if (!__any(state == ST_CONFLICT ||
-                 (state == ST_WANT && (x == rend ? (open || x < written) : x < written))))
-        continue;
-      if (state == ST_CONFLICT) {
-        if (g.plain) {
-          a.fail[js] = 1u;
-          state = ST_DONE;
+      } else {
+        c ^= row;
+        v ^= rv;
+        ++steps;
+        if (c == 0) {
+          active = false;
+          conflict = v != 0;
         } else {
-          vm0 &= ~pm0;  // undo the chunk; the rest of the bucket is bumped
-          vm1 &= ~pm1;
-          code = curk;
-          split_at = chunk_start;
-          x = rend;
-          state = ST_WANT;
-        }
-      }
-      // ---- lanes take their next item ----
-      // Up to three flat passes; each pass may end a bucket, open the next
-      // one from its header and take a record. A lane whose next item has not
-      // reached the FIFO waits for the next round.
-#pragma unroll
-      for (int pass = 0; pass < 3; ++pass) {
-        if (pass > 0 && !__any(state == ST_WANT && (x == rend ? (open || x < written) : x < written)))
-          break;
-        if (state == ST_WANT && x == rend && open) {
-          // end of the current bucket: publish code and bump count
-          const uint64_t beta = fb + q;
-          if (!g.plain) {
-            a.code8[beta] = (uint8_t)code;
-            a.bump[beta] = rend - (split_at == kNoSplit ? rend : split_at);
-          }
-          open = false;
-          if (q + 1 == nq) {
-            a.occ[beta] = (q & 1) ? vm1 : vm0;
-            if (a.spill_occ) a.spill_occ[rho] = (q & 1) ? vm0 : vm1;
-            state = ST_DONE;
-          }
-        }
-        if (state == ST_WANT && x == rend && !open && x < written) {
-          // header of the next bucket; bucket q-1 is final: publish its
-          // occupancy and free its ring half
-          const Rec hd = fifo[(x % kFifo) * 64 + lane];
-          ++q;
-          if (q >= 1) {
-            const uint64_t beta = fb + q - 1;
-            const bool odd = ((q - 1) & 1) != 0;
-            a.occ[beta] = odd ? vm1 : vm0;
-            vm1 = odd ? 0 : vm1;
-            vm0 = odd ? vm0 : 0;
-          }
-          kf = head_kf(hd);
-          code = kf;
-          curk = 4;
-          pm0 = 0;
-          pm1 = 0;
-          split_at = kNoSplit;
-          rend = x + 1 + head_count(hd);
-          ++x;
-          open = true;
-        }
-        if (state == ST_WANT && x != rend && x < written) {
-          // a record of the current bucket
-          const Rec rc = fifo[(x % kFifo) * 64 + lane];
-          const uint32_t k = 3u - meta_rank(rc.meta);
-          if (k <= kf) {
-            // forced part of a range's last bucket: the rest is bumped
-            split_at = x;
-            x = rend;
-          } else {
-            const bool newk = k != curk;
-            pm0 = newk ? 0 : pm0;
-            pm1 = newk ? 0 : pm1;
-            chunk_start = newk ? x : chunk_start;
-            curk = k;
-            c = rc.c;
-            v = meta_value(rc.meta);
-            i = 64u * q + meta_offset(rc.meta);
-            ++x;
-            state = ST_ELIM;
-          }
+          const uint32_t j = (uint32_t)__builtin_ctzll(c);
+          c >>= j;
+          i += j;
         }
       }
     }
-    // ---- round end: commit this round's loads to the FIFO ----
-#define BURR_STAGE_COMMIT(j) \
-    if (j < ldn) fifo4[((ld0 + j) % kFifo) * 64 + lane] = st##j;
-    BURR_STAGE_COMMIT(0) BURR_STAGE_COMMIT(1) BURR_STAGE_COMMIT(2) BURR_STAGE_COMMIT(3)
-    BURR_STAGE_COMMIT(4) BURR_STAGE_COMMIT(5) BURR_STAGE_COMMIT(6) BURR_STAGE_COMMIT(7)
-#undef BURR_STAGE_COMMIT
-    if (ldn) written = ld0 + ldn;
-    if (!__any(state != ST_DONE)) break;
+    if (__any(conflict)) {
+      bad = true;
+      break;
+    }
+    if (__any(result == 2)) {
+      result = 2;
+      break;
+    }
   }
-  if (a.steps) atomicAdd((unsigned long long*)a.steps, (unsigned long long)steps);
-#ifdef BURR_SOLVE_DEBUG
-  if (a.steps) {
-    atomicAdd((unsigned long long*)a.steps + 1, (unsigned long long)dbg_active);
-    atomicAdd((unsigned long long*)a.steps + 2, (unsigned long long)dbg_elim);
-    atomicAdd((unsigned long long*)a.steps + 3, (unsigned long long)dbg_stall);
+  __syncthreads();
+  if (bad || result == 2) {
+    const uint64_t pm0 = R.placed[0], pm1 = R.placed[1];
+    if ((pm0 >> lane) & 1ull) R.c[lane] = 0;
+    if ((pm1 >> lane) & 1ull) R.c[64 + lane] = 0;
   }
-#endif
+  __syncthreads();
+  return result == 2 ? 2u : (bad ? 1u : 0u);
 }
 
-template <typename VT, int K>
-static hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
-  const unsigned blocks = (unsigned)((a.g.nranges + 63) / 64);
-  const size_t lds = solve_lds_bytes<VT>();
-  (void)hipFuncSetAttribute((const void*)k_solve<VT, K>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  k_solve<VT, K><<<blocks, 64, lds, s>>>(a);
-  return hipGetLastError();
+__global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
+  __shared__ WaveRing R;
+  const LayerGeom g = a.g;
+  const uint32_t lane = threadIdx.x;
+  const uint64_t rho = blockIdx.x;
+  if (rho >= g.nranges) return;
+  const uint32_t js = find_struct(g.range_base, g.J, rho);
+  const uint64_t B = g.bucket_base[js + 1] - g.bucket_base[js];
+  const uint64_t Rn = g.range_base[js + 1] - g.range_base[js];
+  const uint64_t lr = rho - g.range_base[js];
+  const uint64_t f0 = lr * B / Rn;
+  const uint64_t fb = g.bucket_base[js] + f0;
+  const uint32_t nq = (uint32_t)((lr + 1) * B / Rn - f0);
+  const uint64_t P0 = fb * 64;
+  const uint32_t limit = 64u * nq;
+  const uint32_t last_item = a.nrec - 1;
+  const uint4* rec4 = reinterpret_cast<const uint4*>(a.rec);
+  R.c[lane] = 0;
+  R.c[64 + lane] = 0;
+  uint64_t steps = 0;
+  bool failed = false;
+  // bucket 0's items, staged through registers
+  uint32_t hq = a.bstart[fb] + (uint32_t)fb;
+  uint4 nx0 = rec4[hq + lane < last_item ? hq + lane : last_item];
+  uint4 nx1 = rec4[hq + 64 + lane < last_item ? hq + 64 + lane : last_item];
+  for (uint32_t q = 0; q < nq && !failed; ++q) {
+    const uint64_t beta = fb + q;
+    hq = a.bstart[beta] + (uint32_t)beta;
+    R.stage[lane] = nx0;
+    R.stage[64 + lane] = nx1;
+    // the slots of bucket q+1 held bucket q-1: publish its occupancy, clear them
+    if (q >= 1) {
+      const uint32_t hb = ((q - 1) & 1u) * 64u;
+      const uint64_t word = wave_ballot(R.c[hb + lane] != 0);
+      if (lane == 0) a.occ[beta - 1] = word;
+      R.c[hb + lane] = 0;
+    }
+    __syncthreads();
+    if (q + 1 < nq) {  // next bucket's items load while this one is inserted
+      const uint32_t hn = a.bstart[beta + 1] + (uint32_t)(beta + 1);
+      nx0 = rec4[hn + lane < last_item ? hn + lane : last_item];
+      nx1 = rec4[hn + 64 + lane < last_item ? hn + 64 + lane : last_item];
+    }
+    const uint4 hd = R.stage[0];
+    const uint32_t count = hd.x, kf = hd.y & 3u;
+    const uint32_t e1 = hd.z, e2 = hd.z + hd.w;  // ends of ranks 0 and 1
+    const uint32_t keep_ranks = g.plain ? 3u : 3u - kf;
+    const uint32_t cand = keep_ranks == 3 ? count : (keep_ranks == 2 ? e2 : (keep_ranks == 1 ? e1 : 0u));
+    uint32_t kept = cand, code = kf;
+    if (cand > 0) {
+      uint32_t res = wave_pass(R, a, rec4, hq, q, 0, cand, P0, limit, rho, steps);
+      if (res == 1 && g.plain) {
+        if (lane == 0) a.fail[js] = 1u;
+        failed = true;
+      } else if (res == 1) {
+        kept = 0;
+        code = 3;
+        uint32_t failed_size = cand;  // smallest prefix known to be inconsistent
+        for (uint32_t rr = keep_ranks - 1; rr >= 1 && res != 2; --rr) {
+          const uint32_t e = rr == 2 ? e2 : e1;
+          if (e == failed_size) continue;  // the same set again
+          res = e ? wave_pass(R, a, rec4, hq, q, 0, e, P0, limit, rho, steps) : 0u;
+          if (res == 0) {
+            kept = e;
+            code = 3 - rr;
+            break;
+          }
+          failed_size = e;
+        }
+      }
+      if (res == 2) {
+        if (lane == 0) {
+          a.fail[js] = 2u;
+          solve_diag(a.diag, 2, rho, js, hq, count, q, nq, cand, 0, kept, code, kf, 0, 0, fb);
+        }
+        failed = true;
+      }
+    }
+    if (!g.plain && lane == 0) {
+      a.code8[beta] = (uint8_t)code;
+      a.bump[beta] = count - kept;
+    }
+    __syncthreads();
+  }
+  if (!failed) {
+    const uint32_t hl = ((nq - 1) & 1u) * 64u;
+    const uint64_t last = wave_ballot(R.c[hl + lane] != 0);
+    const uint64_t spill = wave_ballot(R.c[(64u - hl) + lane] != 0);
+    if (lane == 0) {
+      a.occ[fb + nq - 1] = last;
+      if (a.spill_occ) a.spill_occ[rho] = spill;
+    }
+  }
+  if (a.steps) {
+    for (int d = 32; d >= 1; d >>= 1) steps += __shfl_xor(steps, d, 64);
+    if (lane == 0) atomicAdd((unsigned long long*)a.steps, (unsigned long long)steps);
+  }
 }
 
 hipError_t solve_layer(const SolveArgs& a, hipStream_t s) {
-  if (a.g.r <= 8) return launch_solve<uint8_t, BURR_SOLVE_K>(a, s);
-  if (a.g.r <= 16) return launch_solve<uint16_t, BURR_SOLVE_K>(a, s);
-  return launch_solve<uint32_t, BURR_SOLVE_K>(a, s);
+  if (a.g.nranges == 0) return hipSuccess;
+  k_solve_wave<<<(unsigned)a.g.nranges, 64, 0, s>>>(a);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
