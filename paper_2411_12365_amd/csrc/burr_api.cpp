@@ -193,16 +193,19 @@ struct Table {
 struct Workspace {
   Allocator* al;
   std::vector<void*> owned;
-  uint64_t cap_keys = 0, cap_m = 0, cap_B = 0, cap_counts = 0, cap_items = 0, cap_scan = 0;
-  uint64_t cap_seg = 0, cap_tab = 0, cap_J = 0;
-  uint64_t *keysA = nullptr, *keysT = nullptr, *keysS = nullptr, *slotT = nullptr;
-  uint32_t *valsA = nullptr, *valsT = nullptr;
+  uint64_t cap_keys = 0, cap_m = 0, cap_B = 0, cap_items = 0, cap_scan = 0;
+  uint64_t cap_seg = 0, cap_tab = 0, cap_J = 0, cap_c1 = 0, cap_c2 = 0, cap_plan = 0;
+  uint64_t* keysA = nullptr;  // next layer's keys
+  uint32_t* valsA = nullptr;
+  uint4 *p1 = nullptr, *p2 = nullptr;  // sort intermediates
+  uint32_t *counts1 = nullptr, *counts2 = nullptr;
+  uint32_t *binlo = nullptr, *nch = nullptr, *cbase = nullptr, *sstart = nullptr;
   Rec* rec = nullptr;
   uint64_t* rowsC = nullptr;
   uint32_t* rowsV = nullptr;
   uint64_t* occ = nullptr;
   uint8_t* code8 = nullptr;
-  uint32_t *bump = nullptr, *bstart = nullptr, *counts = nullptr, *scan_tmp = nullptr;
+  uint32_t *bump = nullptr, *bstart = nullptr, *scan_tmp = nullptr;
   uint32_t* fail = nullptr;  // per structure
   uint32_t* soff = nullptr;  // per structure: first bumped key
   uint64_t* steps = nullptr;
@@ -225,8 +228,8 @@ struct Workspace {
   bool reserve_keys(uint64_t n) {
     if (n <= cap_keys && keysA) return true;
     cap_keys = std::max<uint64_t>(n, 1);
-    return alloc(keysA, cap_keys) && alloc(keysT, cap_keys) && alloc(keysS, cap_keys) &&
-           alloc(slotT, cap_keys) && alloc(valsA, cap_keys) && alloc(valsT, cap_keys);
+    return alloc(keysA, cap_keys) && alloc(valsA, cap_keys) && alloc(p1, cap_keys) &&
+           alloc(p2, cap_keys);
   }
   bool reserve_items(uint64_t count) {  // one record per key + one header per bucket
     if (count <= cap_items && rec) return true;
@@ -250,10 +253,17 @@ struct Workspace {
     return alloc(code8, B + 1) && alloc(bump, B + 1) && alloc(bstart, B + 1) &&
            reserve_scan(B + 1);
   }
-  bool reserve_counts(uint64_t c) {
-    if (c <= cap_counts && counts) return reserve_scan(c + 1);
-    cap_counts = c;
-    return alloc(counts, c + 1) && reserve_scan(c + 1);
+  bool reserve_sort(const SortPlan& sp) {
+    const uint64_t c1 = (uint64_t)sp.nb1 * sp.G1, c2 = (uint64_t)sp.U2 * sp.S;
+    const uint64_t pl = std::max<uint64_t>(sp.nb1, sp.nsub) + 1;
+    if ((c1 > cap_c1 || !counts1) && !alloc(counts1, (cap_c1 = c1) + 1)) return false;
+    if ((c2 > cap_c2 || !counts2) && !alloc(counts2, (cap_c2 = c2) + 1)) return false;
+    if (pl > cap_plan || !binlo) {
+      cap_plan = pl;
+      if (!alloc(binlo, pl) || !alloc(nch, pl) || !alloc(cbase, pl) || !alloc(sstart, pl))
+        return false;
+    }
+    return reserve_scan(std::max(c1, c2) + 1);
   }
   bool reserve_structs(uint64_t J) {
     if (J <= cap_J && fail) return true;
@@ -319,17 +329,7 @@ int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s) {
   return BURR_OK;
 }
 
-uint32_t sort_groups(uint64_t n, uint32_t nbins) {
-  // level-1 workgroups: enough to fill the chip, few enough that the
-  // bins x groups count matrix stays small
-  uint64_t g = (n + 4095) / 4096;
-  const uint64_t cap = nbins > 4096 ? 1024 : 2048;
-  if (g > cap) g = cap;
-  if (g < 1) g = 1;
-  return (uint32_t)g;
-}
-
-// Sorts one layer's keys by (bucket, chunk) into ws.keysS / ws.rec / ws.bstart.
+// Sorts one layer's keys by (bucket, chunk) into the item stream ws.rec and ws.bstart.
 int run_sort(Workspace& ws, const uint64_t* keys, const void* vals, uint32_t vbytes,
              bool first_layer, bool filter, uint64_t fp_salt, const LayerGeom& g,
              hipStream_t s) {
@@ -341,17 +341,18 @@ int run_sort(Workspace& ws, const uint64_t* keys, const void* vals, uint32_t vby
   a.filter = filter ? 1u : 0u;
   a.fp_salt = fp_salt;
   a.g = g;
-  a.nbins = (uint32_t)((g.nbuckets + kBucketsPerBin - 1) / kBucketsPerBin);
-  if (a.nbins > kMaxBins) return set_error(BURR_E_INVALID);
-  a.groups = sort_groups(g.nkeys, a.nbins);
-  if (!ws.reserve_counts((uint64_t)a.nbins * a.groups)) return set_error(BURR_E_NOMEM);
+  a.plan = plan_sort(g.nkeys, g.nbuckets);
+  if (!ws.reserve_sort(a.plan)) return set_error(BURR_E_NOMEM);
   if (!ws.reserve_items(g.nkeys + g.nbuckets)) return set_error(BURR_E_NOMEM);
-  a.counts = ws.counts;
+  a.counts1 = ws.counts1;
+  a.counts2 = ws.counts2;
   a.scan_tmp = ws.scan_tmp;
-  a.tmp_keys = ws.keysT;
-  a.tmp_vals = ws.valsT;
-  a.tmp_slot = ws.slotT;
-  a.out_keys = ws.keysS;
+  a.binlo = ws.binlo;
+  a.nch = ws.nch;
+  a.cbase = ws.cbase;
+  a.sstart = ws.sstart;
+  a.p1 = ws.p1;
+  a.p2 = ws.p2;
   a.out_rec = ws.rec;
   a.bstart = ws.bstart;
   HIP_TRY(sort_layer(a, s));
@@ -559,8 +560,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     HIP_TRY(hipMemcpyAsync(soff.data(), ws.soff, (g.J + 1) * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(fails.data(), ws.fail, g.J * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&steps, ws.steps, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(gather_bumped(ws.keysS, ws.rec, ws.bstart, ws.bump, g.nbuckets, ws.keysA, ws.valsA,
-                          s));
+    HIP_TRY(gather_bumped(ws.rec, ws.bstart, ws.bump, g.nbuckets, ws.keysA, ws.valsA, s));
     HIP_TRY(hipEventRecord(ev.e[5], s));
     HIP_TRY(hipStreamSynchronize(s));
     for (uint32_t f : fails)
@@ -782,7 +782,7 @@ uint64_t burr_workspace_bytes(uint64_t n, uint32_t rmax, uint32_t count, const b
   const uint64_t m = std::max(m0, mf) + 64ull * count;
   const uint64_t B = m / 64;
   uint64_t bytes = 0;
-  bytes += 40 * std::max<uint64_t>(n, 1);              // key and value buffers
+  bytes += 44 * std::max<uint64_t>(n, 1);              // next keys/values, sort intermediates
   bytes += 16 * (n + B + 1);                           // item stream
   bytes += 12 * m + 8 * (B + 1);                       // rows and occupancy
   bytes += 9 * (B + 1) + 4 * ((B + 2047) / 2048) * 2048 + 4 * (B + 64);  // codes, counts, scans

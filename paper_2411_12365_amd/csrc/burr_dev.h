@@ -11,9 +11,8 @@ namespace burr {
 constexpr uint32_t kWidth = 64;           // ribbon width w (Sec. 2)
 constexpr uint32_t kBucket = 64;          // bucket size b handled by the kernels
 constexpr uint32_t kRing = 128;           // LDS ring rows per range: bucket q touches slots [64q, 64q+126]
-constexpr uint32_t kBucketsPerBin = 2048; // coarse sort bin = 2048 consecutive buckets
-constexpr uint32_t kDigitsPerBin = 3 * kBucketsPerBin; // (bucket, chunk) digits inside a bin
-constexpr uint32_t kMaxBins = 32768;      // level-1 histogram fits in LDS
+constexpr uint32_t kSubBuckets = 64;      // sort sub-bin: 64 consecutive buckets
+constexpr uint32_t kMaxDigits = 2048;     // most bins (sub-bins) of a partition level
 
 // MurmurHash3's 64-bit finalizer (public domain), used as the key mixer.
 __host__ __device__ inline uint64_t mix64(uint64_t x) {
@@ -81,10 +80,12 @@ __device__ inline uint32_t rank_of(uint32_t o, const LayerGeom& g) {
 }
 
 // One 16-byte element of a layer's item stream. The stream holds, for every
-// bucket in order, a header item followed by the bucket's records:
-//   header : c = number of records | (forced threshold index << 32), meta = 0
-//   record : c = coefficient row, meta = value (bits 0..31) | offset in the
-//            bucket (bits 32..37) | rank (bits 40..41)
+// bucket in order, a header item followed by the bucket's records in chunk
+// (rank) order:
+//   header : c = number of records | (forced threshold index << 32),
+//            meta = records of rank 0 | records of rank 1 << 32
+//   record : c = key, meta = value (bits 0..31) | offset in the bucket
+//            (bits 32..37) | rank (bits 40..41)
 // The record of sorted key position p in bucket beta sits at item p+beta+1,
 // the header of bucket beta at item bstart[beta]+beta.
 struct alignas(16) Rec {

@@ -14,11 +14,23 @@ namespace burr {
 size_t scan_tmp_words(size_t n);
 hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s);
 
-// Sorting of one layer's keys by (bucket, chunk) - two passes:
-//   level 1: hash every key, partition into coarse bins of kBucketsPerBin
-//            global buckets; the start slot travels with the key
-//   level 2: one workgroup per bin orders its keys by (bucket, chunk) in LDS
-//            and writes the item stream (bucket headers + records)
+// Sorting of one layer's keys by (bucket, chunk) - three levels:
+//   level 1: hash every key, partition into nb1 bins of S sub-bins
+//   level 2: per bin, partition into its sub-bins of kSubBuckets buckets
+//   level 3: per sub-bin, order by (bucket, chunk) in LDS and write the
+//            item stream (bucket headers + records) and the bucket starts
+// Every level writes contiguous runs (tiles are ordered in LDS first).
+struct SortPlan {
+  uint32_t nsub;       // sub-bins (level-3 workgroups)
+  uint32_t nb1;        // level-1 bins
+  uint32_t S;          // sub-bins per bin
+  uint32_t G1;         // level-1 workgroups
+  uint64_t per_group;  // keys per level-1 workgroup
+  uint32_t U2;         // level-2 workgroups launched (bound on the chunks)
+  uint32_t pad;
+};
+SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets);
+
 struct SortArgs {
   const uint64_t* keys;   // input keys (g.nkeys), structure j at g.key_off[j]
   const void* vals;       // input values or nullptr (filter fingerprints)
@@ -27,14 +39,16 @@ struct SortArgs {
   uint64_t fp_salt;       // fingerprint salt (filter mode)
   uint32_t filter;        // values are fingerprints
   LayerGeom g;
-  uint32_t nbins;         // ceil(B / kBucketsPerBin)
-  uint32_t groups;        // level-1 workgroups
-  uint32_t* counts;       // nbins * groups u32, scanned in place
-  uint32_t* scan_tmp;
-  uint64_t* tmp_keys;     // level-1 output (nkeys)
-  uint32_t* tmp_vals;
-  uint64_t* tmp_slot;     // global start slot of each key
-  uint64_t* out_keys;     // level-2 output keys (nkeys), bucket order
+  SortPlan plan;
+  uint32_t* counts1;      // nb1 * G1 (+1), scanned in place
+  uint32_t* counts2;      // U2 * S (+1), scanned in place
+  uint32_t* scan_tmp;     // for the larger of the two scans
+  uint32_t* binlo;        // nb1 + 1
+  uint32_t* nch;          // nb1 + 1
+  uint32_t* cbase;        // nb1 + 1
+  uint32_t* sstart;       // nsub + 1
+  uint4* p1;              // nkeys intermediate records (level 1 output)
+  uint4* p2;              // nkeys intermediate records (level 2 output)
   Rec* out_rec;           // item stream (nkeys + nbuckets)
   uint32_t* bstart;       // B + 1 bucket start offsets
 };
@@ -80,7 +94,7 @@ hipError_t pack_codes(const uint8_t* code8, const LayerGeom& g, uint64_t ncode_w
                       uint64_t* words, hipStream_t s);
 
 // Copy the bumped suffix of every bucket into the next layer's input.
-hipError_t gather_bumped(const uint64_t* sorted_keys, const Rec* rec, const uint32_t* bstart,
+hipError_t gather_bumped(const Rec* rec, const uint32_t* bstart,
                          const uint32_t* off /* scanned bump counts, B+1 */, uint64_t B,
                          uint64_t* next_keys, uint32_t* next_vals, hipStream_t s);
 

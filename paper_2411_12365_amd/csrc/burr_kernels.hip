@@ -111,10 +111,39 @@ hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s
 }
 
 // ---------------------------------------------------------------------------
-// Sorting
+// Sorting: three levels, each writing contiguous runs
 // ---------------------------------------------------------------------------
-constexpr int kL1Threads = 256;
-constexpr int kL2Threads = 512;
+// level 1: hash every key (start slot, value), partition into nb1 bins of S
+//          sub-bins; each tile of kTile keys is ordered by bin in LDS first,
+//          so the writes to a bin are runs of consecutive records
+// level 2: per bin, partition into its S sub-bins the same way
+// level 3: one workgroup per sub-bin (64 buckets) orders its records by
+//          (bucket, chunk) in LDS and writes headers and records as one block
+// Intermediate records (16 B): key, value | slot within the bin << 32.
+constexpr int kPartThreads = 256;
+constexpr int kPartPer = 8;
+constexpr uint32_t kTile = kPartThreads * kPartPer;  // keys per tile
+constexpr uint32_t kSubSlots = kSubBuckets * 64;     // slots per sub-bin
+constexpr uint32_t kChunk2 = 16384;                  // level-2 keys per workgroup
+constexpr int kL3Threads = 256;
+constexpr uint32_t kL3Cap = 4608;                    // items of a sub-bin staged in LDS
+
+SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets) {
+  SortPlan p{};
+  p.nsub = (uint32_t)((nbuckets + kSubBuckets - 1) / kSubBuckets);
+  uint32_t nb = 1;
+  while ((uint64_t)nb * nb < p.nsub) ++nb;  // about sqrt(nsub) bins of about sqrt(nsub) sub-bins
+  if (nb > kMaxDigits) nb = kMaxDigits;
+  p.S = (p.nsub + nb - 1) / nb;
+  p.nb1 = (p.nsub + p.S - 1) / p.S;
+  uint64_t g = (nkeys + 4 * kTile - 1) / (4 * kTile);  // at least 4 tiles per workgroup
+  if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  p.G1 = (uint32_t)g;
+  p.per_group = (nkeys + p.G1 - 1) / p.G1;
+  p.U2 = (uint32_t)(nkeys / kChunk2 + p.nb1 + 1);
+  return p;
+}
 
 // Threads walk their keys in increasing index order: the structure of the
 // first key is found by binary search, later ones by stepping forward.
@@ -142,55 +171,257 @@ struct KeyWalk {
   }
 };
 
-__global__ __launch_bounds__(kL1Threads) void k_l1_hist(const uint64_t* __restrict__ keys,
-                                                         LayerGeom g, uint32_t nbins,
-                                                         uint32_t groups, uint64_t per_group,
-                                                         uint32_t* __restrict__ counts) {
-  extern __shared__ uint32_t hist[];
-  for (uint32_t i = threadIdx.x; i < nbins; i += kL1Threads) hist[i] = 0;
-  __syncthreads();
-  const uint64_t lo = (uint64_t)blockIdx.x * per_group;
-  const uint64_t hi = lo + per_group < g.nkeys ? lo + per_group : g.nkeys;
-  KeyWalk w(g, lo + threadIdx.x);
-  for (uint64_t i = lo + threadIdx.x; i < hi; i += kL1Threads) {
-    w.advance(g, i);
-    const uint64_t s = start_of(keys[i], g.salt_s, w.span);
-    atomicAdd(&hist[(uint32_t)((w.bb + (s >> 6)) / kBucketsPerBin)], 1u);
+// Block-wide exclusive scan of n <= kMaxDigits counters in LDS (in place);
+// a[n] receives the total.
+__device__ inline void lds_scan(uint32_t* a, uint32_t n, uint32_t* wsum) {
+  constexpr uint32_t per = (kMaxDigits + kPartThreads - 1) / kPartThreads;
+  uint32_t loc[per];
+  uint32_t tot = 0;
+  const uint32_t base = threadIdx.x * per;
+#pragma unroll
+  for (uint32_t k = 0; k < per; ++k) {
+    loc[k] = base + k < n ? a[base + k] : 0u;
+    tot += loc[k];
   }
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < nbins; i += kL1Threads)
-    counts[(size_t)i * groups + blockIdx.x] = hist[i];
+  uint32_t total;
+  uint32_t run = block_exclusive_scan<kPartThreads>(tot, wsum, wsum + kPartThreads / 64);
+  total = wsum[kPartThreads / 64];
+#pragma unroll
+  for (uint32_t k = 0; k < per; ++k) {
+    if (base + k < n) a[base + k] = run;
+    run += loc[k];
+  }
+  if (threadIdx.x == 0) a[n] = total;
+  __syncthreads();
 }
 
-template <typename VT>
-__global__ __launch_bounds__(kL1Threads) void k_l1_scatter(
-    const uint64_t* __restrict__ keys, const VT* __restrict__ vals, LayerGeom g,
-    uint32_t nbins, uint32_t groups, uint64_t per_group, const uint32_t* __restrict__ offs,
-    uint32_t mask_values, uint32_t filter, uint64_t fp_salt, uint64_t* __restrict__ tk,
-    uint32_t* __restrict__ tv, uint64_t* __restrict__ ts) {
-  extern __shared__ uint32_t cur[];
-  for (uint32_t i = threadIdx.x; i < nbins; i += kL1Threads)
-    cur[i] = offs[(size_t)i * groups + blockIdx.x];
+// Level 1, pass 1: per workgroup, keys per bin.
+__global__ __launch_bounds__(kPartThreads) void k_p1_hist(const uint64_t* __restrict__ keys,
+                                                          LayerGeom g, SortPlan sp,
+                                                          uint32_t* __restrict__ counts) {
+  extern __shared__ uint32_t hist[];
+  for (uint32_t i = threadIdx.x; i < sp.nb1; i += kPartThreads) hist[i] = 0;
   __syncthreads();
-  const uint64_t lo = (uint64_t)blockIdx.x * per_group;
-  const uint64_t hi = lo + per_group < g.nkeys ? lo + per_group : g.nkeys;
+  const uint64_t lo = (uint64_t)blockIdx.x * sp.per_group;
+  const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
+  const uint64_t bin_slots = (uint64_t)sp.S * kSubSlots;
   KeyWalk w(g, lo + threadIdx.x);
-  for (uint64_t i = lo + threadIdx.x; i < hi; i += kL1Threads) {
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kPartThreads) {
     w.advance(g, i);
-    const uint64_t key = keys[i];
-    uint32_t v;
-    if (filter && mask_values)
-      v = (uint32_t)(mix64(key ^ fp_salt) >> (64 - w.r));
-    else if (mask_values)
-      v = (uint32_t)vals[i] & (w.r >= 32 ? 0xffffffffu : ((1u << w.r) - 1u));
-    else
-      v = (uint32_t)vals[i];
-    const uint64_t slot = 64 * w.bb + start_of(key, g.salt_s, w.span);
-    const uint32_t pos = atomicAdd(&cur[(uint32_t)((slot >> 6) / kBucketsPerBin)], 1u);
-    tk[pos] = key;
-    tv[pos] = v;
-    ts[pos] = slot;
+    const uint64_t slot = 64 * w.bb + start_of(keys[i], g.salt_s, w.span);
+    atomicAdd(&hist[(uint32_t)(slot / bin_slots)], 1u);
   }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < sp.nb1; i += kPartThreads)
+    counts[(size_t)i * sp.G1 + blockIdx.x] = hist[i];
+}
+
+// Orders one tile of records by digit in LDS and writes every digit's part
+// as a run at that digit's cursor (cur[d] advances by the tile's count).
+// rec/dig/rank: each thread's kPartPer records (dig = kNoDigit: none).
+constexpr uint32_t kNoDigit = 0xffffffffu;
+__device__ inline void tile_write(uint4 (&rec)[kPartPer], uint32_t (&dig)[kPartPer],
+                                  uint32_t (&rank)[kPartPer], uint32_t D, uint32_t* cur,
+                                  uint32_t* toff, uint4* stage, uint16_t* sdig, uint32_t* wsum,
+                                  uint32_t ntile, uint4* __restrict__ out) {
+  lds_scan(toff, D, wsum);  // tile counts -> tile offsets
+#pragma unroll
+  for (int k = 0; k < kPartPer; ++k)
+    if (dig[k] != kNoDigit) {
+      const uint32_t pos = toff[dig[k]] + rank[k];
+      stage[pos] = rec[k];
+      sdig[pos] = (uint16_t)dig[k];
+    }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < ntile; j += kPartThreads) {
+    const uint32_t d = sdig[j];
+    out[cur[d] + (j - toff[d])] = stage[j];
+  }
+  __syncthreads();
+  for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) cur[d] += toff[d + 1] - toff[d];
+  __syncthreads();
+  for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) toff[d] = 0;
+  __syncthreads();
+}
+
+// LDS layout of the partition kernels: cur[D], toff[D+1], wsum, stage, sdig
+__host__ __device__ constexpr size_t part_lds_bytes(uint32_t D) {
+  return (size_t)(2 * D + 2 + kPartThreads / 64 + 2) * 4 + 15 + (size_t)kTile * 16 + kTile * 2;
+}
+struct PartLds {
+  uint32_t *cur, *toff, *wsum;
+  uint4* stage;
+  uint16_t* sdig;
+  __device__ PartLds(uint32_t* sm, uint32_t D) {
+    cur = sm;
+    toff = sm + D;
+    wsum = toff + D + 2;
+    uint8_t* p = reinterpret_cast<uint8_t*>(wsum + kPartThreads / 64 + 2);
+    p = reinterpret_cast<uint8_t*>(((uintptr_t)p + 15) & ~(uintptr_t)15);
+    stage = reinterpret_cast<uint4*>(p);
+    sdig = reinterpret_cast<uint16_t*>(stage + kTile);
+  }
+};
+
+// Level 1, pass 2: hash, mask or fingerprint the value, write tile runs per bin.
+template <typename VT>
+__global__ __launch_bounds__(kPartThreads) void k_p1_scatter(
+    const uint64_t* __restrict__ keys, const VT* __restrict__ vals, LayerGeom g, SortPlan sp,
+    const uint32_t* __restrict__ offs, uint32_t mask_values, uint32_t filter, uint64_t fp_salt,
+    uint4* __restrict__ out) {
+  extern __shared__ uint32_t sm[];
+  PartLds L(sm, sp.nb1);
+  for (uint32_t d = threadIdx.x; d < sp.nb1; d += kPartThreads) {
+    L.cur[d] = offs[(size_t)d * sp.G1 + blockIdx.x];
+    L.toff[d] = 0;
+  }
+  __syncthreads();
+  const uint64_t lo = (uint64_t)blockIdx.x * sp.per_group;
+  const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
+  const uint64_t bin_slots = (uint64_t)sp.S * kSubSlots;
+  KeyWalk w(g, lo + threadIdx.x);
+  for (uint64_t t0 = lo; t0 < hi; t0 += kTile) {
+    uint4 rec[kPartPer];
+    uint32_t dig[kPartPer], rank[kPartPer];
+#pragma unroll
+    for (int k = 0; k < kPartPer; ++k) {
+      const uint64_t i = t0 + threadIdx.x + (uint64_t)k * kPartThreads;
+      dig[k] = kNoDigit;
+      if (i < hi) {
+        w.advance(g, i);
+        const uint64_t key = keys[i];
+        uint32_t v;
+        if (filter && mask_values)
+          v = (uint32_t)(mix64(key ^ fp_salt) >> (64 - w.r));
+        else if (mask_values)
+          v = (uint32_t)vals[i] & (w.r >= 32 ? 0xffffffffu : ((1u << w.r) - 1u));
+        else
+          v = (uint32_t)vals[i];
+        const uint64_t slot = 64 * w.bb + start_of(key, g.salt_s, w.span);
+        const uint32_t d = (uint32_t)(slot / bin_slots);
+        rec[k] = make_uint4((uint32_t)key, (uint32_t)(key >> 32), v,
+                            (uint32_t)(slot - (uint64_t)d * bin_slots));
+        dig[k] = d;
+        rank[k] = atomicAdd(&L.toff[d], 1u);
+      }
+    }
+    const uint32_t ntile = (uint32_t)(hi - t0 < kTile ? hi - t0 : kTile);
+    __syncthreads();
+    tile_write(rec, dig, rank, sp.nb1, L.cur, L.toff, L.stage, L.sdig, L.wsum, ntile, out);
+  }
+}
+
+// Level 2 plan (one workgroup): bin ranges and level-2 workgroups per bin.
+__global__ __launch_bounds__(kPartThreads) void k_p2_plan(const uint32_t* __restrict__ offs1,
+                                                          SortPlan sp, uint64_t nkeys,
+                                                          uint32_t* __restrict__ binlo,
+                                                          uint32_t* __restrict__ nch,
+                                                          uint32_t* __restrict__ cbase) {
+  __shared__ uint32_t a[kMaxDigits + 1];
+  __shared__ uint32_t wsum[kPartThreads / 64 + 2];
+  for (uint32_t b = threadIdx.x; b < sp.nb1; b += kPartThreads) {
+    const uint32_t lo = offs1[(size_t)b * sp.G1];
+    const uint32_t hi = b + 1 < sp.nb1 ? offs1[(size_t)(b + 1) * sp.G1] : (uint32_t)nkeys;
+    binlo[b] = lo;
+    const uint32_t c = (hi - lo + kChunk2 - 1) / kChunk2;
+    nch[b] = c;
+    a[b] = c;
+  }
+  if (threadIdx.x == 0) binlo[sp.nb1] = (uint32_t)nkeys;
+  __syncthreads();
+  lds_scan(a, sp.nb1, wsum);
+  for (uint32_t b = threadIdx.x; b <= sp.nb1; b += kPartThreads) cbase[b] = a[b];
+}
+
+// level-2 workgroup -> (bin, chunk, key range); false if unused
+struct Chunk2 {
+  uint32_t b, c, lo, hi, base;  // base: first counts2 entry of the bin
+};
+__device__ inline bool chunk2_of(uint32_t wg, const SortPlan& sp, const uint32_t* binlo,
+                                 const uint32_t* nch, const uint32_t* cbase, Chunk2& ch) {
+  if (wg >= cbase[sp.nb1]) return false;
+  uint32_t lo = 0, hi = sp.nb1;  // last bin b with cbase[b] <= wg
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (cbase[mid] <= wg) lo = mid; else hi = mid;
+  }
+  ch.b = lo;
+  ch.c = wg - cbase[lo];
+  ch.lo = binlo[lo] + ch.c * kChunk2;
+  ch.hi = ch.lo + kChunk2 < binlo[lo + 1] ? ch.lo + kChunk2 : binlo[lo + 1];
+  ch.base = cbase[lo] * sp.S;
+  (void)nch;
+  return true;
+}
+
+// Level 2, pass 1: keys per sub-bin of each chunk; counts2 is laid out per
+// bin as [sub-bin][chunk] so that one scan gives every run's position.
+__global__ __launch_bounds__(kPartThreads) void k_p2_hist(const uint4* __restrict__ in,
+                                                          SortPlan sp,
+                                                          const uint32_t* __restrict__ binlo,
+                                                          const uint32_t* __restrict__ nch,
+                                                          const uint32_t* __restrict__ cbase,
+                                                          uint32_t* __restrict__ counts) {
+  extern __shared__ uint32_t hist[];
+  Chunk2 ch;
+  if (!chunk2_of(blockIdx.x, sp, binlo, nch, cbase, ch)) return;
+  for (uint32_t i = threadIdx.x; i < sp.S; i += kPartThreads) hist[i] = 0;
+  __syncthreads();
+  for (uint32_t i = ch.lo + threadIdx.x; i < ch.hi; i += kPartThreads)
+    atomicAdd(&hist[in[i].w / kSubSlots], 1u);
+  __syncthreads();
+  const uint32_t nc = nch[ch.b];
+  for (uint32_t i = threadIdx.x; i < sp.S; i += kPartThreads)
+    counts[ch.base + i * nc + ch.c] = hist[i];
+}
+
+// Level 2, pass 2: tile runs per sub-bin.
+__global__ __launch_bounds__(kPartThreads) void k_p2_scatter(
+    const uint4* __restrict__ in, SortPlan sp, const uint32_t* __restrict__ binlo,
+    const uint32_t* __restrict__ nch, const uint32_t* __restrict__ cbase,
+    const uint32_t* __restrict__ offs, uint4* __restrict__ out) {
+  extern __shared__ uint32_t sm[];
+  Chunk2 ch;
+  if (!chunk2_of(blockIdx.x, sp, binlo, nch, cbase, ch)) return;
+  PartLds L(sm, sp.S);
+  const uint32_t nc = nch[ch.b];
+  for (uint32_t d = threadIdx.x; d < sp.S; d += kPartThreads) {
+    L.cur[d] = offs[ch.base + d * nc + ch.c];
+    L.toff[d] = 0;
+  }
+  __syncthreads();
+  for (uint32_t t0 = ch.lo; t0 < ch.hi; t0 += kTile) {
+    uint4 rec[kPartPer];
+    uint32_t dig[kPartPer], rank[kPartPer];
+#pragma unroll
+    for (int k = 0; k < kPartPer; ++k) {
+      const uint32_t i = t0 + threadIdx.x + k * kPartThreads;
+      dig[k] = kNoDigit;
+      if (i < ch.hi) {
+        rec[k] = in[i];
+        dig[k] = rec[k].w / kSubSlots;
+        rank[k] = atomicAdd(&L.toff[dig[k]], 1u);
+      }
+    }
+    const uint32_t ntile = ch.hi - t0 < kTile ? ch.hi - t0 : kTile;
+    __syncthreads();
+    tile_write(rec, dig, rank, sp.S, L.cur, L.toff, L.stage, L.sdig, L.wsum, ntile, out);
+  }
+}
+
+// First record of every sub-bin (and sstart[nsub] = nkeys).
+__global__ void k_p2_starts(SortPlan sp, uint64_t nkeys, const uint32_t* __restrict__ binlo,
+                            const uint32_t* __restrict__ nch, const uint32_t* __restrict__ cbase,
+                            const uint32_t* __restrict__ offs, uint32_t* __restrict__ sstart) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > sp.nsub) return;
+  if (t == sp.nsub) {
+    sstart[t] = (uint32_t)nkeys;
+    return;
+  }
+  const uint32_t b = t / sp.S, s = t - b * sp.S;
+  sstart[t] = nch[b] ? offs[cbase[b] * sp.S + s * nch[b]] : binlo[b];
 }
 
 // Forced threshold index of global bucket beta: the last bucket of a range
@@ -210,107 +441,125 @@ __device__ inline uint32_t forced_kf(uint64_t beta, uint32_t maxoff, uint32_t co
   return maxoff >= g.t_hi ? 3u : (maxoff >= g.t_lo ? 2u : 1u);
 }
 
-__global__ __launch_bounds__(kL2Threads) void k_l2_sort(
-    const uint64_t* __restrict__ tk, const uint32_t* __restrict__ tv,
-    const uint64_t* __restrict__ ts, LayerGeom g, uint32_t nbins, uint32_t groups,
-    const uint32_t* __restrict__ offs, uint64_t* __restrict__ ok, Rec* __restrict__ items,
-    uint32_t* __restrict__ bstart) {
-  __shared__ uint32_t hist[kDigitsPerBin];
-  __shared__ uint32_t maxoff[kBucketsPerBin];
-  __shared__ uint32_t wsum[kL2Threads / 64];
-  const uint32_t bin = blockIdx.x;
-  const uint64_t lo = offs[(size_t)bin * groups];
-  const uint64_t hi = bin + 1 < nbins ? offs[(size_t)(bin + 1) * groups] : g.nkeys;
-  const uint64_t bbase = (uint64_t)bin * kBucketsPerBin;
-  for (uint32_t i = threadIdx.x; i < kDigitsPerBin; i += kL2Threads) hist[i] = 0;
-  for (uint32_t i = threadIdx.x; i < kBucketsPerBin; i += kL2Threads) maxoff[i] = 0;
+// Level 3: one workgroup per sub-bin. The item stream holds, per bucket, a
+// header and its records ordered by chunk (rank); the sub-bin's items form
+// one contiguous block starting at item sstart[g] + 64 g.
+__global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict__ in,
+                                                        LayerGeom g, SortPlan sp,
+                                                        const uint32_t* __restrict__ sstart,
+                                                        Rec* __restrict__ items,
+                                                        uint32_t* __restrict__ bstart) {
+  __shared__ uint32_t dcur[3 * kSubBuckets + 1];
+  __shared__ uint32_t maxoff[kSubBuckets];
+  __shared__ uint32_t wsum[kL3Threads / 64 + 2];
+  extern __shared__ uint4 stage[];  // kL3Cap items
+  const uint32_t sb = blockIdx.x;
+  const uint32_t lo = sstart[sb], hi = sstart[sb + 1], n = hi - lo;
+  const uint64_t beta0 = (uint64_t)sb * kSubBuckets;
+  const uint32_t nbk = (uint32_t)(g.nbuckets - beta0 < kSubBuckets ? g.nbuckets - beta0 : kSubBuckets);
+  const uint32_t sub_in_bin = sb % sp.S;
+  const uint32_t slot0 = sub_in_bin * kSubSlots;
+  for (uint32_t i = threadIdx.x; i < 3 * kSubBuckets; i += kL3Threads) dcur[i] = 0;
+  for (uint32_t i = threadIdx.x; i < kSubBuckets; i += kL3Threads) maxoff[i] = 0;
   __syncthreads();
-  for (uint64_t i = lo + threadIdx.x; i < hi; i += kL2Threads) {
-    const uint64_t slot = ts[i];
-    const uint32_t b = (uint32_t)((slot >> 6) - bbase);
-    const uint32_t o = (uint32_t)slot & 63u;
-    atomicAdd(&hist[b * 3u + rank_of(o, g)], 1u);
-    atomicMax(&maxoff[b], o);
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += kL3Threads) {
+    const uint32_t sl = in[i].w - slot0;
+    const uint32_t bl = sl >> 6, o = sl & 63u;
+    atomicAdd(&dcur[bl * 3 + rank_of(o, g)], 1u);
+    atomicMax(&maxoff[bl], o);
   }
   __syncthreads();
-  // exclusive scan of the 6144 digit counts, 12 per thread
-  constexpr int kPer = kDigitsPerBin / kL2Threads;
-  uint32_t loc[kPer];
-  uint32_t tot = 0;
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    loc[k] = hist[threadIdx.x * kPer + k];
-    tot += loc[k];
+  {  // exclusive scan of the 192 digit counts
+    uint32_t x = 0;
+    const uint32_t t = threadIdx.x;
+    if (t < 3 * kSubBuckets) x = dcur[t];
+    __syncthreads();
+    const uint32_t run = block_exclusive_scan<kL3Threads>(x, wsum, nullptr);
+    if (t < 3 * kSubBuckets) dcur[t] = run;
+    if (t == 0) dcur[3 * kSubBuckets] = n;
+    __syncthreads();
   }
-  uint32_t run = block_exclusive_scan<kL2Threads>(tot, wsum, nullptr);
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    hist[threadIdx.x * kPer + k] = run;
-    run += loc[k];
+  const bool fits = n + nbk <= kL3Cap;
+  Rec* gout = items + lo + beta0;
+  // headers and bucket starts
+  for (uint32_t bl = threadIdx.x; bl < nbk; bl += kL3Threads) {
+    const uint32_t first = dcur[3 * bl];
+    const uint32_t count = dcur[3 * bl + 3] - first;
+    const uint32_t c0 = dcur[3 * bl + 1] - first, c1 = dcur[3 * bl + 2] - dcur[3 * bl + 1];
+    const uint32_t kf = forced_kf(beta0 + bl, maxoff[bl], count, g);
+    bstart[beta0 + bl] = lo + first;
+    const uint4 hd = make_uint4(count, kf, c0, c1);
+    if (fits)
+      stage[first + bl] = hd;
+    else
+      reinterpret_cast<uint4*>(gout)[first + bl] = hd;
   }
+  if (sb + 1 == sp.nsub && threadIdx.x == 0) bstart[g.nbuckets] = (uint32_t)g.nkeys;
   __syncthreads();
-  // bucket starts and bucket headers
-  for (uint32_t b = threadIdx.x; b < kBucketsPerBin; b += kL2Threads) {
-    const uint64_t beta = bbase + b;
-    if (beta >= g.nbuckets) continue;
-    const uint32_t first = hist[3 * b];
-    const uint32_t next = (b + 1 < kBucketsPerBin) ? hist[3 * b + 3] : (uint32_t)(hi - lo);
-    const uint32_t count = next - first;
-    bstart[beta] = (uint32_t)(lo + first);
-    Rec hd;
-    hd.c = (uint64_t)count | ((uint64_t)forced_kf(beta, maxoff[b], count, g) << 32);
-    // records per chunk: rank 0 (inserted first) and rank 1; rank 2 is the rest
-    hd.meta = (uint64_t)(hist[3 * b + 1] - first) | ((uint64_t)(hist[3 * b + 2] - hist[3 * b + 1]) << 32);
-    items[lo + first + beta] = hd;
-  }
-  if (bin + 1 == nbins && threadIdx.x == 0) bstart[g.nbuckets] = (uint32_t)hi;
-  __syncthreads();
-  for (uint64_t i = lo + threadIdx.x; i < hi; i += kL2Threads) {
-    const uint64_t key = tk[i];
-    const uint64_t slot = ts[i];
-    const uint32_t o = (uint32_t)slot & 63u;
+  // records: key, value | offset << 32 | rank << 40
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += kL3Threads) {
+    const uint4 r = in[i];
+    const uint32_t sl = r.w - slot0;
+    const uint32_t bl = sl >> 6, o = sl & 63u;
     const uint32_t rk = rank_of(o, g);
-    const uint64_t beta = slot >> 6;
-    const uint32_t d = (uint32_t)(beta - bbase) * 3u + rk;
-    const uint64_t pos = lo + atomicAdd(&hist[d], 1u);
-    ok[pos] = key;
-    Rec rc;
-    rc.c = row_of(key, g);
-    rc.meta = (uint64_t)tv[i] | ((uint64_t)o << 32) | ((uint64_t)rk << 40);
-    items[pos + beta + 1] = rc;
+    const uint32_t pos = atomicAdd(&dcur[bl * 3 + rk], 1u) + bl + 1;
+    const uint4 item = make_uint4(r.x, r.y, r.z, o | (rk << 8));
+    if (fits)
+      stage[pos] = item;
+    else
+      reinterpret_cast<uint4*>(gout)[pos] = item;
   }
+  if (!fits) return;
+  __syncthreads();
+  uint4* go = reinterpret_cast<uint4*>(gout);
+  for (uint32_t j = threadIdx.x; j < n + nbk; j += kL3Threads) go[j] = stage[j];
 }
 
 hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
-  const uint64_t per_group = (a.g.nkeys + a.groups - 1) / a.groups;
-  const size_t hist_bytes = (size_t)a.nbins * sizeof(uint32_t);
-  k_l1_hist<<<a.groups, kL1Threads, hist_bytes, s>>>(a.keys, a.g, a.nbins, a.groups,
-                                                     per_group, a.counts);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = scan_exclusive(a.counts, (size_t)a.nbins * a.groups, a.scan_tmp, s);
-  if (e != hipSuccess) return e;
+  const SortPlan& sp = a.plan;
+  const uint64_t n = a.g.nkeys;
+  if (n == 0) return hipErrorInvalidValue;
+  hipError_t e;
+  k_p1_hist<<<sp.G1, kPartThreads, (size_t)sp.nb1 * 4, s>>>(a.keys, a.g, sp, a.counts1);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = scan_exclusive(a.counts1, (size_t)sp.nb1 * sp.G1, a.scan_tmp, s)) != hipSuccess) return e;
+  const size_t lds1 = part_lds_bytes(sp.nb1);
   switch (a.vbytes) {
     case 1:
-      k_l1_scatter<uint8_t><<<a.groups, kL1Threads, hist_bytes, s>>>(
-          a.keys, (const uint8_t*)a.vals, a.g, a.nbins, a.groups, per_group, a.counts,
-          a.mask_values, a.filter, a.fp_salt, a.tmp_keys, a.tmp_vals, a.tmp_slot);
+      k_p1_scatter<uint8_t><<<sp.G1, kPartThreads, lds1, s>>>(
+          a.keys, (const uint8_t*)a.vals, a.g, sp, a.counts1, a.mask_values, a.filter,
+          a.fp_salt, a.p1);
       break;
     case 2:
-      k_l1_scatter<uint16_t><<<a.groups, kL1Threads, hist_bytes, s>>>(
-          a.keys, (const uint16_t*)a.vals, a.g, a.nbins, a.groups, per_group, a.counts,
-          a.mask_values, a.filter, a.fp_salt, a.tmp_keys, a.tmp_vals, a.tmp_slot);
+      k_p1_scatter<uint16_t><<<sp.G1, kPartThreads, lds1, s>>>(
+          a.keys, (const uint16_t*)a.vals, a.g, sp, a.counts1, a.mask_values, a.filter,
+          a.fp_salt, a.p1);
       break;
     default:
-      k_l1_scatter<uint32_t><<<a.groups, kL1Threads, hist_bytes, s>>>(
-          a.keys, (const uint32_t*)a.vals, a.g, a.nbins, a.groups, per_group, a.counts,
-          a.mask_values, a.filter, a.fp_salt, a.tmp_keys, a.tmp_vals, a.tmp_slot);
+      k_p1_scatter<uint32_t><<<sp.G1, kPartThreads, lds1, s>>>(
+          a.keys, (const uint32_t*)a.vals, a.g, sp, a.counts1, a.mask_values, a.filter,
+          a.fp_salt, a.p1);
       break;
   }
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  k_l2_sort<<<a.nbins, kL2Threads, 0, s>>>(a.tmp_keys, a.tmp_vals, a.tmp_slot, a.g, a.nbins,
-                                           a.groups, a.counts, a.out_keys, a.out_rec, a.bstart);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_p2_plan<<<1, kPartThreads, 0, s>>>(a.counts1, sp, n, a.binlo, a.nch, a.cbase);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t n2 = (size_t)sp.U2 * sp.S;
+  if ((e = hipMemsetAsync(a.counts2, 0, (n2 + 1) * 4, s)) != hipSuccess) return e;
+  k_p2_hist<<<sp.U2, kPartThreads, (size_t)sp.S * 4, s>>>(a.p1, sp, a.binlo, a.nch, a.cbase,
+                                                          a.counts2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = scan_exclusive(a.counts2, n2, a.scan_tmp, s)) != hipSuccess) return e;
+  k_p2_scatter<<<sp.U2, kPartThreads, part_lds_bytes(sp.S), s>>>(a.p1, sp, a.binlo, a.nch,
+                                                                 a.cbase, a.counts2, a.p2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_p2_starts<<<(sp.nsub + 256) / 256, 256, 0, s>>>(sp, n, a.binlo, a.nch, a.cbase, a.counts2,
+                                                     a.sstart);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  (void)hipFuncSetAttribute((const void*)k_p3_sort, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(kL3Cap * sizeof(uint4)));
+  k_p3_sort<<<sp.nsub, kL3Threads, kL3Cap * sizeof(uint4), s>>>(a.p2, a.g, sp, a.sstart,
+                                                                a.out_rec, a.bstart);
   return hipGetLastError();
 }
 
@@ -392,7 +641,7 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
     if (!active && next + rank < r1) {
       const uint32_t t = next + rank;
       const uint4 r = t + 1 < kStageItems ? R.stage[t + 1] : rec4[hq + 1 + t];
-      c = (uint64_t)r.x | ((uint64_t)r.y << 32);
+      c = row_of((uint64_t)r.x | ((uint64_t)r.y << 32), a.g);
       v = r.z;
       i = 64u * q + (r.w & 63u);
       active = true;
@@ -922,26 +1171,26 @@ hipError_t struct_offsets(const uint32_t* off, const LayerGeom& g, uint32_t* out
   return hipGetLastError();
 }
 
-__global__ void k_gather(const uint64_t* __restrict__ sorted_keys, const Rec* __restrict__ rec,
-                         const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ off,
-                         uint64_t B, uint64_t* __restrict__ nk, uint32_t* __restrict__ nv) {
+__global__ void k_gather(const Rec* __restrict__ rec, const uint32_t* __restrict__ bstart,
+                         const uint32_t* __restrict__ off, uint64_t B,
+                         uint64_t* __restrict__ nk, uint32_t* __restrict__ nv) {
   const uint64_t beta = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (beta >= B) return;
   const uint32_t o = off[beta];
   const uint32_t cnt = off[beta + 1] - o;
   const uint32_t src = bstart[beta + 1] - cnt;
   for (uint32_t j = 0; j < cnt; ++j) {
-    nk[o + j] = sorted_keys[src + j];
-    nv[o + j] = meta_value(rec[src + j + beta + 1].meta);
+    const Rec r = rec[src + j + beta + 1];
+    nk[o + j] = r.c;
+    nv[o + j] = meta_value(r.meta);
   }
 }
 
-hipError_t gather_bumped(const uint64_t* sorted_keys, const Rec* rec, const uint32_t* bstart,
-                         const uint32_t* off, uint64_t B, uint64_t* next_keys,
-                         uint32_t* next_vals, hipStream_t s) {
+hipError_t gather_bumped(const Rec* rec, const uint32_t* bstart, const uint32_t* off, uint64_t B,
+                         uint64_t* next_keys, uint32_t* next_vals, hipStream_t s) {
   if (B == 0) return hipSuccess;
-  k_gather<<<(unsigned)((B + 255) / 256), 256, 0, s>>>(sorted_keys, rec, bstart, off, B,
-                                                       next_keys, next_vals);
+  k_gather<<<(unsigned)((B + 255) / 256), 256, 0, s>>>(rec, bstart, off, B, next_keys,
+                                                       next_vals);
   return hipGetLastError();
 }
 
