@@ -819,74 +819,99 @@ hipError_t solve_layer(const SolveArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Back-substitution: one lane per range, from the range end down
+// Back-substitution: a group of RG lanes per range, one lane per value column
 // ---------------------------------------------------------------------------
-template <int RMAX>
-__global__ __launch_bounds__(256) void k_backsub(const uint64_t* __restrict__ rowsC,
-                                                 const uint32_t* __restrict__ rowsV,
-                                                 const uint64_t* __restrict__ occ, LayerGeom g,
-                                                 uint64_t* __restrict__ W,
-                                                 const uint32_t* __restrict__ bnd) {
-  const uint64_t rho = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (rho >= g.nranges) return;
-  const uint32_t j = find_struct(g.range_base, g.J, rho);
-  const uint64_t B = g.bucket_base[j + 1] - g.bucket_base[j];
-  const uint64_t R = g.range_base[j + 1] - g.range_base[j];
-  const uint64_t lr = rho - g.range_base[j];
-  const uint64_t fb = g.bucket_base[j] + lr * B / R;
-  const uint64_t lb = g.bucket_base[j] + (lr + 1) * B / R;
-  const uint32_t r = g.rbits[j];
-  const uint64_t wb = g.word_base[j], bb = g.bucket_base[j];  // block k at wb + (k-bb)*r
-  uint64_t win[RMAX];  // bit j of win[col] = column col of Z[i+1+j]
+// From the range end down, per 64-slot block: the group loads the block's
+// rows, values and occupancy word into LDS (the next block's loads are in
+// flight meanwhile), then every lane runs the block's 64 slots for its
+// column: Z[i] = V[i] xor parity(C[i] >> 1 AND the next 63 values), kept as a
+// 64-bit window per column; free slots are 0.
+template <int RG>
+__global__ __launch_bounds__(64) void k_backsub(const uint64_t* __restrict__ rowsC,
+                                                const uint32_t* __restrict__ rowsV,
+                                                const uint64_t* __restrict__ occ, LayerGeom g,
+                                                uint64_t* __restrict__ W,
+                                                const uint32_t* __restrict__ bnd) {
+  constexpr int NG = 64 / RG;   // ranges per wave
+  constexpr int PER = 64 / RG;  // slots each lane loads per block
+  __shared__ uint64_t sc[2][NG][64];
+  __shared__ uint32_t sv[2][NG][64];
+  __shared__ uint64_t so[2][NG];
+  const uint32_t lane = threadIdx.x, grp = lane / RG, col = lane % RG;
+  const uint64_t rho = (uint64_t)blockIdx.x * NG + grp;
+  const bool valid = rho < g.nranges;
+  uint32_t r = 0;
+  uint64_t fb = 0, lb = 0, wb = 0, bb = 0;
+  if (valid) {
+    const uint32_t j = find_struct(g.range_base, g.J, rho);
+    const uint64_t B = g.bucket_base[j + 1] - g.bucket_base[j];
+    const uint64_t R = g.range_base[j + 1] - g.range_base[j];
+    const uint64_t lr = rho - g.range_base[j];
+    bb = g.bucket_base[j];
+    fb = bb + lr * B / R;
+    lb = bb + (lr + 1) * B / R;
+    r = g.rbits[j];
+    wb = g.word_base[j];  // block k of the structure at wb + (k - bb) * r
+  }
+  const uint32_t nblk = (uint32_t)(lb - fb);
+  uint32_t maxblk = nblk;
+  for (int d = 32; d >= 1; d >>= 1) maxblk = max(maxblk, (uint32_t)__shfl_xor((int)maxblk, d, 64));
+  uint64_t win = 0;  // bit t = value of this column at slot i+1+t
+  if (bnd && valid) {
+    // the 63 slots after the range hold known values (final-layer segments)
+    for (uint32_t t = 0; t < 63; ++t) win |= (uint64_t)((bnd[rho * 64 + t] >> col) & 1u) << t;
+  }
+  uint64_t pc[PER];
+  uint32_t pv[PER];
+  uint64_t po = 0;
+#define BURR_BS_LOAD(t)                                                  \
+  if ((t) < nblk) {                                                      \
+    const uint64_t base = (lb - 1 - (t)) * 64;                           \
+    _Pragma("unroll") for (int e = 0; e < PER; ++e) {                    \
+      pc[e] = rowsC[base + col + e * RG];                                \
+      pv[e] = rowsV[base + col + e * RG];                                \
+    }                                                                    \
+    if (col == 0) po = occ[lb - 1 - (t)];                                \
+  }
+  BURR_BS_LOAD(0u)
+  for (uint32_t t = 0; t < maxblk; ++t) {
+    const uint32_t buf = t & 1u;
 #pragma unroll
-  for (int col = 0; col < RMAX; ++col) win[col] = 0;
-  if (bnd) {
-    // rows near the end may reach the 63 slots after it: start from their values
-    for (uint32_t t = 0; t < 63; ++t) {
-      const uint32_t z = bnd[rho * 64 + t];
-#pragma unroll
-      for (int col = 0; col < RMAX; ++col) win[col] |= (uint64_t)((z >> col) & 1u) << t;
+    for (int e = 0; e < PER; ++e) {
+      sc[buf][grp][col + e * RG] = pc[e];
+      sv[buf][grp][col + e * RG] = pv[e];
+    }
+    if (col == 0) so[buf][grp] = po;
+    __syncthreads();
+    BURR_BS_LOAD(t + 1)
+    if (t < nblk) {
+      const uint64_t oc = so[buf][grp];
+      uint64_t out = 0;
+#pragma unroll 8
+      for (int tt = 63; tt >= 0; --tt) {
+        const uint64_t C = sc[buf][grp][tt] >> 1;
+        const uint32_t V = sv[buf][grp][tt];
+        const uint32_t zf = ((V >> col) ^ (uint32_t)__popcll(C & win)) & 1u;
+        const uint64_t z = ((oc >> tt) & 1ull) ? (uint64_t)zf : 0ull;
+        win = (win << 1) | z;
+        out |= z << tt;
+      }
+      const uint64_t k = lb - 1 - t;
+      if (col < r) W[wb + (k - bb) * r + col] = out;
     }
   }
-  for (uint64_t k = lb; k-- > fb;) {
-    const uint64_t oc = occ[k];
-    uint64_t out[RMAX];
-#pragma unroll
-    for (int col = 0; col < RMAX; ++col) out[col] = 0;
-    for (int tt = 63; tt >= 0; --tt) {
-      uint32_t z = 0;
-      if ((oc >> tt) & 1ull) {
-        const uint64_t slot = k * 64 + (uint64_t)tt;
-        const uint64_t C = rowsC[slot] >> 1;
-        const uint32_t V = rowsV[slot];
-#pragma unroll
-        for (int col = 0; col < RMAX; ++col)
-          if ((uint32_t)col < r)
-            z |= ((V >> col) ^ (uint32_t)__popcll(C & win[col])) & 1u ? (1u << col) : 0u;
-      }
-#pragma unroll
-      for (int col = 0; col < RMAX; ++col) {
-        if ((uint32_t)col < r) {
-          const uint64_t b = (z >> col) & 1u;
-          win[col] = (win[col] << 1) | b;
-          out[col] |= b << tt;
-        }
-      }
-    }
-    for (uint32_t col = 0; col < r && col < (uint32_t)RMAX; ++col)
-      W[wb + (k - bb) * r + col] = out[col];
-  }
+#undef BURR_BS_LOAD
 }
 
 hipError_t back_substitute(const uint64_t* rowsC, const uint32_t* rowsV, const uint64_t* occ,
                            const LayerGeom& g, uint64_t* W, hipStream_t s, const uint32_t* bnd) {
-  const unsigned blocks = (unsigned)((g.nranges + 255) / 256);
+  if (g.nranges == 0) return hipSuccess;
   if (g.r <= 8)
-    k_backsub<8><<<blocks, 256, 0, s>>>(rowsC, rowsV, occ, g, W, bnd);
+    k_backsub<8><<<(unsigned)((g.nranges + 7) / 8), 64, 0, s>>>(rowsC, rowsV, occ, g, W, bnd);
   else if (g.r <= 16)
-    k_backsub<16><<<blocks, 256, 0, s>>>(rowsC, rowsV, occ, g, W, bnd);
+    k_backsub<16><<<(unsigned)((g.nranges + 3) / 4), 64, 0, s>>>(rowsC, rowsV, occ, g, W, bnd);
   else
-    k_backsub<32><<<blocks, 256, 0, s>>>(rowsC, rowsV, occ, g, W, bnd);
+    k_backsub<32><<<(unsigned)((g.nranges + 1) / 2), 64, 0, s>>>(rowsC, rowsV, occ, g, W, bnd);
   return hipGetLastError();
 }
 
@@ -1057,77 +1082,79 @@ hipError_t final_merge(const FinalArgs& a, uint64_t max_segments, hipStream_t s)
   return hipSuccess;
 }
 
-// Per segment, back-substitute with the 63 values after the segment unknown:
-// every slot's value is z0 (zero boundary) xor the boundary values selected
-// by a 63-bit dependence word X. Only the first 63 slots' (z0, X) are kept.
+// Per segment (one wave), back-substitute with the 63 values after the
+// segment unknown: every slot's value is z0 (zero boundary) xor the boundary
+// values selected by a 63-bit dependence word X. Lane b < 63 carries bit b
+// of X through a 64-bit window (bit k = X[i+1+k] bit b; past the segment end
+// X[end+k] is the unit word e_k), lane c < r carries column c of z0; the
+// first 63 slots' words are assembled with ballots.
 __global__ __launch_bounds__(64) void k_final_partial(FinalArgs a) {
-  __shared__ uint32_t zwin[64 * 64];
-  __shared__ uint64_t xwin[64 * 64];
+  __shared__ uint64_t sc[64];
+  __shared__ uint32_t sv[64];
   const LayerGeom g = a.g;
   const uint32_t lane = threadIdx.x;
-  const uint64_t p = (uint64_t)blockIdx.x * 64 + lane;
+  const uint64_t p = blockIdx.x;
   if (p >= g.nranges) return;
   const SegBounds sb = seg_bounds(p, g);
   const uint64_t start = sb.start, end = sb.end;
-  for (uint64_t i = end; i-- > start;) {
-    uint32_t z = 0;
-    uint64_t X = 0;
-    if ((a.occ[i / 64] >> (i % 64)) & 1ull) {
-      z = a.rowsV[i];
-      uint64_t bits = a.rowsC[i] >> 1;
-      while (bits) {
-        const uint32_t k = (uint32_t)__builtin_ctzll(bits) + 1;
-        bits &= bits - 1;
-        const uint64_t slot = i + k;
-        if (slot < end) {
-          z ^= zwin[(slot % 64) * 64 + lane];
-          X ^= xwin[(slot % 64) * 64 + lane];
-        } else {
-          X ^= 1ull << (slot - end);
+  const uint32_t r = g.rbits[sb.j];
+  const uint64_t zmask = r >= 32 ? 0xffffffffull : ((1ull << r) - 1);
+  uint64_t wx = lane < 63 ? (1ull << lane) : 0ull;
+  uint64_t wz = 0;
+  for (uint64_t k = end / 64; k-- > start / 64;) {
+    sc[lane] = a.rowsC[k * 64 + lane];
+    sv[lane] = a.rowsV[k * 64 + lane];
+    const uint64_t oc = a.occ[k];
+    __syncthreads();
+    for (int tt = 63; tt >= 0; --tt) {
+      const uint64_t C = sc[tt] >> 1;
+      const bool occd = (oc >> tt) & 1ull;
+      const uint64_t xb = occd ? (uint64_t)(__popcll(C & wx) & 1) : 0ull;
+      const uint32_t vbit = lane < 32 ? (sv[tt] >> lane) : 0u;
+      const uint64_t zb = occd ? (uint64_t)((vbit ^ (uint32_t)__popcll(C & wz)) & 1u) : 0ull;
+      wx = (wx << 1) | xb;
+      wz = (wz << 1) | zb;
+      const uint64_t i = k * 64 + (uint64_t)tt;
+      if (i - start < 63) {
+        const uint64_t X = __ballot(xb != 0) & 0x7fffffffffffffffull;
+        const uint64_t Z = __ballot(zb != 0) & zmask;
+        if (lane == 0) {
+          a.xfirst[p * 64 + (i - start)] = X;
+          a.z0first[p * 64 + (i - start)] = (uint32_t)Z;
         }
       }
     }
-    zwin[(i % 64) * 64 + lane] = z;
-    xwin[(i % 64) * 64 + lane] = X;
-    if (i - start < 63) {
-      a.z0first[p * 64 + (i - start)] = z;
-      a.xfirst[p * 64 + (i - start)] = X;
-    }
+    __syncthreads();
   }
 }
 
-// One workgroup per structure, from its last segment down: the boundary of
+// One wave per structure, from its last segment down: the boundary of
 // segment p-1 is the true value of segment p's first 63 slots = z0 xor (X
-// applied to segment p's boundary).
+// applied to segment p's boundary). Lane t holds boundary value t; column c
+// of the boundary is gathered into one word with a ballot, so X applied to
+// it is one AND and a parity per column.
 __global__ __launch_bounds__(64) void k_final_scan(FinalArgs a) {
-  __shared__ uint32_t b[64];
   const uint32_t t = threadIdx.x;
   const LayerGeom g = a.g;
   const uint32_t j = blockIdx.x;
   const uint64_t first = g.range_base[j], last = g.range_base[j + 1];
-  b[t] = 0;  // nothing lies past the structure's last segment
-  __syncthreads();
+  const uint32_t r = g.rbits[j];
+  uint32_t b = 0;  // nothing lies past the structure's last segment
   for (uint64_t p = last; p-- > first;) {
-    a.bnd[p * 64 + t] = b[t];
-    uint32_t z = 0;
-    if (t < 63) {
-      z = a.z0first[p * 64 + t];
-      uint64_t X = a.xfirst[p * 64 + t];
-      while (X) {
-        const uint32_t k = (uint32_t)__builtin_ctzll(X);
-        X &= X - 1;
-        z ^= b[k];
-      }
+    a.bnd[p * 64 + t] = b;
+    const uint64_t X = t < 63 ? a.xfirst[p * 64 + t] : 0ull;
+    uint32_t nb = t < 63 ? a.z0first[p * 64 + t] : 0u;
+    for (uint32_t c = 0; c < r; ++c) {
+      const uint64_t col = __ballot(((b >> c) & 1u) != 0) & 0x7fffffffffffffffull;
+      nb ^= (uint32_t)(__popcll(X & col) & 1) << c;
     }
-    __syncthreads();
-    b[t] = z;
-    __syncthreads();
+    b = t < 63 ? nb : 0u;
   }
 }
 
 hipError_t final_boundaries(const FinalArgs& a, hipStream_t s) {
   const uint64_t P = a.g.nranges;
-  k_final_partial<<<(unsigned)((P + 63) / 64), 64, 0, s>>>(a);
+  k_final_partial<<<(unsigned)P, 64, 0, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_final_scan<<<a.g.J, 64, 0, s>>>(a);
