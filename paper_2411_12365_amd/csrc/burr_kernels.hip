@@ -617,13 +617,19 @@ struct WaveRing {
 
 __device__ inline uint64_t wave_ballot(bool p) { return __ballot(p); }
 
+#ifndef BURR_SOLVE_K
+#define BURR_SOLVE_K 4
+#endif
+constexpr int kSolveK = BURR_SOLVE_K;  // elimination steps per loop trip
+
 // Inserts records [r0, r1) of the staged bucket q. Returns 0 if the set was
 // consistent, 1 if an inconsistency was met (its rows are removed again), or
-// 2 on an internal error.
+// 2 on an internal error. Each loop trip: lanes without a row take the next
+// records, every lane makes up to kSolveK XOR-and-shift steps against the
+// ring (stopping at an empty slot), then the lanes at an empty slot claim it.
 __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint4* rec4,
                                      uint32_t hq, uint32_t q, uint32_t r0, uint32_t r1,
-                                     uint64_t P0, uint32_t limit, uint64_t rho,
-                                     uint64_t& steps) {
+                                     uint32_t limit, uint64_t& steps) {
   const uint32_t lane = threadIdx.x;
   if (lane < 2) R.placed[lane] = 0;
   __syncthreads();
@@ -640,7 +646,11 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)freem, 0u));
     if (!active && next + rank < r1) {
       const uint32_t t = next + rank;
-      const uint4 r = t + 1 < kStageItems ? R.stage[t + 1] : rec4[hq + 1 + t];
+      uint4 r;
+      if (t + 1 < kStageItems)
+        r = R.stage[t + 1];
+      else
+        r = rec4[hq + 1 + t];  // bucket larger than the stage (rare)
       c = row_of((uint64_t)r.x | ((uint64_t)r.y << 32), a.g);
       v = r.z;
       i = 64u * q + (r.w & 63u);
@@ -653,45 +663,41 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
       result = 2;
       break;
     }
-    // one elimination step
-    const uint32_t p = i & (kRing - 1);
-    const uint64_t row = R.c[p];
-    const uint32_t rv = R.v[p];
-    bool conflict = false;
-    if (active) {
-      if (row == 0) {
-        if (i >= limit && !(a.spillC && i < limit + 64u)) {
-          active = false;  // unreachable: a kept row crossing the range end
-          result = 2;
-        } else {
-          const uint64_t old = atomicCAS((unsigned long long*)&R.c[p], 0ull,
-                                         (unsigned long long)c);
-          if (old == 0) {
-            R.v[p] = v;
-            atomicOr((unsigned long long*)&R.placed[p >> 6], 1ull << (p & 63));
-            if (i < limit) {
-              a.rowsC[P0 + i] = c;
-              a.rowsV[P0 + i] = v;
-            } else {
-              a.spillC[rho * 64 + (i - limit)] = c;
-              a.spillV[rho * 64 + (i - limit)] = v;
-            }
-            active = false;
-          }
-          // otherwise another lane took the slot: step against its row next time
-        }
+    // kSolveK elimination steps; a lane stops at an empty slot
+    bool at_empty = false, conflict = false;
+#pragma unroll
+    for (int u = 0; u < kSolveK; ++u) {
+      const uint32_t p = i & (kRing - 1);
+      const uint64_t row = R.c[p];
+      const uint32_t rv = R.v[p];
+      const bool go = active && !at_empty;
+      at_empty = at_empty || (go && row == 0);
+      const bool step = go && row != 0;
+      const uint64_t cx = c ^ row;
+      const uint32_t vx = v ^ rv;
+      const bool zero = step && cx == 0;
+      const uint32_t j = (uint32_t)__builtin_ctzg(cx, 64);
+      steps += step ? 1u : 0u;
+      conflict = conflict || (zero && vx != 0);
+      active = active && !zero;
+      const bool adv = step && !zero;
+      c = adv ? (cx >> j) : c;
+      v = step ? vx : v;
+      i = adv ? i + j : i;
+    }
+    if (at_empty) {
+      const uint32_t p = i & (kRing - 1);
+      if (i >= limit && !(a.spillC && i < limit + 64u)) {
+        active = false;  // unreachable: a kept row crossing the range end
+        result = 2;
       } else {
-        c ^= row;
-        v ^= rv;
-        ++steps;
-        if (c == 0) {
+        const uint64_t old = atomicCAS((unsigned long long*)&R.c[p], 0ull, (unsigned long long)c);
+        if (old == 0) {
+          R.v[p] = v;
+          atomicOr((unsigned long long*)&R.placed[p >> 6], 1ull << (p & 63));
           active = false;
-          conflict = v != 0;
-        } else {
-          const uint32_t j = (uint32_t)__builtin_ctzll(c);
-          c >>= j;
-          i += j;
         }
+        // otherwise another lane took the slot: step against its row next time
       }
     }
     if (__any(conflict)) {
@@ -713,6 +719,20 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
   return result == 2 ? 2u : (bad ? 1u : 0u);
 }
 
+// Publishes a released ring half: its 64 rows, values and occupancy word go
+// to the layer's row arrays (or, past the range end, to the segment's spill
+// buffer) as one coalesced block.
+__device__ inline void release_half(WaveRing& R, const SolveArgs& a, uint32_t hb,
+                                    uint64_t* rowsC, uint32_t* rowsV, uint64_t* occw) {
+  const uint32_t lane = threadIdx.x;
+  const uint64_t row = R.c[hb + lane];
+  const uint64_t word = wave_ballot(row != 0);
+  rowsC[lane] = row;
+  rowsV[lane] = R.v[hb + lane];
+  if (lane == 0) *occw = word;
+  (void)a;
+}
+
 __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
   __shared__ WaveRing R;
   const LayerGeom g = a.g;
@@ -726,7 +746,6 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
   const uint64_t f0 = lr * B / Rn;
   const uint64_t fb = g.bucket_base[js] + f0;
   const uint32_t nq = (uint32_t)((lr + 1) * B / Rn - f0);
-  const uint64_t P0 = fb * 64;
   const uint32_t limit = 64u * nq;
   const uint32_t last_item = a.nrec - 1;
   const uint4* rec4 = reinterpret_cast<const uint4*>(a.rec);
@@ -743,11 +762,11 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
     hq = a.bstart[beta] + (uint32_t)beta;
     R.stage[lane] = nx0;
     R.stage[64 + lane] = nx1;
-    // the slots of bucket q+1 held bucket q-1: publish its occupancy, clear them
+    // the slots of bucket q+1 held bucket q-1: publish its rows, clear them
     if (q >= 1) {
       const uint32_t hb = ((q - 1) & 1u) * 64u;
-      const uint64_t word = wave_ballot(R.c[hb + lane] != 0);
-      if (lane == 0) a.occ[beta - 1] = word;
+      release_half(R, a, hb, a.rowsC + (beta - 1) * 64, a.rowsV + (beta - 1) * 64,
+                   a.occ + (beta - 1));
       R.c[hb + lane] = 0;
     }
     __syncthreads();
@@ -763,7 +782,7 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
     const uint32_t cand = keep_ranks == 3 ? count : (keep_ranks == 2 ? e2 : (keep_ranks == 1 ? e1 : 0u));
     uint32_t kept = cand, code = kf;
     if (cand > 0) {
-      uint32_t res = wave_pass(R, a, rec4, hq, q, 0, cand, P0, limit, rho, steps);
+      uint32_t res = wave_pass(R, a, rec4, hq, q, 0, cand, limit, steps);
       if (res == 1 && g.plain) {
         if (lane == 0) a.fail[js] = 1u;
         failed = true;
@@ -774,7 +793,7 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
         for (uint32_t rr = keep_ranks - 1; rr >= 1 && res != 2; --rr) {
           const uint32_t e = rr == 2 ? e2 : e1;
           if (e == failed_size) continue;  // the same set again
-          res = e ? wave_pass(R, a, rec4, hq, q, 0, e, P0, limit, rho, steps) : 0u;
+          res = e ? wave_pass(R, a, rec4, hq, q, 0, e, limit, steps) : 0u;
           if (res == 0) {
             kept = e;
             code = 3 - rr;
@@ -799,11 +818,11 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
   }
   if (!failed) {
     const uint32_t hl = ((nq - 1) & 1u) * 64u;
-    const uint64_t last = wave_ballot(R.c[hl + lane] != 0);
-    const uint64_t spill = wave_ballot(R.c[(64u - hl) + lane] != 0);
-    if (lane == 0) {
-      a.occ[fb + nq - 1] = last;
-      if (a.spill_occ) a.spill_occ[rho] = spill;
+    const uint64_t beta = fb + nq - 1;
+    release_half(R, a, hl, a.rowsC + beta * 64, a.rowsV + beta * 64, a.occ + beta);
+    if (a.spill_occ) {  // rows past the segment end (final layer)
+      release_half(R, a, 64u - hl, a.spillC + rho * 64, a.spillV + rho * 64,
+                   a.spill_occ + rho);
     }
   }
   if (a.steps) {
@@ -957,6 +976,9 @@ __global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
   const SegBounds sp = seg_bounds(p, g);
   const uint64_t lp = p - sp.first;
   if (lp % (2ull * G) != 0 || lp + G >= sp.count) return;
+  // a structure whose segment solve already failed keeps no valid rows in
+  // its unfinished buckets: nothing to merge
+  if (a.fail[sp.j]) return;
   const uint64_t R0 = p + G;
   const uint64_t lastL = R0 - 1;
   const uint64_t lastR = (lp + 2ull * G < sp.count ? p + 2ull * G : sp.first + sp.count) - 1;
@@ -1043,6 +1065,11 @@ __global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
         v ^= rv;
         if (c == 0) {
           if (v != 0) bad = true;  // inconsistent: this table size fails
+          break;
+        }
+        if (c & 1ull) {  // a stored row always has its leading bit: corrupt state
+          bad = true;
+          internal = true;
           break;
         }
         const uint32_t j = (uint32_t)__builtin_ctzll(c);
