@@ -50,6 +50,10 @@ enum {
 /* Keep the device copy of every layer's input keys (debugging, parity tests);
  * read them with burr_debug_layer_keys. */
 #define BURR_FLAG_KEEP_LAYER_KEYS 1u
+/* Allocate the build's temporary buffers for this build only instead of
+ * reusing the library's per-device workspace (kept between builds up to
+ * BURR_WORKSPACE_CACHE_BYTES bytes, default 16 GiB; see burr_release_workspaces). */
+#define BURR_FLAG_NO_WORKSPACE_CACHE 2u
 
 typedef void* (*burr_alloc_fn)(size_t bytes, void* stream, void* ctx);
 typedef void (*burr_free_fn)(void* ptr, void* stream, void* ctx);
@@ -287,6 +291,10 @@ int burr_server_get_info(burr_server* s, burr_server_info* info);
 
 /* Waits for running and pending requests, then frees every structure. */
 void burr_server_destroy(burr_server* s);
+
+/* Frees the workspaces the library keeps between builds (device memory
+ * allocated with hipMalloc). Call when no build is running. */
+void burr_release_workspaces(void);
 
 int burr_last_error(void);
 const char* burr_error_string(int code);

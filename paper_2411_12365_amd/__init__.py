@@ -25,6 +25,7 @@ BURR_SERVER_NO_DEVICE = 2
 BURR_REQ_BUILD = 1
 BURR_REQ_QUERY = 2
 BURR_FLAG_KEEP_LAYER_KEYS = 1
+BURR_FLAG_NO_WORKSPACE_CACHE = 2
 ABI_VERSION = 1
 
 _EXPORTS = ("burr_default_params", "burr_build", "burr_query", "burr_contains", "burr_free",
@@ -34,7 +35,7 @@ _EXPORTS = ("burr_default_params", "burr_build", "burr_query", "burr_contains", 
             "burr_server_default_config", "burr_server_create", "burr_server_submit_build",
             "burr_server_submit_query", "burr_server_poll", "burr_server_drain",
             "burr_server_drop", "burr_server_handle", "burr_server_get_info",
-            "burr_server_destroy")
+            "burr_server_destroy", "burr_release_workspaces")
 
 
 class BurrError(RuntimeError):
@@ -177,6 +178,8 @@ def lib():
         L.burr_server_get_info.restype = i32
         L.burr_server_destroy.argtypes = [vp]
         L.burr_server_destroy.restype = None
+        L.burr_release_workspaces.argtypes = []
+        L.burr_release_workspaces.restype = None
         L.burr_last_error.argtypes = []
         L.burr_last_error.restype = i32
         L.burr_error_string.argtypes = [i32]
@@ -421,6 +424,11 @@ def burr_estimate_build_bytes(n: int, r: int, params: Params | None = None):
     if rc != BURR_OK:
         raise BurrError(rc, "burr_estimate_build_bytes")
     return tb.value, wb.value
+
+
+def burr_release_workspaces():
+    """Free the device workspace the library keeps between builds."""
+    lib().burr_release_workspaces()
 
 
 class Server:

@@ -11,7 +11,9 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -117,9 +119,29 @@ struct burr_batch {
   std::vector<Member> members;
   std::vector<burr_handle> views;
   LayerStore layers[kMaxLayers];
-  std::vector<void*> owned;  // final-layer tables and debug key arrays
-  uint64_t table_bytes = 0;  // device bytes of codes and solution words
+  std::vector<void*> owned;  // every device allocation of the batch
+  uint64_t table_bytes = 0;  // device bytes held for tables (arena + extra allocations)
+  uint8_t* arena = nullptr;  // one allocation that the layers' tables are carved from
+  uint64_t arena_cap = 0, arena_used = 0;
   double ms_total = 0, ms_final = 0;
+
+  void* alloc(uint64_t bytes) {
+    void* p = al.get(bytes);
+    if (p) owned.push_back(p);
+    return p;
+  }
+  // table storage: from the arena while it lasts, else its own allocation
+  void* alloc_table(uint64_t bytes) {
+    bytes = (bytes + 255) & ~255ull;
+    if (arena && arena_used + bytes <= arena_cap) {
+      void* p = arena + arena_used;
+      arena_used += bytes;
+      return p;
+    }
+    void* p = alloc(bytes);
+    if (p) table_bytes += bytes;
+    return p;
+  }
 };
 
 namespace {
@@ -188,11 +210,24 @@ struct Table {
   uint32_t J() const { return (uint32_t)rbits.size(); }
 };
 
-// Reusable device workspace of one build; grows on demand (outgrown buffers
-// are released with the workspace, after every launch that used them).
+// Device workspace of a build; grows on demand. Two modes:
+//  - with the build's allocator (caller callbacks or the stream-ordered pool):
+//    outgrown buffers are released with the workspace, after every launch
+//    that used them;
+//  - kept between builds (al == nullptr, plain hipMalloc): an outgrown buffer
+//    is freed at once - reserve calls happen only while the build stream is
+//    idle (every layer ends with a stream synchronization).
 struct Workspace {
   Allocator* al;
   std::vector<void*> owned;
+  std::vector<size_t> owned_bytes;
+  uint64_t bytes = 0;           // device bytes held
+  uint8_t* host = nullptr;      // pinned staging of layer tables (host -> device)
+  size_t host_cap = 0;
+  uint32_t* hres = nullptr;     // pinned copy of the per-layer results
+  size_t hres_cap = 0;
+  uint32_t* res = nullptr;      // per-layer results: fail[J], soff[J+1], steps (u64)
+  uint64_t cap_res = 0;
   uint64_t cap_keys = 0, cap_m = 0, cap_B = 0, cap_items = 0, cap_scan = 0;
   uint64_t cap_seg = 0, cap_tab = 0, cap_J = 0, cap_c1 = 0, cap_c2 = 0, cap_plan = 0;
   uint64_t* keysA = nullptr;  // next layer's keys
@@ -216,15 +251,78 @@ struct Workspace {
 
   explicit Workspace(Allocator* a) : al(a) {}
   ~Workspace() {
-    for (void* p : owned) al->put(p);
+    for (void* p : owned) {
+      if (al)
+        al->put(p);
+      else
+        (void)hipFree(p);
+    }
+    if (host) (void)hipHostFree(host);
+    if (hres) (void)hipHostFree(hres);
   }
   template <typename T>
   bool alloc(T*& ptr, uint64_t count) {
-    ptr = (T*)al->get(count * sizeof(T));
-    if (!ptr) return false;
-    owned.push_back(ptr);
+    const size_t b = ((count * sizeof(T)) + 255) & ~(size_t)255;
+    if (!al) {  // kept between builds: replace the outgrown buffer
+      for (size_t k = 0; ptr && k < owned.size(); ++k)
+        if (owned[k] == (void*)ptr) {
+          (void)hipFree(owned[k]);
+          bytes -= owned_bytes[k];
+          owned.erase(owned.begin() + k);
+          owned_bytes.erase(owned_bytes.begin() + k);
+          break;
+        }
+      void* p = nullptr;
+      if (hipMalloc(&p, b ? b : 256) != hipSuccess) {
+        ptr = nullptr;
+        return false;
+      }
+      ptr = (T*)p;
+    } else {
+      ptr = (T*)al->get(b);
+      if (!ptr) return false;
+    }
+    owned.push_back((void*)ptr);
+    owned_bytes.push_back(b);
+    bytes += b;
     return true;
   }
+  // pinned host staging of at least `need` bytes
+  bool reserve_host(size_t need) {
+    if (need <= host_cap && host) return true;
+    if (host) (void)hipHostFree(host);
+    host = nullptr;
+    host_cap = std::max<size_t>(need, 1 << 16);
+    if (hipHostMalloc((void**)&host, host_cap, hipHostMallocDefault) != hipSuccess) {
+      host = nullptr;
+      host_cap = 0;
+      return false;
+    }
+    return true;
+  }
+  // fail[J] | soff[J+1] | pad | steps u64[4], on the device and pinned on the host
+  bool reserve_results(uint64_t J) {
+    const uint64_t words = 2 * J + 12;
+    if (words > cap_res || !res) {
+      cap_res = words;
+      if (!alloc(res, words)) return false;
+    }
+    if (words * 4 > hres_cap || !hres) {
+      if (hres) (void)hipHostFree(hres);
+      hres = nullptr;
+      hres_cap = words * 4;
+      if (hipHostMalloc((void**)&hres, hres_cap, hipHostMallocDefault) != hipSuccess) {
+        hres = nullptr;
+        hres_cap = 0;
+        return false;
+      }
+    }
+    fail = res;
+    soff = res + J;
+    steps = reinterpret_cast<uint64_t*>(res + 2 * J + 2);
+    return true;
+  }
+  uint64_t results_words(uint64_t J) const { return 2 * J + 10; }
   bool reserve_keys(uint64_t n) {
     if (n <= cap_keys && keysA) return true;
     cap_keys = std::max<uint64_t>(n, 1);
@@ -265,11 +363,7 @@ struct Workspace {
     }
     return reserve_scan(std::max(c1, c2) + 1);
   }
-  bool reserve_structs(uint64_t J) {
-    if (J <= cap_J && fail) return true;
-    cap_J = J;
-    return alloc(fail, J + 1) && alloc(soff, J + 1);
-  }
+  bool reserve_structs(uint64_t J) { return reserve_results(J); }
   bool reserve_table(uint64_t words) {
     if (words <= cap_tab && tab) return true;
     cap_tab = words;
@@ -287,23 +381,24 @@ void print_diag(const uint64_t* d) {
   uint64_t h[16] = {0};
   if (hipMemcpy(h, d, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess || !h[0]) return;
   fprintf(stderr,
-          "burr: lane state: code %llu range %llu structure %llu x %llu xend %llu q %llu/%llu "
-          "state %llu open %llu written %llu rend %llu kf %llu curk %llu i %llu first bucket "
-          "%llu\n",
+          "burr: wave state: code %llu range %llu structure %llu header item %llu records %llu "
+          "bucket %llu of %llu candidates %llu kept %llu threshold %llu forced %llu first "
+          "bucket %llu\n",
           (unsigned long long)h[1], (unsigned long long)h[2], (unsigned long long)h[3],
           (unsigned long long)h[4], (unsigned long long)h[5], (unsigned long long)h[6],
-          (unsigned long long)h[7], (unsigned long long)h[8], (unsigned long long)h[9],
-          (unsigned long long)h[10], (unsigned long long)h[11], (unsigned long long)h[12],
-          (unsigned long long)h[13], (unsigned long long)h[14], (unsigned long long)h[15]);
+          (unsigned long long)h[7], (unsigned long long)h[8], (unsigned long long)h[10],
+          (unsigned long long)h[11], (unsigned long long)h[12], (unsigned long long)h[15]);
 }
 
 // Uploads a table (one device buffer) and fills the geometry's pointers and totals.
 int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s) {
   const uint64_t J = t.J();
   const uint64_t words = 6 * (J + 1) + (J + 1) / 2 + 1;
-  if (!ws.reserve_table(words)) return set_error(BURR_E_NOMEM);
-  std::vector<uint64_t> host(words, 0);
-  uint64_t* h = host.data();
+  if (!ws.reserve_table(words) || !ws.reserve_host(words * 8)) return set_error(BURR_E_NOMEM);
+  // the pinned staging is reused only after the stream has passed this copy
+  // (every layer ends with a synchronization)
+  uint64_t* h = reinterpret_cast<uint64_t*>(ws.host);
+  memset(h, 0, words * 8);
   memcpy(h, t.key_off.data(), (J + 1) * 8);
   memcpy(h + (J + 1), t.span.data(), J * 8);
   memcpy(h + 2 * (J + 1), t.bucket_base.data(), (J + 1) * 8);
@@ -312,7 +407,6 @@ int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s) {
   memcpy(h + 5 * (J + 1), t.code_base.data(), (J + 1) * 8);
   memcpy(h + 6 * (J + 1), t.rbits.data(), J * 4);
   HIP_TRY(hipMemcpyAsync(ws.tab, h, words * 8, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));  // the host copy dies with this function
   g.key_off = ws.tab;
   g.span = ws.tab + (J + 1);
   g.bucket_base = ws.tab + 2 * (J + 1);
@@ -409,7 +503,7 @@ int final_attempt(burr_batch* b, Workspace& ws, const std::vector<uint32_t>& lis
     return set_error(BURR_E_NOMEM);
   rc = run_sort(ws, keys, vals, vbytes, first_layer, p.filter_mode != 0, mix64(~p.seed), g, s);
   if (rc != BURR_OK) return rc;
-  HIP_TRY(hipMemsetAsync(ws.fail, 0, (g.J + 1) * 4, s));
+  HIP_TRY(hipMemsetAsync(ws.res, 0, ws.results_words(g.J) * 4, s));
   HIP_TRY(hipMemsetAsync(ws.spill_occ, 0, g.nranges * 8, s));
   SolveArgs sa{};
   sa.rec = ws.rec;
@@ -441,14 +535,12 @@ int final_attempt(burr_batch* b, Workspace& ws, const std::vector<uint32_t>& lis
   // boundaries and back-substitution run for every listed member; the
   // words of a member that failed are never referenced
   HIP_TRY(final_boundaries(fa, s));
-  uint64_t* W = (uint64_t*)b->al.get(t.word_base.back() * 8 + 8);
+  uint64_t* W = (uint64_t*)b->alloc_table(t.word_base.back() * 8 + 8);
   if (!W) return set_error(BURR_E_NOMEM);
-  b->owned.push_back(W);
-  b->table_bytes += t.word_base.back() * 8 + 8;
   HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, ws.occ, g, W, s, ws.bnd));
-  fails.assign(g.J, 0);
-  HIP_TRY(hipMemcpyAsync(fails.data(), ws.fail, g.J * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(ws.hres, ws.res, g.J * 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  fails.assign(ws.hres, ws.hres + g.J);
   for (size_t i = 0; i < list.size(); ++i) {
     if (fails[i] >= 2) {
       fprintf(stderr, "burr: internal error %u in the final layer\n", fails[i]);
@@ -467,6 +559,73 @@ int final_attempt(burr_batch* b, Workspace& ws, const std::vector<uint32_t>& lis
 
 // Builds every member of b. Member i's keys are keys[off[i], off[i+1]), its
 // values the same range of `values` (elements of value_bytes(max r) bytes).
+// Workspaces kept between builds, per device (plain hipMalloc memory), up
+// to a total size (environment variable BURR_WORKSPACE_CACHE_BYTES, default
+// 16 GiB); burr_release_workspaces() frees them.
+constexpr int kMaxDevices = 64;
+std::mutex g_ws_mu;
+std::vector<Workspace*> g_ws_free[kMaxDevices];
+
+uint64_t ws_cache_limit() {
+  static const uint64_t lim = [] {
+    const char* e = getenv("BURR_WORKSPACE_CACHE_BYTES");
+    return e ? strtoull(e, nullptr, 10) : (16ull << 30);
+  }();
+  return lim;
+}
+
+// The workspace of one build: taken from the cache unless the caller
+// supplied an allocator or opted out (BURR_FLAG_NO_WORKSPACE_CACHE).
+struct WsLease {
+  Workspace* ws = nullptr;
+  int dev = -1;
+  bool cached = false;
+  hipStream_t s;
+  WsLease(Allocator* al, const burr_params& p, hipStream_t st) : s(st) {
+    cached = !al->fn && !(p.flags & BURR_FLAG_NO_WORKSPACE_CACHE) &&
+             hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices;
+    if (cached) {
+      std::lock_guard<std::mutex> lk(g_ws_mu);
+      if (!g_ws_free[dev].empty()) {
+        ws = g_ws_free[dev].back();
+        g_ws_free[dev].pop_back();
+      }
+    }
+    if (!ws) ws = new (std::nothrow) Workspace(cached ? nullptr : al);
+  }
+  ~WsLease() {
+    if (!ws) return;
+    if (!cached) {
+      delete ws;
+      return;
+    }
+    (void)hipStreamSynchronize(s);  // no launch of this build may still use it
+    std::unique_lock<std::mutex> lk(g_ws_mu);
+    uint64_t held = ws->bytes;
+    for (Workspace* w : g_ws_free[dev]) held += w->bytes;
+    if (held <= ws_cache_limit()) {
+      g_ws_free[dev].push_back(ws);
+      return;
+    }
+    lk.unlock();
+    delete ws;
+  }
+};
+
+// Device bytes the tables of a batch are expected to need: layer 0 exactly,
+// deeper layers at the bump-rate bound, plus the final layer.
+uint64_t batch_table_estimate(const burr_batch* b, const std::vector<uint64_t>& off) {
+  uint64_t words = 0;
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    const uint64_t n = off[i + 1] - off[i];
+    if (!n) continue;
+    uint64_t m, R;
+    plan_layer(b->p, n, &m, &R);
+    words += (m / 64) * b->members[i].r + (m / 64 + 31) / 32;
+  }
+  return words * 8 * 116 / 100 + 4096ull * (b->p.layers + 2);
+}
+
 int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
                 const std::vector<uint64_t>& off) {
   const burr_params& p = b->p;
@@ -475,10 +634,16 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   const uint32_t M = (uint32_t)b->members.size();
   uint32_t rmax = 1;
   for (const Member& mb : b->members) rmax = std::max(rmax, mb.r);
-  Workspace ws(&b->al);
+  WsLease lease(&b->al, p, s);
+  if (!lease.ws) return set_error(BURR_E_NOMEM);
+  Workspace& ws = *lease.ws;
+  b->arena_cap = batch_table_estimate(b, off);
+  b->arena = (uint8_t*)b->alloc(b->arena_cap);
+  if (!b->arena) return set_error(BURR_E_NOMEM);
+  b->table_bytes = b->arena_cap;
   Events ev;
   if (!ev.ok) return set_error(BURR_E_DEVICE);
-  if (!ws.reserve_keys(off.back()) || !ws.alloc(ws.steps, 8) || !ws.alloc(ws.diag, 16))
+  if (!ws.reserve_keys(off.back()) || (!ws.diag && !ws.alloc(ws.diag, 16)))
     return set_error(BURR_E_NOMEM);
   HIP_TRY(hipMemsetAsync(ws.diag, 0, 16 * 8, s));
   HIP_TRY(hipEventRecord(ev.e[0], s));
@@ -515,7 +680,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     if (!ws.reserve_slots(g.m) || !ws.reserve_buckets(g.nbuckets) || !ws.reserve_structs(g.J))
       return set_error(BURR_E_NOMEM);
     if (p.flags & BURR_FLAG_KEEP_LAYER_KEYS) {
-      LS.keys = (uint64_t*)b->al.get(g.nkeys * 8);
+      LS.keys = (uint64_t*)b->alloc(g.nkeys * 8);
       if (!LS.keys) return set_error(BURR_E_NOMEM);
       HIP_TRY(hipMemcpyAsync(LS.keys, cur_keys, g.nkeys * 8, hipMemcpyDeviceToDevice, s));
     }
@@ -536,16 +701,14 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     sa.steps = ws.steps;
     sa.diag = ws.diag;
     sa.nrec = (uint32_t)(g.nkeys + g.nbuckets);
-    HIP_TRY(hipMemsetAsync(ws.steps, 0, 64, s));
-    HIP_TRY(hipMemsetAsync(ws.fail, 0, (g.J + 1) * 4, s));
+    HIP_TRY(hipMemsetAsync(ws.res, 0, ws.results_words(g.J) * 4, s));
     HIP_TRY(hipEventRecord(ev.e[2], s));
     HIP_TRY(solve_layer(sa, s));
     HIP_TRY(hipEventRecord(ev.e[3], s));
 
-    LS.codes = (uint64_t*)b->al.get(t.code_base.back() * 8);
-    LS.W = (uint64_t*)b->al.get(t.word_base.back() * 8);
+    LS.codes = (uint64_t*)b->alloc_table(t.code_base.back() * 8);
+    LS.W = (uint64_t*)b->alloc_table(t.word_base.back() * 8);
     if (!LS.codes || !LS.W) return set_error(BURR_E_NOMEM);
-    b->table_bytes += (t.code_base.back() + t.word_base.back()) * 8;
     HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, ws.occ, g, LS.W, s));
     HIP_TRY(pack_codes(ws.code8, g, t.code_base.back(), LS.codes, s));
     HIP_TRY(hipEventRecord(ev.e[4], s));
@@ -555,17 +718,17 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     HIP_TRY(hipMemsetAsync(ws.bump + g.nbuckets, 0, 4, s));
     HIP_TRY(scan_exclusive(ws.bump, g.nbuckets + 1, ws.scan_tmp, s));
     HIP_TRY(struct_offsets(ws.bump, g, ws.soff, s));
-    std::vector<uint32_t> soff(g.J + 1), fails(g.J);
-    uint64_t steps = 0;
-    HIP_TRY(hipMemcpyAsync(soff.data(), ws.soff, (g.J + 1) * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(fails.data(), ws.fail, g.J * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&steps, ws.steps, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ws.hres, ws.res, ws.results_words(g.J) * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(gather_bumped(ws.rec, ws.bstart, ws.bump, g.nbuckets, ws.keysA, ws.valsA, s));
     HIP_TRY(hipEventRecord(ev.e[5], s));
     HIP_TRY(hipStreamSynchronize(s));
-    for (uint32_t f : fails)
-      if (f) {
-        fprintf(stderr, "burr: internal error %u in the insertion kernel, layer %u\n", f, li);
+    const uint32_t* fails = ws.hres;
+    const uint32_t* soff = ws.hres + g.J;
+    const uint64_t steps = *reinterpret_cast<const uint64_t*>(ws.hres + 2 * g.J + 2);
+    for (uint32_t k = 0; k < g.J; ++k)
+      if (fails[k]) {
+        fprintf(stderr, "burr: internal error %u in the insertion kernel, layer %u\n", fails[k],
+                li);
         print_diag(ws.diag);
         return set_error(BURR_E_DEVICE);
       }
@@ -611,9 +774,8 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     fin_off[a + 1] = fin_off[a] + cur_n[a];
   }
   if ((p.flags & BURR_FLAG_KEEP_LAYER_KEYS) && !active.empty()) {
-    uint64_t* kk = (uint64_t*)b->al.get(fin_off.back() * 8);
+    uint64_t* kk = (uint64_t*)b->alloc(fin_off.back() * 8);
     if (!kk) return set_error(BURR_E_NOMEM);
-    b->owned.push_back(kk);
     HIP_TRY(hipMemcpyAsync(kk, cur_keys, fin_off.back() * 8, hipMemcpyDeviceToDevice, s));
     for (size_t a = 0; a < active.size(); ++a) b->members[active[a]].fin_keys = kk + fin_off[a];
   }
@@ -666,11 +828,6 @@ burr_batch* new_batch(const burr_params* p, uint32_t count) {
 
 void free_batch(burr_batch* b) {
   if (!b) return;
-  for (uint32_t i = 0; i < kMaxLayers; ++i) {
-    b->al.put(b->layers[i].codes);
-    b->al.put(b->layers[i].W);
-    b->al.put(b->layers[i].keys);
-  }
   for (void* q : b->owned) b->al.put(q);
   (void)hipStreamSynchronize(b->stream);
   delete b;
@@ -1061,7 +1218,7 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
   mb.built = hdr[15];
   auto load_words = [&](uint64_t nw, uint64_t** dst) -> bool {
     if (in.off + nw * 8 > in.len) return false;
-    *dst = (uint64_t*)b->al.get(nw * 8 + 8);
+    *dst = (uint64_t*)b->alloc_table(nw * 8 + 8);
     if (!*dst) return false;
     if (nw && hipMemcpy(*dst, in.buf + in.off, nw * 8, hipMemcpyHostToDevice) != hipSuccess)
       return false;
@@ -1081,7 +1238,6 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
     L.ncode = (L.m / 64 + 31) / 32;
     L.nW = (L.m / 64) * mb.r;
     ok = load_words(L.ncode, &b->layers[l].codes) && load_words(L.nW, &b->layers[l].W);
-    b->table_bytes += (L.ncode + L.nW) * 8 + 16;
   }
   if (ok) {
     mb.fin.n = in.get(8);
@@ -1092,8 +1248,6 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
       mb.fin.nW = (mb.fin.m / 64) * mb.r;
       uint64_t* w = nullptr;
       ok = load_words(mb.fin.nW, &w);
-      if (w) b->owned.push_back(w);
-      b->table_bytes += mb.fin.nW * 8 + 8;
       mb.fin_W = w;
     }
   }
@@ -1126,6 +1280,18 @@ int64_t burr_debug_layer_keys(const burr_handle* h, uint32_t layer, uint64_t* ho
       return set_error(BURR_E_DEVICE);
   }
   return (int64_t)n;
+}
+
+void burr_release_workspaces(void) {
+  std::vector<Workspace*> all;
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    for (auto& v : g_ws_free) {
+      all.insert(all.end(), v.begin(), v.end());
+      v.clear();
+    }
+  }
+  for (Workspace* w : all) delete w;
 }
 
 int burr_last_error(void) { return g_last_error; }

@@ -74,9 +74,9 @@ struct SolveArgs {
   uint64_t* spillC;
   uint32_t* spillV;
   uint64_t* spill_occ;
-  // optional, 16 u64 zeroed by the caller: the first lane that stops with an
-  // internal error records [1, code, range, structure, x, xend, q, nq,
-  // state, open, written, rend, kf, curk, i, bucket]
+  // optional, 16 u64 zeroed by the caller: the first wave that stops with an
+  // internal error records [1, code, range, structure, header item, records,
+  // bucket, buckets, candidates, 0, kept, threshold, forced, 0, 0, first bucket]
   uint64_t* diag;
 };
 hipError_t solve_layer(const SolveArgs& a, hipStream_t s);

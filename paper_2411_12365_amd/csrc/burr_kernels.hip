@@ -563,26 +563,26 @@ hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Records the state of the first lane that stops with an internal error.
+// Records the state of the first wave that stops with an internal error.
 __device__ inline void solve_diag(uint64_t* d, uint32_t code, uint64_t rho, uint32_t js,
-                                  uint32_t x, uint32_t xend, uint32_t q, uint32_t nq,
-                                  uint32_t state, bool open, uint32_t written, uint32_t rend,
-                                  uint32_t kf, uint32_t curk, uint32_t i, uint64_t fb) {
+                                  uint32_t hq, uint32_t count, uint32_t q, uint32_t nq,
+                                  uint32_t cand, bool unused0, uint32_t kept, uint32_t thr,
+                                  uint32_t kf, uint32_t unused1, uint32_t unused2, uint64_t fb) {
   if (!d || atomicCAS((unsigned long long*)d, 0ull, 1ull) != 0ull) return;
   d[1] = code;
   d[2] = rho;
   d[3] = js;
-  d[4] = x;
-  d[5] = xend;
+  d[4] = hq;
+  d[5] = count;
   d[6] = q;
   d[7] = nq;
-  d[8] = state;
-  d[9] = open;
-  d[10] = written;
-  d[11] = rend;
+  d[8] = cand;
+  d[9] = unused0;
+  d[10] = kept;
+  d[11] = thr;
   d[12] = kf;
-  d[13] = curk;
-  d[14] = i;
+  d[13] = unused1;
+  d[14] = unused2;
   d[15] = fb;
 }
 

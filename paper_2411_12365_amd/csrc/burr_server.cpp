@@ -301,6 +301,7 @@ burr_batch* build_group(burr_server* s, uint32_t w, const std::vector<Req>& g,
   p.alloc = nullptr;
   p.free = nullptr;
   p.alloc_ctx = nullptr;
+  p.flags |= BURR_FLAG_NO_WORKSPACE_CACHE;  // the budget accounts every workspace
   std::vector<uint64_t> off(idx.size() + 1, 0);
   std::vector<uint32_t> rs(idx.size());
   uint32_t rmax = 1;
