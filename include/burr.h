@@ -127,8 +127,8 @@ burr_handle* burr_build(const uint64_t* keys, const void* values, uint64_t n, ui
 /* Queries n keys (device u64[n]) into out (device, value width of r): for
  * each layer, skip it if the key's offset is below its bucket's threshold,
  * else return the parity of the key's row AND the table window, per column
- * (Sec. 2, Fig. 1a). Enqueued on `stream` (NULL: the build's stream) and
- * returns without waiting. */
+ * (Sec. 2, Fig. 1a). Enqueued on `stream` (a hipStream_t; NULL: the null
+ * stream) and returns without waiting. */
 int burr_query(const burr_handle* h, const uint64_t* keys, uint64_t n, void* out, void* stream);
 
 /* Filter mode only: out[i] = 1 if the stored value of keys[i] equals its

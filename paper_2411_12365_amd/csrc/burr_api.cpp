@@ -1059,7 +1059,7 @@ int burr_query(const burr_handle* h, const uint64_t* keys, uint64_t n, void* out
   const Member* mb = member_of(h);
   if (!mb || (n > 0 && (!keys || !out))) return set_error(BURR_E_INVALID);
   const QueryPlan plan = make_plan(h->b, *mb);
-  hipStream_t s = stream ? (hipStream_t)stream : h->b->stream;
+  hipStream_t s = (hipStream_t)stream;  // NULL: the null stream
   if (query(plan, keys, n, out, value_bytes(mb->r), 0, 0, s) != hipSuccess)
     return set_error(BURR_E_DEVICE);
   return BURR_OK;
@@ -1070,7 +1070,7 @@ int burr_contains(const burr_handle* h, const uint64_t* keys, uint64_t n, uint8_
   const Member* mb = member_of(h);
   if (!mb || !h->b->p.filter_mode || (n > 0 && (!keys || !out))) return set_error(BURR_E_INVALID);
   const QueryPlan plan = make_plan(h->b, *mb);
-  hipStream_t s = stream ? (hipStream_t)stream : h->b->stream;
+  hipStream_t s = (hipStream_t)stream;  // NULL: the null stream
   if (query(plan, keys, n, out, 1, 1, mix64(~h->b->p.seed), s) != hipSuccess)
     return set_error(BURR_E_DEVICE);
   return BURR_OK;

@@ -963,14 +963,20 @@ __device__ inline SegBounds seg_bounds(uint64_t p, const LayerGeom& g) {
   return sb;
 }
 
-constexpr uint32_t kMergeWin = 384;  // slots of the right group staged in LDS
+constexpr uint32_t kMergeWin = 1024;  // slots of the right group staged in LDS
 
 // One workgroup per segment p; it merges at level G when p starts a left
-// group of G segments inside its structure and a right group follows.
+// group of G segments inside its structure and a right group follows. The
+// left group's spill rows (at most 63) are inserted into the right group in
+// parallel, one lane per row, with the same step-and-claim scheme as the
+// insertion kernel over an LDS window of the right group (empty slots hold
+// 0). Rows whose walk leaves the window are finished one by one in global
+// memory afterwards.
 __global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
   __shared__ uint64_t wc[kMergeWin];
   __shared__ uint32_t wv[kMergeWin];
-  __shared__ uint64_t wocc[kMergeWin / 64];
+  __shared__ uint64_t oc_[64];
+  __shared__ uint32_t ov_[64], oi_[64];
   const LayerGeom g = a.g;
   const uint64_t p = blockIdx.x;
   const SegBounds sp = seg_bounds(p, g);
@@ -986,117 +992,163 @@ __global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
   const uint64_t endR = seg_bounds(lastR, g).end;  // slot after the right group
   // window: slots [start, start + win); slots >= endR are the right group's
   // spill zone, which the window holds either completely or not at all
+  // (start, endR and the window are multiples of 64)
   const uint64_t span = endR + 64 - start;
   const uint64_t body = endR - start;
   const uint32_t win = (uint32_t)(span <= kMergeWin ? span : (body < kMergeWin ? body : kMergeWin));
   const uint32_t lane = threadIdx.x;
-  for (uint32_t t = lane; t < win; t += 64) {
-    const uint64_t slot = start + t;
+  for (uint32_t blk = 0; blk < win / 64; ++blk) {
+    const uint64_t slot = start + 64ull * blk + lane;
+    uint64_t row;
+    uint32_t val;
+    bool occd;
     if (slot < endR) {
-      wc[t] = a.rowsC[slot];
-      wv[t] = a.rowsV[slot];
+      occd = (a.occ[slot / 64] >> (slot % 64)) & 1ull;
+      row = a.rowsC[slot];
+      val = a.rowsV[slot];
     } else {
-      wc[t] = a.spillC[lastR * 64 + (slot - endR)];
-      wv[t] = a.spillV[lastR * 64 + (slot - endR)];
+      occd = (a.spill_occ[lastR] >> (slot - endR)) & 1ull;
+      row = a.spillC[lastR * 64 + (slot - endR)];
+      val = a.spillV[lastR * 64 + (slot - endR)];
     }
-  }
-  for (uint32_t b = lane; b < win / 64; b += 64) {
-    const uint64_t slot = start + 64ull * b;
-    wocc[b] = slot < endR ? a.occ[slot / 64] : a.spill_occ[lastR];
+    wc[64 * blk + lane] = occd ? row : 0ull;
+    wv[64 * blk + lane] = val;
   }
   __syncthreads();
+  // parallel phase
+  const uint64_t pend = a.spill_occ[lastL];
+  bool active = (pend >> lane) & 1ull;
+  uint64_t c = active ? a.spillC[lastL * 64 + lane] : 0ull;
+  uint32_t v = active ? a.spillV[lastL * 64 + lane] : 0u;
+  uint32_t i = lane;  // relative to start: the left group ends where the right one begins
+  bool over = false, bad = false, internal = false;
+  uint32_t guard = 64u * (win + 64u) + 1024u;
+  while (__any(active)) {
+    if (guard-- == 0) {
+      internal = true;
+      break;
+    }
+    bool at_empty = false, conflict = false, corrupt = false;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (active && !at_empty && i >= win) {  // leaves the window: finish later
+        over = true;
+        active = false;
+      }
+      const uint32_t ii = i < win ? i : 0u;
+      const uint64_t row = wc[ii];
+      const uint32_t rv = wv[ii];
+      const bool go = active && !at_empty;
+      at_empty = at_empty || (go && row == 0);
+      const bool step = go && row != 0;
+      const uint64_t cx = c ^ row;
+      const uint32_t vx = v ^ rv;
+      const bool zero = step && cx == 0;
+      corrupt = corrupt || (step && !zero && (cx & 1ull));  // stored rows have their leading bit
+      conflict = conflict || (zero && vx != 0);
+      active = active && !zero && !(step && (cx & 1ull));
+      const bool adv = step && !zero && !(cx & 1ull);
+      const uint32_t j = (uint32_t)__builtin_ctzg(cx, 64);
+      c = adv ? (cx >> j) : c;
+      v = step ? vx : v;
+      i = adv ? i + j : i;
+    }
+    if (at_empty && active) {
+      const uint64_t old = atomicCAS((unsigned long long*)&wc[i], 0ull, (unsigned long long)c);
+      if (old == 0) {
+        wv[i] = v;
+        active = false;
+      }
+    }
+    if (__any(conflict || corrupt)) {
+      bad = true;
+      internal = internal || __any(corrupt);
+      break;
+    }
+  }
+  bad = bad || internal;
+  __syncthreads();
+  // write the window back with its occupancy
+  for (uint32_t blk = 0; blk < win / 64; ++blk) {
+    const uint64_t slot = start + 64ull * blk + lane;
+    const uint64_t row = wc[64 * blk + lane];
+    const uint64_t word = __ballot(row != 0);
+    if (slot < endR) {
+      if (row) {
+        a.rowsC[slot] = row;
+        a.rowsV[slot] = wv[64 * blk + lane];
+      }
+      if (lane == 0) a.occ[slot / 64] = word;
+    } else {
+      if (row) {
+        a.spillC[lastR * 64 + (slot - endR)] = row;
+        a.spillV[lastR * 64 + (slot - endR)] = wv[64 * blk + lane];
+      }
+      if (lane == 0) a.spill_occ[lastR] = word;
+    }
+  }
+  // rows that left the window, one by one in global memory (rare)
+  const uint64_t overm = __ballot(over && !bad);
+  oc_[lane] = c;
+  ov_[lane] = v;
+  oi_[lane] = i;
+  __syncthreads();
   if (lane == 0) {
-    uint64_t pend = a.spill_occ[lastL];
-    bool bad = false, internal = false;
-    while (pend && !bad) {
-      const uint32_t t0 = (uint32_t)__builtin_ctzll(pend);
-      pend &= pend - 1;
-      uint64_t c = a.spillC[lastL * 64 + t0];
-      uint32_t v = a.spillV[lastL * 64 + t0];
-      uint32_t i = t0;  // relative to start (the left group ends where the right one begins)
+    uint64_t rest = overm;
+    while (rest && !bad) {
+      const uint32_t t0 = (uint32_t)__builtin_ctzll(rest);
+      rest &= rest - 1;
+      uint64_t cc = oc_[t0];
+      uint32_t vv = ov_[t0];
+      uint64_t slot = start + oi_[t0];
       while (true) {
         bool occupied;
         uint64_t row;
         uint32_t rv;
-        if (i < win) {
-          occupied = (wocc[i / 64] >> (i % 64)) & 1ull;
-          row = wc[i];
-          rv = wv[i];
+        if (slot < endR) {
+          occupied = (a.occ[slot / 64] >> (slot % 64)) & 1ull;
+          row = a.rowsC[slot];
+          rv = a.rowsV[slot];
         } else {
-          // beyond the staged window: read the right group in global memory
-          const uint64_t slot = start + i;
-          if (slot < endR) {
-            occupied = (a.occ[slot / 64] >> (slot % 64)) & 1ull;
-            row = a.rowsC[slot];
-            rv = a.rowsV[slot];
-          } else {
-            const uint64_t t = slot - endR;
-            if (t >= 64) {  // unreachable: rows end at most 62 slots past the group
-              bad = true;
-              internal = true;
-              break;
-            }
-            occupied = (a.spill_occ[lastR] >> t) & 1ull;
-            row = a.spillC[lastR * 64 + t];
-            rv = a.spillV[lastR * 64 + t];
+          const uint64_t t = slot - endR;
+          if (t >= 64) {  // unreachable: rows end at most 62 slots past the group
+            bad = internal = true;
+            break;
           }
+          occupied = (a.spill_occ[lastR] >> t) & 1ull;
+          row = a.spillC[lastR * 64 + t];
+          rv = a.spillV[lastR * 64 + t];
         }
         if (!occupied) {
-          if (i < win) {
-            wc[i] = c;
-            wv[i] = v;
-            wocc[i / 64] |= 1ull << (i % 64);
+          if (slot < endR) {
+            a.rowsC[slot] = cc;
+            a.rowsV[slot] = vv;
+            a.occ[slot / 64] |= 1ull << (slot % 64);
           } else {
-            const uint64_t slot = start + i;
-            if (slot < endR) {
-              a.rowsC[slot] = c;
-              a.rowsV[slot] = v;
-              a.occ[slot / 64] |= 1ull << (slot % 64);
-            } else {
-              const uint64_t t = slot - endR;
-              a.spillC[lastR * 64 + t] = c;
-              a.spillV[lastR * 64 + t] = v;
-              a.spill_occ[lastR] |= 1ull << t;
-            }
+            const uint64_t t = slot - endR;
+            a.spillC[lastR * 64 + t] = cc;
+            a.spillV[lastR * 64 + t] = vv;
+            a.spill_occ[lastR] |= 1ull << t;
           }
           break;
         }
-        c ^= row;
-        v ^= rv;
-        if (c == 0) {
-          if (v != 0) bad = true;  // inconsistent: this table size fails
+        cc ^= row;
+        vv ^= rv;
+        if (cc == 0) {
+          if (vv != 0) bad = true;  // inconsistent: this table size fails
           break;
         }
-        if (c & 1ull) {  // a stored row always has its leading bit: corrupt state
-          bad = true;
-          internal = true;
+        if (cc & 1ull) {  // a stored row always has its leading bit: corrupt state
+          bad = internal = true;
           break;
         }
-        const uint32_t j = (uint32_t)__builtin_ctzll(c);
-        c >>= j;
-        i += j;
+        const uint32_t j = (uint32_t)__builtin_ctzll(cc);
+        cc >>= j;
+        slot += j;
       }
     }
     if (bad) a.fail[sp.j] = internal ? 2u : 1u;
     a.spill_occ[lastL] = 0;
-  }
-  __syncthreads();
-  for (uint32_t t = lane; t < win; t += 64) {
-    const uint64_t slot = start + t;
-    if (slot < endR) {
-      a.rowsC[slot] = wc[t];
-      a.rowsV[slot] = wv[t];
-    } else {
-      a.spillC[lastR * 64 + (slot - endR)] = wc[t];
-      a.spillV[lastR * 64 + (slot - endR)] = wv[t];
-    }
-  }
-  for (uint32_t b = lane; b < win / 64; b += 64) {
-    const uint64_t slot = start + 64ull * b;
-    if (slot < endR)
-      a.occ[slot / 64] = wocc[b];
-    else
-      a.spill_occ[lastR] = wocc[b];
   }
 }
 
