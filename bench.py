@@ -44,11 +44,13 @@ def algorithmic_build_bytes(stats, r):
 
 
 def solve_kernel_bytes(L, r):
-    """Algorithmic bytes of one insertion launch: read the 16-byte sorted
-    records and the bucket starts, write every placed row (u64 row + u32
-    value), the occupancy bits, one code byte and one bump count per bucket."""
+    """Algorithmic bytes of one insertion launch: read the 16-byte item stream
+    (one record per key, one header per bucket) and the bucket starts, write
+    every placed row (u64 row + u32 value), the occupancy bits, one code byte
+    and one bump count per bucket."""
     pivots = L["n"] - L["bumped"]
-    return 16 * L["n"] + 4 * (L["nbuckets"] + 1) + 12 * pivots + L["m"] // 8 + 5 * L["nbuckets"]
+    return (16 * (L["n"] + L["nbuckets"]) + 4 * (L["nbuckets"] + 1) + 12 * pivots + L["m"] // 8
+            + 5 * L["nbuckets"])
 
 
 def measured_traffic(kernel_key):
@@ -410,13 +412,13 @@ def main():
     solve_bytes = solve_kernel_bytes(L0, R_BITS)
     solve_gbs = solve_bytes / (solve_ms / 1e3) / 1e9
     roofline = {
-        "kernel": "k_solve (layer 0 insertion)",
+        "kernel": "k_solve_wave (layer 0 insertion)",
         "bound": "hbm",
         "achieved": round(solve_gbs, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(solve_gbs / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic("k_solve_layer0") if n == N_KEYS else None,
+        "traffic": measured_traffic("k_solve_wave_layer0") if n == N_KEYS else None,
         "bytes_per_launch": solve_bytes,
         "ms_per_launch": round(solve_ms, 4),
     }
