@@ -120,13 +120,15 @@ hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s
 // level 3: one workgroup per sub-bin (64 buckets) orders its records by
 //          (bucket, chunk) in LDS and writes headers and records as one block
 // Intermediate records (16 B): key, value | slot within the bin << 32.
-constexpr int kPartThreads = 256;
+constexpr int kPartThreads = 256;   // level 1 (hashing needs more registers)
+constexpr int kPart2Threads = 512;  // level 2
 constexpr int kPartPer = 8;
-constexpr uint32_t kTile = kPartThreads * kPartPer;  // keys per tile
+constexpr uint32_t kTile = kPartThreads * kPartPer;  // level-1 keys per tile
 constexpr uint32_t kSubSlots = kSubBuckets * 64;     // slots per sub-bin
 constexpr uint32_t kChunk2 = 16384;                  // level-2 keys per workgroup
 constexpr int kL3Threads = 256;
-constexpr uint32_t kL3Cap = 4608;                    // items of a sub-bin staged in LDS
+constexpr int kL3Per = 18;                           // records per thread held in registers
+constexpr uint32_t kL3Cap = kL3Threads * kL3Per;     // items of a sub-bin staged in LDS
 
 SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets) {
   SortPlan p{};
@@ -173,8 +175,9 @@ struct KeyWalk {
 
 // Block-wide exclusive scan of n <= kMaxDigits counters in LDS (in place);
 // a[n] receives the total.
+template <int NT = kPartThreads>
 __device__ inline void lds_scan(uint32_t* a, uint32_t n, uint32_t* wsum) {
-  constexpr uint32_t per = (kMaxDigits + kPartThreads - 1) / kPartThreads;
+  constexpr uint32_t per = (kMaxDigits + NT - 1) / NT;
   uint32_t loc[per];
   uint32_t tot = 0;
   const uint32_t base = threadIdx.x * per;
@@ -185,8 +188,8 @@ __device__ inline void lds_scan(uint32_t* a, uint32_t n, uint32_t* wsum) {
   }
   __syncthreads();
   uint32_t total;
-  uint32_t run = block_exclusive_scan<kPartThreads>(tot, wsum, wsum + kPartThreads / 64);
-  total = wsum[kPartThreads / 64];
+  uint32_t run = block_exclusive_scan<NT>(tot, wsum, wsum + NT / 64);
+  total = wsum[NT / 64];
 #pragma unroll
   for (uint32_t k = 0; k < per; ++k) {
     if (base + k < n) a[base + k] = run;
@@ -221,11 +224,12 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_hist(const uint64_t* __rest
 // as a run at that digit's cursor (cur[d] advances by the tile's count).
 // rec/dig/rank: each thread's kPartPer records (dig = kNoDigit: none).
 constexpr uint32_t kNoDigit = 0xffffffffu;
+template <int NT>
 __device__ inline void tile_write(uint4 (&rec)[kPartPer], uint32_t (&dig)[kPartPer],
                                   uint32_t (&rank)[kPartPer], uint32_t D, uint32_t* cur,
                                   uint32_t* toff, uint4* stage, uint16_t* sdig, uint32_t* wsum,
                                   uint32_t ntile, uint4* __restrict__ out) {
-  lds_scan(toff, D, wsum);  // tile counts -> tile offsets
+  lds_scan<NT>(toff, D, wsum);  // tile counts -> tile offsets
 #pragma unroll
   for (int k = 0; k < kPartPer; ++k)
     if (dig[k] != kNoDigit) {
@@ -234,21 +238,23 @@ __device__ inline void tile_write(uint4 (&rec)[kPartPer], uint32_t (&dig)[kPartP
       sdig[pos] = (uint16_t)dig[k];
     }
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j < ntile; j += kPartThreads) {
+  for (uint32_t j = threadIdx.x; j < ntile; j += NT) {
     const uint32_t d = sdig[j];
     out[cur[d] + (j - toff[d])] = stage[j];
   }
   __syncthreads();
-  for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) cur[d] += toff[d + 1] - toff[d];
+  for (uint32_t d = threadIdx.x; d < D; d += NT) cur[d] += toff[d + 1] - toff[d];
   __syncthreads();
-  for (uint32_t d = threadIdx.x; d < D; d += kPartThreads) toff[d] = 0;
+  for (uint32_t d = threadIdx.x; d < D; d += NT) toff[d] = 0;
   __syncthreads();
 }
 
 // LDS layout of the partition kernels: cur[D], toff[D+1], wsum, stage, sdig
+template <int NT>
 __host__ __device__ constexpr size_t part_lds_bytes(uint32_t D) {
-  return (size_t)(2 * D + 2 + kPartThreads / 64 + 2) * 4 + 15 + (size_t)kTile * 16 + kTile * 2;
+  return (size_t)(2 * D + 2 + NT / 64 + 2) * 4 + 15 + (size_t)NT * kPartPer * 18;
 }
+template <int NT>
 struct PartLds {
   uint32_t *cur, *toff, *wsum;
   uint4* stage;
@@ -257,10 +263,10 @@ struct PartLds {
     cur = sm;
     toff = sm + D;
     wsum = toff + D + 2;
-    uint8_t* p = reinterpret_cast<uint8_t*>(wsum + kPartThreads / 64 + 2);
+    uint8_t* p = reinterpret_cast<uint8_t*>(wsum + NT / 64 + 2);
     p = reinterpret_cast<uint8_t*>(((uintptr_t)p + 15) & ~(uintptr_t)15);
     stage = reinterpret_cast<uint4*>(p);
-    sdig = reinterpret_cast<uint16_t*>(stage + kTile);
+    sdig = reinterpret_cast<uint16_t*>(stage + NT * kPartPer);
   }
 };
 
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_scatter(
     const uint32_t* __restrict__ offs, uint32_t mask_values, uint32_t filter, uint64_t fp_salt,
     uint4* __restrict__ out) {
   extern __shared__ uint32_t sm[];
-  PartLds L(sm, sp.nb1);
+  PartLds<kPartThreads> L(sm, sp.nb1);
   for (uint32_t d = threadIdx.x; d < sp.nb1; d += kPartThreads) {
     L.cur[d] = offs[(size_t)d * sp.G1 + blockIdx.x];
     L.toff[d] = 0;
@@ -308,7 +314,8 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_scatter(
     }
     const uint32_t ntile = (uint32_t)(hi - t0 < kTile ? hi - t0 : kTile);
     __syncthreads();
-    tile_write(rec, dig, rank, sp.nb1, L.cur, L.toff, L.stage, L.sdig, L.wsum, ntile, out);
+    tile_write<kPartThreads>(rec, dig, rank, sp.nb1, L.cur, L.toff, L.stage, L.sdig, L.wsum,
+                             ntile, out);
   }
 }
 
@@ -357,7 +364,7 @@ __device__ inline bool chunk2_of(uint32_t wg, const SortPlan& sp, const uint32_t
 
 // Level 2, pass 1: keys per sub-bin of each chunk; counts2 is laid out per
 // bin as [sub-bin][chunk] so that one scan gives every run's position.
-__global__ __launch_bounds__(kPartThreads) void k_p2_hist(const uint4* __restrict__ in,
+__global__ __launch_bounds__(kPart2Threads) void k_p2_hist(const uint4* __restrict__ in,
                                                           SortPlan sp,
                                                           const uint32_t* __restrict__ binlo,
                                                           const uint32_t* __restrict__ nch,
@@ -366,47 +373,51 @@ __global__ __launch_bounds__(kPartThreads) void k_p2_hist(const uint4* __restric
   extern __shared__ uint32_t hist[];
   Chunk2 ch;
   if (!chunk2_of(blockIdx.x, sp, binlo, nch, cbase, ch)) return;
-  for (uint32_t i = threadIdx.x; i < sp.S; i += kPartThreads) hist[i] = 0;
+  for (uint32_t i = threadIdx.x; i < sp.S; i += kPart2Threads) hist[i] = 0;
   __syncthreads();
-  for (uint32_t i = ch.lo + threadIdx.x; i < ch.hi; i += kPartThreads)
+  for (uint32_t i = ch.lo + threadIdx.x; i < ch.hi; i += kPart2Threads)
     atomicAdd(&hist[in[i].w / kSubSlots], 1u);
   __syncthreads();
   const uint32_t nc = nch[ch.b];
-  for (uint32_t i = threadIdx.x; i < sp.S; i += kPartThreads)
+  for (uint32_t i = threadIdx.x; i < sp.S; i += kPart2Threads)
     counts[ch.base + i * nc + ch.c] = hist[i];
 }
 
 // Level 2, pass 2: tile runs per sub-bin.
-__global__ __launch_bounds__(kPartThreads) void k_p2_scatter(
+__global__ __launch_bounds__(kPart2Threads) void k_p2_scatter(
     const uint4* __restrict__ in, SortPlan sp, const uint32_t* __restrict__ binlo,
     const uint32_t* __restrict__ nch, const uint32_t* __restrict__ cbase,
     const uint32_t* __restrict__ offs, uint4* __restrict__ out) {
   extern __shared__ uint32_t sm[];
   Chunk2 ch;
   if (!chunk2_of(blockIdx.x, sp, binlo, nch, cbase, ch)) return;
-  PartLds L(sm, sp.S);
+  PartLds<kPart2Threads> L(sm, sp.S);
   const uint32_t nc = nch[ch.b];
-  for (uint32_t d = threadIdx.x; d < sp.S; d += kPartThreads) {
+  for (uint32_t d = threadIdx.x; d < sp.S; d += kPart2Threads) {
     L.cur[d] = offs[ch.base + d * nc + ch.c];
     L.toff[d] = 0;
   }
   __syncthreads();
-  for (uint32_t t0 = ch.lo; t0 < ch.hi; t0 += kTile) {
+  constexpr uint32_t T2 = kPart2Threads * kPartPer;
+  for (uint32_t t0 = ch.lo; t0 < ch.hi; t0 += T2) {
     uint4 rec[kPartPer];
     uint32_t dig[kPartPer], rank[kPartPer];
 #pragma unroll
     for (int k = 0; k < kPartPer; ++k) {
-      const uint32_t i = t0 + threadIdx.x + k * kPartThreads;
+      const uint32_t i = t0 + threadIdx.x + k * kPart2Threads;
       dig[k] = kNoDigit;
+      rank[k] = 0;
+      rec[k] = make_uint4(0, 0, 0, 0);
       if (i < ch.hi) {
         rec[k] = in[i];
         dig[k] = rec[k].w / kSubSlots;
         rank[k] = atomicAdd(&L.toff[dig[k]], 1u);
       }
     }
-    const uint32_t ntile = ch.hi - t0 < kTile ? ch.hi - t0 : kTile;
+    const uint32_t ntile = ch.hi - t0 < T2 ? ch.hi - t0 : T2;
     __syncthreads();
-    tile_write(rec, dig, rank, sp.S, L.cur, L.toff, L.stage, L.sdig, L.wsum, ntile, out);
+    tile_write<kPart2Threads>(rec, dig, rank, sp.S, L.cur, L.toff, L.stage, L.sdig, L.wsum,
+                              ntile, out);
   }
 }
 
@@ -462,11 +473,33 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict_
   for (uint32_t i = threadIdx.x; i < 3 * kSubBuckets; i += kL3Threads) dcur[i] = 0;
   for (uint32_t i = threadIdx.x; i < kSubBuckets; i += kL3Threads) maxoff[i] = 0;
   __syncthreads();
-  for (uint32_t i = lo + threadIdx.x; i < hi; i += kL3Threads) {
-    const uint32_t sl = in[i].w - slot0;
-    const uint32_t bl = sl >> 6, o = sl & 63u;
-    atomicAdd(&dcur[bl * 3 + rank_of(o, g)], 1u);
-    atomicMax(&maxoff[bl], o);
+  // the block is assembled in LDS when it fits; then every record is read
+  // once, into registers, and its rank inside its digit comes from the
+  // counting atomic
+  const bool fits = n + nbk <= kL3Cap;
+  uint4 rec[kL3Per];
+  uint32_t dr[kL3Per];  // digit | rank << 8
+  if (fits) {
+#pragma unroll
+    for (int k = 0; k < kL3Per; ++k) {
+      const uint32_t i = lo + threadIdx.x + k * kL3Threads;
+      dr[k] = 0xffffffffu;
+      if (i < hi) {
+        rec[k] = in[i];
+        const uint32_t sl = rec[k].w - slot0;
+        const uint32_t bl = sl >> 6, o = sl & 63u;
+        const uint32_t d = bl * 3 + rank_of(o, g);
+        dr[k] = d | (atomicAdd(&dcur[d], 1u) << 8);
+        atomicMax(&maxoff[bl], o);
+      }
+    }
+  } else {
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kL3Threads) {
+      const uint32_t sl = in[i].w - slot0;
+      const uint32_t bl = sl >> 6, o = sl & 63u;
+      atomicAdd(&dcur[bl * 3 + rank_of(o, g)], 1u);
+      atomicMax(&maxoff[bl], o);
+    }
   }
   __syncthreads();
   {  // exclusive scan of the 192 digit counts
@@ -479,7 +512,6 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict_
     if (t == 0) dcur[3 * kSubBuckets] = n;
     __syncthreads();
   }
-  const bool fits = n + nbk <= kL3Cap;
   Rec* gout = items + lo + beta0;
   // headers and bucket starts
   for (uint32_t bl = threadIdx.x; bl < nbk; bl += kL3Threads) {
@@ -495,24 +527,30 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict_
       reinterpret_cast<uint4*>(gout)[first + bl] = hd;
   }
   if (sb + 1 == sp.nsub && threadIdx.x == 0) bstart[g.nbuckets] = (uint32_t)g.nkeys;
-  __syncthreads();
   // records: key, value | offset << 32 | rank << 40
+  if (fits) {
+#pragma unroll
+    for (int k = 0; k < kL3Per; ++k) {
+      if (dr[k] == 0xffffffffu) continue;
+      const uint32_t d = dr[k] & 0xffu;
+      const uint32_t bl = d / 3, rk = d - bl * 3;
+      const uint32_t o = (rec[k].w - slot0) & 63u;
+      stage[dcur[d] + (dr[k] >> 8) + bl + 1] = make_uint4(rec[k].x, rec[k].y, rec[k].z, o | (rk << 8));
+    }
+    __syncthreads();
+    uint4* go = reinterpret_cast<uint4*>(gout);
+    for (uint32_t j = threadIdx.x; j < n + nbk; j += kL3Threads) go[j] = stage[j];
+    return;
+  }
+  __syncthreads();
   for (uint32_t i = lo + threadIdx.x; i < hi; i += kL3Threads) {
     const uint4 r = in[i];
     const uint32_t sl = r.w - slot0;
     const uint32_t bl = sl >> 6, o = sl & 63u;
     const uint32_t rk = rank_of(o, g);
     const uint32_t pos = atomicAdd(&dcur[bl * 3 + rk], 1u) + bl + 1;
-    const uint4 item = make_uint4(r.x, r.y, r.z, o | (rk << 8));
-    if (fits)
-      stage[pos] = item;
-    else
-      reinterpret_cast<uint4*>(gout)[pos] = item;
+    reinterpret_cast<uint4*>(gout)[pos] = make_uint4(r.x, r.y, r.z, o | (rk << 8));
   }
-  if (!fits) return;
-  __syncthreads();
-  uint4* go = reinterpret_cast<uint4*>(gout);
-  for (uint32_t j = threadIdx.x; j < n + nbk; j += kL3Threads) go[j] = stage[j];
 }
 
 hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
@@ -523,7 +561,7 @@ hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
   k_p1_hist<<<sp.G1, kPartThreads, (size_t)sp.nb1 * 4, s>>>(a.keys, a.g, sp, a.counts1);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = scan_exclusive(a.counts1, (size_t)sp.nb1 * sp.G1, a.scan_tmp, s)) != hipSuccess) return e;
-  const size_t lds1 = part_lds_bytes(sp.nb1);
+  const size_t lds1 = part_lds_bytes<kPartThreads>(sp.nb1);
   switch (a.vbytes) {
     case 1:
       k_p1_scatter<uint8_t><<<sp.G1, kPartThreads, lds1, s>>>(
@@ -546,12 +584,12 @@ hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t n2 = (size_t)sp.U2 * sp.S;
   if ((e = hipMemsetAsync(a.counts2, 0, (n2 + 1) * 4, s)) != hipSuccess) return e;
-  k_p2_hist<<<sp.U2, kPartThreads, (size_t)sp.S * 4, s>>>(a.p1, sp, a.binlo, a.nch, a.cbase,
-                                                          a.counts2);
+  k_p2_hist<<<sp.U2, kPart2Threads, (size_t)sp.S * 4, s>>>(a.p1, sp, a.binlo, a.nch, a.cbase,
+                                                           a.counts2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = scan_exclusive(a.counts2, n2, a.scan_tmp, s)) != hipSuccess) return e;
-  k_p2_scatter<<<sp.U2, kPartThreads, part_lds_bytes(sp.S), s>>>(a.p1, sp, a.binlo, a.nch,
-                                                                 a.cbase, a.counts2, a.p2);
+  k_p2_scatter<<<sp.U2, kPart2Threads, part_lds_bytes<kPart2Threads>(sp.S), s>>>(
+      a.p1, sp, a.binlo, a.nch, a.cbase, a.counts2, a.p2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_p2_starts<<<(sp.nsub + 256) / 256, 256, 0, s>>>(sp, n, a.binlo, a.nch, a.cbase, a.counts2,
                                                      a.sstart);
