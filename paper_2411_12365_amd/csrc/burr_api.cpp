@@ -725,6 +725,15 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     const uint32_t* fails = ws.hres;
     const uint32_t* soff = ws.hres + g.J;
     const uint64_t steps = *reinterpret_cast<const uint64_t*>(ws.hres + 2 * g.J + 2);
+#ifdef BURR_SOLVE_STATS
+    {
+      const uint64_t* st = reinterpret_cast<const uint64_t*>(ws.hres + 2 * g.J + 2);
+      fprintf(stderr, "solve-stats layer %u: keys %llu buckets %llu steps %llu trips %llu passes %llu "
+              "active-lanes %llu\n", li, (unsigned long long)g.nkeys,
+              (unsigned long long)g.nbuckets, (unsigned long long)st[0], (unsigned long long)st[1],
+              (unsigned long long)st[2], (unsigned long long)st[3]);
+    }
+#endif
     for (uint32_t k = 0; k < g.J; ++k)
       if (fails[k]) {
         fprintf(stderr, "burr: internal error %u in the insertion kernel, layer %u\n", fails[k],

@@ -660,6 +660,18 @@ __device__ inline uint64_t wave_ballot(bool p) { return __ballot(p); }
 #endif
 constexpr int kSolveK = BURR_SOLVE_K;  // elimination steps per loop trip
 
+// Optional counters (-DBURR_SOLVE_STATS): loop trips, passes and active lanes
+// per trip, added to the three words after the step count.
+#ifdef BURR_SOLVE_STATS
+struct SolveStats {
+  uint64_t trips = 0, passes = 0, lanes = 0;
+};
+#define BURR_STAT(x) x
+#else
+struct SolveStats {};
+#define BURR_STAT(x)
+#endif
+
 // Inserts records [r0, r1) of the staged bucket q. Returns 0 if the set was
 // consistent, 1 if an inconsistency was met (its rows are removed again), or
 // 2 on an internal error. Each loop trip: lanes without a row take the next
@@ -667,7 +679,9 @@ constexpr int kSolveK = BURR_SOLVE_K;  // elimination steps per loop trip
 // ring (stopping at an empty slot), then the lanes at an empty slot claim it.
 __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint4* rec4,
                                      uint32_t hq, uint32_t q, uint32_t r0, uint32_t r1,
-                                     uint32_t limit, uint64_t& steps) {
+                                     uint32_t limit, uint64_t& steps, SolveStats& st) {
+  (void)st;
+  BURR_STAT(++st.passes;)
   const uint32_t lane = threadIdx.x;
   if (lane < 2) R.placed[lane] = 0;
   __syncthreads();
@@ -697,6 +711,7 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
     const uint32_t nfree = (uint32_t)__popcll(freem);
     next = (r1 - next < nfree) ? r1 : next + nfree;
     if (!__any(active)) break;
+    BURR_STAT(++st.trips; st.lanes += __popcll(wave_ballot(active));)
     if (guard-- == 0) {
       result = 2;
       break;
@@ -790,6 +805,7 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
   R.c[lane] = 0;
   R.c[64 + lane] = 0;
   uint64_t steps = 0;
+  SolveStats sst;
   bool failed = false;
   // bucket 0's items, staged through registers
   uint32_t hq = a.bstart[fb] + (uint32_t)fb;
@@ -820,7 +836,7 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
     const uint32_t cand = keep_ranks == 3 ? count : (keep_ranks == 2 ? e2 : (keep_ranks == 1 ? e1 : 0u));
     uint32_t kept = cand, code = kf;
     if (cand > 0) {
-      uint32_t res = wave_pass(R, a, rec4, hq, q, 0, cand, limit, steps);
+      uint32_t res = wave_pass(R, a, rec4, hq, q, 0, cand, limit, steps, sst);
       if (res == 1 && g.plain) {
         if (lane == 0) a.fail[js] = 1u;
         failed = true;
@@ -831,7 +847,7 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
         for (uint32_t rr = keep_ranks - 1; rr >= 1 && res != 2; --rr) {
           const uint32_t e = rr == 2 ? e2 : e1;
           if (e == failed_size) continue;  // the same set again
-          res = e ? wave_pass(R, a, rec4, hq, q, 0, e, limit, steps) : 0u;
+          res = e ? wave_pass(R, a, rec4, hq, q, 0, e, limit, steps, sst) : 0u;
           if (res == 0) {
             kept = e;
             code = 3 - rr;
@@ -866,6 +882,13 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
   if (a.steps) {
     for (int d = 32; d >= 1; d >>= 1) steps += __shfl_xor(steps, d, 64);
     if (lane == 0) atomicAdd((unsigned long long*)a.steps, (unsigned long long)steps);
+#ifdef BURR_SOLVE_STATS
+    if (lane == 0) {
+      atomicAdd((unsigned long long*)a.steps + 1, (unsigned long long)sst.trips);
+      atomicAdd((unsigned long long*)a.steps + 2, (unsigned long long)sst.passes);
+      atomicAdd((unsigned long long*)a.steps + 3, (unsigned long long)sst.lanes);
+    }
+#endif
   }
 }
 
