@@ -52,7 +52,8 @@ enum {
 #define BURR_FLAG_KEEP_LAYER_KEYS 1u
 /* Allocate the build's temporary buffers for this build only instead of
  * reusing the library's per-device workspace (kept between builds up to
- * BURR_WORKSPACE_CACHE_BYTES bytes, default 16 GiB; see burr_release_workspaces). */
+ * BURR_WORKSPACE_CACHE_BYTES bytes per device, default a quarter of the
+ * device's memory; see burr_release_workspaces). */
 #define BURR_FLAG_NO_WORKSPACE_CACHE 2u
 
 typedef void* (*burr_alloc_fn)(size_t bytes, void* stream, void* ctx);

@@ -277,7 +277,7 @@ class Batch:
 
     def __init__(self, ptr: int, rs, params: Params):
         self._b = ptr
-        self.rs = list(rs)
+        self.rs = rs
         self.params = params
 
     def __del__(self):
@@ -305,7 +305,6 @@ def burr_build_batch(keys, values, offsets, rs, params: Params | None = None,
     import torch
     params = params or Params()
     _check_tensor(keys, "keys", (torch.int64, torch.uint64))
-    rs = [int(r) for r in rs]
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
     rr = np.ascontiguousarray(np.asarray(rs, dtype=np.uint32))
     if len(rr) == 0 or off.shape != (len(rr) + 1,):
@@ -314,7 +313,7 @@ def burr_build_batch(keys, values, offsets, rs, params: Params | None = None,
         raise ValueError("offsets[-1] must equal the number of keys")
     vptr = None
     if values is not None:
-        _check_tensor(values, "values", (value_dtype(max(rs)),))
+        _check_tensor(values, "values", (value_dtype(int(rr.max())),))
         if values.numel() != keys.numel():
             raise ValueError("keys and values differ in length")
         vptr = values.data_ptr() if values.numel() else None
@@ -323,7 +322,7 @@ def burr_build_batch(keys, values, offsets, rs, params: Params | None = None,
                                off.ctypes.data, rr.ctypes.data, len(rr), ctypes.byref(cp))
     if not b:
         raise BurrError(lib().burr_last_error(), "burr_build_batch")
-    return Batch(b, rs, params)
+    return Batch(b, rr, params)
 
 
 def burr_batch_size(b: Batch) -> int:
@@ -334,7 +333,7 @@ def burr_batch_member(b: Batch, i: int) -> Handle:
     h = lib().burr_batch_member(b._b, i)
     if not h:
         raise BurrError(lib().burr_last_error(), "burr_batch_member")
-    return Handle(h, b.rs[i], b.params, batch=b)
+    return Handle(h, int(b.rs[i]), b.params, batch=b)
 
 
 def burr_batch_free(b: Batch):

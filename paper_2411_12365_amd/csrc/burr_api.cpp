@@ -84,21 +84,28 @@ struct MemberLayer {
   uint64_t key_off = 0;              // debug: first key in the layer's kept key array
 };
 
-// storage shared by all members of a batch for one layer
+// storage shared by all members of a batch for one layer, and the records of
+// the members with keys in it (ids ascending, ml[k] belongs to ids[k])
 struct LayerStore {
   uint64_t* codes = nullptr;
   uint64_t* W = nullptr;
   uint64_t* keys = nullptr;  // kept input keys (debug flag)
   uint64_t steps = 0;
   double ms_sort = 0, ms_solve = 0, ms_backsub = 0, ms_gather = 0;
+  std::vector<uint32_t> ids;
+  std::vector<MemberLayer> ml;
+};
+
+// the final plain layer of one member
+struct FinalLayer {
+  uint64_t n = 0, m = 0, nW = 0;
 };
 
 struct Member {
   uint64_t n = 0;
   uint32_t r = 0;
-  uint32_t built = 0;  // BuRR layers with keys
-  MemberLayer layer[kMaxLayers];
-  MemberLayer fin;
+  uint32_t built = 0;  // BuRR layers with keys (their records sit in the layer stores)
+  FinalLayer fin;
   uint64_t fin_attempt = 0;
   const uint64_t* fin_W = nullptr;
   const uint64_t* fin_keys = nullptr;  // debug
@@ -145,6 +152,13 @@ struct burr_batch {
 };
 
 namespace {
+
+// member idx's record of layer l < its built count
+const MemberLayer& layer_of(const burr_batch* b, uint32_t idx, uint32_t l) {
+  const LayerStore& LS = b->layers[l];
+  const size_t k = std::lower_bound(LS.ids.begin(), LS.ids.end(), idx) - LS.ids.begin();
+  return LS.ml[k];
+}
 
 bool params_ok(const burr_params* p) {
   if (!p || p->abi_version != BURR_ABI_VERSION) return false;
@@ -560,18 +574,23 @@ int final_attempt(burr_batch* b, Workspace& ws, const std::vector<uint32_t>& lis
 // Builds every member of b. Member i's keys are keys[off[i], off[i+1]), its
 // values the same range of `values` (elements of value_bytes(max r) bytes).
 // Workspaces kept between builds, per device (plain hipMalloc memory), up
-// to a total size (environment variable BURR_WORKSPACE_CACHE_BYTES, default
-// 16 GiB); burr_release_workspaces() frees them.
+// to a total size per device: the environment variable
+// BURR_WORKSPACE_CACHE_BYTES, else a quarter of the device's memory.
+// burr_release_workspaces() frees them.
 constexpr int kMaxDevices = 64;
 std::mutex g_ws_mu;
 std::vector<Workspace*> g_ws_free[kMaxDevices];
 
-uint64_t ws_cache_limit() {
-  static const uint64_t lim = [] {
-    const char* e = getenv("BURR_WORKSPACE_CACHE_BYTES");
-    return e ? strtoull(e, nullptr, 10) : (16ull << 30);
-  }();
-  return lim;
+uint64_t ws_cache_limit(int dev) {
+  static const char* env = getenv("BURR_WORKSPACE_CACHE_BYTES");
+  if (env) return strtoull(env, nullptr, 10);
+  static uint64_t lim[kMaxDevices] = {};  // read under g_ws_mu
+  if (!lim[dev]) {
+    size_t total = 0;
+    if (hipDeviceTotalMem(&total, dev) != hipSuccess || total == 0) total = 64ull << 30;
+    lim[dev] = total / 4;
+  }
+  return lim[dev];
 }
 
 // The workspace of one build: taken from the cache unless the caller
@@ -603,7 +622,7 @@ struct WsLease {
     std::unique_lock<std::mutex> lk(g_ws_mu);
     uint64_t held = ws->bytes;
     for (Workspace* w : g_ws_free[dev]) held += w->bytes;
-    if (held <= ws_cache_limit()) {
+    if (held <= ws_cache_limit(dev)) {
       g_ws_free[dev].push_back(ws);
       return;
     }
@@ -749,9 +768,11 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
 
     std::vector<uint32_t> next_active;
     std::vector<uint64_t> next_n;
+    LS.ids = active;
+    LS.ml.resize(active.size());
     for (size_t a = 0; a < active.size(); ++a) {
       Member& mb = b->members[active[a]];
-      MemberLayer& L = mb.layer[li];
+      MemberLayer& L = LS.ml[a];
       L.n = cur_n[a];
       L.m = t.span[a] + kWidth - 1;
       L.R = t.range_base[a + 1] - t.range_base[a];
@@ -847,7 +868,7 @@ QueryPlan make_plan(const burr_batch* b, const Member& mb) {
   plan.r = mb.r;
   uint32_t l = 0;
   for (; l < mb.built; ++l) {
-    const MemberLayer& L = mb.layer[l];
+    const MemberLayer& L = layer_of(b, (uint32_t)(&mb - b->members.data()), l);
     QueryLayer& q = plan.layer[l];
     q.salt_s = mix64(b->p.seed ^ (2ull * l + 1ull));
     q.salt_c = mix64(b->p.seed ^ (2ull * l + 2ull));
@@ -1105,7 +1126,7 @@ int burr_get_stats(const burr_handle* h, burr_stats* st) {
   uint64_t bytes = 0;
   double ms_sort = 0, ms_solve = 0;
   for (uint32_t i = 0; i < mb->built; ++i) {
-    const MemberLayer& L = mb->layer[i];
+    const MemberLayer& L = layer_of(b, h->idx, i);
     const LayerStore& LS = b->layers[i];
     st->layer[i].n = L.n;
     st->layer[i].m = L.m;
@@ -1154,7 +1175,7 @@ int burr_export(const burr_handle* h, void* host_buf, size_t cap, size_t* needed
   };
   const bool fill = host_buf != nullptr;
   for (uint32_t l = 0; l < mb->built; ++l) {
-    const MemberLayer& L = mb->layer[l];
+    const MemberLayer& L = layer_of(b, h->idx, l);
     o.put(L.n, 8);
     o.put(L.m, 8);
     o.put(L.R, 8);
@@ -1236,7 +1257,9 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
   };
   bool ok = in.ok;
   for (uint32_t l = 0; ok && l < mb.built; ++l) {
-    MemberLayer& L = mb.layer[l];
+    b->layers[l].ids.assign(1, 0);
+    b->layers[l].ml.assign(1, MemberLayer{});
+    MemberLayer& L = b->layers[l].ml[0];
     L.n = in.get(8);
     L.m = in.get(8);
     L.R = in.get(8);
@@ -1277,8 +1300,9 @@ int64_t burr_debug_layer_keys(const burr_handle* h, uint32_t layer, uint64_t* ho
   const uint64_t* src;
   uint64_t n;
   if (layer < mb->built) {
-    src = h->b->layers[layer].keys + mb->layer[layer].key_off;
-    n = mb->layer[layer].n;
+    const MemberLayer& L = layer_of(h->b, h->idx, layer);
+    src = h->b->layers[layer].keys + L.key_off;
+    n = L.n;
   } else {
     src = mb->fin_keys;
     n = mb->fin.n;
