@@ -121,6 +121,16 @@ def lib():
         for fn in ("ref_layer_keys", "ref_layer_codes", "ref_layer_solution"):
             getattr(L, fn).restype = u64
             getattr(L, fn).argtypes = [vp, u32, vp, u64]
+        p64 = ctypes.POINTER(u64)
+        L.ref_layer_geometry.restype = None
+        L.ref_layer_geometry.argtypes = [ctypes.POINTER(_Params), u64, p64, p64, p64]
+        L.ref_range_buckets.restype = None
+        L.ref_range_buckets.argtypes = [u64, u64, u64, p64, p64]
+        L.ref_start_buckets.restype = None
+        L.ref_start_buckets.argtypes = [vp, u64, u32, u64, u64, u32, vp]
+        L.ref_layer_range.restype = ctypes.c_int
+        L.ref_layer_range.argtypes = [ctypes.POINTER(_Params), u32, u32, u64, u64, vp, vp, u64,
+                                      vp, vp, vp, p64]
         _lib = L
     return _lib
 
@@ -237,3 +247,56 @@ def hash_key(key: int, layer: int, m: int, seed: int) -> tuple[int, int]:
 
 def fingerprint(key: int, r: int, seed: int) -> int:
     return int(lib().ref_fingerprint(key, r, seed))
+
+
+def layer_geometry(params: Params, nkeys: int) -> tuple[int, int, int]:
+    """(slots m, buckets, ranges) of a BuRR layer entered by nkeys keys."""
+    m, B, R = ctypes.c_uint64(0), ctypes.c_uint64(0), ctypes.c_uint64(0)
+    cp = params._c()
+    lib().ref_layer_geometry(ctypes.byref(cp), nkeys, ctypes.byref(m), ctypes.byref(B),
+                             ctypes.byref(R))
+    return int(m.value), int(B.value), int(R.value)
+
+
+def range_buckets(nbuckets: int, nranges: int, rho: int) -> tuple[int, int]:
+    """Buckets [first, last) of range rho."""
+    f, l = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    lib().ref_range_buckets(nbuckets, nranges, rho, ctypes.byref(f), ctypes.byref(l))
+    return int(f.value), int(l.value)
+
+
+def start_buckets(keys: np.ndarray, layer: int, m: int, params: Params) -> np.ndarray:
+    """Start bucket of every key in layer `layer` of m slots (u32)."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    out = np.empty(len(keys), dtype=np.uint32)
+    if len(keys):
+        lib().ref_start_buckets(keys.ctypes.data, len(keys), layer, m, params.seed,
+                                params.bucket, out.ctypes.data)
+    return out
+
+
+def layer_range(keys: np.ndarray, values: np.ndarray | None, r: int, params: Params,
+                layer: int, n_layer: int, rho: int) -> dict:
+    """Range rho of layer `layer` (entered by n_layer keys) solved on its own
+    from the keys that start in it: threshold codes per bucket, the range's
+    column-interleaved solution words and its bumped keys."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    m, B, R = layer_geometry(params, n_layer)
+    first, last = range_buckets(B, R, rho)
+    codes = np.zeros(last - first, dtype=np.uint8)
+    W = np.zeros((last - first) * params.bucket // 64 * r + 1, dtype=np.uint64)
+    bumped = np.zeros(len(keys) + 1, dtype=np.uint64)
+    nb = ctypes.c_uint64(0)
+    vptr = None
+    if values is not None:
+        values = np.ascontiguousarray(values, dtype=value_dtype(r))
+        vptr = values.ctypes.data
+    cp = params._c()
+    rc = lib().ref_layer_range(ctypes.byref(cp), r, layer, n_layer, rho,
+                               keys.ctypes.data if len(keys) else None, vptr, len(keys),
+                               codes.ctypes.data, W.ctypes.data, bumped.ctypes.data,
+                               ctypes.byref(nb))
+    if rc != OK:
+        raise OracleError(rc)
+    return {"first": first, "last": last, "codes": codes, "W": W[:-1],
+            "bumped": bumped[:int(nb.value)]}

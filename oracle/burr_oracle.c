@@ -237,6 +237,82 @@ static int ref_pos_cmp(const void* a, const void* b) {
 /* ------------------------------------------------------------------------ */
 
 /*
+ * Range rho of a layer with B buckets cut into R ranges: its buckets
+ * [first, last) are processed in order (thresholds, chunks and forced bumps
+ * as described at ref_build_layer). The rows live in C/V, which cover the
+ * slot window [base, base + mwin): slot s is C[s - base]. order lists the
+ * keys of these buckets sorted by start slot; bstart[beta - bbase] is the
+ * first position of bucket beta in order and codes[beta - bbase] receives its
+ * threshold code. bump[idx] is set for every bumped key (idx = the key's
+ * order[].idx); placed is scratch of one entry per key.
+ */
+static void ref_solve_range(const ref_params* p, uint64_t B, uint64_t R, uint64_t rho,
+                            const ref_pos* order, const uint64_t* bstart, uint64_t bbase,
+                            const uint64_t* coef, const uint32_t* vals, uint64_t* C,
+                            uint32_t* V, uint64_t mwin, uint64_t base, uint8_t* codes,
+                            uint8_t* bump, uint64_t* placed, ref_layer_info* info) {
+  const uint64_t b = p->bucket;
+  const uint64_t theta[4] = {0, p->t_lo, p->t_hi, b};
+  uint64_t first = ref_range_first_bucket(rho, B, R);
+  uint64_t last = ref_range_first_bucket(rho + 1, B, R); /* exclusive */
+  uint64_t range_end = last * b;                         /* slot */
+  for (uint64_t beta = first; beta < last; beta++) {
+    uint64_t lo = bstart[beta - bbase], hi = bstart[beta - bbase + 1];
+    /* forced bumps: only in a range's last bucket, never in the last range */
+    unsigned kf = 0;
+    if (rho + 1 < R && beta + 1 == last) {
+      int any = 0;
+      uint64_t omax = 0;
+      for (uint64_t t = lo; t < hi; t++) {
+        uint64_t s = order[t].s;
+        if (s + REF_W > range_end) { /* s > range_end - w */
+          any = 1;
+          if (s - beta * b > omax) omax = s - beta * b;
+        }
+      }
+      if (any) {
+        kf = 4; /* smallest theta above omax; theta[3] = b > omax always */
+        for (unsigned k = 0; k < 4; k++)
+          if (theta[k] > omax) { kf = k; break; }
+      }
+    }
+    unsigned code = kf;
+    for (unsigned k = 3; k > kf; k--) {
+      uint64_t nplaced = 0;
+      int conflict = 0;
+      for (uint64_t t = lo; t < hi && !conflict; t++) {
+        uint64_t s = order[t].s;
+        uint64_t o = s - beta * b;
+        if (o < theta[k - 1] || o >= theta[k]) continue;
+        uint64_t id = order[t].idx;
+        uint64_t at = 0;
+        int res = ref_insert(C, V, mwin, s - base, coef[id], vals[id], &at, &info->steps);
+        if (res == INS_PLACED) placed[nplaced++] = at;
+        else if (res == INS_REDUNDANT) info->redundant++;
+        else conflict = 1;
+      }
+      if (conflict) {
+        for (uint64_t u = 0; u < nplaced; u++) {
+          C[placed[u]] = 0;
+          V[placed[u]] = 0;
+        }
+        code = k;
+        break;
+      }
+    }
+    codes[beta - bbase] = (uint8_t)code;
+    for (uint64_t t = lo; t < hi; t++) {
+      uint64_t o = order[t].s - beta * b;
+      if (o < theta[code]) {
+        bump[order[t].idx] = 1;
+        info->bumped++;
+        if (beta + 1 == last && rho + 1 < R && order[t].s + REF_W > range_end) info->forced++;
+      }
+    }
+  }
+}
+
+/*
  * Builds layer `li` from keys/vals (n of them). Returns the bumped keys in
  * *next_keys / *next_vals (malloc'd) and their count in *next_n.
  *
@@ -267,7 +343,6 @@ static int ref_build_layer(ref_burr* h, uint32_t li, const uint64_t* keys,
   const uint64_t m = ref_layer_slots(p, n);
   const uint64_t B = m / b;
   const uint64_t R = ref_layer_ranges(p, B);
-  const uint64_t theta[4] = {0, p->t_lo, p->t_hi, b};
 
   memset(&L->info, 0, sizeof(L->info));
   L->info.n = n;
@@ -307,66 +382,9 @@ static int ref_build_layer(ref_burr* h, uint32_t li, const uint64_t* keys,
   }
 
   /* 3. ranges, buckets, chunks */
-  for (uint64_t rho = 0; rho < R; rho++) {
-    uint64_t first = ref_range_first_bucket(rho, B, R);
-    uint64_t last = ref_range_first_bucket(rho + 1, B, R); /* exclusive */
-    uint64_t range_end = last * b;                         /* slot */
-    for (uint64_t beta = first; beta < last; beta++) {
-      uint64_t lo = bstart[beta], hi = bstart[beta + 1];
-      /* forced bumps: only in a range's last bucket, never in the last range */
-      unsigned kf = 0;
-      if (rho + 1 < R && beta + 1 == last) {
-        int any = 0;
-        uint64_t omax = 0;
-        for (uint64_t t = lo; t < hi; t++) {
-          uint64_t s = order[t].s;
-          if (s + REF_W > range_end) { /* s > range_end - w */
-            any = 1;
-            if (s - beta * b > omax) omax = s - beta * b;
-          }
-        }
-        if (any) {
-          kf = 4; /* smallest theta above omax; theta[3] = b > omax always */
-          for (unsigned k = 0; k < 4; k++)
-            if (theta[k] > omax) { kf = k; break; }
-        }
-      }
-      unsigned code = kf;
-      for (unsigned k = 3; k > kf; k--) {
-        uint64_t nplaced = 0;
-        int conflict = 0;
-        for (uint64_t t = lo; t < hi && !conflict; t++) {
-          uint64_t s = order[t].s;
-          uint64_t o = s - beta * b;
-          if (o < theta[k - 1] || o >= theta[k]) continue;
-          uint64_t id = order[t].idx;
-          uint64_t at = 0;
-          int res = ref_insert(C, V, m, s, coef[id], vals[id], &at, &L->info.steps);
-          if (res == INS_PLACED) placed[nplaced++] = at;
-          else if (res == INS_REDUNDANT) L->info.redundant++;
-          else conflict = 1;
-        }
-        if (conflict) {
-          for (uint64_t u = 0; u < nplaced; u++) {
-            C[placed[u]] = 0;
-            V[placed[u]] = 0;
-          }
-          code = k;
-          break;
-        }
-      }
-      L->code[beta] = (uint8_t)code;
-      for (uint64_t t = lo; t < hi; t++) {
-        uint64_t o = order[t].s - beta * b;
-        if (o < theta[code]) {
-          bump[order[t].idx] = 1;
-          L->info.bumped++;
-          if (beta + 1 == last && rho + 1 < R && order[t].s + REF_W > range_end)
-            L->info.forced++;
-        }
-      }
-    }
-  }
+  for (uint64_t rho = 0; rho < R; rho++)
+    ref_solve_range(p, B, R, rho, order, bstart, 0, coef, vals, C, V, m, 0, L->code, bump,
+                    placed, &L->info);
   for (uint64_t i = 0; i < m; i++) L->info.pivots += (C[i] != 0);
   /* redundant count above includes equations later undone with their chunk;
    * recount them exactly: kept = n - bumped = pivots + redundant */
@@ -536,6 +554,94 @@ int ref_build(const uint64_t* keys, const void* values, uint64_t n, uint32_t r,
   if (rc != REF_OK) { ref_free(h); return rc; }
   *out = h;
   return REF_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One range of a layer on its own (Sec. 3: once the keys whose rows could   */
+/* cross a range end are bumped, the ranges solve independently). Used for  */
+/* sampled checks of structures too large for a whole oracle build.          */
+/* ------------------------------------------------------------------------ */
+
+void ref_layer_geometry(const ref_params* p, uint64_t nkeys, uint64_t* m, uint64_t* nbuckets,
+                        uint64_t* nranges) {
+  *m = ref_layer_slots(p, nkeys);
+  *nbuckets = *m / p->bucket;
+  *nranges = ref_layer_ranges(p, *nbuckets);
+}
+
+void ref_range_buckets(uint64_t nbuckets, uint64_t nranges, uint64_t rho, uint64_t* first,
+                       uint64_t* last) {
+  *first = ref_range_first_bucket(rho, nbuckets, nranges);
+  *last = ref_range_first_bucket(rho + 1, nbuckets, nranges);
+}
+
+void ref_start_buckets(const uint64_t* keys, uint64_t n, uint32_t layer, uint64_t m,
+                       uint64_t seed, uint32_t bucket, uint32_t* out) {
+  for (uint64_t i = 0; i < n; i++) {
+    uint64_t s, c;
+    ref_hash(keys[i], layer, m, seed, &s, &c);
+    out[i] = (uint32_t)(s / bucket);
+  }
+}
+
+int ref_layer_range(const ref_params* p, uint32_t r, uint32_t layer, uint64_t n_layer,
+                    uint64_t rho, const uint64_t* keys, const void* values, uint64_t n,
+                    uint8_t* codes, uint64_t* W, uint64_t* bumped, uint64_t* nbumped) {
+  if (!ref_params_valid(p, r, values) || layer >= p->layers || n > n_layer) return REF_E_INVALID;
+  if (n > 0 && keys == NULL) return REF_E_INVALID;
+  const uint64_t b = p->bucket;
+  uint64_t m, B, R, first, last;
+  ref_layer_geometry(p, n_layer, &m, &B, &R);
+  if (rho >= R) return REF_E_INVALID;
+  ref_range_buckets(B, R, rho, &first, &last);
+  /* rows of kept keys stay inside the range: forced bumps keep them off its
+   * end, and in the last range s <= m - w */
+  const uint64_t base = first * b, mwin = (last - first) * b;
+  uint64_t* C = (uint64_t*)calloc(mwin, sizeof(uint64_t));
+  uint32_t* V = (uint32_t*)calloc(mwin, sizeof(uint32_t));
+  uint32_t* Z = (uint32_t*)calloc(mwin, sizeof(uint32_t));
+  ref_pos* order = (ref_pos*)malloc((n + 1) * sizeof(ref_pos));
+  uint64_t* coef = (uint64_t*)malloc((n + 1) * sizeof(uint64_t));
+  uint32_t* vals = (uint32_t*)malloc((n + 1) * sizeof(uint32_t));
+  uint64_t* bstart = (uint64_t*)calloc(last - first + 1, sizeof(uint64_t));
+  uint8_t* bump = (uint8_t*)calloc(n + 1, 1);
+  uint64_t* placed = (uint64_t*)malloc((n + 1) * sizeof(uint64_t));
+  int rc = REF_OK;
+  if (!C || !V || !Z || !order || !coef || !vals || !bstart || !bump || !placed) {
+    rc = REF_E_NOMEM;
+    goto done;
+  }
+  for (uint64_t i = 0; i < n; i++) {
+    uint64_t s, c;
+    ref_hash(keys[i], layer, m, p->seed, &s, &c);
+    if (s < base || s >= base + mwin) {
+      rc = REF_E_INVALID; /* the key belongs to another range */
+      goto done;
+    }
+    order[i].s = s;
+    order[i].idx = i;
+    coef[i] = c;
+    vals[i] = p->filter_mode ? ref_fingerprint(keys[i], r, p->seed)
+                             : (ref_value_at(values, r, i) & ref_mask(r));
+  }
+  qsort(order, n, sizeof(ref_pos), ref_pos_cmp);
+  for (uint64_t i = 0, beta = first; beta <= last; beta++) {
+    while (i < n && order[i].s / b < beta) i++;
+    bstart[beta - first] = i;
+  }
+  ref_layer_info info;
+  memset(&info, 0, sizeof(info));
+  ref_solve_range(p, B, R, rho, order, bstart, first, coef, vals, C, V, mwin, base, codes, bump,
+                  placed, &info);
+  ref_back_substitute(C, V, Z, mwin);
+  ref_interleave(Z, mwin, r, W);
+  *nbumped = 0;
+  for (uint64_t i = 0; i < n; i++)
+    if (bump[i]) bumped[(*nbumped)++] = keys[i];
+done:
+  free(C); free(V); free(Z); free(order); free(coef); free(vals); free(bstart); free(bump);
+  free(placed);
+  return rc;
 }
 
 /* ------------------------------------------------------------------------ */

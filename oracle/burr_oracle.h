@@ -89,6 +89,26 @@ int ref_build(const uint64_t* keys, const void* values, uint64_t n, uint32_t r,
               const ref_params* p, ref_burr** out);
 void ref_free(ref_burr* h);
 
+/* Layer geometry of a BuRR layer entered by nkeys keys: slots, buckets and
+ * ranges (Sec. 3: equal bucket-aligned ranges of at least minbpt buckets). */
+void ref_layer_geometry(const ref_params* p, uint64_t nkeys, uint64_t* m, uint64_t* nbuckets,
+                        uint64_t* nranges);
+/* Buckets [first, last) of range rho. */
+void ref_range_buckets(uint64_t nbuckets, uint64_t nranges, uint64_t rho, uint64_t* first,
+                       uint64_t* last);
+/* Start bucket s / bucket of each key in layer `layer` of m slots. */
+void ref_start_buckets(const uint64_t* keys, uint64_t n, uint32_t layer, uint64_t m,
+                       uint64_t seed, uint32_t bucket, uint32_t* out);
+/* Range rho of layer `layer` (< p->layers) entered by n_layer keys, solved on
+ * its own from the n keys whose start slot lies in it (values as for
+ * ref_build; ignored in filter mode). Writes the range's threshold codes (one
+ * byte per bucket), its column-interleaved solution words ((last - first) *
+ * bucket / 64 * r words) and its bumped keys in input order (cap n).
+ * REF_E_INVALID if a key starts outside the range. */
+int ref_layer_range(const ref_params* p, uint32_t r, uint32_t layer, uint64_t n_layer,
+                    uint64_t rho, const uint64_t* keys, const void* values, uint64_t n,
+                    uint8_t* codes, uint64_t* W, uint64_t* bumped, uint64_t* nbumped);
+
 /* Query n keys; out has the value width of r (u8/u16/u32). */
 int ref_query(const ref_burr* h, const uint64_t* keys, uint64_t n, void* out);
 

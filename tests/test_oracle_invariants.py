@@ -245,3 +245,52 @@ def test_config_geometry_examples():
     assert layer_geometry(p2, 10 ** 8)[:3] == (97_000_000, 1_515_625, 65_536)
     p3 = oracle.Params(ranges=1 << 18)
     assert layer_geometry(p3, 10 ** 9)[:3] == (970_000_000, 15_156_250, 262_144)
+
+
+@pytest.mark.parametrize("n,r,layer,kw", [
+    (30_000, 8, 0, dict(ranges=16)),
+    (30_000, 8, 1, dict(ranges=16, minbpt=2)),
+    (20_000, 1, 0, dict(ranges=9, minbpt=3, filter_mode=1, seed=4)),
+    (24_000, 16, 0, dict(ranges=6, bucket=128, t_lo=32, t_hi=64)),
+    (3_000, 5, 0, dict(ranges=1)),
+])
+def test_range_entry_point_matches_whole_build(n, r, layer, kw):
+    # The one-range entry point (used for sampled checks of very large
+    # builds) reproduces the whole build's layer range by range: codes,
+    # solution words and bumped keys.
+    p = oracle.Params(**kw)
+    keys = W.keys(n, 21)
+    vals = W.values(n, r, 1021)
+    ref = oracle.build(keys, None if p.filter_mode else vals, r, p)
+    magic, hdr, seed, nn, layers, fin = _parse_export(ref.export(), r)
+    lk = ref.layer_keys(layer)
+    n_layer = len(lk)
+    m, B, R, first = layer_geometry(p, n_layer)
+    assert oracle.layer_geometry(p, n_layer) == (m, B, R)
+    assert layers[layer]["m"] == m and layers[layer]["R"] == R
+    value_of = dict(zip(keys.tolist(), vals.tolist()))
+    lv = np.array([value_of[int(k)] for k in lk], dtype=vals.dtype)
+    sb = oracle.start_buckets(lk, layer, m, p)
+    assert all(sb[i] == oracle.hash_key(int(lk[i]), layer, m, p.seed)[0] // p.bucket
+               for i in range(0, n_layer, 97))
+    codes = ref.layer_codes(layer)
+    words = np.array(layers[layer]["words"], dtype=np.uint64)
+    bumped = set(ref.layer_keys(layer + 1).tolist()) if layer + 1 < ref.layers_built else \
+        set(ref.layer_keys(ref.layers_built).tolist())
+    got_bumped = set()
+    wpb = p.bucket // 64 * r  # solution words per bucket
+    for rho in range(R):
+        assert oracle.range_buckets(B, R, rho) == (first[rho], first[rho + 1])
+        sel = (sb >= first[rho]) & (sb < first[rho + 1])
+        out = oracle.layer_range(lk[sel], None if p.filter_mode else lv[sel], r, p, layer,
+                                 n_layer, rho)
+        assert np.array_equal(out["codes"], codes[first[rho]:first[rho + 1]])
+        assert np.array_equal(out["W"], words[first[rho] * wpb:first[rho + 1] * wpb])
+        got_bumped |= set(out["bumped"].tolist())
+    assert got_bumped == bumped
+    # a key of another range is rejected
+    if R > 1:
+        sel = sb < first[1]
+        with pytest.raises(oracle.OracleError):
+            oracle.layer_range(lk[sel], None if p.filter_mode else lv[sel], r, p, layer,
+                               n_layer, 1)

@@ -28,7 +28,7 @@ MUTANTS = {
     "final_scale": ("(uint64_t)a * p->final_den", "(uint64_t)a * p->final_den * 0"),
     "row_not_anchored": ("*coeff = ref_fmix64(key ^ salt_c) | 1ull;",
                          "*coeff = ref_fmix64(key ^ salt_c) | 2ull;"),
-    "code_shifted": ("code = k;\n          break;", "code = k - 1;\n          break;"),
+    "code_shifted": ("code = k;\n        break;", "code = k - 1;\n        break;"),
     "redundant_is_conflict": ("return v == 0 ? INS_REDUNDANT : INS_CONFLICT;",
                               "return INS_CONFLICT;"),
     "query_threshold": ("if (o < theta[L->code[beta]]) continue;",
