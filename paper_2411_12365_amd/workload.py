@@ -29,6 +29,36 @@ def splitmix64(seed: int, start: int, count: int) -> np.ndarray:
     return z
 
 
+def _signed(x: int) -> int:
+    x &= 0xFFFFFFFFFFFFFFFF
+    return x - (1 << 64) if x >> 63 else x
+
+
+def splitmix64_device(seed: int, start: int, count: int, device, chunk: int = 1 << 27):
+    """The same stream as splitmix64(), computed with torch int64 arithmetic
+    on `device` (products wrap modulo 2^64; right shifts are made logical by
+    masking). Returns an int64 tensor holding the u64 bit patterns."""
+    import torch
+    out = torch.empty(count, dtype=torch.int64, device=device)
+
+    def lsr(z, k):
+        return (z >> k) & ((1 << (64 - k)) - 1)
+
+    for lo in range(0, count, chunk):
+        c = min(chunk, count - lo)
+        z = torch.arange(start + lo + 1, start + lo + c + 1, dtype=torch.int64, device=device)
+        z = z * _signed(int(_GAMMA)) + _signed(seed)
+        z = (z ^ lsr(z, 30)) * _signed(int(_M1))
+        z = (z ^ lsr(z, 27)) * _signed(int(_M2))
+        out[lo:lo + c] = z ^ lsr(z, 31)
+    return out
+
+
+def keys_device(n: int, seed: int, device, start: int = 0):
+    """keys(n, seed, start) generated on `device` (int64 tensor)."""
+    return splitmix64_device(seed, start, n, device)
+
+
 def value_dtype(r: int):
     return np.uint8 if r <= 8 else (np.uint16 if r <= 16 else np.uint32)
 
