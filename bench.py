@@ -102,8 +102,13 @@ def _device_stream(gen, n, dtype, dev, chunk=100_000_000):
     return out
 
 
+TUNE_CLASSES = [250, 1000, 4000, 16_000, 64_000, 200_000]  # size classes (max keys)
+TUNE_CANDIDATES = [2, 4, 8, 16, 32, 64]                     # minimum buckets per range
+
+
 def run_batched(args, dev):
-    """Many small structures: one batched build against one build per structure."""
+    """Many small structures: one batched build against one build per structure,
+    with the range split per size class picked by the autotuner."""
     import numpy as np
     import torch
     import paper_2411_12365_amd as burr
@@ -118,16 +123,28 @@ def run_batched(args, dev):
                           .astype(np.uint8), N, torch.uint8, dev)
     torch.cuda.synchronize()
     params = burr.Params(ranges=1 << 16)
+    print(f"# batched: autotune over {len(TUNE_CLASSES)} size classes", file=sys.stderr,
+          flush=True)
+    t0 = time.perf_counter()
+    table = burr.autotune(2, TUNE_CLASSES, TUNE_CANDIDATES, keys_per_trial=args.tune_keys,
+                          reps=2, params=params)
+    t_tune = time.perf_counter() - t0
     print(f"# batched: {count} structures, {N} keys", file=sys.stderr, flush=True)
-    b = burr.build_batch(keys, vals, offs, rs, params)
+
+    def timed(build):
+        build().free()
+        times = []
+        for k in range(args.batch_steps):
+            t0 = time.perf_counter()
+            b = build()
+            times.append(time.perf_counter() - t0)
+            if k + 1 < args.batch_steps:
+                b.free()
+        return b, np.array(times) * 1e3
+
+    b, ms_default = timed(lambda: burr.build_batch(keys, vals, offs, rs, params))
     b.free()
-    times = []
-    for _ in range(args.batch_steps):
-        t0 = time.perf_counter()
-        b = burr.build_batch(keys, vals, offs, rs, params)
-        times.append(time.perf_counter() - t0)
-        if len(times) < args.batch_steps:
-            b.free()
+    b, ms = timed(lambda: burr.build_batch_tuned(keys, vals, offs, rs, table, params))
     # spot check: members of sampled structures retrieve their values
     ok = True
     for i in np.linspace(0, count - 1, 64).astype(int):
@@ -136,35 +153,49 @@ def run_batched(args, dev):
         ok &= bool(torch.equal(got, vals[lo:hi] & ((1 << int(rs[i])) - 1)))
     st = b.member(0).stats()
     b.free()
-    # per-structure baseline on the first S structures, and the batch on the same S
+    # per-structure baseline on the first S structures (each with its tuned
+    # range split), and the batch on the same S
     S = min(args.batch_single_sample, count)
+    bounds = np.array([e["n_max"] for e in table])
+
+    def minbpt_of(n):
+        k = int(np.searchsorted(bounds, n))
+        return int(table[min(k, len(table) - 1)]["minbpt"])
+
     t0 = time.perf_counter()
     for i in range(S):
         lo, hi = int(offs[i]), int(offs[i + 1])
-        h = burr.build(keys[lo:hi], vals[lo:hi], int(rs[i]), params)
+        p1 = burr.Params(ranges=1 << 16, minbpt=minbpt_of(hi - lo))
+        h = burr.build(keys[lo:hi], vals[lo:hi], int(rs[i]), p1)
         h.free()
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t0
-    bs = burr.build_batch(keys[:int(offs[S])], vals[:int(offs[S])], offs[:S + 1], rs[:S], params)
-    bs.free()
+    kS, vS = keys[:int(offs[S])], vals[:int(offs[S])]
+    burr.build_batch_tuned(kS, vS, offs[:S + 1], rs[:S], table, params).free()
     t0 = time.perf_counter()
-    bs = burr.build_batch(keys[:int(offs[S])], vals[:int(offs[S])], offs[:S + 1], rs[:S], params)
+    bs = burr.build_batch_tuned(kS, vS, offs[:S + 1], rs[:S], table, params)
     t_sample = time.perf_counter() - t0
     bs.free()
-    ms = np.array(times) * 1e3
     return {
         "workload": f"{count} structures, log-normal sizes (median 2000, clipped 100..200000), "
-                    f"{N} keys, r uniform in {{1,2,3}}, one batched build, {args.batch_steps} "
-                    f"timed builds",
+                    f"{N} keys, r uniform in {{1,2,3}}, one batched build with the autotuned "
+                    f"range split, {args.batch_steps} timed builds",
         "structures": count, "keys": N,
-        "builds_per_s": round(count / float(np.mean(times)), 1),
-        "Mkeys_per_s": round(N / float(np.mean(times)) / 1e6, 1),
+        "builds_per_s": round(count / float(np.mean(ms) / 1e3), 1),
+        "Mkeys_per_s": round(N / float(np.mean(ms) / 1e3) / 1e6, 1),
         "build_ms_p50": round(float(np.percentile(ms, 50)), 2),
         "build_ms_max": round(float(ms.max()), 2),
+        "untuned_minbpt16_build_ms_p50": round(float(np.percentile(ms_default, 50)), 2),
         "members_ok": ok,
         "layer0_device_ms": {k: round(st["layers"][0][k], 3) for k in
                              ("ms_sort", "ms_solve", "ms_backsub", "ms_gather")},
         "device_total_ms": round(st["ms_total"], 2),
+        "autotune": {"seconds": round(t_tune, 2), "keys_per_trial": args.tune_keys,
+                     "value_bits": 2, "candidates_minbpt": TUNE_CANDIDATES,
+                     "classes": [{"n_max": int(e["n_max"]), "minbpt": int(e["minbpt"]),
+                                  "ns_per_key": round(e["ns_per_key"], 3),
+                                  "bits_per_key": round(e["bits_per_key"], 3)}
+                                 for e in table]},
         "per_structure_baseline": {
             "structures": S, "keys": int(offs[S]),
             "one_build_per_structure_builds_per_s": round(S / t_single, 1),
@@ -315,6 +346,8 @@ def main():
     ap.add_argument("--batch-single-sample", type=int, default=2000,
                     help="structures built one by one for the per-structure baseline")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--tune-keys", type=int, default=200_000_000,
+                    help="keys per autotuner trial batch")
     ap.add_argument("--serve-builds", type=int, default=200,
                     help="build requests per load level (8 query batches per build)")
     ap.add_argument("--serve-loads", type=str, default="0.5,0.8,0.95")

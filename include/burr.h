@@ -160,6 +160,45 @@ burr_batch* burr_build_batch(const uint64_t* keys, const void* values,
                              const uint64_t* host_offsets, const uint32_t* host_r,
                              uint32_t count, const burr_params* p);
 
+/* One size class of a tuning table: structures with up to n_max keys (in the
+ * last class also any larger ones) keep at least minbpt buckets per range.
+ * ns_per_key and bits_per_key are what burr_autotune measured for this
+ * choice (informational). */
+typedef struct burr_tune_entry {
+  uint64_t n_max;
+  uint32_t minbpt;
+  uint32_t reserved;
+  double ns_per_key;
+  double bits_per_key;
+} burr_tune_entry;
+
+/* burr_build_batch with each structure's minimum buckets per range (Sec. 3
+ * "Minimum Buckets per Thread": it fixes how many ranges, hence boundary
+ * bumps, a layer has) taken from the size class of `table` (entries
+ * ascending in n_max) that holds its key count, instead of p->minbpt. Each
+ * member's export records its own value, so burr_build with that minbpt
+ * gives the same structure. BURR_E_INVALID if the table is empty, not
+ * strictly ascending or holds a zero minbpt. */
+burr_batch* burr_build_batch_tuned(const uint64_t* keys, const void* values,
+                                   const uint64_t* host_offsets, const uint32_t* host_r,
+                                   uint32_t count, const burr_params* p,
+                                   const burr_tune_entry* table, uint32_t entries);
+
+/* Autotuner of the range split per size class. For each class c (n_max[]
+ * ascending, nclasses of them) it builds batches of synthetic structures
+ * (uniform random keys and r-bit values, made on the device) whose size is
+ * the geometric middle of the class (from n_max[c-1], or n_max[0]/4, to
+ * n_max[c]), about keys_per_trial keys per batch, once per candidate
+ * minimum buckets per range (candidates[], ncandidates of them, each >= 1),
+ * with p's other settings on the current device and p->stream. Each choice
+ * is timed as the best of reps builds after one warm-up. out[c] keeps the
+ * fastest candidate or, among those within 3 % of it, the one with the
+ * smallest tables (bits per key). Allocates and frees device memory for the
+ * synthetic inputs. BURR_OK, or BURR_E_INVALID / NOMEM / DEVICE. */
+int burr_autotune(const burr_params* p, uint32_t r, const uint64_t* n_max, uint32_t nclasses,
+                  const uint32_t* candidates, uint32_t ncandidates, uint64_t keys_per_trial,
+                  uint32_t reps, burr_tune_entry* out);
+
 /* Number of structures in a batch (0 for NULL). */
 uint32_t burr_batch_size(const burr_batch* b);
 

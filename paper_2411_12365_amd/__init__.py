@@ -35,7 +35,8 @@ _EXPORTS = ("burr_default_params", "burr_build", "burr_query", "burr_contains", 
             "burr_server_default_config", "burr_server_create", "burr_server_submit_build",
             "burr_server_submit_query", "burr_server_poll", "burr_server_drain",
             "burr_server_drop", "burr_server_handle", "burr_server_get_info",
-            "burr_server_destroy", "burr_release_workspaces")
+            "burr_server_destroy", "burr_release_workspaces", "burr_build_batch_tuned",
+            "burr_autotune")
 
 
 class BurrError(RuntimeError):
@@ -72,6 +73,12 @@ class _CStats(ctypes.Structure):
         ("ms_sort", ctypes.c_double), ("ms_solve", ctypes.c_double),
         ("ms_final", ctypes.c_double), ("ms_total", ctypes.c_double),
     ]
+
+
+class _CTuneEntry(ctypes.Structure):
+    _fields_ = [("n_max", ctypes.c_uint64), ("minbpt", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("ns_per_key", ctypes.c_double),
+                ("bits_per_key", ctypes.c_double)]
 
 
 class _CServerConfig(ctypes.Structure):
@@ -148,6 +155,12 @@ def lib():
         L.burr_debug_layer_keys.restype = ctypes.c_int64
         L.burr_build_batch.argtypes = [vp, vp, vp, vp, u32, ctypes.POINTER(_CParams)]
         L.burr_build_batch.restype = vp
+        L.burr_build_batch_tuned.argtypes = [vp, vp, vp, vp, u32, ctypes.POINTER(_CParams),
+                                             ctypes.POINTER(_CTuneEntry), u32]
+        L.burr_build_batch_tuned.restype = vp
+        L.burr_autotune.argtypes = [ctypes.POINTER(_CParams), u32, vp, u32, vp, u32, u64, u32,
+                                    ctypes.POINTER(_CTuneEntry)]
+        L.burr_autotune.restype = ctypes.c_int
         L.burr_batch_size.argtypes = [vp]
         L.burr_batch_size.restype = u32
         L.burr_batch_member.argtypes = [vp, u32]
@@ -295,15 +308,9 @@ class Batch:
             self._b = None
 
 
-def burr_build_batch(keys, values, offsets, rs, params: Params | None = None,
-                     stream=None) -> Batch:
-    """keys: GPU int64/uint64 tensor holding every structure's keys back to
-    back; offsets: host sequence of len(rs)+1 key offsets (offsets[0] = 0);
-    rs: value bits per structure; values: GPU tensor laid out like keys with
-    the value dtype of max(rs), or None in filter mode."""
+def _batch_args(keys, values, offsets, rs):
     import numpy as np
     import torch
-    params = params or Params()
     _check_tensor(keys, "keys", (torch.int64, torch.uint64))
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
     rr = np.ascontiguousarray(np.asarray(rs, dtype=np.uint32))
@@ -317,12 +324,68 @@ def burr_build_batch(keys, values, offsets, rs, params: Params | None = None,
         if values.numel() != keys.numel():
             raise ValueError("keys and values differ in length")
         vptr = values.data_ptr() if values.numel() else None
+    return (keys.data_ptr() if keys.numel() else None), vptr, off, rr
+
+
+def burr_build_batch(keys, values, offsets, rs, params: Params | None = None,
+                     stream=None) -> Batch:
+    """keys: GPU int64/uint64 tensor holding every structure's keys back to
+    back; offsets: host sequence of len(rs)+1 key offsets (offsets[0] = 0);
+    rs: value bits per structure; values: GPU tensor laid out like keys with
+    the value dtype of max(rs), or None in filter mode."""
+    params = params or Params()
+    kptr, vptr, off, rr = _batch_args(keys, values, offsets, rs)
     cp = params.c(_stream_of(stream))
-    b = lib().burr_build_batch(keys.data_ptr() if keys.numel() else None, vptr,
-                               off.ctypes.data, rr.ctypes.data, len(rr), ctypes.byref(cp))
+    b = lib().burr_build_batch(kptr, vptr, off.ctypes.data, rr.ctypes.data, len(rr),
+                               ctypes.byref(cp))
     if not b:
         raise BurrError(lib().burr_last_error(), "burr_build_batch")
     return Batch(b, rr, params)
+
+
+def _tune_array(table):
+    arr = (_CTuneEntry * len(table))()
+    for i, e in enumerate(table):
+        arr[i].n_max = int(e["n_max"])
+        arr[i].minbpt = int(e["minbpt"])
+        arr[i].ns_per_key = float(e.get("ns_per_key", 0.0))
+        arr[i].bits_per_key = float(e.get("bits_per_key", 0.0))
+    return arr
+
+
+def burr_build_batch_tuned(keys, values, offsets, rs, table, params: Params | None = None,
+                           stream=None) -> Batch:
+    """burr_build_batch with each structure's minimum buckets per range from
+    the size class of `table` (a list of dicts with n_max and minbpt, as
+    returned by burr_autotune) that holds its key count."""
+    params = params or Params()
+    kptr, vptr, off, rr = _batch_args(keys, values, offsets, rs)
+    arr = _tune_array(table)
+    cp = params.c(_stream_of(stream))
+    b = lib().burr_build_batch_tuned(kptr, vptr, off.ctypes.data, rr.ctypes.data, len(rr),
+                                     ctypes.byref(cp), arr, len(table))
+    if not b:
+        raise BurrError(lib().burr_last_error(), "burr_build_batch_tuned")
+    return Batch(b, rr, params)
+
+
+def burr_autotune(r: int, n_max, candidates, keys_per_trial: int, reps: int = 2,
+                  params: Params | None = None, stream=None) -> list[dict]:
+    """Measures, per size class (upper bounds n_max, ascending), which
+    candidate minimum of buckets per range builds batches fastest; returns
+    the table for burr_build_batch_tuned."""
+    import numpy as np
+    params = params or Params()
+    nm = np.ascontiguousarray(np.asarray(n_max, dtype=np.uint64))
+    cand = np.ascontiguousarray(np.asarray(candidates, dtype=np.uint32))
+    out = (_CTuneEntry * max(len(nm), 1))()
+    cp = params.c(_stream_of(stream))
+    rc = lib().burr_autotune(ctypes.byref(cp), r, nm.ctypes.data, len(nm), cand.ctypes.data,
+                             len(cand), keys_per_trial, reps, out)
+    if rc != BURR_OK:
+        raise BurrError(rc, "burr_autotune")
+    return [{f: getattr(out[i], f) for f in ("n_max", "minbpt", "ns_per_key", "bits_per_key")}
+            for i in range(len(nm))]
 
 
 def burr_batch_size(b: Batch) -> int:
@@ -534,4 +597,6 @@ class Server:
 # short aliases
 build = burr_build
 build_batch = burr_build_batch
+build_batch_tuned = burr_build_batch_tuned
+autotune = burr_autotune
 import_ = burr_import

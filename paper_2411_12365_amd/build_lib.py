@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libburr.so")
-SOURCES = ["burr_kernels.hip", "burr_api.cpp", "burr_server.cpp"]
+SOURCES = ["burr_kernels.hip", "burr_api.cpp", "burr_server.cpp", "burr_tune.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

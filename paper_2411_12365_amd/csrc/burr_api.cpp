@@ -105,6 +105,7 @@ struct Member {
   uint64_t n = 0;
   uint32_t r = 0;
   uint32_t built = 0;  // BuRR layers with keys (their records sit in the layer stores)
+  uint32_t minbpt = 0;  // minimum buckets per range of this structure (0: the batch's)
   FinalLayer fin;
   uint64_t fin_attempt = 0;
   const uint64_t* fin_W = nullptr;
@@ -174,11 +175,13 @@ bool params_ok(const burr_params* p) {
 uint64_t ceil_div(unsigned __int128 a, unsigned __int128 b) { return (uint64_t)((a + b - 1) / b); }
 
 // BuRR layer: m = b * max(1, ceil(load * n / b)) slots, B = m/b buckets,
-// R = min(ranges, B / max(minbpt, 2)) ranges, at least 1.
-void plan_layer(const burr_params& p, uint64_t n, uint64_t* m, uint64_t* R) {
+// R = min(ranges, B / max(minbpt, 2)) ranges, at least 1 (minbpt: the
+// structure's own value, 0 = the parameter block's).
+void plan_layer(const burr_params& p, uint64_t n, uint64_t* m, uint64_t* R, uint32_t minbpt = 0) {
   uint64_t nb = ceil_div((unsigned __int128)n * p.load_num, (unsigned __int128)p.load_den * kBucket);
   if (nb < 1) nb = 1;
-  const uint64_t per = p.minbpt < 2 ? 2 : p.minbpt;
+  if (!minbpt) minbpt = p.minbpt;
+  const uint64_t per = minbpt < 2 ? 2 : minbpt;
   uint64_t r = nb / per;
   if (r > p.ranges) r = p.ranges;
   if (r < 1) r = 1;
@@ -685,7 +688,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     Table t;
     for (size_t a = 0; a < active.size(); ++a) {
       uint64_t m, R;
-      plan_layer(p, cur_n[a], &m, &R);
+      plan_layer(p, cur_n[a], &m, &R, b->members[active[a]].minbpt);
       t.add(cur_n[a], m, R, b->members[active[a]].r);
     }
     LayerGeom g{};
@@ -955,6 +958,15 @@ uint64_t estimate_table(uint64_t n, uint32_t r, const burr_params& p, uint64_t* 
 
 uint64_t burr_batch_device_bytes(const burr_batch* b) { return b ? b->table_bytes : 0; }
 
+uint64_t burr_batch_table_bits(const burr_batch* b) {
+  if (!b) return 0;
+  uint64_t words = 0;
+  for (const LayerStore& LS : b->layers)
+    for (const MemberLayer& L : LS.ml) words += L.ncode + L.nW;
+  for (const Member& mb : b->members) words += mb.fin.nW;
+  return words * 64;
+}
+
 int burr_set_error(int code) { return set_error(code); }
 
 uint64_t burr_workspace_bytes(uint64_t n, uint32_t rmax, uint32_t count, const burr_params* p,
@@ -1035,9 +1047,27 @@ burr_handle* burr_build(const uint64_t* keys, const void* values, uint64_t n, ui
   return &b->views[0];
 }
 
-burr_batch* burr_build_batch(const uint64_t* keys, const void* values,
-                             const uint64_t* host_offsets, const uint32_t* host_r,
-                             uint32_t count, const burr_params* p) {
+namespace {
+
+// minimum buckets per range of a structure with n keys: the first class of
+// the table that holds n, the last one for larger structures
+uint32_t tuned_minbpt(const burr_tune_entry* table, uint32_t entries, uint64_t n) {
+  uint32_t lo = 0, hi = entries - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (table[mid].n_max >= n)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return table[lo].minbpt;
+}
+
+// Batched build; with a table, each member's minimum buckets per range comes
+// from its size class (else the parameter block's applies).
+burr_batch* batch_entry(const uint64_t* keys, const void* values, const uint64_t* host_offsets,
+                        const uint32_t* host_r, uint32_t count, const burr_params* p,
+                        const burr_tune_entry* table, uint32_t entries) {
   if (!params_ok(p) || !host_offsets || !host_r || count == 0) {
     set_error(BURR_E_INVALID);
     return nullptr;
@@ -1060,8 +1090,10 @@ burr_batch* burr_build_batch(const uint64_t* keys, const void* values,
     return nullptr;
   }
   for (uint32_t i = 0; i < count; ++i) {
-    b->members[i].n = off[i + 1] - off[i];
-    b->members[i].r = host_r[i];
+    Member& mb = b->members[i];
+    mb.n = off[i + 1] - off[i];
+    mb.r = host_r[i];
+    mb.minbpt = table ? tuned_minbpt(table, entries, mb.n) : 0u;
   }
   const int rc = build_batch(b, keys, values, off);
   if (rc != BURR_OK) {
@@ -1071,6 +1103,30 @@ burr_batch* burr_build_batch(const uint64_t* keys, const void* values,
   }
   set_error(BURR_OK);
   return b;
+}
+
+}  // namespace
+
+burr_batch* burr_build_batch(const uint64_t* keys, const void* values,
+                             const uint64_t* host_offsets, const uint32_t* host_r,
+                             uint32_t count, const burr_params* p) {
+  return batch_entry(keys, values, host_offsets, host_r, count, p, nullptr, 0);
+}
+
+burr_batch* burr_build_batch_tuned(const uint64_t* keys, const void* values,
+                                   const uint64_t* host_offsets, const uint32_t* host_r,
+                                   uint32_t count, const burr_params* p,
+                                   const burr_tune_entry* table, uint32_t entries) {
+  if (!table || entries == 0) {
+    set_error(BURR_E_INVALID);
+    return nullptr;
+  }
+  for (uint32_t e = 0; e < entries; ++e)
+    if (table[e].minbpt == 0 || (e > 0 && table[e].n_max <= table[e - 1].n_max)) {
+      set_error(BURR_E_INVALID);
+      return nullptr;
+    }
+  return batch_entry(keys, values, host_offsets, host_r, count, p, table, entries);
 }
 
 uint32_t burr_batch_size(const burr_batch* b) { return b ? (uint32_t)b->members.size() : 0; }
@@ -1159,10 +1215,11 @@ int burr_export(const burr_handle* h, void* host_buf, size_t cap, size_t* needed
   const burr_batch* b = h->b;
   Out o{(uint8_t*)host_buf, host_buf ? cap : 0};
   const burr_params& p = b->p;
+  const uint32_t mb_minbpt = mb->minbpt ? mb->minbpt : p.minbpt;
   o.put(kExportMagic, 8);
   const uint32_t hdr[16] = {kExportVersion, kWidth,      p.bucket,    mb->r,    p.load_num,
                             p.load_den,     p.final_num, p.final_den, p.layers, p.t_lo,
-                            p.t_hi,         p.ranges,    p.minbpt,    p.final_attempts,
+                            p.t_hi,         p.ranges,    mb_minbpt,   p.final_attempts,
                             p.filter_mode,  mb->built};
   for (uint32_t x : hdr) o.put(x, 4);
   o.put(p.seed, 8);

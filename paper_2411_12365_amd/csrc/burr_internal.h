@@ -12,6 +12,10 @@ int burr_set_error(int code);
 // Device bytes a batch holds for its members' tables (all layers).
 uint64_t burr_batch_device_bytes(const burr_batch* b);
 
+// Table bits of all members of a batch: codes and solution words of every
+// layer, without allocation padding.
+uint64_t burr_batch_table_bits(const burr_batch* b);
+
 // Workspace bytes of one build of `count` structures with n keys in total
 // and largest value width rmax, including (staged != 0) a contiguous copy of
 // the inputs of structures that arrive in separate arrays.

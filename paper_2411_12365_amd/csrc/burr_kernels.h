@@ -127,6 +127,11 @@ hipError_t final_boundaries(const FinalArgs& a, hipStream_t s);
 hipError_t concat_inputs(const uint64_t* tab, uint32_t J, uint64_t n, uint64_t* out_keys,
                          void* out_vals, uint32_t out_vb, hipStream_t s);
 
+// n synthetic keys (SplitMix64 stream of `seed`) and, if vals, n values
+// (stream of vseed AND vmask) in elements of vb bytes.
+hipError_t fill_stream(uint64_t* keys, void* vals, uint32_t vb, uint64_t n, uint64_t seed,
+                       uint64_t vseed, uint64_t vmask, hipStream_t s);
+
 hipError_t query(const QueryPlan& plan, const uint64_t* keys, uint64_t n, void* out,
                  uint32_t out_bytes, uint32_t contains, uint64_t fp_salt, hipStream_t s);
 

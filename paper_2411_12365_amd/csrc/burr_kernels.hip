@@ -1401,6 +1401,42 @@ hipError_t concat_inputs(const uint64_t* tab, uint32_t J, uint64_t n, uint64_t* 
 }
 
 // ---------------------------------------------------------------------------
+// Synthetic inputs (autotuner): SplitMix64 stream outputs, element i of the
+// stream seeded with `seed` is mix(seed + (start + i + 1) * golden gamma)
+// (Steele, Lea, Flood, OOPSLA 2014)
+// ---------------------------------------------------------------------------
+__device__ inline uint64_t splitmix(uint64_t seed, uint64_t ctr) {
+  uint64_t z = seed + ctr * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_fill_stream(uint64_t* __restrict__ keys, void* vals,
+                                                     uint32_t vb, uint64_t n, uint64_t seed,
+                                                     uint64_t vseed, uint64_t vmask) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = splitmix(seed, i + 1);
+  if (!vals) return;
+  const uint64_t v = splitmix(vseed, i + 1) & vmask;
+  if (vb == 1)
+    reinterpret_cast<uint8_t*>(vals)[i] = (uint8_t)v;
+  else if (vb == 2)
+    reinterpret_cast<uint16_t*>(vals)[i] = (uint16_t)v;
+  else
+    reinterpret_cast<uint32_t*>(vals)[i] = (uint32_t)v;
+}
+
+hipError_t fill_stream(uint64_t* keys, void* vals, uint32_t vb, uint64_t n, uint64_t seed,
+                       uint64_t vseed, uint64_t vmask, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_fill_stream<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(keys, vals, vb, n, seed, vseed,
+                                                              vmask);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Query: one lane per key
 // ---------------------------------------------------------------------------
 template <typename OT>

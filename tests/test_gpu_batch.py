@@ -123,3 +123,51 @@ def test_member_handles_do_not_free_the_batch():
     got = b.member(1).query(to_dev(keys[1000:])).cpu().numpy()
     assert np.array_equal(got, vals[1000:])
     b.free()
+
+
+def test_tuned_batch_uses_each_members_size_class():
+    # members of different size classes get different minimum buckets per
+    # range; each must equal the oracle's structure built with that value
+    burr = _burr()
+    table = [dict(n_max=1000, minbpt=2), dict(n_max=20_000, minbpt=5),
+             dict(n_max=60_000, minbpt=40)]
+    sizes = [700, 1000, 1001, 5000, 19_999, 20_001, 45_000, 90_000, 0, 3000]
+    rs = [8, 3, 8, 1, 8, 2, 8, 8, 8, 16]
+    kw = dict(ranges=1 << 10)
+    keys, vals, offs = _make(sizes, rs, 61)
+    print(f"[batch] tuned, {len(sizes)} structures", flush=True)
+    b = burr.build_batch_tuned(to_dev(keys), to_dev(vals), offs, rs, table,
+                               burr.Params(flags=burr.BURR_FLAG_KEEP_LAYER_KEYS, **kw))
+    for i, n in enumerate(sizes):
+        cls = next((e for e in table if e["n_max"] >= n), table[-1])
+        mk, ref = _member_ref(keys, vals, offs, rs, i, dict(kw, minbpt=cls["minbpt"]))
+        check_handle(b.member(i), ref, mk, n_queries=2000)
+    # the class really changed the range split: 45k keys -> 683 buckets, 17 ranges
+    st = b.member(6).stats()
+    assert st["layers"][0]["nranges"] == \
+        oracle.layer_geometry(oracle.Params(minbpt=40, **kw), 45_000)[2] == 17
+    b.free()
+
+
+def test_autotune_table_is_valid_and_builds_exactly():
+    burr = _burr()
+    print("[batch] autotune", flush=True)
+    params = burr.Params(ranges=1 << 16)
+    table = burr.autotune(2, [1000, 10_000, 100_000], [4, 16, 64], keys_per_trial=2_000_000,
+                          reps=1, params=params)
+    assert [e["n_max"] for e in table] == [1000, 10_000, 100_000]
+    for e in table:
+        assert e["minbpt"] in (4, 16, 64)
+        assert e["ns_per_key"] > 0 and 2.0 <= e["bits_per_key"] < 3.0
+    print(f"[batch] table {table}", flush=True)
+    sizes = [300, 4000, 50_000, 150_000]
+    rs = [2, 2, 2, 2]
+    keys, vals, offs = _make(sizes, rs, 71)
+    b = burr.build_batch_tuned(to_dev(keys), to_dev(vals), offs, rs, table,
+                               burr.Params(ranges=1 << 16, flags=burr.BURR_FLAG_KEEP_LAYER_KEYS))
+    for i, n in enumerate(sizes):
+        cls = next((e for e in table if e["n_max"] >= n), table[-1])
+        mk, ref = _member_ref(keys, vals, offs, rs, i,
+                              dict(ranges=1 << 16, minbpt=cls["minbpt"]))
+        check_handle(b.member(i), ref, mk, n_queries=2000)
+    b.free()

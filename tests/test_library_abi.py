@@ -71,6 +71,38 @@ def test_invalid_batch_arguments_fail_without_touching_the_device():
     assert lib.burr_batch_member(None, 0) is None
 
 
+def test_invalid_tuning_arguments_fail_without_touching_the_device():
+    import numpy as np
+    import paper_2411_12365_amd as burr
+    lib = burr.lib()
+    p = burr.Params().c(None)
+    off = np.array([0, 3, 5], dtype=np.uint64)
+    rs = np.array([8, 8], dtype=np.uint32)
+    fake = ctypes.c_void_p(0x1000)                  # never dereferenced
+    for table in ([], [dict(n_max=100, minbpt=0)],                    # empty, zero minbpt
+                  [dict(n_max=100, minbpt=4), dict(n_max=100, minbpt=8)]):  # not ascending
+        arr = burr._tune_array(table) if table else None
+        assert lib.burr_build_batch_tuned(fake, fake, off.ctypes.data, rs.ctypes.data, 2,
+                                          ctypes.byref(p), arr, len(table)) is None
+        assert lib.burr_last_error() == burr.BURR_E_INVALID
+    # a valid table does not excuse invalid offsets
+    arr = burr._tune_array([dict(n_max=100, minbpt=4)])
+    bad = np.array([0, 5, 3], dtype=np.uint64)
+    assert lib.burr_build_batch_tuned(fake, fake, bad.ctypes.data, rs.ctypes.data, 2,
+                                      ctypes.byref(p), arr, 1) is None
+    out = (burr._CTuneEntry * 2)()
+    nm = np.array([1000, 500], dtype=np.uint64)     # not ascending
+    cand = np.array([4, 16], dtype=np.uint32)
+    assert lib.burr_autotune(ctypes.byref(p), 8, nm.ctypes.data, 2, cand.ctypes.data, 2,
+                             10_000, 1, out) == burr.BURR_E_INVALID
+    nm = np.array([500, 1000], dtype=np.uint64)
+    zero = np.array([4, 0], dtype=np.uint32)
+    assert lib.burr_autotune(ctypes.byref(p), 8, nm.ctypes.data, 2, zero.ctypes.data, 2,
+                             10_000, 1, out) == burr.BURR_E_INVALID
+    assert lib.burr_autotune(ctypes.byref(p), 0, nm.ctypes.data, 2, cand.ctypes.data, 2,
+                             10_000, 1, out) == burr.BURR_E_INVALID
+
+
 def test_python_binding_fails_loudly_without_library(monkeypatch):
     import paper_2411_12365_amd as burr
     monkeypatch.setattr(burr, "_lib", None)
