@@ -92,7 +92,8 @@ typedef struct burr_layer_stats {
   uint64_t nbuckets; /* m / b */
   uint64_t nranges;  /* independently solved ranges */
   uint64_t bumped;   /* keys passed to the next layer */
-  uint64_t steps;    /* XOR-and-shift elimination steps */
+  uint64_t steps;    /* XOR-and-shift elimination steps; counted only by a library
+                        built with -DBURR_SOLVE_STATS, else 0 */
   double ms_sort;    /* device time of the sort kernels (hipEvents) */
   double ms_solve;   /* device time of the insertion kernel */
   double ms_backsub; /* device time of back-substitution + code packing */

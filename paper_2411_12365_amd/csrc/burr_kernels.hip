@@ -647,11 +647,14 @@ __device__ inline void solve_diag(uint64_t* d, uint32_t code, uint64_t rho, uint
 constexpr uint32_t kStageItems = 128;  // header + 127 records staged in LDS per bucket
 
 struct WaveRing {
-  uint64_t c[kRing];
-  uint32_t v[kRing];
+  uint4 slot[kRing];  // {row low word, row high word, value, 0}; an empty slot is all zero
   uint4 stage[kStageItems];
   uint64_t placed[2];  // slots claimed by the current pass
 };
+
+__device__ inline uint64_t slot_row(const uint4& s) {
+  return (uint64_t)s.x | ((uint64_t)s.y << 32);
+}
 
 __device__ inline uint64_t wave_ballot(bool p) { return __ballot(p); }
 
@@ -660,8 +663,8 @@ __device__ inline uint64_t wave_ballot(bool p) { return __ballot(p); }
 #endif
 constexpr int kSolveK = BURR_SOLVE_K;  // elimination steps per loop trip
 
-// Optional counters (-DBURR_SOLVE_STATS): loop trips, passes and active lanes
-// per trip, added to the three words after the step count.
+// Optional counters (-DBURR_SOLVE_STATS): elimination steps, and loop trips,
+// passes and active lanes per trip in the three words after the step count.
 #ifdef BURR_SOLVE_STATS
 struct SolveStats {
   uint64_t trips = 0, passes = 0, lanes = 0;
@@ -675,8 +678,11 @@ struct SolveStats {};
 // Inserts records [r0, r1) of the staged bucket q. Returns 0 if the set was
 // consistent, 1 if an inconsistency was met (its rows are removed again), or
 // 2 on an internal error. Each loop trip: lanes without a row take the next
-// records, every lane makes up to kSolveK XOR-and-shift steps against the
-// ring (stopping at an empty slot), then the lanes at an empty slot claim it.
+// records, every lane makes kSolveK XOR-and-shift steps against the ring,
+// then the lanes at an empty slot claim it. The steps need no per-lane
+// masking: at an empty slot (row 0, value 0) a step leaves the lane's row,
+// value and position unchanged (its row keeps bit 0, so the shift is 0),
+// and the state of lanes that finished is not used again.
 __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint4* rec4,
                                      uint32_t hq, uint32_t q, uint32_t r0, uint32_t r1,
                                      uint32_t limit, uint64_t& steps, SolveStats& st) {
@@ -716,37 +722,35 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
       result = 2;
       break;
     }
-    // kSolveK elimination steps; a lane stops at an empty slot
-    bool at_empty = false, conflict = false;
+    bool conflict = false;
+    uint64_t row = 0;
 #pragma unroll
     for (int u = 0; u < kSolveK; ++u) {
-      const uint32_t p = i & (kRing - 1);
-      const uint64_t row = R.c[p];
-      const uint32_t rv = R.v[p];
-      const bool go = active && !at_empty;
-      at_empty = at_empty || (go && row == 0);
-      const bool step = go && row != 0;
+      const uint4 sl = R.slot[i & (kRing - 1)];
+      row = slot_row(sl);
       const uint64_t cx = c ^ row;
-      const uint32_t vx = v ^ rv;
-      const bool zero = step && cx == 0;
-      const uint32_t j = (uint32_t)__builtin_ctzg(cx, 64);
-      steps += step ? 1u : 0u;
+      const uint32_t vx = v ^ sl.z;
+      const bool zero = active && cx == 0;  // reduced to 0 = vx: redundant or inconsistent
+      BURR_STAT(steps += (active && row != 0) ? 1u : 0u;)
       conflict = conflict || (zero && vx != 0);
       active = active && !zero;
-      const bool adv = step && !zero;
-      c = adv ? (cx >> j) : c;
-      v = step ? vx : v;
-      i = adv ? i + j : i;
+      const uint32_t j = (uint32_t)__builtin_ctzg(cx, 64);
+      c = cx >> (j & 63u);
+      v = vx;
+      i += j;
     }
+    // the last step read an empty slot: the lane stayed on it
+    const bool at_empty = active && row == 0;
     if (at_empty) {
       const uint32_t p = i & (kRing - 1);
       if (i >= limit && !(a.spillC && i < limit + 64u)) {
         active = false;  // unreachable: a kept row crossing the range end
         result = 2;
       } else {
-        const uint64_t old = atomicCAS((unsigned long long*)&R.c[p], 0ull, (unsigned long long)c);
+        const uint64_t old =
+            atomicCAS((unsigned long long*)&R.slot[p], 0ull, (unsigned long long)c);
         if (old == 0) {
-          R.v[p] = v;
+          R.slot[p].z = v;
           atomicOr((unsigned long long*)&R.placed[p >> 6], 1ull << (p & 63));
           active = false;
         }
@@ -765,8 +769,8 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
   __syncthreads();
   if (bad || result == 2) {
     const uint64_t pm0 = R.placed[0], pm1 = R.placed[1];
-    if ((pm0 >> lane) & 1ull) R.c[lane] = 0;
-    if ((pm1 >> lane) & 1ull) R.c[64 + lane] = 0;
+    if ((pm0 >> lane) & 1ull) R.slot[lane] = make_uint4(0, 0, 0, 0);
+    if ((pm1 >> lane) & 1ull) R.slot[64 + lane] = make_uint4(0, 0, 0, 0);
   }
   __syncthreads();
   return result == 2 ? 2u : (bad ? 1u : 0u);
@@ -778,10 +782,11 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
 __device__ inline void release_half(WaveRing& R, const SolveArgs& a, uint32_t hb,
                                     uint64_t* rowsC, uint32_t* rowsV, uint64_t* occw) {
   const uint32_t lane = threadIdx.x;
-  const uint64_t row = R.c[hb + lane];
+  const uint4 sl = R.slot[hb + lane];
+  const uint64_t row = slot_row(sl);
   const uint64_t word = wave_ballot(row != 0);
   rowsC[lane] = row;
-  rowsV[lane] = R.v[hb + lane];
+  rowsV[lane] = sl.z;
   if (lane == 0) *occw = word;
   (void)a;
 }
@@ -802,8 +807,8 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
   const uint32_t limit = 64u * nq;
   const uint32_t last_item = a.nrec - 1;
   const uint4* rec4 = reinterpret_cast<const uint4*>(a.rec);
-  R.c[lane] = 0;
-  R.c[64 + lane] = 0;
+  R.slot[lane] = make_uint4(0, 0, 0, 0);
+  R.slot[64 + lane] = make_uint4(0, 0, 0, 0);
   uint64_t steps = 0;
   SolveStats sst;
   bool failed = false;
@@ -821,7 +826,7 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
       const uint32_t hb = ((q - 1) & 1u) * 64u;
       release_half(R, a, hb, a.rowsC + (beta - 1) * 64, a.rowsV + (beta - 1) * 64,
                    a.occ + (beta - 1));
-      R.c[hb + lane] = 0;
+      R.slot[hb + lane] = make_uint4(0, 0, 0, 0);
     }
     __syncthreads();
     if (q + 1 < nq) {  // next bucket's items load while this one is inserted
