@@ -644,19 +644,44 @@ __device__ inline void solve_diag(uint64_t* d, uint32_t code, uint64_t rho, uint
 // bucket's threshold - the outcome of inserting the chunks one after the
 // other in decreasing offset order (Sec. 2, 2-bit thresholds), since a
 // prefix of a consistent set is consistent.
-constexpr uint32_t kStageItems = 128;  // header + 127 records staged in LDS per bucket
+// header + 127 records staged in LDS per bucket; a staged record holds its
+// coefficient row instead of its key: {row low, row high, value, offset|rank}
+constexpr uint32_t kStageItems = 128;
 
+// The ring of one range: rows and values in separate arrays (their 8-byte
+// and 4-byte strides spread the lanes' random slots over more LDS banks than
+// one 16-byte slot would); an empty slot has row 0 and value 0.
 struct WaveRing {
-  uint4 slot[kRing];  // {row low word, row high word, value, 0}; an empty slot is all zero
+  uint64_t c[kRing];
+  uint32_t v[kRing];
   uint4 stage[kStageItems];
   uint64_t placed[2];  // slots claimed by the current pass
 };
+__device__ inline void ring_read(const WaveRing& R, uint32_t i, uint64_t& row, uint32_t& val) {
+  const uint32_t off = (i & (kRing - 1)) << 3;
+  row = *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(R.c) + off);
+  val = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(R.v) + (off >> 1));
+}
+__device__ inline unsigned long long* ring_row_ptr(WaveRing& R, uint32_t p) {
+  return reinterpret_cast<unsigned long long*>(&R.c[p]);
+}
+__device__ inline void ring_set_value(WaveRing& R, uint32_t p, uint32_t val) { R.v[p] = val; }
+__device__ inline void ring_clear(WaveRing& R, uint32_t p) {
+  R.c[p] = 0;
+  R.v[p] = 0;
+}
 
 __device__ inline uint64_t slot_row(const uint4& s) {
   return (uint64_t)s.x | ((uint64_t)s.y << 32);
 }
 
 __device__ inline uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+// a record of the item stream as staged: its key replaced by its row
+__device__ inline uint4 staged(const uint4& r, const LayerGeom& g) {
+  const uint64_t c = row_of((uint64_t)r.x | ((uint64_t)r.y << 32), g);
+  return make_uint4((uint32_t)c, (uint32_t)(c >> 32), r.z, r.w);
+}
 
 #ifndef BURR_SOLVE_K
 #define BURR_SOLVE_K 4
@@ -705,11 +730,13 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
     if (!active && next + rank < r1) {
       const uint32_t t = next + rank;
       uint4 r;
-      if (t + 1 < kStageItems)
+      if (t + 1 < kStageItems) {
         r = R.stage[t + 1];
-      else
+        c = slot_row(r);
+      } else {
         r = rec4[hq + 1 + t];  // bucket larger than the stage (rare)
-      c = row_of((uint64_t)r.x | ((uint64_t)r.y << 32), a.g);
+        c = row_of((uint64_t)r.x | ((uint64_t)r.y << 32), a.g);
+      }
       v = r.z;
       i = 64u * q + (r.w & 63u);
       active = true;
@@ -726,10 +753,10 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
     uint64_t row = 0;
 #pragma unroll
     for (int u = 0; u < kSolveK; ++u) {
-      const uint4 sl = R.slot[i & (kRing - 1)];
-      row = slot_row(sl);
+      uint32_t rv;
+      ring_read(R, i, row, rv);
       const uint64_t cx = c ^ row;
-      const uint32_t vx = v ^ sl.z;
+      const uint32_t vx = v ^ rv;
       const bool zero = active && cx == 0;  // reduced to 0 = vx: redundant or inconsistent
       BURR_STAT(steps += (active && row != 0) ? 1u : 0u;)
       conflict = conflict || (zero && vx != 0);
@@ -747,10 +774,9 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
         active = false;  // unreachable: a kept row crossing the range end
         result = 2;
       } else {
-        const uint64_t old =
-            atomicCAS((unsigned long long*)&R.slot[p], 0ull, (unsigned long long)c);
+        const uint64_t old = atomicCAS(ring_row_ptr(R, p), 0ull, (unsigned long long)c);
         if (old == 0) {
-          R.slot[p].z = v;
+          ring_set_value(R, p, v);
           atomicOr((unsigned long long*)&R.placed[p >> 6], 1ull << (p & 63));
           active = false;
         }
@@ -769,8 +795,8 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
   __syncthreads();
   if (bad || result == 2) {
     const uint64_t pm0 = R.placed[0], pm1 = R.placed[1];
-    if ((pm0 >> lane) & 1ull) R.slot[lane] = make_uint4(0, 0, 0, 0);
-    if ((pm1 >> lane) & 1ull) R.slot[64 + lane] = make_uint4(0, 0, 0, 0);
+    if ((pm0 >> lane) & 1ull) ring_clear(R, lane);
+    if ((pm1 >> lane) & 1ull) ring_clear(R, 64 + lane);
   }
   __syncthreads();
   return result == 2 ? 2u : (bad ? 1u : 0u);
@@ -782,11 +808,12 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
 __device__ inline void release_half(WaveRing& R, const SolveArgs& a, uint32_t hb,
                                     uint64_t* rowsC, uint32_t* rowsV, uint64_t* occw) {
   const uint32_t lane = threadIdx.x;
-  const uint4 sl = R.slot[hb + lane];
-  const uint64_t row = slot_row(sl);
+  uint64_t row;
+  uint32_t val;
+  ring_read(R, hb + lane, row, val);
   const uint64_t word = wave_ballot(row != 0);
   rowsC[lane] = row;
-  rowsV[lane] = sl.z;
+  rowsV[lane] = val;
   if (lane == 0) *occw = word;
   (void)a;
 }
@@ -807,8 +834,8 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
   const uint32_t limit = 64u * nq;
   const uint32_t last_item = a.nrec - 1;
   const uint4* rec4 = reinterpret_cast<const uint4*>(a.rec);
-  R.slot[lane] = make_uint4(0, 0, 0, 0);
-  R.slot[64 + lane] = make_uint4(0, 0, 0, 0);
+  ring_clear(R, lane);
+  ring_clear(R, 64 + lane);
   uint64_t steps = 0;
   SolveStats sst;
   bool failed = false;
@@ -819,14 +846,14 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
   for (uint32_t q = 0; q < nq && !failed; ++q) {
     const uint64_t beta = fb + q;
     hq = a.bstart[beta] + (uint32_t)beta;
-    R.stage[lane] = nx0;
-    R.stage[64 + lane] = nx1;
+    R.stage[lane] = lane == 0 ? nx0 : staged(nx0, g);  // entry 0 is the bucket header
+    R.stage[64 + lane] = staged(nx1, g);
     // the slots of bucket q+1 held bucket q-1: publish its rows, clear them
     if (q >= 1) {
       const uint32_t hb = ((q - 1) & 1u) * 64u;
       release_half(R, a, hb, a.rowsC + (beta - 1) * 64, a.rowsV + (beta - 1) * 64,
                    a.occ + (beta - 1));
-      R.slot[hb + lane] = make_uint4(0, 0, 0, 0);
+      ring_clear(R, hb + lane);
     }
     __syncthreads();
     if (q + 1 < nq) {  // next bucket's items load while this one is inserted
