@@ -644,29 +644,39 @@ __device__ inline void solve_diag(uint64_t* d, uint32_t code, uint64_t rho, uint
 // bucket's threshold - the outcome of inserting the chunks one after the
 // other in decreasing offset order (Sec. 2, 2-bit thresholds), since a
 // prefix of a consistent set is consistent.
-// header + 127 records staged in LDS per bucket; a staged record holds its
-// coefficient row instead of its key: {row low, row high, value, offset|rank}
-constexpr uint32_t kStageItems = 128;
+// Lane groups: LANES lanes insert one range, so a wave holds 64 / LANES
+// ranges, each with its own ring and stage in LDS. A bucket takes as long as
+// its longest elimination chain while its ~66 keys need far fewer lane-steps
+// than 64 lanes offer, so with 32 lanes per range two ranges share the lanes
+// one range would leave idle.
+//
+// The staged bucket: header + records, a staged record holding its
+// coefficient row instead of its key: {row low, row high, value,
+// offset|rank}; records past the stage are read from the item stream.
+template <int LANES>
+struct Stage {
+  static constexpr uint32_t items = LANES == 64 ? 128 : 96;
+  static constexpr uint32_t per_lane = items / LANES;
+};
 
 // The ring of one range: rows and values in separate arrays (their 8-byte
 // and 4-byte strides spread the lanes' random slots over more LDS banks than
 // one 16-byte slot would); an empty slot has row 0 and value 0.
+template <int LANES>
 struct WaveRing {
   uint64_t c[kRing];
   uint32_t v[kRing];
-  uint4 stage[kStageItems];
+  uint4 stage[Stage<LANES>::items];
   uint64_t placed[2];  // slots claimed by the current pass
 };
-__device__ inline void ring_read(const WaveRing& R, uint32_t i, uint64_t& row, uint32_t& val) {
+template <class Ring>
+__device__ inline void ring_read(const Ring& R, uint32_t i, uint64_t& row, uint32_t& val) {
   const uint32_t off = (i & (kRing - 1)) << 3;
   row = *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(R.c) + off);
   val = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(R.v) + (off >> 1));
 }
-__device__ inline unsigned long long* ring_row_ptr(WaveRing& R, uint32_t p) {
-  return reinterpret_cast<unsigned long long*>(&R.c[p]);
-}
-__device__ inline void ring_set_value(WaveRing& R, uint32_t p, uint32_t val) { R.v[p] = val; }
-__device__ inline void ring_clear(WaveRing& R, uint32_t p) {
+template <class Ring>
+__device__ inline void ring_clear(Ring& R, uint32_t p) {
   R.c[p] = 0;
   R.v[p] = 0;
 }
@@ -675,13 +685,46 @@ __device__ inline uint64_t slot_row(const uint4& s) {
   return (uint64_t)s.x | ((uint64_t)s.y << 32);
 }
 
-__device__ inline uint64_t wave_ballot(bool p) { return __ballot(p); }
-
 // a record of the item stream as staged: its key replaced by its row
 __device__ inline uint4 staged(const uint4& r, const LayerGeom& g) {
   const uint64_t c = row_of((uint64_t)r.x | ((uint64_t)r.y << 32), g);
   return make_uint4((uint32_t)c, (uint32_t)(c >> 32), r.z, r.w);
 }
+
+// This lane's group: ballots, "any" and ranks restricted to the group's
+// lanes. Within one wave, LDS operations complete in order, so a fence that
+// waits for them orders the group's LDS traffic (no barrier is needed, and
+// none is used inside code where the groups diverge).
+template <int LANES>
+struct Grp {
+  uint32_t id;    // group within the wave
+  uint32_t lane;  // lane within the group
+  __device__ Grp() : id(LANES == 64 ? 0u : threadIdx.x / LANES), lane(threadIdx.x % LANES) {}
+  __device__ uint64_t ballot(bool p) const {
+    const uint64_t m = __ballot(p);
+    if constexpr (LANES == 64)
+      return m;
+    else
+      return (m >> (id * LANES)) & ((1ull << LANES) - 1);
+  }
+  __device__ bool any(bool p) const { return ballot(p) != 0; }
+  // set bits of a group mask below this lane
+  __device__ uint32_t rank(uint64_t m) const {
+    if constexpr (LANES == 64)
+      return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    else
+      return (uint32_t)__popcll(m & ((1ull << lane) - 1));
+  }
+  __device__ void sync() const {
+    if constexpr (LANES == 64) {
+      __syncthreads();
+    } else {
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+};
 
 #ifndef BURR_SOLVE_K
 #define BURR_SOLVE_K 4
@@ -708,14 +751,16 @@ struct SolveStats {};
 // masking: at an empty slot (row 0, value 0) a step leaves the lane's row,
 // value and position unchanged (its row keeps bit 0, so the shift is 0),
 // and the state of lanes that finished is not used again.
-__device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint4* rec4,
-                                     uint32_t hq, uint32_t q, uint32_t r0, uint32_t r1,
-                                     uint32_t limit, uint64_t& steps, SolveStats& st) {
+template <int LANES>
+__device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
+                                     const SolveArgs& a, const uint4* rec4, uint32_t hq,
+                                     uint32_t q, uint32_t r0, uint32_t r1, uint32_t limit,
+                                     uint64_t& steps, SolveStats& st) {
   (void)st;
+  (void)steps;
   BURR_STAT(++st.passes;)
-  const uint32_t lane = threadIdx.x;
-  if (lane < 2) R.placed[lane] = 0;
-  __syncthreads();
+  if (G.lane < 2) R.placed[G.lane] = 0;
+  G.sync();
   bool active = false, bad = false;
   uint64_t c = 0;
   uint32_t v = 0, i = 0;
@@ -724,13 +769,12 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
   uint32_t result = 0;
   while (true) {
     // lanes without a row take the next records
-    const uint64_t freem = wave_ballot(!active);
-    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(freem >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)freem, 0u));
+    const uint64_t freem = G.ballot(!active);
+    const uint32_t rank = G.rank(freem);
     if (!active && next + rank < r1) {
       const uint32_t t = next + rank;
       uint4 r;
-      if (t + 1 < kStageItems) {
+      if (t + 1 < Stage<LANES>::items) {
         r = R.stage[t + 1];
         c = slot_row(r);
       } else {
@@ -743,8 +787,8 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
     }
     const uint32_t nfree = (uint32_t)__popcll(freem);
     next = (r1 - next < nfree) ? r1 : next + nfree;
-    if (!__any(active)) break;
-    BURR_STAT(++st.trips; st.lanes += __popcll(wave_ballot(active));)
+    if (!G.any(active)) break;
+    BURR_STAT(++st.trips; st.lanes += __popcll(G.ballot(active));)
     if (guard-- == 0) {
       result = 2;
       break;
@@ -774,92 +818,124 @@ __device__ inline uint32_t wave_pass(WaveRing& R, const SolveArgs& a, const uint
         active = false;  // unreachable: a kept row crossing the range end
         result = 2;
       } else {
-        const uint64_t old = atomicCAS(ring_row_ptr(R, p), 0ull, (unsigned long long)c);
+        const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(&R.c[p]), 0ull,
+                                       (unsigned long long)c);
         if (old == 0) {
-          ring_set_value(R, p, v);
+          R.v[p] = v;
           atomicOr((unsigned long long*)&R.placed[p >> 6], 1ull << (p & 63));
           active = false;
         }
         // otherwise another lane took the slot: step against its row next time
       }
     }
-    if (__any(conflict)) {
+    if (G.any(conflict)) {
       bad = true;
       break;
     }
-    if (__any(result == 2)) {
+    if (G.any(result == 2)) {
       result = 2;
       break;
     }
   }
-  __syncthreads();
+  G.sync();
   if (bad || result == 2) {
     const uint64_t pm0 = R.placed[0], pm1 = R.placed[1];
-    if ((pm0 >> lane) & 1ull) ring_clear(R, lane);
-    if ((pm1 >> lane) & 1ull) ring_clear(R, 64 + lane);
+#pragma unroll
+    for (uint32_t k = 0; k < kRing / LANES; ++k) {
+      const uint32_t t = k * LANES + G.lane;
+      if ((((t < 64) ? pm0 : pm1) >> (t & 63)) & 1ull) ring_clear(R, t);
+    }
   }
-  __syncthreads();
+  G.sync();
   return result == 2 ? 2u : (bad ? 1u : 0u);
 }
 
 // Publishes a released ring half: its 64 rows, values and occupancy word go
 // to the layer's row arrays (or, past the range end, to the segment's spill
-// buffer) as one coalesced block.
-__device__ inline void release_half(WaveRing& R, const SolveArgs& a, uint32_t hb,
+// buffer) as one coalesced block, and clears it.
+template <int LANES>
+__device__ inline void release_half(WaveRing<LANES>& R, const Grp<LANES>& G, uint32_t hb,
                                     uint64_t* rowsC, uint32_t* rowsV, uint64_t* occw) {
-  const uint32_t lane = threadIdx.x;
-  uint64_t row;
-  uint32_t val;
-  ring_read(R, hb + lane, row, val);
-  const uint64_t word = wave_ballot(row != 0);
-  rowsC[lane] = row;
-  rowsV[lane] = val;
-  if (lane == 0) *occw = word;
-  (void)a;
+  uint64_t word = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 64 / LANES; ++k) {
+    const uint32_t t = k * LANES + G.lane;
+    uint64_t row;
+    uint32_t val;
+    ring_read(R, hb + t, row, val);
+    word |= G.ballot(row != 0) << (k * LANES);
+    rowsC[t] = row;
+    rowsV[t] = val;
+  }
+  if (G.lane == 0) *occw = word;
 }
 
+template <int LANES>
+__device__ inline void clear_half(WaveRing<LANES>& R, const Grp<LANES>& G, uint32_t hb) {
+#pragma unroll
+  for (uint32_t k = 0; k < 64 / LANES; ++k) ring_clear(R, hb + k * LANES + G.lane);
+}
+
+template <int LANES>
 __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
-  __shared__ WaveRing R;
+  constexpr uint32_t NG = 64 / LANES;
+  constexpr uint32_t SP = Stage<LANES>::per_lane;
+  __shared__ WaveRing<LANES> RR[NG];
+  const Grp<LANES> G;
+  WaveRing<LANES>& R = RR[G.id];
   const LayerGeom g = a.g;
-  const uint32_t lane = threadIdx.x;
-  const uint64_t rho = blockIdx.x;
-  if (rho >= g.nranges) return;
-  const uint32_t js = find_struct(g.range_base, g.J, rho);
-  const uint64_t B = g.bucket_base[js + 1] - g.bucket_base[js];
-  const uint64_t Rn = g.range_base[js + 1] - g.range_base[js];
-  const uint64_t lr = rho - g.range_base[js];
-  const uint64_t f0 = lr * B / Rn;
-  const uint64_t fb = g.bucket_base[js] + f0;
-  const uint32_t nq = (uint32_t)((lr + 1) * B / Rn - f0);
+  const uint64_t rho = (uint64_t)blockIdx.x * NG + G.id;
+  // this group's range: buckets [fb, fb + nq) of structure js (none past the last range)
+  uint32_t js = 0, nq = 0;
+  uint64_t fb = 0;
+  if (rho < g.nranges) {
+    js = find_struct(g.range_base, g.J, rho);
+    const uint64_t B = g.bucket_base[js + 1] - g.bucket_base[js];
+    const uint64_t Rn = g.range_base[js + 1] - g.range_base[js];
+    const uint64_t lr = rho - g.range_base[js];
+    const uint64_t f0 = lr * B / Rn;
+    fb = g.bucket_base[js] + f0;
+    nq = (uint32_t)((lr + 1) * B / Rn - f0);
+  }
   const uint32_t limit = 64u * nq;
   const uint32_t last_item = a.nrec - 1;
   const uint4* rec4 = reinterpret_cast<const uint4*>(a.rec);
-  ring_clear(R, lane);
-  ring_clear(R, 64 + lane);
+#pragma unroll
+  for (uint32_t k = 0; k < kRing / LANES; ++k) ring_clear(R, k * LANES + G.lane);
   uint64_t steps = 0;
   SolveStats sst;
   bool failed = false;
   // bucket 0's items, staged through registers
-  uint32_t hq = a.bstart[fb] + (uint32_t)fb;
-  uint4 nx0 = rec4[hq + lane < last_item ? hq + lane : last_item];
-  uint4 nx1 = rec4[hq + 64 + lane < last_item ? hq + 64 + lane : last_item];
+  uint4 nx[SP];
+  uint32_t hq = nq ? a.bstart[fb] + (uint32_t)fb : 0u;
+  if (nq) {
+#pragma unroll
+    for (uint32_t k = 0; k < SP; ++k) {
+      const uint32_t t = hq + k * LANES + G.lane;
+      nx[k] = rec4[t < last_item ? t : last_item];
+    }
+  }
   for (uint32_t q = 0; q < nq && !failed; ++q) {
     const uint64_t beta = fb + q;
     hq = a.bstart[beta] + (uint32_t)beta;
-    R.stage[lane] = lane == 0 ? nx0 : staged(nx0, g);  // entry 0 is the bucket header
-    R.stage[64 + lane] = staged(nx1, g);
+#pragma unroll
+    for (uint32_t k = 0; k < SP; ++k)  // entry 0 is the bucket header
+      R.stage[k * LANES + G.lane] = (k == 0 && G.lane == 0) ? nx[0] : staged(nx[k], g);
     // the slots of bucket q+1 held bucket q-1: publish its rows, clear them
     if (q >= 1) {
       const uint32_t hb = ((q - 1) & 1u) * 64u;
-      release_half(R, a, hb, a.rowsC + (beta - 1) * 64, a.rowsV + (beta - 1) * 64,
+      release_half(R, G, hb, a.rowsC + (beta - 1) * 64, a.rowsV + (beta - 1) * 64,
                    a.occ + (beta - 1));
-      ring_clear(R, hb + lane);
+      clear_half(R, G, hb);
     }
-    __syncthreads();
+    G.sync();
     if (q + 1 < nq) {  // next bucket's items load while this one is inserted
       const uint32_t hn = a.bstart[beta + 1] + (uint32_t)(beta + 1);
-      nx0 = rec4[hn + lane < last_item ? hn + lane : last_item];
-      nx1 = rec4[hn + 64 + lane < last_item ? hn + 64 + lane : last_item];
+#pragma unroll
+      for (uint32_t k = 0; k < SP; ++k) {
+        const uint32_t t = hn + k * LANES + G.lane;
+        nx[k] = rec4[t < last_item ? t : last_item];
+      }
     }
     const uint4 hd = R.stage[0];
     const uint32_t count = hd.x, kf = hd.y & 3u;
@@ -868,9 +944,9 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
     const uint32_t cand = keep_ranks == 3 ? count : (keep_ranks == 2 ? e2 : (keep_ranks == 1 ? e1 : 0u));
     uint32_t kept = cand, code = kf;
     if (cand > 0) {
-      uint32_t res = wave_pass(R, a, rec4, hq, q, 0, cand, limit, steps, sst);
+      uint32_t res = wave_pass(R, G, a, rec4, hq, q, 0, cand, limit, steps, sst);
       if (res == 1 && g.plain) {
-        if (lane == 0) a.fail[js] = 1u;
+        if (G.lane == 0) a.fail[js] = 1u;
         failed = true;
       } else if (res == 1) {
         kept = 0;
@@ -879,7 +955,7 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
         for (uint32_t rr = keep_ranks - 1; rr >= 1 && res != 2; --rr) {
           const uint32_t e = rr == 2 ? e2 : e1;
           if (e == failed_size) continue;  // the same set again
-          res = e ? wave_pass(R, a, rec4, hq, q, 0, e, limit, steps, sst) : 0u;
+          res = e ? wave_pass(R, G, a, rec4, hq, q, 0, e, limit, steps, sst) : 0u;
           if (res == 0) {
             kept = e;
             code = 3 - rr;
@@ -889,44 +965,54 @@ __global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
         }
       }
       if (res == 2) {
-        if (lane == 0) {
+        if (G.lane == 0) {
           a.fail[js] = 2u;
           solve_diag(a.diag, 2, rho, js, hq, count, q, nq, cand, 0, kept, code, kf, 0, 0, fb);
         }
         failed = true;
       }
     }
-    if (!g.plain && lane == 0) {
+    if (!g.plain && G.lane == 0) {
       a.code8[beta] = (uint8_t)code;
       a.bump[beta] = count - kept;
     }
-    __syncthreads();
+    G.sync();
   }
-  if (!failed) {
+  if (nq && !failed) {
     const uint32_t hl = ((nq - 1) & 1u) * 64u;
     const uint64_t beta = fb + nq - 1;
-    release_half(R, a, hl, a.rowsC + beta * 64, a.rowsV + beta * 64, a.occ + beta);
+    release_half(R, G, hl, a.rowsC + beta * 64, a.rowsV + beta * 64, a.occ + beta);
     if (a.spill_occ) {  // rows past the segment end (final layer)
-      release_half(R, a, 64u - hl, a.spillC + rho * 64, a.spillV + rho * 64,
+      release_half(R, G, 64u - hl, a.spillC + rho * 64, a.spillV + rho * 64,
                    a.spill_occ + rho);
     }
   }
   if (a.steps) {
     for (int d = 32; d >= 1; d >>= 1) steps += __shfl_xor(steps, d, 64);
-    if (lane == 0) atomicAdd((unsigned long long*)a.steps, (unsigned long long)steps);
+    if (threadIdx.x == 0) atomicAdd((unsigned long long*)a.steps, (unsigned long long)steps);
 #ifdef BURR_SOLVE_STATS
-    if (lane == 0) {
-      atomicAdd((unsigned long long*)a.steps + 1, (unsigned long long)sst.trips);
-      atomicAdd((unsigned long long*)a.steps + 2, (unsigned long long)sst.passes);
-      atomicAdd((unsigned long long*)a.steps + 3, (unsigned long long)sst.lanes);
+    uint64_t t3[3] = {sst.trips, sst.passes, sst.lanes};
+    for (int k = 0; k < 3; ++k) {
+      uint64_t x = G.lane == 0 ? t3[k] : 0;  // one count per group
+      for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+      if (threadIdx.x == 0) atomicAdd((unsigned long long*)a.steps + 1 + k, (unsigned long long)x);
     }
 #endif
   }
 }
 
+// Lanes per range. 64: one range per wave (default). 32 (-DBURR_SOLVE_LANES=32):
+// two ranges per wave; same results, measured no faster at 100M keys (the
+// per-group control moves from scalar to vector registers and occupancy
+// drops from 7 to 5 waves per SIMD) and slower on small layers.
+#ifndef BURR_SOLVE_LANES
+#define BURR_SOLVE_LANES 64
+#endif
+
 hipError_t solve_layer(const SolveArgs& a, hipStream_t s) {
   if (a.g.nranges == 0) return hipSuccess;
-  k_solve_wave<<<(unsigned)a.g.nranges, 64, 0, s>>>(a);
+  constexpr int NG = 64 / BURR_SOLVE_LANES;
+  k_solve_wave<BURR_SOLVE_LANES><<<(unsigned)((a.g.nranges + NG - 1) / NG), 64, 0, s>>>(a);
   return hipGetLastError();
 }
 
