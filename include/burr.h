@@ -334,7 +334,8 @@ int burr_server_get_info(burr_server* s, burr_server_info* info);
 void burr_server_destroy(burr_server* s);
 
 /* Frees the workspaces the library keeps between builds (device memory
- * allocated with hipMalloc). Call when no build is running. */
+ * allocated with hipMalloc) and the host tables of freed batches it keeps for
+ * reuse. Call when no build is running. */
 void burr_release_workspaces(void);
 
 int burr_last_error(void);

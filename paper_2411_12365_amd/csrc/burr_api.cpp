@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -76,7 +77,67 @@ void keep_pool_memory(int dev) {
   done[dev] = true;
 }
 
-// one layer of one member
+// Host copy of a layer's per-structure table (see LayerGeom).
+struct Table {
+  std::vector<uint64_t> key_off{0}, span, bucket_base{0}, range_base{0}, word_base{0},
+      code_base{0};
+  std::vector<uint32_t> rbits;
+  void reserve(size_t J) {
+    for (auto* v : {&key_off, &span, &bucket_base, &range_base, &word_base, &code_base})
+      v->reserve(J + 1);
+    rbits.reserve(J);
+  }
+  // the whole table at once: geo(i, &n, &m, &R, &r) gives structure i's keys,
+  // slots, ranges and value bits
+  template <class Geo>
+  void fill(size_t J, Geo geo) {
+    key_off.resize(J + 1);
+    span.resize(J);
+    bucket_base.resize(J + 1);
+    range_base.resize(J + 1);
+    word_base.resize(J + 1);
+    code_base.resize(J + 1);
+    rbits.resize(J);
+    uint64_t ko = 0, bb = 0, rb = 0, wb = 0, cb = 0;
+    for (size_t i = 0; i < J; ++i) {
+      uint64_t n, m, R;
+      uint32_t r;
+      geo(i, &n, &m, &R, &r);
+      const uint64_t B = m / 64;
+      key_off[i] = ko;
+      span[i] = m - kWidth + 1;
+      bucket_base[i] = bb;
+      range_base[i] = rb;
+      word_base[i] = wb;
+      code_base[i] = cb;
+      rbits[i] = r;
+      ko += n;
+      bb += B;
+      rb += R;
+      wb += B * r;
+      cb += (B + 31) / 32;
+    }
+    key_off[J] = ko;
+    bucket_base[J] = bb;
+    range_base[J] = rb;
+    word_base[J] = wb;
+    code_base[J] = cb;
+  }
+  // next structure: n keys, m slots, R ranges (final layer: segments), r value bits
+  void add(uint64_t n, uint64_t m, uint64_t R, uint32_t r) {
+    const uint64_t B = m / 64;
+    key_off.push_back(key_off.back() + n);
+    span.push_back(m - kWidth + 1);
+    bucket_base.push_back(bucket_base.back() + B);
+    range_base.push_back(range_base.back() + R);
+    word_base.push_back(word_base.back() + B * r);
+    code_base.push_back(code_base.back() + (B + 31) / 32);
+    rbits.push_back(r);
+  }
+  uint32_t J() const { return (uint32_t)rbits.size(); }
+};
+
+// one layer of one member, as derived from its layer's table
 struct MemberLayer {
   uint64_t n = 0, m = 0, R = 0, bumped = 0;
   uint64_t code_off = 0, ncode = 0;  // words of the layer's shared code array
@@ -84,8 +145,9 @@ struct MemberLayer {
   uint64_t key_off = 0;              // debug: first key in the layer's kept key array
 };
 
-// storage shared by all members of a batch for one layer, and the records of
-// the members with keys in it (ids ascending, ml[k] belongs to ids[k])
+// storage shared by all members of a batch for one layer, and the geometry
+// of the members with keys in it: ids ascending, entry k of the table and of
+// `bumped` (keys passed to the next layer) belongs to member ids[k]
 struct LayerStore {
   uint64_t* codes = nullptr;
   uint64_t* W = nullptr;
@@ -93,7 +155,8 @@ struct LayerStore {
   uint64_t steps = 0;
   double ms_sort = 0, ms_solve = 0, ms_backsub = 0, ms_gather = 0;
   std::vector<uint32_t> ids;
-  std::vector<MemberLayer> ml;
+  Table t;
+  std::vector<uint32_t> bumped;
 };
 
 // the final plain layer of one member
@@ -155,10 +218,21 @@ struct burr_batch {
 namespace {
 
 // member idx's record of layer l < its built count
-const MemberLayer& layer_of(const burr_batch* b, uint32_t idx, uint32_t l) {
+MemberLayer layer_of(const burr_batch* b, uint32_t idx, uint32_t l) {
   const LayerStore& LS = b->layers[l];
   const size_t k = std::lower_bound(LS.ids.begin(), LS.ids.end(), idx) - LS.ids.begin();
-  return LS.ml[k];
+  const Table& t = LS.t;
+  MemberLayer L;
+  L.n = t.key_off[k + 1] - t.key_off[k];
+  L.m = t.span[k] + kWidth - 1;
+  L.R = t.range_base[k + 1] - t.range_base[k];
+  L.bumped = LS.bumped[k];
+  L.code_off = t.code_base[k];
+  L.ncode = t.code_base[k + 1] - t.code_base[k];
+  L.word_off = t.word_base[k];
+  L.nW = t.word_base[k + 1] - t.word_base[k];
+  L.key_off = t.key_off[k];
+  return L;
 }
 
 bool params_ok(const burr_params* p) {
@@ -178,7 +252,10 @@ uint64_t ceil_div(unsigned __int128 a, unsigned __int128 b) { return (uint64_t)(
 // R = min(ranges, B / max(minbpt, 2)) ranges, at least 1 (minbpt: the
 // structure's own value, 0 = the parameter block's).
 void plan_layer(const burr_params& p, uint64_t n, uint64_t* m, uint64_t* R, uint32_t minbpt = 0) {
-  uint64_t nb = ceil_div((unsigned __int128)n * p.load_num, (unsigned __int128)p.load_den * kBucket);
+  const uint64_t den = (uint64_t)p.load_den * kBucket;
+  uint64_t nb = n <= (~0ull - den) / p.load_num
+                    ? (n * p.load_num + den - 1) / den
+                    : ceil_div((unsigned __int128)n * p.load_num, (unsigned __int128)den);
   if (nb < 1) nb = 1;
   if (!minbpt) minbpt = p.minbpt;
   const uint64_t per = minbpt < 2 ? 2 : minbpt;
@@ -188,6 +265,44 @@ void plan_layer(const burr_params& p, uint64_t n, uint64_t* m, uint64_t* R, uint
   *m = nb * kBucket;
   *R = r;
 }
+
+// Division by a divisor fixed for a whole build, by a precomputed
+// reciprocal: q = high word of n * floor(2^64 / d) is q or q-1, one
+// correction step fixes it (the tables of large batches plan hundreds of
+// thousands of structures per layer).
+struct FastDiv {
+  uint64_t d = 1, M = 0;
+  FastDiv() = default;
+  explicit FastDiv(uint64_t dd) : d(dd), M(dd > 1 ? (uint64_t)(((unsigned __int128)1 << 64) / dd) : 0) {}
+  uint64_t div(uint64_t n) const {
+    if (d == 1) return n;
+    uint64_t q = (uint64_t)(((unsigned __int128)n * M) >> 64);
+    if (n - q * d >= d) ++q;
+    return q;
+  }
+};
+
+// plan_layer for many structures of one build
+struct LayerPlanner {
+  const burr_params& p;
+  FastDiv den, per;
+  uint64_t lim;  // up to lim keys, n * load_num + den - 1 fits 64 bits
+  explicit LayerPlanner(const burr_params& pp)
+      : p(pp), den((uint64_t)pp.load_den * kBucket), per(pp.minbpt < 2 ? 2 : pp.minbpt),
+        lim((~0ull - den.d) / pp.load_num) {}
+  void plan(uint64_t n, uint32_t minbpt, uint64_t* m, uint64_t* R) const {
+    uint64_t nb = n <= lim ? den.div(n * p.load_num + den.d - 1)
+                           : ceil_div((unsigned __int128)n * p.load_num, (unsigned __int128)den.d);
+    if (nb < 1) nb = 1;
+    if (!minbpt) minbpt = p.minbpt;
+    const uint64_t pr = minbpt < 2 ? 2 : minbpt;
+    uint64_t r = pr == per.d ? per.div(nb) : nb / pr;
+    if (r > p.ranges) r = p.ranges;
+    if (r < 1) r = 1;
+    *m = nb * kBucket;
+    *R = r;
+  }
+};
 
 // Final plain ribbon, attempt a: m = 64 * max(1, ceil(n * (final + a/10) / 64)).
 uint64_t plan_final(const burr_params& p, uint64_t n, uint32_t attempt) {
@@ -207,25 +322,6 @@ uint64_t plan_final(const burr_params& p, uint64_t n, uint32_t attempt) {
       return set_error(BURR_E_DEVICE);                                                 \
     }                                                                                  \
   } while (0)
-
-// Host copy of a layer's per-structure table (see LayerGeom).
-struct Table {
-  std::vector<uint64_t> key_off{0}, span, bucket_base{0}, range_base{0}, word_base{0},
-      code_base{0};
-  std::vector<uint32_t> rbits;
-  // next structure: n keys, m slots, R ranges (final layer: segments), r value bits
-  void add(uint64_t n, uint64_t m, uint64_t R, uint32_t r) {
-    const uint64_t B = m / 64;
-    key_off.push_back(key_off.back() + n);
-    span.push_back(m - kWidth + 1);
-    bucket_base.push_back(bucket_base.back() + B);
-    range_base.push_back(range_base.back() + R);
-    word_base.push_back(word_base.back() + B * r);
-    code_base.push_back(code_base.back() + (B + 31) / 32);
-    rbits.push_back(r);
-  }
-  uint32_t J() const { return (uint32_t)rbits.size(); }
-};
 
 // Device workspace of a build; grows on demand. Two modes:
 //  - with the build's allocator (caller callbacks or the stream-ordered pool):
@@ -648,8 +744,58 @@ uint64_t batch_table_estimate(const burr_batch* b, const std::vector<uint64_t>& 
   return words * 8 * 116 / 100 + 4096ull * (b->p.layers + 2);
 }
 
+// Host vectors of freed batches (layer tables, member lists, member
+// records), kept for the next batches: a large batch's per-layer tables are
+// megabytes, and fresh allocations of that size come back from the C library
+// as new pages whose first-touch faults cost milliseconds per layer.
+struct HostPool {
+  std::mutex mu;
+  std::vector<LayerStore> layers;  // only their host vectors are used
+  std::vector<std::vector<Member>> members;
+  std::vector<std::vector<burr_handle>> views;
+  static constexpr size_t kMaxLayers = 8, kMaxBatches = 2;
+};
+HostPool g_host;
+
+// host vectors of an earlier layer for a layer of J structures: the
+// smallest kept ones that hold J entries, else the largest
+void take_host(LayerStore& LS, size_t J) {
+  std::lock_guard<std::mutex> lk(g_host.mu);
+  if (g_host.layers.empty()) return;
+  size_t pick = 0;
+  for (size_t i = 1; i < g_host.layers.size(); ++i) {
+    const size_t c = g_host.layers[i].ids.capacity(), cp = g_host.layers[pick].ids.capacity();
+    if ((c >= J && (cp < J || c < cp)) || (cp < J && c > cp)) pick = i;
+  }
+  LayerStore& src = g_host.layers[pick];
+  LS.t = std::move(src.t);
+  LS.ids = std::move(src.ids);
+  LS.bumped = std::move(src.bumped);
+  g_host.layers.erase(g_host.layers.begin() + (ptrdiff_t)pick);
+}
+
+// Optional host timing of the batched build's phases (-DBURR_HOST_TIMING).
+#ifdef BURR_HOST_TIMING
+struct HostClock {
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void lap(const char* what, uint32_t li) {
+    const auto n = std::chrono::steady_clock::now();
+    fprintf(stderr, "host %-12s layer %u %.3f ms\n", what, li,
+            std::chrono::duration<double, std::milli>(n - t).count());
+    t = n;
+  }
+};
+#define HOST_LAP(hc, what, li) hc.lap(what, li)
+#else
+struct HostClock {};
+#define HOST_LAP(hc, what, li)
+#endif
+
 int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
                 const std::vector<uint64_t>& off) {
+  HostClock hc;
+  (void)hc;
+  const LayerPlanner planner(b->p);
   const burr_params& p = b->p;
   hipStream_t s = b->stream;
   const uint64_t fp_salt = mix64(~p.seed);
@@ -660,6 +806,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   if (!lease.ws) return set_error(BURR_E_NOMEM);
   Workspace& ws = *lease.ws;
   b->arena_cap = batch_table_estimate(b, off);
+  HOST_LAP(hc, "estimate", 0u);
   b->arena = (uint8_t*)b->alloc(b->arena_cap);
   if (!b->arena) return set_error(BURR_E_NOMEM);
   b->table_bytes = b->arena_cap;
@@ -678,6 +825,10 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
       active.push_back(i);
       cur_n.push_back(off[i + 1] - off[i]);
     }
+  std::vector<uint32_t> next_active;  // reused across layers
+  std::vector<uint64_t> next_n;
+  next_active.reserve(active.size());
+  next_n.reserve(active.size());
   const uint64_t* cur_keys = keys;
   const void* cur_vals = values;
   uint32_t cur_vbytes = value_bytes(rmax);
@@ -685,22 +836,26 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
 
   for (uint32_t li = 0; li < p.layers && !active.empty(); ++li) {
     LayerStore& LS = b->layers[li];
-    Table t;
-    for (size_t a = 0; a < active.size(); ++a) {
-      uint64_t m, R;
-      plan_layer(p, cur_n[a], &m, &R, b->members[active[a]].minbpt);
-      t.add(cur_n[a], m, R, b->members[active[a]].r);
-    }
+    take_host(LS, active.size());
+    Table t = std::move(LS.t);
+    t.fill(active.size(), [&](size_t a, uint64_t* n, uint64_t* m, uint64_t* R, uint32_t* r) {
+      const Member& mb = b->members[active[a]];
+      *n = cur_n[a];
+      *r = mb.r;
+      planner.plan(*n, mb.minbpt, m, R);
+    });
     LayerGeom g{};
     g.salt_s = mix64(p.seed ^ (2ull * li + 1ull));
     g.salt_c = mix64(p.seed ^ (2ull * li + 2ull));
     g.t_lo = p.t_lo;
     g.t_hi = p.t_hi;
     g.plain = 0;
+    HOST_LAP(hc, "table", li);
     int rc = upload_table(ws, t, g, s);
     if (rc != BURR_OK) return rc;
     if (!ws.reserve_slots(g.m) || !ws.reserve_buckets(g.nbuckets) || !ws.reserve_structs(g.J))
       return set_error(BURR_E_NOMEM);
+    HOST_LAP(hc, "upload", li);
     if (p.flags & BURR_FLAG_KEEP_LAYER_KEYS) {
       LS.keys = (uint64_t*)b->alloc(g.nkeys * 8);
       if (!LS.keys) return set_error(BURR_E_NOMEM);
@@ -743,7 +898,9 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     HIP_TRY(hipMemcpyAsync(ws.hres, ws.res, ws.results_words(g.J) * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(gather_bumped(ws.rec, ws.bstart, ws.bump, g.nbuckets, ws.keysA, ws.valsA, s));
     HIP_TRY(hipEventRecord(ev.e[5], s));
+    HOST_LAP(hc, "launch", li);
     HIP_TRY(hipStreamSynchronize(s));
+    HOST_LAP(hc, "device", li);
     const uint32_t* fails = ws.hres;
     const uint32_t* soff = ws.hres + g.J;
     const uint64_t steps = *reinterpret_cast<const uint64_t*>(ws.hres + 2 * g.J + 2);
@@ -769,30 +926,24 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     LS.ms_gather = elapsed_ms(ev.e[4], ev.e[5]);
     LS.steps = steps;
 
-    std::vector<uint32_t> next_active;
-    std::vector<uint64_t> next_n;
-    LS.ids = active;
-    LS.ml.resize(active.size());
+    next_active.clear();
+    next_n.clear();
+    LS.bumped.resize(active.size());
+    LS.ids.clear();
     for (size_t a = 0; a < active.size(); ++a) {
-      Member& mb = b->members[active[a]];
-      MemberLayer& L = LS.ml[a];
-      L.n = cur_n[a];
-      L.m = t.span[a] + kWidth - 1;
-      L.R = t.range_base[a + 1] - t.range_base[a];
-      L.bumped = soff[a + 1] - soff[a];
-      L.code_off = t.code_base[a];
-      L.ncode = t.code_base[a + 1] - t.code_base[a];
-      L.word_off = t.word_base[a];
-      L.nW = t.word_base[a + 1] - t.word_base[a];
-      L.key_off = t.key_off[a];
-      mb.built = li + 1;
-      if (L.bumped) {
+      const uint32_t nb = soff[a + 1] - soff[a];
+      LS.bumped[a] = nb;
+      b->members[active[a]].built = li + 1;
+      if (nb) {
         next_active.push_back(active[a]);
-        next_n.push_back(L.bumped);
+        next_n.push_back(nb);
       }
     }
+    LS.ids.assign(active.begin(), active.end());
+    LS.t = std::move(t);
     active.swap(next_active);
     cur_n.swap(next_n);
+    HOST_LAP(hc, "records", li);
     cur_keys = ws.keysA;
     cur_vals = ws.valsA;
     cur_vbytes = 4;
@@ -834,6 +985,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   }
   HIP_TRY(hipEventRecord(ev.e[2], s));
   HIP_TRY(hipStreamSynchronize(s));
+  HOST_LAP(hc, "final", p.layers);
   b->ms_final = elapsed_ms(ev.e[1], ev.e[2]);
   b->ms_total = elapsed_ms(ev.e[0], ev.e[2]);
   return BURR_OK;
@@ -842,6 +994,19 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
 burr_batch* new_batch(const burr_params* p, uint32_t count) {
   burr_batch* b = new (std::nothrow) burr_batch();
   if (!b) return nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_host.mu);
+    if (!g_host.members.empty()) {
+      b->members = std::move(g_host.members.back());
+      g_host.members.pop_back();
+      b->members.clear();
+    }
+    if (!g_host.views.empty()) {
+      b->views = std::move(g_host.views.back());
+      g_host.views.pop_back();
+      b->views.clear();
+    }
+  }
   b->p = *p;
   b->stream = (hipStream_t)p->stream;
   b->al.fn = p->alloc;
@@ -863,6 +1028,21 @@ void free_batch(burr_batch* b) {
   if (!b) return;
   for (void* q : b->owned) b->al.put(q);
   (void)hipStreamSynchronize(b->stream);
+  {
+    std::lock_guard<std::mutex> lk(g_host.mu);
+    for (LayerStore& LS : b->layers) {
+      if (LS.ids.capacity() == 0 || g_host.layers.size() >= HostPool::kMaxLayers) continue;
+      LayerStore keep;
+      keep.t = std::move(LS.t);
+      keep.ids = std::move(LS.ids);
+      keep.bumped = std::move(LS.bumped);
+      g_host.layers.push_back(std::move(keep));
+    }
+    if (g_host.members.size() < HostPool::kMaxBatches) {
+      g_host.members.push_back(std::move(b->members));
+      g_host.views.push_back(std::move(b->views));
+    }
+  }
   delete b;
 }
 
@@ -962,7 +1142,7 @@ uint64_t burr_batch_table_bits(const burr_batch* b) {
   if (!b) return 0;
   uint64_t words = 0;
   for (const LayerStore& LS : b->layers)
-    for (const MemberLayer& L : LS.ml) words += L.ncode + L.nW;
+    if (!LS.ids.empty()) words += LS.t.code_base.back() + LS.t.word_base.back();
   for (const Member& mb : b->members) words += mb.fin.nW;
   return words * 64;
 }
@@ -1314,9 +1494,7 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
   };
   bool ok = in.ok;
   for (uint32_t l = 0; ok && l < mb.built; ++l) {
-    b->layers[l].ids.assign(1, 0);
-    b->layers[l].ml.assign(1, MemberLayer{});
-    MemberLayer& L = b->layers[l].ml[0];
+    MemberLayer L;
     L.n = in.get(8);
     L.m = in.get(8);
     L.R = in.get(8);
@@ -1324,14 +1502,21 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
       ok = false;
       break;
     }
-    L.ncode = (L.m / 64 + 31) / 32;
-    L.nW = (L.m / 64) * mb.r;
-    ok = load_words(L.ncode, &b->layers[l].codes) && load_words(L.nW, &b->layers[l].W);
+    LayerStore& LS = b->layers[l];
+    LS.ids.assign(1, 0);
+    LS.t = Table();
+    LS.t.add(L.n, L.m, L.R, mb.r);
+    LS.bumped.assign(1, 0);
+    if (l > 0) b->layers[l - 1].bumped[0] = (uint32_t)L.n;  // keys passed on
+    L.ncode = LS.t.code_base.back();
+    L.nW = LS.t.word_base.back();
+    ok = load_words(L.ncode, &LS.codes) && load_words(L.nW, &LS.W);
   }
   if (ok) {
     mb.fin.n = in.get(8);
     mb.fin.m = in.get(8);
     mb.fin_attempt = in.get(8);
+    if (mb.built > 0) b->layers[mb.built - 1].bumped[0] = (uint32_t)mb.fin.n;
     ok = in.ok && mb.fin.m % 64 == 0;
     if (ok) {
       mb.fin.nW = (mb.fin.m / 64) * mb.r;
@@ -1373,6 +1558,13 @@ int64_t burr_debug_layer_keys(const burr_handle* h, uint32_t layer, uint64_t* ho
 }
 
 void burr_release_workspaces(void) {
+  {
+    std::lock_guard<std::mutex> lk(g_host.mu);
+    g_host.layers.clear();
+    g_host.layers.shrink_to_fit();
+    g_host.members.clear();
+    g_host.views.clear();
+  }
   std::vector<Workspace*> all;
   {
     std::lock_guard<std::mutex> lk(g_ws_mu);
