@@ -102,6 +102,41 @@ def _device_stream(gen, n, dtype, dev, chunk=100_000_000):
     return out
 
 
+SWEEP_RANGES = [1 << 8, 1 << 10, 1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 19]
+
+
+def run_space_sweep(keys, vals, n):
+    """Space of the 100M-key build against its number of ranges (the GPU
+    analog of the paper's space overhead per thread, Sec. 5 Fig. 3/4): every
+    range end bumps keys into deeper layers and adds table bits."""
+    import numpy as np
+    import paper_2411_12365_amd as burr
+    pts = []
+    for R in SWEEP_RANGES:
+        p = burr.Params(ranges=R, minbpt=2)
+        burr.build(keys, vals, R_BITS, p).free()
+        t0 = time.perf_counter()
+        h = burr.build(keys, vals, R_BITS, p)
+        dt = time.perf_counter() - t0
+        st = h.stats()
+        h.free()
+        L0 = st["layers"][0]
+        pts.append({"ranges": L0["nranges"],
+                    "buckets_per_range": round(L0["nbuckets"] / L0["nranges"], 1),
+                    "table_bytes": st["table_bytes"],
+                    "bits_per_key": round(st["table_bytes"] * 8 / n, 4),
+                    "layer0_bumped_frac": round(L0["bumped"] / n, 5),
+                    "build_ms": round(dt * 1e3, 2)})
+    x = np.array([q["ranges"] for q in pts[:5]], dtype=np.float64)
+    y = np.array([q["table_bytes"] for q in pts[:5]], dtype=np.float64)
+    slope = float(np.polyfit(x, y, 1)[0])
+    return {"workload": f"the {n:,}-key build above (r={R_BITS}) with minbpt 2 and the "
+                        f"layer-0 range count varied",
+            "points": pts,
+            "overhead_bytes_per_range": round(slope, 1),
+            "fit": f"least squares over {int(x[0])}..{int(x[-1])} ranges"}
+
+
 TUNE_CLASSES = [250, 1000, 4000, 16_000, 64_000, 200_000]  # size classes (max keys)
 TUNE_CANDIDATES = [2, 4, 8, 16, 32, 64]                     # minimum buckets per range
 
@@ -352,6 +387,7 @@ def main():
                     help="build requests per load level (8 query batches per build)")
     ap.add_argument("--serve-loads", type=str, default="0.5,0.8,0.95")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-space-sweep", action="store_true")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB once (a plain copy kernel of "
                          "known size, for scaling hardware byte counters)")
@@ -495,7 +531,11 @@ def main():
                     "paper_hw": "AMD EPYC 7551P 32C/64T, b=128, minbpt=1000, 8-bit filter"},
     }
     h.free()
-    del keys, vals, qkeys, out
+    del qkeys, out
+    if not args.no_space_sweep:
+        print("# space sweep", file=sys.stderr, flush=True)
+        res["space_sweep"] = run_space_sweep(keys, vals, n)
+    del keys, vals
     if args.calibration_copy_mib:
         src = torch.ones(args.calibration_copy_mib << 18, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
