@@ -1390,23 +1390,42 @@ __global__ __launch_bounds__(64) void k_final_partial(FinalArgs a) {
 // segment p-1 is the true value of segment p's first 63 slots = z0 xor (X
 // applied to segment p's boundary). Lane t holds boundary value t; column c
 // of the boundary is gathered into one word with a ballot, so X applied to
-// it is one AND and a parity per column.
+// it is one AND and a parity per column. The segments' X and z0 words do not
+// depend on the scan, so they are loaded kScanChunk segments at a time into
+// LDS (the loads overlap) and the sequential part reads LDS only.
+constexpr uint32_t kScanChunk = 32;
 __global__ __launch_bounds__(64) void k_final_scan(FinalArgs a) {
+  __shared__ uint64_t sx[kScanChunk][64];
+  __shared__ uint32_t sz[kScanChunk][64];
   const uint32_t t = threadIdx.x;
   const LayerGeom g = a.g;
   const uint32_t j = blockIdx.x;
   const uint64_t first = g.range_base[j], last = g.range_base[j + 1];
   const uint32_t r = g.rbits[j];
   uint32_t b = 0;  // nothing lies past the structure's last segment
-  for (uint64_t p = last; p-- > first;) {
-    a.bnd[p * 64 + t] = b;
-    const uint64_t X = t < 63 ? a.xfirst[p * 64 + t] : 0ull;
-    uint32_t nb = t < 63 ? a.z0first[p * 64 + t] : 0u;
-    for (uint32_t c = 0; c < r; ++c) {
-      const uint64_t col = __ballot(((b >> c) & 1u) != 0) & 0x7fffffffffffffffull;
-      nb ^= (uint32_t)(__popcll(X & col) & 1) << c;
+  for (uint64_t hi = last; hi > first;) {
+    const uint64_t lo = hi - first > kScanChunk ? hi - kScanChunk : first;
+#pragma unroll 8
+    for (uint32_t k = 0; k < kScanChunk; ++k) {
+      const uint64_t p = lo + k;
+      if (p < hi) {
+        sx[k][t] = t < 63 ? a.xfirst[p * 64 + t] : 0ull;
+        sz[k][t] = t < 63 ? a.z0first[p * 64 + t] : 0u;
+      }
     }
-    b = t < 63 ? nb : 0u;
+    __syncthreads();
+    for (uint64_t p = hi; p-- > lo;) {
+      a.bnd[p * 64 + t] = b;
+      const uint64_t X = sx[p - lo][t];
+      uint32_t nb = sz[p - lo][t];
+      for (uint32_t c = 0; c < r; ++c) {
+        const uint64_t col = __ballot(((b >> c) & 1u) != 0) & 0x7fffffffffffffffull;
+        nb ^= (uint32_t)(__popcll(X & col) & 1) << c;
+      }
+      b = t < 63 ? nb : 0u;
+    }
+    __syncthreads();
+    hi = lo;
   }
 }
 
