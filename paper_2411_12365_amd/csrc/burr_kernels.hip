@@ -876,8 +876,10 @@ __device__ inline void clear_half(WaveRing<LANES>& R, const Grp<LANES>& G, uint3
   for (uint32_t k = 0; k < 64 / LANES; ++k) ring_clear(R, hb + k * LANES + G.lane);
 }
 
+// 8 waves per SIMD: the kernel then fits 64 VGPRs (62, no spills), and the
+// ring and stage of 32 waves (3.6 KB each) fit a CU's LDS.
 template <int LANES>
-__global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
+__global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
   constexpr uint32_t NG = 64 / LANES;
   constexpr uint32_t SP = Stage<LANES>::per_lane;
   __shared__ WaveRing<LANES> RR[NG];
