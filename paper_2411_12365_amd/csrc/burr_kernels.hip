@@ -120,14 +120,16 @@ hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s
 // level 3: one workgroup per sub-bin (64 buckets) orders its records by
 //          (bucket, chunk) in LDS and writes headers and records as one block
 // Intermediate records (16 B): key, value | slot within the bin << 32.
-constexpr int kPartThreads = 256;   // level 1 (hashing needs more registers)
-constexpr int kPart2Threads = 512;  // level 2
-constexpr int kPartPer = 8;
+// 4 records per thread: 70 and 48 VGPRs, so 7-8 waves per SIMD stream the
+// tiles (8 records per thread left 4 waves per SIMD)
+constexpr int kPartPer = 4;                         // records per thread of a tile
+constexpr int kPartThreads = 2048 / kPartPer;       // level 1: 2048-key tiles
+constexpr int kPart2Threads = 4096 / kPartPer;      // level 2: 4096-key tiles
 constexpr uint32_t kTile = kPartThreads * kPartPer;  // level-1 keys per tile
 constexpr uint32_t kSubSlots = kSubBuckets * 64;     // slots per sub-bin
 constexpr uint32_t kChunk2 = 16384;                  // level-2 keys per workgroup
-constexpr int kL3Threads = 256;
-constexpr int kL3Per = 18;                           // records per thread held in registers
+constexpr int kL3Threads = 512;  // 8 waves: with the 73 KB block, 4 waves per SIMD
+constexpr int kL3Per = 9;                            // records per thread held in registers
 constexpr uint32_t kL3Cap = kL3Threads * kL3Per;     // items of a sub-bin staged in LDS
 
 SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets) {
