@@ -661,21 +661,27 @@ struct Stage {
   static constexpr uint32_t per_lane = items / LANES;
 };
 
-// The ring of one range: rows and values in separate arrays (their 8-byte
-// and 4-byte strides spread the lanes' random slots over more LDS banks than
-// one 16-byte slot would); an empty slot has row 0 and value 0.
+// The ring of one range: rows and values in separate arrays with the same
+// 8-byte stride (one masked byte offset addresses both; separate arrays
+// spread the lanes' random slots over more LDS banks than 16-byte slots);
+// an empty slot has row 0 and value 0.
 template <int LANES>
 struct WaveRing {
   uint64_t c[kRing];
-  uint32_t v[kRing];
+  uint64_t v[kRing];  // value in the low word
   uint4 stage[Stage<LANES>::items];
   uint64_t placed[2];  // slots claimed by the current pass
 };
+// row and value of slot i, given ib = 8 i (the ring wraps every 1 KB)
+template <class Ring>
+__device__ inline void ring_read_b(const Ring& R, uint32_t ib, uint64_t& row, uint32_t& val) {
+  const uint32_t off = ib & (kRing * 8 - 8);
+  row = *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(R.c) + off);
+  val = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(R.v) + off);
+}
 template <class Ring>
 __device__ inline void ring_read(const Ring& R, uint32_t i, uint64_t& row, uint32_t& val) {
-  const uint32_t off = (i & (kRing - 1)) << 3;
-  row = *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(R.c) + off);
-  val = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(R.v) + (off >> 1));
+  ring_read_b(R, i << 3, row, val);
 }
 template <class Ring>
 __device__ inline void ring_clear(Ring& R, uint32_t p) {
@@ -797,21 +803,23 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
     }
     bool conflict = false;
     uint64_t row = 0;
+    uint32_t ib = i << 3;  // byte offset of the lane's slot
 #pragma unroll
     for (int u = 0; u < kSolveK; ++u) {
       uint32_t rv;
-      ring_read(R, i, row, rv);
+      ring_read_b(R, ib, row, rv);
       const uint64_t cx = c ^ row;
       const uint32_t vx = v ^ rv;
-      const bool zero = active && cx == 0;  // reduced to 0 = vx: redundant or inconsistent
+      const bool nz = cx != 0;  // else reduced to 0 = vx: redundant or inconsistent
       BURR_STAT(steps += (active && row != 0) ? 1u : 0u;)
-      conflict = conflict || (zero && vx != 0);
-      active = active && !zero;
+      conflict = conflict || (active && !nz && vx != 0);
+      active = active && nz;
       const uint32_t j = (uint32_t)__builtin_ctzg(cx, 64);
       c = cx >> (j & 63u);
       v = vx;
-      i += j;
+      ib += j << 3;
     }
+    i = ib >> 3;
     // the last step read an empty slot: the lane stayed on it
     const bool at_empty = active && row == 0;
     if (at_empty) {
