@@ -670,7 +670,6 @@ struct WaveRing {
   uint64_t c[kRing];
   uint64_t v[kRing];  // value in the low word
   uint4 stage[Stage<LANES>::items];
-  uint64_t placed[2];  // slots claimed by the current pass
 };
 // row and value of slot i, given ib = 8 i (the ring wraps every 1 KB)
 template <class Ring>
@@ -767,8 +766,16 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
   (void)st;
   (void)steps;
   BURR_STAT(++st.passes;)
-  if (G.lane < 2) R.placed[G.lane] = 0;
-  G.sync();
+  // occupied slots before the pass: an undo clears the slots claimed since
+  uint64_t before[kRing / 64];
+#pragma unroll
+  for (uint32_t h = 0; h < kRing / 64; ++h) {
+    uint64_t m = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 64 / LANES; ++k)
+      m |= G.ballot(R.c[h * 64 + k * LANES + G.lane] != 0) << (k * LANES);
+    before[h] = m;
+  }
   bool active = false, bad = false;
   uint64_t c = 0;
   uint32_t v = 0, i = 0;
@@ -781,12 +788,11 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
     const uint32_t rank = G.rank(freem);
     if (!active && next + rank < r1) {
       const uint32_t t = next + rank;
-      uint4 r;
-      if (t + 1 < Stage<LANES>::items) {
-        r = R.stage[t + 1];
-        c = slot_row(r);
-      } else {
-        r = rec4[hq + 1 + t];  // bucket larger than the stage (rare)
+      constexpr uint32_t last = Stage<LANES>::items - 1;
+      uint4 r = R.stage[t < last ? t + 1 : last];
+      c = slot_row(r);
+      if (t >= last) {  // bucket larger than the stage (rare)
+        r = rec4[hq + 1 + t];
         c = row_of((uint64_t)r.x | ((uint64_t)r.y << 32), a.g);
       }
       v = r.z;
@@ -832,7 +838,6 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
                                        (unsigned long long)c);
         if (old == 0) {
           R.v[p] = v;
-          atomicOr((unsigned long long*)&R.placed[p >> 6], 1ull << (p & 63));
           active = false;
         }
         // otherwise another lane took the slot: step against its row next time
@@ -849,11 +854,10 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
   }
   G.sync();
   if (bad || result == 2) {
-    const uint64_t pm0 = R.placed[0], pm1 = R.placed[1];
 #pragma unroll
     for (uint32_t k = 0; k < kRing / LANES; ++k) {
       const uint32_t t = k * LANES + G.lane;
-      if ((((t < 64) ? pm0 : pm1) >> (t & 63)) & 1ull) ring_clear(R, t);
+      if (R.c[t] != 0 && !((before[t >> 6] >> (t & 63)) & 1ull)) ring_clear(R, t);
     }
   }
   G.sync();
