@@ -708,7 +708,7 @@ struct Grp {
   uint32_t lane;  // lane within the group
   __device__ Grp() : id(LANES == 64 ? 0u : threadIdx.x / LANES), lane(threadIdx.x % LANES) {}
   __device__ uint64_t ballot(bool p) const {
-    const uint64_t m = __ballot(p);
+    const uint64_t m = __builtin_amdgcn_ballot_w64(p);
     if constexpr (LANES == 64)
       return m;
     else
@@ -791,8 +791,10 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
       constexpr uint32_t last = Stage<LANES>::items - 1;
       uint4 r = R.stage[t < last ? t + 1 : last];
       c = slot_row(r);
-      if (t >= last) {  // bucket larger than the stage (rare)
-        r = rec4[hq + 1 + t];
+      if (t >= last) {  // bucket larger than the stage (rare; a load that cannot merge with the LDS read)
+        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 g4 = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(rec4 + hq + 1 + t));
+        r = make_uint4(g4.x, g4.y, g4.z, g4.w);
         c = row_of((uint64_t)r.x | ((uint64_t)r.y << 32), a.g);
       }
       v = r.z;
@@ -801,6 +803,7 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
     }
     const uint32_t nfree = (uint32_t)__popcll(freem);
     next = (r1 - next < nfree) ? r1 : next + nfree;
+    if constexpr (LANES == 64) next = __builtin_amdgcn_readfirstlane(next);  // uniform
     if (!G.any(active)) break;
     BURR_STAT(++st.trips; st.lanes += __popcll(G.ballot(active));)
     if (guard-- == 0) {
