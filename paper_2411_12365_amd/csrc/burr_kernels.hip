@@ -1595,7 +1595,40 @@ hipError_t fill_stream(uint64_t* keys, void* vals, uint32_t vb, uint64_t n, uint
 // ---------------------------------------------------------------------------
 // Query: one lane per key
 // ---------------------------------------------------------------------------
-template <typename OT>
+// r-bit result of one layer: parity of c AND the 64-slot window at s, per
+// column, from the column-interleaved words of blocks s/64 and s/64 + 1
+template <int R>
+__device__ inline uint32_t window_parity(const uint64_t* w, uint32_t sh, uint64_t c) {
+  uint64_t lo[R], hi[R];
+#pragma unroll
+  for (int col = 0; col < R; ++col) {
+    lo[col] = w[col];
+    hi[col] = sh ? w[R + col] : 0ull;
+  }
+  uint32_t res = 0;
+#pragma unroll
+  for (int col = 0; col < R; ++col) {
+    const uint64_t win = sh ? ((lo[col] >> sh) | (hi[col] << (64 - sh))) : lo[col];
+    res |= ((uint32_t)__popcll(win & c) & 1u) << col;
+  }
+  return res;
+}
+__device__ inline uint32_t window_parity_any(const uint64_t* w, uint32_t r, uint32_t sh,
+                                             uint64_t c) {
+  uint32_t res = 0;
+  for (uint32_t col = 0; col < r; ++col) {
+    uint64_t win = w[col] >> sh;
+    if (sh) win |= w[r + col] << (64 - sh);
+    res |= ((uint32_t)__popcll(win & c) & 1u) << col;
+  }
+  return res;
+}
+
+// Query: one lane per key. Per layer, the bucket's code word and the table
+// words of the key's window are independent loads (both follow from the start
+// slot), so they are issued together; the threshold then decides whether
+// the layer answers.
+template <typename OT, int RC>
 __global__ __launch_bounds__(256) void k_query(QueryPlan plan, const uint64_t* __restrict__ keys,
                                                uint64_t n, OT* __restrict__ out,
                                                uint32_t contains, uint64_t fp_salt) {
@@ -1608,21 +1641,22 @@ __global__ __launch_bounds__(256) void k_query(QueryPlan plan, const uint64_t* _
     const QueryLayer& L = plan.layer[l];
     if (L.empty) break;
     const uint64_t s = __umul64hi(mix64(key ^ L.salt_s), L.span);
-    if (!L.plain) {
-      const uint64_t beta = s >> 6;
-      const uint32_t o = (uint32_t)s & 63u;
-      const uint32_t code = (uint32_t)(L.codes[beta >> 5] >> (2 * (beta & 31))) & 3u;
-      const uint32_t th = code == 0 ? 0u : (code == 1 ? L.t_lo : (code == 2 ? L.t_hi : 64u));
-      if (o < th) continue;
-    }
     const uint64_t c = mix64(key ^ L.salt_c) | 1ull;
     const uint32_t sh = (uint32_t)s & 63u;
     const uint64_t* w = L.W + (s >> 6) * r;
-    for (uint32_t col = 0; col < r; ++col) {
-      uint64_t win = w[col] >> sh;
-      if (sh) win |= w[r + col] << (64 - sh);
-      res |= ((uint32_t)__popcll(win & c) & 1u) << col;
+    const uint64_t beta = s >> 6;
+    const uint64_t cw = L.plain ? 0ull : L.codes[beta >> 5];
+    uint32_t val;
+    if constexpr (RC > 0)
+      val = window_parity<RC>(w, sh, c);
+    else
+      val = window_parity_any(w, r, sh, c);
+    if (!L.plain) {
+      const uint32_t code = (uint32_t)(cw >> (2 * (beta & 31))) & 3u;
+      const uint32_t th = code == 0 ? 0u : (code == 1 ? L.t_lo : (code == 2 ? L.t_hi : 64u));
+      if (sh < th) continue;
     }
+    res = val;
     break;
   }
   if (contains)
@@ -1635,12 +1669,19 @@ hipError_t query(const QueryPlan& plan, const uint64_t* keys, uint64_t n, void* 
                  uint32_t out_bytes, uint32_t contains, uint64_t fp_salt, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n + 255) / 256);
-  if (out_bytes == 1)
-    k_query<uint8_t><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
+  if (out_bytes == 1 && plan.r == 8)
+    k_query<uint8_t, 8><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
+  else if (out_bytes == 1 && plan.r == 1)
+    k_query<uint8_t, 1><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
+  else if (out_bytes == 1)
+    k_query<uint8_t, 0><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
+  else if (out_bytes == 2 && plan.r == 16)
+    k_query<uint16_t, 16><<<blocks, 256, 0, s>>>(plan, keys, n, (uint16_t*)out, contains,
+                                                 fp_salt);
   else if (out_bytes == 2)
-    k_query<uint16_t><<<blocks, 256, 0, s>>>(plan, keys, n, (uint16_t*)out, contains, fp_salt);
+    k_query<uint16_t, 0><<<blocks, 256, 0, s>>>(plan, keys, n, (uint16_t*)out, contains, fp_salt);
   else
-    k_query<uint32_t><<<blocks, 256, 0, s>>>(plan, keys, n, (uint32_t*)out, contains, fp_salt);
+    k_query<uint32_t, 0><<<blocks, 256, 0, s>>>(plan, keys, n, (uint32_t*)out, contains, fp_salt);
   return hipGetLastError();
 }
 
