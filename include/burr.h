@@ -185,20 +185,27 @@ burr_batch* burr_build_batch_tuned(const uint64_t* keys, const void* values,
                                    uint32_t count, const burr_params* p,
                                    const burr_tune_entry* table, uint32_t entries);
 
-/* Autotuner of the range split per size class. For each class c (n_max[]
- * ascending, nclasses of them) it builds batches of synthetic structures
- * (uniform random keys and r-bit values, made on the device) whose size is
- * the geometric middle of the class (from n_max[c-1], or n_max[0]/4, to
- * n_max[c]), about keys_per_trial keys per batch, once per candidate
- * minimum buckets per range (candidates[], ncandidates of them, each >= 1),
- * with p's other settings on the current device and p->stream. Each choice
- * is timed as the best of reps builds after one warm-up. out[c] keeps the
- * fastest candidate or, among those within 3 % of it, the one with the
- * smallest tables (bits per key). Allocates and frees device memory for the
+/* Autotuner of the range split per size class (classes: n_max[] ascending,
+ * nclasses of them; candidates[]: minimum buckets per range to try, each
+ * >= 1), run with p's other settings on the current device and p->stream on
+ * synthetic inputs (uniform random keys and r-bit values made on the
+ * device). Each timing is the best of reps builds after one warm-up.
+ *  - With a size sample (sizes[], nsizes structure sizes, e.g. a sample of
+ *    the batches to be built): coordinate descent on whole batches of that
+ *    mix. Every class starts at p->minbpt; class by class, a candidate
+ *    replaces it only if the mixed batch builds more than 3 % faster.
+ *  - Without (sizes NULL): each class is timed alone, as batches of about
+ *    keys_per_trial keys of structures of the geometric middle of the class
+ *    (from n_max[c-1], or n_max[0]/4, to n_max[c]); out[c] keeps the fastest
+ *    candidate, among those within 3 % of it p->minbpt if it is one, else
+ *    the one with the smallest tables.
+ * out receives nclasses entries (with the mix: the mixed batch's ns and bits
+ * per key in every entry). Allocates and frees device memory for the
  * synthetic inputs. BURR_OK, or BURR_E_INVALID / NOMEM / DEVICE. */
-int burr_autotune(const burr_params* p, uint32_t r, const uint64_t* n_max, uint32_t nclasses,
-                  const uint32_t* candidates, uint32_t ncandidates, uint64_t keys_per_trial,
-                  uint32_t reps, burr_tune_entry* out);
+int burr_autotune(const burr_params* p, uint32_t r, const uint64_t* sizes, uint64_t nsizes,
+                  const uint64_t* n_max, uint32_t nclasses, const uint32_t* candidates,
+                  uint32_t ncandidates, uint64_t keys_per_trial, uint32_t reps,
+                  burr_tune_entry* out);
 
 /* Number of structures in a batch (0 for NULL). */
 uint32_t burr_batch_size(const burr_batch* b);

@@ -158,8 +158,8 @@ def lib():
         L.burr_build_batch_tuned.argtypes = [vp, vp, vp, vp, u32, ctypes.POINTER(_CParams),
                                              ctypes.POINTER(_CTuneEntry), u32]
         L.burr_build_batch_tuned.restype = vp
-        L.burr_autotune.argtypes = [ctypes.POINTER(_CParams), u32, vp, u32, vp, u32, u64, u32,
-                                    ctypes.POINTER(_CTuneEntry)]
+        L.burr_autotune.argtypes = [ctypes.POINTER(_CParams), u32, vp, u64, vp, u32, vp, u32,
+                                    u64, u32, ctypes.POINTER(_CTuneEntry)]
         L.burr_autotune.restype = ctypes.c_int
         L.burr_batch_size.argtypes = [vp]
         L.burr_batch_size.restype = u32
@@ -369,19 +369,23 @@ def burr_build_batch_tuned(keys, values, offsets, rs, table, params: Params | No
     return Batch(b, rr, params)
 
 
-def burr_autotune(r: int, n_max, candidates, keys_per_trial: int, reps: int = 2,
-                  params: Params | None = None, stream=None) -> list[dict]:
-    """Measures, per size class (upper bounds n_max, ascending), which
-    candidate minimum of buckets per range builds batches fastest; returns
-    the table for burr_build_batch_tuned."""
+def burr_autotune(r: int, n_max, candidates, keys_per_trial: int = 0, reps: int = 2,
+                  params: Params | None = None, stream=None, sizes=None) -> list[dict]:
+    """Picks, per size class (upper bounds n_max, ascending), the minimum
+    buckets per range among `candidates`: on whole batches of the structure
+    sizes `sizes` (coordinate descent), or, without sizes, timing each class
+    alone on batches of about keys_per_trial keys. Returns the table for
+    burr_build_batch_tuned."""
     import numpy as np
     params = params or Params()
     nm = np.ascontiguousarray(np.asarray(n_max, dtype=np.uint64))
     cand = np.ascontiguousarray(np.asarray(candidates, dtype=np.uint32))
+    sz = None if sizes is None else np.ascontiguousarray(np.asarray(sizes, dtype=np.uint64))
     out = (_CTuneEntry * max(len(nm), 1))()
     cp = params.c(_stream_of(stream))
-    rc = lib().burr_autotune(ctypes.byref(cp), r, nm.ctypes.data, len(nm), cand.ctypes.data,
-                             len(cand), keys_per_trial, reps, out)
+    rc = lib().burr_autotune(ctypes.byref(cp), r, None if sz is None else sz.ctypes.data,
+                             0 if sz is None else len(sz), nm.ctypes.data, len(nm),
+                             cand.ctypes.data, len(cand), keys_per_trial, reps, out)
     if rc != BURR_OK:
         raise BurrError(rc, "burr_autotune")
     return [{f: getattr(out[i], f) for f in ("n_max", "minbpt", "ns_per_key", "bits_per_key")}

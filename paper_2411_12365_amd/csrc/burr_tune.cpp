@@ -34,17 +34,111 @@ uint32_t value_bytes(uint32_t r) { return r <= 8 ? 1 : (r <= 16 ? 2 : 4); }
 
 }  // namespace
 
-extern "C" int burr_autotune(const burr_params* p, uint32_t r, const uint64_t* n_max,
-                             uint32_t nclasses, const uint32_t* candidates, uint32_t ncandidates,
+namespace {
+
+// Best-of-reps seconds of one batched build (after a warm-up) and its table
+// bits, or an error code in *rc.
+double time_batch(const uint64_t* keys, const void* vals, const std::vector<uint64_t>& off,
+                  const std::vector<uint32_t>& rs, const burr_params* p,
+                  const std::vector<burr_tune_entry>& table, uint32_t reps, double* bits,
+                  int* rc) {
+  double best = 0;
+  for (uint32_t t = 0; t <= reps; ++t) {  // t = 0: warm-up
+    const auto t0 = std::chrono::steady_clock::now();
+    burr_batch* b = burr_build_batch_tuned(keys, vals, off.data(), rs.data(),
+                                           (uint32_t)rs.size(), p, table.data(),
+                                           (uint32_t)table.size());
+    const auto t1 = std::chrono::steady_clock::now();
+    if (!b) {
+      *rc = burr_last_error();
+      return 0;
+    }
+    const double sec = std::chrono::duration<double>(t1 - t0).count();
+    if (t == 1 || (t > 1 && sec < best)) best = sec;
+    if (t == reps && bits) *bits = (double)burr_batch_table_bits(b);
+    burr_batch_free(b);
+  }
+  *rc = BURR_OK;
+  return best;
+}
+
+// Tuning on a mix of structure sizes: coordinate descent over the classes,
+// starting from p->minbpt everywhere; a class takes another candidate only
+// if the whole mixed batch builds more than 3 % faster with it.
+int tune_mix(const burr_params* p, uint32_t r, const uint64_t* sizes, uint64_t nsizes,
+             const uint64_t* n_max, uint32_t nclasses, const uint32_t* candidates,
+             uint32_t ncandidates, uint32_t reps, burr_tune_entry* out) {
+  std::vector<uint64_t> off(nsizes + 1, 0);
+  for (uint64_t i = 0; i < nsizes; ++i) off[i + 1] = off[i] + sizes[i];
+  const uint64_t total = off.back();
+  if (total == 0 || nsizes > 0xffffffffull) return burr_set_error(BURR_E_INVALID);
+  std::vector<uint32_t> rs(nsizes, r);
+  const uint32_t vb = value_bytes(r);
+  DeviceInputs in;
+  if (hipMalloc((void**)&in.keys, total * 8) != hipSuccess ||
+      (!p->filter_mode && hipMalloc(&in.vals, total * vb) != hipSuccess))
+    return burr_set_error(BURR_E_NOMEM);
+  hipStream_t s = (hipStream_t)p->stream;
+  const uint64_t vmask = r >= 32 ? 0xffffffffull : ((1ull << r) - 1);
+  if (burr::fill_stream(in.keys, in.vals, vb, total, 0x5eed0001ull, 0x5eed0002ull, vmask, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return burr_set_error(BURR_E_DEVICE);
+  std::vector<burr_tune_entry> table(nclasses);
+  for (uint32_t c = 0; c < nclasses; ++c) {
+    table[c] = burr_tune_entry{};
+    table[c].n_max = n_max[c];
+    table[c].minbpt = p->minbpt ? p->minbpt : 1;
+  }
+  int rc = BURR_OK;
+  double bits = 0;
+  double cur = time_batch(in.keys, in.vals, off, rs, p, table, reps, &bits, &rc);
+  if (rc != BURR_OK) return burr_set_error(rc);
+  for (uint32_t c = 0; c < nclasses; ++c) {
+    const uint32_t keep = table[c].minbpt;
+    uint32_t best = keep;
+    double best_t = cur, best_bits = bits;
+    for (uint32_t k = 0; k < ncandidates; ++k) {
+      if (candidates[k] == keep) continue;
+      table[c].minbpt = candidates[k];
+      double b2 = 0;
+      const double t = time_batch(in.keys, in.vals, off, rs, p, table, reps, &b2, &rc);
+      if (rc != BURR_OK) return burr_set_error(rc);
+      if (t < best_t * 0.97) {
+        best = candidates[k];
+        best_t = t;
+        best_bits = b2;
+      }
+    }
+    table[c].minbpt = best;
+    cur = best_t;
+    bits = best_bits;
+  }
+  for (uint32_t c = 0; c < nclasses; ++c) {
+    out[c] = table[c];
+    out[c].ns_per_key = cur * 1e9 / (double)total;
+    out[c].bits_per_key = bits / (double)total;
+  }
+  burr_set_error(BURR_OK);
+  return BURR_OK;
+}
+
+}  // namespace
+
+extern "C" int burr_autotune(const burr_params* p, uint32_t r, const uint64_t* sizes,
+                             uint64_t nsizes, const uint64_t* n_max, uint32_t nclasses,
+                             const uint32_t* candidates, uint32_t ncandidates,
                              uint64_t keys_per_trial, uint32_t reps, burr_tune_entry* out) {
   if (!p || !n_max || !candidates || !out || nclasses == 0 || ncandidates == 0 || r < 1 ||
-      r > 32 || keys_per_trial == 0 || reps == 0)
+      r > 32 || reps == 0 || (!sizes && keys_per_trial == 0) || (sizes && nsizes == 0))
     return burr_set_error(BURR_E_INVALID);
   for (uint32_t c = 0; c < nclasses; ++c)
     if (n_max[c] == 0 || (c > 0 && n_max[c] <= n_max[c - 1]))
       return burr_set_error(BURR_E_INVALID);
   for (uint32_t k = 0; k < ncandidates; ++k)
     if (candidates[k] == 0) return burr_set_error(BURR_E_INVALID);
+  if (sizes) return tune_mix(p, r, sizes, nsizes, n_max, nclasses, candidates, ncandidates, reps,
+                             out);
 
   // inputs for the largest trial batch, made once
   uint64_t cap = 0;
@@ -92,12 +186,21 @@ extern "C" int burr_autotune(const burr_params* p, uint32_t r, const uint64_t* n
       }
       ns[k] = best * 1e9 / keys;
     }
+    // the fastest candidate; among those within 3 % of it (timing noise),
+    // the parameter block's own value if it is one, else the smallest tables
     uint32_t pick = 0;
     for (uint32_t k = 1; k < ncandidates; ++k)
       if (ns[k] < ns[pick]) pick = k;
     const double fastest = ns[pick];
+    int def = -1;
     for (uint32_t k = 0; k < ncandidates; ++k)
-      if (ns[k] <= fastest * 1.03 && bits[k] < bits[pick]) pick = k;
+      if (candidates[k] == p->minbpt && ns[k] <= fastest * 1.03) def = (int)k;
+    if (def >= 0) {
+      pick = (uint32_t)def;
+    } else {
+      for (uint32_t k = 0; k < ncandidates; ++k)
+        if (ns[k] <= fastest * 1.03 && bits[k] < bits[pick]) pick = k;
+    }
     out[c].n_max = n_max[c];
     out[c].minbpt = candidates[pick];
     out[c].reserved = 0;

@@ -171,3 +171,26 @@ def test_autotune_table_is_valid_and_builds_exactly():
                               dict(ranges=1 << 16, minbpt=cls["minbpt"]))
         check_handle(b.member(i), ref, mk, n_queries=2000)
     b.free()
+
+
+def test_autotune_on_a_size_mix_builds_exactly():
+    burr = _burr()
+    params = burr.Params(ranges=1 << 16)
+    mix = W.batch_sizes(3000, 7)
+    print(f"[batch] autotune on a mix of {len(mix)} sizes", flush=True)
+    table = burr.autotune(3, [1000, 10_000, 200_000], [4, 16, 64], sizes=mix, reps=1,
+                          params=params)
+    assert [e["n_max"] for e in table] == [1000, 10_000, 200_000]
+    assert all(e["minbpt"] in (4, 16, 64) for e in table)
+    assert table[0]["ns_per_key"] > 0 and 3.0 <= table[0]["bits_per_key"] < 4.5
+    print(f"[batch] table {table}", flush=True)
+    sizes = [500, 8000, 120_000]
+    rs = [3, 3, 3]
+    keys, vals, offs = _make(sizes, rs, 73)
+    b = burr.build_batch_tuned(to_dev(keys), to_dev(vals), offs, rs, table,
+                               burr.Params(ranges=1 << 16, flags=burr.BURR_FLAG_KEEP_LAYER_KEYS))
+    for i, n in enumerate(sizes):
+        cls = next((e for e in table if e["n_max"] >= n), table[-1])
+        mk, ref = _member_ref(keys, vals, offs, rs, i, dict(ranges=1 << 16, minbpt=cls["minbpt"]))
+        check_handle(b.member(i), ref, mk, n_queries=2000)
+    b.free()

@@ -93,14 +93,17 @@ def test_invalid_tuning_arguments_fail_without_touching_the_device():
     out = (burr._CTuneEntry * 2)()
     nm = np.array([1000, 500], dtype=np.uint64)     # not ascending
     cand = np.array([4, 16], dtype=np.uint32)
-    assert lib.burr_autotune(ctypes.byref(p), 8, nm.ctypes.data, 2, cand.ctypes.data, 2,
-                             10_000, 1, out) == burr.BURR_E_INVALID
+    assert lib.burr_autotune(ctypes.byref(p), 8, None, 0, nm.ctypes.data, 2, cand.ctypes.data,
+                             2, 10_000, 1, out) == burr.BURR_E_INVALID
     nm = np.array([500, 1000], dtype=np.uint64)
     zero = np.array([4, 0], dtype=np.uint32)
-    assert lib.burr_autotune(ctypes.byref(p), 8, nm.ctypes.data, 2, zero.ctypes.data, 2,
-                             10_000, 1, out) == burr.BURR_E_INVALID
-    assert lib.burr_autotune(ctypes.byref(p), 0, nm.ctypes.data, 2, cand.ctypes.data, 2,
-                             10_000, 1, out) == burr.BURR_E_INVALID
+    assert lib.burr_autotune(ctypes.byref(p), 8, None, 0, nm.ctypes.data, 2, zero.ctypes.data,
+                             2, 10_000, 1, out) == burr.BURR_E_INVALID
+    assert lib.burr_autotune(ctypes.byref(p), 0, None, 0, nm.ctypes.data, 2, cand.ctypes.data,
+                             2, 10_000, 1, out) == burr.BURR_E_INVALID
+    sizes = np.array([100, 200], dtype=np.uint64)  # a size sample of length 0
+    assert lib.burr_autotune(ctypes.byref(p), 8, sizes.ctypes.data, 0, nm.ctypes.data, 2,
+                             cand.ctypes.data, 2, 0, 1, out) == burr.BURR_E_INVALID
 
 
 def test_python_binding_fails_loudly_without_library(monkeypatch):
