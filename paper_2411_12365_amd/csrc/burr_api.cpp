@@ -328,8 +328,9 @@ uint64_t plan_final(const burr_params& p, uint64_t n, uint32_t attempt) {
 //    outgrown buffers are released with the workspace, after every launch
 //    that used them;
 //  - kept between builds (al == nullptr, plain hipMalloc): an outgrown buffer
-//    is freed at once - reserve calls happen only while the build stream is
-//    idle (every layer ends with a stream synchronization).
+//    is freed at once; hipFree waits for the device first, so a buffer that
+//    the previous layer's last kernels still use is never freed under them
+//    (the next layer is planned while they run).
 struct Workspace {
   Allocator* al;
   std::vector<void*> owned;
@@ -509,7 +510,7 @@ int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s) {
   const uint64_t words = 6 * (J + 1) + (J + 1) / 2 + 1;
   if (!ws.reserve_table(words) || !ws.reserve_host(words * 8)) return set_error(BURR_E_NOMEM);
   // the pinned staging is reused only after the stream has passed this copy
-  // (every layer ends with a synchronization)
+  // (the host waits for each layer's results, which follow it on the stream)
   uint64_t* h = reinterpret_cast<uint64_t*>(ws.host);
   memset(h, 0, words * 8);
   memcpy(h, t.key_off.data(), (J + 1) * 8);
@@ -573,9 +574,9 @@ double elapsed_ms(hipEvent_t a, hipEvent_t b) {
 }
 
 struct Events {
-  hipEvent_t e[6] = {};
+  std::vector<hipEvent_t> e;
   bool ok = true;
-  Events() {
+  explicit Events(size_t n = 6) : e(n, nullptr) {
     for (auto& x : e) ok = hipEventCreate(&x) == hipSuccess && ok;
   }
   ~Events() {
@@ -810,8 +811,10 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   b->arena = (uint8_t*)b->alloc(b->arena_cap);
   if (!b->arena) return set_error(BURR_E_NOMEM);
   b->table_bytes = b->arena_cap;
-  Events ev;
+  // events: [0] start, 6 per layer, then the final layer's start and end
+  Events ev(3 + 6 * (size_t)p.layers);
   if (!ev.ok) return set_error(BURR_E_DEVICE);
+  hipEvent_t* const evfin = ev.e.data() + 1 + 6 * p.layers;
   if (!ws.reserve_keys(off.back()) || (!ws.diag && !ws.alloc(ws.diag, 16)))
     return set_error(BURR_E_NOMEM);
   HIP_TRY(hipMemsetAsync(ws.diag, 0, 16 * 8, s));
@@ -834,8 +837,10 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   uint32_t cur_vbytes = value_bytes(rmax);
   bool first = true;
 
+  uint32_t nlayers = 0;  // layers launched
   for (uint32_t li = 0; li < p.layers && !active.empty(); ++li) {
     LayerStore& LS = b->layers[li];
+    hipEvent_t* const el = ev.e.data() + 1 + 6 * li;  // sort, solve, solved, results, backsub, end
     take_host(LS, active.size());
     Table t = std::move(LS.t);
     t.fill(active.size(), [&](size_t a, uint64_t* n, uint64_t* m, uint64_t* R, uint32_t* r) {
@@ -861,7 +866,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
       if (!LS.keys) return set_error(BURR_E_NOMEM);
       HIP_TRY(hipMemcpyAsync(LS.keys, cur_keys, g.nkeys * 8, hipMemcpyDeviceToDevice, s));
     }
-    HIP_TRY(hipEventRecord(ev.e[1], s));
+    HIP_TRY(hipEventRecord(el[0], s));
     rc = run_sort(ws, cur_keys, cur_vals, cur_vbytes, first, p.filter_mode != 0, fp_salt, g, s);
     if (rc != BURR_OK) return rc;
 
@@ -879,27 +884,31 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     sa.diag = ws.diag;
     sa.nrec = (uint32_t)(g.nkeys + g.nbuckets);
     HIP_TRY(hipMemsetAsync(ws.res, 0, ws.results_words(g.J) * 4, s));
-    HIP_TRY(hipEventRecord(ev.e[2], s));
+    HIP_TRY(hipEventRecord(el[1], s));
     HIP_TRY(solve_layer(sa, s));
-    HIP_TRY(hipEventRecord(ev.e[3], s));
+    HIP_TRY(hipEventRecord(el[2], s));
 
+    // per-structure bump counts (an exclusive scan of the per-bucket counts)
+    // go to the host first: they are all the next layer's planning needs, so
+    // the host plans and launches it while back-substitution and the gather
+    // of the bumped keys still run (the next layer's keys stay grouped by
+    // structure in structure order)
+    HIP_TRY(hipMemsetAsync(ws.bump + g.nbuckets, 0, 4, s));
+    HIP_TRY(scan_exclusive(ws.bump, g.nbuckets + 1, ws.scan_tmp, s));
+    HIP_TRY(struct_offsets(ws.bump, g, ws.soff, s));
+    HIP_TRY(hipMemcpyAsync(ws.hres, ws.res, ws.results_words(g.J) * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(el[3], s));
     LS.codes = (uint64_t*)b->alloc_table(t.code_base.back() * 8);
     LS.W = (uint64_t*)b->alloc_table(t.word_base.back() * 8);
     if (!LS.codes || !LS.W) return set_error(BURR_E_NOMEM);
     HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, ws.occ, g, LS.W, s));
     HIP_TRY(pack_codes(ws.code8, g, t.code_base.back(), LS.codes, s));
-    HIP_TRY(hipEventRecord(ev.e[4], s));
-
-    // bumped keys: exclusive scan of per-bucket counts, then gather; the
-    // next layer's keys stay grouped by structure in structure order
-    HIP_TRY(hipMemsetAsync(ws.bump + g.nbuckets, 0, 4, s));
-    HIP_TRY(scan_exclusive(ws.bump, g.nbuckets + 1, ws.scan_tmp, s));
-    HIP_TRY(struct_offsets(ws.bump, g, ws.soff, s));
-    HIP_TRY(hipMemcpyAsync(ws.hres, ws.res, ws.results_words(g.J) * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(el[4], s));
     HIP_TRY(gather_bumped(ws.rec, ws.bstart, ws.bump, g.nbuckets, ws.keysA, ws.valsA, s));
-    HIP_TRY(hipEventRecord(ev.e[5], s));
+    HIP_TRY(hipEventRecord(el[5], s));
+    nlayers = li + 1;
     HOST_LAP(hc, "launch", li);
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipEventSynchronize(el[3]));
     HOST_LAP(hc, "device", li);
     const uint32_t* fails = ws.hres;
     const uint32_t* soff = ws.hres + g.J;
@@ -920,10 +929,6 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
         print_diag(ws.diag);
         return set_error(BURR_E_DEVICE);
       }
-    LS.ms_sort = elapsed_ms(ev.e[1], ev.e[2]);
-    LS.ms_solve = elapsed_ms(ev.e[2], ev.e[3]);
-    LS.ms_backsub = elapsed_ms(ev.e[3], ev.e[4]);
-    LS.ms_gather = elapsed_ms(ev.e[4], ev.e[5]);
     LS.steps = steps;
 
     next_active.clear();
@@ -951,7 +956,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   }
 
   // final plain layer of every member that still has keys
-  HIP_TRY(hipEventRecord(ev.e[1], s));
+  HIP_TRY(hipEventRecord(evfin[0], s));
   std::vector<uint64_t> fin_off(active.size() + 1, 0);
   for (size_t a = 0; a < active.size(); ++a) {
     b->members[active[a]].fin.n = cur_n[a];
@@ -983,11 +988,19 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
       if (!solved) return set_error(BURR_E_UNSOLVABLE);
     }
   }
-  HIP_TRY(hipEventRecord(ev.e[2], s));
+  HIP_TRY(hipEventRecord(evfin[1], s));
   HIP_TRY(hipStreamSynchronize(s));
   HOST_LAP(hc, "final", p.layers);
-  b->ms_final = elapsed_ms(ev.e[1], ev.e[2]);
-  b->ms_total = elapsed_ms(ev.e[0], ev.e[2]);
+  for (uint32_t li = 0; li < nlayers; ++li) {
+    const hipEvent_t* el = ev.e.data() + 1 + 6 * li;
+    LayerStore& LS = b->layers[li];
+    LS.ms_sort = elapsed_ms(el[0], el[1]);
+    LS.ms_solve = elapsed_ms(el[1], el[2]);
+    LS.ms_backsub = elapsed_ms(el[3], el[4]);
+    LS.ms_gather = elapsed_ms(el[2], el[3]) + elapsed_ms(el[4], el[5]);
+  }
+  b->ms_final = elapsed_ms(evfin[0], evfin[1]);
+  b->ms_total = elapsed_ms(ev.e[0], evfin[1]);
   return BURR_OK;
 }
 
