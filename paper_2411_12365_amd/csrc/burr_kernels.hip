@@ -751,21 +751,42 @@ struct SolveStats {};
 #endif
 
 // Inserts records [r0, r1) of the staged bucket q. Returns 0 if the set was
-// consistent, 1 if an inconsistency was met (its rows are removed again), or
-// 2 on an internal error. Each loop trip: lanes without a row take the next
-// records, every lane makes kSolveK XOR-and-shift steps against the ring,
-// then the lanes at an empty slot claim it. The steps need no per-lane
-// masking: at an empty slot (row 0, value 0) a step leaves the lane's row,
-// value and position unchanged (its row keeps bit 0, so the shift is 0),
-// and the state of lanes that finished is not used again.
-template <int LANES>
+// consistent, 1 if an inconsistency was met (its rows are removed again), 2
+// on an internal error, or 3 (FAST only) if the pass has to be run exactly.
+// Each loop trip: lanes without a row take the next records, every lane
+// makes kSolveK XOR-and-shift steps against the ring, then the lanes at an
+// empty slot claim it. The steps need no per-lane masking: at an empty slot
+// (row 0, value 0) a step leaves the lane's row, value and position
+// unchanged (its row keeps bit 0, so the shift is 0), and the state of lanes
+// that finished is not used again.
+// A lane's position is kept as the byte offset of its slot within the ring
+// (8 (i mod 128) for slot i), which addresses the slot's row and value; a
+// step advances it with one shift-add and one mask. Bucket q's rows lie in
+// slots [64 q, 64 q + 126], so a row ending in the other ring half than
+// bucket q's own has crossed into bucket q+1: when q is the range's last
+// bucket and there is no spill buffer (last_half set), claiming it would be
+// an error.
+// With 64 lanes per range, r0, r1 and next are wave-uniform (scalar), so the
+// record hand-out costs no vector instructions once the records are taken.
+//
+// FAST: a step finds the shift from the row's low word alone. Rows are hash
+// words with bit 0 set, so after an XOR with an occupied slot's row the low
+// word is nonzero unless the row reduced to zero (redundant or inconsistent)
+// or, with probability 2^-31, its lowest set bit is in the high word. If an
+// active lane met a zero low word in a trip, the pass stops before that
+// trip's claims, is undone and returns 3, and the caller runs it again
+// exactly (not FAST), which gives the outcome of sequential insertion in
+// every case. Without such an event, lanes only leave the active state by
+// claiming, so the steps track nothing else. FAST passes are not used with
+// last_half (they do not check claims against the range end).
+template <int LANES, bool FAST>
 __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
                                      const SolveArgs& a, const uint4* rec4, uint32_t hq,
-                                     uint32_t q, uint32_t r0, uint32_t r1, uint32_t limit,
+                                     uint32_t q, uint32_t r0, uint32_t r1, bool last_half,
                                      uint64_t& steps, SolveStats& st) {
   (void)st;
   (void)steps;
-  BURR_STAT(++st.passes;)
+  BURR_STAT(++st.passes; uint64_t pass_steps = 0;)
   // occupied slots before the pass: an undo clears the slots claimed since
   uint64_t before[kRing / 64];
 #pragma unroll
@@ -776,87 +797,110 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
       m |= G.ballot(R.c[h * 64 + k * LANES + G.lane] != 0) << (k * LANES);
     before[h] = m;
   }
-  bool active = false, bad = false;
+  // byte offset of a slot within the ring, opaque to the compiler: with a
+  // known mask it merges the steps' masked shift-adds into longer sums
+  uint32_t kMask;
+  asm("s_mov_b32 %0, %1" : "=s"(kMask) : "i"(kRing * 8 - 8));
+  const uint32_t base = (q & 1u) * 512u;  // byte offset of bucket q's first slot
+  bool active = false, conflict = false, err = false, hung = false, special = false;
   uint64_t c = 0;
-  uint32_t v = 0, i = 0;
+  uint32_t v = 0, ib = 0;  // ib: byte offset of the lane's slot
   uint32_t next = r0;
   uint32_t guard = (r1 - r0) * 256u + 1024u;  // a lane advances or stops every other step
-  uint32_t result = 0;
   while (true) {
-    // lanes without a row take the next records
-    const uint64_t freem = G.ballot(!active);
-    const uint32_t rank = G.rank(freem);
-    if (!active && next + rank < r1) {
-      const uint32_t t = next + rank;
-      constexpr uint32_t last = Stage<LANES>::items - 1;
-      uint4 r = R.stage[t < last ? t + 1 : last];
-      c = slot_row(r);
-      if (t >= last) {  // bucket larger than the stage (rare; a load that cannot merge with the LDS read)
-        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-        const u32x4 g4 = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(rec4 + hq + 1 + t));
-        r = make_uint4(g4.x, g4.y, g4.z, g4.w);
-        c = row_of((uint64_t)r.x | ((uint64_t)r.y << 32), a.g);
+    if (next < r1) {
+      // lanes without a row take the next records
+      const uint64_t freem = G.ballot(!active);
+      const uint32_t rank = G.rank(freem);
+      if (!active && rank < r1 - next) {
+        const uint32_t t = next + rank;
+        constexpr uint32_t last = Stage<LANES>::items - 1;
+        uint4 r = R.stage[t < last ? t + 1 : last];
+        c = slot_row(r);
+        if (t >= last) {  // bucket larger than the stage (rare; a load that cannot merge with the LDS read)
+          typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+          const u32x4 g4 = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(rec4 + hq + 1 + t));
+          r = make_uint4(g4.x, g4.y, g4.z, g4.w);
+          c = row_of((uint64_t)r.x | ((uint64_t)r.y << 32), a.g);
+        }
+        v = r.z;
+        ib = ((r.w & 63u) << 3) + base;
+        active = true;
       }
-      v = r.z;
-      i = 64u * q + (r.w & 63u);
-      active = true;
-    }
-    const uint32_t nfree = (uint32_t)__popcll(freem);
-    next = (r1 - next < nfree) ? r1 : next + nfree;
-    if constexpr (LANES == 64) next = __builtin_amdgcn_readfirstlane(next);  // uniform
-    if (!G.any(active)) break;
-    BURR_STAT(++st.trips; st.lanes += __popcll(G.ballot(active));)
-    if (guard-- == 0) {
-      result = 2;
+      const uint32_t nfree = (uint32_t)__popcll(freem);
+      next = (r1 - next < nfree) ? r1 : next + nfree;
+      if constexpr (LANES == 64) next = __builtin_amdgcn_readfirstlane(next);  // uniform
+      // a record was taken, or every lane already had one: some lane is active
+    } else if (!G.any(active)) {
       break;
     }
-    bool conflict = false;
+    BURR_STAT(++st.trips; st.lanes += __popcll(G.ballot(active));)
+    if (guard-- == 0) {
+      hung = true;
+      break;
+    }
     uint64_t row = 0;
-    uint32_t ib = i << 3;  // byte offset of the lane's slot
+    uint32_t off = ib;
+    bool low_ok = true;  // FAST: every step's low word was nonzero
 #pragma unroll
     for (int u = 0; u < kSolveK; ++u) {
-      uint32_t rv;
-      ring_read_b(R, ib, row, rv);
+      off = ib;
+      row = *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(R.c) + off);
+      const uint32_t rv = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(R.v) + off);
       const uint64_t cx = c ^ row;
       const uint32_t vx = v ^ rv;
-      const bool nz = cx != 0;  // else reduced to 0 = vx: redundant or inconsistent
-      BURR_STAT(steps += (active && row != 0) ? 1u : 0u;)
-      conflict = conflict || (active && !nz && vx != 0);
-      active = active && nz;
-      const uint32_t j = (uint32_t)__builtin_ctzg(cx, 64);
+      BURR_STAT(pass_steps += (active && row != 0) ? 1u : 0u;)
+      uint32_t j;
+      if constexpr (FAST) {
+        const uint32_t lo = (uint32_t)cx;
+        low_ok = low_ok && lo != 0;
+        // lowest set bit of the low word (all ones for 0: the pass stops)
+        asm("v_ffbl_b32 %0, %1" : "=v"(j) : "v"(lo));
+      } else {
+        const bool nz = cx != 0;  // else reduced to 0 = vx: redundant or inconsistent
+        conflict = conflict || (active && !nz && vx != 0);
+        active = active && nz;
+        j = (uint32_t)__builtin_ctzg(cx, 64);
+      }
       c = cx >> (j & 63u);
       v = vx;
-      ib += j << 3;
+      ib = (ib + (j << 3)) & kMask;
     }
-    i = ib >> 3;
-    // the last step read an empty slot: the lane stayed on it
+    // the last step read an empty slot: the lane stayed on it (at byte offset off)
     const bool at_empty = active && row == 0;
+    if constexpr (FAST) {
+      if (G.any(active && !low_ok)) {
+        special = true;
+        break;
+      }
+    }
     if (at_empty) {
-      const uint32_t p = i & (kRing - 1);
-      if (i >= limit && !(a.spillC && i < limit + 64u)) {
+      if (!FAST && last_half && ((off ^ base) & 512u)) {
         active = false;  // unreachable: a kept row crossing the range end
-        result = 2;
+        err = true;
       } else {
-        const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(&R.c[p]), 0ull,
-                                       (unsigned long long)c);
+        const uint64_t old = atomicCAS(
+            reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(R.c) + off), 0ull,
+            (unsigned long long)c);
         if (old == 0) {
-          R.v[p] = v;
+          *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(R.v) + off) = v;
           active = false;
         }
         // otherwise another lane took the slot: step against its row next time
       }
     }
-    if (G.any(conflict)) {
-      bad = true;
-      break;
-    }
-    if (G.any(result == 2)) {
-      result = 2;
-      break;
+    if constexpr (!FAST) {
+      if (G.any(conflict || err)) break;
     }
   }
   G.sync();
-  if (bad || result == 2) {
+  uint32_t result;
+  if constexpr (FAST)
+    result = hung ? 2u : (special ? 3u : 0u);
+  else
+    result = (hung || G.any(err)) ? 2u : (G.any(conflict) ? 1u : 0u);
+  BURR_STAT(if (result != 3) steps += pass_steps;)  // a stopped FAST pass is run again
+  if (result != 0) {
 #pragma unroll
     for (uint32_t k = 0; k < kRing / LANES; ++k) {
       const uint32_t t = k * LANES + G.lane;
@@ -864,7 +908,7 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
     }
   }
   G.sync();
-  return result == 2 ? 2u : (bad ? 1u : 0u);
+  return result;
 }
 
 // Publishes a released ring half: its 64 rows, values and occupancy word go
@@ -916,7 +960,6 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
     fb = g.bucket_base[js] + f0;
     nq = (uint32_t)((lr + 1) * B / Rn - f0);
   }
-  const uint32_t limit = 64u * nq;
   const uint32_t last_item = a.nrec - 1;
   const uint4* rec4 = reinterpret_cast<const uint4*>(a.rec);
 #pragma unroll
@@ -956,14 +999,30 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
         nx[k] = rec4[t < last_item ? t : last_item];
       }
     }
-    const uint4 hd = R.stage[0];
+    uint4 hd = R.stage[0];
+    if constexpr (LANES == 64) {  // the same for every lane: keep it scalar
+      hd.x = __builtin_amdgcn_readfirstlane(hd.x);
+      hd.y = __builtin_amdgcn_readfirstlane(hd.y);
+      hd.z = __builtin_amdgcn_readfirstlane(hd.z);
+      hd.w = __builtin_amdgcn_readfirstlane(hd.w);
+    }
     const uint32_t count = hd.x, kf = hd.y & 3u;
     const uint32_t e1 = hd.z, e2 = hd.z + hd.w;  // ends of ranks 0 and 1
+    // claims past the range end: only from its last bucket, without a spill buffer
+    const bool last_half = q + 1 == nq && !a.spillC;
     const uint32_t keep_ranks = g.plain ? 3u : 3u - kf;
     const uint32_t cand = keep_ranks == 3 ? count : (keep_ranks == 2 ? e2 : (keep_ranks == 1 ? e1 : 0u));
     uint32_t kept = cand, code = kf;
     if (cand > 0) {
-      uint32_t res = wave_pass(R, G, a, rec4, hq, q, 0, cand, limit, steps, sst);
+      // records [0, n) of the bucket: fast pass, exact pass if it stopped
+      // (exact only in a range's last bucket without a spill buffer)
+      auto pass = [&](uint32_t n) {
+        const uint32_t res =
+            last_half ? 3u : wave_pass<LANES, true>(R, G, a, rec4, hq, q, 0, n, false, steps, sst);
+        return res == 3 ? wave_pass<LANES, false>(R, G, a, rec4, hq, q, 0, n, last_half, steps, sst)
+                        : res;
+      };
+      uint32_t res = pass(cand);
       if (res == 1 && g.plain) {
         if (G.lane == 0) a.fail[js] = 1u;
         failed = true;
@@ -974,7 +1033,7 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
         for (uint32_t rr = keep_ranks - 1; rr >= 1 && res != 2; --rr) {
           const uint32_t e = rr == 2 ? e2 : e1;
           if (e == failed_size) continue;  // the same set again
-          res = e ? wave_pass(R, G, a, rec4, hq, q, 0, e, limit, steps, sst) : 0u;
+          res = e ? pass(e) : 0u;
           if (res == 0) {
             kept = e;
             code = 3 - rr;
