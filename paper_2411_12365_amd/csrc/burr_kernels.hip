@@ -661,26 +661,40 @@ struct Stage {
   static constexpr uint32_t per_lane = items / LANES;
 };
 
-// The ring of one range: rows and values in separate arrays with the same
-// 8-byte stride (one masked byte offset addresses both; separate arrays
-// spread the lanes' random slots over more LDS banks than 16-byte slots);
-// an empty slot has row 0 and value 0.
+// The ring of one range: rows in an array of 8-byte slots and values in an
+// array of 4-byte slots, addressed by the row's byte offset (the value's is
+// half of it). Lanes read random slots, so the narrow value array spreads
+// their value reads over twice as many LDS banks as an 8-byte stride would
+// (measured: 16-byte {row, value} slots and 8-byte value slots both had
+// more bank conflicts). An empty slot has row 0 and value 0; a row has bit 0
+// set.
 template <int LANES>
 struct WaveRing {
   uint64_t c[kRing];
-  uint64_t v[kRing];  // value in the low word
+  uint32_t v[kRing];
   uint4 stage[Stage<LANES>::items];
 };
-// row and value of slot i, given ib = 8 i (the ring wraps every 1 KB)
+// row and value of the slot at byte offset off = 8 * slot
 template <class Ring>
-__device__ inline void ring_read_b(const Ring& R, uint32_t ib, uint64_t& row, uint32_t& val) {
-  const uint32_t off = ib & (kRing * 8 - 8);
+__device__ inline void ring_read_b(const Ring& R, uint32_t off, uint64_t& row, uint32_t& val) {
   row = *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(R.c) + off);
-  val = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(R.v) + off);
+  val = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(R.v) + (off >> 1));
+}
+// claims the empty slot at byte offset off for row c and value v; false if
+// another lane took it first
+template <class Ring>
+__device__ inline bool ring_claim(Ring& R, uint32_t off, uint64_t c, uint32_t v) {
+  const uint64_t old = atomicCAS(
+      reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(R.c) + off), 0ull,
+      (unsigned long long)c);
+  if (old != 0) return false;
+  *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(R.v) + (off >> 1)) = v;
+  return true;
 }
 template <class Ring>
 __device__ inline void ring_read(const Ring& R, uint32_t i, uint64_t& row, uint32_t& val) {
-  ring_read_b(R, i << 3, row, val);
+  row = R.c[i];
+  val = R.v[i];
 }
 template <class Ring>
 __device__ inline void ring_clear(Ring& R, uint32_t p) {
@@ -800,8 +814,9 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
   // byte offset of a slot within the ring, opaque to the compiler: with a
   // known mask it merges the steps' masked shift-adds into longer sums
   uint32_t kMask;
-  asm("s_mov_b32 %0, %1" : "=s"(kMask) : "i"(kRing * 8 - 8));
-  const uint32_t base = (q & 1u) * 512u;  // byte offset of bucket q's first slot
+  asm("s_mov_b32 %0, %1" : "=s"(kMask) : "i"((kRing - 1) * 8));
+  constexpr uint32_t kHalf = 64u * 8u;  // byte size of a ring half (rows)
+  const uint32_t base = (q & 1u) * kHalf;        // byte offset of bucket q's first slot
   bool active = false, conflict = false, err = false, hung = false, special = false;
   uint64_t c = 0;
   uint32_t v = 0, ib = 0;  // ib: byte offset of the lane's slot
@@ -845,8 +860,8 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
 #pragma unroll
     for (int u = 0; u < kSolveK; ++u) {
       off = ib;
-      row = *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(R.c) + off);
-      const uint32_t rv = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(R.v) + off);
+      uint32_t rv;
+      ring_read_b(R, off, row, rv);
       const uint64_t cx = c ^ row;
       const uint32_t vx = v ^ rv;
       BURR_STAT(pass_steps += (active && row != 0) ? 1u : 0u;)
@@ -875,17 +890,11 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
       }
     }
     if (at_empty) {
-      if (!FAST && last_half && ((off ^ base) & 512u)) {
+      if (!FAST && last_half && ((off ^ base) & kHalf)) {
         active = false;  // unreachable: a kept row crossing the range end
         err = true;
       } else {
-        const uint64_t old = atomicCAS(
-            reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(R.c) + off), 0ull,
-            (unsigned long long)c);
-        if (old == 0) {
-          *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(R.v) + off) = v;
-          active = false;
-        }
+        if (ring_claim(R, off, c, v)) active = false;
         // otherwise another lane took the slot: step against its row next time
       }
     }
@@ -937,8 +946,8 @@ __device__ inline void clear_half(WaveRing<LANES>& R, const Grp<LANES>& G, uint3
   for (uint32_t k = 0; k < 64 / LANES; ++k) ring_clear(R, hb + k * LANES + G.lane);
 }
 
-// 8 waves per SIMD: the kernel then fits 64 VGPRs (62, no spills), and the
-// ring and stage of 32 waves (3.6 KB each) fit a CU's LDS.
+// 8 waves per SIMD: the kernel then fits 64 VGPRs (no spills), and the
+// ring and stage of 32 waves (3.5 KB each) fit a CU's LDS.
 template <int LANES>
 __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
   constexpr uint32_t NG = 64 / LANES;
