@@ -651,7 +651,7 @@ int final_attempt(burr_batch* b, Workspace& ws, const std::vector<uint32_t>& lis
   HIP_TRY(final_boundaries(fa, s));
   uint64_t* W = (uint64_t*)b->alloc_table(t.word_base.back() * 8 + 8);
   if (!W) return set_error(BURR_E_NOMEM);
-  HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, ws.occ, g, W, s, ws.bnd));
+  HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, g, W, s, ws.bnd));
   HIP_TRY(hipMemcpyAsync(ws.hres, ws.res, g.J * 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   fails.assign(ws.hres, ws.hres + g.J);
@@ -901,7 +901,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     LS.codes = (uint64_t*)b->alloc_table(t.code_base.back() * 8);
     LS.W = (uint64_t*)b->alloc_table(t.word_base.back() * 8);
     if (!LS.codes || !LS.W) return set_error(BURR_E_NOMEM);
-    HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, ws.occ, g, LS.W, s));
+    HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, g, LS.W, s));
     HIP_TRY(pack_codes(ws.code8, g, t.code_base.back(), LS.codes, s));
     HIP_TRY(hipEventRecord(el[4], s));
     HIP_TRY(gather_bumped(ws.rec, ws.bstart, ws.bump, g.nbuckets, ws.keysA, ws.valsA, s));

@@ -82,12 +82,12 @@ struct SolveArgs {
 hipError_t solve_layer(const SolveArgs& a, hipStream_t s);
 
 // Back-substitution per range into column-interleaved words
-// W[word_base[j] + k*r_j + col]. bnd (optional, 64 u32 per range): solution
-// values of the 63 slots after each range's end (final-layer segments, whose
-// rows cross segment ends).
-hipError_t back_substitute(const uint64_t* rowsC, const uint32_t* rowsV, const uint64_t* occ,
-                           const LayerGeom& g, uint64_t* W, hipStream_t s,
-                           const uint32_t* bnd = nullptr);
+// W[word_base[j] + k*r_j + col]. Free slots hold row 0 and value 0 (as every
+// released block does). bnd (optional, 64 u32 per range): solution values of
+// the 63 slots after each range's end (final-layer segments, whose rows
+// cross segment ends).
+hipError_t back_substitute(const uint64_t* rowsC, const uint32_t* rowsV, const LayerGeom& g,
+                           uint64_t* W, hipStream_t s, const uint32_t* bnd = nullptr);
 
 // code8[B] -> packed 2-bit code words of every structure
 hipError_t pack_codes(const uint8_t* code8, const LayerGeom& g, uint64_t ncode_words,

@@ -1107,21 +1107,24 @@ hipError_t solve_layer(const SolveArgs& a, hipStream_t s) {
 // Back-substitution: a group of RG lanes per range, one lane per value column
 // ---------------------------------------------------------------------------
 // From the range end down, per 64-slot block: the group loads the block's
-// rows, values and occupancy word into LDS (the next block's loads are in
-// flight meanwhile), then every lane runs the block's 64 slots for its
-// column: Z[i] = V[i] xor parity(C[i] >> 1 AND the next 63 values), kept as a
-// 64-bit window per column; free slots are 0.
+// rows and values into LDS (the next block's loads are in flight meanwhile),
+// then every lane runs the block's 64 slots for its column:
+// Z[i] = V[i] xor parity(C[i] >> 1 AND the next 63 values), kept as a 64-bit
+// window per column. Free slots are 0 without a test: every released block
+// holds row 0 and value 0 in its free slots (the ring's empty slots are
+// zero, and merges write occupied slots only), which gives Z = 0 there. After
+// a block's 64 slots the window holds exactly the block's values.
 template <int RG>
 __global__ __launch_bounds__(64) void k_backsub(const uint64_t* __restrict__ rowsC,
-                                                const uint32_t* __restrict__ rowsV,
-                                                const uint64_t* __restrict__ occ, LayerGeom g,
+                                                const uint32_t* __restrict__ rowsV, LayerGeom g,
                                                 uint64_t* __restrict__ W,
                                                 const uint32_t* __restrict__ bnd) {
   constexpr int NG = 64 / RG;   // ranges per wave
   constexpr int PER = 64 / RG;  // slots each lane loads per block
-  __shared__ uint64_t sc[2][NG][64];
-  __shared__ uint32_t sv[2][NG][64];
-  __shared__ uint64_t so[2][NG];
+  // one padding slot per range: the groups read slot tt of their own block
+  // at the same time, which would otherwise fall into one LDS bank
+  __shared__ uint64_t sc[2][NG][65];  // rows shifted right by 1 (bit 0 is the pivot)
+  __shared__ uint32_t sv[2][NG][65];
   const uint32_t lane = threadIdx.x, grp = lane / RG, col = lane % RG;
   const uint64_t rho = (uint64_t)blockIdx.x * NG + grp;
   const bool valid = rho < g.nranges;
@@ -1148,7 +1151,6 @@ __global__ __launch_bounds__(64) void k_backsub(const uint64_t* __restrict__ row
   }
   uint64_t pc[PER];
   uint32_t pv[PER];
-  uint64_t po = 0;
 #define BURR_BS_LOAD(t)                                                  \
   if ((t) < nblk) {                                                      \
     const uint64_t base = (lb - 1 - (t)) * 64;                           \
@@ -1156,47 +1158,44 @@ __global__ __launch_bounds__(64) void k_backsub(const uint64_t* __restrict__ row
       pc[e] = rowsC[base + col + e * RG];                                \
       pv[e] = rowsV[base + col + e * RG];                                \
     }                                                                    \
-    if (col == 0) po = occ[lb - 1 - (t)];                                \
   }
   BURR_BS_LOAD(0u)
   for (uint32_t t = 0; t < maxblk; ++t) {
     const uint32_t buf = t & 1u;
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
-      sc[buf][grp][col + e * RG] = pc[e];
+      sc[buf][grp][col + e * RG] = pc[e] >> 1;
       sv[buf][grp][col + e * RG] = pv[e];
     }
-    if (col == 0) so[buf][grp] = po;
     __syncthreads();
     BURR_BS_LOAD(t + 1)
     if (t < nblk) {
-      const uint64_t oc = so[buf][grp];
-      uint64_t out = 0;
 #pragma unroll 8
       for (int tt = 63; tt >= 0; --tt) {
-        const uint64_t C = sc[buf][grp][tt] >> 1;
+        const uint64_t C = sc[buf][grp][tt];
         const uint32_t V = sv[buf][grp][tt];
-        const uint32_t zf = ((V >> col) ^ (uint32_t)__popcll(C & win)) & 1u;
-        const uint64_t z = ((oc >> tt) & 1ull) ? (uint64_t)zf : 0ull;
+        // parity of C AND win plus this column's value bit: the two words'
+        // ANDs folded by XOR, counted on top of V >> col, then bit 0
+        const uint32_t x = ((uint32_t)C & (uint32_t)win) ^ ((uint32_t)(C >> 32) & (uint32_t)(win >> 32));
+        const uint32_t z = ((uint32_t)__popc(x) + (V >> col)) & 1u;
         win = (win << 1) | z;
-        out |= z << tt;
       }
       const uint64_t k = lb - 1 - t;
-      if (col < r) W[wb + (k - bb) * r + col] = out;
+      if (col < r) W[wb + (k - bb) * r + col] = win;
     }
   }
 #undef BURR_BS_LOAD
 }
 
-hipError_t back_substitute(const uint64_t* rowsC, const uint32_t* rowsV, const uint64_t* occ,
-                           const LayerGeom& g, uint64_t* W, hipStream_t s, const uint32_t* bnd) {
+hipError_t back_substitute(const uint64_t* rowsC, const uint32_t* rowsV, const LayerGeom& g,
+                           uint64_t* W, hipStream_t s, const uint32_t* bnd) {
   if (g.nranges == 0) return hipSuccess;
   if (g.r <= 8)
-    k_backsub<8><<<(unsigned)((g.nranges + 7) / 8), 64, 0, s>>>(rowsC, rowsV, occ, g, W, bnd);
+    k_backsub<8><<<(unsigned)((g.nranges + 7) / 8), 64, 0, s>>>(rowsC, rowsV, g, W, bnd);
   else if (g.r <= 16)
-    k_backsub<16><<<(unsigned)((g.nranges + 3) / 4), 64, 0, s>>>(rowsC, rowsV, occ, g, W, bnd);
+    k_backsub<16><<<(unsigned)((g.nranges + 3) / 4), 64, 0, s>>>(rowsC, rowsV, g, W, bnd);
   else
-    k_backsub<32><<<(unsigned)((g.nranges + 1) / 2), 64, 0, s>>>(rowsC, rowsV, occ, g, W, bnd);
+    k_backsub<32><<<(unsigned)((g.nranges + 1) / 2), 64, 0, s>>>(rowsC, rowsV, g, W, bnd);
   return hipGetLastError();
 }
 
