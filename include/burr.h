@@ -77,7 +77,10 @@ typedef struct burr_params {
   uint32_t filter_mode;    /* 1: values ignored, store an r-bit fingerprint */
   uint32_t flags;          /* BURR_FLAG_* */
   uint64_t seed;           /* hash seed */
-  void* stream;            /* hipStream_t for all work; NULL = null stream */
+  void* stream;            /* hipStream_t all work is ordered on (a build's
+                              back-substitution runs on an internal stream that
+                              waits for and is waited on by this one through
+                              events); NULL = null stream */
   burr_alloc_fn alloc;     /* device workspace allocator; NULL = HIP pool */
   burr_free_fn free;
   void* alloc_ctx;
@@ -96,8 +99,10 @@ typedef struct burr_layer_stats {
                         built with -DBURR_SOLVE_STATS, else 0 */
   double ms_sort;    /* device time of the sort kernels (hipEvents) */
   double ms_solve;   /* device time of the insertion kernel */
-  double ms_backsub; /* device time of back-substitution + code packing */
-  double ms_gather;  /* device time of bumped-key compaction */
+  double ms_backsub; /* device time of back-substitution (on an internal stream,
+                        beside the next layer's work) */
+  double ms_gather;  /* device time of code packing, bump counts and bumped-key
+                        compaction */
 } burr_layer_stats;
 
 typedef struct burr_stats {

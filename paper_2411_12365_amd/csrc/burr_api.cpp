@@ -342,23 +342,27 @@ struct Workspace {
   size_t hres_cap = 0;
   uint32_t* res = nullptr;      // per-layer results: fail[J], soff[J+1], steps (u64)
   uint64_t cap_res = 0;
-  uint64_t cap_keys = 0, cap_m = 0, cap_B = 0, cap_items = 0, cap_scan = 0;
-  uint64_t cap_seg = 0, cap_tab = 0, cap_J = 0, cap_c1 = 0, cap_c2 = 0, cap_plan = 0;
+  uint64_t cap_keys = 0, cap_B = 0, cap_items = 0, cap_scan = 0;
+  uint64_t cap_seg = 0, cap_tab[2] = {0, 0}, cap_J = 0, cap_c1 = 0, cap_c2 = 0, cap_plan = 0;
   uint64_t* keysA = nullptr;  // next layer's keys
   uint32_t* valsA = nullptr;
   uint4 *p1 = nullptr, *p2 = nullptr;  // sort intermediates
   uint32_t *counts1 = nullptr, *counts2 = nullptr;
   uint32_t *binlo = nullptr, *nch = nullptr, *cbase = nullptr, *sstart = nullptr;
   Rec* rec = nullptr;
-  uint64_t* rowsC = nullptr;
-  uint32_t* rowsV = nullptr;
-  uint64_t* occ = nullptr;
+  // two sets of row arrays: layer L inserts into set L % 2 while the
+  // back-substitution of layer L-1 reads the other set on the side stream
+  uint64_t* rowsC[2] = {nullptr, nullptr};
+  uint32_t* rowsV[2] = {nullptr, nullptr};
+  uint64_t* occ[2] = {nullptr, nullptr};
+  uint64_t cap_m[2] = {0, 0};
+  hipStream_t side = nullptr;  // back-substitution (default priority, non-blocking)
   uint8_t* code8 = nullptr;
   uint32_t *bump = nullptr, *bstart = nullptr, *scan_tmp = nullptr;
   uint32_t* fail = nullptr;  // per structure
   uint32_t* soff = nullptr;  // per structure: first bumped key
   uint64_t* steps = nullptr;
-  uint64_t* tab = nullptr;   // layer table
+  uint64_t* tab[2] = {nullptr, nullptr};  // layer tables, in the row sets' alternation
   uint64_t* diag = nullptr;  // insertion-kernel diagnostics (16 u64)
   uint64_t *spillC = nullptr, *spill_occ = nullptr, *xfirst = nullptr;
   uint32_t *spillV = nullptr, *z0first = nullptr, *bnd = nullptr;
@@ -373,6 +377,12 @@ struct Workspace {
     }
     if (host) (void)hipHostFree(host);
     if (hres) (void)hipHostFree(hres);
+    if (side) (void)hipStreamDestroy(side);
+  }
+  hipStream_t side_stream() {
+    if (!side && hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess)
+      side = nullptr;
+    return side;
   }
   template <typename T>
   bool alloc(T*& ptr, uint64_t count) {
@@ -448,10 +458,10 @@ struct Workspace {
     cap_items = count;
     return alloc(rec, count);
   }
-  bool reserve_slots(uint64_t m) {
-    if (m <= cap_m && rowsC) return true;
-    cap_m = m;
-    return alloc(rowsC, m) && alloc(rowsV, m) && alloc(occ, m / 64 + 1);
+  bool reserve_slots(uint64_t m, int set) {
+    if (m <= cap_m[set] && rowsC[set]) return true;
+    cap_m[set] = m;
+    return alloc(rowsC[set], m) && alloc(rowsV[set], m) && alloc(occ[set], m / 64 + 1);
   }
   bool reserve_scan(uint64_t n) {
     const uint64_t need = scan_tmp_words(n) + 64;
@@ -478,10 +488,10 @@ struct Workspace {
     return reserve_scan(std::max(c1, c2) + 1);
   }
   bool reserve_structs(uint64_t J) { return reserve_results(J); }
-  bool reserve_table(uint64_t words) {
-    if (words <= cap_tab && tab) return true;
-    cap_tab = words;
-    return alloc(tab, words);
+  bool reserve_table(uint64_t words, int set) {
+    if (words <= cap_tab[set] && tab[set]) return true;
+    cap_tab[set] = words;
+    return alloc(tab[set], words);
   }
   bool reserve_segments(uint64_t P) {
     if (P <= cap_seg && spillC) return true;
@@ -505,10 +515,13 @@ void print_diag(const uint64_t* d) {
 }
 
 // Uploads a table (one device buffer) and fills the geometry's pointers and totals.
-int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s) {
+// The table goes to ws.tab[set]: a layer's back-substitution reads it on the
+// side stream while the next layer uploads its own into the other buffer.
+int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s, int set) {
   const uint64_t J = t.J();
   const uint64_t words = 6 * (J + 1) + (J + 1) / 2 + 1;
-  if (!ws.reserve_table(words) || !ws.reserve_host(words * 8)) return set_error(BURR_E_NOMEM);
+  if (!ws.reserve_table(words, set) || !ws.reserve_host(words * 8)) return set_error(BURR_E_NOMEM);
+  uint64_t* const tab = ws.tab[set];
   // the pinned staging is reused only after the stream has passed this copy
   // (the host waits for each layer's results, which follow it on the stream)
   uint64_t* h = reinterpret_cast<uint64_t*>(ws.host);
@@ -520,14 +533,14 @@ int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s) {
   memcpy(h + 4 * (J + 1), t.word_base.data(), (J + 1) * 8);
   memcpy(h + 5 * (J + 1), t.code_base.data(), (J + 1) * 8);
   memcpy(h + 6 * (J + 1), t.rbits.data(), J * 4);
-  HIP_TRY(hipMemcpyAsync(ws.tab, h, words * 8, hipMemcpyHostToDevice, s));
-  g.key_off = ws.tab;
-  g.span = ws.tab + (J + 1);
-  g.bucket_base = ws.tab + 2 * (J + 1);
-  g.range_base = ws.tab + 3 * (J + 1);
-  g.word_base = ws.tab + 4 * (J + 1);
-  g.code_base = ws.tab + 5 * (J + 1);
-  g.rbits = (const uint32_t*)(ws.tab + 6 * (J + 1));
+  HIP_TRY(hipMemcpyAsync(tab, h, words * 8, hipMemcpyHostToDevice, s));
+  g.key_off = tab;
+  g.span = tab + (J + 1);
+  g.bucket_base = tab + 2 * (J + 1);
+  g.range_base = tab + 3 * (J + 1);
+  g.word_base = tab + 4 * (J + 1);
+  g.code_base = tab + 5 * (J + 1);
+  g.rbits = (const uint32_t*)(tab + 6 * (J + 1));
   g.J = (uint32_t)J;
   g.nkeys = t.key_off.back();
   g.nbuckets = t.bucket_base.back();
@@ -590,7 +603,7 @@ struct Events {
 // into segments of kFinalSegBuckets buckets that are solved in parallel;
 // rows crossing a segment end are merged afterwards. fails[i] = 1 if member
 // list[i]'s system was inconsistent at this size (then it keeps no table).
-int final_attempt(burr_batch* b, Workspace& ws, const std::vector<uint32_t>& list,
+int final_attempt(burr_batch* b, Workspace& ws, int set, const std::vector<uint32_t>& list,
                   const std::vector<uint32_t>& attempt, const uint64_t* keys, const void* vals,
                   uint32_t vbytes, bool first_layer, std::vector<uint32_t>& fails) {
   const burr_params& p = b->p;
@@ -610,10 +623,10 @@ int final_attempt(burr_batch* b, Workspace& ws, const std::vector<uint32_t>& lis
   g.t_lo = p.t_lo;
   g.t_hi = p.t_hi;
   g.plain = 1;
-  int rc = upload_table(ws, t, g, s);
+  int rc = upload_table(ws, t, g, s, set);
   if (rc != BURR_OK) return rc;
-  if (!ws.reserve_slots(g.m) || !ws.reserve_buckets(g.nbuckets) || !ws.reserve_structs(g.J) ||
-      !ws.reserve_segments(g.nranges))
+  if (!ws.reserve_slots(g.m, set) || !ws.reserve_buckets(g.nbuckets) ||
+      !ws.reserve_structs(g.J) || !ws.reserve_segments(g.nranges))
     return set_error(BURR_E_NOMEM);
   rc = run_sort(ws, keys, vals, vbytes, first_layer, p.filter_mode != 0, mix64(~p.seed), g, s);
   if (rc != BURR_OK) return rc;
@@ -623,9 +636,9 @@ int final_attempt(burr_batch* b, Workspace& ws, const std::vector<uint32_t>& lis
   sa.rec = ws.rec;
   sa.bstart = ws.bstart;
   sa.g = g;
-  sa.rowsC = ws.rowsC;
-  sa.rowsV = ws.rowsV;
-  sa.occ = ws.occ;
+  sa.rowsC = ws.rowsC[set];
+  sa.rowsV = ws.rowsV[set];
+  sa.occ = ws.occ[set];
   sa.fail = ws.fail;
   sa.nrec = (uint32_t)(g.nkeys + g.nbuckets);
   sa.spillC = ws.spillC;
@@ -635,9 +648,9 @@ int final_attempt(burr_batch* b, Workspace& ws, const std::vector<uint32_t>& lis
   HIP_TRY(solve_layer(sa, s));
   FinalArgs fa{};
   fa.g = g;
-  fa.rowsC = ws.rowsC;
-  fa.rowsV = ws.rowsV;
-  fa.occ = ws.occ;
+  fa.rowsC = ws.rowsC[set];
+  fa.rowsV = ws.rowsV[set];
+  fa.occ = ws.occ[set];
   fa.spillC = ws.spillC;
   fa.spillV = ws.spillV;
   fa.spill_occ = ws.spill_occ;
@@ -651,7 +664,7 @@ int final_attempt(burr_batch* b, Workspace& ws, const std::vector<uint32_t>& lis
   HIP_TRY(final_boundaries(fa, s));
   uint64_t* W = (uint64_t*)b->alloc_table(t.word_base.back() * 8 + 8);
   if (!W) return set_error(BURR_E_NOMEM);
-  HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, g, W, s, ws.bnd));
+  HIP_TRY(back_substitute(ws.rowsC[set], ws.rowsV[set], g, W, s, ws.bnd));
   HIP_TRY(hipMemcpyAsync(ws.hres, ws.res, g.J * 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   fails.assign(ws.hres, ws.hres + g.J);
@@ -715,10 +728,12 @@ struct WsLease {
   ~WsLease() {
     if (!ws) return;
     if (!cached) {
+      if (ws->side) (void)hipStreamSynchronize(ws->side);
       delete ws;
       return;
     }
     (void)hipStreamSynchronize(s);  // no launch of this build may still use it
+    if (ws->side) (void)hipStreamSynchronize(ws->side);
     std::unique_lock<std::mutex> lk(g_ws_mu);
     uint64_t held = ws->bytes;
     for (Workspace* w : g_ws_free[dev]) held += w->bytes;
@@ -811,10 +826,13 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   b->arena = (uint8_t*)b->alloc(b->arena_cap);
   if (!b->arena) return set_error(BURR_E_NOMEM);
   b->table_bytes = b->arena_cap;
-  // events: [0] start, 6 per layer, then the final layer's start and end
-  Events ev(3 + 6 * (size_t)p.layers);
+  // events: [0] start, 7 per layer, then the final layer's start and end
+  Events ev(3 + 7 * (size_t)p.layers);
   if (!ev.ok) return set_error(BURR_E_DEVICE);
-  hipEvent_t* const evfin = ev.e.data() + 1 + 6 * p.layers;
+  hipEvent_t* const evfin = ev.e.data() + 1 + 7 * p.layers;
+  hipStream_t side = ws.side_stream();
+  if (!side) return set_error(BURR_E_DEVICE);
+  auto bs_end = [&](uint32_t li) { return ev.e[1 + 7 * (size_t)li + 4]; };  // layer li's back-substitution done
   if (!ws.reserve_keys(off.back()) || (!ws.diag && !ws.alloc(ws.diag, 16)))
     return set_error(BURR_E_NOMEM);
   HIP_TRY(hipMemsetAsync(ws.diag, 0, 16 * 8, s));
@@ -840,7 +858,9 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   uint32_t nlayers = 0;  // layers launched
   for (uint32_t li = 0; li < p.layers && !active.empty(); ++li) {
     LayerStore& LS = b->layers[li];
-    hipEvent_t* const el = ev.e.data() + 1 + 6 * li;  // sort, solve, solved, results, backsub, end
+    // sort, solve, solved, back-substitution start and end (side stream), results, end
+    hipEvent_t* const el = ev.e.data() + 1 + 7 * li;
+    const int set = (int)(li & 1);
     take_host(LS, active.size());
     Table t = std::move(LS.t);
     t.fill(active.size(), [&](size_t a, uint64_t* n, uint64_t* m, uint64_t* R, uint32_t* r) {
@@ -856,10 +876,16 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     g.t_hi = p.t_hi;
     g.plain = 0;
     HOST_LAP(hc, "table", li);
-    int rc = upload_table(ws, t, g, s);
+    // this table buffer and row set were last read by layer li-2's
+    // back-substitution (side stream)
+    if (li >= 2) HIP_TRY(hipStreamWaitEvent(s, bs_end(li - 2), 0));
+    int rc = upload_table(ws, t, g, s, set);
     if (rc != BURR_OK) return rc;
-    if (!ws.reserve_slots(g.m) || !ws.reserve_buckets(g.nbuckets) || !ws.reserve_structs(g.J))
+    if (!ws.reserve_slots(g.m, set) || !ws.reserve_buckets(g.nbuckets) || !ws.reserve_structs(g.J))
       return set_error(BURR_E_NOMEM);
+    LS.codes = (uint64_t*)b->alloc_table(t.code_base.back() * 8);
+    LS.W = (uint64_t*)b->alloc_table(t.word_base.back() * 8);
+    if (!LS.codes || !LS.W) return set_error(BURR_E_NOMEM);
     HOST_LAP(hc, "upload", li);
     if (p.flags & BURR_FLAG_KEEP_LAYER_KEYS) {
       LS.keys = (uint64_t*)b->alloc(g.nkeys * 8);
@@ -874,9 +900,9 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     sa.rec = ws.rec;
     sa.bstart = ws.bstart;
     sa.g = g;
-    sa.rowsC = ws.rowsC;
-    sa.rowsV = ws.rowsV;
-    sa.occ = ws.occ;
+    sa.rowsC = ws.rowsC[set];
+    sa.rowsV = ws.rowsV[set];
+    sa.occ = ws.occ[set];
     sa.code8 = ws.code8;
     sa.bump = ws.bump;
     sa.fail = ws.fail;
@@ -887,6 +913,14 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     HIP_TRY(hipEventRecord(el[1], s));
     HIP_TRY(solve_layer(sa, s));
     HIP_TRY(hipEventRecord(el[2], s));
+    // back-substitution on the side stream: the deeper layers leave most of
+    // the device idle, so it overlaps with them
+    HIP_TRY(hipStreamWaitEvent(side, el[2], 0));
+    HIP_TRY(hipEventRecord(el[3], side));
+    HIP_TRY(back_substitute(ws.rowsC[set], ws.rowsV[set], g, LS.W, side));
+    HIP_TRY(hipEventRecord(el[4], side));
+    // codes now: the next layer's insertion rewrites code8
+    HIP_TRY(pack_codes(ws.code8, g, t.code_base.back(), LS.codes, s));
 
     // per-structure bump counts (an exclusive scan of the per-bucket counts)
     // go to the host first: they are all the next layer's planning needs, so
@@ -897,18 +931,12 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     HIP_TRY(scan_exclusive(ws.bump, g.nbuckets + 1, ws.scan_tmp, s));
     HIP_TRY(struct_offsets(ws.bump, g, ws.soff, s));
     HIP_TRY(hipMemcpyAsync(ws.hres, ws.res, ws.results_words(g.J) * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipEventRecord(el[3], s));
-    LS.codes = (uint64_t*)b->alloc_table(t.code_base.back() * 8);
-    LS.W = (uint64_t*)b->alloc_table(t.word_base.back() * 8);
-    if (!LS.codes || !LS.W) return set_error(BURR_E_NOMEM);
-    HIP_TRY(back_substitute(ws.rowsC, ws.rowsV, g, LS.W, s));
-    HIP_TRY(pack_codes(ws.code8, g, t.code_base.back(), LS.codes, s));
-    HIP_TRY(hipEventRecord(el[4], s));
-    HIP_TRY(gather_bumped(ws.rec, ws.bstart, ws.bump, g.nbuckets, ws.keysA, ws.valsA, s));
     HIP_TRY(hipEventRecord(el[5], s));
+    HIP_TRY(gather_bumped(ws.rec, ws.bstart, ws.bump, g.nbuckets, ws.keysA, ws.valsA, s));
+    HIP_TRY(hipEventRecord(el[6], s));
     nlayers = li + 1;
     HOST_LAP(hc, "launch", li);
-    HIP_TRY(hipEventSynchronize(el[3]));
+    HIP_TRY(hipEventSynchronize(el[5]));
     HOST_LAP(hc, "device", li);
     const uint32_t* fails = ws.hres;
     const uint32_t* soff = ws.hres + g.J;
@@ -968,9 +996,13 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     HIP_TRY(hipMemcpyAsync(kk, cur_keys, fin_off.back() * 8, hipMemcpyDeviceToDevice, s));
     for (size_t a = 0; a < active.size(); ++a) b->members[active[a]].fin_keys = kk + fin_off[a];
   }
+  // the final layer's table and rows go to the set the last BuRR layer did
+  // not use, after the back-substitution that read it last
+  const int fset = (int)(nlayers & 1);
+  if (nlayers >= 2) HIP_TRY(hipStreamWaitEvent(s, bs_end(nlayers - 2), 0));
   if (!active.empty()) {
     std::vector<uint32_t> zero(active.size(), 0), fails;
-    int rc = final_attempt(b, ws, active, zero, cur_keys, cur_vals, cur_vbytes, first, fails);
+    int rc = final_attempt(b, ws, fset, active, zero, cur_keys, cur_vals, cur_vbytes, first, fails);
     if (rc != BURR_OK) return rc;
     // rare: a member whose final system was inconsistent retries alone with
     // larger tables (Sec. 3: the last layer grows until it succeeds)
@@ -981,23 +1013,24 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
       bool solved = false;
       for (uint32_t att = 1; att < p.final_attempts && !solved; ++att) {
         std::vector<uint32_t> one(1, active[a]), at(1, att), f1;
-        rc = final_attempt(b, ws, one, at, cur_keys + fin_off[a], v, cur_vbytes, first, f1);
+        rc = final_attempt(b, ws, fset, one, at, cur_keys + fin_off[a], v, cur_vbytes, first, f1);
         if (rc != BURR_OK) return rc;
         solved = f1[0] == 0;
       }
       if (!solved) return set_error(BURR_E_UNSOLVABLE);
     }
   }
+  if (nlayers >= 1) HIP_TRY(hipStreamWaitEvent(s, bs_end(nlayers - 1), 0));
   HIP_TRY(hipEventRecord(evfin[1], s));
   HIP_TRY(hipStreamSynchronize(s));
   HOST_LAP(hc, "final", p.layers);
   for (uint32_t li = 0; li < nlayers; ++li) {
-    const hipEvent_t* el = ev.e.data() + 1 + 6 * li;
+    const hipEvent_t* el = ev.e.data() + 1 + 7 * li;
     LayerStore& LS = b->layers[li];
     LS.ms_sort = elapsed_ms(el[0], el[1]);
     LS.ms_solve = elapsed_ms(el[1], el[2]);
     LS.ms_backsub = elapsed_ms(el[3], el[4]);
-    LS.ms_gather = elapsed_ms(el[2], el[3]) + elapsed_ms(el[4], el[5]);
+    LS.ms_gather = elapsed_ms(el[2], el[6]);
   }
   b->ms_final = elapsed_ms(evfin[0], evfin[1]);
   b->ms_total = elapsed_ms(ev.e[0], evfin[1]);
