@@ -1561,25 +1561,48 @@ hipError_t struct_offsets(const uint32_t* off, const LayerGeom& g, uint32_t* out
   return hipGetLastError();
 }
 
-__global__ void k_gather(const Rec* __restrict__ rec, const uint32_t* __restrict__ bstart,
-                         const uint32_t* __restrict__ off, uint64_t B,
-                         uint64_t* __restrict__ nk, uint32_t* __restrict__ nv) {
-  const uint64_t beta = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (beta >= B) return;
-  const uint32_t o = off[beta];
-  const uint32_t cnt = off[beta + 1] - o;
-  const uint32_t src = bstart[beta + 1] - cnt;
-  for (uint32_t j = 0; j < cnt; ++j) {
-    const Rec r = rec[src + j + beta + 1];
-    nk[o + j] = r.c;
-    nv[o + j] = meta_value(r.meta);
+// One wave per 64 consecutive buckets: the lanes take the wave's bumped
+// records in output order (consecutive outputs, so the writes coalesce and
+// a bucket's records are read as a run), each finding its record's bucket by
+// a binary search over the 64 buckets' first output positions.
+__global__ __launch_bounds__(256) void k_gather(const Rec* __restrict__ rec,
+                                                const uint32_t* __restrict__ bstart,
+                                                const uint32_t* __restrict__ off, uint64_t B,
+                                                uint64_t* __restrict__ nk,
+                                                uint32_t* __restrict__ nv) {
+  const uint64_t b0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) / 64 * 64;
+  if (b0 >= B) return;  // the whole wave
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t beta = b0 + lane;
+  const uint64_t bend = b0 + 64 < B ? b0 + 64 : B;
+  // this lane's bucket: first output position and the item of its first bumped record
+  const uint32_t o = off[beta < B ? beta : B];
+  uint32_t first = 0;
+  if (beta < B) first = bstart[beta + 1] - (off[beta + 1] - o) + (uint32_t)beta + 1;
+  const uint32_t base = off[b0], end = off[bend];
+  for (uint32_t k = base + lane; k - lane < end; k += 64) {
+    uint32_t l = 0;  // last lane whose bucket starts at or before k
+#pragma unroll
+    for (uint32_t step = 32; step >= 1; step >>= 1) {
+      const uint32_t c = l + step;
+      const uint32_t oc = (uint32_t)__shfl((int)o, (int)(c & 63u), 64);
+      if (c < 64 && oc <= k) l = c;
+    }
+    const uint32_t ol = (uint32_t)__shfl((int)o, (int)l, 64);
+    const uint32_t fl = (uint32_t)__shfl((int)first, (int)l, 64);
+    if (k < end) {
+      const Rec r = rec[fl + (k - ol)];
+      nk[k] = r.c;
+      nv[k] = meta_value(r.meta);
+    }
   }
 }
 
 hipError_t gather_bumped(const Rec* rec, const uint32_t* bstart, const uint32_t* off, uint64_t B,
                          uint64_t* next_keys, uint32_t* next_vals, hipStream_t s) {
   if (B == 0) return hipSuccess;
-  k_gather<<<(unsigned)((B + 255) / 256), 256, 0, s>>>(rec, bstart, off, B, next_keys,
+  const uint64_t waves = (B + 63) / 64;
+  k_gather<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(rec, bstart, off, B, next_keys,
                                                        next_vals);
   return hipGetLastError();
 }
