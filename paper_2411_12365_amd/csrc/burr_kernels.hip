@@ -132,11 +132,20 @@ constexpr int kL3Threads = 512;  // 8 waves: with the 73 KB block, 4 waves per S
 constexpr int kL3Per = 9;                            // records per thread held in registers
 constexpr uint32_t kL3Cap = kL3Threads * kL3Per;     // items of a sub-bin staged in LDS
 
+// Up to this many sub-bins, level 1 partitions into the sub-bins directly
+// (a 2048-key tile still writes runs of 16 or more records per sub-bin) and
+// level 2 is skipped.
+constexpr uint32_t kSingleLevelSubs = 128;
+
 SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets) {
   SortPlan p{};
   p.nsub = (uint32_t)((nbuckets + kSubBuckets - 1) / kSubBuckets);
   uint32_t nb = 1;
-  while ((uint64_t)nb * nb < p.nsub) ++nb;  // about sqrt(nsub) bins of about sqrt(nsub) sub-bins
+  if (p.nsub <= kSingleLevelSubs)
+    nb = p.nsub;  // one sub-bin per bin
+  else
+    while ((uint64_t)nb * nb < p.nsub) ++nb;  // about sqrt(nsub) bins of about sqrt(nsub) sub-bins
+  if (nb < 1) nb = 1;
   if (nb > kMaxDigits) nb = kMaxDigits;
   p.S = (p.nsub + nb - 1) / nb;
   p.nb1 = (p.nsub + p.S - 1) / p.S;
@@ -584,6 +593,13 @@ hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_p2_plan<<<1, kPartThreads, 0, s>>>(a.counts1, sp, n, a.binlo, a.nch, a.cbase);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  (void)hipFuncSetAttribute((const void*)k_p3_sort, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(kL3Cap * sizeof(uint4)));
+  if (sp.S == 1) {  // the bins are the sub-bins: level 3 reads level 1's output
+    k_p3_sort<<<sp.nsub, kL3Threads, kL3Cap * sizeof(uint4), s>>>(a.p1, a.g, sp, a.binlo,
+                                                                  a.out_rec, a.bstart);
+    return hipGetLastError();
+  }
   const size_t n2 = (size_t)sp.U2 * sp.S;
   if ((e = hipMemsetAsync(a.counts2, 0, (n2 + 1) * 4, s)) != hipSuccess) return e;
   k_p2_hist<<<sp.U2, kPart2Threads, (size_t)sp.S * 4, s>>>(a.p1, sp, a.binlo, a.nch, a.cbase,
@@ -596,8 +612,6 @@ hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
   k_p2_starts<<<(sp.nsub + 256) / 256, 256, 0, s>>>(sp, n, a.binlo, a.nch, a.cbase, a.counts2,
                                                      a.sstart);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  (void)hipFuncSetAttribute((const void*)k_p3_sort, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(kL3Cap * sizeof(uint4)));
   k_p3_sort<<<sp.nsub, kL3Threads, kL3Cap * sizeof(uint4), s>>>(a.p2, a.g, sp, a.sstart,
                                                                 a.out_rec, a.bstart);
   return hipGetLastError();
