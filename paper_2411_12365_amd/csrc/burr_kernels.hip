@@ -1252,8 +1252,8 @@ constexpr uint32_t kMergeWin = 1024;  // slots of the right group staged in LDS
 // 0). Rows whose walk leaves the window are finished one by one in global
 // memory afterwards.
 __global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
-  __shared__ uint64_t wc[kMergeWin];
-  __shared__ uint32_t wv[kMergeWin];
+  __shared__ uint64_t wc[kMergeWin + 1];  // + a zero slot for walks past the window
+  __shared__ uint32_t wv[kMergeWin + 1];
   __shared__ uint64_t oc_[64];
   __shared__ uint32_t ov_[64], oi_[64];
   const LayerGeom g = a.g;
@@ -1291,7 +1291,11 @@ __global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
       val = a.spillV[lastR * 64 + (slot - endR)];
     }
     wc[64 * blk + lane] = occd ? row : 0ull;
-    wv[64 * blk + lane] = val;
+    wv[64 * blk + lane] = occd ? val : 0u;  // empty slots: row 0, value 0
+  }
+  if (lane == 0) {
+    wc[kMergeWin] = 0;
+    wv[kMergeWin] = 0;
   }
   __syncthreads();
   // parallel phase
@@ -1307,41 +1311,37 @@ __global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
       internal = true;
       break;
     }
-    bool at_empty = false, conflict = false, corrupt = false;
+    // unmasked steps as in the insertion kernel; a walk that leaves the
+    // window reads the zero slot past it from then on, which holds it in place
+    bool conflict = false;
+    uint64_t row = 0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if (active && !at_empty && i >= win) {  // leaves the window: finish later
-        over = true;
-        active = false;
-      }
-      const uint32_t ii = i < win ? i : 0u;
-      const uint64_t row = wc[ii];
+      const uint32_t ii = i < win ? i : kMergeWin;
+      row = wc[ii];
       const uint32_t rv = wv[ii];
-      const bool go = active && !at_empty;
-      at_empty = at_empty || (go && row == 0);
-      const bool step = go && row != 0;
       const uint64_t cx = c ^ row;
       const uint32_t vx = v ^ rv;
-      const bool zero = step && cx == 0;
-      corrupt = corrupt || (step && !zero && (cx & 1ull));  // stored rows have their leading bit
-      conflict = conflict || (zero && vx != 0);
-      active = active && !zero && !(step && (cx & 1ull));
-      const bool adv = step && !zero && !(cx & 1ull);
+      const bool nz = cx != 0;  // else redundant (vx = 0) or inconsistent
+      conflict = conflict || (active && !nz && vx != 0);
+      active = active && nz;
       const uint32_t j = (uint32_t)__builtin_ctzg(cx, 64);
-      c = adv ? (cx >> j) : c;
-      v = step ? vx : v;
-      i = adv ? i + j : i;
+      c = cx >> (j & 63u);
+      v = vx;
+      i += j;
     }
-    if (at_empty && active) {
+    if (active && i >= win) {  // left the window: finish later
+      over = true;
+      active = false;
+    } else if (active && row == 0) {
       const uint64_t old = atomicCAS((unsigned long long*)&wc[i], 0ull, (unsigned long long)c);
       if (old == 0) {
         wv[i] = v;
         active = false;
       }
     }
-    if (__any(conflict || corrupt)) {
+    if (__any(conflict)) {
       bad = true;
-      internal = internal || __any(corrupt);
       break;
     }
   }
@@ -1493,7 +1493,10 @@ __global__ __launch_bounds__(64) void k_final_partial(FinalArgs a) {
 // it is one AND and a parity per column. The segments' X and z0 words do not
 // depend on the scan, so they are loaded kScanChunk segments at a time into
 // LDS (the loads overlap) and the sequential part reads LDS only.
+// RC >= r columns, a compile-time count so that the column ballots of one
+// segment are independent instructions (columns >= r are zero).
 constexpr uint32_t kScanChunk = 32;
+template <uint32_t RC>
 __global__ __launch_bounds__(64) void k_final_scan(FinalArgs a) {
   __shared__ uint64_t sx[kScanChunk][64];
   __shared__ uint32_t sz[kScanChunk][64];
@@ -1501,7 +1504,6 @@ __global__ __launch_bounds__(64) void k_final_scan(FinalArgs a) {
   const LayerGeom g = a.g;
   const uint32_t j = blockIdx.x;
   const uint64_t first = g.range_base[j], last = g.range_base[j + 1];
-  const uint32_t r = g.rbits[j];
   uint32_t b = 0;  // nothing lies past the structure's last segment
   for (uint64_t hi = last; hi > first;) {
     const uint64_t lo = hi - first > kScanChunk ? hi - kScanChunk : first;
@@ -1518,9 +1520,11 @@ __global__ __launch_bounds__(64) void k_final_scan(FinalArgs a) {
       a.bnd[p * 64 + t] = b;
       const uint64_t X = sx[p - lo][t];
       uint32_t nb = sz[p - lo][t];
-      for (uint32_t c = 0; c < r; ++c) {
+#pragma unroll
+      for (uint32_t c = 0; c < RC; ++c) {
         const uint64_t col = __ballot(((b >> c) & 1u) != 0) & 0x7fffffffffffffffull;
-        nb ^= (uint32_t)(__popcll(X & col) & 1) << c;
+        const uint32_t x = ((uint32_t)X & (uint32_t)col) ^ ((uint32_t)(X >> 32) & (uint32_t)(col >> 32));
+        nb ^= ((uint32_t)__popc(x) & 1u) << c;
       }
       b = t < 63 ? nb : 0u;
     }
@@ -1534,7 +1538,12 @@ hipError_t final_boundaries(const FinalArgs& a, hipStream_t s) {
   k_final_partial<<<(unsigned)P, 64, 0, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_final_scan<<<a.g.J, 64, 0, s>>>(a);
+  if (a.g.r <= 8)
+    k_final_scan<8><<<a.g.J, 64, 0, s>>>(a);
+  else if (a.g.r <= 16)
+    k_final_scan<16><<<a.g.J, 64, 0, s>>>(a);
+  else
+    k_final_scan<32><<<a.g.J, 64, 0, s>>>(a);
   return hipGetLastError();
 }
 

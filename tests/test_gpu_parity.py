@@ -113,3 +113,58 @@ def test_ten_million_keys_many_ranges():
     keys = W.keys(10_000_000, 2)
     vals = W.values(10_000_000, 8, 1002)
     _compare(keys, vals, 8, dict(ranges=1 << 16), "10M")
+
+
+def _low_word_pair(m, seed, tries=1 << 24, chunk=1 << 22):
+    """Two keys that both start at slot 0 of a layer-0 table of m slots and
+    whose coefficient rows agree in their low 32 bits but not in their high
+    ones. Candidates are screened with a numpy copy of the hash; the oracle's
+    hash confirms the pair."""
+    def mix(x):
+        x = x ^ (x >> np.uint64(33))
+        x = x * np.uint64(0xFF51AFD7ED558CCD)
+        x = x ^ (x >> np.uint64(33))
+        x = x * np.uint64(0xC4CEB9FE1A85EC53)
+        return x ^ (x >> np.uint64(33))
+
+    salt_s = np.uint64(oracle.fmix64(seed ^ 1))
+    salt_c = np.uint64(oracle.fmix64(seed ^ 2))
+    span = m - 63
+    first = (2**64 - 1) // span  # start 0 <=> hash * span < 2^64
+    rng = np.random.default_rng(2411)
+    cand = []
+    with np.errstate(over="ignore"):
+        for _ in range(tries // chunk):
+            k = rng.integers(0, 2**64 - 1, size=chunk, dtype=np.uint64, endpoint=True)
+            k = k[mix(k ^ salt_s) <= np.uint64(first)]
+            cand.append(k)
+        k = np.concatenate(cand)
+        low = (mix(k ^ salt_c) | np.uint64(1)) & np.uint64(0xFFFFFFFF)
+    order = np.argsort(low, kind="stable")
+    ls, ks = low[order], k[order]
+    for i in np.nonzero(ls[1:] == ls[:-1])[0]:
+        a, b = int(ks[i]), int(ks[i + 1])
+        (sa, ra), (sb, rb) = oracle.hash_key(a, 0, m, seed), oracle.hash_key(b, 0, m, seed)
+        if sa == sb == 0 and (ra ^ rb) & 0xFFFFFFFF == 0 and ra != rb:
+            return a, b
+    raise AssertionError("no colliding pair among the candidates")
+
+
+def test_low_word_collision_takes_the_exact_pass():
+    # Two keys start at slot 0 of bucket 0 (of 2) with rows equal in their
+    # low 32 bits: one claims slot 0, the other's XOR with it has a zero low
+    # word and a nonzero high word, which stops the fast pass; the exact pass
+    # must then give the oracle's structure. The other 98 keys start later,
+    # so slot 0 is empty when the pair arrives.
+    n = 100
+    m = 128  # 64 * ceil(0.97 * 100 / 64): two buckets, one range
+    a, b = _low_word_pair(m, 0)
+    rng = np.random.default_rng(7)
+    others = []
+    while len(others) < n - 2:
+        k = int(rng.integers(0, 2**63))
+        if oracle.hash_key(k, 0, m, 0)[0] != 0 and k not in (a, b):
+            others.append(k)
+    keys = np.array([a, b] + others, dtype=np.uint64)
+    vals = W.values(n, 8, 31)
+    _compare(keys, vals, 8, dict(ranges=1), "low-word pair")
