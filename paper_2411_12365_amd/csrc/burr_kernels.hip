@@ -1447,8 +1447,8 @@ hipError_t final_merge(const FinalArgs& a, uint64_t max_segments, hipStream_t s)
 // X[end+k] is the unit word e_k), lane c < r carries column c of z0; the
 // first 63 slots' words are assembled with ballots.
 __global__ __launch_bounds__(64) void k_final_partial(FinalArgs a) {
-  __shared__ uint64_t sc[64];
-  __shared__ uint32_t sv[64];
+  __shared__ uint64_t sc[2][64];  // rows shifted right by 1
+  __shared__ uint32_t sv[2][64];
   const LayerGeom g = a.g;
   const uint32_t lane = threadIdx.x;
   const uint64_t p = blockIdx.x;
@@ -1459,21 +1459,37 @@ __global__ __launch_bounds__(64) void k_final_partial(FinalArgs a) {
   const uint64_t zmask = r >= 32 ? 0xffffffffull : ((1ull << r) - 1);
   uint64_t wx = lane < 63 ? (1ull << lane) : 0ull;
   uint64_t wz = 0;
-  for (uint64_t k = end / 64; k-- > start / 64;) {
-    sc[lane] = a.rowsC[k * 64 + lane];
-    sv[lane] = a.rowsV[k * 64 + lane];
-    const uint64_t oc = a.occ[k];
+  // free slots hold row 0 and value 0, so they give 0 without a test; the
+  // next block's row and value load while this one is processed
+  const uint64_t kb = start / 64;
+  uint64_t k = end / 64;
+  uint64_t pc = 0;
+  uint32_t pv = 0;
+  if (k > kb) {
+    pc = a.rowsC[(k - 1) * 64 + lane];
+    pv = a.rowsV[(k - 1) * 64 + lane];
+  }
+  for (uint32_t buf = 0; k-- > kb; buf ^= 1u) {
+    sc[buf][lane] = pc >> 1;
+    sv[buf][lane] = pv;
     __syncthreads();
+    if (k > kb) {
+      pc = a.rowsC[(k - 1) * 64 + lane];
+      pv = a.rowsV[(k - 1) * 64 + lane];
+    }
+    const bool head = k * 64 - start < 63;  // the block holds some of the first 63 slots
+#pragma unroll 8
     for (int tt = 63; tt >= 0; --tt) {
-      const uint64_t C = sc[tt] >> 1;
-      const bool occd = (oc >> tt) & 1ull;
-      const uint64_t xb = occd ? (uint64_t)(__popcll(C & wx) & 1) : 0ull;
-      const uint32_t vbit = lane < 32 ? (sv[tt] >> lane) : 0u;
-      const uint64_t zb = occd ? (uint64_t)((vbit ^ (uint32_t)__popcll(C & wz)) & 1u) : 0ull;
+      const uint64_t C = sc[buf][tt];
+      const uint32_t vbit = lane < 32 ? (sv[buf][tt] >> lane) : 0u;
+      const uint32_t x1 = ((uint32_t)C & (uint32_t)wx) ^ ((uint32_t)(C >> 32) & (uint32_t)(wx >> 32));
+      const uint32_t x2 = ((uint32_t)C & (uint32_t)wz) ^ ((uint32_t)(C >> 32) & (uint32_t)(wz >> 32));
+      const uint64_t xb = (uint32_t)__popc(x1) & 1u;
+      const uint64_t zb = ((uint32_t)__popc(x2) + vbit) & 1u;
       wx = (wx << 1) | xb;
       wz = (wz << 1) | zb;
       const uint64_t i = k * 64 + (uint64_t)tt;
-      if (i - start < 63) {
+      if (head && i - start < 63) {
         const uint64_t X = __ballot(xb != 0) & 0x7fffffffffffffffull;
         const uint64_t Z = __ballot(zb != 0) & zmask;
         if (lane == 0) {
@@ -1482,7 +1498,6 @@ __global__ __launch_bounds__(64) void k_final_partial(FinalArgs a) {
         }
       }
     }
-    __syncthreads();
   }
 }
 
