@@ -149,7 +149,7 @@ SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets) {
   if (nb > kMaxDigits) nb = kMaxDigits;
   p.S = (p.nsub + nb - 1) / nb;
   p.nb1 = (p.nsub + p.S - 1) / p.S;
-  uint64_t g = (nkeys + 4 * kTile - 1) / (4 * kTile);  // at least 4 tiles per workgroup
+  uint64_t g = (nkeys + kTile - 1) / kTile;  // up to one workgroup per tile
   if (g > 2048) g = 2048;
   if (g < 1) g = 1;
   p.G1 = (uint32_t)g;
