@@ -685,7 +685,7 @@ struct Stage {
 template <int LANES>
 struct WaveRing {
   uint64_t c[kRing];
-  uint32_t v[kRing];
+  uint32_t v[kRing + 64];  // + one spare word per lane (claims that lose write there)
   uint4 stage[Stage<LANES>::items];
 };
 // row and value of the slot at byte offset off = 8 * slot
@@ -701,9 +701,12 @@ __device__ inline bool ring_claim(Ring& R, uint32_t off, uint64_t c, uint32_t v)
   const uint64_t old = atomicCAS(
       reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(R.c) + off), 0ull,
       (unsigned long long)c);
-  if (old != 0) return false;
-  *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(R.v) + (off >> 1)) = v;
-  return true;
+  const bool won = old == 0;
+  // the value goes to the slot if the row did, else to this lane's spare word
+  // (a select instead of a branch inside the claim)
+  const uint32_t voff = won ? (off >> 1) : (uint32_t)((kRing + (threadIdx.x & 63u)) * 4u);
+  *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(R.v) + voff) = v;
+  return won;
 }
 template <class Ring>
 __device__ inline void ring_read(const Ring& R, uint32_t i, uint64_t& row, uint32_t& val) {
