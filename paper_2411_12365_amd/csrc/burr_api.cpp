@@ -830,8 +830,14 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   Events ev(3 + 7 * (size_t)p.layers);
   if (!ev.ok) return set_error(BURR_E_DEVICE);
   hipEvent_t* const evfin = ev.e.data() + 1 + 7 * p.layers;
-  hipStream_t side = ws.side_stream();
-  if (!side) return set_error(BURR_E_DEVICE);
+  // back-substitution on the workspace's side stream when the workspace is
+  // kept between builds; a per-build workspace (server, caller allocator)
+  // keeps it on the build's stream rather than create a stream per build
+  hipStream_t side = s;
+  if (!ws.al) {
+    side = ws.side_stream();
+    if (!side) return set_error(BURR_E_DEVICE);
+  }
   auto bs_end = [&](uint32_t li) { return ev.e[1 + 7 * (size_t)li + 4]; };  // layer li's back-substitution done
   if (!ws.reserve_keys(off.back()) || (!ws.diag && !ws.alloc(ws.diag, 16)))
     return set_error(BURR_E_NOMEM);
