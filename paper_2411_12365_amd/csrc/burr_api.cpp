@@ -357,6 +357,7 @@ struct Workspace {
   uint64_t* occ[2] = {nullptr, nullptr};
   uint64_t cap_m[2] = {0, 0};
   hipStream_t side = nullptr;  // back-substitution (default priority, non-blocking)
+  std::vector<hipEvent_t> evs;  // a build's timing and ordering events, kept for the next
   uint8_t* code8 = nullptr;
   uint32_t *bump = nullptr, *bstart = nullptr, *scan_tmp = nullptr;
   uint32_t* fail = nullptr;  // per structure
@@ -378,6 +379,16 @@ struct Workspace {
     if (host) (void)hipHostFree(host);
     if (hres) (void)hipHostFree(hres);
     if (side) (void)hipStreamDestroy(side);
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+  }
+  // at least n events (created once per workspace; a build records all it uses)
+  hipEvent_t* events(size_t n) {
+    while (evs.size() < n) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      evs.push_back(e);
+    }
+    return evs.data();
   }
   hipStream_t side_stream() {
     if (!side && hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess)
@@ -585,18 +596,6 @@ double elapsed_ms(hipEvent_t a, hipEvent_t b) {
   if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0;
   return ms;
 }
-
-struct Events {
-  std::vector<hipEvent_t> e;
-  bool ok = true;
-  explicit Events(size_t n = 6) : e(n, nullptr) {
-    for (auto& x : e) ok = hipEventCreate(&x) == hipSuccess && ok;
-  }
-  ~Events() {
-    for (auto& x : e)
-      if (x) (void)hipEventDestroy(x);
-  }
-};
 
 // Final plain layer of the listed members at one attempt index each. Their
 // final keys lie contiguously at `keys`, in list order. The table is cut
@@ -827,9 +826,9 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   if (!b->arena) return set_error(BURR_E_NOMEM);
   b->table_bytes = b->arena_cap;
   // events: [0] start, 7 per layer, then the final layer's start and end
-  Events ev(3 + 7 * (size_t)p.layers);
-  if (!ev.ok) return set_error(BURR_E_DEVICE);
-  hipEvent_t* const evfin = ev.e.data() + 1 + 7 * p.layers;
+  hipEvent_t* const ev = ws.events(3 + 7 * (size_t)p.layers);
+  if (!ev) return set_error(BURR_E_DEVICE);
+  hipEvent_t* const evfin = ev + 1 + 7 * p.layers;
   // back-substitution on the workspace's side stream when the workspace is
   // kept between builds; a per-build workspace (server, caller allocator)
   // keeps it on the build's stream rather than create a stream per build
@@ -838,11 +837,11 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     side = ws.side_stream();
     if (!side) return set_error(BURR_E_DEVICE);
   }
-  auto bs_end = [&](uint32_t li) { return ev.e[1 + 7 * (size_t)li + 4]; };  // layer li's back-substitution done
+  auto bs_end = [&](uint32_t li) { return ev[1 + 7 * (size_t)li + 4]; };  // layer li's back-substitution done
   if (!ws.reserve_keys(off.back()) || (!ws.diag && !ws.alloc(ws.diag, 16)))
     return set_error(BURR_E_NOMEM);
   HIP_TRY(hipMemsetAsync(ws.diag, 0, 16 * 8, s));
-  HIP_TRY(hipEventRecord(ev.e[0], s));
+  HIP_TRY(hipEventRecord(ev[0], s));
 
   // members with keys in the current layer, in key order, and their key counts
   std::vector<uint32_t> active;
@@ -865,7 +864,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   for (uint32_t li = 0; li < p.layers && !active.empty(); ++li) {
     LayerStore& LS = b->layers[li];
     // sort, solve, solved, back-substitution start and end (side stream), results, end
-    hipEvent_t* const el = ev.e.data() + 1 + 7 * li;
+    hipEvent_t* const el = ev + 1 + 7 * li;
     const int set = (int)(li & 1);
     take_host(LS, active.size());
     Table t = std::move(LS.t);
@@ -1031,7 +1030,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   HIP_TRY(hipStreamSynchronize(s));
   HOST_LAP(hc, "final", p.layers);
   for (uint32_t li = 0; li < nlayers; ++li) {
-    const hipEvent_t* el = ev.e.data() + 1 + 7 * li;
+    const hipEvent_t* el = ev + 1 + 7 * li;
     LayerStore& LS = b->layers[li];
     LS.ms_sort = elapsed_ms(el[0], el[1]);
     LS.ms_solve = elapsed_ms(el[1], el[2]);
@@ -1039,7 +1038,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     LS.ms_gather = elapsed_ms(el[2], el[6]);
   }
   b->ms_final = elapsed_ms(evfin[0], evfin[1]);
-  b->ms_total = elapsed_ms(ev.e[0], evfin[1]);
+  b->ms_total = elapsed_ms(ev[0], evfin[1]);
   return BURR_OK;
 }
 
