@@ -1123,6 +1123,9 @@ QueryPlan make_plan(const burr_batch* b, const Member& mb) {
   f.plain = 1;
   f.empty = mb.fin.m == 0;
   plan.nlayers = l + 1;
+  plan.aligned = mb.r % 2 == 0;
+  for (uint32_t k = 0; k < plan.nlayers; ++k)
+    if (reinterpret_cast<uintptr_t>(plan.layer[k].W) % 16 != 0) plan.aligned = 0;
   return plan;
 }
 

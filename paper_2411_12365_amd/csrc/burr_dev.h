@@ -114,6 +114,7 @@ struct QueryPlan {
   QueryLayer layer[kMaxQueryLayers];
   uint32_t nlayers; // BuRR layers + 1 (final)
   uint32_t r;
+  uint32_t aligned; // every layer's W is 16-byte aligned and r is even: 16-byte loads
 };
 
 }  // namespace burr

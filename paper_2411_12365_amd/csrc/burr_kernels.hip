@@ -1728,13 +1728,30 @@ hipError_t fill_stream(uint64_t* keys, void* vals, uint32_t vb, uint64_t n, uint
 // ---------------------------------------------------------------------------
 // r-bit result of one layer: parity of c AND the 64-slot window at s, per
 // column, from the column-interleaved words of blocks s/64 and s/64 + 1
-template <int R>
+// AL: w is 16-byte aligned (R even), so the words load two at a time
+template <int R, bool AL>
 __device__ inline uint32_t window_parity(const uint64_t* w, uint32_t sh, uint64_t c) {
   uint64_t lo[R], hi[R];
+  if constexpr (AL) {
+    const uint4* p = reinterpret_cast<const uint4*>(w);
 #pragma unroll
-  for (int col = 0; col < R; ++col) {
-    lo[col] = w[col];
-    hi[col] = sh ? w[R + col] : 0ull;
+    for (int k = 0; k < R / 2; ++k) {
+      const uint4 a = p[k];
+      lo[2 * k] = (uint64_t)a.x | ((uint64_t)a.y << 32);
+      lo[2 * k + 1] = (uint64_t)a.z | ((uint64_t)a.w << 32);
+    }
+#pragma unroll
+    for (int k = 0; k < R / 2; ++k) {
+      const uint4 a = sh ? p[R / 2 + k] : make_uint4(0, 0, 0, 0);
+      hi[2 * k] = (uint64_t)a.x | ((uint64_t)a.y << 32);
+      hi[2 * k + 1] = (uint64_t)a.z | ((uint64_t)a.w << 32);
+    }
+  } else {
+#pragma unroll
+    for (int col = 0; col < R; ++col) {
+      lo[col] = w[col];
+      hi[col] = sh ? w[R + col] : 0ull;
+    }
   }
   uint32_t res = 0;
 #pragma unroll
@@ -1759,7 +1776,7 @@ __device__ inline uint32_t window_parity_any(const uint64_t* w, uint32_t r, uint
 // words of the key's window are independent loads (both follow from the start
 // slot), so they are issued together; the threshold then decides whether
 // the layer answers.
-template <typename OT, int RC>
+template <typename OT, int RC, bool AL>
 __global__ __launch_bounds__(256) void k_query(QueryPlan plan, const uint64_t* __restrict__ keys,
                                                uint64_t n, OT* __restrict__ out,
                                                uint32_t contains, uint64_t fp_salt) {
@@ -1779,7 +1796,7 @@ __global__ __launch_bounds__(256) void k_query(QueryPlan plan, const uint64_t* _
     const uint64_t cw = L.plain ? 0ull : L.codes[beta >> 5];
     uint32_t val;
     if constexpr (RC > 0)
-      val = window_parity<RC>(w, sh, c);
+      val = window_parity<RC, AL>(w, sh, c);
     else
       val = window_parity_any(w, r, sh, c);
     if (!L.plain) {
@@ -1800,19 +1817,25 @@ hipError_t query(const QueryPlan& plan, const uint64_t* keys, uint64_t n, void* 
                  uint32_t out_bytes, uint32_t contains, uint64_t fp_salt, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n + 255) / 256);
-  if (out_bytes == 1 && plan.r == 8)
-    k_query<uint8_t, 8><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
+  const bool al = plan.aligned != 0;
+  if (out_bytes == 1 && plan.r == 8 && al)
+    k_query<uint8_t, 8, true><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
+  else if (out_bytes == 1 && plan.r == 8)
+    k_query<uint8_t, 8, false><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
   else if (out_bytes == 1 && plan.r == 1)
-    k_query<uint8_t, 1><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
+    k_query<uint8_t, 1, false><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
   else if (out_bytes == 1)
-    k_query<uint8_t, 0><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
+    k_query<uint8_t, 0, false><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
+  else if (out_bytes == 2 && plan.r == 16 && al)
+    k_query<uint16_t, 16, true><<<blocks, 256, 0, s>>>(plan, keys, n, (uint16_t*)out, contains,
+                                                       fp_salt);
   else if (out_bytes == 2 && plan.r == 16)
-    k_query<uint16_t, 16><<<blocks, 256, 0, s>>>(plan, keys, n, (uint16_t*)out, contains,
-                                                 fp_salt);
+    k_query<uint16_t, 16, false><<<blocks, 256, 0, s>>>(plan, keys, n, (uint16_t*)out, contains,
+                                                        fp_salt);
   else if (out_bytes == 2)
-    k_query<uint16_t, 0><<<blocks, 256, 0, s>>>(plan, keys, n, (uint16_t*)out, contains, fp_salt);
+    k_query<uint16_t, 0, false><<<blocks, 256, 0, s>>>(plan, keys, n, (uint16_t*)out, contains, fp_salt);
   else
-    k_query<uint32_t, 0><<<blocks, 256, 0, s>>>(plan, keys, n, (uint32_t*)out, contains, fp_salt);
+    k_query<uint32_t, 0, false><<<blocks, 256, 0, s>>>(plan, keys, n, (uint32_t*)out, contains, fp_salt);
   return hipGetLastError();
 }
 
