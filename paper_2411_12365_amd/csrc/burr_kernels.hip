@@ -1106,9 +1106,10 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
 }
 
 // Lanes per range. 64: one range per wave (default). 32 (-DBURR_SOLVE_LANES=32):
-// two ranges per wave; same results, measured no faster at 100M keys (the
-// per-group control moves from scalar to vector registers and occupancy
-// drops from 7 to 5 waves per SIMD) and slower on small layers.
+// two ranges per wave; same results, measured slower at 100M keys (3.30
+// against 2.60 ms: the per-group control moves from scalar to vector
+// registers and occupancy drops from 8 to 5 waves per SIMD) and on small
+// layers.
 #ifndef BURR_SOLVE_LANES
 #define BURR_SOLVE_LANES 64
 #endif
