@@ -56,23 +56,42 @@ constexpr int kScanThreads = 256;
 constexpr int kScanPer = 8;
 constexpr size_t kScanTile = (size_t)kScanThreads * kScanPer;
 
+// VEC: data is 16-byte aligned, so a thread's 8 words move as two 16-byte
+// accesses (one per 4 words) wherever all 8 lie inside [0, n)
+template <bool VEC>
 __global__ __launch_bounds__(kScanThreads) void k_scan_tile(uint32_t* data, size_t n,
                                                              uint32_t* sums) {
   __shared__ uint32_t wsum[kScanThreads / 64];
   __shared__ uint32_t total;
   const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanPer;
+  const bool whole = VEC && base + kScanPer <= n;
   uint32_t v[kScanPer];
   uint32_t tot = 0;
+  if (whole) {
+    const uint4 a = *reinterpret_cast<const uint4*>(data + base);
+    const uint4 b = *reinterpret_cast<const uint4*>(data + base + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    v[k] = (base + k < n) ? data[base + k] : 0u;
-    tot += v[k];
+    for (int k = 0; k < kScanPer; ++k) v[k] = (base + k < n) ? data[base + k] : 0u;
   }
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) tot += v[k];
   uint32_t run = block_exclusive_scan<kScanThreads>(tot, wsum, &total);
+  uint32_t o[kScanPer];
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
-    if (base + k < n) data[base + k] = run;
+    o[k] = run;
     run += v[k];
+  }
+  if (whole) {
+    *reinterpret_cast<uint4*>(data + base) = make_uint4(o[0], o[1], o[2], o[3]);
+    *reinterpret_cast<uint4*>(data + base + 4) = make_uint4(o[4], o[5], o[6], o[7]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+      if (base + k < n) data[base + k] = o[k];
   }
   if (threadIdx.x == 0 && sums) sums[blockIdx.x] = total;
 }
@@ -97,11 +116,18 @@ size_t scan_tmp_words(size_t n) {
 hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s) {
   if (n == 0) return hipSuccess;
   size_t tiles = (n + kScanTile - 1) / kScanTile;
+  const bool vec = reinterpret_cast<uintptr_t>(data) % 16 == 0;
   if (tiles == 1) {
-    k_scan_tile<<<1, kScanThreads, 0, s>>>(data, n, nullptr);
+    if (vec)
+      k_scan_tile<true><<<1, kScanThreads, 0, s>>>(data, n, nullptr);
+    else
+      k_scan_tile<false><<<1, kScanThreads, 0, s>>>(data, n, nullptr);
     return hipGetLastError();
   }
-  k_scan_tile<<<(unsigned)tiles, kScanThreads, 0, s>>>(data, n, tmp);
+  if (vec)
+    k_scan_tile<true><<<(unsigned)tiles, kScanThreads, 0, s>>>(data, n, tmp);
+  else
+    k_scan_tile<false><<<(unsigned)tiles, kScanThreads, 0, s>>>(data, n, tmp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = scan_exclusive(tmp, tiles, tmp + tiles, s);
