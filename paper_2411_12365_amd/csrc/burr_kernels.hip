@@ -990,7 +990,7 @@ __device__ inline void clear_half(WaveRing<LANES>& R, const Grp<LANES>& G, uint3
 }
 
 // 8 waves per SIMD: the kernel then fits 64 VGPRs (no spills), and the
-// ring and stage of 32 waves (3.5 KB each) fit a CU's LDS.
+// ring and stage of 32 waves (3.75 KB each) fit a CU's LDS.
 template <int LANES>
 __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
   constexpr uint32_t NG = 64 / LANES;
