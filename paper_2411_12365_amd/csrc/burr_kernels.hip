@@ -247,10 +247,24 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_hist(const uint64_t* __rest
   const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
   const uint64_t bin_slots = (uint64_t)sp.S * kSubSlots;
   KeyWalk w(g, lo + threadIdx.x);
-  for (uint64_t i = lo + threadIdx.x; i < hi; i += kPartThreads) {
-    w.advance(g, i);
-    const uint64_t slot = 64 * w.bb + start_of(keys[i], g.salt_s, w.span);
-    atomicAdd(&hist[(uint32_t)(slot / bin_slots)], 1u);
+  for (uint64_t t0 = lo; t0 < hi; t0 += kTile) {
+    // all of a thread's loads are issued before the first is used (past
+    // the end, the last key is read again and not counted)
+    uint64_t kk[kPartPer];
+#pragma unroll
+    for (int k = 0; k < kPartPer; ++k) {
+      const uint64_t i = t0 + threadIdx.x + (uint64_t)k * kPartThreads;
+      kk[k] = keys[i < hi ? i : hi - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < kPartPer; ++k) {
+      const uint64_t i = t0 + threadIdx.x + (uint64_t)k * kPartThreads;
+      if (i < hi) {
+        w.advance(g, i);
+        const uint64_t slot = 64 * w.bb + start_of(kk[k], g.salt_s, w.span);
+        atomicAdd(&hist[(uint32_t)(slot / bin_slots)], 1u);
+      }
+    }
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < sp.nb1; i += kPartThreads)
@@ -327,20 +341,31 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_scatter(
   for (uint64_t t0 = lo; t0 < hi; t0 += kTile) {
     uint4 rec[kPartPer];
     uint32_t dig[kPartPer], rank[kPartPer];
+    // all of a thread's loads are issued before the first is used (past
+    // the end, the last key is read again and not used)
+    uint64_t kk[kPartPer];
+    uint32_t vv[kPartPer];
+#pragma unroll
+    for (int k = 0; k < kPartPer; ++k) {
+      const uint64_t i = t0 + threadIdx.x + (uint64_t)k * kPartThreads;
+      const uint64_t ic = i < hi ? i : hi - 1;
+      kk[k] = keys[ic];
+      vv[k] = filter && mask_values ? 0u : (uint32_t)vals[ic];
+    }
 #pragma unroll
     for (int k = 0; k < kPartPer; ++k) {
       const uint64_t i = t0 + threadIdx.x + (uint64_t)k * kPartThreads;
       dig[k] = kNoDigit;
       if (i < hi) {
         w.advance(g, i);
-        const uint64_t key = keys[i];
+        const uint64_t key = kk[k];
         uint32_t v;
         if (filter && mask_values)
           v = (uint32_t)(mix64(key ^ fp_salt) >> (64 - w.r));
         else if (mask_values)
-          v = (uint32_t)vals[i] & (w.r >= 32 ? 0xffffffffu : ((1u << w.r) - 1u));
+          v = vv[k] & (w.r >= 32 ? 0xffffffffu : ((1u << w.r) - 1u));
         else
-          v = (uint32_t)vals[i];
+          v = vv[k];
         const uint64_t slot = 64 * w.bb + start_of(key, g.salt_s, w.span);
         const uint32_t d = (uint32_t)(slot / bin_slots);
         rec[k] = make_uint4((uint32_t)key, (uint32_t)(key >> 32), v,
@@ -412,8 +437,18 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_hist(const uint4* __restri
   if (!chunk2_of(blockIdx.x, sp, binlo, nch, cbase, ch)) return;
   for (uint32_t i = threadIdx.x; i < sp.S; i += kPart2Threads) hist[i] = 0;
   __syncthreads();
-  for (uint32_t i = ch.lo + threadIdx.x; i < ch.hi; i += kPart2Threads)
-    atomicAdd(&hist[in[i].w / kSubSlots], 1u);
+  constexpr uint32_t T2 = kPart2Threads * kPartPer;
+  for (uint32_t t0 = ch.lo; t0 < ch.hi; t0 += T2) {
+    uint32_t sl[kPartPer];  // loads first, then the counting atomics
+#pragma unroll
+    for (int k = 0; k < kPartPer; ++k) {
+      const uint32_t i = t0 + threadIdx.x + k * kPart2Threads;
+      if (i < ch.hi) sl[k] = in[i].w;
+    }
+#pragma unroll
+    for (int k = 0; k < kPartPer; ++k)
+      if (t0 + threadIdx.x + k * kPart2Threads < ch.hi) atomicAdd(&hist[sl[k] / kSubSlots], 1u);
+  }
   __syncthreads();
   const uint32_t nc = nch[ch.b];
   for (uint32_t i = threadIdx.x; i < sp.S; i += kPart2Threads)
@@ -440,13 +475,17 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_scatter(
     uint4 rec[kPartPer];
     uint32_t dig[kPartPer], rank[kPartPer];
 #pragma unroll
+    for (int k = 0; k < kPartPer; ++k) {  // loads first, then the counting atomics
+      const uint32_t i = t0 + threadIdx.x + k * kPart2Threads;
+      rec[k] = make_uint4(0, 0, 0, 0);
+      if (i < ch.hi) rec[k] = in[i];
+    }
+#pragma unroll
     for (int k = 0; k < kPartPer; ++k) {
       const uint32_t i = t0 + threadIdx.x + k * kPart2Threads;
       dig[k] = kNoDigit;
       rank[k] = 0;
-      rec[k] = make_uint4(0, 0, 0, 0);
       if (i < ch.hi) {
-        rec[k] = in[i];
         dig[k] = rec[k].w / kSubSlots;
         rank[k] = atomicAdd(&L.toff[dig[k]], 1u);
       }
@@ -518,11 +557,15 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict_
   uint32_t dr[kL3Per];  // digit | rank << 8
   if (fits) {
 #pragma unroll
+    for (int k = 0; k < kL3Per; ++k) {  // loads first, then the counting atomics
+      const uint32_t i = lo + threadIdx.x + k * kL3Threads;
+      if (i < hi) rec[k] = in[i];
+    }
+#pragma unroll
     for (int k = 0; k < kL3Per; ++k) {
       const uint32_t i = lo + threadIdx.x + k * kL3Threads;
       dr[k] = 0xffffffffu;
       if (i < hi) {
-        rec[k] = in[i];
         const uint32_t sl = rec[k].w - slot0;
         const uint32_t bl = sl >> 6, o = sl & 63u;
         const uint32_t d = bl * 3 + rank_of(o, g);
