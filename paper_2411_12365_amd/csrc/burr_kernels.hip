@@ -403,18 +403,30 @@ __global__ __launch_bounds__(kPartThreads) void k_p2_plan(const uint32_t* __rest
   for (uint32_t b = threadIdx.x; b <= sp.nb1; b += kPartThreads) cbase[b] = a[b];
 }
 
-// level-2 workgroup -> (bin, chunk, key range); false if unused
+// level-2 workgroup -> (bin, chunk, key range); false if unused.
+// Called by every thread of the workgroup. The bin is the last b with
+// cbase[b] <= wg (cbase is non-decreasing); each wave finds it with 64-way
+// rounds, a ballot over 64 evenly spaced entries per round (two rounds for
+// up to 4096 bins), so a workgroup waits on three dependent loads before
+// its records rather than on one per halving of a binary search.
 struct Chunk2 {
   uint32_t b, c, lo, hi, base;  // base: first counts2 entry of the bin
 };
 __device__ inline bool chunk2_of(uint32_t wg, const SortPlan& sp, const uint32_t* binlo,
                                  const uint32_t* nch, const uint32_t* cbase, Chunk2& ch) {
-  if (wg >= cbase[sp.nb1]) return false;
-  uint32_t lo = 0, hi = sp.nb1;  // last bin b with cbase[b] <= wg
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (cbase[mid] <= wg) lo = mid; else hi = mid;
+  const uint32_t used = cbase[sp.nb1];
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t lo = 0, len = sp.nb1;  // the bin is in [lo, lo + len), and cbase[lo] <= wg
+  while (len > 1) {
+    const uint32_t step = (len + 63) >> 6;
+    const uint32_t idx = lo + lane * step;
+    const uint64_t ok = __ballot(idx < lo + len && cbase[idx] <= wg);
+    const uint32_t k = 63u - (uint32_t)__clzll((long long)ok);  // lane 0 is set
+    lo += k * step;
+    const uint32_t rest = len - k * step;
+    len = step < rest ? step : rest;
   }
+  if (wg >= used) return false;
   ch.b = lo;
   ch.c = wg - cbase[lo];
   ch.lo = binlo[lo] + ch.c * kChunk2;
