@@ -1361,23 +1361,34 @@ __global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
   const uint64_t body = endR - start;
   const uint32_t win = (uint32_t)(span <= kMergeWin ? span : (body < kMergeWin ? body : kMergeWin));
   const uint32_t lane = threadIdx.x;
-  for (uint32_t blk = 0; blk < win / 64; ++blk) {
-    const uint64_t slot = start + 64ull * blk + lane;
-    uint64_t row;
-    uint32_t val;
-    bool occd;
-    if (slot < endR) {
-      occd = (a.occ[slot / 64] >> (slot % 64)) & 1ull;
-      row = a.rowsC[slot];
-      val = a.rowsV[slot];
+  // every load of the window is issued before the first LDS store (win >= 64;
+  // blocks past the window repeat its last block and are not stored)
+  constexpr uint32_t kWinBlocks = kMergeWin / 64;
+  const uint32_t nblk = win / 64;
+  uint64_t lrow[kWinBlocks], locc[kWinBlocks];
+  uint32_t lval[kWinBlocks], lsh[kWinBlocks];
+#pragma unroll
+  for (uint32_t blk = 0; blk < kWinBlocks; ++blk) {
+    const uint64_t slot = start + 64ull * (blk < nblk ? blk : nblk - 1) + lane;
+    if (slot < endR) {  // uniform per block: endR is a multiple of 64
+      locc[blk] = a.occ[slot / 64];
+      lsh[blk] = (uint32_t)(slot % 64);
+      lrow[blk] = a.rowsC[slot];
+      lval[blk] = a.rowsV[slot];
     } else {
-      occd = (a.spill_occ[lastR] >> (slot - endR)) & 1ull;
-      row = a.spillC[lastR * 64 + (slot - endR)];
-      val = a.spillV[lastR * 64 + (slot - endR)];
+      locc[blk] = a.spill_occ[lastR];
+      lsh[blk] = (uint32_t)(slot - endR);
+      lrow[blk] = a.spillC[lastR * 64 + (slot - endR)];
+      lval[blk] = a.spillV[lastR * 64 + (slot - endR)];
     }
-    wc[64 * blk + lane] = occd ? row : 0ull;
-    wv[64 * blk + lane] = occd ? val : 0u;  // empty slots: row 0, value 0
   }
+#pragma unroll
+  for (uint32_t blk = 0; blk < kWinBlocks; ++blk)
+    if (blk < nblk) {
+      const bool occd = (locc[blk] >> lsh[blk]) & 1ull;
+      wc[64 * blk + lane] = occd ? lrow[blk] : 0ull;
+      wv[64 * blk + lane] = occd ? lval[blk] : 0u;  // empty slots: row 0, value 0
+    }
   if (lane == 0) {
     wc[kMergeWin] = 0;
     wv[kMergeWin] = 0;
@@ -1607,13 +1618,20 @@ __global__ __launch_bounds__(64) void k_final_scan(FinalArgs a) {
   uint32_t b = 0;  // nothing lies past the structure's last segment
   for (uint64_t hi = last; hi > first;) {
     const uint64_t lo = hi - first > kScanChunk ? hi - kScanChunk : first;
-#pragma unroll 8
+    // every load of the chunk is issued before the first LDS store (entries
+    // past hi repeat segment hi-1 and are never read)
+    uint64_t rx[kScanChunk];
+    uint32_t rz[kScanChunk];
+#pragma unroll
     for (uint32_t k = 0; k < kScanChunk; ++k) {
-      const uint64_t p = lo + k;
-      if (p < hi) {
-        sx[k][t] = t < 63 ? a.xfirst[p * 64 + t] : 0ull;
-        sz[k][t] = t < 63 ? a.z0first[p * 64 + t] : 0u;
-      }
+      const uint64_t p = lo + k < hi ? lo + k : hi - 1;
+      rx[k] = t < 63 ? a.xfirst[p * 64 + t] : 0ull;
+      rz[k] = t < 63 ? a.z0first[p * 64 + t] : 0u;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kScanChunk; ++k) {
+      sx[k][t] = rx[k];
+      sz[k][t] = rz[k];
     }
     __syncthreads();
     for (uint64_t p = hi; p-- > lo;) {
