@@ -146,8 +146,10 @@ hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s
 // level 3: one workgroup per sub-bin (64 buckets) orders its records by
 //          (bucket, chunk) in LDS and writes headers and records as one block
 // Intermediate records (16 B): key, value | slot within the bin << 32.
-// 4 records per thread: 70 and 48 VGPRs, so 7-8 waves per SIMD stream the
-// tiles (8 records per thread left 4 waves per SIMD)
+// 4 records per thread: level 1 takes 82 VGPRs (5 waves per SIMD; with its
+// loads issued together it is faster than at 70 VGPRs and 7 waves, and held
+// to 80 VGPRs it is slower), level 2 takes 48 (8 waves per SIMD); 8 records
+// per thread left 4 waves per SIMD
 constexpr int kPartPer = 4;                         // records per thread of a tile
 constexpr int kPartThreads = 2048 / kPartPer;       // level 1: 2048-key tiles
 constexpr int kPart2Threads = 4096 / kPartPer;      // level 2: 4096-key tiles
