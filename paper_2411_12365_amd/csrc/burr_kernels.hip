@@ -154,6 +154,7 @@ constexpr int kPartPer = 4;                         // records per thread of a t
 constexpr int kPartThreads = 2048 / kPartPer;       // level 1: 2048-key tiles
 constexpr int kPart2Threads = 4096 / kPartPer;      // level 2: 4096-key tiles
 constexpr uint32_t kTile = kPartThreads * kPartPer;  // level-1 keys per tile
+constexpr int kHistPer = 8;  // keys (records) per thread and step of the counting passes
 constexpr uint32_t kSubSlots = kSubBuckets * 64;     // slots per sub-bin
 constexpr uint32_t kChunk2 = 16384;                  // level-2 keys per workgroup
 constexpr int kL3Threads = 512;  // 8 waves: with the 73 KB block, 4 waves per SIMD
@@ -249,17 +250,17 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_hist(const uint64_t* __rest
   const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
   const uint64_t bin_slots = (uint64_t)sp.S * kSubSlots;
   KeyWalk w(g, lo + threadIdx.x);
-  for (uint64_t t0 = lo; t0 < hi; t0 += kTile) {
+  for (uint64_t t0 = lo; t0 < hi; t0 += kHistPer * kPartThreads) {
     // all of a thread's loads are issued before the first is used (past
     // the end, the last key is read again and not counted)
-    uint64_t kk[kPartPer];
+    uint64_t kk[kHistPer];
 #pragma unroll
-    for (int k = 0; k < kPartPer; ++k) {
+    for (int k = 0; k < kHistPer; ++k) {
       const uint64_t i = t0 + threadIdx.x + (uint64_t)k * kPartThreads;
       kk[k] = keys[i < hi ? i : hi - 1];
     }
 #pragma unroll
-    for (int k = 0; k < kPartPer; ++k) {
+    for (int k = 0; k < kHistPer; ++k) {
       const uint64_t i = t0 + threadIdx.x + (uint64_t)k * kPartThreads;
       if (i < hi) {
         w.advance(g, i);
@@ -451,16 +452,16 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_hist(const uint4* __restri
   if (!chunk2_of(blockIdx.x, sp, binlo, nch, cbase, ch)) return;
   for (uint32_t i = threadIdx.x; i < sp.S; i += kPart2Threads) hist[i] = 0;
   __syncthreads();
-  constexpr uint32_t T2 = kPart2Threads * kPartPer;
+  constexpr uint32_t T2 = kPart2Threads * kHistPer;
   for (uint32_t t0 = ch.lo; t0 < ch.hi; t0 += T2) {
-    uint32_t sl[kPartPer];  // loads first, then the counting atomics
+    uint32_t sl[kHistPer];  // loads first, then the counting atomics
 #pragma unroll
-    for (int k = 0; k < kPartPer; ++k) {
+    for (int k = 0; k < kHistPer; ++k) {
       const uint32_t i = t0 + threadIdx.x + k * kPart2Threads;
       if (i < ch.hi) sl[k] = in[i].w;
     }
 #pragma unroll
-    for (int k = 0; k < kPartPer; ++k)
+    for (int k = 0; k < kHistPer; ++k)
       if (t0 + threadIdx.x + k * kPart2Threads < ch.hi) atomicAdd(&hist[sl[k] / kSubSlots], 1u);
   }
   __syncthreads();
