@@ -139,7 +139,10 @@ burr_handle* burr_build(const uint64_t* keys, const void* values, uint64_t n, ui
 int burr_query(const burr_handle* h, const uint64_t* keys, uint64_t n, void* out, void* stream);
 
 /* Filter mode only: out[i] = 1 if the stored value of keys[i] equals its
- * fingerprint (always 1 for stored keys; 2^-r false positive rate). */
+ * fingerprint (always 1 for stored keys; 2^-r false positive rate): a
+ * retrieval structure that stores key fingerprints is an approximate
+ * membership filter (Sec. 1; the paper's experiments use BuRR as an 8-bit
+ * filter, Sec. 4). Same layer walk as burr_query; out is a device u8[n]. */
 int burr_contains(const burr_handle* h, const uint64_t* keys, uint64_t n, uint8_t* out,
                   void* stream);
 

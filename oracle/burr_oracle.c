@@ -31,8 +31,8 @@
 #define REF_W 64u
 
 /* ------------------------------------------------------------------------ */
-/* Hashing (Sec. 2: "the 1-bits in the hash of a key determine which slots   */
-/* are XORed"; spatial coupling confines them to a window of width w).       */
+/* Hashing (Sec. 2: a key's hash row selects the slots whose XOR is its     */
+/* value; spatial coupling confines the row to a window of width w).         */
 /* Reading: MurmurHash3's 64-bit finalizer as the mixer, Lemire's            */
 /* multiply-shift reduction for the start slot.                              */
 /* ------------------------------------------------------------------------ */
@@ -118,7 +118,7 @@ static void ref_store_value(void* out, uint32_t r, uint64_t i, uint32_t v) {
 /* ------------------------------------------------------------------------ */
 
 /* Slots of a BuRR layer with nkeys keys: the overloaded table of Sec. 2
- * ("more equations than can fit"), m = b * max(1, ceil(load * n / b)). */
+ * (fewer slots than keys), m = b * max(1, ceil(load * n / b)). */
 static uint64_t ref_layer_slots(const ref_params* p, uint64_t nkeys) {
   uint64_t b = p->bucket;
   unsigned __int128 num = (unsigned __int128)nkeys * p->load_num;
@@ -146,7 +146,7 @@ static uint64_t ref_range_first_bucket(uint64_t rho, uint64_t B, uint64_t R) {
 
 /* Final layer slots for attempt a: 64 * max(1, ceil(n * (final + a/10))),
  * i.e. each failed attempt scales the table up by a tenth of n
- * (Sec. 3/4: the last layer "needs to be scaled up" if it cannot solve). */
+ * (Sec. 3 and 4: a last layer that does not solve is made larger). */
 static uint64_t ref_final_slots(const ref_params* p, uint64_t nkeys, uint32_t a) {
   unsigned __int128 num =
       (unsigned __int128)nkeys * ((uint64_t)p->final_num * 10u + (uint64_t)a * p->final_den);
@@ -218,8 +218,8 @@ static void ref_interleave(const uint32_t* Z, uint64_t m, uint32_t r, uint64_t* 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Sorting by start slot (Sec. 4: "sorting the hashes by their insertion     */
-/* position"). Plain qsort of (start, input index).                          */
+/* Sorting by start slot (Sec. 4 names this sorting step). Plain qsort of   */
+/* (start, input index).                                                     */
 /* ------------------------------------------------------------------------ */
 
 typedef struct { uint64_t s; uint64_t idx; } ref_pos;
@@ -415,8 +415,8 @@ static int ref_build_layer(ref_burr* h, uint32_t li, const uint64_t* keys,
 
 /* ------------------------------------------------------------------------ */
 /* Final layer: plain ribbon, no bumping, scaled up until it solves          */
-/* (Sec. 3: "the last layer ... cannot bump any keys"; Sec. 4: it "needs to  */
-/* be scaled up if its equations cannot be solved").                         */
+/* (Sec. 3: no bumping is possible in the last layer; Sec. 4: when its      */
+/* system has no solution, the layer is made larger and built again).       */
 /* ------------------------------------------------------------------------ */
 static int ref_build_final(ref_burr* h, const uint64_t* keys, const uint32_t* vals,
                            uint64_t n) {

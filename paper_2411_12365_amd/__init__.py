@@ -118,9 +118,57 @@ class Params:
     flags: int = 0
     seed: int = 0
 
-    def c(self, stream: int | None = None) -> _CParams:
-        return _CParams(abi_version=ABI_VERSION, stream=stream, alloc=None, free=None,
-                        alloc_ctx=None, **asdict(self))
+    def c(self, stream: int | None = None, allocator: "TorchAllocator | None" = None) -> _CParams:
+        cp = _CParams(abi_version=ABI_VERSION, stream=stream, alloc=None, free=None,
+                      alloc_ctx=None, **asdict(self))
+        if allocator is not None:
+            cp.alloc = ctypes.cast(allocator._alloc_cb, ctypes.c_void_p)
+            cp.free = ctypes.cast(allocator._free_cb, ctypes.c_void_p)
+        return cp
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class TorchAllocator:
+    """Device memory for the library from PyTorch's caching allocator: passed
+    as burr_params.alloc/free, every workspace buffer and table of a build
+    then lives in torch-managed memory (stream-ordered on the build's stream)
+    instead of the library's own hipMalloc cache or HIP's pool. Counts the
+    bytes it has handed out and not yet taken back."""
+
+    def __init__(self, device=None):
+        import torch
+        self.device = torch.cuda.current_device() if device is None else \
+            torch.device(device).index or 0
+        self.live = {}          # pointer -> bytes
+        self.allocations = 0    # calls that returned memory
+        self.peak = 0
+
+        def _alloc(nbytes, stream, ctx):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device,
+                                                         int(stream or 0))
+            except Exception:  # reported by the library as BURR_E_NOMEM
+                return None
+            self.live[ptr] = int(nbytes)
+            self.allocations += 1
+            self.peak = max(self.peak, sum(self.live.values()))
+            return ptr
+
+        def _free(ptr, stream, ctx):
+            if ptr:
+                self.live.pop(ptr, None)
+                torch.cuda.caching_allocator_delete(ptr)
+
+        # kept referenced for as long as the allocator lives
+        self._alloc_cb = _ALLOC_FN(_alloc)
+        self._free_cb = _FREE_FN(_free)
+
+    @property
+    def live_bytes(self) -> int:
+        return sum(self.live.values())
 
 
 _lib = None
@@ -233,11 +281,13 @@ class Handle:
     """A structure built on the GPU; owns its device memory until free().
     A batch member's handle owns nothing: it keeps its batch alive."""
 
-    def __init__(self, ptr: int, r: int, params: Params, batch: "Batch | None" = None):
+    def __init__(self, ptr: int, r: int, params: Params, batch: "Batch | None" = None,
+                 allocator: TorchAllocator | None = None):
         self._h = ptr
         self.r = r
         self.params = params
         self._batch = batch
+        self._allocator = allocator  # frees through it, so it must outlive the handle
 
     def __del__(self):
         self.free()
@@ -265,9 +315,11 @@ class Handle:
         return burr_debug_layer_keys(self, layer)
 
 
-def burr_build(keys, values, r: int, params: Params | None = None, stream=None) -> Handle:
+def burr_build(keys, values, r: int, params: Params | None = None, stream=None,
+               allocator: TorchAllocator | None = None) -> Handle:
     """keys: int64/uint64 GPU tensor (bit pattern of u64 keys); values: GPU
-    tensor of uint8/uint16/uint32 (by r) or None in filter mode."""
+    tensor of uint8/uint16/uint32 (by r) or None in filter mode. With an
+    allocator (TorchAllocator), the build's device memory comes from PyTorch."""
     import torch
     params = params or Params()
     _check_tensor(keys, "keys", (torch.int64, torch.uint64))
@@ -277,21 +329,22 @@ def burr_build(keys, values, r: int, params: Params | None = None, stream=None) 
         if values.numel() != keys.numel():
             raise ValueError("keys and values differ in length")
         vptr = values.data_ptr()
-    cp = params.c(_stream_of(stream))
+    cp = params.c(_stream_of(stream), allocator)
     h = lib().burr_build(keys.data_ptr() if keys.numel() else None, vptr, keys.numel(), r,
                          ctypes.byref(cp))
     if not h:
         raise BurrError(lib().burr_last_error(), "burr_build")
-    return Handle(h, r, params)
+    return Handle(h, r, params, allocator=allocator)
 
 
 class Batch:
     """Independent structures built together by burr_build_batch."""
 
-    def __init__(self, ptr: int, rs, params: Params):
+    def __init__(self, ptr: int, rs, params: Params, allocator: TorchAllocator | None = None):
         self._b = ptr
         self.rs = rs
         self.params = params
+        self._allocator = allocator
 
     def __del__(self):
         self.free()
@@ -328,19 +381,19 @@ def _batch_args(keys, values, offsets, rs):
 
 
 def burr_build_batch(keys, values, offsets, rs, params: Params | None = None,
-                     stream=None) -> Batch:
+                     stream=None, allocator: TorchAllocator | None = None) -> Batch:
     """keys: GPU int64/uint64 tensor holding every structure's keys back to
     back; offsets: host sequence of len(rs)+1 key offsets (offsets[0] = 0);
     rs: value bits per structure; values: GPU tensor laid out like keys with
     the value dtype of max(rs), or None in filter mode."""
     params = params or Params()
     kptr, vptr, off, rr = _batch_args(keys, values, offsets, rs)
-    cp = params.c(_stream_of(stream))
+    cp = params.c(_stream_of(stream), allocator)
     b = lib().burr_build_batch(kptr, vptr, off.ctypes.data, rr.ctypes.data, len(rr),
                                ctypes.byref(cp))
     if not b:
         raise BurrError(lib().burr_last_error(), "burr_build_batch")
-    return Batch(b, rr, params)
+    return Batch(b, rr, params, allocator)
 
 
 def _tune_array(table):

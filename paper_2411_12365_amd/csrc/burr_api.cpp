@@ -1527,6 +1527,12 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
   def.final_attempts = hdr[13];
   def.filter_mode = hdr[14];
   def.seed = in.get(8);
+  // the imported parameters must be ones a build accepts, and the layer
+  // count must fit them
+  if (!params_ok(&def) || hdr[15] > def.layers) {
+    set_error(BURR_E_INVALID);
+    return nullptr;
+  }
   burr_batch* b = new_batch(&def, 1);
   if (!b) {
     set_error(BURR_E_NOMEM);
@@ -1537,6 +1543,13 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
   mb.r = hdr[3];
   mb.n = in.get(8);
   mb.built = hdr[15];
+  // words of a layer of m slots that the rest of the buffer can hold: a
+  // size read from the buffer is checked against it before any product
+  // that could wrap (m / 64 words of codes or r words per 64 slots)
+  auto fits = [&](uint64_t m, uint64_t per_block) -> bool {
+    const uint64_t rest = (in.len - std::min<size_t>(in.off, in.len)) / 8;
+    return m / 64 <= rest / per_block;
+  };
   auto load_words = [&](uint64_t nw, uint64_t** dst) -> bool {
     if (in.off + nw * 8 > in.len) return false;
     *dst = (uint64_t*)b->alloc_table(nw * 8 + 8);
@@ -1552,7 +1565,7 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
     L.n = in.get(8);
     L.m = in.get(8);
     L.R = in.get(8);
-    if (!in.ok || L.m % 64 || L.m < 64) {
+    if (!in.ok || L.m % 64 || L.m < 64 || !fits(L.m, mb.r) || L.R == 0 || L.R > L.m / 64) {
       ok = false;
       break;
     }
@@ -1571,7 +1584,7 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
     mb.fin.m = in.get(8);
     mb.fin_attempt = in.get(8);
     if (mb.built > 0) b->layers[mb.built - 1].bumped[0] = (uint32_t)mb.fin.n;
-    ok = in.ok && mb.fin.m % 64 == 0;
+    ok = in.ok && mb.fin.m % 64 == 0 && fits(mb.fin.m, mb.r) && (mb.fin.m == 0) == (mb.fin.n == 0);
     if (ok) {
       mb.fin.nW = (mb.fin.m / 64) * mb.r;
       uint64_t* w = nullptr;

@@ -168,3 +168,25 @@ def test_low_word_collision_takes_the_exact_pass():
     keys = np.array([a, b] + others, dtype=np.uint64)
     vals = W.values(n, 8, 31)
     _compare(keys, vals, 8, dict(ranges=1), "low-word pair")
+
+
+@pytest.mark.parametrize("n,r,kw", [
+    (120_000, 8, dict(ranges=16, load_num=50, load_den=100, seed=31)),
+    (150_000, 16, dict(ranges=1, load_num=60, load_den=100, seed=32)),
+])
+def test_overfull_buckets_and_sub_bins(n, r, kw):
+    """Two rarely taken kernel paths, reached on purpose: at 0.5-0.6 slots per
+    key, layer-0 buckets hold 100-128 keys on average, so the insertion
+    kernel must read records past its 127-record LDS stage from the item
+    stream, and 64-bucket sub-bins hold more than the 4,608 records the
+    level-3 sort stages in LDS, so it takes its two-pass global path."""
+    keys = W.keys(n, 3000 + n)
+    vals = W.values(n, r, 4000 + n)
+    op = oracle.Params(**kw)
+    m, B, R = oracle.layer_geometry(op, n)
+    per_bucket = np.bincount(oracle.start_buckets(keys, 0, m, op), minlength=B)
+    assert per_bucket.max() >= 128, "no bucket exceeds the insertion stage"
+    per_sub = np.add.reduceat(per_bucket, np.arange(0, B, 64)) + \
+        np.minimum(64, B - np.arange(0, B, 64))  # records + one header per bucket
+    assert per_sub.max() > 4608, "no sub-bin exceeds the level-3 LDS block"
+    _compare(keys, vals, r, kw, "overfull")

@@ -37,6 +37,16 @@ MUTANTS = {
                    "uint64_t salt_s = ref_fmix64(seed ^ (2ull * layer + 2ull));"),
     "range_split": ("return (uint64_t)(((unsigned __int128)rho * B) / R);",
                     "return (uint64_t)(((unsigned __int128)rho * B + R - 1) / R);"),
+    "start_span_short": ("*start = ref_fastrange(ref_fmix64(key ^ salt_s), m - REF_W + 1);",
+                         "*start = ref_fastrange(ref_fmix64(key ^ salt_s), m - REF_W);"),
+    "salt_plus_not_xor": ("uint64_t salt_s = ref_fmix64(seed ^ (2ull * layer + 1ull));",
+                          "uint64_t salt_s = ref_fmix64(seed + (2ull * layer + 1ull));"),
+    "salts_swapped": ("uint64_t salt_s = ref_fmix64(seed ^ (2ull * layer + 1ull));\n"
+                      "  uint64_t salt_c = ref_fmix64(seed ^ (2ull * layer + 2ull));",
+                      "uint64_t salt_s = ref_fmix64(seed ^ (2ull * layer + 2ull));\n"
+                      "  uint64_t salt_c = ref_fmix64(seed ^ (2ull * layer + 1ull));"),
+    "fingerprint_salt": ("uint64_t h = ref_fmix64(key ^ ref_fmix64(~seed));",
+                         "uint64_t h = ref_fmix64(key ^ ref_fmix64(seed));"),
     "load_rounding": ("uint64_t nb = (uint64_t)((num + den - 1) / den);\n  if (nb < 1) nb = 1;\n  return nb * b;",
                       "uint64_t nb = (uint64_t)(num / den);\n  if (nb < 1) nb = 1;\n  return nb * b;"),
 }
@@ -48,6 +58,7 @@ import oracle
 oracle._LIB_PATH = {lib!r}
 oracle._lib = None
 from tests import test_oracle_bruteforce as bf, test_oracle_hash as th
+from tests import test_oracle_hash_composition as hc
 from paper_2411_12365_amd import workload as W
 import numpy as np
 failed = []
@@ -66,6 +77,12 @@ run("fmix", th.test_fmix64_is_inverted_by_the_published_steps)
 run("fastrange", th.test_fastrange_is_exact_floor)
 run("hashshape", th.test_hash_ranges_and_row_shape)
 run("layers", th.test_layers_hash_independently)
+for layer in (0, 3):
+    run("start_salt%d" % layer, hc.test_start_salt_zero_reduces_to_the_finalizer, layer)
+    run("row_salt%d" % layer, hc.test_row_salt_zero_reduces_to_the_finalizer, layer)
+run("fp_salt", hc.test_fingerprint_salt_zero_reduces_to_the_finalizer)
+run("largest_start", hc.test_largest_start_at_any_seed)
+run("golden", hc.test_golden_vectors)
 def query_inv():
     k = W.keys(20000, 3); v = W.values(20000, 8, 4)
     b = oracle.build(k, v, 8, oracle.Params(ranges=16))
