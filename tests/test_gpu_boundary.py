@@ -44,7 +44,8 @@ def test_build_through_torch_allocator():
     # handle still holds (its tables) is torch memory
     assert alloc.allocations >= 10
     assert alloc.live_bytes >= st["table_bytes"] > 0
-    assert torch.cuda.memory_allocated() - base == alloc.live_bytes
+    held = torch.cuda.memory_allocated() - base  # torch rounds blocks up to 512 bytes
+    assert alloc.live_bytes <= held <= alloc.live_bytes + 512 * len(alloc.live)
     ref = oracle.build(keys, vals, r, oracle.Params(**kw))
     check_handle(h, ref, keys)
     h.free()
