@@ -131,6 +131,28 @@ void burr_default_params(burr_params* p);
 burr_handle* burr_build(const uint64_t* keys, const void* values, uint64_t n, uint32_t r,
                         const burr_params* p);
 
+/* burr_build for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same structure, export bytes and query results as burr_build with the same
+ * keys, values, r and *p, but the call makes no device allocation (no
+ * hipMalloc, hipFree, stream-ordered pool or allocator callback; p->alloc and
+ * p->free are ignored) and creates no stream. Its temporary buffers live in a
+ * fixed device array of 128 MiB that the library holds on every GPU it runs
+ * on until the process ends (enough for about 1.3M keys; more keys:
+ * BURR_E_INVALID, with a message on stderr). The structure's tables are
+ * written to table_mem (device, 256-byte aligned, caller-owned, table_cap
+ * bytes; burr_estimate_build_bytes's table_bytes is enough); it must outlive
+ * the handle. BURR_E_NOMEM if table_cap turns out too small. The array is
+ * shared by every call on a GPU and keeps the last call's contents: calls
+ * that overlap on one GPU would race for it, so the library serializes them
+ * (a second call waits until the first has returned). Runs on p->stream and
+ * returns when the build is complete; BURR_FLAG_KEEP_LAYER_KEYS is rejected.
+ * burr_free releases the handle (not table_mem). Host bookkeeping of the
+ * handle is ordinary host memory. */
+burr_handle* burr_build_noalloc(const uint64_t* keys, const void* values, uint64_t n,
+                                uint32_t r, const burr_params* p, void* table_mem,
+                                size_t table_cap);
+
 /* Queries n keys (device u64[n]) into out (device, value width of r): for
  * each layer, skip it if the key's offset is below its bucket's threshold,
  * else return the parity of the key's row AND the table window, per column

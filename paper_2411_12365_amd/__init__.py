@@ -36,7 +36,7 @@ _EXPORTS = ("burr_default_params", "burr_build", "burr_query", "burr_contains", 
             "burr_server_submit_query", "burr_server_poll", "burr_server_drain",
             "burr_server_drop", "burr_server_handle", "burr_server_get_info",
             "burr_server_destroy", "burr_release_workspaces", "burr_build_batch_tuned",
-            "burr_autotune")
+            "burr_autotune", "burr_build_noalloc")
 
 
 class BurrError(RuntimeError):
@@ -187,6 +187,9 @@ def lib():
         L.burr_default_params.restype = None
         L.burr_build.argtypes = [vp, vp, u64, u32, ctypes.POINTER(_CParams)]
         L.burr_build.restype = vp
+        L.burr_build_noalloc.argtypes = [vp, vp, u64, u32, ctypes.POINTER(_CParams), vp,
+                                         ctypes.c_size_t]
+        L.burr_build_noalloc.restype = vp
         L.burr_query.argtypes = [vp, vp, u64, vp, vp]
         L.burr_query.restype = i32
         L.burr_contains.argtypes = [vp, vp, u64, vp, vp]
@@ -335,6 +338,31 @@ def burr_build(keys, values, r: int, params: Params | None = None, stream=None,
     if not h:
         raise BurrError(lib().burr_last_error(), "burr_build")
     return Handle(h, r, params, allocator=allocator)
+
+
+def burr_build_noalloc(keys, values, r: int, table, params: Params | None = None,
+                       stream=None) -> Handle:
+    """burr_build without any device allocation by the library: temporary
+    buffers come from its fixed scratch array, the tables go to `table` (a
+    caller-owned uint8 GPU tensor, kept alive by the handle)."""
+    import torch
+    params = params or Params()
+    _check_tensor(keys, "keys", (torch.int64, torch.uint64))
+    _check_tensor(table, "table", (torch.uint8,))
+    vptr = None
+    if values is not None:
+        _check_tensor(values, "values", (value_dtype(r),))
+        if values.numel() != keys.numel():
+            raise ValueError("keys and values differ in length")
+        vptr = values.data_ptr()
+    cp = params.c(_stream_of(stream))
+    h = lib().burr_build_noalloc(keys.data_ptr() if keys.numel() else None, vptr, keys.numel(),
+                                 r, ctypes.byref(cp), table.data_ptr(), table.numel())
+    if not h:
+        raise BurrError(lib().burr_last_error(), "burr_build_noalloc")
+    hd = Handle(h, r, params)
+    hd._table = table
+    return hd
 
 
 class Batch:
@@ -654,6 +682,7 @@ class Server:
 # short aliases
 build = burr_build
 build_batch = burr_build_batch
+build_noalloc = burr_build_noalloc
 build_batch_tuned = burr_build_batch_tuned
 autotune = burr_autotune
 import_ = burr_import

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -195,8 +196,10 @@ struct burr_batch {
   uint8_t* arena = nullptr;  // one allocation that the layers' tables are carved from
   uint64_t arena_cap = 0, arena_used = 0;
   double ms_total = 0, ms_final = 0;
+  bool no_alloc = false;  // tables live in caller memory (the arena) only
 
   void* alloc(uint64_t bytes) {
+    if (no_alloc) return nullptr;
     void* p = al.get(bytes);
     if (p) owned.push_back(p);
     return p;
@@ -367,8 +370,16 @@ struct Workspace {
   uint64_t* diag = nullptr;  // insertion-kernel diagnostics (16 u64)
   uint64_t *spillC = nullptr, *spill_occ = nullptr, *xfirst = nullptr;
   uint32_t *spillV = nullptr, *z0first = nullptr, *bnd = nullptr;
+  // scratch mode (builds that allocate nothing): every device buffer is
+  // carved from a fixed region, the host staging and results use the fixed
+  // arrays below (pageable), and nothing is freed
+  uint8_t* scr = nullptr;
+  uint64_t scr_cap = 0, scr_used = 0;
+  uint64_t fixed_host[64];
+  uint32_t fixed_res[64];
 
   explicit Workspace(Allocator* a) : al(a) {}
+  Workspace(uint8_t* region, uint64_t cap) : al(nullptr), scr(region), scr_cap(cap) {}
   ~Workspace() {
     for (void* p : owned) {
       if (al)
@@ -376,8 +387,8 @@ struct Workspace {
       else
         (void)hipFree(p);
     }
-    if (host) (void)hipHostFree(host);
-    if (hres) (void)hipHostFree(hres);
+    if (host && !scr) (void)hipHostFree(host);
+    if (hres && !scr) (void)hipHostFree(hres);
     if (side) (void)hipStreamDestroy(side);
     for (hipEvent_t e : evs) (void)hipEventDestroy(e);
   }
@@ -398,6 +409,17 @@ struct Workspace {
   template <typename T>
   bool alloc(T*& ptr, uint64_t count) {
     const size_t b = ((count * sizeof(T)) + 255) & ~(size_t)255;
+    if (scr) {  // carve from the fixed region; an outgrown buffer stays where it is
+      const uint64_t need = b ? b : 256;
+      if (need > scr_cap - scr_used) {
+        ptr = nullptr;
+        return false;
+      }
+      ptr = reinterpret_cast<T*>(scr + scr_used);
+      scr_used += need;
+      bytes += need;
+      return true;
+    }
     if (!al) {  // kept between builds: replace the outgrown buffer
       for (size_t k = 0; ptr && k < owned.size(); ++k)
         if (owned[k] == (void*)ptr) {
@@ -424,6 +446,11 @@ struct Workspace {
   }
   // pinned host staging of at least `need` bytes
   bool reserve_host(size_t need) {
+    if (scr) {
+      host = reinterpret_cast<uint8_t*>(fixed_host);
+      host_cap = sizeof(fixed_host);
+      return need <= host_cap;
+    }
     if (need <= host_cap && host) return true;
     if (host) (void)hipHostFree(host);
     host = nullptr;
@@ -442,7 +469,11 @@ struct Workspace {
       cap_res = words;
       if (!alloc(res, words)) return false;
     }
-    if (words * 4 > hres_cap || !hres) {
+    if (scr) {
+      hres = fixed_res;
+      hres_cap = sizeof(fixed_res);
+      if (words * 4 > hres_cap) return false;
+    } else if (words * 4 > hres_cap || !hres) {
       if (hres) (void)hipHostFree(hres);
       hres = nullptr;
       hres_cap = words * 4;
@@ -807,7 +838,7 @@ struct HostClock {};
 #endif
 
 int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
-                const std::vector<uint64_t>& off) {
+                const std::vector<uint64_t>& off, Workspace* fixed_ws = nullptr) {
   HostClock hc;
   (void)hc;
   const LayerPlanner planner(b->p);
@@ -817,14 +848,23 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   const uint32_t M = (uint32_t)b->members.size();
   uint32_t rmax = 1;
   for (const Member& mb : b->members) rmax = std::max(rmax, mb.r);
-  WsLease lease(&b->al, p, s);
-  if (!lease.ws) return set_error(BURR_E_NOMEM);
-  Workspace& ws = *lease.ws;
-  b->arena_cap = batch_table_estimate(b, off);
-  HOST_LAP(hc, "estimate", 0u);
-  b->arena = (uint8_t*)b->alloc(b->arena_cap);
-  if (!b->arena) return set_error(BURR_E_NOMEM);
-  b->table_bytes = b->arena_cap;
+  // the workspace: the caller's (scratch builds), else one from the cache
+  // or made for this build
+  std::unique_ptr<WsLease> lease;
+  Workspace* wsp = fixed_ws;
+  if (!wsp) {
+    lease.reset(new (std::nothrow) WsLease(&b->al, p, s));
+    if (!lease || !lease->ws) return set_error(BURR_E_NOMEM);
+    wsp = lease->ws;
+  }
+  Workspace& ws = *wsp;
+  if (!b->arena) {  // scratch builds bring the caller's table memory
+    b->arena_cap = batch_table_estimate(b, off);
+    HOST_LAP(hc, "estimate", 0u);
+    b->arena = (uint8_t*)b->alloc(b->arena_cap);
+    if (!b->arena) return set_error(BURR_E_NOMEM);
+    b->table_bytes = b->arena_cap;
+  }
   // events: [0] start, 7 per layer, then the final layer's start and end
   hipEvent_t* const ev = ws.events(3 + 7 * (size_t)p.layers);
   if (!ev) return set_error(BURR_E_DEVICE);
@@ -833,7 +873,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   // kept between builds; a per-build workspace (server, caller allocator)
   // keeps it on the build's stream rather than create a stream per build
   hipStream_t side = s;
-  if (!ws.al) {
+  if (!ws.al && !ws.scr) {
     side = ws.side_stream();
     if (!side) return set_error(BURR_E_DEVICE);
   }
@@ -1042,7 +1082,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   return BURR_OK;
 }
 
-burr_batch* new_batch(const burr_params* p, uint32_t count) {
+burr_batch* new_batch(const burr_params* p, uint32_t count, bool no_alloc = false) {
   burr_batch* b = new (std::nothrow) burr_batch();
   if (!b) return nullptr;
   {
@@ -1070,8 +1110,9 @@ burr_batch* new_batch(const burr_params* p, uint32_t count) {
     b->views[i].b = b;
     b->views[i].idx = i;
   }
+  b->no_alloc = no_alloc;
   int dev = 0;
-  if (hipGetDevice(&dev) == hipSuccess) keep_pool_memory(dev);
+  if (!no_alloc && hipGetDevice(&dev) == hipSuccess) keep_pool_memory(dev);
   return b;
 }
 
@@ -1272,6 +1313,104 @@ burr_handle* burr_build(const uint64_t* keys, const void* values, uint64_t n, ui
   b->views[0].owner = true;
   const std::vector<uint64_t> off = {0, n};
   const int rc = build_batch(b, keys, values, off);
+  if (rc != BURR_OK) {
+    free_batch(b);
+    set_error(rc);
+    return nullptr;
+  }
+  set_error(BURR_OK);
+  return &b->views[0];
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Builds that allocate nothing (burr_build_noalloc)
+// ---------------------------------------------------------------------------
+// The build's temporary buffers come from one fixed device array per GPU.
+// In host code `scratch` names a host-side stand-in, not device memory: the
+// array is only ever used through the device address hipGetSymbolAddress
+// returns for the current device (kept per device in g_scratch).
+namespace {
+constexpr uint64_t kScratchBytes = 128ull << 20;
+}
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+
+struct ScratchState {
+  std::mutex mu;                  // one scratch build per device at a time
+  uint8_t* ptr = nullptr;         // device address of this device's array
+  std::vector<hipEvent_t> evs;    // a build's events, created by the first call
+};
+ScratchState g_scratch[kMaxDevices];
+
+// Workspace bytes the build of n keys may carve from the array: the
+// workspace estimate with a quarter added for what it leaves out (the second
+// row set of the deeper layers, buffers outgrown by a final-layer retry) and
+// 4 MiB of fixed-size buffers.
+uint64_t scratch_need(uint64_t n, uint32_t r, const burr_params* p) {
+  return burr_workspace_bytes(n, r, 1, p, 0) / 4 * 5 + (4ull << 20);
+}
+
+}  // namespace
+
+extern "C" {
+
+burr_handle* burr_build_noalloc(const uint64_t* keys, const void* values, uint64_t n,
+                                uint32_t r, const burr_params* p, void* table_mem,
+                                size_t table_cap) {
+  if (!params_ok(p) || r < 1 || r > 32 || (n > 0 && !keys) ||
+      (!p->filter_mode && !values && n > 0) || n >= kMaxKeys || !table_mem ||
+      reinterpret_cast<uintptr_t>(table_mem) % 256 != 0 ||
+      (p->flags & BURR_FLAG_KEEP_LAYER_KEYS)) {
+    set_error(BURR_E_INVALID);
+    return nullptr;
+  }
+  const uint64_t need = scratch_need(n, r, p);
+  if (need > kScratchBytes) {
+    fprintf(stderr,
+            "burr_build_noalloc: %llu keys need about %llu bytes of scratch, more than its "
+            "%llu bytes\n",
+            (unsigned long long)n, (unsigned long long)need, (unsigned long long)kScratchBytes);
+    set_error(BURR_E_INVALID);
+    return nullptr;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    set_error(BURR_E_DEVICE);
+    return nullptr;
+  }
+  ScratchState& st = g_scratch[dev];
+  std::lock_guard<std::mutex> lk(st.mu);
+  if (!st.ptr) {  // set-up, once per device, with the device current
+    void* addr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !addr) {
+      fprintf(stderr, "burr_build_noalloc: hipGetSymbolAddress failed: %s\n",
+              hipGetErrorString(e));
+      set_error(BURR_E_DEVICE);
+      return nullptr;
+    }
+    st.ptr = static_cast<uint8_t*>(addr);
+  }
+  burr_batch* b = new_batch(p, 1, true);
+  if (!b) {
+    set_error(BURR_E_NOMEM);
+    return nullptr;
+  }
+  b->members[0].n = n;
+  b->members[0].r = r;
+  b->views[0].owner = true;
+  b->arena = static_cast<uint8_t*>(table_mem);
+  b->arena_cap = table_cap;
+  b->table_bytes = table_cap;
+  Workspace ws(st.ptr, kScratchBytes);
+  ws.evs.swap(st.evs);  // events are made by the first call and kept
+  const std::vector<uint64_t> off = {0, n};
+  const int rc = build_batch(b, keys, values, off, &ws);
+  (void)hipStreamSynchronize(b->stream);  // the array is free for the next call
+  ws.evs.swap(st.evs);
   if (rc != BURR_OK) {
     free_batch(b);
     set_error(rc);
