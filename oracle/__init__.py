@@ -31,7 +31,7 @@ def compile_oracle(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + f".tmp{os.getpid()}"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+            ["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-fPIC", "-shared", "-pthread",
              _SRC, "-o", tmp])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -52,6 +52,10 @@ class _Params(ctypes.Structure):
         ("final_attempts", ctypes.c_uint32),
         ("filter_mode", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
+        ("threshold_mode", ctypes.c_uint32),
+        ("cut_strategy", ctypes.c_uint32),
+        ("cut_search", ctypes.c_uint32),
+        ("pad", ctypes.c_uint32),
     ]
 
 
@@ -81,9 +85,12 @@ class Params:
     final_attempts: int = 16
     filter_mode: int = 0
     seed: int = 0
+    threshold_mode: int = 0   # 0: 2-bit, 1: 1+-bit thresholds
+    cut_strategy: int = 0     # 0: equal split, 1 minbump, 2 maxprev, 3 diff
+    cut_search: int = 0       # buckets searched around each equal-split cut
 
     def _c(self) -> _Params:
-        return _Params(**asdict(self))
+        return _Params(**asdict(self), pad=0)
 
 
 _lib = None
@@ -118,6 +125,14 @@ def lib():
         L.ref_get_layer_info.argtypes = [vp, u32, ctypes.POINTER(_LayerInfo)]
         L.ref_get_final_info.restype = ctypes.c_int
         L.ref_get_final_info.argtypes = [vp, ctypes.POINTER(_FinalInfo)]
+        L.ref_build_mt.restype = ctypes.c_int
+        L.ref_build_mt.argtypes = [vp, vp, u64, u32, ctypes.POINTER(_Params), u32,
+                                   ctypes.POINTER(vp)]
+        L.ref_build_from.restype = ctypes.c_int
+        L.ref_build_from.argtypes = [vp, vp, u64, u32, ctypes.POINTER(_Params), u32, u32,
+                                     ctypes.POINTER(vp)]
+        L.ref_layer_cuts.restype = u64
+        L.ref_layer_cuts.argtypes = [vp, u32, vp, u64]
         for fn in ("ref_layer_keys", "ref_layer_codes", "ref_layer_solution"):
             getattr(L, fn).restype = u64
             getattr(L, fn).argtypes = [vp, u32, vp, u64]
@@ -205,6 +220,12 @@ class RefBurr:
         lib().ref_layer_codes(self._h, layer, out.ctypes.data, n)
         return out
 
+    def layer_cuts(self, layer: int) -> np.ndarray:
+        n = lib().ref_layer_cuts(self._h, layer, None, 0)
+        out = np.zeros(n, dtype=np.uint64)
+        lib().ref_layer_cuts(self._h, layer, out.ctypes.data, n)
+        return out
+
     def layer_solution(self, layer: int) -> np.ndarray:
         n = lib().ref_layer_solution(self._h, layer, None, 0)
         out = np.zeros(n, dtype=np.uint32)
@@ -213,8 +234,12 @@ class RefBurr:
 
 
 def build(keys: np.ndarray, values: np.ndarray | None, r: int,
-          params: Params | None = None) -> RefBurr:
-    """Build with the oracle. Raises OracleError on failure."""
+          params: Params | None = None, threads: int = 1,
+          first_layer: int = 0) -> RefBurr:
+    """Build with the oracle. threads > 1 (or 0: every CPU) uses the
+    range-parallel driver, which gives the same structure; first_layer > 0
+    builds only the layers from that one on, from keys that enter it.
+    Raises OracleError on failure."""
     params = params or Params()
     keys = np.ascontiguousarray(keys, dtype=np.uint64)
     vptr = None
@@ -223,8 +248,15 @@ def build(keys: np.ndarray, values: np.ndarray | None, r: int,
         vptr = values.ctypes.data
     h = ctypes.c_void_p(0)
     cp = params._c()
-    rc = lib().ref_build(keys.ctypes.data if len(keys) else None, vptr, len(keys), r,
-                         ctypes.byref(cp), ctypes.byref(h))
+    kptr = keys.ctypes.data if len(keys) else None
+    if first_layer:
+        rc = lib().ref_build_from(kptr, vptr, len(keys), r, ctypes.byref(cp), first_layer,
+                                  threads if threads else os.cpu_count(), ctypes.byref(h))
+    elif threads == 1:
+        rc = lib().ref_build(kptr, vptr, len(keys), r, ctypes.byref(cp), ctypes.byref(h))
+    else:
+        rc = lib().ref_build_mt(kptr, vptr, len(keys), r, ctypes.byref(cp), threads,
+                                ctypes.byref(h))
     if rc != OK:
         raise OracleError(rc)
     return RefBurr(h.value, r, params, len(keys))

@@ -13,6 +13,9 @@
  * detail it leaves open is fixed by the readings listed in each function's
  * comment in burr_oracle.c.
  *
+ * A range-parallel driver (ref_build_mt) builds the same bytes on many
+ * threads; it is pinned to the sequential builder by equality of exports.
+ *
  * Parity pins: thresholds, solution words and bump sets are pinned by dense
  * GF(2) brute force on tiny inputs, the query invariant, range independence
  * and closed-form bounds (tests/test_oracle_*.py). The hash is a reading of
@@ -50,6 +53,11 @@ typedef struct ref_params {
   uint32_t final_attempts;  /* scale-up attempts of the final layer */
   uint32_t filter_mode;     /* 1: stored value is an r-bit key fingerprint */
   uint64_t seed;
+  uint32_t threshold_mode;  /* 0: 2-bit thresholds, 1: 1+-bit thresholds (Sec. 2) */
+  uint32_t cut_strategy;    /* range ends (Sec. 3 "Selecting Cut Points"): 0 equal
+                               split, 1 minbump, 2 maxprev, 3 diff */
+  uint32_t cut_search;      /* buckets searched around each equal-split cut */
+  uint32_t pad;
 } ref_params;
 
 /* per-layer statistics, index 0..layers_built-1; the final layer is
@@ -89,6 +97,21 @@ int ref_build(const uint64_t* keys, const void* values, uint64_t n, uint32_t r,
               const ref_params* p, ref_burr** out);
 void ref_free(ref_burr* h);
 
+/* The same structure built by the range-parallel driver (Sec. 3: every
+ * thread solves its own ranges) on `threads` threads (0: all online CPUs).
+ * Byte-identical export to ref_build. */
+int ref_build_mt(const uint64_t* keys, const void* values, uint64_t n, uint32_t r,
+                 const ref_params* p, uint32_t threads, ref_burr** out);
+
+/* Layers first_layer..layers-1 and the final layer, built from keys that
+ * enter layer first_layer (values as for ref_build); threads as for
+ * ref_build_mt (1: sequential). Its export starts at that layer (the header
+ * records it). Used to check the deeper layers of a structure whose first
+ * layers are too large for the oracle, fed with the GPU's own bumped keys. */
+int ref_build_from(const uint64_t* keys, const void* values, uint64_t n, uint32_t r,
+                   const ref_params* p, uint32_t first_layer, uint32_t threads,
+                   ref_burr** out);
+
 /* Layer geometry of a BuRR layer entered by nkeys keys: slots, buckets and
  * ranges (Sec. 3: equal bucket-aligned ranges of at least minbpt buckets). */
 void ref_layer_geometry(const ref_params* p, uint64_t nkeys, uint64_t* m, uint64_t* nbuckets,
@@ -121,8 +144,11 @@ int ref_get_final_info(const ref_burr* h, ref_final_info* out);
 /* Keys entering layer `layer` (layer == layers_built: the final layer), in
  * the oracle's own order; copy at most cap keys, return the count. */
 uint64_t ref_layer_keys(const ref_burr* h, uint32_t layer, uint64_t* out, uint64_t cap);
-/* 2-bit threshold codes of layer `layer`, one byte per bucket. */
+/* Thresholds of layer `layer`, one byte per bucket: the 2-bit code index,
+ * or with 1+-bit thresholds the threshold itself. */
 uint64_t ref_layer_codes(const ref_burr* h, uint32_t layer, uint8_t* out, uint64_t cap);
+/* Last bucket of every range of layer `layer` (cut points). */
+uint64_t ref_layer_cuts(const ref_burr* h, uint32_t layer, uint64_t* out, uint64_t cap);
 /* Solution Z of layer `layer` (layer == layers_built: final), one u32 per slot. */
 uint64_t ref_layer_solution(const ref_burr* h, uint32_t layer, uint32_t* out, uint64_t cap);
 

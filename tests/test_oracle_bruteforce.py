@@ -9,6 +9,7 @@ solution of the kept equations with free columns zero, the bump set is the set
 of keys below their bucket's threshold, and the final layer's attempt is the
 first table size whose dense system is consistent.
 """
+import bisect
 import random
 
 import numpy as np
@@ -33,6 +34,57 @@ def layer_geometry(p: oracle.Params, n: int):
     return m, B, R, first
 
 
+def thresholds(p: oracle.Params):
+    """Allowed threshold values: four with 2-bit thresholds (Sec. 2), every
+    offset 0..b with 1+-bit thresholds (an exact value per bumped bucket)."""
+    if p.threshold_mode == 1:
+        return list(range(p.bucket + 1))
+    return [0, p.t_lo, p.t_hi, p.bucket]
+
+
+def forced_threshold(p, starts, beta):
+    """Smallest allowed threshold above every offset of a key of bucket beta
+    whose row would cross the end of a range ending with beta (0 if none)."""
+    end = (beta + 1) * p.bucket
+    forced = [s - beta * p.bucket for s in starts if s > end - WIDTH]
+    if not forced:
+        return 0
+    return min(t for t in thresholds(p) if t > max(forced))
+
+
+def brute_cuts(p, starts_by_bucket, B, R):
+    """First bucket of every range (and B): the equal split, or, with a cut
+    strategy, each cut moved within its window to the bucket that the
+    strategy's score prefers (Sec. 3 "Selecting Cut Points"), computed here
+    from the start slots directly."""
+    first = [rho * B // R for rho in range(R + 1)]
+    if p.cut_strategy == 0 or p.cut_search < 2 or R < 2:
+        return first
+    h = min(p.cut_search // 2, max(0, (B // R - 2) // 2))
+    if h == 0:
+        return first
+    all_starts = sorted(s for bk in starts_by_bucket for s in bk)
+    out = [0]
+
+    def keys_in(lo, hi):  # keys with start slot in [lo, hi)
+        return bisect.bisect_left(all_starts, hi) - bisect.bisect_left(all_starts, lo)
+
+    for rho in range(R - 1):
+        b0 = first[rho + 1] - 1
+        best = None
+        for beta in range(b0 - h, b0 + h + 1):
+            T = forced_threshold(p, starts_by_bucket[beta], beta)
+            bumped = sum(1 for s in starts_by_bucket[beta] if s - beta * p.bucket < T)
+            prev = keys_in(beta * p.bucket - (WIDTH - 1), beta * p.bucket)
+            score = {1: bumped, 2: -prev, 3: bumped - prev}[p.cut_strategy]
+            key = (score, abs(beta - b0), beta)
+            if best is None or key < best[0]:
+                best = (key, beta)
+        out.append(best[1] + 1)
+    out.append(B)
+    return out
+
+
 def final_slots(p: oracle.Params, n: int, a: int) -> int:
     num = n * (p.final_num * 10 + a * p.final_den)
     return WIDTH * max(1, _ceil_div(num, p.final_den * 10 * WIDTH))
@@ -40,8 +92,8 @@ def final_slots(p: oracle.Params, n: int, a: int) -> int:
 
 def brute_layer(keys, vals, layer, p: oracle.Params):
     n = len(keys)
-    m, B, R, first = layer_geometry(p, n)
-    theta = [0, p.t_lo, p.t_hi, p.bucket]
+    m, B, R, _ = layer_geometry(p, n)
+    theta = thresholds(p)
     eq = []
     for k, v in zip(keys, vals):
         s, c = oracle.hash_key(int(k), layer, m, p.seed)
@@ -49,6 +101,7 @@ def brute_layer(keys, vals, layer, p: oracle.Params):
     by_bucket = [[] for _ in range(B)]
     for e in eq:
         by_bucket[e[0] // p.bucket].append(e)
+    first = brute_cuts(p, [[e[0] for e in bk] for bk in by_bucket], B, R)
     range_of = np.searchsorted(first, np.arange(B), side="right") - 1
     kept_rows, kept_rhs = [], []
     codes, bumped = [], []
@@ -57,10 +110,7 @@ def brute_layer(keys, vals, layer, p: oracle.Params):
         rho = int(range_of[beta])
         tf = 0
         if rho < R - 1 and beta == first[rho + 1] - 1:
-            end = first[rho + 1] * p.bucket
-            forced = [e[0] - beta * p.bucket for e in members if e[0] > end - WIDTH]
-            if forced:
-                tf = min(t for t in theta if t > max(forced))
+            tf = forced_threshold(p, [e[0] for e in members], beta)
         T = None
         for t in theta:
             if t < tf:
@@ -70,7 +120,7 @@ def brute_layer(keys, vals, layer, p: oracle.Params):
                 T = t
                 break
         assert T is not None
-        codes.append(theta.index(T))
+        codes.append(T if p.threshold_mode == 1 else theta.index(T))
         for e in members:
             if e[0] - beta * p.bucket >= T:
                 kept_rows.append(e[1])
@@ -79,7 +129,8 @@ def brute_layer(keys, vals, layer, p: oracle.Params):
                 bumped.append(e[3])
     Z = gf2.solve(kept_rows, kept_rhs, m)
     assert Z is not None and gf2.check(kept_rows, kept_rhs, Z)
-    return dict(m=m, B=B, R=R, codes=codes, Z=Z, bumped=bumped)
+    return dict(m=m, B=B, R=R, codes=codes, Z=Z, bumped=bumped,
+                cut_last=[f - 1 for f in first[1:]])
 
 
 def brute_final(keys, vals, p: oracle.Params):
@@ -114,6 +165,20 @@ CASES = [
     (1, 8, dict(ranges=4)),
     # heavily overloaded with r = 1: half of the eliminated rows are redundant
     (800, 1, dict(load_num=60, load_den=100, ranges=2, minbpt=2, seed=3)),
+    # 1+-bit thresholds (any offset 0..b): one range, several, bucket 128, overloaded
+    (1000, 8, dict(ranges=1, threshold_mode=1)),
+    (1200, 5, dict(ranges=4, minbpt=2, threshold_mode=1, seed=21)),
+    (900, 3, dict(bucket=128, t_lo=32, t_hi=64, ranges=3, minbpt=2, threshold_mode=1)),
+    (800, 1, dict(load_num=70, load_den=100, ranges=3, minbpt=2, threshold_mode=1, seed=8)),
+    # searched cut points, each strategy, with both threshold modes
+    (1500, 8, dict(ranges=3, minbpt=2, cut_strategy=1, cut_search=50, seed=31)),
+    (1500, 8, dict(ranges=3, minbpt=2, cut_strategy=2, cut_search=50, seed=32)),
+    (1500, 6, dict(ranges=3, minbpt=2, cut_strategy=3, cut_search=4, seed=33)),
+    (1500, 4, dict(ranges=4, minbpt=2, cut_strategy=2, cut_search=50, threshold_mode=1,
+                   load_num=90, load_den=100, seed=34)),
+    (1400, 7, dict(ranges=3, minbpt=2, cut_strategy=3, cut_search=50, threshold_mode=1,
+                   seed=35)),
+    (2000, 8, dict(ranges=2, minbpt=2, threshold_mode=1, load_num=90, load_den=100, seed=41)),
 ]
 
 
@@ -135,6 +200,7 @@ def test_layers_match_dense_definition(n, r, kw):
         info = ref.layer_info(layer)
         assert (info["m"], info["nbuckets"], info["nranges"]) == (bl["m"], bl["B"], bl["R"])
         assert list(ref.layer_codes(layer)) == bl["codes"]
+        assert [int(c) for c in ref.layer_cuts(layer)] == bl["cut_last"]
         assert [int(z) for z in ref.layer_solution(layer)] == bl["Z"]
         assert info["bumped"] == len(bl["bumped"])
         vmap = dict(zip(cur_k, cur_v))
@@ -262,3 +328,32 @@ def test_gf2_helper_catches_planted_errors():
         dep = rows[0] ^ rows[1]
         assert gf2.consistent(rows + [dep], rhs + [rhs[0] ^ rhs[1]])
         assert not gf2.consistent(rows + [dep], rhs + [rhs[0] ^ rhs[1] ^ 1])
+
+
+CUT_CASES = [
+    (200_000, dict(ranges=2000, minbpt=8, cut_strategy=1, cut_search=50)),
+    (200_000, dict(ranges=2000, minbpt=8, cut_strategy=2, cut_search=50)),
+    (200_000, dict(ranges=1000, minbpt=8, cut_strategy=3, cut_search=50, threshold_mode=1)),
+    (150_000, dict(ranges=500, minbpt=8, cut_strategy=2, cut_search=6, seed=9)),
+    (100_000, dict(ranges=60, minbpt=2, cut_strategy=3, cut_search=50, bucket=128, t_lo=32,
+                   t_hi=64)),
+]
+
+
+@pytest.mark.parametrize("n,kw", CUT_CASES)
+def test_cut_points_match_definition(n, kw):
+    """The cut points alone (they depend only on start slots and forced
+    thresholds), at sizes too large for the dense check: every layer-0 cut
+    of the oracle equals the one the strategy's definition picks."""
+    p = oracle.Params(**kw)
+    keys = W.keys(n, 77 + n % 13)
+    ref = oracle.build(keys, W.values(n, 4, 5), 4, p)
+    m, B, R, first = layer_geometry(p, n)
+    starts = [[] for _ in range(B)]
+    for k in keys.tolist():
+        s, _ = oracle.hash_key(k, 0, m, p.seed)
+        starts[s // p.bucket].append(s)
+    want = [f - 1 for f in brute_cuts(p, starts, B, R)[1:]]
+    got = [int(c) for c in ref.layer_cuts(0)]
+    assert got == want
+    assert sum(a != b for a, b in zip(got, [f - 1 for f in first[1:]])) > R // 4

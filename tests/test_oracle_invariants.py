@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import export_format
 from paper_2411_12365_amd import workload as W
 from tests.test_oracle_bruteforce import layer_geometry
 
@@ -189,43 +190,16 @@ def test_missing_values_need_filter_mode():
         oracle.build(W.keys(10, 1), None, 8, oracle.Params())
 
 
-def _parse_export(buf: bytes, r: int):
-    """Independent reader of the canonical export layout."""
-    off = 0
-
-    def take(fmt):
-        nonlocal off
-        v = struct.unpack_from("<" + fmt, buf, off)
-        off += struct.calcsize("<" + fmt)
-        return v
-
-    (magic,) = take("Q")
-    hdr = take("16I")
-    seed, n = take("2Q")
-    built = hdr[15]
-    layers = []
-    for _ in range(built):
-        ln, lm, lr = take("3Q")
-        B = lm // hdr[2]
-        codes = take(f"{(B + 31) // 32}Q")
-        words = take(f"{(lm // 64) * r}Q")
-        layers.append(dict(n=ln, m=lm, R=lr, codes=codes, words=words))
-    fn, fm, fa = take("3Q")
-    fwords = take(f"{(fm // 64) * r}Q")
-    assert off == len(buf)
-    return magic, hdr, seed, n, layers, dict(n=fn, m=fm, attempt=fa, words=fwords)
-
-
 def test_export_layout_encodes_codes_and_solution():
     r = 5
     keys, vals, ref, p = _build(40_000, r, ranges=8, seed=12)
-    magic, hdr, seed, n, layers, fin = _parse_export(ref.export(), r)
-    assert magic.to_bytes(8, "little") == b"BuRRexp1"
-    assert hdr[:4] == (1, 64, p.bucket, r) and n == 40_000 and seed == p.seed
+    e = export_format.parse(ref.export())
+    hdr, layers, fin = e["header"], e["layers"], e["final"]
+    assert e["magic"].to_bytes(8, "little") == b"BuRRexp1"
+    assert (hdr["version"], hdr["w"], hdr["b"], hdr["r"]) == (2, 64, p.bucket, r)
+    assert hdr["n"] == 40_000 and hdr["seed"] == p.seed and hdr["first_layer"] == 0
     for li, L in enumerate(layers):
-        codes = ref.layer_codes(li)
-        for beta in range(len(codes)):
-            assert (L["codes"][beta // 32] >> (2 * (beta % 32))) & 3 == codes[beta]
+        assert L["codes"] == [int(c) for c in ref.layer_codes(li)]
         Z = ref.layer_solution(li)
         for i in range(0, L["m"], 7):
             for col in range(r):
@@ -235,6 +209,20 @@ def test_export_layout_encodes_codes_and_solution():
     for i in range(fin["m"]):
         for col in range(r):
             assert (fin["words"][(i // 64) * r + col] >> (i % 64)) & 1 == (int(Zf[i]) >> col) & 1
+
+
+def test_export_layout_of_one_plus_bit_thresholds_and_cuts():
+    r = 3
+    keys, vals, ref, p = _build(30_000, r, ranges=16, minbpt=8, seed=13, threshold_mode=1,
+                                cut_strategy=2, cut_search=6)
+    e = export_format.parse(ref.export())
+    assert (e["header"]["threshold_mode"], e["header"]["cut_strategy"],
+            e["header"]["cut_search"]) == (1, 2, 6)
+    for li, L in enumerate(e["layers"]):
+        assert L["thresholds"] == [int(c) for c in ref.layer_codes(li)]
+        assert L["K"] == sum(1 for c in ref.layer_codes(li) if c)
+        assert L["cuts"] == [int(c) for c in ref.layer_cuts(li)[:-1]]
+    assert (ref.query(keys) == vals).all()
 
 
 def test_config_geometry_examples():
@@ -253,6 +241,7 @@ def test_config_geometry_examples():
     (20_000, 1, 0, dict(ranges=9, minbpt=3, filter_mode=1, seed=4)),
     (24_000, 16, 0, dict(ranges=6, bucket=128, t_lo=32, t_hi=64)),
     (3_000, 5, 0, dict(ranges=1)),
+    (30_000, 8, 0, dict(ranges=16, threshold_mode=1)),
 ])
 def test_range_entry_point_matches_whole_build(n, r, layer, kw):
     # The one-range entry point (used for sampled checks of very large
@@ -262,7 +251,7 @@ def test_range_entry_point_matches_whole_build(n, r, layer, kw):
     keys = W.keys(n, 21)
     vals = W.values(n, r, 1021)
     ref = oracle.build(keys, None if p.filter_mode else vals, r, p)
-    magic, hdr, seed, nn, layers, fin = _parse_export(ref.export(), r)
+    layers = export_format.parse(ref.export())["layers"]
     lk = ref.layer_keys(layer)
     n_layer = len(lk)
     m, B, R, first = layer_geometry(p, n_layer)

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 MUTANTS = {
     "chunks_low_to_high": ("for (unsigned k = 3; k > kf; k--) {",
                            "for (unsigned k = kf + 1; k <= 3; k++) {"),
-    "bump_high_offsets": ("if (o < theta[code]) {", "if (o >= theta[code] && code) {"),
+    "bump_high_offsets": ("if (o < T) {", "if (o >= T && T) {"),
     "forced_off_by_one": ("if (s + REF_W > range_end) {", "if (s + REF_W > range_end + 1) {"),
     "backsub_index": ("z ^= Z[i + j];", "z ^= Z[i + j - 1];"),
     "mixer_constant": ("k *= 0xc4ceb9fe1a85ec53ULL;", "k *= 0xc4ceb9fe1a85ec55ULL;"),
@@ -28,11 +28,11 @@ MUTANTS = {
     "final_scale": ("(uint64_t)a * p->final_den", "(uint64_t)a * p->final_den * 0"),
     "row_not_anchored": ("*coeff = ref_fmix64(key ^ salt_c) | 1ull;",
                          "*coeff = ref_fmix64(key ^ salt_c) | 2ull;"),
-    "code_shifted": ("code = k;\n        break;", "code = k - 1;\n        break;"),
+    "code_shifted": ("code = k;\n          break;", "code = k - 1;\n          break;"),
     "redundant_is_conflict": ("return v == 0 ? INS_REDUNDANT : INS_CONFLICT;",
                               "return INS_CONFLICT;"),
-    "query_threshold": ("if (o < theta[L->code[beta]]) continue;",
-                        "if (o <= theta[L->code[beta]]) continue;"),
+    "query_threshold": ("if (o < ref_theta(p, L->code[beta])) continue;",
+                        "if (o <= ref_theta(p, L->code[beta])) continue;"),
     "layer_salt": ("uint64_t salt_s = ref_fmix64(seed ^ (2ull * layer + 1ull));",
                    "uint64_t salt_s = ref_fmix64(seed ^ (2ull * layer + 2ull));"),
     "range_split": ("return (uint64_t)(((unsigned __int128)rho * B) / R);",
@@ -47,6 +47,20 @@ MUTANTS = {
                       "  uint64_t salt_c = ref_fmix64(seed ^ (2ull * layer + 1ull));"),
     "fingerprint_salt": ("uint64_t h = ref_fmix64(key ^ ref_fmix64(~seed));",
                          "uint64_t h = ref_fmix64(key ^ ref_fmix64(seed));"),
+    "one_plus_threshold_low": ("code = (unsigned)(o + 1);", "code = (unsigned)o;"),
+    "one_plus_undo_earlier_groups": ("          nplaced = 0; /* earlier groups are final */\n", ""),
+    "one_plus_forced": ("if (p->threshold_mode == 1) return (unsigned)(omax + 1);",
+                        "if (p->threshold_mode == 1) return (unsigned)(omax + 2);"),
+    "cut_prev_window": ("if (order[t].s + (REF_W - 1) < beta * b) break;",
+                        "if (order[t].s + REF_W < beta * b) break;"),
+    "cut_tie_break": ("(score == best && dist < best_dist)", "(score == best && dist <= best_dist)"),
+    "cut_window": ("const uint64_t hmax = L >= 2 ? (L - 2) / 2 : 0;",
+                   "const uint64_t hmax = L >= 2 ? (L - 1) / 2 : 0;"),
+    "cut_maxprev_sign": ("p->cut_strategy == 2 ? -prev", "p->cut_strategy == 2 ? prev"),
+    "parallel_backsub_short": ("ref_back_substitute(M->C + base, M->V + base, M->Z + base, len);",
+                               "ref_back_substitute(M->C + base, M->V + base, M->Z + base, len - 64);"),
+    "parallel_part_of_slot": ("return (uint64_t)(((unsigned __int128)(s / M->p->bucket) * M->T) / M->B);",
+                              "return (uint64_t)(((unsigned __int128)(s / M->p->bucket) * M->T) / M->B) % 2;"),
     "load_rounding": ("uint64_t nb = (uint64_t)((num + den - 1) / den);\n  if (nb < 1) nb = 1;\n  return nb * b;",
                       "uint64_t nb = (uint64_t)(num / den);\n  if (nb < 1) nb = 1;\n  return nb * b;"),
 }
@@ -67,8 +81,13 @@ def run(name, fn, *a):
         fn(*a)
     except Exception as e:
         failed.append(name)
-for case in bf.CASES[:5] + bf.CASES[7:8] + bf.CASES[-1:]:
+for case in bf.CASES[:5] + bf.CASES[7:8] + bf.CASES[12:]:
     run("brute%r" % (case[:2],), bf.test_layers_match_dense_definition, *case)
+for case in bf.CUT_CASES[1:2] + bf.CUT_CASES[3:4]:
+    run("cuts%r" % (case[0],), bf.test_cut_points_match_definition, *case)
+from tests import test_oracle_parallel as tp
+for case in (tp.CASES[0], tp.CASES[3], tp.CASES[4]):
+    run("parallel%r" % (case[:2],), tp.test_parallel_driver_equals_sequential, *case, 3)
 run("edge", bf.test_boundary_edge_case)
 run("dups", bf.test_equal_duplicates_are_redundant_equations)
 run("indep", th.test_start_and_row_are_independent)
