@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define BURR_ABI_VERSION 1u
+#define BURR_ABI_VERSION 2u
 
 enum {
   BURR_OK = 0,
@@ -84,7 +84,30 @@ typedef struct burr_params {
   burr_alloc_fn alloc;     /* device workspace allocator; NULL = HIP pool */
   burr_free_fn free;
   void* alloc_ctx;
+  uint32_t threshold_mode; /* BURR_THRESH_*: how bump thresholds are stored (Sec. 2) */
+  uint32_t cut_strategy;   /* BURR_CUT_*: where ranges end (Sec. 3 "Selecting Cut
+                              Points"); with a strategy other than EQUAL, each range
+                              end is chosen among the cut_search buckets around the
+                              equal split's (at most half a range away on either
+                              side), by the bucket headers of the sorted keys */
+  uint32_t cut_search;     /* buckets searched per cut (the paper uses 50) */
+  uint32_t reserved;       /* 0 */
 } burr_params;
+
+/* threshold_mode: 2-bit thresholds (four values {0, t_lo, t_hi, b} per
+ * bucket), or 1+-bit thresholds (one bit per bucket; the exact threshold,
+ * any offset, stored only for buckets that bump, found through a rank
+ * directory of the bits) (Sec. 2). */
+#define BURR_THRESH_2BIT 0u
+#define BURR_THRESH_1PLUS 1u
+/* cut_strategy (Sec. 3): EQUAL splits the buckets evenly; MINBUMP ends a
+ * range at the bucket whose forced bumping bumps the fewest keys; MAXPREV at
+ * the bucket with the most keys starting in the w-1 slots before it (keys
+ * that can fill the gap); DIFF at the smallest difference of the two. */
+#define BURR_CUT_EQUAL 0u
+#define BURR_CUT_MINBUMP 1u
+#define BURR_CUT_MAXPREV 2u
+#define BURR_CUT_DIFF 3u
 
 typedef struct burr_handle burr_handle;
 typedef struct burr_batch burr_batch;
@@ -248,9 +271,12 @@ const burr_handle* burr_batch_member(const burr_batch* b, uint32_t i);
 /* Frees a batch and every member's tables. */
 void burr_batch_free(burr_batch* b);
 
-/* Canonical little-endian serialisation (layout in the library's export
- * code): header, then per BuRR layer n, m, ranges, packed 2-bit codes and
- * column-interleaved solution words, then the final layer. Copies to host
+/* Canonical little-endian serialisation, version 2 (layout in the library's
+ * export code): header (parameters, r, layers built, threshold mode, cut
+ * strategy), then per BuRR layer n, m, ranges, the thresholds (packed 2-bit
+ * codes, or 1+-bit bit words, count and threshold bytes), the
+ * column-interleaved solution words and, with a cut strategy, the last
+ * bucket of every range but the last; then the final layer. Copies to host
  * memory; *needed receives the size (pass host_buf = NULL to query it). */
 int burr_export(const burr_handle* h, void* host_buf, size_t cap, size_t* needed);
 

@@ -26,7 +26,13 @@ BURR_REQ_BUILD = 1
 BURR_REQ_QUERY = 2
 BURR_FLAG_KEEP_LAYER_KEYS = 1
 BURR_FLAG_NO_WORKSPACE_CACHE = 2
-ABI_VERSION = 1
+ABI_VERSION = 2
+BURR_THRESH_2BIT = 0
+BURR_THRESH_1PLUS = 1
+BURR_CUT_EQUAL = 0
+BURR_CUT_MINBUMP = 1
+BURR_CUT_MAXPREV = 2
+BURR_CUT_DIFF = 3
 
 _EXPORTS = ("burr_default_params", "burr_build", "burr_query", "burr_contains", "burr_free",
             "burr_get_stats", "burr_export", "burr_import", "burr_debug_layer_keys",
@@ -56,6 +62,8 @@ class _CParams(ctypes.Structure):
         ("final_attempts", ctypes.c_uint32), ("filter_mode", ctypes.c_uint32),
         ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p),
         ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p), ("alloc_ctx", ctypes.c_void_p),
+        ("threshold_mode", ctypes.c_uint32), ("cut_strategy", ctypes.c_uint32),
+        ("cut_search", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -117,6 +125,9 @@ class Params:
     filter_mode: int = 0
     flags: int = 0
     seed: int = 0
+    threshold_mode: int = 0   # BURR_THRESH_2BIT / BURR_THRESH_1PLUS
+    cut_strategy: int = 0     # BURR_CUT_EQUAL / MINBUMP / MAXPREV / DIFF
+    cut_search: int = 0       # buckets searched per cut
 
     def c(self, stream: int | None = None, allocator: "TorchAllocator | None" = None) -> _CParams:
         cp = _CParams(abi_version=ABI_VERSION, stream=stream, alloc=None, free=None,

@@ -35,7 +35,7 @@ int set_error(int code) {
 }
 
 constexpr uint64_t kExportMagic = 0x3170786552527542ull;  // "BuRRexp1"
-constexpr uint32_t kExportVersion = 1;
+constexpr uint32_t kExportVersion = 2;
 constexpr uint32_t kMaxLayers = 32;
 constexpr uint64_t kFinalSegBuckets = 4;  // final layer: buckets per segment
 // item indices (one per key plus one per bucket) are 32-bit
@@ -81,10 +81,14 @@ void keep_pool_memory(int dev) {
 // Host copy of a layer's per-structure table (see LayerGeom).
 struct Table {
   std::vector<uint64_t> key_off{0}, span, bucket_base{0}, range_base{0}, word_base{0},
-      code_base{0};
+      code_base{0}, thr_base{0}, rank_base{0};
   std::vector<uint32_t> rbits;
+  uint32_t thr_mode = 0;  // 1: 1+-bit thresholds (bit words, bytes, rank directory)
+  // threshold words of a structure with B buckets: 2-bit codes or 1+-bit bits
+  uint64_t code_words(uint64_t B) const { return thr_mode ? (B + 63) / 64 : (B + 31) / 32; }
   void reserve(size_t J) {
-    for (auto* v : {&key_off, &span, &bucket_base, &range_base, &word_base, &code_base})
+    for (auto* v : {&key_off, &span, &bucket_base, &range_base, &word_base, &code_base,
+                    &thr_base, &rank_base})
       v->reserve(J + 1);
     rbits.reserve(J);
   }
@@ -98,8 +102,10 @@ struct Table {
     range_base.resize(J + 1);
     word_base.resize(J + 1);
     code_base.resize(J + 1);
+    thr_base.resize(J + 1);
+    rank_base.resize(J + 1);
     rbits.resize(J);
-    uint64_t ko = 0, bb = 0, rb = 0, wb = 0, cb = 0;
+    uint64_t ko = 0, bb = 0, rb = 0, wb = 0, cb = 0, tb = 0, kb = 0;
     for (size_t i = 0; i < J; ++i) {
       uint64_t n, m, R;
       uint32_t r;
@@ -111,18 +117,24 @@ struct Table {
       range_base[i] = rb;
       word_base[i] = wb;
       code_base[i] = cb;
+      thr_base[i] = tb;
+      rank_base[i] = kb;
       rbits[i] = r;
       ko += n;
       bb += B;
       rb += R;
       wb += B * r;
-      cb += (B + 31) / 32;
+      cb += code_words(B);
+      tb += B;
+      kb += (code_words(B) + 7) / 8;
     }
     key_off[J] = ko;
     bucket_base[J] = bb;
     range_base[J] = rb;
     word_base[J] = wb;
     code_base[J] = cb;
+    thr_base[J] = tb;
+    rank_base[J] = kb;
   }
   // next structure: n keys, m slots, R ranges (final layer: segments), r value bits
   void add(uint64_t n, uint64_t m, uint64_t R, uint32_t r) {
@@ -132,7 +144,9 @@ struct Table {
     bucket_base.push_back(bucket_base.back() + B);
     range_base.push_back(range_base.back() + R);
     word_base.push_back(word_base.back() + B * r);
-    code_base.push_back(code_base.back() + (B + 31) / 32);
+    code_base.push_back(code_base.back() + code_words(B));
+    thr_base.push_back(thr_base.back() + B);
+    rank_base.push_back(rank_base.back() + (code_words(B) + 7) / 8);
     rbits.push_back(r);
   }
   uint32_t J() const { return (uint32_t)rbits.size(); }
@@ -141,17 +155,25 @@ struct Table {
 // one layer of one member, as derived from its layer's table
 struct MemberLayer {
   uint64_t n = 0, m = 0, R = 0, bumped = 0;
-  uint64_t code_off = 0, ncode = 0;  // words of the layer's shared code array
+  uint64_t code_off = 0, ncode = 0;  // words of the layer's shared code (1+-bit: bit) array
   uint64_t word_off = 0, nW = 0;     // words of the layer's shared solution array
   uint64_t key_off = 0;              // debug: first key in the layer's kept key array
+  uint64_t thr_off = 0, K = 0;       // 1+-bit: first threshold byte, thresholds
+  uint64_t rank_off = 0, nrank = 0;  // 1+-bit: rank directory entries
+  uint64_t range_off = 0;            // first global range (cut points)
 };
 
 // storage shared by all members of a batch for one layer, and the geometry
 // of the members with keys in it: ids ascending, entry k of the table and of
 // `bumped` (keys passed to the next layer) belongs to member ids[k]
 struct LayerStore {
-  uint64_t* codes = nullptr;
+  uint64_t* codes = nullptr;  // 2-bit code words, or 1+-bit bit words
   uint64_t* W = nullptr;
+  uint8_t* thr = nullptr;     // 1+-bit: thresholds - 1 (table.thr_base per structure)
+  uint32_t* rank = nullptr;   // 1+-bit: rank directory (table.rank_base per structure)
+  uint32_t* kcount = nullptr; // 1+-bit: thresholds per structure (device)
+  std::vector<uint32_t> kthr; // the same on the host, after the build
+  uint32_t* rfirst = nullptr; // with a cut strategy: first bucket of every range (+1)
   uint64_t* keys = nullptr;  // kept input keys (debug flag)
   uint64_t steps = 0;
   double ms_sort = 0, ms_solve = 0, ms_backsub = 0, ms_gather = 0;
@@ -235,6 +257,11 @@ MemberLayer layer_of(const burr_batch* b, uint32_t idx, uint32_t l) {
   L.word_off = t.word_base[k];
   L.nW = t.word_base[k + 1] - t.word_base[k];
   L.key_off = t.key_off[k];
+  L.thr_off = t.thr_base[k];
+  L.K = k < LS.kthr.size() ? LS.kthr[k] : 0;
+  L.rank_off = t.rank_base[k];
+  L.nrank = t.rank_base[k + 1] - t.rank_base[k];
+  L.range_off = t.range_base[k];
   return L;
 }
 
@@ -246,6 +273,7 @@ bool params_ok(const burr_params* p) {
   if (p->final_num < p->final_den) return false;
   if (p->layers > kMaxLayers - 1) return false;
   if (!p->ranges || !p->final_attempts) return false;
+  if (p->threshold_mode > 1 || p->cut_strategy > 3) return false;
   return true;
 }
 
@@ -363,6 +391,8 @@ struct Workspace {
   std::vector<hipEvent_t> evs;  // a build's timing and ordering events, kept for the next
   uint8_t* code8 = nullptr;
   uint32_t *bump = nullptr, *bstart = nullptr, *scan_tmp = nullptr;
+  uint32_t* pcount = nullptr;  // 1+-bit thresholds: popcounts of the bit words, scanned
+  uint64_t cap_pc = 0;
   uint32_t* fail = nullptr;  // per structure
   uint32_t* soff = nullptr;  // per structure: first bumped key
   uint64_t* steps = nullptr;
@@ -530,6 +560,11 @@ struct Workspace {
     return reserve_scan(std::max(c1, c2) + 1);
   }
   bool reserve_structs(uint64_t J) { return reserve_results(J); }
+  bool reserve_pcount(uint64_t words) {
+    if (words <= cap_pc && pcount) return reserve_scan(words + 1);
+    cap_pc = words;
+    return alloc(pcount, words + 1) && reserve_scan(words + 1);
+  }
   bool reserve_table(uint64_t words, int set) {
     if (words <= cap_tab[set] && tab[set]) return true;
     cap_tab[set] = words;
@@ -561,7 +596,7 @@ void print_diag(const uint64_t* d) {
 // side stream while the next layer uploads its own into the other buffer.
 int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s, int set) {
   const uint64_t J = t.J();
-  const uint64_t words = 6 * (J + 1) + (J + 1) / 2 + 1;
+  const uint64_t words = 8 * (J + 1) + (J + 1) / 2 + 1;
   if (!ws.reserve_table(words, set) || !ws.reserve_host(words * 8)) return set_error(BURR_E_NOMEM);
   uint64_t* const tab = ws.tab[set];
   // the pinned staging is reused only after the stream has passed this copy
@@ -574,7 +609,9 @@ int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s, int
   memcpy(h + 3 * (J + 1), t.range_base.data(), (J + 1) * 8);
   memcpy(h + 4 * (J + 1), t.word_base.data(), (J + 1) * 8);
   memcpy(h + 5 * (J + 1), t.code_base.data(), (J + 1) * 8);
-  memcpy(h + 6 * (J + 1), t.rbits.data(), J * 4);
+  memcpy(h + 6 * (J + 1), t.thr_base.data(), (J + 1) * 8);
+  memcpy(h + 7 * (J + 1), t.rank_base.data(), (J + 1) * 8);
+  memcpy(h + 8 * (J + 1), t.rbits.data(), J * 4);
   HIP_TRY(hipMemcpyAsync(tab, h, words * 8, hipMemcpyHostToDevice, s));
   g.key_off = tab;
   g.span = tab + (J + 1);
@@ -582,7 +619,9 @@ int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s, int
   g.range_base = tab + 3 * (J + 1);
   g.word_base = tab + 4 * (J + 1);
   g.code_base = tab + 5 * (J + 1);
-  g.rbits = (const uint32_t*)(tab + 6 * (J + 1));
+  g.thr_base = tab + 6 * (J + 1);
+  g.rank_base = tab + 7 * (J + 1);
+  g.rbits = (const uint32_t*)(tab + 8 * (J + 1));
   g.J = (uint32_t)J;
   g.nkeys = t.key_off.back();
   g.nbuckets = t.bucket_base.back();
@@ -785,7 +824,11 @@ uint64_t batch_table_estimate(const burr_batch* b, const std::vector<uint64_t>& 
     if (!n) continue;
     uint64_t m, R;
     plan_layer(b->p, n, &m, &R);
-    words += (m / 64) * b->members[i].r + (m / 64 + 31) / 32;
+    const uint64_t B = m / 64;
+    words += B * b->members[i].r + (B + 31) / 32;
+    // 1+-bit: thresholds (a byte per bucket at most), rank directory, count
+    if (b->p.threshold_mode == 1) words += B / 8 + (B + 63) / 64 / 16 + 3;
+    if (b->p.cut_strategy) words += R / 2 + 1;  // cut points
   }
   return words * 8 * 116 / 100 + 4096ull * (b->p.layers + 2);
 }
@@ -908,6 +951,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     const int set = (int)(li & 1);
     take_host(LS, active.size());
     Table t = std::move(LS.t);
+    t.thr_mode = p.threshold_mode;
     t.fill(active.size(), [&](size_t a, uint64_t* n, uint64_t* m, uint64_t* R, uint32_t* r) {
       const Member& mb = b->members[active[a]];
       *n = cur_n[a];
@@ -920,6 +964,10 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     g.t_lo = p.t_lo;
     g.t_hi = p.t_hi;
     g.plain = 0;
+    g.thr_mode = p.threshold_mode;
+    g.cut_strategy = p.cut_strategy;
+    g.cut_search = p.cut_search;
+    const bool cuts = p.cut_strategy != 0;
     HOST_LAP(hc, "table", li);
     // this table buffer and row set were last read by layer li-2's
     // back-substitution (side stream)
@@ -931,6 +979,17 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     LS.codes = (uint64_t*)b->alloc_table(t.code_base.back() * 8);
     LS.W = (uint64_t*)b->alloc_table(t.word_base.back() * 8);
     if (!LS.codes || !LS.W) return set_error(BURR_E_NOMEM);
+    if (p.threshold_mode == 1) {
+      LS.thr = (uint8_t*)b->alloc_table(t.thr_base.back());
+      LS.rank = (uint32_t*)b->alloc_table(t.rank_base.back() * 4);
+      LS.kcount = (uint32_t*)b->alloc_table(g.J * 4);
+      if (!LS.thr || !LS.rank || !LS.kcount || !ws.reserve_pcount(t.code_base.back()))
+        return set_error(BURR_E_NOMEM);
+    }
+    if (cuts) {
+      LS.rfirst = (uint32_t*)b->alloc_table((g.nranges + 1) * 4);
+      if (!LS.rfirst) return set_error(BURR_E_NOMEM);
+    }
     HOST_LAP(hc, "upload", li);
     if (p.flags & BURR_FLAG_KEEP_LAYER_KEYS) {
       LS.keys = (uint64_t*)b->alloc(g.nkeys * 8);
@@ -940,6 +999,10 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     HIP_TRY(hipEventRecord(el[0], s));
     rc = run_sort(ws, cur_keys, cur_vals, cur_vbytes, first, p.filter_mode != 0, fp_salt, g, s);
     if (rc != BURR_OK) return rc;
+    if (cuts) {  // range ends chosen from the sorted buckets (kept with the tables)
+      HIP_TRY(choose_cuts(ws.rec, ws.bstart, g, LS.rfirst, s));
+      g.rfirst = LS.rfirst;
+    }
 
     SolveArgs sa{};
     sa.rec = ws.rec;
@@ -965,7 +1028,11 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     HIP_TRY(back_substitute(ws.rowsC[set], ws.rowsV[set], g, LS.W, side));
     HIP_TRY(hipEventRecord(el[4], side));
     // codes now: the next layer's insertion rewrites code8
-    HIP_TRY(pack_codes(ws.code8, g, t.code_base.back(), LS.codes, s));
+    if (p.threshold_mode == 1)
+      HIP_TRY(pack_thresholds(ws.code8, g, t.code_base.back(), LS.codes, ws.pcount, ws.scan_tmp,
+                              LS.thr, LS.rank, LS.kcount, s));
+    else
+      HIP_TRY(pack_codes(ws.code8, g, t.code_base.back(), LS.codes, s));
 
     // per-structure bump counts (an exclusive scan of the per-bucket counts)
     // go to the host first: they are all the next layer's planning needs, so
@@ -1076,6 +1143,11 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     LS.ms_solve = elapsed_ms(el[1], el[2]);
     LS.ms_backsub = elapsed_ms(el[3], el[4]);
     LS.ms_gather = elapsed_ms(el[2], el[6]);
+    LS.kthr.clear();
+    if (LS.kcount) {  // thresholds kept per structure (1+-bit)
+      LS.kthr.resize(LS.t.J());
+      HIP_TRY(hipMemcpy(LS.kthr.data(), LS.kcount, LS.kthr.size() * 4, hipMemcpyDeviceToHost));
+    }
   }
   b->ms_final = elapsed_ms(evfin[0], evfin[1]);
   b->ms_total = elapsed_ms(ev[0], evfin[1]);
@@ -1154,6 +1226,11 @@ QueryPlan make_plan(const burr_batch* b, const Member& mb) {
     q.t_hi = b->p.t_hi;
     q.plain = 0;
     q.empty = 0;
+    q.thr_mode = b->p.threshold_mode;
+    if (q.thr_mode == 1) {
+      q.rank = b->layers[l].rank + L.rank_off;
+      q.thr = b->layers[l].thr + L.thr_off;
+    }
   }
   QueryLayer& f = plan.layer[l];
   f.salt_s = mix64(b->p.seed ^ (2ull * b->p.layers + 1ull));
@@ -1221,7 +1298,14 @@ uint64_t estimate_table(uint64_t n, uint32_t r, const burr_params& p, uint64_t* 
     uint64_t m, R;
     plan_layer(p, cur, &m, &R);
     const uint64_t B = m / 64;
-    bytes += align256((B + 31) / 32 * 8) + align256(B * r * 8);
+    if (p.threshold_mode == 1) {  // bit words, threshold bytes, rank directory, count
+      const uint64_t bw = (B + 63) / 64;
+      bytes += align256(bw * 8) + align256(B) + align256((bw + 7) / 8 * 4) + align256(4);
+    } else {
+      bytes += align256((B + 31) / 32 * 8);
+    }
+    if (p.cut_strategy) bytes += align256((R + 1) * 4);
+    bytes += align256(B * r * 8);
     cur = (uint64_t)((double)cur * kBumpBound) + (cur > 0 ? 1 : 0);
   }
   if (n_final) *n_final = cur;
@@ -1236,8 +1320,12 @@ uint64_t burr_batch_device_bytes(const burr_batch* b) { return b ? b->table_byte
 uint64_t burr_batch_table_bits(const burr_batch* b) {
   if (!b) return 0;
   uint64_t words = 0;
-  for (const LayerStore& LS : b->layers)
-    if (!LS.ids.empty()) words += LS.t.code_base.back() + LS.t.word_base.back();
+  for (const LayerStore& LS : b->layers) {
+    if (LS.ids.empty()) continue;
+    words += LS.t.code_base.back() + LS.t.word_base.back();
+    for (uint32_t k : LS.kthr) words += 1 + (k + 7) / 8;  // 1+-bit thresholds
+    if (!LS.kthr.empty()) words += (LS.t.rank_base.back() + 1) / 2;
+  }
   for (const Member& mb : b->members) words += mb.fin.nW;
   return words * 64;
 }
@@ -1570,6 +1658,7 @@ int burr_get_stats(const burr_handle* h, burr_stats* st) {
     ms_sort += LS.ms_sort;
     ms_solve += LS.ms_solve + LS.ms_backsub;
     bytes += (L.ncode + L.nW) * 8;
+    if (b->p.threshold_mode == 1) bytes += (1 + (L.K + 7) / 8) * 8 + L.nrank * 4;
   }
   st->final_n = mb->fin.n;
   st->final_m = mb->fin.m;
@@ -1590,10 +1679,11 @@ int burr_export(const burr_handle* h, void* host_buf, size_t cap, size_t* needed
   const burr_params& p = b->p;
   const uint32_t mb_minbpt = mb->minbpt ? mb->minbpt : p.minbpt;
   o.put(kExportMagic, 8);
-  const uint32_t hdr[16] = {kExportVersion, kWidth,      p.bucket,    mb->r,    p.load_num,
-                            p.load_den,     p.final_num, p.final_den, p.layers, p.t_lo,
-                            p.t_hi,         p.ranges,    mb_minbpt,   p.final_attempts,
-                            p.filter_mode,  mb->built};
+  const uint32_t hdr[20] = {kExportVersion,   kWidth,         p.bucket,       mb->r,
+                            p.load_num,       p.load_den,     p.final_num,    p.final_den,
+                            p.layers,         p.t_lo,         p.t_hi,         p.ranges,
+                            mb_minbpt,        p.final_attempts, p.filter_mode, mb->built,
+                            p.threshold_mode, p.cut_strategy, p.cut_search,   0u};
   for (uint32_t x : hdr) o.put(x, 4);
   o.put(p.seed, 8);
   o.put(mb->n, 8);
@@ -1609,13 +1699,36 @@ int burr_export(const burr_handle* h, void* host_buf, size_t cap, size_t* needed
     o.put(L.n, 8);
     o.put(L.m, 8);
     o.put(L.R, 8);
+    const LayerStore& LS = b->layers[l];
+    const bool one_plus = p.threshold_mode == 1;
+    const bool cuts = p.cut_strategy != 0;
+    const uint64_t thr_words = one_plus ? 1 + (L.K + 7) / 8 : 0;  // K, then the bytes
+    const uint64_t cut_words = cuts ? L.R / 2 : 0;                 // ceil((R-1)/2)
     if (fill) {
-      if (!copy_words(b->layers[l].codes + L.code_off, L.ncode)) return set_error(BURR_E_DEVICE);
+      if (!copy_words(LS.codes + L.code_off, L.ncode)) return set_error(BURR_E_DEVICE);
       o.put_words(tmp);
-      if (!copy_words(b->layers[l].W + L.word_off, L.nW)) return set_error(BURR_E_DEVICE);
+      if (one_plus) {
+        o.put(L.K, 8);
+        std::vector<uint8_t> tb(L.K);
+        if (L.K && hipMemcpy(tb.data(), LS.thr + L.thr_off, L.K, hipMemcpyDeviceToHost) != hipSuccess)
+          return set_error(BURR_E_DEVICE);
+        for (uint8_t x : tb) o.put(x, 1);
+        for (uint64_t k = L.K; k % 8; ++k) o.put(0, 1);
+      }
+      if (!copy_words(LS.W + L.word_off, L.nW)) return set_error(BURR_E_DEVICE);
       o.put_words(tmp);
+      if (cuts) {  // last bucket of ranges 0..R-2, structure-local
+        std::vector<uint32_t> rf(L.R + 1);
+        if (hipMemcpy(rf.data(), LS.rfirst + L.range_off, (L.R + 1) * 4,
+                      hipMemcpyDeviceToHost) != hipSuccess)
+          return set_error(BURR_E_DEVICE);
+        const uint64_t bb = rf[0];
+        uint64_t k = 1;
+        for (; k < L.R; ++k) o.put(rf[k] - bb - 1, 4);
+        for (; (k - 1) % 2; ++k) o.put(0, 4);
+      }
     } else {
-      o.len += (L.ncode + L.nW) * 8;
+      o.len += (L.ncode + thr_words + L.nW + cut_words) * 8;
     }
   }
   o.put(mb->fin.n, 8);
@@ -1646,10 +1759,10 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
     set_error(BURR_E_INVALID);
     return nullptr;
   }
-  uint32_t hdr[16];
+  uint32_t hdr[20];
   for (auto& x : hdr) x = (uint32_t)in.get(4);
   if (!in.ok || hdr[0] != kExportVersion || hdr[1] != kWidth || hdr[2] != kBucket ||
-      hdr[3] < 1 || hdr[3] > 32 || hdr[15] >= kMaxLayers) {
+      hdr[3] < 1 || hdr[3] > 32 || hdr[15] >= kMaxLayers || hdr[19] != 0) {
     set_error(BURR_E_INVALID);
     return nullptr;
   }
@@ -1665,6 +1778,9 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
   def.minbpt = hdr[12];
   def.final_attempts = hdr[13];
   def.filter_mode = hdr[14];
+  def.threshold_mode = hdr[16];
+  def.cut_strategy = hdr[17];
+  def.cut_search = hdr[18];
   def.seed = in.get(8);
   // the imported parameters must be ones a build accepts, and the layer
   // count must fit them
@@ -1711,12 +1827,56 @@ burr_handle* burr_import(const void* host_buf, size_t len, const burr_params* pi
     LayerStore& LS = b->layers[l];
     LS.ids.assign(1, 0);
     LS.t = Table();
+    LS.t.thr_mode = def.threshold_mode;
     LS.t.add(L.n, L.m, L.R, mb.r);
     LS.bumped.assign(1, 0);
     if (l > 0) b->layers[l - 1].bumped[0] = (uint32_t)L.n;  // keys passed on
     L.ncode = LS.t.code_base.back();
     L.nW = LS.t.word_base.back();
-    ok = load_words(L.ncode, &LS.codes) && load_words(L.nW, &LS.W);
+    const uint64_t B = L.m / 64;
+    ok = load_words(L.ncode, &LS.codes);
+    if (ok && def.threshold_mode == 1) {
+      // bit words (already loaded), K, K bytes; the rank directory is
+      // rebuilt here from the bit words
+      std::vector<uint64_t> bits(L.ncode);
+      memcpy(bits.data(), in.buf + in.off - L.ncode * 8, L.ncode * 8);
+      const uint64_t K = in.get(8);
+      uint64_t ones = 0;
+      std::vector<uint32_t> rank(LS.t.rank_base.back());
+      for (uint64_t w = 0; w < L.ncode; ++w) {
+        if (w % 8 == 0) rank[w / 8] = (uint32_t)ones;
+        ones += (uint64_t)__builtin_popcountll(bits[w]);
+      }
+      ok = in.ok && K == ones && K <= B && in.off + (K + 7) / 8 * 8 <= in.len;
+      if (ok) {
+        LS.thr = (uint8_t*)b->alloc_table(B);
+        LS.rank = (uint32_t*)b->alloc_table(rank.size() * 4 + 4);
+        ok = LS.thr && LS.rank &&
+             (K == 0 || hipMemcpy(LS.thr, in.buf + in.off, K, hipMemcpyHostToDevice) == hipSuccess) &&
+             hipMemcpy(LS.rank, rank.data(), rank.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+        in.off += (K + 7) / 8 * 8;
+        LS.kthr.assign(1, (uint32_t)K);
+      }
+    }
+    ok = ok && load_words(L.nW, &LS.W);
+    if (ok && def.cut_strategy != 0) {  // last bucket of ranges 0..R-2, as u32
+      const uint64_t cw = L.R / 2;
+      ok = in.off + cw * 8 <= in.len;
+      std::vector<uint32_t> rf(L.R + 1, 0);
+      for (uint64_t k = 0; ok && k + 1 < L.R; ++k) {
+        uint32_t c;
+        memcpy(&c, in.buf + in.off + 4 * k, 4);
+        rf[k + 1] = c + 1;
+        ok = rf[k + 1] > rf[k] && rf[k + 1] < B;
+      }
+      rf[L.R] = (uint32_t)B;
+      if (ok) {
+        in.off += cw * 8;
+        LS.rfirst = (uint32_t*)b->alloc_table((L.R + 1) * 4);
+        ok = LS.rfirst &&
+             hipMemcpy(LS.rfirst, rf.data(), (L.R + 1) * 4, hipMemcpyHostToDevice) == hipSuccess;
+      }
+    }
   }
   if (ok) {
     mb.fin.n = in.get(8);

@@ -54,6 +54,12 @@ struct SortArgs {
 };
 hipError_t sort_layer(const SortArgs& a, hipStream_t s);
 
+// Cut points of a BuRR layer (g.cut_strategy != 0): rfirst[rho] = first
+// global bucket of global range rho (nranges + 1 entries), from the bucket
+// headers of the sorted item stream.
+hipError_t choose_cuts(const Rec* rec, const uint32_t* bstart, const LayerGeom& g, uint32_t* rfirst,
+                       hipStream_t s);
+
 // Per-range insertion with 2-bit thresholds and boundary bumping: one wave
 // per range, its 64 lanes insert a bucket's records together against a ring
 // of 128 rows in LDS.
@@ -92,6 +98,14 @@ hipError_t back_substitute(const uint64_t* rowsC, const uint32_t* rowsV, const L
 // code8[B] -> packed 2-bit code words of every structure
 hipError_t pack_codes(const uint8_t* code8, const LayerGeom& g, uint64_t ncode_words,
                       uint64_t* words, hipStream_t s);
+
+// 1+-bit thresholds: code8[B] (threshold per bucket, 0 = none) -> bit words
+// (nwords = code_base of the layer), thresholds - 1 as bytes at thr_base[j],
+// rank directory at rank_base[j] (u32 per 8 bit words), thresholds per
+// structure in kcount[J]. pc: nwords + 1 u32 of workspace.
+hipError_t pack_thresholds(const uint8_t* code8, const LayerGeom& g, uint64_t nwords,
+                           uint64_t* bits, uint32_t* pc, uint32_t* scan_tmp, uint8_t* thr,
+                           uint32_t* rank, uint32_t* kcount, hipStream_t s);
 
 // Copy the bumped suffix of every bucket into the next layer's input.
 hipError_t gather_bumped(const Rec* rec, const uint32_t* bstart,

@@ -526,50 +526,49 @@ __global__ void k_p2_starts(SortPlan sp, uint64_t nkeys, const uint32_t* __restr
   sstart[t] = nch[b] ? offs[cbase[b] * sp.S + s * nch[b]] : binlo[b];
 }
 
-// Forced threshold index of global bucket beta: the last bucket of a range
-// that is not its structure's last range must bump every key that starts
-// past its first slot (b = w = 64), so its threshold is the smallest 2-bit
-// value above the largest offset of such a key (Sec. 3 "Bumping").
-__device__ inline uint32_t forced_kf(uint64_t beta, uint32_t maxoff, uint32_t count,
-                                     const LayerGeom& g) {
-  if (g.plain || count == 0 || maxoff == 0) return 0;
-  const uint32_t j = find_struct(g.bucket_base, g.J, beta);
-  const uint64_t B = g.bucket_base[j + 1] - g.bucket_base[j];
-  const uint64_t R = g.range_base[j + 1] - g.range_base[j];
-  const uint64_t b = beta - g.bucket_base[j];
-  const uint64_t rho = ((b + 1) * R - 1) / B;
-  if (rho + 1 >= R) return 0;
-  if ((rho + 1) * B / R != b + 1) return 0;
-  return maxoff >= g.t_hi ? 3u : (maxoff >= g.t_lo ? 2u : 1u);
-}
-
 // Level 3: one workgroup per sub-bin. The item stream holds, per bucket, a
-// header and its records ordered by chunk (rank); the sub-bin's items form
-// one contiguous block starting at item sstart[g] + 64 g.
+// header and its records ordered by digit - the chunk (2-bit thresholds,
+// final layer) or the offset, highest first (1+-bit thresholds); the
+// sub-bin's items form one contiguous block starting at item sstart[g] + 64 g.
+// The header carries the bucket's record count, its largest offset and its
+// number of records at offset 0: the insertion kernel derives the threshold
+// forced on a range's last bucket from them, and the cut-point search its
+// scores.
+// Dynamic LDS: the staged block (kL3Cap items), then the digit counters.
+__host__ __device__ constexpr size_t l3_lds_bytes(uint32_t D) {
+  return (size_t)kL3Cap * sizeof(uint4) + ((size_t)kSubBuckets * D + 1) * 4;
+}
 __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict__ in,
                                                         LayerGeom g, SortPlan sp,
                                                         const uint32_t* __restrict__ sstart,
                                                         Rec* __restrict__ items,
                                                         uint32_t* __restrict__ bstart) {
-  __shared__ uint32_t dcur[3 * kSubBuckets + 1];
   __shared__ uint32_t maxoff[kSubBuckets];
+  __shared__ uint32_t nzero[kSubBuckets];
   __shared__ uint32_t wsum[kL3Threads / 64 + 2];
-  extern __shared__ uint4 stage[];  // kL3Cap items
+  extern __shared__ uint4 stage[];  // kL3Cap items, then the digit counters
+  const uint32_t D = digits_per_bucket(g);
+  uint32_t* dcur = reinterpret_cast<uint32_t*>(stage + kL3Cap);
+  const uint32_t nd = kSubBuckets * D;
   const uint32_t sb = blockIdx.x;
   const uint32_t lo = sstart[sb], hi = sstart[sb + 1], n = hi - lo;
   const uint64_t beta0 = (uint64_t)sb * kSubBuckets;
   const uint32_t nbk = (uint32_t)(g.nbuckets - beta0 < kSubBuckets ? g.nbuckets - beta0 : kSubBuckets);
   const uint32_t sub_in_bin = sb % sp.S;
   const uint32_t slot0 = sub_in_bin * kSubSlots;
-  for (uint32_t i = threadIdx.x; i < 3 * kSubBuckets; i += kL3Threads) dcur[i] = 0;
-  for (uint32_t i = threadIdx.x; i < kSubBuckets; i += kL3Threads) maxoff[i] = 0;
+  auto digit = [&](uint32_t o) { return D == 3 ? rank_of(o, g) : 63u - o; };
+  for (uint32_t i = threadIdx.x; i < nd; i += kL3Threads) dcur[i] = 0;
+  for (uint32_t i = threadIdx.x; i < kSubBuckets; i += kL3Threads) {
+    maxoff[i] = 0;
+    nzero[i] = 0;
+  }
   __syncthreads();
   // the block is assembled in LDS when it fits; then every record is read
   // once, into registers, and its rank inside its digit comes from the
   // counting atomic
   const bool fits = n + nbk <= kL3Cap;
   uint4 rec[kL3Per];
-  uint32_t dr[kL3Per];  // digit | rank << 8
+  uint32_t dr[kL3Per];  // digit | rank << 12
   if (fits) {
 #pragma unroll
     for (int k = 0; k < kL3Per; ++k) {  // loads first, then the counting atomics
@@ -583,39 +582,55 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict_
       if (i < hi) {
         const uint32_t sl = rec[k].w - slot0;
         const uint32_t bl = sl >> 6, o = sl & 63u;
-        const uint32_t d = bl * 3 + rank_of(o, g);
-        dr[k] = d | (atomicAdd(&dcur[d], 1u) << 8);
+        const uint32_t d = bl * D + digit(o);
+        dr[k] = d | (atomicAdd(&dcur[d], 1u) << 12);
         atomicMax(&maxoff[bl], o);
+        if (o == 0) atomicAdd(&nzero[bl], 1u);
       }
     }
   } else {
     for (uint32_t i = lo + threadIdx.x; i < hi; i += kL3Threads) {
       const uint32_t sl = in[i].w - slot0;
       const uint32_t bl = sl >> 6, o = sl & 63u;
-      atomicAdd(&dcur[bl * 3 + rank_of(o, g)], 1u);
+      atomicAdd(&dcur[bl * D + digit(o)], 1u);
       atomicMax(&maxoff[bl], o);
+      if (o == 0) atomicAdd(&nzero[bl], 1u);
     }
   }
   __syncthreads();
-  {  // exclusive scan of the 192 digit counts
-    uint32_t x = 0;
-    const uint32_t t = threadIdx.x;
-    if (t < 3 * kSubBuckets) x = dcur[t];
+  {  // exclusive scan of the digit counts (a thread owns up to 8 consecutive ones)
+    constexpr uint32_t kMaxPer = (kSubBuckets * 64 + kL3Threads - 1) / kL3Threads;
+    const uint32_t per = (nd + kL3Threads - 1) / kL3Threads;
+    const uint32_t base = threadIdx.x * per;
+    uint32_t loc[kMaxPer];
+    uint32_t tot = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kMaxPer; ++k) {
+      loc[k] = (k < per && base + k < nd) ? dcur[base + k] : 0u;
+      tot += loc[k];
+    }
     __syncthreads();
-    const uint32_t run = block_exclusive_scan<kL3Threads>(x, wsum, nullptr);
-    if (t < 3 * kSubBuckets) dcur[t] = run;
-    if (t == 0) dcur[3 * kSubBuckets] = n;
+    uint32_t run = block_exclusive_scan<kL3Threads>(tot, wsum, nullptr);
+#pragma unroll
+    for (uint32_t k = 0; k < kMaxPer; ++k) {
+      if (k < per && base + k < nd) dcur[base + k] = run;
+      run += loc[k];
+    }
+    if (threadIdx.x == 0) dcur[nd] = n;
     __syncthreads();
   }
   Rec* gout = items + lo + beta0;
   // headers and bucket starts
   for (uint32_t bl = threadIdx.x; bl < nbk; bl += kL3Threads) {
-    const uint32_t first = dcur[3 * bl];
-    const uint32_t count = dcur[3 * bl + 3] - first;
-    const uint32_t c0 = dcur[3 * bl + 1] - first, c1 = dcur[3 * bl + 2] - dcur[3 * bl + 1];
-    const uint32_t kf = forced_kf(beta0 + bl, maxoff[bl], count, g);
+    const uint32_t first = dcur[D * bl];
+    const uint32_t count = dcur[D * bl + D] - first;
+    uint32_t c0 = 0, c1 = 0;
+    if (D == 3) {
+      c0 = dcur[3 * bl + 1] - first;
+      c1 = dcur[3 * bl + 2] - dcur[3 * bl + 1];
+    }
     bstart[beta0 + bl] = lo + first;
-    const uint4 hd = make_uint4(count, kf, c0, c1);
+    const uint4 hd = make_uint4(count, maxoff[bl] | (nzero[bl] << 8), c0, c1);
     if (fits)
       stage[first + bl] = hd;
     else
@@ -627,10 +642,10 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict_
 #pragma unroll
     for (int k = 0; k < kL3Per; ++k) {
       if (dr[k] == 0xffffffffu) continue;
-      const uint32_t d = dr[k] & 0xffu;
-      const uint32_t bl = d / 3, rk = d - bl * 3;
+      const uint32_t d = dr[k] & 0xfffu;
+      const uint32_t bl = d / D, rk = D == 3 ? d - bl * 3 : 0u;
       const uint32_t o = (rec[k].w - slot0) & 63u;
-      stage[dcur[d] + (dr[k] >> 8) + bl + 1] = make_uint4(rec[k].x, rec[k].y, rec[k].z, o | (rk << 8));
+      stage[dcur[d] + (dr[k] >> 12) + bl + 1] = make_uint4(rec[k].x, rec[k].y, rec[k].z, o | (rk << 8));
     }
     __syncthreads();
     uint4* go = reinterpret_cast<uint4*>(gout);
@@ -642,8 +657,9 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict_
     const uint4 r = in[i];
     const uint32_t sl = r.w - slot0;
     const uint32_t bl = sl >> 6, o = sl & 63u;
-    const uint32_t rk = rank_of(o, g);
-    const uint32_t pos = atomicAdd(&dcur[bl * 3 + rk], 1u) + bl + 1;
+    const uint32_t dg = digit(o);
+    const uint32_t rk = D == 3 ? dg : 0u;
+    const uint32_t pos = atomicAdd(&dcur[bl * D + dg], 1u) + bl + 1;
     reinterpret_cast<uint4*>(gout)[pos] = make_uint4(r.x, r.y, r.z, o | (rk << 8));
   }
 }
@@ -677,11 +693,11 @@ hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_p2_plan<<<1, kPartThreads, 0, s>>>(a.counts1, sp, n, a.binlo, a.nch, a.cbase);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t lds3 = l3_lds_bytes(digits_per_bucket(a.g));
   (void)hipFuncSetAttribute((const void*)k_p3_sort, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(kL3Cap * sizeof(uint4)));
+                            (int)l3_lds_bytes(64));
   if (sp.S == 1) {  // the bins are the sub-bins: level 3 reads level 1's output
-    k_p3_sort<<<sp.nsub, kL3Threads, kL3Cap * sizeof(uint4), s>>>(a.p1, a.g, sp, a.binlo,
-                                                                  a.out_rec, a.bstart);
+    k_p3_sort<<<sp.nsub, kL3Threads, lds3, s>>>(a.p1, a.g, sp, a.binlo, a.out_rec, a.bstart);
     return hipGetLastError();
   }
   const size_t n2 = (size_t)sp.U2 * sp.S;
@@ -696,8 +712,71 @@ hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
   k_p2_starts<<<(sp.nsub + 256) / 256, 256, 0, s>>>(sp, n, a.binlo, a.nch, a.cbase, a.counts2,
                                                      a.sstart);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_p3_sort<<<sp.nsub, kL3Threads, kL3Cap * sizeof(uint4), s>>>(a.p2, a.g, sp, a.sstart,
-                                                                a.out_rec, a.bstart);
+  k_p3_sort<<<sp.nsub, kL3Threads, lds3, s>>>(a.p2, a.g, sp, a.sstart, a.out_rec, a.bstart);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cut points (Sec. 3 "Selecting Cut Points")
+// ---------------------------------------------------------------------------
+// One thread per global range rho: rfirst[rho] = its first global bucket,
+// rfirst[nranges] = nbuckets. A structure's first range starts at its first
+// bucket; the range before every other range ends at a bucket chosen within
+// h of the equal split's last bucket b0, h = min(cut_search / 2,
+// (floor(B/R) - 2) / 2) (every range keeps two buckets, so each cut is chosen
+// on its own). Scores of a candidate last bucket beta, from the bucket
+// headers: bumped = its records if any lies past offset 0 (the threshold
+// forced on a range's last bucket then bumps all of them, b = w = 64), prev
+// = the records of bucket beta-1 past offset 0 (starts in the w-1 slots
+// before beta). minbump: fewest bumped; maxprev: most prev; diff: smallest
+// bumped - prev; ties to the nearest candidate, then the lower one.
+__global__ void k_cuts(LayerGeom g, const uint4* __restrict__ rec,
+                       const uint32_t* __restrict__ bstart, uint32_t* __restrict__ rfirst) {
+  const uint64_t rho = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rho > g.nranges) return;
+  if (rho == g.nranges) {
+    rfirst[rho] = (uint32_t)g.nbuckets;
+    return;
+  }
+  const uint32_t j = find_struct(g.range_base, g.J, rho);
+  const uint64_t bb = g.bucket_base[j];
+  const uint64_t B = g.bucket_base[j + 1] - bb;
+  const uint64_t R = g.range_base[j + 1] - g.range_base[j];
+  const uint64_t lr = rho - g.range_base[j];
+  uint64_t first = bb + lr * B / R;
+  const uint64_t L = B / R;
+  uint64_t h = g.cut_search / 2;
+  const uint64_t hmax = L >= 2 ? (L - 2) / 2 : 0;
+  if (h > hmax) h = hmax;
+  if (lr > 0 && g.cut_strategy != 0 && g.cut_search >= 2 && h > 0) {
+    const uint64_t b0 = first - 1;
+    int64_t best = 0;
+    uint64_t best_beta = b0, best_dist = 0;
+    bool have = false;
+    for (uint64_t beta = b0 - h; beta <= b0 + h; ++beta) {
+      const uint4 hd = rec[bstart[beta] + beta];
+      const uint4 hp = rec[bstart[beta - 1] + beta - 1];
+      const int64_t bumped = (hd.y & 63u) ? (int64_t)hd.x : 0;
+      const int64_t prev = (int64_t)hp.x - (int64_t)(hp.y >> 8);
+      const int64_t score = g.cut_strategy == 1 ? bumped : (g.cut_strategy == 2 ? -prev : bumped - prev);
+      const uint64_t dist = beta > b0 ? beta - b0 : b0 - beta;
+      if (!have || score < best || (score == best && dist < best_dist)) {
+        have = true;
+        best = score;
+        best_beta = beta;
+        best_dist = dist;
+      }
+    }
+    first = best_beta + 1;
+  }
+  rfirst[rho] = (uint32_t)first;
+}
+
+hipError_t choose_cuts(const Rec* rec, const uint32_t* bstart, const LayerGeom& g, uint32_t* rfirst,
+                       hipStream_t s) {
+  const uint64_t n = g.nranges + 1;
+  k_cuts<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, reinterpret_cast<const uint4*>(rec), bstart,
+                                                     rfirst);
   return hipGetLastError();
 }
 
@@ -1058,17 +1137,18 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
   WaveRing<LANES>& R = RR[G.id];
   const LayerGeom g = a.g;
   const uint64_t rho = (uint64_t)blockIdx.x * NG + G.id;
-  // this group's range: buckets [fb, fb + nq) of structure js (none past the last range)
+  // this group's range: buckets [fb, fb + nq) of structure js (none past the
+  // last range); the structure's last range bumps nothing for its end
   uint32_t js = 0, nq = 0;
   uint64_t fb = 0;
+  bool last_range = true;
   if (rho < g.nranges) {
     js = find_struct(g.range_base, g.J, rho);
-    const uint64_t B = g.bucket_base[js + 1] - g.bucket_base[js];
-    const uint64_t Rn = g.range_base[js + 1] - g.range_base[js];
-    const uint64_t lr = rho - g.range_base[js];
-    const uint64_t f0 = lr * B / Rn;
-    fb = g.bucket_base[js] + f0;
-    nq = (uint32_t)((lr + 1) * B / Rn - f0);
+    uint64_t f0, f1;
+    range_buckets(g, js, rho, f0, f1);
+    fb = f0;
+    nq = (uint32_t)(f1 - f0);
+    last_range = rho + 1 == g.range_base[js + 1];
   }
   const uint32_t last_item = a.nrec - 1;
   const uint4* rec4 = reinterpret_cast<const uint4*>(a.rec);
@@ -1116,23 +1196,92 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
       hd.z = __builtin_amdgcn_readfirstlane(hd.z);
       hd.w = __builtin_amdgcn_readfirstlane(hd.w);
     }
-    const uint32_t count = hd.x, kf = hd.y & 3u;
+    const uint32_t count = hd.x, maxo = hd.y & 63u;
+    // the last bucket of a range that is not its structure's last: every key
+    // past the bucket's first slot would cross the range end (b = w = 64), so
+    // the threshold is forced above the largest offset (Sec. 3 "Bumping"):
+    // the smallest 2-bit value above it, or with 1+-bit thresholds the
+    // offset + 1 (kf: 2-bit code index, or 1+-bit threshold value)
+    const bool at_end = !g.plain && !last_range && q + 1 == nq && maxo > 0;
+    const uint32_t kf = !at_end ? 0u
+                      : g.thr_mode == 1 ? maxo + 1u
+                      : (maxo >= g.t_hi ? 3u : (maxo >= g.t_lo ? 2u : 1u));
     const uint32_t e1 = hd.z, e2 = hd.z + hd.w;  // ends of ranks 0 and 1
     // claims past the range end: only from its last bucket, without a spill buffer
     const bool last_half = q + 1 == nq && !a.spillC;
+    // records [r0, r1) of the bucket on top of the ring: fast pass, exact
+    // pass if it stopped (exact only in a range's last bucket without a
+    // spill buffer)
+    auto pass = [&](uint32_t r0, uint32_t r1) {
+      const uint32_t res =
+          last_half ? 3u : wave_pass<LANES, true>(R, G, a, rec4, hq, q, r0, r1, false, steps, sst);
+      return res == 3 ? wave_pass<LANES, false>(R, G, a, rec4, hq, q, r0, r1, last_half, steps, sst)
+                      : res;
+    };
+    const bool one_plus = g.thr_mode == 1 && !g.plain;
+    // 1+-bit: kf > 0 lies above every offset, so then nothing is a candidate
     const uint32_t keep_ranks = g.plain ? 3u : 3u - kf;
-    const uint32_t cand = keep_ranks == 3 ? count : (keep_ranks == 2 ? e2 : (keep_ranks == 1 ? e1 : 0u));
+    const uint32_t cand = one_plus ? (kf == 0 ? count : 0u)
+                        : keep_ranks == 3 ? count : (keep_ranks == 2 ? e2 : (keep_ranks == 1 ? e1 : 0u));
     uint32_t kept = cand, code = kf;
-    if (cand > 0) {
-      // records [0, n) of the bucket: fast pass, exact pass if it stopped
-      // (exact only in a range's last bucket without a spill buffer)
-      auto pass = [&](uint32_t n) {
-        const uint32_t res =
-            last_half ? 3u : wave_pass<LANES, true>(R, G, a, rec4, hq, q, 0, n, false, steps, sst);
-        return res == 3 ? wave_pass<LANES, false>(R, G, a, rec4, hq, q, 0, n, last_half, steps, sst)
-                        : res;
+    if (cand > 0 && one_plus) {
+      // records ordered by offset, highest first: the records with offset
+      // >= theta are a prefix of the bucket; its length from ballots over
+      // the staged offsets (records past the stage from the item stream)
+      auto prefix_len = [&](uint32_t theta) {
+        uint32_t c = 0;
+        for (uint32_t t0 = 0; t0 < count; t0 += LANES) {
+          const uint32_t t = t0 + G.lane;
+          uint32_t o = 0;
+          if (t < count) {
+            constexpr uint32_t last = Stage<LANES>::items - 1;
+            o = (t < last ? R.stage[t + 1].w : rec4[hq + 1 + t].w) & 63u;
+          }
+          c += (uint32_t)__popcll(G.ballot(t < count && o >= theta));
+        }
+        return c;
       };
-      uint32_t res = pass(cand);
+      uint32_t res = pass(0, cand);
+      if (res == 1) {
+        // the smallest threshold whose kept set is consistent, by bisection
+        // over offsets: the ring keeps the rows of the largest prefix known
+        // to be consistent (threshold `good`), a trial inserts the next
+        // records on top of it and is undone if it fails (a prefix of a
+        // consistent set is consistent, so the outcome equals inserting the
+        // keys one by one in decreasing offset order)
+        uint32_t good = 64, n_good = 0, bad = kf, n_bad = cand;
+        res = 0;
+        while (good - bad > 1 && res != 2) {
+          const uint32_t mid = (good + bad) >> 1;
+          const uint32_t n_mid = prefix_len(mid);
+          if (n_mid == n_good) {
+            good = mid;
+          } else if (n_mid == n_bad) {
+            bad = mid;
+          } else {
+            res = pass(n_good, n_mid);
+            if (res == 0) {
+              good = mid;
+              n_good = n_mid;
+            } else if (res == 1) {
+              bad = mid;
+              n_bad = n_mid;
+              res = 0;
+            }
+          }
+        }
+        kept = n_good;
+        code = good;
+      }
+      if (res == 2) {
+        if (G.lane == 0) {
+          a.fail[js] = 2u;
+          solve_diag(a.diag, 2, rho, js, hq, count, q, nq, cand, 0, kept, code, kf, 0, 0, fb);
+        }
+        failed = true;
+      }
+    } else if (cand > 0) {
+      uint32_t res = pass(0, cand);
       if (res == 1 && g.plain) {
         if (G.lane == 0) a.fail[js] = 1u;
         failed = true;
@@ -1143,7 +1292,7 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
         for (uint32_t rr = keep_ranks - 1; rr >= 1 && res != 2; --rr) {
           const uint32_t e = rr == 2 ? e2 : e1;
           if (e == failed_size) continue;  // the same set again
-          res = e ? pass(e) : 0u;
+          res = e ? pass(0, e) : 0u;
           if (res == 0) {
             kept = e;
             code = 3 - rr;
@@ -1234,12 +1383,8 @@ __global__ __launch_bounds__(64) void k_backsub(const uint64_t* __restrict__ row
   uint64_t fb = 0, lb = 0, wb = 0, bb = 0;
   if (valid) {
     const uint32_t j = find_struct(g.range_base, g.J, rho);
-    const uint64_t B = g.bucket_base[j + 1] - g.bucket_base[j];
-    const uint64_t R = g.range_base[j + 1] - g.range_base[j];
-    const uint64_t lr = rho - g.range_base[j];
     bb = g.bucket_base[j];
-    fb = bb + lr * B / R;
-    lb = bb + (lr + 1) * B / R;
+    range_buckets(g, j, rho, fb, lb);
     r = g.rbits[j];
     wb = g.word_base[j];  // block k of the structure at wb + (k - bb) * r
   }
@@ -1694,6 +1839,67 @@ hipError_t pack_codes(const uint8_t* code8, const LayerGeom& g, uint64_t ncode_w
   return hipGetLastError();
 }
 
+// 1+-bit thresholds (Sec. 2: one bit per bucket, the exact threshold only
+// for buckets that bump). Per structure: bit words (64 buckets each), the
+// thresholds minus 1 of the bumping buckets in bucket order (one byte each),
+// and a rank directory - the set bits before every block of 8 bit words -
+// that finds a bucket's threshold with at most 8 popcounts.
+// Pass 1: the bit words and their popcounts (pc, scanned afterwards).
+__global__ void k_pack_bits(const uint8_t* __restrict__ code8, LayerGeom g, uint64_t nwords,
+                            uint64_t* __restrict__ bits, uint32_t* __restrict__ pc) {
+  const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nwords) return;
+  const uint32_t j = find_struct(g.code_base, g.J, w);
+  const uint64_t bb = g.bucket_base[j];
+  const uint64_t B = g.bucket_base[j + 1] - bb;
+  const uint64_t wl = w - g.code_base[j];
+  uint64_t word = 0;
+  for (uint64_t t = 0; t < 64; ++t) {
+    const uint64_t b = wl * 64 + t;
+    if (b < B && code8[bb + b]) word |= 1ull << t;
+  }
+  bits[w] = word;
+  pc[w] = (uint32_t)__popcll(word);
+}
+
+// Pass 2 (pc scanned, pc[nwords] = total): thresholds, rank directory and
+// the number of thresholds of every structure.
+__global__ void k_pack_thr(const uint8_t* __restrict__ code8, LayerGeom g, uint64_t nwords,
+                           const uint64_t* __restrict__ bits, const uint32_t* __restrict__ pc,
+                           uint8_t* __restrict__ thr, uint32_t* __restrict__ rank,
+                           uint32_t* __restrict__ kcount) {
+  const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nwords) return;
+  const uint32_t j = find_struct(g.code_base, g.J, w);
+  const uint64_t bb = g.bucket_base[j];
+  const uint64_t wl = w - g.code_base[j];
+  const uint32_t base = pc[g.code_base[j]];
+  uint32_t k = pc[w] - base;
+  if (wl % 8 == 0) rank[g.rank_base[j] + wl / 8] = k;
+  uint64_t word = bits[w];
+  while (word) {
+    const uint32_t t = (uint32_t)__builtin_ctzll(word);
+    thr[g.thr_base[j] + k] = (uint8_t)(code8[bb + wl * 64 + t] - 1u);
+    ++k;
+    word &= word - 1;
+  }
+  if (w + 1 == g.code_base[j + 1]) kcount[j] = pc[w + 1] - base;
+}
+
+hipError_t pack_thresholds(const uint8_t* code8, const LayerGeom& g, uint64_t nwords,
+                           uint64_t* bits, uint32_t* pc, uint32_t* scan_tmp, uint8_t* thr,
+                           uint32_t* rank, uint32_t* kcount, hipStream_t s) {
+  if (nwords == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((nwords + 255) / 256);
+  k_pack_bits<<<blocks, 256, 0, s>>>(code8, g, nwords, bits, pc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = hipMemsetAsync(pc + nwords, 0, 4, s)) != hipSuccess) return e;
+  if ((e = scan_exclusive(pc, nwords + 1, scan_tmp, s)) != hipSuccess) return e;
+  k_pack_thr<<<blocks, 256, 0, s>>>(code8, g, nwords, bits, pc, thr, rank, kcount);
+  return hipGetLastError();
+}
+
 __global__ void k_struct_offsets(const uint32_t* __restrict__ off, LayerGeom g,
                                  uint32_t* __restrict__ out) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1896,15 +2102,28 @@ __global__ __launch_bounds__(256) void k_query(QueryPlan plan, const uint64_t* _
     const uint32_t sh = (uint32_t)s & 63u;
     const uint64_t* w = L.W + (s >> 6) * r;
     const uint64_t beta = s >> 6;
-    const uint64_t cw = L.plain ? 0ull : L.codes[beta >> 5];
+    const uint64_t cw = L.plain ? 0ull : L.codes[L.thr_mode ? (beta >> 6) : (beta >> 5)];
     uint32_t val;
     if constexpr (RC > 0)
       val = window_parity<RC, AL>(w, sh, c);
     else
       val = window_parity_any(w, r, sh, c);
     if (!L.plain) {
-      const uint32_t code = (uint32_t)(cw >> (2 * (beta & 31))) & 3u;
-      const uint32_t th = code == 0 ? 0u : (code == 1 ? L.t_lo : (code == 2 ? L.t_hi : 64u));
+      uint32_t th;
+      if (L.thr_mode) {  // 1+-bit: a set bit sends the lookup to the threshold bytes
+        th = 0;
+        const uint32_t bit = (uint32_t)(beta & 63);
+        if ((cw >> bit) & 1ull) {
+          const uint64_t wi = beta >> 6, blk = wi >> 3;
+          uint32_t rk = L.rank[blk];
+          for (uint64_t x = blk << 3; x < wi; ++x) rk += (uint32_t)__popcll(L.codes[x]);
+          rk += (uint32_t)__popcll(cw & ((1ull << bit) - 1ull));
+          th = (uint32_t)L.thr[rk] + 1u;
+        }
+      } else {
+        const uint32_t code = (uint32_t)(cw >> (2 * (beta & 31))) & 3u;
+        th = code == 0 ? 0u : (code == 1 ? L.t_lo : (code == 2 ? L.t_hi : 64u));
+      }
       if (sh < th) continue;
     }
     res = val;

@@ -194,3 +194,18 @@ def test_autotune_on_a_size_mix_builds_exactly():
         mk, ref = _member_ref(keys, vals, offs, rs, i, dict(ranges=1 << 16, minbpt=cls["minbpt"]))
         check_handle(b.member(i), ref, mk, n_queries=2000)
     b.free()
+
+
+@pytest.mark.parametrize("kw", [
+    dict(ranges=64, minbpt=4, threshold_mode=1),
+    dict(ranges=64, minbpt=4, cut_strategy=2, cut_search=50, seed=3),
+    dict(ranges=64, minbpt=4, threshold_mode=1, cut_strategy=3, cut_search=20, seed=4),
+])
+def test_batch_with_one_plus_bit_thresholds_and_cut_search(kw):
+    # every member's bit words, threshold bytes and cut points sit at its own
+    # offsets of the layer's shared arrays; each must export exactly the
+    # oracle's structure of its own keys
+    sizes = [0, 64, 150, 999, 3000, 20000, 7, 45000, 1200, 80000]
+    rs = [3, 1, 8, 2, 5, 8, 3, 1, 16, 8]
+    b, *_ = _check_batch(sizes, rs, kw, seed=91)
+    b.free()

@@ -79,8 +79,8 @@ def test_batch_through_torch_allocator():
 
 
 def _header(r=8, built=0, layers=3, bucket=64, n=5, seed=0):
-    hdr = [1, 64, bucket, r, 97, 100, 110, 100, layers, 16, 32, 1, 16, 16, 0, built]
-    return struct.pack("<Q16IQQ", 0x3170786552527542, *hdr, seed, n)
+    hdr = [2, 64, bucket, r, 97, 100, 110, 100, layers, 16, 32, 1, 16, 16, 0, built, 0, 0, 0, 0]
+    return struct.pack("<Q20IQQ", 0x3170786552527542, *hdr, seed, n)
 
 
 def test_import_rejects_sizes_that_would_overflow():

@@ -59,6 +59,22 @@ CASES = [
     # some of them only when segments are merged
     (60000, 8, dict(layers=0, final_num=100, final_den=100, seed=4)),
     (60000, 8, dict(layers=0, final_num=100, final_den=100, seed=5)),
+    # 1+-bit thresholds: exact thresholds found by bisection in the ring
+    (20000, 8, dict(ranges=64, threshold_mode=1)),
+    (200000, 8, dict(ranges=4096, minbpt=4, threshold_mode=1)),
+    (100000, 16, dict(ranges=16, threshold_mode=1, filter_mode=1, seed=3)),
+    (40000, 8, dict(ranges=64, load_num=80, load_den=100, threshold_mode=1, seed=4)),
+    (30000, 1, dict(ranges=8, load_num=70, load_den=100, threshold_mode=1, seed=14)),
+    (20000, 32, dict(ranges=1, threshold_mode=1, layers=5, seed=15)),
+    # searched cut points: every strategy, search ranges wider and narrower
+    # than half a range, with both threshold modes
+    (200000, 8, dict(ranges=1000, minbpt=8, cut_strategy=1, cut_search=50)),
+    (200000, 8, dict(ranges=1000, minbpt=8, cut_strategy=2, cut_search=50, seed=6)),
+    (200000, 4, dict(ranges=1000, minbpt=8, cut_strategy=3, cut_search=50, seed=7)),
+    (100000, 8, dict(ranges=300, minbpt=2, cut_strategy=2, cut_search=6, seed=8)),
+    (150000, 8, dict(ranges=2000, minbpt=4, cut_strategy=3, cut_search=50,
+                     threshold_mode=1, seed=9)),
+    (50000, 3, dict(ranges=100, cut_strategy=1, cut_search=1, seed=10)),
 ]
 
 
@@ -173,6 +189,7 @@ def test_low_word_collision_takes_the_exact_pass():
 @pytest.mark.parametrize("n,r,kw", [
     (120_000, 8, dict(ranges=16, load_num=50, load_den=100, seed=31)),
     (150_000, 16, dict(ranges=1, load_num=60, load_den=100, seed=32)),
+    (120_000, 8, dict(ranges=16, load_num=50, load_den=100, seed=33, threshold_mode=1)),
 ])
 def test_overfull_buckets_and_sub_bins(n, r, kw):
     """Two rarely taken kernel paths, reached on purpose: at 0.5-0.6 slots per
@@ -190,3 +207,22 @@ def test_overfull_buckets_and_sub_bins(n, r, kw):
         np.minimum(64, B - np.arange(0, B, 64))  # records + one header per bucket
     assert per_sub.max() > 4608, "no sub-bin exceeds the level-3 LDS block"
     _compare(keys, vals, r, kw, "overfull")
+
+
+@pytest.mark.parametrize("kw", [
+    dict(ranges=64, threshold_mode=1, seed=2),
+    dict(ranges=64, minbpt=8, cut_strategy=2, cut_search=50, seed=3),
+    dict(ranges=64, minbpt=8, threshold_mode=1, cut_strategy=1, cut_search=10, seed=4),
+])
+def test_import_roundtrip_of_new_sections(kw):
+    # the oracle's export (1+-bit bit words, threshold bytes, cut points)
+    # imported by the library answers like the oracle and exports the same bytes
+    burr = _burr()
+    keys, vals = W.keys(50_000, 61), W.values(50_000, 8, 62)
+    ref = oracle.build(keys, vals, 8, oracle.Params(**kw))
+    print(f"[parity] import {kw}", flush=True)
+    h = burr.import_(ref.export())
+    assert h.export() == ref.export()
+    q = np.concatenate([keys[:20_000], W.non_members(50_000, 20_000, 63)])
+    assert np.array_equal(h.query(_dev(q)).cpu().numpy(), ref.query(q))
+    h.free()

@@ -28,7 +28,7 @@ def test_default_params_and_error_strings():
     p = burr._CParams()
     lib.burr_default_params(ctypes.byref(p))
     assert (p.abi_version, p.bucket, p.load_num, p.load_den, p.layers, p.t_lo, p.t_hi) == \
-        (1, 64, 97, 100, 3, 16, 32)
+        (2, 64, 97, 100, 3, 16, 32)
     assert lib.burr_error_string(burr.BURR_E_UNSOLVABLE).startswith(b"final layer")
 
 
@@ -42,6 +42,10 @@ def test_invalid_arguments_fail_without_touching_the_device():
     assert lib.burr_build(None, None, 10, 0, ctypes.byref(p)) is None
     assert lib.burr_import(b"not an export", 13, None) is None
     assert lib.burr_last_error() == burr.BURR_E_INVALID
+    for bad in (dict(threshold_mode=2), dict(cut_strategy=4)):
+        p = burr.Params(**bad).c(None)
+        assert lib.burr_build(None, None, 0, 8, ctypes.byref(p)) is None
+        assert lib.burr_last_error() == burr.BURR_E_INVALID
 
 
 def test_invalid_batch_arguments_fail_without_touching_the_device():
