@@ -16,6 +16,8 @@ Layout (little endian):
 """
 import struct
 
+import numpy as np
+
 HEADER_FIELDS = ("version", "w", "b", "r", "load_num", "load_den", "final_num", "final_den",
                  "layers", "t_lo", "t_hi", "ranges", "minbpt", "final_attempts",
                  "filter_mode", "built", "threshold_mode", "cut_strategy", "cut_search",
@@ -23,6 +25,11 @@ HEADER_FIELDS = ("version", "w", "b", "r", "load_num", "load_den", "final_num", 
 
 
 def parse(buf: bytes) -> dict:
+    """Sections as numpy views of buf (no copies: exports of a billion keys
+    are gigabytes): per layer codes or thresholds (uint8 per bucket), words
+    (uint64), cuts (uint32, with a cut strategy) and `bytes`, a memoryview of
+    the layer's whole section; the final layer likewise."""
+    mv = memoryview(buf)
     off = 0
 
     def take(fmt):
@@ -30,6 +37,12 @@ def parse(buf: bytes) -> dict:
         v = struct.unpack_from("<" + fmt, buf, off)
         off += struct.calcsize("<" + fmt)
         return v
+
+    def words(count):
+        nonlocal off
+        a = np.frombuffer(buf, dtype="<u8", count=count, offset=off)
+        off += 8 * count
+        return a
 
     (magic,) = take("Q")
     hdr = dict(zip(HEADER_FIELDS, take("20I")))
@@ -40,37 +53,34 @@ def parse(buf: bytes) -> dict:
         start = off
         n, m, R = take("3Q")
         B = m // b
+        idx = np.arange(B, dtype=np.uint64)
         L = dict(layer=li, n=n, m=m, R=R)
         if hdr["threshold_mode"] == 1:
-            bits = take(f"{(B + 63) // 64}Q")
+            bits = words((B + 63) // 64)
             (K,) = take("Q")
-            thr = buf[off:off + K]
+            thr = np.frombuffer(buf, dtype=np.uint8, count=K, offset=off)
             off += (K + 7) // 8 * 8
-            T = []
-            k = 0
-            for beta in range(B):
-                if (bits[beta // 64] >> (beta % 64)) & 1:
-                    T.append(thr[k] + 1)
-                    k += 1
-                else:
-                    T.append(0)
-            assert k == K
+            set_ = ((bits[idx >> np.uint64(6)] >> (idx & np.uint64(63))) & np.uint64(1)).astype(bool)
+            assert int(set_.sum()) == K
+            T = np.zeros(B, dtype=np.uint16)
+            T[set_] = thr.astype(np.uint16) + 1
             L["thresholds"] = T
             L["K"] = K
         else:
-            codes = take(f"{(B + 31) // 32}Q")
-            L["codes"] = [(codes[beta // 32] >> (2 * (beta % 32))) & 3 for beta in range(B)]
-        L["words"] = take(f"{(m // 64) * r}Q")
+            cw = words((B + 31) // 32)
+            L["codes"] = ((cw[idx >> np.uint64(5)] >> ((idx & np.uint64(31)) * np.uint64(2)))
+                          & np.uint64(3)).astype(np.uint8)
+        L["words"] = words((m // 64) * r)
         if hdr["cut_strategy"]:
-            cw = (R - 1 + 1) // 2
-            cuts = take(f"{2 * cw}I")
-            L["cuts"] = list(cuts[:R - 1])
-        L["bytes"] = buf[start:off]
+            cw = R // 2  # ceil((R - 1) / 2) words of u32
+            L["cuts"] = np.frombuffer(buf, dtype="<u4", count=2 * cw, offset=off)[:R - 1]
+            off += 8 * cw
+        L["bytes"] = mv[start:off]
         layers.append(L)
     start = off
     fn, fm, fa = take("3Q")
-    fwords = take(f"{(fm // 64) * r}Q")
-    fin = dict(n=fn, m=fm, attempt=fa, words=fwords, bytes=buf[start:off])
+    fwords = words((fm // 64) * r)
+    fin = dict(n=fn, m=fm, attempt=fa, words=fwords, bytes=mv[start:off])
     assert off == len(buf), (off, len(buf))
     return dict(magic=magic, header=hdr, layers=layers, final=fin)
 

@@ -1,23 +1,32 @@
-"""GPU: the full-size workloads - the 1B-key filter build (2^18 ranges, r = 16
-and r = 1), the 100M-key retrieval build (2^16 ranges, r = 8) and the
-200,000-structure batch.
+"""GPU: the full-size workloads - the 100M-key retrieval build (2^16 ranges,
+r = 8), the 1B-key filter builds (2^18 ranges, r = 16 and r = 1) and the
+200,000-structure batch - checked against the oracle.
 
-The oracle cannot build a billion keys within a test, so this checks
-(1) properties that hold at any size: every member is found, the
-false-positive rate of non-members matches 2^-r (Sec. 1: a retrieval
-structure of r-bit fingerprints is a filter), and each layer's geometry
-follows its closed form; and (2) exact parity on sampled layer-0 ranges: the
-oracle solves each sampled range alone from the keys that start in it
-(ranges are independent, Sec. 3), and its threshold codes, solution words
-and bumped keys must equal the library's; batch members sampled across the
-size range must export exactly the oracle's structure of their own keys."""
-import struct
+- 100M keys: the whole export equals the oracle's, built by its range-parallel
+  driver (itself pinned byte for byte to the sequential oracle on the CPU).
+- 1B keys: too large for a whole oracle build within a test, so
+  (1) properties that hold at any size: every member is found, the
+      false-positive rate of 10^9 non-members matches 2^-r (Sec. 1: a
+      retrieval structure of r-bit fingerprints is a filter), every layer's
+      geometry follows its closed form;
+  (2) layer 0 exactly on 1,000 sampled ranges: the oracle solves each alone
+      from the keys that start in it (ranges are independent, Sec. 3) and its
+      threshold codes, solution words and bumped keys equal the library's;
+  (3) the chain below layer 0 exactly: the oracle builds layers 1, 2 and the
+      final layer from the GPU's own layer-1 keys, and every byte of those
+      sections of the export equals the library's.
+- 200,000 structures: every member's export equals the oracle's structure of
+  its own keys (the oracle runs on a thread pool: its C calls release the
+  interpreter lock)."""
+import concurrent.futures as cf
+import os
 
 import numpy as np
 import pytest
 
 import oracle
 from paper_2411_12365_amd import workload as W
+from tests import export_format
 
 pytestmark = pytest.mark.gpu
 
@@ -27,11 +36,19 @@ N = 1_000_000_000
 RANGES = 1 << 18
 SEED_KEYS = 3
 CHUNK = 100_000_000
+SAMPLED_RANGES = 1000
+THREADS = min(16, os.cpu_count() or 1)
 
 
 def _burr():
     import paper_2411_12365_amd as burr
     return burr
+
+
+def _sample_ranges(R, seed, count):
+    rng = np.random.default_rng(seed)
+    rest = rng.choice(np.arange(2, R - 2), size=count - 5, replace=False)
+    return sorted({0, 1, R // 2, R - 2, R - 1, *rest.tolist()})
 
 
 @pytest.fixture(scope="module")
@@ -47,18 +64,21 @@ def big():
     assert (m, B, R) == (970_000_000, 15_156_250, RANGES)
     print("[large] oracle start buckets of every key", flush=True)
     sb = oracle.start_buckets(keys, 0, m, op)
-    # sampled ranges: both ends, the middle and a few random ones
-    rng = np.random.default_rng(33)
-    rhos = sorted({0, 1, R // 2, R - 2, R - 1, *rng.integers(0, R, 3).tolist()})
-    lut = np.full(B, -1, dtype=np.int8)
+    rhos = _sample_ranges(R, 33, SAMPLED_RANGES)
+    lut = np.full(B, -1, dtype=np.int16)
     bounds = []
     for i, rho in enumerate(rhos):
         first, last = oracle.range_buckets(B, R, rho)
         lut[first:last] = i
         bounds.append((first, last))
     tag = lut[sb]
+    del sb
     sel = np.flatnonzero(tag >= 0)
-    members = {rho: keys[sel[tag[sel] == i]] for i, rho in enumerate(rhos)}
+    order = np.argsort(tag[sel], kind="stable")
+    sel = sel[order]
+    cuts = np.searchsorted(tag[sel], np.arange(len(rhos) + 1))
+    members = {rho: keys[sel[cuts[i]:cuts[i + 1]]] for i, rho in enumerate(rhos)}
+    del tag, sel
     yield dict(keys_dev=keys_dev, keys=keys, op=op, m=m, B=B, R=R, rhos=rhos,
                bounds=bounds, members=members, lut=lut)
     del keys_dev
@@ -66,17 +86,39 @@ def big():
     torch.cuda.empty_cache()
 
 
-def _layer0(buf: bytes, r: int):
-    """Layer-0 codes and solution words of a canonical export."""
-    off = 8 + 16 * 4 + 16
-    n0, m0, R0 = struct.unpack_from("<3Q", buf, off)
-    off += 24
-    B = m0 // 64
-    ncode = (B + 31) // 32
-    codes = np.frombuffer(buf, dtype=np.uint64, count=ncode, offset=off)
-    off += ncode * 8
-    words = np.frombuffer(buf, dtype=np.uint64, count=(m0 // 64) * r, offset=off)
-    return n0, m0, R0, codes, words
+def _check_sampled_ranges(e, r, op, n, rhos, bounds, members, lut, m, bumped_gpu, vals_of=None):
+    """Layer 0 of export e on the sampled ranges equals the oracle's one-range
+    solves: codes, solution words and bump sets."""
+    L0 = e["layers"][0]
+    codes = np.array(L0["codes"], dtype=np.uint8)
+    words = np.array(L0["words"], dtype=np.uint64)
+    btag = lut[oracle.start_buckets(bumped_gpu, 0, m, op)]
+    order = np.argsort(btag, kind="stable")
+    bsorted = bumped_gpu[order]
+    bcuts = np.searchsorted(btag[order], np.arange(len(rhos) + 1))
+    for i, rho in enumerate(rhos):
+        first, last = bounds[i]
+        mk = members[rho]
+        mv = None if vals_of is None else vals_of(mk)
+        ref = oracle.layer_range(mk, mv, r, op, 0, n, rho)
+        assert np.array_equal(codes[first:last], ref["codes"]), f"codes, range {rho}"
+        assert np.array_equal(words[first * r:last * r], ref["W"]), f"words, range {rho}"
+        got = np.sort(bsorted[bcuts[i]:bcuts[i + 1]])
+        assert np.array_equal(got, np.sort(ref["bumped"])), f"bumped keys, range {rho}"
+
+
+def _check_chain(h, e, r, op, vals_of=None):
+    """Layers 1.. and the final layer of export e equal the oracle's build of
+    those layers from the GPU's own layer-1 keys."""
+    k1 = h.layer_keys(1)
+    v1 = None if vals_of is None else vals_of(k1)
+    print(f"[large] oracle chain from layer 1: {len(k1)} keys", flush=True)
+    part = oracle.build(k1, v1, r, op, threads=THREADS, first_layer=1)
+    ep = export_format.parse(part.export())
+    assert len(ep["layers"]) == len(e["layers"]) - 1
+    for a, b in zip(ep["layers"], e["layers"][1:]):
+        assert a["bytes"] == b["bytes"], f"layer {b['layer']}"
+    assert ep["final"]["bytes"] == e["final"]["bytes"], "final layer"
 
 
 @pytest.mark.parametrize("r", [16, 1])
@@ -114,38 +156,14 @@ def test_billion_key_filter(big, r):
     print(f"[large] r={r}: {fp} false positives, expected {mean:.0f} +- {sd:.0f}", flush=True)
     assert abs(fp - mean) <= 6 * sd
 
-    # sampled ranges: exact codes, solution words and bump sets
-    print("[large] sampled ranges", flush=True)
-    n0, m0, R0, codes, words = _layer0(h.export(), r)
-    assert (n0, m0, R0) == (N, big["m"], big["R"])
-    bumped_gpu = h.layer_keys(1)
-    bsb = oracle.start_buckets(bumped_gpu, 0, big["m"], big["op"])
-    btag = big["lut"][bsb]
-    for i, rho in enumerate(big["rhos"]):
-        first, last = big["bounds"][i]
-        ref = oracle.layer_range(big["members"][rho], None, r, big["op"], 0, N, rho)
-        beta = np.arange(first, last, dtype=np.uint64)
-        got_codes = (codes[beta // 32] >> (2 * (beta % 32))) & 3
-        assert np.array_equal(got_codes.astype(np.uint8), ref["codes"]), f"codes, range {rho}"
-        assert np.array_equal(words[first * r:last * r], ref["W"]), f"words, range {rho}"
-        assert set(bumped_gpu[btag == i].tolist()) == set(ref["bumped"].tolist()), \
-            f"bumped keys, range {rho}"
+    print(f"[large] {len(big['rhos'])} sampled layer-0 ranges", flush=True)
+    e = export_format.parse(h.export())
+    L0 = e["layers"][0]
+    assert (L0["n"], L0["m"], L0["R"]) == (N, big["m"], big["R"])
+    _check_sampled_ranges(e, r, big["op"], N, big["rhos"], big["bounds"], big["members"],
+                          big["lut"], big["m"], h.layer_keys(1))
+    _check_chain(h, e, r, big["op"])
     h.free()
-
-
-def _sampled_ranges(keys, op, n, R_expect, seed):
-    m, B, R = oracle.layer_geometry(op, n)
-    assert R == R_expect
-    sb = oracle.start_buckets(keys, 0, m, op)
-    rng = np.random.default_rng(seed)
-    rhos = sorted({0, 1, R // 2, R - 2, R - 1, *rng.integers(0, R, 3).tolist()})
-    lut = np.full(B, -1, dtype=np.int8)
-    bounds = []
-    for i, rho in enumerate(rhos):
-        first, last = oracle.range_buckets(B, R, rho)
-        lut[first:last] = i
-        bounds.append((first, last))
-    return m, B, R, rhos, bounds, lut, lut[sb]
 
 
 def test_hundred_million_key_retrieval():
@@ -159,26 +177,15 @@ def test_hundred_million_key_retrieval():
     vals = vals_dev.cpu().numpy()
     assert np.array_equal(vals[:1000], W.values(1000, r, 1002))
     op = oracle.Params(ranges=R_expect)
-    m, B, R, rhos, bounds, lut, tag = _sampled_ranges(keys, op, n, R_expect, 22)
-    h = burr.build(keys_dev, vals_dev, r,
-                   burr.Params(ranges=R_expect, flags=burr.BURR_FLAG_KEEP_LAYER_KEYS))
+    h = burr.build(keys_dev, vals_dev, r, burr.Params(ranges=R_expect))
     for lo in range(0, n, CHUNK):
         assert torch.equal(h.query(keys_dev[lo:lo + CHUNK]), vals_dev[lo:lo + CHUNK])
-    n0, m0, R0, codes, words = _layer0(h.export(), r)
-    assert (n0, m0, R0) == (n, m, R)
-    bumped_gpu = h.layer_keys(1)
-    btag = lut[oracle.start_buckets(bumped_gpu, 0, m, op)]
-    sel = np.flatnonzero(tag >= 0)
-    for i, rho in enumerate(rhos):
-        first, last = bounds[i]
-        idx = sel[tag[sel] == i]
-        ref = oracle.layer_range(keys[idx], vals[idx], r, op, 0, n, rho)
-        beta = np.arange(first, last, dtype=np.uint64)
-        got_codes = (codes[beta // 32] >> (2 * (beta % 32))) & 3
-        assert np.array_equal(got_codes.astype(np.uint8), ref["codes"]), f"codes, range {rho}"
-        assert np.array_equal(words[first * r:last * r], ref["W"]), f"words, range {rho}"
-        assert set(bumped_gpu[btag == i].tolist()) == set(ref["bumped"].tolist()), \
-            f"bumped keys, range {rho}"
+    print(f"[large] oracle build of all {n} keys on {THREADS} threads", flush=True)
+    ref = oracle.build(keys, vals, r, op, threads=THREADS)
+    got = h.export()
+    want = ref.export()
+    assert len(got) == len(want)
+    assert got == want, "100M-key export differs from the oracle's"
     h.free()
 
 
@@ -188,23 +195,36 @@ def test_two_hundred_thousand_structure_batch():
     sizes = W.batch_sizes(count, 4)
     rs = np.random.default_rng(4).integers(1, 4, size=count).astype(np.uint32)
     offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
-    N = int(offs[-1])
+    NK = int(offs[-1])
     dev = torch.device("cuda:0")
-    print(f"[large] batch of {count} structures, {N} keys", flush=True)
-    keys_dev = W.keys_device(N, 4, dev)
-    vals_dev = (W.splitmix64_device(1004, 0, N, dev) & 0xFF).to(torch.uint8)
+    print(f"[large] batch of {count} structures, {NK} keys", flush=True)
+    keys_dev = W.keys_device(NK, 4, dev)
+    vals_dev = (W.splitmix64_device(1004, 0, NK, dev) & 0xFF).to(torch.uint8)
+    keys = keys_dev.cpu().numpy().view(np.uint64)
+    vals = vals_dev.cpu().numpy()
     params = burr.Params(ranges=1 << 16)
+    op = oracle.Params(ranges=1 << 16)
     b = burr.build_batch(keys_dev, vals_dev, offs, rs, params)
-    order = np.argsort(sizes, kind="stable")
-    picks = sorted({int(order[0]), int(order[-1]), int(order[count // 2]),
-                    *np.random.default_rng(44).integers(0, count, 29).tolist(),
-                    *order[-8:].tolist()})
-    for i in picks:
-        lo, hi, r = int(offs[i]), int(offs[i + 1]), int(rs[i])
-        mk = W.keys(hi - lo, 4, lo)
-        mv = (W.splitmix64(1004, lo, hi - lo) & np.uint64((1 << r) - 1)).astype(np.uint8)
-        ref = oracle.build(mk, mv, r, oracle.Params(ranges=1 << 16))
-        hm = b.member(i)
-        assert hm.export() == ref.export(), f"member {i} ({hi - lo} keys, r={r})"
-        assert torch.equal(hm.query(keys_dev[lo:hi]), vals_dev[lo:hi] & ((1 << r) - 1))
+
+    def oracle_export(i):
+        lo, hi, ri = int(offs[i]), int(offs[i + 1]), int(rs[i])
+        mv = vals[lo:hi] & np.uint8((1 << ri) - 1)
+        return oracle.build(keys[lo:hi], mv, ri, op).export()
+
+    print(f"[large] every member against the oracle on {THREADS} threads", flush=True)
+    bad = []
+    with cf.ThreadPoolExecutor(max_workers=THREADS) as pool:
+        for lo in range(0, count, 20_000):
+            idx = range(lo, min(count, lo + 20_000))
+            refs = pool.map(oracle_export, idx)
+            for i, ref in zip(idx, refs):
+                if b.member(i).export() != ref:
+                    bad.append(i)
+            print(f"[large] members checked: {idx[-1] + 1}", flush=True)
+    assert not bad, f"{len(bad)} members differ, first {bad[:5]}"
+    # members retrieve their values (spot check across the size range)
+    for i in np.linspace(0, count - 1, 200).astype(int):
+        lo, hi, ri = int(offs[i]), int(offs[i + 1]), int(rs[i])
+        assert torch.equal(b.member(int(i)).query(keys_dev[lo:hi]),
+                           vals_dev[lo:hi] & ((1 << ri) - 1))
     b.free()
