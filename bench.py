@@ -82,24 +82,50 @@ def measured_traffic(kernel_key):
     return None
 
 
-def cpu_baseline(n_sample):
-    import numpy as np  # noqa: F401
+def host_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
+def cpu_baseline(keys, vals, n_sample):
+    """The oracle on the host: (1) the plain sequential builder on one core
+    over the first n_sample keys of the workload's streams (same ~23 buckets
+    per range), (2) its range-parallel driver (the paper's scheme: each thread
+    solves its own ranges; byte-identical output) on every host core over the
+    whole workload."""
     import oracle
-    from paper_2411_12365_amd import workload as W
-    keys = W.keys(n_sample, 2)
-    vals = W.values(n_sample, R_BITS, 1002)
+    n = len(keys)
     ranges = max(1, round(RANGES * n_sample / N_KEYS))
     t0 = time.perf_counter()
-    ref = oracle.build(keys, vals, R_BITS, oracle.Params(ranges=ranges))
+    ref = oracle.build(keys[:n_sample], vals[:n_sample], R_BITS, oracle.Params(ranges=ranges))
     dt = time.perf_counter() - t0
+    del ref
+    threads = os.cpu_count() or 1
+    ranges_all = max(1, round(RANGES * n / N_KEYS))
+    t0 = time.perf_counter()
+    ref = oracle.build(keys, vals, R_BITS, oracle.Params(ranges=ranges_all), threads=threads)
+    dt_all = time.perf_counter() - t0
     del ref
     return {
         "value": round(n_sample / dt / 1e6, 3),
         "unit": "Mkeys/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"first {n_sample:,} keys of the same key/value streams, {ranges} ranges "
+        "sample": f"first {n_sample:,} keys of the workload's key/value streams, {ranges} ranges "
                   f"(same ~23 buckets per range), full build incl. all layers; {dt:.1f} s",
+        "all_cores": {"value": round(n / dt_all / 1e6, 3), "unit": "Mkeys/s", "cores": threads,
+                      "kind": "oracle, range-parallel driver (output equal to the sequential "
+                              "oracle byte for byte)",
+                      "sample": f"the whole workload: {n:,} keys, {ranges_all} ranges; "
+                                f"{dt_all:.1f} s"},
+        "host": host_info(),
     }
 
 
@@ -116,38 +142,196 @@ def _device_stream(gen, n, dtype, dev, chunk=100_000_000):
 
 
 SWEEP_RANGES = [1 << 8, 1 << 10, 1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 19]
+SWEEP_MINBPT = [2, 4, 8, 16, 32, 64, 128, 256, 1000]
+MODES = {"2bit": 0, "1plus": 1}
+CUT_NAMES = {0: "equal", 1: "minbump", 2: "maxprev", 3: "diff"}
 
 
-def run_space_sweep(keys, vals, n):
-    """Space of the 100M-key build against its number of ranges (the GPU
-    analog of the paper's space overhead per thread, Sec. 5 Fig. 3/4): every
-    range end bumps keys into deeper layers and adds table bits."""
-    import numpy as np
+def _timed_build(keys, vals, p, reps=1):
+    """Table bytes, per-layer stats and best build ms of `reps` builds after a warm-up."""
     import paper_2411_12365_amd as burr
-    pts = []
-    for R in SWEEP_RANGES:
-        p = burr.Params(ranges=R, minbpt=2)
-        burr.build(keys, vals, R_BITS, p).free()
+    burr.build(keys, vals, R_BITS, p).free()
+    best, st = None, None
+    for _ in range(reps):
         t0 = time.perf_counter()
         h = burr.build(keys, vals, R_BITS, p)
-        dt = time.perf_counter() - t0
+        dt = (time.perf_counter() - t0) * 1e3
         st = h.stats()
         h.free()
+        best = dt if best is None else min(best, dt)
+    return st, best
+
+
+def run_sweeps(keys, vals, n):
+    """Space against the number of ranges (the GPU analog of the paper's
+    space overhead per thread, Sec. 4 Fig. 3 and 4) for both threshold
+    modes: every range end bumps keys into deeper layers and adds table bits;
+    the same with the minimum buckets per range varied (Fig. 4: space against
+    speed); and the cut-point strategies against fixed cuts (Fig. 5)."""
+    import numpy as np
+    import paper_2411_12365_amd as burr
+    out = {"workload": f"the {n:,}-key build above (r={R_BITS}); table bytes = thresholds + "
+                       f"solution words of every layer (cut points excluded)"}
+    # 1. range count, both threshold modes (minbpt 2 so the count is the cap)
+    pts = {}
+    for mode, tm in MODES.items():
+        pts[mode] = []
+        for R in SWEEP_RANGES:
+            st, ms = _timed_build(keys, vals, burr.Params(ranges=R, minbpt=2, threshold_mode=tm))
+            L0 = st["layers"][0]
+            pts[mode].append({"ranges": L0["nranges"],
+                              "buckets_per_range": round(L0["nbuckets"] / L0["nranges"], 1),
+                              "table_bytes": st["table_bytes"],
+                              "bits_per_key": round(st["table_bytes"] * 8 / n, 4),
+                              "layer0_bumped_frac": round(L0["bumped"] / n, 5),
+                              "build_ms": round(ms, 2)})
+    fit = {}
+    for mode in MODES:
+        x = np.array([q["ranges"] for q in pts[mode][:5]], dtype=np.float64)
+        y = np.array([q["table_bytes"] for q in pts[mode][:5]], dtype=np.float64)
+        fit[mode] = round(float(np.polyfit(x, y, 1)[0]), 1)
+    out["ranges"] = {"points": pts, "overhead_bytes_per_range": fit,
+                     "fit": f"least squares over {SWEEP_RANGES[0]}..{SWEEP_RANGES[4]} ranges"}
+    # 2. minimum buckets per range (ranges capped at 2^20)
+    mp = {}
+    for mode, tm in MODES.items():
+        mp[mode] = []
+        for mb in SWEEP_MINBPT:
+            st, ms = _timed_build(keys, vals, burr.Params(ranges=1 << 20, minbpt=mb,
+                                                          threshold_mode=tm))
+            mp[mode].append({"minbpt": mb, "ranges_layer0": st["layers"][0]["nranges"],
+                             "table_bytes": st["table_bytes"],
+                             "bits_per_key": round(st["table_bytes"] * 8 / n, 4),
+                             "build_ms": round(ms, 2),
+                             "Mkeys_per_s": round(n / ms / 1e3, 1)})
+    out["minbpt"] = mp
+    # 3. cut-point search (search range 50) against the equal split
+    cs = {}
+    for R in (1 << 16, 1 << 12):
+        for mode, tm in MODES.items():
+            row = {}
+            base = None
+            for strat, name in CUT_NAMES.items():
+                p = burr.Params(ranges=R, minbpt=2, threshold_mode=tm, cut_strategy=strat,
+                                cut_search=50 if strat else 0)
+                st, ms = _timed_build(keys, vals, p)
+                tb = st["table_bytes"]
+                if base is None:
+                    base = tb
+                row[name] = {"table_bytes": tb, "build_ms": round(ms, 2),
+                             "bytes_saved_per_boundary": round((base - tb) / (R - 1), 2)}
+            cs[f"{R}_ranges_{mode}"] = row
+    out["cut_search"] = cs
+    return out
+
+
+def run_c1(args, dev):
+    """Plain single-structure BuRR: 1M keys, one range (no boundary bumping)."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2411_12365_amd as burr
+    from paper_2411_12365_amd import workload as W
+    n = 1_000_000
+    kn, vn = W.keys(n, 1), W.values(n, R_BITS, 1001)
+    keys = torch.from_numpy(kn.view(np.int64)).to(dev)
+    vals = torch.from_numpy(vn).to(dev)
+    p = burr.Params(ranges=1)
+    for _ in range(3):
+        burr.build(keys, vals, R_BITS, p).free()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(20):
+        t0 = time.perf_counter()
+        h = burr.build(keys, vals, R_BITS, p)
+        ms.append((time.perf_counter() - t0) * 1e3)
+        st = h.stats()
+        exp = h.export()
+        h.free()
+    t0 = time.perf_counter()
+    ref = oracle.build(kn, vn, R_BITS, oracle.Params(ranges=1))
+    dt = time.perf_counter() - t0
+    ms = np.array(ms)
+    return {"workload": "1,000,000 keys, r=8, one range, 3 layers + final", "n": n,
+            "build_ms_p50": round(float(np.percentile(ms, 50)), 3),
+            "build_ms_p99": round(float(np.percentile(ms, 99)), 3),
+            "Mkeys_per_s": round(n / float(np.percentile(ms, 50)) / 1e3, 1),
+            "device_total_ms": round(st["ms_total"], 3),
+            "bits_per_key": round(st["table_bytes"] * 8 / n, 4),
+            "export_equals_oracle": exp == ref.export(),
+            "oracle_1core_Mkeys_per_s": round(n / dt / 1e6, 3)}
+
+
+def _kernel_rates(L, r, kv):
+    """Per-kernel device ms (hipEvents on the build stream) and GB/s against
+    the algorithmic bytes of layer L: the sort reads the input and makes one
+    out-of-place grouping pass, the insertion reads the item stream and writes
+    the placed rows, back-substitution reads the rows and writes the
+    solution, the gather moves the bumped keys."""
+    n, B, m, bumped = L["n"], L["nbuckets"], L["m"], L["bumped"]
+    pivots = n - bumped
+    bytes_ = {"sort": 3 * kv * n,
+              "solve": 16 * (n + B) + 4 * (B + 1) + 12 * pivots + m // 8 + 5 * B,
+              "backsub": 12 * m + m * r // 8,
+              "gather": 16 * bumped + 12 * bumped}
+    out = {}
+    for k, b in bytes_.items():
+        ms = L["ms_" + k]
+        out[k] = {"ms": round(ms, 3), "GBps": round(b / (ms / 1e3) / 1e9, 1) if ms > 0 else None,
+                  "algorithmic_bytes": b}
+    return out
+
+
+def run_c3(args, dev):
+    """Large filter builds: 1B keys, 2^18 ranges, r in {16, 1}; queries and the
+    false-positive rate on 10^9 non-members."""
+    import numpy as np
+    import torch
+    import paper_2411_12365_amd as burr
+    from paper_2411_12365_amd import workload as W
+    n, chunk = 1_000_000_000, 100_000_000
+    keys = W.keys_device(n, 3, dev)
+    out = {"workload": "1,000,000,000 keys (SplitMix64 stream 3), filter mode, 2^18 ranges, "
+                       "queries: 10^9 non-members (counters >= n)"}
+    for r in (16, 1):
+        p = burr.Params(ranges=1 << 18, filter_mode=1)
+        burr.build(keys, None, r, p).free()
+        ms = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            h = burr.build(keys, None, r, p)
+            ms.append((time.perf_counter() - t0) * 1e3)
+            st = h.stats()
+            if len(ms) < 3:
+                h.free()
+        # 10^9 non-member queries, timed with events on the current stream
+        qms, fp = 0.0, 0
+        outb = torch.empty(chunk, dtype=torch.uint8, device=dev)
+        for lo in range(0, n, chunk):
+            q = W.keys_device(chunk, 3, dev, start=n + lo)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            h.contains(q, outb)
+            e1.record()
+            torch.cuda.synchronize()
+            qms += e0.elapsed_time(e1)
+            fp += int(outb.sum())
+            del q
+        h.free()
+        p_fp = 2.0 ** -r
         L0 = st["layers"][0]
-        pts.append({"ranges": L0["nranges"],
-                    "buckets_per_range": round(L0["nbuckets"] / L0["nranges"], 1),
-                    "table_bytes": st["table_bytes"],
-                    "bits_per_key": round(st["table_bytes"] * 8 / n, 4),
-                    "layer0_bumped_frac": round(L0["bumped"] / n, 5),
-                    "build_ms": round(dt * 1e3, 2)})
-    x = np.array([q["ranges"] for q in pts[:5]], dtype=np.float64)
-    y = np.array([q["table_bytes"] for q in pts[:5]], dtype=np.float64)
-    slope = float(np.polyfit(x, y, 1)[0])
-    return {"workload": f"the {n:,}-key build above (r={R_BITS}) with minbpt 2 and the "
-                        f"layer-0 range count varied",
-            "points": pts,
-            "overhead_bytes_per_range": round(slope, 1),
-            "fit": f"least squares over {int(x[0])}..{int(x[-1])} ranges"}
+        out[f"r{r}"] = {
+            "build_ms_p50": round(float(np.median(ms)), 2),
+            "Gkeys_per_s": round(n / float(np.median(ms)) / 1e6, 2),
+            "device_total_ms": round(st["ms_total"], 2),
+            "bits_per_key": round(st["table_bytes"] * 8 / n, 4),
+            "layer0_kernels": _kernel_rates(L0, r, 8),
+            "query_ms": round(qms, 2), "query_Gq_per_s": round(n / qms / 1e6, 2),
+            "false_positives": fp, "fpr": fp / n,
+            "fpr_expected": p_fp, "fpr_sigma": (p_fp * (1 - p_fp) / n) ** 0.5,
+        }
+    del keys
+    return out
 
 
 TUNE_CLASSES = [250, 1000, 4000, 16_000, 64_000, 200_000]  # size classes (max keys)
@@ -239,6 +423,9 @@ def run_batched(args, dev):
         "layer0_device_ms": {k: round(st["layers"][0][k], 3) for k in
                              ("ms_sort", "ms_solve", "ms_backsub", "ms_gather")},
         "device_total_ms": round(st["ms_total"], 2),
+        # what launching from the host costs beyond the device's own time: the
+        # most a graph-captured replay of the whole batch could save
+        "host_overhead_ms": round(float(np.percentile(ms, 50)) - st["ms_total"], 2),
         "autotune": {"seconds": round(t_tune, 2),
                      "trials": "coordinate descent on whole batches of every 4th structure's "
                                "size (synthetic keys), best of 2 builds each",
@@ -356,6 +543,61 @@ def run_serving(args, dev):
         return dict(wall_s=wall, requests=len(lat[1]) + len(lat[2]) + failed, lat=lat, keys=keys_done, ok=ok,
                     failed=failed, peak_gb=info["peak_bytes"] / 2**30, batches=info["batches"])
 
+    def plain_run(nb, rate, seed):
+        """The same request stream served one request at a time, each a plain
+        burr_build or burr_query (no concurrency, no packing): latency is
+        completion minus arrival."""
+        bsz = W.serving_sizes(nb, seed, "build")
+        qsz = W.serving_sizes(nb * QPB, seed + 1, "query")
+        tb = W.poisson_arrivals(nb, rate / (1 + QPB), seed + 2)
+        tq = W.poisson_arrivals(nb * QPB, rate * QPB / (1 + QPB), seed + 3)
+        events = sorted([(t, 0, i) for i, t in enumerate(tb)] +
+                        [(t, 1, i) for i, t in enumerate(tq)])
+        off = 0
+        built = {}  # build index -> (handle, pool offset, n, queries answered)
+        resident = []
+        lat = {1: [], 2: []}
+        keys_done = {1: 0, 2: 0}
+        rng = np.random.default_rng(seed + 4)
+        last_build = None
+        t0 = time.perf_counter()
+        for t, kind, i in events:
+            now = time.perf_counter() - t0
+            if now < t:
+                time.sleep(t - now)
+            if kind == 0:
+                n = int(bsz[i])
+                if off + n > pool_n:
+                    off = 0
+                h = burr.build(pool_k[off:off + n], pool_v[off:off + n], 8, params)
+                built[i] = [h, off, n, 0]
+                resident.append(i)
+                last_build = i
+                off += n
+                lat[1].append((time.perf_counter() - t0 - t) * 1e3)
+                keys_done[1] += n
+            else:
+                cands = [b for b in resident if built[b][3] < QPB]
+                bi = cands[int(rng.integers(len(cands)))] if cands else last_build
+                if bi is None or built[bi][3] >= QPB:
+                    continue
+                h, so, sn, _ = built[bi]
+                q = int(qsz[i])
+                lo = max(0, so + sn - q // 2)
+                hi = min(pool_n, lo + q)
+                h.query(pool_k[lo:hi])
+                torch.cuda.synchronize()
+                lat[2].append((time.perf_counter() - t0 - t) * 1e3)
+                keys_done[2] += hi - lo
+                built[bi][3] += 1
+                if built[bi][3] == QPB:
+                    resident.remove(bi)
+                    h.free()
+        wall = time.perf_counter() - t0
+        for b in resident:
+            built[b][0].free()
+        return dict(wall_s=wall, lat=lat, keys=keys_done)
+
     nb = args.serve_builds
     print(f"# serving: saturation burst", file=sys.stderr, flush=True)
     sat = one_run(max(20, nb // 4), 0, 50, burst=True)
@@ -364,6 +606,8 @@ def run_serving(args, dev):
     for load in [float(x) for x in args.serve_loads.split(",") if x]:
         print(f"# serving: load {load}", file=sys.stderr, flush=True)
         r = one_run(nb, load * rate_sat, 60 + int(load * 100))
+        print(f"# serving: load {load}, one request at a time", file=sys.stderr, flush=True)
+        pr = plain_run(nb, load * rate_sat, 60 + int(load * 100))
         levels.append({
             "load": load, "offered_req_per_s": round(load * rate_sat, 1),
             "requests": r["requests"], "wall_s": round(r["wall_s"], 3),
@@ -373,11 +617,19 @@ def run_serving(args, dev):
             "query_Mkeys_per_s": round(r["keys"][2] / r["wall_s"] / 1e6, 1),
             "batched_builds": r["batches"], "failed": r["failed"],
             "peak_budget_GiB": round(r["peak_gb"], 2), "results_ok": r["ok"],
+            "one_request_at_a_time": {
+                "wall_s": round(pr["wall_s"], 3),
+                "build_ms_p50": _pct(pr["lat"][1], 50), "build_ms_p99": _pct(pr["lat"][1], 99),
+                "query_ms_p50": _pct(pr["lat"][2], 50), "query_ms_p99": _pct(pr["lat"][2], 99),
+                "build_Mkeys_per_s": round(pr["keys"][1] / pr["wall_s"] / 1e6, 1),
+                "query_Mkeys_per_s": round(pr["keys"][2] / pr["wall_s"] / 1e6, 1)},
         })
     return {
-        "workload": "Poisson arrivals: builds log-normal 1e3..1e7 keys (median 1e5, r=8), "
-                    "query batches log-normal 1e4..1e6 keys (median 1e5, half members), 8 query "
-                    "batches per structure then dropped; 4 workers; 200 GiB budget",
+        "workload": f"Poisson arrivals: {nb} builds per load, log-normal 1e3..1e7 keys (median "
+                    f"1e5, r=8), query batches log-normal 1e4..1e6 keys (median 1e5, half "
+                    f"members), 8 query batches per structure then dropped; 4 workers; 200 GiB "
+                    f"budget; each load also served one request at a time with plain "
+                    f"burr_build/burr_query (the same arrivals)",
         "saturated_req_per_s": round(rate_sat, 1),
         "levels": levels,
     }
@@ -390,18 +642,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=N_KEYS)
     ap.add_argument("--queries", type=int, default=N_KEYS)
-    ap.add_argument("--cpu-sample", type=int, default=10_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=30_000_000,
+                    help="keys of the one-core oracle leg (the all-cores leg builds all n)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-structures", type=int, default=200_000)
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--batch-single-sample", type=int, default=2000,
                     help="structures built one by one for the per-structure baseline")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--serve-builds", type=int, default=200,
+    ap.add_argument("--serve-builds", type=int, default=2000,
                     help="build requests per load level (8 query batches per build)")
     ap.add_argument("--serve-loads", type=str, default="0.5,0.8,0.95")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-space-sweep", action="store_true")
+    ap.add_argument("--no-space-sweep", action="store_true",
+                    help="skip the range / minbpt / cut-point sweeps")
+    ap.add_argument("--no-c1", action="store_true")
+    ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB once (a plain copy kernel of "
                          "known size, for scaling hardware byte counters)")
@@ -554,7 +810,7 @@ def main():
     del qkeys, out
     if not args.no_space_sweep:
         print("# space sweep", file=sys.stderr, flush=True)
-        res["space_sweep"] = run_space_sweep(keys, vals, n)
+        res["sweeps"] = run_sweeps(keys, vals, n)
     del keys, vals
     if args.calibration_copy_mib:
         src = torch.ones(args.calibration_copy_mib << 18, dtype=torch.int32, device=dev)
@@ -565,6 +821,17 @@ def main():
         del src, dst
     torch.cuda.empty_cache()
     # secondary sections: a failure is reported in the JSON line, not raised
+    if not args.no_c1:
+        print("# C1: 1M keys, one range", file=sys.stderr, flush=True)
+        res["c1"] = run_c1(args, dev)
+    if not args.no_c3:
+        print("# C3: 1B-key filters", file=sys.stderr, flush=True)
+        try:
+            res["c3"] = run_c3(args, dev)
+        except (burr.BurrError, torch.cuda.OutOfMemoryError) as e:
+            res["c3"] = {"error": str(e)}
+        burr.burr_release_workspaces()
+        torch.cuda.empty_cache()
     if not args.no_serve:
         # the serving loop starts without the build workspaces the section
         # above left in the library's cache; its own builds use per-build
@@ -585,7 +852,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(min(args.cpu_sample, n))
+        res["cpu_baseline"] = cpu_baseline(keys_np, vals_np, min(args.cpu_sample, n))
     print(json.dumps(res))
 
 

@@ -246,7 +246,9 @@ burr_batch* burr_build_batch_tuned(const uint64_t* keys, const void* values,
  *  - With a size sample (sizes[], nsizes structure sizes, e.g. a sample of
  *    the batches to be built): coordinate descent on whole batches of that
  *    mix. Every class starts at p->minbpt; class by class, a candidate
- *    replaces it only if the mixed batch builds more than 3 % faster.
+ *    replaces it if the mixed batch builds more than 3 % faster, or if it
+ *    gives smaller tables (fewer bits per key) at no more than 3 % above the
+ *    fastest time so far and above the untuned batch's time.
  *  - Without (sizes NULL): each class is timed alone, as batches of about
  *    keys_per_trial keys of structures of the geometric middle of the class
  *    (from n_max[c-1], or n_max[0]/4, to n_max[c]); out[c] keeps the fastest

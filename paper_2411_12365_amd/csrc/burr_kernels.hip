@@ -1127,8 +1127,10 @@ __device__ inline void clear_half(WaveRing<LANES>& R, const Grp<LANES>& G, uint3
 }
 
 // 8 waves per SIMD: the kernel then fits 64 VGPRs (no spills), and the
-// ring and stage of 32 waves (3.75 KB each) fit a CU's LDS.
-template <int LANES>
+// ring and stage of 32 waves (3.75 KB each) fit a CU's LDS. ONE_PLUS: the
+// instantiation for 1+-bit thresholds of BuRR layers (the 2-bit one carries
+// no code of the threshold bisection).
+template <int LANES, bool ONE_PLUS>
 __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
   constexpr uint32_t NG = 64 / LANES;
   constexpr uint32_t SP = Stage<LANES>::per_lane;
@@ -1204,7 +1206,7 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
     // offset + 1 (kf: 2-bit code index, or 1+-bit threshold value)
     const bool at_end = !g.plain && !last_range && q + 1 == nq && maxo > 0;
     const uint32_t kf = !at_end ? 0u
-                      : g.thr_mode == 1 ? maxo + 1u
+                      : ONE_PLUS ? maxo + 1u
                       : (maxo >= g.t_hi ? 3u : (maxo >= g.t_lo ? 2u : 1u));
     const uint32_t e1 = hd.z, e2 = hd.z + hd.w;  // ends of ranks 0 and 1
     // claims past the range end: only from its last bucket, without a spill buffer
@@ -1218,13 +1220,14 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
       return res == 3 ? wave_pass<LANES, false>(R, G, a, rec4, hq, q, r0, r1, last_half, steps, sst)
                       : res;
     };
-    const bool one_plus = g.thr_mode == 1 && !g.plain;
+    constexpr bool one_plus = ONE_PLUS;
     // 1+-bit: kf > 0 lies above every offset, so then nothing is a candidate
     const uint32_t keep_ranks = g.plain ? 3u : 3u - kf;
     const uint32_t cand = one_plus ? (kf == 0 ? count : 0u)
                         : keep_ranks == 3 ? count : (keep_ranks == 2 ? e2 : (keep_ranks == 1 ? e1 : 0u));
     uint32_t kept = cand, code = kf;
-    if (cand > 0 && one_plus) {
+    if constexpr (ONE_PLUS) {
+     if (cand > 0) {
       // records ordered by offset, highest first: the records with offset
       // >= theta are a prefix of the bucket; its length from ballots over
       // the staged offsets (records past the stage from the item stream)
@@ -1280,6 +1283,7 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
         }
         failed = true;
       }
+     }
     } else if (cand > 0) {
       uint32_t res = pass(0, cand);
       if (res == 1 && g.plain) {
@@ -1350,7 +1354,11 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
 hipError_t solve_layer(const SolveArgs& a, hipStream_t s) {
   if (a.g.nranges == 0) return hipSuccess;
   constexpr int NG = 64 / BURR_SOLVE_LANES;
-  k_solve_wave<BURR_SOLVE_LANES><<<(unsigned)((a.g.nranges + NG - 1) / NG), 64, 0, s>>>(a);
+  const unsigned grid = (unsigned)((a.g.nranges + NG - 1) / NG);
+  if (a.g.thr_mode == 1 && !a.g.plain)
+    k_solve_wave<BURR_SOLVE_LANES, true><<<grid, 64, 0, s>>>(a);
+  else
+    k_solve_wave<BURR_SOLVE_LANES, false><<<grid, 64, 0, s>>>(a);
   return hipGetLastError();
 }
 

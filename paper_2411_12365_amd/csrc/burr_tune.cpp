@@ -63,8 +63,11 @@ double time_batch(const uint64_t* keys, const void* vals, const std::vector<uint
 }
 
 // Tuning on a mix of structure sizes: coordinate descent over the classes,
-// starting from p->minbpt everywhere; a class takes another candidate only
-// if the whole mixed batch builds more than 3 % faster with it.
+// starting from p->minbpt everywhere; a class takes another candidate if the
+// whole mixed batch builds more than 3 % faster with it, or if its tables are
+// smaller while it stays within 3 % of the fastest time seen and of the
+// untuned batch's time (space counts where time is a draw, as in the paper's
+// Fig. 4 trade-off; the 3 % margin is above the timing noise of the repeats).
 int tune_mix(const burr_params* p, uint32_t r, const uint64_t* sizes, uint64_t nsizes,
              const uint64_t* n_max, uint32_t nclasses, const uint32_t* candidates,
              uint32_t ncandidates, uint32_t reps, burr_tune_entry* out) {
@@ -94,6 +97,8 @@ int tune_mix(const burr_params* p, uint32_t r, const uint64_t* sizes, uint64_t n
   double bits = 0;
   double cur = time_batch(in.keys, in.vals, off, rs, p, table, reps, &bits, &rc);
   if (rc != BURR_OK) return burr_set_error(rc);
+  const double untuned = cur;
+  double fastest = cur;  // fastest mixed batch seen
   for (uint32_t c = 0; c < nclasses; ++c) {
     const uint32_t keep = table[c].minbpt;
     uint32_t best = keep;
@@ -104,11 +109,14 @@ int tune_mix(const burr_params* p, uint32_t r, const uint64_t* sizes, uint64_t n
       double b2 = 0;
       const double t = time_batch(in.keys, in.vals, off, rs, p, table, reps, &b2, &rc);
       if (rc != BURR_OK) return burr_set_error(rc);
-      if (t < best_t * 0.97) {
+      const bool faster = t < best_t * 0.97;
+      const bool smaller = b2 < best_bits && t <= fastest * 1.03 && t <= untuned * 1.03;
+      if (faster || smaller) {
         best = candidates[k];
         best_t = t;
         best_bits = b2;
       }
+      fastest = std::min(fastest, t);
     }
     table[c].minbpt = best;
     cur = best_t;
