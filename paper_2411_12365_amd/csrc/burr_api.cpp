@@ -377,7 +377,7 @@ struct Workspace {
   uint64_t cap_seg = 0, cap_tab[2] = {0, 0}, cap_J = 0, cap_c1 = 0, cap_c2 = 0, cap_plan = 0;
   uint64_t* keysA = nullptr;  // next layer's keys
   uint32_t* valsA = nullptr;
-  uint4 *p1 = nullptr, *p2 = nullptr;  // sort intermediates
+  uint4 *p1 = nullptr, *p2 = nullptr;  // sort intermediates (12- or 16-byte records)
   uint32_t *counts1 = nullptr, *counts2 = nullptr;
   uint32_t *binlo = nullptr, *nch = nullptr, *cbase = nullptr, *sstart = nullptr;
   Rec* rec = nullptr;
@@ -653,8 +653,8 @@ int run_sort(Workspace& ws, const uint64_t* keys, const void* vals, uint32_t vby
   a.nch = ws.nch;
   a.cbase = ws.cbase;
   a.sstart = ws.sstart;
-  a.p1 = ws.p1;
-  a.p2 = ws.p2;
+  a.r1 = ws.p1;
+  a.r2 = ws.p2;
   a.out_rec = ws.rec;
   a.bstart = ws.bstart;
   HIP_TRY(sort_layer(a, s));

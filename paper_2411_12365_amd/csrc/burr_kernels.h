@@ -47,8 +47,8 @@ struct SortArgs {
   uint32_t* nch;          // nb1 + 1
   uint32_t* cbase;        // nb1 + 1
   uint32_t* sstart;       // nsub + 1
-  uint4* p1;              // nkeys intermediate records (level 1 output)
-  uint4* p2;              // nkeys intermediate records (level 2 output)
+  void* r1;               // nkeys intermediate records of 12 or 16 bytes (level 1 output)
+  void* r2;               // the same, level 2 output
   Rec* out_rec;           // item stream (nkeys + nbuckets)
   uint32_t* bstart;       // B + 1 bucket start offsets
 };

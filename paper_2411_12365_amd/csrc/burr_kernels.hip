@@ -274,15 +274,40 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_hist(const uint64_t* __rest
     counts[(size_t)i * sp.G1 + blockIdx.x] = hist[i];
 }
 
+// Intermediate records of the partition levels. PACKED (every value fits
+// 8 bits, every slot within a level-1 bin fits 24): 12 bytes {key low, key
+// high, slot | value << 24}, one dwordx3 access; else 16 bytes {key low, key
+// high, value, slot}.
+template <bool PACKED>
+struct PRec {
+  using T = uint4;
+  __device__ static T make(uint64_t key, uint32_t slot, uint32_t v) {
+    return make_uint4((uint32_t)key, (uint32_t)(key >> 32), v, slot);
+  }
+  __device__ static uint32_t slot(const T& r) { return r.w; }
+  __device__ static uint4 unpack(const T& r) { return r; }  // {key lo, key hi, value, slot}
+};
+template <>
+struct PRec<true> {
+  using T = uint3;
+  __device__ static T make(uint64_t key, uint32_t slot, uint32_t v) {
+    return make_uint3((uint32_t)key, (uint32_t)(key >> 32), slot | (v << 24));
+  }
+  __device__ static uint32_t slot(const T& r) { return r.z & 0xffffffu; }
+  __device__ static uint4 unpack(const T& r) {
+    return make_uint4(r.x, r.y, r.z >> 24, r.z & 0xffffffu);
+  }
+};
+
 // Orders one tile of records by digit in LDS and writes every digit's part
 // as a run at that digit's cursor (cur[d] advances by the tile's count).
 // rec/dig/rank: each thread's kPartPer records (dig = kNoDigit: none).
 constexpr uint32_t kNoDigit = 0xffffffffu;
-template <int NT>
-__device__ inline void tile_write(uint4 (&rec)[kPartPer], uint32_t (&dig)[kPartPer],
-                                  uint32_t (&rank)[kPartPer], uint32_t D, uint32_t* cur,
-                                  uint32_t* toff, uint4* stage, uint16_t* sdig, uint32_t* wsum,
-                                  uint32_t ntile, uint4* __restrict__ out) {
+template <int NT, class R>
+__device__ inline void tile_write(const R (&rec)[kPartPer], const uint32_t (&dig)[kPartPer],
+                                  const uint32_t (&rank)[kPartPer], uint32_t D, uint32_t* cur,
+                                  uint32_t* toff, R* stage, uint16_t* sdig, uint32_t* wsum,
+                                  uint32_t ntile, R* __restrict__ out) {
   lds_scan<NT>(toff, D, wsum);  // tile counts -> tile offsets
 #pragma unroll
   for (int k = 0; k < kPartPer; ++k)
@@ -308,10 +333,10 @@ template <int NT>
 __host__ __device__ constexpr size_t part_lds_bytes(uint32_t D) {
   return (size_t)(2 * D + 2 + NT / 64 + 2) * 4 + 15 + (size_t)NT * kPartPer * 18;
 }
-template <int NT>
+template <int NT, class R>
 struct PartLds {
   uint32_t *cur, *toff, *wsum;
-  uint4* stage;
+  R* stage;
   uint16_t* sdig;
   __device__ PartLds(uint32_t* sm, uint32_t D) {
     cur = sm;
@@ -319,19 +344,21 @@ struct PartLds {
     wsum = toff + D + 2;
     uint8_t* p = reinterpret_cast<uint8_t*>(wsum + NT / 64 + 2);
     p = reinterpret_cast<uint8_t*>(((uintptr_t)p + 15) & ~(uintptr_t)15);
-    stage = reinterpret_cast<uint4*>(p);
+    stage = reinterpret_cast<R*>(p);
     sdig = reinterpret_cast<uint16_t*>(stage + NT * kPartPer);
   }
 };
 
 // Level 1, pass 2: hash, mask or fingerprint the value, write tile runs per bin.
-template <typename VT>
+template <typename VT, bool PACKED>
 __global__ __launch_bounds__(kPartThreads) void k_p1_scatter(
     const uint64_t* __restrict__ keys, const VT* __restrict__ vals, LayerGeom g, SortPlan sp,
     const uint32_t* __restrict__ offs, uint32_t mask_values, uint32_t filter, uint64_t fp_salt,
-    uint4* __restrict__ out) {
+    void* __restrict__ out_raw) {
+  using R = typename PRec<PACKED>::T;
   extern __shared__ uint32_t sm[];
-  PartLds<kPartThreads> L(sm, sp.nb1);
+  PartLds<kPartThreads, R> L(sm, sp.nb1);
+  R* out = reinterpret_cast<R*>(out_raw);
   for (uint32_t d = threadIdx.x; d < sp.nb1; d += kPartThreads) {
     L.cur[d] = offs[(size_t)d * sp.G1 + blockIdx.x];
     L.toff[d] = 0;
@@ -342,7 +369,7 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_scatter(
   const uint64_t bin_slots = (uint64_t)sp.S * kSubSlots;
   KeyWalk w(g, lo + threadIdx.x);
   for (uint64_t t0 = lo; t0 < hi; t0 += kTile) {
-    uint4 rec[kPartPer];
+    R rec[kPartPer];
     uint32_t dig[kPartPer], rank[kPartPer];
     // all of a thread's loads are issued before the first is used (past
     // the end, the last key is read again and not used)
@@ -359,6 +386,7 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_scatter(
     for (int k = 0; k < kPartPer; ++k) {
       const uint64_t i = t0 + threadIdx.x + (uint64_t)k * kPartThreads;
       dig[k] = kNoDigit;
+      rank[k] = 0;
       if (i < hi) {
         w.advance(g, i);
         const uint64_t key = kk[k];
@@ -371,16 +399,15 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_scatter(
           v = vv[k];
         const uint64_t slot = 64 * w.bb + start_of(key, g.salt_s, w.span);
         const uint32_t d = (uint32_t)(slot / bin_slots);
-        rec[k] = make_uint4((uint32_t)key, (uint32_t)(key >> 32), v,
-                            (uint32_t)(slot - (uint64_t)d * bin_slots));
+        rec[k] = PRec<PACKED>::make(key, (uint32_t)(slot - (uint64_t)d * bin_slots), v);
         dig[k] = d;
         rank[k] = atomicAdd(&L.toff[d], 1u);
       }
     }
     const uint32_t ntile = (uint32_t)(hi - t0 < kTile ? hi - t0 : kTile);
     __syncthreads();
-    tile_write<kPartThreads>(rec, dig, rank, sp.nb1, L.cur, L.toff, L.stage, L.sdig, L.wsum,
-                             ntile, out);
+    tile_write<kPartThreads, R>(rec, dig, rank, sp.nb1, L.cur, L.toff, L.stage, L.sdig, L.wsum,
+                                ntile, out);
   }
 }
 
@@ -441,12 +468,15 @@ __device__ inline bool chunk2_of(uint32_t wg, const SortPlan& sp, const uint32_t
 
 // Level 2, pass 1: keys per sub-bin of each chunk; counts2 is laid out per
 // bin as [sub-bin][chunk] so that one scan gives every run's position.
-__global__ __launch_bounds__(kPart2Threads) void k_p2_hist(const uint4* __restrict__ in,
+template <bool PACKED>
+__global__ __launch_bounds__(kPart2Threads) void k_p2_hist(const void* __restrict__ in_raw,
                                                           SortPlan sp,
                                                           const uint32_t* __restrict__ binlo,
                                                           const uint32_t* __restrict__ nch,
                                                           const uint32_t* __restrict__ cbase,
                                                           uint32_t* __restrict__ counts) {
+  using R = typename PRec<PACKED>::T;
+  const R* in = reinterpret_cast<const R*>(in_raw);
   extern __shared__ uint32_t hist[];
   Chunk2 ch;
   if (!chunk2_of(blockIdx.x, sp, binlo, nch, cbase, ch)) return;
@@ -458,7 +488,7 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_hist(const uint4* __restri
 #pragma unroll
     for (int k = 0; k < kHistPer; ++k) {
       const uint32_t i = t0 + threadIdx.x + k * kPart2Threads;
-      if (i < ch.hi) sl[k] = in[i].w;
+      if (i < ch.hi) sl[k] = PACKED ? (in[i].z & 0xffffffu) : reinterpret_cast<const uint4*>(in)[i].w;
     }
 #pragma unroll
     for (int k = 0; k < kHistPer; ++k)
@@ -471,14 +501,18 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_hist(const uint4* __restri
 }
 
 // Level 2, pass 2: tile runs per sub-bin.
+template <bool PACKED>
 __global__ __launch_bounds__(kPart2Threads) void k_p2_scatter(
-    const uint4* __restrict__ in, SortPlan sp, const uint32_t* __restrict__ binlo,
+    const void* __restrict__ in_raw, SortPlan sp, const uint32_t* __restrict__ binlo,
     const uint32_t* __restrict__ nch, const uint32_t* __restrict__ cbase,
-    const uint32_t* __restrict__ offs, uint4* __restrict__ out) {
+    const uint32_t* __restrict__ offs, void* __restrict__ out_raw) {
+  using R = typename PRec<PACKED>::T;
+  const R* in = reinterpret_cast<const R*>(in_raw);
+  R* out = reinterpret_cast<R*>(out_raw);
   extern __shared__ uint32_t sm[];
   Chunk2 ch;
   if (!chunk2_of(blockIdx.x, sp, binlo, nch, cbase, ch)) return;
-  PartLds<kPart2Threads> L(sm, sp.S);
+  PartLds<kPart2Threads, R> L(sm, sp.S);
   const uint32_t nc = nch[ch.b];
   for (uint32_t d = threadIdx.x; d < sp.S; d += kPart2Threads) {
     L.cur[d] = offs[ch.base + d * nc + ch.c];
@@ -487,12 +521,12 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_scatter(
   __syncthreads();
   constexpr uint32_t T2 = kPart2Threads * kPartPer;
   for (uint32_t t0 = ch.lo; t0 < ch.hi; t0 += T2) {
-    uint4 rec[kPartPer];
+    R rec[kPartPer];
     uint32_t dig[kPartPer], rank[kPartPer];
 #pragma unroll
     for (int k = 0; k < kPartPer; ++k) {  // loads first, then the counting atomics
       const uint32_t i = t0 + threadIdx.x + k * kPart2Threads;
-      rec[k] = make_uint4(0, 0, 0, 0);
+      rec[k] = R{};
       if (i < ch.hi) rec[k] = in[i];
     }
 #pragma unroll
@@ -501,14 +535,14 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_scatter(
       dig[k] = kNoDigit;
       rank[k] = 0;
       if (i < ch.hi) {
-        dig[k] = rec[k].w / kSubSlots;
+        dig[k] = PRec<PACKED>::slot(rec[k]) / kSubSlots;
         rank[k] = atomicAdd(&L.toff[dig[k]], 1u);
       }
     }
     const uint32_t ntile = ch.hi - t0 < T2 ? ch.hi - t0 : T2;
     __syncthreads();
-    tile_write<kPart2Threads>(rec, dig, rank, sp.S, L.cur, L.toff, L.stage, L.sdig, L.wsum,
-                              ntile, out);
+    tile_write<kPart2Threads, R>(rec, dig, rank, sp.S, L.cur, L.toff, L.stage, L.sdig, L.wsum,
+                                 ntile, out);
   }
 }
 
@@ -538,7 +572,13 @@ __global__ void k_p2_starts(SortPlan sp, uint64_t nkeys, const uint32_t* __restr
 __host__ __device__ constexpr size_t l3_lds_bytes(uint32_t D) {
   return (size_t)kL3Cap * sizeof(uint4) + ((size_t)kSubBuckets * D + 1) * 4;
 }
-__global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict__ in,
+// a level-2 record as {key low, key high, value, slot within the level-1 bin}
+template <bool PACKED>
+__device__ inline uint4 part_rec(const void* in, uint32_t i) {
+  return PRec<PACKED>::unpack(reinterpret_cast<const typename PRec<PACKED>::T*>(in)[i]);
+}
+template <bool PACKED, uint32_t D>
+__global__ __launch_bounds__(kL3Threads) void k_p3_sort(const void* __restrict__ in,
                                                         LayerGeom g, SortPlan sp,
                                                         const uint32_t* __restrict__ sstart,
                                                         Rec* __restrict__ items,
@@ -547,7 +587,6 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict_
   __shared__ uint32_t nzero[kSubBuckets];
   __shared__ uint32_t wsum[kL3Threads / 64 + 2];
   extern __shared__ uint4 stage[];  // kL3Cap items, then the digit counters
-  const uint32_t D = digits_per_bucket(g);
   uint32_t* dcur = reinterpret_cast<uint32_t*>(stage + kL3Cap);
   const uint32_t nd = kSubBuckets * D;
   const uint32_t sb = blockIdx.x;
@@ -573,7 +612,7 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict_
 #pragma unroll
     for (int k = 0; k < kL3Per; ++k) {  // loads first, then the counting atomics
       const uint32_t i = lo + threadIdx.x + k * kL3Threads;
-      if (i < hi) rec[k] = in[i];
+      if (i < hi) rec[k] = part_rec<PACKED>(in, i);
     }
 #pragma unroll
     for (int k = 0; k < kL3Per; ++k) {
@@ -590,7 +629,7 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict_
     }
   } else {
     for (uint32_t i = lo + threadIdx.x; i < hi; i += kL3Threads) {
-      const uint32_t sl = in[i].w - slot0;
+      const uint32_t sl = part_rec<PACKED>(in, i).w - slot0;
       const uint32_t bl = sl >> 6, o = sl & 63u;
       atomicAdd(&dcur[bl * D + digit(o)], 1u);
       atomicMax(&maxoff[bl], o);
@@ -654,7 +693,7 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict_
   }
   __syncthreads();
   for (uint32_t i = lo + threadIdx.x; i < hi; i += kL3Threads) {
-    const uint4 r = in[i];
+    const uint4 r = part_rec<PACKED>(in, i);
     const uint32_t sl = r.w - slot0;
     const uint32_t bl = sl >> 6, o = sl & 63u;
     const uint32_t dg = digit(o);
@@ -664,10 +703,10 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const uint4* __restrict_
   }
 }
 
-hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
+template <bool PACKED>
+hipError_t sort_layer_t(const SortArgs& a, hipStream_t s) {
   const SortPlan& sp = a.plan;
   const uint64_t n = a.g.nkeys;
-  if (n == 0) return hipErrorInvalidValue;
   hipError_t e;
   k_p1_hist<<<sp.G1, kPartThreads, (size_t)sp.nb1 * 4, s>>>(a.keys, a.g, sp, a.counts1);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -675,45 +714,64 @@ hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
   const size_t lds1 = part_lds_bytes<kPartThreads>(sp.nb1);
   switch (a.vbytes) {
     case 1:
-      k_p1_scatter<uint8_t><<<sp.G1, kPartThreads, lds1, s>>>(
+      k_p1_scatter<uint8_t, PACKED><<<sp.G1, kPartThreads, lds1, s>>>(
           a.keys, (const uint8_t*)a.vals, a.g, sp, a.counts1, a.mask_values, a.filter,
-          a.fp_salt, a.p1);
+          a.fp_salt, a.r1);
       break;
     case 2:
-      k_p1_scatter<uint16_t><<<sp.G1, kPartThreads, lds1, s>>>(
+      k_p1_scatter<uint16_t, PACKED><<<sp.G1, kPartThreads, lds1, s>>>(
           a.keys, (const uint16_t*)a.vals, a.g, sp, a.counts1, a.mask_values, a.filter,
-          a.fp_salt, a.p1);
+          a.fp_salt, a.r1);
       break;
     default:
-      k_p1_scatter<uint32_t><<<sp.G1, kPartThreads, lds1, s>>>(
+      k_p1_scatter<uint32_t, PACKED><<<sp.G1, kPartThreads, lds1, s>>>(
           a.keys, (const uint32_t*)a.vals, a.g, sp, a.counts1, a.mask_values, a.filter,
-          a.fp_salt, a.p1);
+          a.fp_salt, a.r1);
       break;
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_p2_plan<<<1, kPartThreads, 0, s>>>(a.counts1, sp, n, a.binlo, a.nch, a.cbase);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t lds3 = l3_lds_bytes(digits_per_bucket(a.g));
-  (void)hipFuncSetAttribute((const void*)k_p3_sort, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)l3_lds_bytes(64));
-  if (sp.S == 1) {  // the bins are the sub-bins: level 3 reads level 1's output
-    k_p3_sort<<<sp.nsub, kL3Threads, lds3, s>>>(a.p1, a.g, sp, a.binlo, a.out_rec, a.bstart);
+  // level 3 with the digits per bucket of the layer (one per chunk or per offset)
+  const bool by_offset = digits_per_bucket(a.g) == 64;
+  auto level3 = [&](const void* in, const uint32_t* starts) {
+    if (by_offset) {
+      (void)hipFuncSetAttribute((const void*)k_p3_sort<PACKED, 64>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3_lds_bytes(64));
+      k_p3_sort<PACKED, 64><<<sp.nsub, kL3Threads, l3_lds_bytes(64), s>>>(in, a.g, sp, starts,
+                                                                          a.out_rec, a.bstart);
+    } else {
+      (void)hipFuncSetAttribute((const void*)k_p3_sort<PACKED, 3>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3_lds_bytes(3));
+      k_p3_sort<PACKED, 3><<<sp.nsub, kL3Threads, l3_lds_bytes(3), s>>>(in, a.g, sp, starts,
+                                                                        a.out_rec, a.bstart);
+    }
     return hipGetLastError();
-  }
+  };
+  if (sp.S == 1)  // the bins are the sub-bins: level 3 reads level 1's output
+    return level3(a.r1, a.binlo);
   const size_t n2 = (size_t)sp.U2 * sp.S;
   if ((e = hipMemsetAsync(a.counts2, 0, (n2 + 1) * 4, s)) != hipSuccess) return e;
-  k_p2_hist<<<sp.U2, kPart2Threads, (size_t)sp.S * 4, s>>>(a.p1, sp, a.binlo, a.nch, a.cbase,
-                                                           a.counts2);
+  k_p2_hist<PACKED><<<sp.U2, kPart2Threads, (size_t)sp.S * 4, s>>>(a.r1, sp, a.binlo, a.nch,
+                                                                   a.cbase, a.counts2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = scan_exclusive(a.counts2, n2, a.scan_tmp, s)) != hipSuccess) return e;
-  k_p2_scatter<<<sp.U2, kPart2Threads, part_lds_bytes<kPart2Threads>(sp.S), s>>>(
-      a.p1, sp, a.binlo, a.nch, a.cbase, a.counts2, a.p2);
+  k_p2_scatter<PACKED><<<sp.U2, kPart2Threads, part_lds_bytes<kPart2Threads>(sp.S), s>>>(
+      a.r1, sp, a.binlo, a.nch, a.cbase, a.counts2, a.r2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_p2_starts<<<(sp.nsub + 256) / 256, 256, 0, s>>>(sp, n, a.binlo, a.nch, a.cbase, a.counts2,
                                                      a.sstart);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_p3_sort<<<sp.nsub, kL3Threads, lds3, s>>>(a.p2, a.g, sp, a.sstart, a.out_rec, a.bstart);
-  return hipGetLastError();
+  return level3(a.r2, a.sstart);
+}
+
+// Values ride in the top byte of the meta word when every value fits 8 bits
+// and every slot within a level-1 bin fits its low 24 bits.
+hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
+  if (a.g.nkeys == 0) return hipErrorInvalidValue;
+  const uint64_t bin_slots = (uint64_t)a.plan.S * kSubSlots;
+  if (a.g.r <= 8 && bin_slots <= (1ull << 24)) return sort_layer_t<true>(a, s);
+  return sort_layer_t<false>(a, s);
 }
 
 // ---------------------------------------------------------------------------
