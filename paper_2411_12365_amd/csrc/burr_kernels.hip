@@ -1,15 +1,18 @@
 // burr_kernels.hip - HIP kernels of the BuRR library for gfx950 (CDNA4).
 //
 // Per layer (Sec. 2 and Sec. 3 of the paper):
-//   sort      : two-level partition of the keys by (bucket, chunk); level 1
-//               scatters into coarse bins of 2048 buckets through LDS
-//               histograms, level 2 orders one bin per workgroup in LDS and
-//               writes 16-byte records (row + value/offset/chunk)
+//   sort      : partition of the keys by (bucket, chunk) in up to three
+//               levels (bins, 64-bucket sub-bins, then (bucket, chunk) inside
+//               a sub-bin), each writing contiguous runs ordered in LDS; the
+//               output is the item stream (a header per bucket + 16-byte
+//               records: key, value, offset, chunk)
 //   solve     : one wave per range; the lanes insert a bucket's records
 //               together (banded GF(2) elimination against a 128-row ring in
-//               LDS, claims by compare-and-swap), bucket by bucket, 2-bit
-//               thresholds from chunk prefixes, forced bumps at range ends
-//   backsub   : one lane per range, column-interleaved output words
+//               LDS, claims by compare-and-swap), bucket by bucket, thresholds
+//               from chunk prefixes (2-bit) or by bisection (1+-bit), forced
+//               bumps at range ends
+//   backsub   : a group of lanes per range, one lane per value column,
+//               column-interleaved output words
 //   gather    : bumped keys (a suffix of every bucket) -> next layer input
 //   query     : one lane per key, layer walk, two-word window, popcount parity
 #include "burr_kernels.h"
