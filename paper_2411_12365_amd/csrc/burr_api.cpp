@@ -921,6 +921,34 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     if (!side) return set_error(BURR_E_DEVICE);
   }
   auto bs_end = [&](uint32_t li) { return ev[1 + 7 * (size_t)li + 4]; };  // layer li's back-substitution done
+  // A layer's back-substitution is queued once the next layer's insertion is
+  // queued, and starts when the next layer's sort is done (the last BuRR
+  // layer's is queued before the final layer): its grid fills the device, so
+  // started right after the layer's insertion it held back the gather of the
+  // bumped keys and the next sort, which are on the build's critical path;
+  // beside the next insertion it overlaps the deeper layers' small launches.
+  // Layer li+2 reuses layer li's row set and table buffer only after waiting
+  // for bs_end(li), which is recorded by then.
+  struct PendingBacksub {
+    bool on = false;
+    uint32_t li = 0;
+    int set = 0;
+    LayerGeom g{};
+    uint64_t* W = nullptr;
+  } pend;
+  // after: an event of the build's stream the back-substitution also waits
+  // for (the next layer's sort done), or null
+  auto launch_backsub = [&](hipEvent_t after) -> int {
+    if (!pend.on) return BURR_OK;
+    pend.on = false;
+    hipEvent_t* const e = ev + 1 + 7 * (size_t)pend.li;
+    HIP_TRY(hipStreamWaitEvent(side, e[2], 0));
+    if (after) HIP_TRY(hipStreamWaitEvent(side, after, 0));
+    HIP_TRY(hipEventRecord(e[3], side));
+    HIP_TRY(back_substitute(ws.rowsC[pend.set], ws.rowsV[pend.set], pend.g, pend.W, side));
+    HIP_TRY(hipEventRecord(e[4], side));
+    return BURR_OK;
+  };
   if (!ws.reserve_keys(off.back()) || (!ws.diag && !ws.alloc(ws.diag, 16)))
     return set_error(BURR_E_NOMEM);
   HIP_TRY(hipMemsetAsync(ws.diag, 0, 16 * 8, s));
@@ -1021,12 +1049,15 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     HIP_TRY(hipEventRecord(el[1], s));
     HIP_TRY(solve_layer(sa, s));
     HIP_TRY(hipEventRecord(el[2], s));
-    // back-substitution on the side stream: the deeper layers leave most of
-    // the device idle, so it overlaps with them
-    HIP_TRY(hipStreamWaitEvent(side, el[2], 0));
-    HIP_TRY(hipEventRecord(el[3], side));
-    HIP_TRY(back_substitute(ws.rowsC[set], ws.rowsV[set], g, LS.W, side));
-    HIP_TRY(hipEventRecord(el[4], side));
+    // the previous layer's back-substitution now (side stream), this layer's
+    // once the next layer's insertion is queued
+    rc = launch_backsub(el[1]);
+    if (rc != BURR_OK) return rc;
+    pend.on = true;
+    pend.li = li;
+    pend.set = set;
+    pend.g = g;
+    pend.W = LS.W;
     // codes now: the next layer's insertion rewrites code8
     if (p.threshold_mode == 1)
       HIP_TRY(pack_thresholds(ws.code8, g, t.code_base.back(), LS.codes, ws.pcount, ws.scan_tmp,
@@ -1112,6 +1143,10 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   // not use, after the back-substitution that read it last
   const int fset = (int)(nlayers & 1);
   if (nlayers >= 2) HIP_TRY(hipStreamWaitEvent(s, bs_end(nlayers - 2), 0));
+  {  // the last BuRR layer's back-substitution overlaps the final layer
+    const int rc = launch_backsub(nullptr);
+    if (rc != BURR_OK) return rc;
+  }
   if (!active.empty()) {
     std::vector<uint32_t> zero(active.size(), 0), fails;
     int rc = final_attempt(b, ws, fset, active, zero, cur_keys, cur_vals, cur_vbytes, first, fails);
