@@ -548,7 +548,7 @@ struct Workspace {
            reserve_scan(B + 1);
   }
   bool reserve_sort(const SortPlan& sp) {
-    const uint64_t c1 = (uint64_t)sp.nb1 * sp.G1, c2 = (uint64_t)sp.U2 * sp.S;
+    const uint64_t c1 = (uint64_t)sp.nb1 * sp.G1, c2 = sort_counts2_words(sp);
     const uint64_t pl = std::max<uint64_t>(sp.nb1, sp.nsub) + 1;
     if ((c1 > cap_c1 || !counts1) && !alloc(counts1, (cap_c1 = c1) + 1)) return false;
     if ((c2 > cap_c2 || !counts2) && !alloc(counts2, (cap_c2 = c2) + 1)) return false;

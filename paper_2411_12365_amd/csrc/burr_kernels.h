@@ -19,7 +19,9 @@ hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s
 //   level 2: per bin, partition into its sub-bins of kSubBuckets buckets
 //   level 3: per sub-bin, order by (bucket, chunk) in LDS and write the
 //            item stream (bucket headers + records) and the bucket starts
-// Every level writes contiguous runs (tiles are ordered in LDS first).
+// Every level writes contiguous runs (tiles are ordered in LDS first). When
+// a workgroup's (bin, sub-bin) counters fit in LDS, one counting pass over
+// the keys serves both partition levels (plan.H > 0).
 struct SortPlan {
   uint32_t nsub;       // sub-bins (level-3 workgroups)
   uint32_t nb1;        // level-1 bins
@@ -27,9 +29,15 @@ struct SortPlan {
   uint32_t G1;         // level-1 workgroups
   uint64_t per_group;  // keys per level-1 workgroup
   uint32_t U2;         // level-2 workgroups launched (bound on the chunks)
-  uint32_t pad;
+  uint32_t H;          // fused counting: level-2 chunks per bin (0: a counting pass per level)
+  float invS;          // 1/S rounded to nearest (on the host)
+  uint32_t cs;         // fused counting: level-1 workgroups per level-2 chunk
+  uint32_t cc;         // fused counting: level-1 workgroups per counting workgroup (divides cs)
+  uint32_t Hc;         // fused counting: counting workgroups
 };
 SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets);
+// u32 words of counts2 a plan needs
+uint64_t sort_counts2_words(const SortPlan& sp);
 
 struct SortArgs {
   const uint64_t* keys;   // input keys (g.nkeys), structure j at g.key_off[j]
@@ -41,7 +49,7 @@ struct SortArgs {
   LayerGeom g;
   SortPlan plan;
   uint32_t* counts1;      // nb1 * G1 (+1), scanned in place
-  uint32_t* counts2;      // U2 * S (+1), scanned in place
+  uint32_t* counts2;      // sort_counts2_words(plan), scanned in place
   uint32_t* scan_tmp;     // for the larger of the two scans
   uint32_t* binlo;        // nb1 + 1
   uint32_t* nch;          // nb1 + 1

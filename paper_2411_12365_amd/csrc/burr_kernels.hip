@@ -169,6 +169,27 @@ constexpr uint32_t kL3Cap = kL3Threads * kL3Per;     // items of a sub-bin stage
 // level 2 is skipped.
 constexpr uint32_t kSingleLevelSubs = 128;
 
+// Fused counting (plan.H > 0): counting workgroup c covers the keys of the
+// cc level-1 workgroups [cc c, cc (c+1)) and counts them per (bin, level-1
+// workgroup), which level 1 scatters by, and per (bin, sub-bin) into row c.
+// The records level-1 workgroups [cs h, cs (h+1)) write into bin d are
+// contiguous; they form level 2's chunk (d, h), whose output position for
+// sub-bin s is the number of records of all sub-bins before (d, s) plus
+// those of (d, s) in the rows before the chunk's first row c = h cs/cc - a
+// prefix over the rows. That replaces level 2's own counting pass over the
+// level-1 records. cs is chosen so that a chunk holds about kChunkFused
+// records (most of one level-2 tile), cc so that the counting workgroups
+// fill the device (kCountWgs).
+constexpr uint32_t kCountThreads = 1024;
+constexpr uint32_t kCountSlicesMax = 32;
+constexpr uint32_t kChunkFused = 3800;
+constexpr uint32_t kCountWgs = 512;
+constexpr uint32_t kCountLdsMax = 112 * 1024;  // one counting workgroup per CU
+constexpr uint32_t kColBlock = 32;             // h per block of the prefix over h
+__host__ __device__ constexpr uint64_t count_lds_bytes(uint32_t nb1, uint32_t S, uint32_t cs) {
+  return ((uint64_t)nb1 * S + (uint64_t)nb1 * cs) * 4;
+}
+
 SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets) {
   SortPlan p{};
   p.nsub = (uint32_t)((nbuckets + kSubBuckets - 1) / kSubBuckets);
@@ -187,7 +208,27 @@ SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets) {
   p.G1 = (uint32_t)g;
   p.per_group = (nkeys + p.G1 - 1) / p.G1;
   p.U2 = (uint32_t)(nkeys / kChunk2 + p.nb1 + 1);
+  p.invS = 1.0f / (float)p.S;
+  p.H = 0;
+  uint64_t cs = ((uint64_t)kChunkFused * p.nb1 + p.per_group / 2) / p.per_group;
+  cs = cs < 1 ? 1 : (cs > kCountSlicesMax ? kCountSlicesMax : cs);
+  uint32_t cc = (p.G1 + kCountWgs - 1) / kCountWgs;  // counting rows: about kCountWgs
+  if (cc > cs) cc = (uint32_t)cs;
+  p.cs = (uint32_t)((cs + cc - 1) / cc * cc);  // a multiple of cc
+  p.cc = cc;
+  if (p.S > 1 && count_lds_bytes(p.nb1, p.S, p.cc) <= kCountLdsMax) {
+    p.H = (p.G1 + p.cs - 1) / p.cs;
+    p.Hc = (p.G1 + p.cc - 1) / p.cc;
+    p.U2 = p.nb1 * p.H;
+  }
   return p;
+}
+
+uint64_t sort_counts2_words(const SortPlan& sp) {
+  if (!sp.H) return (uint64_t)sp.U2 * sp.S + 1;
+  const uint64_t nds = (uint64_t)sp.nb1 * sp.S;
+  const uint64_t hb = (sp.Hc + kColBlock - 1) / kColBlock;
+  return nds * sp.Hc + nds * hb + nds + 1;  // counts per (row, sub-bin), block prefixes, sub-bin starts
 }
 
 // Threads walk their keys in increasing index order: the structure of the
@@ -213,6 +254,28 @@ struct KeyWalk {
       ++j;
       load(g);
     }
+  }
+};
+
+// Level-1 bin of a global slot and the slot's offset within the bin. A bin
+// is S sub-bins of kSubSlots slots, so the bin is the global sub-bin index
+// (below 2^24, checked when the layer is sorted) divided by S, computed in
+// single precision from 1/S rounded on the host: the index and S are exact,
+// the rounded product is off by less than one and one integer step corrects
+// it (a 64-bit integer division took most of the level-1 kernels' issue).
+struct BinSplit {
+  uint32_t S;
+  float inv;  // 1/S
+  __device__ explicit BinSplit(const SortPlan& sp) : S(sp.S), inv(sp.invS) {}
+  __device__ uint32_t bin(uint64_t slot, uint32_t& in_bin) const {
+    const uint32_t gsb = (uint32_t)(slot / kSubSlots);
+    uint32_t d = (uint32_t)((float)gsb * inv);
+    if (d * S > gsb)
+      --d;
+    else if ((d + 1) * S <= gsb)
+      ++d;
+    in_bin = (gsb - d * S) * kSubSlots + (uint32_t)(slot % kSubSlots);
+    return d;
   }
 };
 
@@ -251,7 +314,7 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_hist(const uint64_t* __rest
   __syncthreads();
   const uint64_t lo = (uint64_t)blockIdx.x * sp.per_group;
   const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
-  const uint64_t bin_slots = (uint64_t)sp.S * kSubSlots;
+  const BinSplit bs(sp);
   KeyWalk w(g, lo + threadIdx.x);
   for (uint64_t t0 = lo; t0 < hi; t0 += kHistPer * kPartThreads) {
     // all of a thread's loads are issued before the first is used (past
@@ -268,13 +331,121 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_hist(const uint64_t* __rest
       if (i < hi) {
         w.advance(g, i);
         const uint64_t slot = 64 * w.bb + start_of(kk[k], g.salt_s, w.span);
-        atomicAdd(&hist[(uint32_t)(slot / bin_slots)], 1u);
+        uint32_t in_bin;
+        atomicAdd(&hist[bs.bin(slot, in_bin)], 1u);
       }
     }
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < sp.nb1; i += kPartThreads)
     counts[(size_t)i * sp.G1 + blockIdx.x] = hist[i];
+}
+
+// Fused counting pass: per (bin, level-1 workgroup) into counts1 ([bin][w]
+// layout, as k_p1_hist) and per (bin, sub-bin) into counts2t[h][d*S+s].
+__global__ __launch_bounds__(kCountThreads) void k_p1_count(const uint64_t* __restrict__ keys,
+                                                            LayerGeom g, SortPlan sp,
+                                                            uint32_t* __restrict__ counts1,
+                                                            uint32_t* __restrict__ counts2t) {
+  extern __shared__ uint32_t sm[];
+  const uint32_t nds = sp.nb1 * sp.S;
+  uint32_t* h2 = sm;        // per (bin, sub-bin)
+  uint32_t* h1 = sm + nds;  // per (bin, slice)
+  for (uint32_t i = threadIdx.x; i < nds + sp.nb1 * sp.cc; i += kCountThreads) sm[i] = 0;
+  __syncthreads();
+  const BinSplit bs(sp);
+  for (uint32_t wl = 0; wl < sp.cc; ++wl) {
+    const uint64_t w = (uint64_t)blockIdx.x * sp.cc + wl;
+    if (w >= sp.G1) break;
+    const uint64_t lo = w * sp.per_group;
+    const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
+    if (lo >= hi) break;
+    KeyWalk kw(g, lo + threadIdx.x);
+    for (uint64_t t0 = lo; t0 < hi; t0 += kHistPer * kCountThreads) {
+      uint64_t kk[kHistPer];  // all loads issued before the first is used
+#pragma unroll
+      for (int k = 0; k < kHistPer; ++k) {
+        const uint64_t i = t0 + threadIdx.x + (uint64_t)k * kCountThreads;
+        kk[k] = keys[i < hi ? i : hi - 1];
+      }
+#pragma unroll
+      for (int k = 0; k < kHistPer; ++k) {
+        const uint64_t i = t0 + threadIdx.x + (uint64_t)k * kCountThreads;
+        if (i < hi) {
+          kw.advance(g, i);
+          const uint64_t slot = 64 * kw.bb + start_of(kk[k], g.salt_s, kw.span);
+          uint32_t in_bin;
+          const uint32_t d = bs.bin(slot, in_bin);
+          const uint32_t sb = in_bin / kSubSlots;
+          atomicAdd(&h2[d * sp.S + sb], 1u);
+          atomicAdd(&h1[d * sp.cc + wl], 1u);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < sp.nb1 * sp.cc; i += kCountThreads) {
+    const uint32_t d = i / sp.cc;
+    const uint64_t w = (uint64_t)blockIdx.x * sp.cc + (i - d * sp.cc);
+    if (w < sp.G1) counts1[(size_t)d * sp.G1 + w] = h1[i];
+  }
+  uint32_t* out = counts2t + (size_t)blockIdx.x * nds;
+  for (uint32_t i = threadIdx.x; i < nds; i += kCountThreads) out[i] = h2[i];
+}
+
+// Prefix over h of counts2t[h][x] (x = d*S+s), in three steps around a scan
+// of the sub-bin totals: block sums over kColBlock consecutive h ...
+__global__ __launch_bounds__(256) void k_col_blocksum(const uint32_t* __restrict__ c2t,
+                                                      uint32_t nds, uint32_t H,
+                                                      uint32_t* __restrict__ psum) {
+  const uint32_t x = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t hb = blockIdx.y;
+  if (x >= nds) return;
+  const uint32_t h0 = hb * kColBlock;
+  const uint32_t h1 = h0 + kColBlock < H ? h0 + kColBlock : H;
+  uint32_t v[kColBlock];
+#pragma unroll
+  for (uint32_t k = 0; k < kColBlock; ++k)
+    v[k] = h0 + k < h1 ? c2t[(size_t)(h0 + k) * nds + x] : 0u;
+  uint32_t t = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kColBlock; ++k) t += v[k];
+  psum[(size_t)hb * nds + x] = t;
+}
+// ... block sums to exclusive block prefixes, sub-bin totals to tot[x] ...
+__global__ __launch_bounds__(256) void k_col_blockbase(uint32_t* __restrict__ psum, uint32_t nds,
+                                                       uint32_t HB, uint32_t* __restrict__ tot) {
+  const uint32_t x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= nds) return;
+  uint32_t run = 0;
+  for (uint32_t hb = 0; hb < HB; ++hb) {
+    const uint32_t t = psum[(size_t)hb * nds + x];
+    psum[(size_t)hb * nds + x] = run;
+    run += t;
+  }
+  tot[x] = run;
+}
+// ... and, once tot holds each sub-bin's start, every count to the output
+// position of chunk (d, h) in sub-bin (d, s); tot[nds] = nkeys.
+__global__ __launch_bounds__(256) void k_col_apply(uint32_t* __restrict__ c2t, uint32_t nds,
+                                                   uint32_t H, const uint32_t* __restrict__ psum,
+                                                   uint32_t* __restrict__ tot, uint32_t nkeys) {
+  const uint32_t x = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t hb = blockIdx.y;
+  if (x == 0 && hb == 0) tot[nds] = nkeys;
+  if (x >= nds) return;
+  const uint32_t h0 = hb * kColBlock;
+  const uint32_t h1 = h0 + kColBlock < H ? h0 + kColBlock : H;
+  uint32_t v[kColBlock];
+#pragma unroll
+  for (uint32_t k = 0; k < kColBlock; ++k)
+    v[k] = h0 + k < h1 ? c2t[(size_t)(h0 + k) * nds + x] : 0u;
+  uint32_t run = tot[x] + psum[(size_t)hb * nds + x];
+#pragma unroll
+  for (uint32_t k = 0; k < kColBlock; ++k) {
+    if (h0 + k < h1) c2t[(size_t)(h0 + k) * nds + x] = run;
+    run += v[k];
+  }
 }
 
 // Intermediate records of the partition levels. PACKED (every value fits
@@ -369,7 +540,7 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_scatter(
   __syncthreads();
   const uint64_t lo = (uint64_t)blockIdx.x * sp.per_group;
   const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
-  const uint64_t bin_slots = (uint64_t)sp.S * kSubSlots;
+  const BinSplit bs(sp);
   KeyWalk w(g, lo + threadIdx.x);
   for (uint64_t t0 = lo; t0 < hi; t0 += kTile) {
     R rec[kPartPer];
@@ -401,8 +572,9 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_scatter(
         else
           v = vv[k];
         const uint64_t slot = 64 * w.bb + start_of(key, g.salt_s, w.span);
-        const uint32_t d = (uint32_t)(slot / bin_slots);
-        rec[k] = PRec<PACKED>::make(key, (uint32_t)(slot - (uint64_t)d * bin_slots), v);
+        uint32_t in_bin;
+        const uint32_t d = bs.bin(slot, in_bin);
+        rec[k] = PRec<PACKED>::make(key, in_bin, v);
         dig[k] = d;
         rank[k] = atomicAdd(&L.toff[d], 1u);
       }
@@ -503,23 +675,43 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_hist(const void* __restric
     counts[ch.base + i * nc + ch.c] = hist[i];
 }
 
-// Level 2, pass 2: tile runs per sub-bin.
-template <bool PACKED>
+// Level 2, pass 2: tile runs per sub-bin. FUSED (plan.H > 0): workgroup
+// d*H + h takes chunk (d, h), the run level-1 workgroups [cs h, cs (h+1))
+// wrote into bin d (offs1: the scanned level-1 counts), and its sub-bin
+// positions from the prefixed fused counts (offs).
+template <bool PACKED, bool FUSED>
 __global__ __launch_bounds__(kPart2Threads) void k_p2_scatter(
     const void* __restrict__ in_raw, SortPlan sp, const uint32_t* __restrict__ binlo,
     const uint32_t* __restrict__ nch, const uint32_t* __restrict__ cbase,
-    const uint32_t* __restrict__ offs, void* __restrict__ out_raw) {
+    const uint32_t* __restrict__ offs, const uint32_t* __restrict__ offs1, uint64_t nkeys,
+    void* __restrict__ out_raw) {
   using R = typename PRec<PACKED>::T;
   const R* in = reinterpret_cast<const R*>(in_raw);
   R* out = reinterpret_cast<R*>(out_raw);
   extern __shared__ uint32_t sm[];
   Chunk2 ch;
-  if (!chunk2_of(blockIdx.x, sp, binlo, nch, cbase, ch)) return;
   PartLds<kPart2Threads, R> L(sm, sp.S);
-  const uint32_t nc = nch[ch.b];
-  for (uint32_t d = threadIdx.x; d < sp.S; d += kPart2Threads) {
-    L.cur[d] = offs[ch.base + d * nc + ch.c];
-    L.toff[d] = 0;
+  if constexpr (FUSED) {
+    const uint32_t d = blockIdx.x / sp.H, h = blockIdx.x - d * sp.H;
+    const uint32_t w0 = h * sp.cs;
+    const uint32_t w1 = w0 + sp.cs < sp.G1 ? w0 + sp.cs : sp.G1;
+    ch.lo = offs1[(size_t)d * sp.G1 + w0];
+    ch.hi = w1 < sp.G1 ? offs1[(size_t)d * sp.G1 + w1]
+          : (d + 1 < sp.nb1 ? offs1[(size_t)(d + 1) * sp.G1] : (uint32_t)nkeys);
+    const uint32_t* o = offs + (size_t)h * (sp.cs / sp.cc) * sp.nb1 * sp.S + (size_t)d * sp.S;
+    for (uint32_t x = threadIdx.x; x < sp.S; x += kPart2Threads) {
+      L.cur[x] = o[x];
+      L.toff[x] = 0;
+    }
+  } else {
+    (void)offs1;
+    (void)nkeys;
+    if (!chunk2_of(blockIdx.x, sp, binlo, nch, cbase, ch)) return;
+    const uint32_t nc = nch[ch.b];
+    for (uint32_t d = threadIdx.x; d < sp.S; d += kPart2Threads) {
+      L.cur[d] = offs[ch.base + d * nc + ch.c];
+      L.toff[d] = 0;
+    }
   }
   __syncthreads();
   constexpr uint32_t T2 = kPart2Threads * kPartPer;
@@ -711,7 +903,15 @@ hipError_t sort_layer_t(const SortArgs& a, hipStream_t s) {
   const SortPlan& sp = a.plan;
   const uint64_t n = a.g.nkeys;
   hipError_t e;
-  k_p1_hist<<<sp.G1, kPartThreads, (size_t)sp.nb1 * 4, s>>>(a.keys, a.g, sp, a.counts1);
+  const size_t nds = (size_t)sp.nb1 * sp.S;
+  if (sp.H) {  // one counting pass for both partition levels
+    const size_t lds = count_lds_bytes(sp.nb1, sp.S, sp.cc);
+    (void)hipFuncSetAttribute((const void*)k_p1_count, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    k_p1_count<<<sp.Hc, kCountThreads, lds, s>>>(a.keys, a.g, sp, a.counts1, a.counts2);
+  } else {
+    k_p1_hist<<<sp.G1, kPartThreads, (size_t)sp.nb1 * 4, s>>>(a.keys, a.g, sp, a.counts1);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = scan_exclusive(a.counts1, (size_t)sp.nb1 * sp.G1, a.scan_tmp, s)) != hipSuccess) return e;
   const size_t lds1 = part_lds_bytes<kPartThreads>(sp.nb1);
@@ -733,8 +933,10 @@ hipError_t sort_layer_t(const SortArgs& a, hipStream_t s) {
       break;
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_p2_plan<<<1, kPartThreads, 0, s>>>(a.counts1, sp, n, a.binlo, a.nch, a.cbase);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (!sp.H) {
+    k_p2_plan<<<1, kPartThreads, 0, s>>>(a.counts1, sp, n, a.binlo, a.nch, a.cbase);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   // level 3 with the digits per bucket of the layer (one per chunk or per offset)
   const bool by_offset = digits_per_bucket(a.g) == 64;
   auto level3 = [&](const void* in, const uint32_t* starts) {
@@ -753,14 +955,31 @@ hipError_t sort_layer_t(const SortArgs& a, hipStream_t s) {
   };
   if (sp.S == 1)  // the bins are the sub-bins: level 3 reads level 1's output
     return level3(a.r1, a.binlo);
+  if (sp.H) {  // positions of the fused counts: prefix over the rows, sub-bin starts
+    const uint32_t HB = (sp.Hc + kColBlock - 1) / kColBlock;
+    uint32_t* psum = a.counts2 + nds * sp.Hc;
+    uint32_t* tot = psum + nds * HB;  // nds + 1: the sub-bin starts
+    const dim3 gb((unsigned)((nds + 255) / 256), HB);
+    k_col_blocksum<<<gb, 256, 0, s>>>(a.counts2, (uint32_t)nds, sp.Hc, psum);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_col_blockbase<<<(unsigned)((nds + 255) / 256), 256, 0, s>>>(psum, (uint32_t)nds, HB, tot);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan_exclusive(tot, nds, a.scan_tmp, s)) != hipSuccess) return e;
+    k_col_apply<<<gb, 256, 0, s>>>(a.counts2, (uint32_t)nds, sp.Hc, psum, tot, (uint32_t)n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_p2_scatter<PACKED, true><<<sp.U2, kPart2Threads, part_lds_bytes<kPart2Threads>(sp.S), s>>>(
+        a.r1, sp, a.binlo, a.nch, a.cbase, a.counts2, a.counts1, n, a.r2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return level3(a.r2, tot);
+  }
   const size_t n2 = (size_t)sp.U2 * sp.S;
   if ((e = hipMemsetAsync(a.counts2, 0, (n2 + 1) * 4, s)) != hipSuccess) return e;
   k_p2_hist<PACKED><<<sp.U2, kPart2Threads, (size_t)sp.S * 4, s>>>(a.r1, sp, a.binlo, a.nch,
                                                                    a.cbase, a.counts2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = scan_exclusive(a.counts2, n2, a.scan_tmp, s)) != hipSuccess) return e;
-  k_p2_scatter<PACKED><<<sp.U2, kPart2Threads, part_lds_bytes<kPart2Threads>(sp.S), s>>>(
-      a.r1, sp, a.binlo, a.nch, a.cbase, a.counts2, a.r2);
+  k_p2_scatter<PACKED, false><<<sp.U2, kPart2Threads, part_lds_bytes<kPart2Threads>(sp.S), s>>>(
+      a.r1, sp, a.binlo, a.nch, a.cbase, a.counts2, nullptr, n, a.r2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_p2_starts<<<(sp.nsub + 256) / 256, 256, 0, s>>>(sp, n, a.binlo, a.nch, a.cbase, a.counts2,
                                                      a.sstart);
@@ -772,6 +991,7 @@ hipError_t sort_layer_t(const SortArgs& a, hipStream_t s) {
 // and every slot within a level-1 bin fits its low 24 bits.
 hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
   if (a.g.nkeys == 0) return hipErrorInvalidValue;
+  if (a.plan.nsub >= (1u << 24)) return hipErrorInvalidValue;  // level-1 bin arithmetic
   const uint64_t bin_slots = (uint64_t)a.plan.S * kSubSlots;
   if (a.g.r <= 8 && bin_slots <= (1ull << 24)) return sort_layer_t<true>(a, s);
   return sort_layer_t<false>(a, s);
