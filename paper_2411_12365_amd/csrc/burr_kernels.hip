@@ -151,9 +151,15 @@ hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s
 // Intermediate records (16 B): key, value | slot within the bin << 32.
 // 4 records per thread: level 1 takes 82 VGPRs (5 waves per SIMD; with its
 // loads issued together it is faster than at 70 VGPRs and 7 waves, and held
-// to 80 VGPRs it is slower), level 2 takes 48 (8 waves per SIMD); 8 records
-// per thread left 4 waves per SIMD
+// to 80 VGPRs it is slower), level 2 takes 48 (8 waves per SIMD). A level
+// with more than kBigTileDigits digits has tiles of twice as many records,
+// so that a tile still gives each digit a run of about 8 or more: level 1
+// with twice the threads (at 8 records per thread it would take over 128
+// VGPRs), level 2 with 8 records per thread (one 16-wave workgroup per CU)
 constexpr int kPartPer = 4;                         // records per thread of a tile
+constexpr int kPartPerBig = 8;                      // level 2 with many sub-bins
+constexpr int kPart1BigThreads = 1024;              // level 1 with many bins
+constexpr uint32_t kBigTileDigits = 256;
 constexpr int kPartThreads = 2048 / kPartPer;       // level 1: 2048-key tiles
 constexpr int kPart2Threads = 4096 / kPartPer;      // level 2: 4096-key tiles
 constexpr uint32_t kTile = kPartThreads * kPartPer;  // level-1 keys per tile
@@ -475,20 +481,24 @@ struct PRec<true> {
 
 // Orders one tile of records by digit in LDS and writes every digit's part
 // as a run at that digit's cursor (cur[d] advances by the tile's count).
-// rec/dig/rank: each thread's kPartPer records (dig = kNoDigit: none).
+// rec/dr: each thread's PER records and their digit << kRankBits | rank
+// within the digit (kNoDigit: none).
 constexpr uint32_t kNoDigit = 0xffffffffu;
-template <int NT, class R>
-__device__ inline void tile_write(const R (&rec)[kPartPer], const uint32_t (&dig)[kPartPer],
-                                  const uint32_t (&rank)[kPartPer], uint32_t D, uint32_t* cur,
-                                  uint32_t* toff, R* stage, uint16_t* sdig, uint32_t* wsum,
-                                  uint32_t ntile, R* __restrict__ out) {
+constexpr uint32_t kRankBits = 13;  // ranks within a tile of at most 8192 records
+static_assert(kPart2Threads * kPartPerBig <= (1u << kRankBits), "tile rank bits");
+static_assert(kMaxDigits <= (1u << (32 - kRankBits)), "tile digit bits");
+template <int NT, int PER, class R>
+__device__ inline void tile_write(const R (&rec)[PER], const uint32_t (&dr)[PER], uint32_t D,
+                                  uint32_t* cur, uint32_t* toff, R* stage, uint16_t* sdig,
+                                  uint32_t* wsum, uint32_t ntile, R* __restrict__ out) {
   lds_scan<NT>(toff, D, wsum);  // tile counts -> tile offsets
 #pragma unroll
-  for (int k = 0; k < kPartPer; ++k)
-    if (dig[k] != kNoDigit) {
-      const uint32_t pos = toff[dig[k]] + rank[k];
+  for (int k = 0; k < PER; ++k)
+    if (dr[k] != kNoDigit) {
+      const uint32_t d = dr[k] >> kRankBits;
+      const uint32_t pos = toff[d] + (dr[k] & ((1u << kRankBits) - 1u));
       stage[pos] = rec[k];
-      sdig[pos] = (uint16_t)dig[k];
+      sdig[pos] = (uint16_t)d;
     }
   __syncthreads();
   for (uint32_t j = threadIdx.x; j < ntile; j += NT) {
@@ -503,11 +513,12 @@ __device__ inline void tile_write(const R (&rec)[kPartPer], const uint32_t (&dig
 }
 
 // LDS layout of the partition kernels: cur[D], toff[D+1], wsum, stage, sdig
-template <int NT>
-__host__ __device__ constexpr size_t part_lds_bytes(uint32_t D) {
-  return (size_t)(2 * D + 2 + NT / 64 + 2) * 4 + 15 + (size_t)NT * kPartPer * 18;
+// (RB: bytes of a record)
+template <int NT, int PER>
+__host__ __device__ constexpr size_t part_lds_bytes(uint32_t D, size_t RB) {
+  return (size_t)(2 * D + 2 + NT / 64 + 2) * 4 + 15 + (size_t)NT * PER * (RB + 2);
 }
-template <int NT, class R>
+template <int NT, int PER, class R>
 struct PartLds {
   uint32_t *cur, *toff, *wsum;
   R* stage;
@@ -519,21 +530,24 @@ struct PartLds {
     uint8_t* p = reinterpret_cast<uint8_t*>(wsum + NT / 64 + 2);
     p = reinterpret_cast<uint8_t*>(((uintptr_t)p + 15) & ~(uintptr_t)15);
     stage = reinterpret_cast<R*>(p);
-    sdig = reinterpret_cast<uint16_t*>(stage + NT * kPartPer);
+    sdig = reinterpret_cast<uint16_t*>(stage + NT * PER);
   }
 };
 
 // Level 1, pass 2: hash, mask or fingerprint the value, write tile runs per bin.
-template <typename VT, bool PACKED>
-__global__ __launch_bounds__(kPartThreads) void k_p1_scatter(
+template <typename VT, bool PACKED, int NT>
+__global__ __launch_bounds__(NT) void k_p1_scatter(
     const uint64_t* __restrict__ keys, const VT* __restrict__ vals, LayerGeom g, SortPlan sp,
     const uint32_t* __restrict__ offs, uint32_t mask_values, uint32_t filter, uint64_t fp_salt,
-    void* __restrict__ out_raw) {
+    uint32_t fp_late, void* __restrict__ out_raw) {
   using R = typename PRec<PACKED>::T;
   extern __shared__ uint32_t sm[];
-  PartLds<kPartThreads, R> L(sm, sp.nb1);
+  constexpr int PER = kPartPer;
+  const bool no_vals = filter && (mask_values || fp_late);  // values not read
+  PartLds<NT, PER, R> L(sm, sp.nb1);
+  constexpr uint32_t T1 = NT * PER;
   R* out = reinterpret_cast<R*>(out_raw);
-  for (uint32_t d = threadIdx.x; d < sp.nb1; d += kPartThreads) {
+  for (uint32_t d = threadIdx.x; d < sp.nb1; d += NT) {
     L.cur[d] = offs[(size_t)d * sp.G1 + blockIdx.x];
     L.toff[d] = 0;
   }
@@ -542,30 +556,31 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_scatter(
   const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
   const BinSplit bs(sp);
   KeyWalk w(g, lo + threadIdx.x);
-  for (uint64_t t0 = lo; t0 < hi; t0 += kTile) {
-    R rec[kPartPer];
-    uint32_t dig[kPartPer], rank[kPartPer];
+  for (uint64_t t0 = lo; t0 < hi; t0 += T1) {
+    R rec[PER];
+    uint32_t dr[PER];
     // all of a thread's loads are issued before the first is used (past
     // the end, the last key is read again and not used)
-    uint64_t kk[kPartPer];
-    uint32_t vv[kPartPer];
+    uint64_t kk[PER];
+    uint32_t vv[PER];
 #pragma unroll
-    for (int k = 0; k < kPartPer; ++k) {
-      const uint64_t i = t0 + threadIdx.x + (uint64_t)k * kPartThreads;
+    for (int k = 0; k < PER; ++k) {
+      const uint64_t i = t0 + threadIdx.x + (uint64_t)k * NT;
       const uint64_t ic = i < hi ? i : hi - 1;
       kk[k] = keys[ic];
-      vv[k] = filter && mask_values ? 0u : (uint32_t)vals[ic];
+      vv[k] = no_vals ? 0u : (uint32_t)vals[ic];
     }
 #pragma unroll
-    for (int k = 0; k < kPartPer; ++k) {
-      const uint64_t i = t0 + threadIdx.x + (uint64_t)k * kPartThreads;
-      dig[k] = kNoDigit;
-      rank[k] = 0;
+    for (int k = 0; k < PER; ++k) {
+      const uint64_t i = t0 + threadIdx.x + (uint64_t)k * NT;
+      dr[k] = kNoDigit;
       if (i < hi) {
         w.advance(g, i);
         const uint64_t key = kk[k];
         uint32_t v;
-        if (filter && mask_values)
+        if (fp_late)  // fingerprint computed at level 3
+          v = 0;
+        else if (filter && mask_values)
           v = (uint32_t)(mix64(key ^ fp_salt) >> (64 - w.r));
         else if (mask_values)
           v = vv[k] & (w.r >= 32 ? 0xffffffffu : ((1u << w.r) - 1u));
@@ -575,14 +590,12 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_scatter(
         uint32_t in_bin;
         const uint32_t d = bs.bin(slot, in_bin);
         rec[k] = PRec<PACKED>::make(key, in_bin, v);
-        dig[k] = d;
-        rank[k] = atomicAdd(&L.toff[d], 1u);
+        dr[k] = d << kRankBits | atomicAdd(&L.toff[d], 1u);
       }
     }
-    const uint32_t ntile = (uint32_t)(hi - t0 < kTile ? hi - t0 : kTile);
+    const uint32_t ntile = (uint32_t)(hi - t0 < T1 ? hi - t0 : T1);
     __syncthreads();
-    tile_write<kPartThreads, R>(rec, dig, rank, sp.nb1, L.cur, L.toff, L.stage, L.sdig, L.wsum,
-                                ntile, out);
+    tile_write<NT, PER, R>(rec, dr, sp.nb1, L.cur, L.toff, L.stage, L.sdig, L.wsum, ntile, out);
   }
 }
 
@@ -679,7 +692,7 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_hist(const void* __restric
 // d*H + h takes chunk (d, h), the run level-1 workgroups [cs h, cs (h+1))
 // wrote into bin d (offs1: the scanned level-1 counts), and its sub-bin
 // positions from the prefixed fused counts (offs).
-template <bool PACKED, bool FUSED>
+template <bool PACKED, bool FUSED, int PER>
 __global__ __launch_bounds__(kPart2Threads) void k_p2_scatter(
     const void* __restrict__ in_raw, SortPlan sp, const uint32_t* __restrict__ binlo,
     const uint32_t* __restrict__ nch, const uint32_t* __restrict__ cbase,
@@ -690,7 +703,7 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_scatter(
   R* out = reinterpret_cast<R*>(out_raw);
   extern __shared__ uint32_t sm[];
   Chunk2 ch;
-  PartLds<kPart2Threads, R> L(sm, sp.S);
+  PartLds<kPart2Threads, PER, R> L(sm, sp.S);
   if constexpr (FUSED) {
     const uint32_t d = blockIdx.x / sp.H, h = blockIdx.x - d * sp.H;
     const uint32_t w0 = h * sp.cs;
@@ -714,30 +727,29 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_scatter(
     }
   }
   __syncthreads();
-  constexpr uint32_t T2 = kPart2Threads * kPartPer;
+  constexpr uint32_t T2 = kPart2Threads * PER;
   for (uint32_t t0 = ch.lo; t0 < ch.hi; t0 += T2) {
-    R rec[kPartPer];
-    uint32_t dig[kPartPer], rank[kPartPer];
+    R rec[PER];
+    uint32_t dr[PER];
 #pragma unroll
-    for (int k = 0; k < kPartPer; ++k) {  // loads first, then the counting atomics
+    for (int k = 0; k < PER; ++k) {  // loads first, then the counting atomics
       const uint32_t i = t0 + threadIdx.x + k * kPart2Threads;
       rec[k] = R{};
       if (i < ch.hi) rec[k] = in[i];
     }
 #pragma unroll
-    for (int k = 0; k < kPartPer; ++k) {
+    for (int k = 0; k < PER; ++k) {
       const uint32_t i = t0 + threadIdx.x + k * kPart2Threads;
-      dig[k] = kNoDigit;
-      rank[k] = 0;
+      dr[k] = kNoDigit;
       if (i < ch.hi) {
-        dig[k] = PRec<PACKED>::slot(rec[k]) / kSubSlots;
-        rank[k] = atomicAdd(&L.toff[dig[k]], 1u);
+        const uint32_t d = PRec<PACKED>::slot(rec[k]) / kSubSlots;
+        dr[k] = d << kRankBits | atomicAdd(&L.toff[d], 1u);
       }
     }
     const uint32_t ntile = ch.hi - t0 < T2 ? ch.hi - t0 : T2;
     __syncthreads();
-    tile_write<kPart2Threads, R>(rec, dig, rank, sp.S, L.cur, L.toff, L.stage, L.sdig, L.wsum,
-                                 ntile, out);
+    tile_write<kPart2Threads, PER, R>(rec, dr, sp.S, L.cur, L.toff, L.stage, L.sdig, L.wsum,
+                                      ntile, out);
   }
 }
 
@@ -777,7 +789,8 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const void* __restrict__
                                                         LayerGeom g, SortPlan sp,
                                                         const uint32_t* __restrict__ sstart,
                                                         Rec* __restrict__ items,
-                                                        uint32_t* __restrict__ bstart) {
+                                                        uint32_t* __restrict__ bstart,
+                                                        uint64_t fp_salt, uint32_t fp_bits) {
   __shared__ uint32_t maxoff[kSubBuckets];
   __shared__ uint32_t nzero[kSubBuckets];
   __shared__ uint32_t wsum[kL3Threads / 64 + 2];
@@ -791,6 +804,12 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const void* __restrict__
   const uint32_t sub_in_bin = sb % sp.S;
   const uint32_t slot0 = sub_in_bin * kSubSlots;
   auto digit = [&](uint32_t o) { return D == 3 ? rank_of(o, g) : 63u - o; };
+  // the value of an item: from the record, or (fp_bits > 0) the key's
+  // fingerprint, which level 1 left out of the record
+  auto value = [&](uint32_t klo, uint32_t khi, uint32_t v) {
+    const uint64_t key = (uint64_t)klo | (uint64_t)khi << 32;
+    return fp_bits ? (uint32_t)(mix64(key ^ fp_salt) >> (64 - fp_bits)) : v;
+  };
   for (uint32_t i = threadIdx.x; i < nd; i += kL3Threads) dcur[i] = 0;
   for (uint32_t i = threadIdx.x; i < kSubBuckets; i += kL3Threads) {
     maxoff[i] = 0;
@@ -879,7 +898,8 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const void* __restrict__
       const uint32_t d = dr[k] & 0xfffu;
       const uint32_t bl = d / D, rk = D == 3 ? d - bl * 3 : 0u;
       const uint32_t o = (rec[k].w - slot0) & 63u;
-      stage[dcur[d] + (dr[k] >> 12) + bl + 1] = make_uint4(rec[k].x, rec[k].y, rec[k].z, o | (rk << 8));
+      stage[dcur[d] + (dr[k] >> 12) + bl + 1] =
+          make_uint4(rec[k].x, rec[k].y, value(rec[k].x, rec[k].y, rec[k].z), o | (rk << 8));
     }
     __syncthreads();
     uint4* go = reinterpret_cast<uint4*>(gout);
@@ -894,12 +914,25 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const void* __restrict__
     const uint32_t dg = digit(o);
     const uint32_t rk = D == 3 ? dg : 0u;
     const uint32_t pos = atomicAdd(&dcur[bl * D + dg], 1u) + bl + 1;
-    reinterpret_cast<uint4*>(gout)[pos] = make_uint4(r.x, r.y, r.z, o | (rk << 8));
+    reinterpret_cast<uint4*>(gout)[pos] = make_uint4(r.x, r.y, value(r.x, r.y, r.z), o | (rk << 8));
   }
 }
 
+template <int V>
+struct IntTag {
+  static constexpr int value = V;
+};
+template <bool V>
+struct BoolTag {
+  static constexpr bool value = V;
+};
+template <class T>
+struct TypeTag {
+  using type = T;
+};
+
 template <bool PACKED>
-hipError_t sort_layer_t(const SortArgs& a, hipStream_t s) {
+hipError_t sort_layer_t(const SortArgs& a, bool fp_late, hipStream_t s) {
   const SortPlan& sp = a.plan;
   const uint64_t n = a.g.nkeys;
   hipError_t e;
@@ -914,25 +947,56 @@ hipError_t sort_layer_t(const SortArgs& a, hipStream_t s) {
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = scan_exclusive(a.counts1, (size_t)sp.nb1 * sp.G1, a.scan_tmp, s)) != hipSuccess) return e;
-  const size_t lds1 = part_lds_bytes<kPartThreads>(sp.nb1);
-  switch (a.vbytes) {
-    case 1:
-      k_p1_scatter<uint8_t, PACKED><<<sp.G1, kPartThreads, lds1, s>>>(
-          a.keys, (const uint8_t*)a.vals, a.g, sp, a.counts1, a.mask_values, a.filter,
-          a.fp_salt, a.r1);
-      break;
-    case 2:
-      k_p1_scatter<uint16_t, PACKED><<<sp.G1, kPartThreads, lds1, s>>>(
-          a.keys, (const uint16_t*)a.vals, a.g, sp, a.counts1, a.mask_values, a.filter,
-          a.fp_salt, a.r1);
-      break;
-    default:
-      k_p1_scatter<uint32_t, PACKED><<<sp.G1, kPartThreads, lds1, s>>>(
-          a.keys, (const uint32_t*)a.vals, a.g, sp, a.counts1, a.mask_values, a.filter,
-          a.fp_salt, a.r1);
-      break;
-  }
+  using R = typename PRec<PACKED>::T;
+  // level 1: threads per workgroup by the bin count
+  auto scatter1 = [&](auto nt, auto vt) {
+    constexpr int NT = decltype(nt)::value;
+    using VT = typename decltype(vt)::type;
+    const size_t lds = part_lds_bytes<NT, kPartPer>(sp.nb1, sizeof(R));
+    (void)hipFuncSetAttribute((const void*)k_p1_scatter<VT, PACKED, NT>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_p1_scatter<VT, PACKED, NT><<<sp.G1, NT, lds, s>>>(
+        a.keys, (const VT*)a.vals, a.g, sp, a.counts1, a.mask_values, a.filter, a.fp_salt,
+        fp_late ? 1u : 0u, a.r1);
+  };
+  auto scatter1_v = [&](auto nt) {
+    switch (a.vbytes) {
+      case 1: scatter1(nt, TypeTag<uint8_t>{}); break;
+      case 2: scatter1(nt, TypeTag<uint16_t>{}); break;
+      default: scatter1(nt, TypeTag<uint32_t>{}); break;
+    }
+  };
+  // Larger tiles pay only where a tile's records spread over many digits:
+  // over every bin (sub-bin) of a large structure, but in a batch of small
+  // structures a tile holds few structures and each spans few digits, so
+  // its runs are long already and larger tiles cost occupancy (measured).
+  // The digits a structure spans, on average:
+  const uint64_t J = a.g.J ? a.g.J : 1;
+  const uint64_t span1 = sp.nb1 / J;
+  const uint64_t span2 = sp.nsub / J < sp.S ? sp.nsub / J : sp.S;
+  if (span1 > kBigTileDigits)
+    scatter1_v(IntTag<kPart1BigThreads>{});
+  else
+    scatter1_v(IntTag<kPartThreads>{});
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  // level 2: records per thread by the sub-bin count
+  auto scatter2 = [&](auto per, auto fused, const uint32_t* offs, const uint32_t* offs1) {
+    constexpr int PER = decltype(per)::value;
+    constexpr bool FU = decltype(fused)::value;
+    const size_t lds = part_lds_bytes<kPart2Threads, PER>(sp.S, sizeof(R));
+    (void)hipFuncSetAttribute((const void*)k_p2_scatter<PACKED, FU, PER>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_p2_scatter<PACKED, FU, PER><<<sp.U2, kPart2Threads, lds, s>>>(
+        a.r1, sp, a.binlo, a.nch, a.cbase, offs, offs1, n, a.r2);
+  };
+  auto scatter2_p = [&](auto fused, const uint32_t* offs, const uint32_t* offs1) {
+    if constexpr (decltype(fused)::value)  // fused counts fit LDS only with few sub-bins
+      scatter2(IntTag<kPartPer>{}, fused, offs, offs1);
+    else if (span2 > kBigTileDigits)
+      scatter2(IntTag<kPartPerBig>{}, fused, offs, offs1);
+    else
+      scatter2(IntTag<kPartPer>{}, fused, offs, offs1);
+  };
   if (!sp.H) {
     k_p2_plan<<<1, kPartThreads, 0, s>>>(a.counts1, sp, n, a.binlo, a.nch, a.cbase);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -943,13 +1007,13 @@ hipError_t sort_layer_t(const SortArgs& a, hipStream_t s) {
     if (by_offset) {
       (void)hipFuncSetAttribute((const void*)k_p3_sort<PACKED, 64>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3_lds_bytes(64));
-      k_p3_sort<PACKED, 64><<<sp.nsub, kL3Threads, l3_lds_bytes(64), s>>>(in, a.g, sp, starts,
-                                                                          a.out_rec, a.bstart);
+      k_p3_sort<PACKED, 64><<<sp.nsub, kL3Threads, l3_lds_bytes(64), s>>>(
+          in, a.g, sp, starts, a.out_rec, a.bstart, a.fp_salt, fp_late ? a.g.r : 0u);
     } else {
       (void)hipFuncSetAttribute((const void*)k_p3_sort<PACKED, 3>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3_lds_bytes(3));
-      k_p3_sort<PACKED, 3><<<sp.nsub, kL3Threads, l3_lds_bytes(3), s>>>(in, a.g, sp, starts,
-                                                                        a.out_rec, a.bstart);
+      k_p3_sort<PACKED, 3><<<sp.nsub, kL3Threads, l3_lds_bytes(3), s>>>(
+          in, a.g, sp, starts, a.out_rec, a.bstart, a.fp_salt, fp_late ? a.g.r : 0u);
     }
     return hipGetLastError();
   };
@@ -967,8 +1031,7 @@ hipError_t sort_layer_t(const SortArgs& a, hipStream_t s) {
     if ((e = scan_exclusive(tot, nds, a.scan_tmp, s)) != hipSuccess) return e;
     k_col_apply<<<gb, 256, 0, s>>>(a.counts2, (uint32_t)nds, sp.Hc, psum, tot, (uint32_t)n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_p2_scatter<PACKED, true><<<sp.U2, kPart2Threads, part_lds_bytes<kPart2Threads>(sp.S), s>>>(
-        a.r1, sp, a.binlo, a.nch, a.cbase, a.counts2, a.counts1, n, a.r2);
+    scatter2_p(BoolTag<true>{}, a.counts2, a.counts1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return level3(a.r2, tot);
   }
@@ -978,8 +1041,7 @@ hipError_t sort_layer_t(const SortArgs& a, hipStream_t s) {
                                                                    a.cbase, a.counts2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = scan_exclusive(a.counts2, n2, a.scan_tmp, s)) != hipSuccess) return e;
-  k_p2_scatter<PACKED, false><<<sp.U2, kPart2Threads, part_lds_bytes<kPart2Threads>(sp.S), s>>>(
-      a.r1, sp, a.binlo, a.nch, a.cbase, a.counts2, nullptr, n, a.r2);
+  scatter2_p(BoolTag<false>{}, a.counts2, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_p2_starts<<<(sp.nsub + 256) / 256, 256, 0, s>>>(sp, n, a.binlo, a.nch, a.cbase, a.counts2,
                                                      a.sstart);
@@ -987,14 +1049,20 @@ hipError_t sort_layer_t(const SortArgs& a, hipStream_t s) {
   return level3(a.r2, a.sstart);
 }
 
-// Values ride in the top byte of the meta word when every value fits 8 bits
-// and every slot within a level-1 bin fits its low 24 bits.
+// Records are packed when every slot within a level-1 bin fits the low 24
+// bits of the meta word and every value fits its top byte - or is left out:
+// the fingerprints of a single filter structure wider than 8 bits are
+// computed again from the keys at level 3 (one hash per key there against 4
+// bytes more per record through both partition levels).
 hipError_t sort_layer(const SortArgs& a, hipStream_t s) {
   if (a.g.nkeys == 0) return hipErrorInvalidValue;
   if (a.plan.nsub >= (1u << 24)) return hipErrorInvalidValue;  // level-1 bin arithmetic
   const uint64_t bin_slots = (uint64_t)a.plan.S * kSubSlots;
-  if (a.g.r <= 8 && bin_slots <= (1ull << 24)) return sort_layer_t<true>(a, s);
-  return sort_layer_t<false>(a, s);
+  if (bin_slots <= (1ull << 24)) {
+    if (a.g.r <= 8) return sort_layer_t<true>(a, false, s);
+    if (a.filter && a.g.J == 1) return sort_layer_t<true>(a, true, s);
+  }
+  return sort_layer_t<false>(a, false, s);
 }
 
 // ---------------------------------------------------------------------------

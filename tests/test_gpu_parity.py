@@ -46,6 +46,9 @@ CASES = [
     (30000, 32, dict(ranges=8, seed=5)),
     (25000, 13, dict(ranges=100, minbpt=2, load_num=90, load_den=100, layers=5)),
     (20000, 5, dict(ranges=37, minbpt=3, filter_mode=1, seed=9)),
+    # a filter wider than 8 bits through every partition level: its
+    # fingerprints are left out of the records and computed at level 3
+    (700000, 12, dict(ranges=512, filter_mode=1, seed=21)),
     (8000, 8, dict(layers=0)),
     (20000, 8, dict(ranges=16, t_lo=8, t_hi=40, seed=123)),
     (3000, 4, dict(ranges=6, minbpt=2, load_num=60, load_den=100, layers=4)),
