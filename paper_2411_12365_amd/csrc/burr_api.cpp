@@ -643,7 +643,7 @@ int run_sort(Workspace& ws, const uint64_t* keys, const void* vals, uint32_t vby
   a.filter = filter ? 1u : 0u;
   a.fp_salt = fp_salt;
   a.g = g;
-  a.plan = plan_sort(g.nkeys, g.nbuckets);
+  a.plan = plan_sort(g.nkeys, g.nbuckets, g.J);
   if (!ws.reserve_sort(a.plan)) return set_error(BURR_E_NOMEM);
   if (!ws.reserve_items(g.nkeys + g.nbuckets)) return set_error(BURR_E_NOMEM);
   a.counts1 = ws.counts1;

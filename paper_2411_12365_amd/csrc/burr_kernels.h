@@ -34,8 +34,10 @@ struct SortPlan {
   uint32_t cs;         // fused counting: level-1 workgroups per level-2 chunk
   uint32_t cc;         // fused counting: level-1 workgroups per counting workgroup (divides cs)
   uint32_t Hc;         // fused counting: counting workgroups
+  bool big1, big2;     // tiles of twice the records at level 1 / level 2
 };
-SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets);
+// nstructs: structures in the layer (a batch's tiles are sized for them)
+SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets, uint32_t nstructs);
 // u32 words of counts2 a plan needs
 uint64_t sort_counts2_words(const SortPlan& sp);
 

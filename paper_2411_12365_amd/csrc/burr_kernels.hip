@@ -153,13 +153,14 @@ hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s
 // loads issued together it is faster than at 70 VGPRs and 7 waves, and held
 // to 80 VGPRs it is slower), level 2 takes 48 (8 waves per SIMD). A level
 // with more than kBigTileDigits digits has tiles of twice as many records,
-// so that a tile still gives each digit a run of about 8 or more: level 1
+// so that a tile still gives each digit a run of about 16 or more: level 1
 // with twice the threads (at 8 records per thread it would take over 128
-// VGPRs), level 2 with 8 records per thread (one 16-wave workgroup per CU)
+// VGPRs; held to 64 VGPRs for two workgroups per CU, it spills and is
+// slower), level 2 with 8 records per thread (one 16-wave workgroup per CU)
 constexpr int kPartPer = 4;                         // records per thread of a tile
 constexpr int kPartPerBig = 8;                      // level 2 with many sub-bins
 constexpr int kPart1BigThreads = 1024;              // level 1 with many bins
-constexpr uint32_t kBigTileDigits = 256;
+constexpr uint32_t kBigTileDigits = 128;
 constexpr int kPartThreads = 2048 / kPartPer;       // level 1: 2048-key tiles
 constexpr int kPart2Threads = 4096 / kPartPer;      // level 2: 4096-key tiles
 constexpr uint32_t kTile = kPartThreads * kPartPer;  // level-1 keys per tile
@@ -184,8 +185,8 @@ constexpr uint32_t kSingleLevelSubs = 128;
 // those of (d, s) in the rows before the chunk's first row c = h cs/cc - a
 // prefix over the rows. That replaces level 2's own counting pass over the
 // level-1 records. cs is chosen so that a chunk holds about kChunkFused
-// records (most of one level-2 tile), cc so that the counting workgroups
-// fill the device (kCountWgs).
+// records (most of one level-2 tile; twice that with the larger tiles), cc
+// so that the counting workgroups fill the device (kCountWgs).
 constexpr uint32_t kCountThreads = 1024;
 constexpr uint32_t kCountSlicesMax = 32;
 constexpr uint32_t kChunkFused = 3800;
@@ -196,8 +197,9 @@ __host__ __device__ constexpr uint64_t count_lds_bytes(uint32_t nb1, uint32_t S,
   return ((uint64_t)nb1 * S + (uint64_t)nb1 * cs) * 4;
 }
 
-SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets) {
+SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets, uint32_t nstructs) {
   SortPlan p{};
+  const uint64_t J = nstructs ? nstructs : 1;
   p.nsub = (uint32_t)((nbuckets + kSubBuckets - 1) / kSubBuckets);
   uint32_t nb = 1;
   if (p.nsub <= kSingleLevelSubs)
@@ -215,8 +217,17 @@ SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets) {
   p.per_group = (nkeys + p.G1 - 1) / p.G1;
   p.U2 = (uint32_t)(nkeys / kChunk2 + p.nb1 + 1);
   p.invS = 1.0f / (float)p.S;
+  // Larger tiles pay only where a tile's records spread over many digits:
+  // over every bin (sub-bin) of a large structure, but in a batch of small
+  // structures a tile holds few structures and each spans few digits, so
+  // its runs are long already and larger tiles cost occupancy (measured).
+  // The digits a structure spans, on average:
+  const uint64_t span1 = p.nb1 / J, span2 = p.nsub / J < p.S ? p.nsub / J : p.S;
+  p.big1 = span1 > kBigTileDigits;
+  p.big2 = span2 > kBigTileDigits;
   p.H = 0;
-  uint64_t cs = ((uint64_t)kChunkFused * p.nb1 + p.per_group / 2) / p.per_group;
+  const uint64_t chunk = (uint64_t)kChunkFused * (p.big2 ? kPartPerBig / kPartPer : 1);
+  uint64_t cs = (chunk * p.nb1 + p.per_group / 2) / p.per_group;
   cs = cs < 1 ? 1 : (cs > kCountSlicesMax ? kCountSlicesMax : cs);
   uint32_t cc = (p.G1 + kCountWgs - 1) / kCountWgs;  // counting rows: about kCountWgs
   if (cc > cs) cc = (uint32_t)cs;
@@ -527,9 +538,12 @@ struct PartLds {
     cur = sm;
     toff = sm + D;
     wsum = toff + D + 2;
-    uint8_t* p = reinterpret_cast<uint8_t*>(wsum + NT / 64 + 2);
-    p = reinterpret_cast<uint8_t*>(((uintptr_t)p + 15) & ~(uintptr_t)15);
-    stage = reinterpret_cast<R*>(p);
+    // the stage at the next 16-byte boundary of the (16-byte aligned) block,
+    // by pointer arithmetic alone: a pointer that passes through an integer
+    // loses its LDS address space, and the stage's accesses then become flat
+    // instructions, which wait on the global stores of the tile's write
+    const uint32_t w = (2 * D + 2 + NT / 64 + 2 + 3) & ~3u;
+    stage = reinterpret_cast<R*>(sm + w);
     sdig = reinterpret_cast<uint16_t*>(stage + NT * PER);
   }
 };
@@ -541,7 +555,7 @@ __global__ __launch_bounds__(NT) void k_p1_scatter(
     const uint32_t* __restrict__ offs, uint32_t mask_values, uint32_t filter, uint64_t fp_salt,
     uint32_t fp_late, void* __restrict__ out_raw) {
   using R = typename PRec<PACKED>::T;
-  extern __shared__ uint32_t sm[];
+  extern __shared__ __align__(16) uint32_t sm[];
   constexpr int PER = kPartPer;
   const bool no_vals = filter && (mask_values || fp_late);  // values not read
   PartLds<NT, PER, R> L(sm, sp.nb1);
@@ -701,7 +715,7 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_scatter(
   using R = typename PRec<PACKED>::T;
   const R* in = reinterpret_cast<const R*>(in_raw);
   R* out = reinterpret_cast<R*>(out_raw);
-  extern __shared__ uint32_t sm[];
+  extern __shared__ __align__(16) uint32_t sm[];
   Chunk2 ch;
   PartLds<kPart2Threads, PER, R> L(sm, sp.S);
   if constexpr (FUSED) {
@@ -966,15 +980,7 @@ hipError_t sort_layer_t(const SortArgs& a, bool fp_late, hipStream_t s) {
       default: scatter1(nt, TypeTag<uint32_t>{}); break;
     }
   };
-  // Larger tiles pay only where a tile's records spread over many digits:
-  // over every bin (sub-bin) of a large structure, but in a batch of small
-  // structures a tile holds few structures and each spans few digits, so
-  // its runs are long already and larger tiles cost occupancy (measured).
-  // The digits a structure spans, on average:
-  const uint64_t J = a.g.J ? a.g.J : 1;
-  const uint64_t span1 = sp.nb1 / J;
-  const uint64_t span2 = sp.nsub / J < sp.S ? sp.nsub / J : sp.S;
-  if (span1 > kBigTileDigits)
+  if (sp.big1)
     scatter1_v(IntTag<kPart1BigThreads>{});
   else
     scatter1_v(IntTag<kPartThreads>{});
@@ -990,9 +996,7 @@ hipError_t sort_layer_t(const SortArgs& a, bool fp_late, hipStream_t s) {
         a.r1, sp, a.binlo, a.nch, a.cbase, offs, offs1, n, a.r2);
   };
   auto scatter2_p = [&](auto fused, const uint32_t* offs, const uint32_t* offs1) {
-    if constexpr (decltype(fused)::value)  // fused counts fit LDS only with few sub-bins
-      scatter2(IntTag<kPartPer>{}, fused, offs, offs1);
-    else if (span2 > kBigTileDigits)
+    if (sp.big2)
       scatter2(IntTag<kPartPerBig>{}, fused, offs, offs1);
     else
       scatter2(IntTag<kPartPer>{}, fused, offs, offs1);
@@ -1587,7 +1591,12 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
           uint32_t o = 0;
           if (t < count) {
             constexpr uint32_t last = Stage<LANES>::items - 1;
-            o = (t < last ? R.stage[t + 1].w : rec4[hq + 1 + t].w) & 63u;
+            if (t < last) {  // two kinds of load, not one through a selected (flat) pointer
+              o = R.stage[t + 1].w & 63u;
+            } else {
+              typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+              o = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(rec4 + hq + 1 + t)).w & 63u;
+            }
           }
           c += (uint32_t)__popcll(G.ballot(t < count && o >= theta));
         }
