@@ -686,12 +686,18 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_hist(const void* __restric
   __syncthreads();
   constexpr uint32_t T2 = kPart2Threads * kHistPer;
   for (uint32_t t0 = ch.lo; t0 < ch.hi; t0 += T2) {
-    uint32_t sl[kHistPer];  // loads first, then the counting atomics
+    // loads first (unconditional: past the end the last record is read
+    // again and not counted), then the counting atomics
+    uint32_t sl[kHistPer];
 #pragma unroll
     for (int k = 0; k < kHistPer; ++k) {
       const uint32_t i = t0 + threadIdx.x + k * kPart2Threads;
-      if (i < ch.hi) sl[k] = PACKED ? (in[i].z & 0xffffffu) : reinterpret_cast<const uint4*>(in)[i].w;
+      const uint32_t ic = i < ch.hi ? i : ch.hi - 1;
+      sl[k] = PACKED ? in[ic].z : reinterpret_cast<const uint4*>(in)[ic].w;
     }
+#pragma unroll
+    for (int k = 0; k < kHistPer; ++k)
+      if (PACKED) sl[k] &= 0xffffffu;
 #pragma unroll
     for (int k = 0; k < kHistPer; ++k)
       if (t0 + threadIdx.x + k * kPart2Threads < ch.hi) atomicAdd(&hist[sl[k] / kSubSlots], 1u);
@@ -837,16 +843,25 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const void* __restrict__
   uint4 rec[kL3Per];
   uint32_t dr[kL3Per];  // digit | rank << 12
   if (fits) {
+    // loads first, then the counting atomics. The loads are unconditional
+    // (past the end the last record is read again and not used): a load
+    // under a branch whose record is unpacked inside it waits there for its
+    // data, and the loads then run one after another
+    using PT = typename PRec<PACKED>::T;
+    PT raw[kL3Per];
+    if (n) {
 #pragma unroll
-    for (int k = 0; k < kL3Per; ++k) {  // loads first, then the counting atomics
-      const uint32_t i = lo + threadIdx.x + k * kL3Threads;
-      if (i < hi) rec[k] = part_rec<PACKED>(in, i);
+      for (int k = 0; k < kL3Per; ++k) {
+        const uint32_t i = lo + threadIdx.x + k * kL3Threads;
+        raw[k] = reinterpret_cast<const PT*>(in)[i < hi ? i : hi - 1];
+      }
     }
 #pragma unroll
     for (int k = 0; k < kL3Per; ++k) {
       const uint32_t i = lo + threadIdx.x + k * kL3Threads;
       dr[k] = 0xffffffffu;
       if (i < hi) {
+        rec[k] = PRec<PACKED>::unpack(raw[k]);
         const uint32_t sl = rec[k].w - slot0;
         const uint32_t bl = sl >> 6, o = sl & 63u;
         const uint32_t d = bl * D + digit(o);
@@ -1203,6 +1218,7 @@ struct WaveRing {
   uint64_t c[kRing];
   uint32_t v[kRing + 64];  // + one spare word per lane (claims that lose write there)
   uint4 stage[Stage<LANES>::items];
+  uint32_t bs[LANES];      // bucket starts of a window of LANES buckets
 };
 // row and value of the slot at byte offset off = 8 * slot
 template <class Ring>
@@ -1480,7 +1496,7 @@ __device__ inline void clear_half(WaveRing<LANES>& R, const Grp<LANES>& G, uint3
 }
 
 // 8 waves per SIMD: the kernel then fits 64 VGPRs (no spills), and the
-// ring and stage of 32 waves (3.75 KB each) fit a CU's LDS. ONE_PLUS: the
+// ring, stage and bucket starts of 32 waves (4 KB each) fit a CU's LDS. ONE_PLUS: the
 // instantiation for 1+-bit thresholds of BuRR layers (the 2-bit one carries
 // no code of the threshold bisection).
 template <int LANES, bool ONE_PLUS>
@@ -1512,38 +1528,52 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
   uint64_t steps = 0;
   SolveStats sst;
   bool failed = false;
-  // bucket 0's items, staged through registers
+  // Item index of bucket q's header, from the starts of a window of LANES
+  // buckets that the group keeps in LDS (loaded once per window), so that a
+  // bucket's items are loaded without first waiting for its start.
+  auto load_window = [&](uint32_t w) {
+    const uint64_t b = fb + w + G.lane;
+    R.bs[G.lane] = a.bstart[b < g.nbuckets ? b : g.nbuckets];
+  };
+  auto item_of = [&](uint32_t q) -> uint32_t {
+    uint32_t st = R.bs[q % LANES];
+    if constexpr (LANES == 64) st = __builtin_amdgcn_readfirstlane(st);
+    return st + (uint32_t)(fb + q);
+  };
+  // A bucket's items are staged through registers: loaded (unconditionally:
+  // past the range, the next buckets' items, not used) before the previous
+  // bucket is inserted and written to the stage after it. The loads are
+  // then not waited for before that insertion; a conditional load, or
+  // registers that carry a value from one loop trip into the next, make the
+  // compiler copy the loaded values, and wait for them, right away.
   uint4 nx[SP];
-  uint32_t hq = nq ? a.bstart[fb] + (uint32_t)fb : 0u;
-  if (nq) {
+  auto load_items = [&](uint32_t h) {
 #pragma unroll
     for (uint32_t k = 0; k < SP; ++k) {
-      const uint32_t t = hq + k * LANES + G.lane;
+      const uint32_t t = h + k * LANES + G.lane;
       nx[k] = rec4[t < last_item ? t : last_item];
     }
-  }
-  for (uint32_t q = 0; q < nq && !failed; ++q) {
-    const uint64_t beta = fb + q;
-    hq = a.bstart[beta] + (uint32_t)beta;
+  };
+  auto stage_items = [&]() {
 #pragma unroll
     for (uint32_t k = 0; k < SP; ++k)  // entry 0 is the bucket header
       R.stage[k * LANES + G.lane] = (k == 0 && G.lane == 0) ? nx[0] : staged(nx[k], g);
-    // the slots of bucket q+1 held bucket q-1: publish its rows, clear them
-    if (q >= 1) {
-      const uint32_t hb = ((q - 1) & 1u) * 64u;
-      release_half(R, G, hb, a.rowsC + (beta - 1) * 64, a.rowsV + (beta - 1) * 64,
-                   a.occ + (beta - 1));
-      clear_half(R, G, hb);
+  };
+  if (nq) {
+    load_window(0);
+    G.sync();
+    load_items(item_of(0));
+    stage_items();
+  }
+  for (uint32_t q = 0; q < nq && !failed; ++q) {
+    const uint64_t beta = fb + q;
+    const uint32_t hq = item_of(q);
+    if ((q + 1) % LANES == 0) {
+      G.sync();  // every lane has read its start of this window
+      load_window(q + 1);
     }
     G.sync();
-    if (q + 1 < nq) {  // next bucket's items load while this one is inserted
-      const uint32_t hn = a.bstart[beta + 1] + (uint32_t)(beta + 1);
-#pragma unroll
-      for (uint32_t k = 0; k < SP; ++k) {
-        const uint32_t t = hn + k * LANES + G.lane;
-        nx[k] = rec4[t < last_item ? t : last_item];
-      }
-    }
+    load_items(item_of(q + 1));  // while bucket q is inserted
     uint4 hd = R.stage[0];
     if constexpr (LANES == 64) {  // the same for every lane: keep it scalar
       hd.x = __builtin_amdgcn_readfirstlane(hd.x);
@@ -1585,19 +1615,20 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
       // >= theta are a prefix of the bucket; its length from ballots over
       // the staged offsets (records past the stage from the item stream)
       auto prefix_len = [&](uint32_t theta) {
+        constexpr uint32_t last = Stage<LANES>::items - 1;
+        const uint32_t ns = count < last ? count : last;  // staged records
         uint32_t c = 0;
-        for (uint32_t t0 = 0; t0 < count; t0 += LANES) {
+        for (uint32_t t0 = 0; t0 < ns; t0 += LANES) {
           const uint32_t t = t0 + G.lane;
-          uint32_t o = 0;
-          if (t < count) {
-            constexpr uint32_t last = Stage<LANES>::items - 1;
-            if (t < last) {  // two kinds of load, not one through a selected (flat) pointer
-              o = R.stage[t + 1].w & 63u;
-            } else {
-              typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-              o = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(rec4 + hq + 1 + t)).w & 63u;
-            }
-          }
+          const uint32_t o = t < ns ? R.stage[t + 1].w & 63u : 0u;
+          c += (uint32_t)__popcll(G.ballot(t < ns && o >= theta));
+        }
+        // records past the stage (a bucket of more than `last` records,
+        // rare) in a loop of their own: a global load beside the stage
+        // reads would make them wait for every memory operation in flight
+        for (uint32_t t0 = last; t0 < count; t0 += LANES) {
+          const uint32_t t = t0 + G.lane;
+          const uint32_t o = t < count ? rec4[hq + 1 + (t < count ? t : last)].w & 63u : 0u;
           c += (uint32_t)__popcll(G.ballot(t < count && o >= theta));
         }
         return c;
@@ -1671,11 +1702,25 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
         failed = true;
       }
     }
+    G.sync();
+    // bucket q+1's items to the stage first: their loads are the oldest
+    // memory operations in flight, so waiting for them does not wait for
+    // the stores below. Unconditionally (after the last bucket the stage is
+    // not read again): with a path on which the loads stay unused, the
+    // compiler waits for all memory operations, stores included, before it
+    // reuses their registers.
+    stage_items();
     if (!g.plain && G.lane == 0) {
       a.code8[beta] = (uint8_t)code;
       a.bump[beta] = count - kept;
     }
-    G.sync();
+    if (q + 1 < nq && !failed) {
+      // bucket q+1's upper slots reuse the ring half of bucket q's first 64
+      // slots, which no later bucket changes: publish its rows, clear them
+      const uint32_t hb = (q & 1u) * 64u;
+      release_half(R, G, hb, a.rowsC + beta * 64, a.rowsV + beta * 64, a.occ + beta);
+      clear_half(R, G, hb);
+    }
   }
   if (nq && !failed) {
     const uint32_t hl = ((nq - 1) & 1u) * 64u;
@@ -2189,11 +2234,19 @@ __global__ void k_pack_codes(const uint8_t* __restrict__ code8, LayerGeom g,
   const uint32_t j = find_struct(g.code_base, g.J, w);
   const uint64_t B = g.bucket_base[j + 1] - g.bucket_base[j];
   const uint64_t wl = w - g.code_base[j];
-  uint64_t word = 0;
-  for (uint64_t t = 0; t < 32; ++t) {
+  // the 32 loads are unconditional (past the structure's end its last code
+  // is read again and not used), so that they are all in flight together
+  const uint8_t* c = code8 + g.bucket_base[j];
+  uint32_t cv[32];
+#pragma unroll
+  for (uint32_t t = 0; t < 32; ++t) {
     const uint64_t b = wl * 32 + t;
-    if (b < B) word |= (uint64_t)(code8[g.bucket_base[j] + b] & 3u) << (2 * t);
+    cv[t] = c[b < B ? b : B - 1];
   }
+  uint64_t word = 0;
+#pragma unroll
+  for (uint32_t t = 0; t < 32; ++t)
+    if (wl * 32 + t < B) word |= (uint64_t)(cv[t] & 3u) << (2 * t);
   words[w] = word;
 }
 
