@@ -274,6 +274,31 @@ struct KeyWalk {
   }
 };
 
+// The same for a layer of one structure: its geometry is the same for every
+// key, held in scalar registers, and there is nothing to walk.
+struct OneWalk {
+  uint64_t span;
+  uint64_t bb = 0;
+  uint32_t r;
+  __device__ explicit OneWalk(const LayerGeom& g) {
+    const uint64_t sp = g.span[0];
+    span = (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)sp) |
+           (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sp >> 32)) << 32;
+    r = __builtin_amdgcn_readfirstlane(g.rbits[0]);
+  }
+  __device__ void advance(const LayerGeom&, uint64_t) {}
+};
+template <bool ONE>
+struct WalkOf {
+  using T = KeyWalk;
+  __device__ static KeyWalk make(const LayerGeom& g, uint64_t i) { return KeyWalk(g, i); }
+};
+template <>
+struct WalkOf<true> {
+  using T = OneWalk;
+  __device__ static OneWalk make(const LayerGeom& g, uint64_t) { return OneWalk(g); }
+};
+
 // Level-1 bin of a global slot and the slot's offset within the bin. A bin
 // is S sub-bins of kSubSlots slots, so the bin is the global sub-bin index
 // (below 2^24, checked when the layer is sorted) divided by S, computed in
@@ -323,6 +348,7 @@ __device__ inline void lds_scan(uint32_t* a, uint32_t n, uint32_t* wsum) {
 }
 
 // Level 1, pass 1: per workgroup, keys per bin.
+template <bool ONE>
 __global__ __launch_bounds__(kPartThreads) void k_p1_hist(const uint64_t* __restrict__ keys,
                                                           LayerGeom g, SortPlan sp,
                                                           uint32_t* __restrict__ counts) {
@@ -332,7 +358,7 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_hist(const uint64_t* __rest
   const uint64_t lo = (uint64_t)blockIdx.x * sp.per_group;
   const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
   const BinSplit bs(sp);
-  KeyWalk w(g, lo + threadIdx.x);
+  auto w = WalkOf<ONE>::make(g, lo + threadIdx.x);
   for (uint64_t t0 = lo; t0 < hi; t0 += kHistPer * kPartThreads) {
     // all of a thread's loads are issued before the first is used (past
     // the end, the last key is read again and not counted)
@@ -360,6 +386,7 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_hist(const uint64_t* __rest
 
 // Fused counting pass: per (bin, level-1 workgroup) into counts1 ([bin][w]
 // layout, as k_p1_hist) and per (bin, sub-bin) into counts2t[h][d*S+s].
+template <bool ONE>
 __global__ __launch_bounds__(kCountThreads) void k_p1_count(const uint64_t* __restrict__ keys,
                                                             LayerGeom g, SortPlan sp,
                                                             uint32_t* __restrict__ counts1,
@@ -377,7 +404,7 @@ __global__ __launch_bounds__(kCountThreads) void k_p1_count(const uint64_t* __re
     const uint64_t lo = w * sp.per_group;
     const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
     if (lo >= hi) break;
-    KeyWalk kw(g, lo + threadIdx.x);
+    auto kw = WalkOf<ONE>::make(g, lo + threadIdx.x);
     for (uint64_t t0 = lo; t0 < hi; t0 += kHistPer * kCountThreads) {
       uint64_t kk[kHistPer];  // all loads issued before the first is used
 #pragma unroll
@@ -549,7 +576,7 @@ struct PartLds {
 };
 
 // Level 1, pass 2: hash, mask or fingerprint the value, write tile runs per bin.
-template <typename VT, bool PACKED, int NT>
+template <typename VT, bool PACKED, int NT, bool ONE>
 __global__ __launch_bounds__(NT) void k_p1_scatter(
     const uint64_t* __restrict__ keys, const VT* __restrict__ vals, LayerGeom g, SortPlan sp,
     const uint32_t* __restrict__ offs, uint32_t mask_values, uint32_t filter, uint64_t fp_salt,
@@ -569,7 +596,7 @@ __global__ __launch_bounds__(NT) void k_p1_scatter(
   const uint64_t lo = (uint64_t)blockIdx.x * sp.per_group;
   const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
   const BinSplit bs(sp);
-  KeyWalk w(g, lo + threadIdx.x);
+  auto w = WalkOf<ONE>::make(g, lo + threadIdx.x);
   for (uint64_t t0 = lo; t0 < hi; t0 += T1) {
     R rec[PER];
     uint32_t dr[PER];
@@ -968,11 +995,19 @@ hipError_t sort_layer_t(const SortArgs& a, bool fp_late, hipStream_t s) {
   const size_t nds = (size_t)sp.nb1 * sp.S;
   if (sp.H) {  // one counting pass for both partition levels
     const size_t lds = count_lds_bytes(sp.nb1, sp.S, sp.cc);
-    (void)hipFuncSetAttribute((const void*)k_p1_count, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    k_p1_count<<<sp.Hc, kCountThreads, lds, s>>>(a.keys, a.g, sp, a.counts1, a.counts2);
+    if (a.g.J == 1) {
+      (void)hipFuncSetAttribute((const void*)k_p1_count<true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      k_p1_count<true><<<sp.Hc, kCountThreads, lds, s>>>(a.keys, a.g, sp, a.counts1, a.counts2);
+    } else {
+      (void)hipFuncSetAttribute((const void*)k_p1_count<false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      k_p1_count<false><<<sp.Hc, kCountThreads, lds, s>>>(a.keys, a.g, sp, a.counts1, a.counts2);
+    }
+  } else if (a.g.J == 1) {
+    k_p1_hist<true><<<sp.G1, kPartThreads, (size_t)sp.nb1 * 4, s>>>(a.keys, a.g, sp, a.counts1);
   } else {
-    k_p1_hist<<<sp.G1, kPartThreads, (size_t)sp.nb1 * 4, s>>>(a.keys, a.g, sp, a.counts1);
+    k_p1_hist<false><<<sp.G1, kPartThreads, (size_t)sp.nb1 * 4, s>>>(a.keys, a.g, sp, a.counts1);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = scan_exclusive(a.counts1, (size_t)sp.nb1 * sp.G1, a.scan_tmp, s)) != hipSuccess) return e;
@@ -982,11 +1017,19 @@ hipError_t sort_layer_t(const SortArgs& a, bool fp_late, hipStream_t s) {
     constexpr int NT = decltype(nt)::value;
     using VT = typename decltype(vt)::type;
     const size_t lds = part_lds_bytes<NT, kPartPer>(sp.nb1, sizeof(R));
-    (void)hipFuncSetAttribute((const void*)k_p1_scatter<VT, PACKED, NT>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_p1_scatter<VT, PACKED, NT><<<sp.G1, NT, lds, s>>>(
-        a.keys, (const VT*)a.vals, a.g, sp, a.counts1, a.mask_values, a.filter, a.fp_salt,
-        fp_late ? 1u : 0u, a.r1);
+    if (a.g.J == 1) {
+      (void)hipFuncSetAttribute((const void*)k_p1_scatter<VT, PACKED, NT, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      k_p1_scatter<VT, PACKED, NT, true><<<sp.G1, NT, lds, s>>>(
+          a.keys, (const VT*)a.vals, a.g, sp, a.counts1, a.mask_values, a.filter, a.fp_salt,
+          fp_late ? 1u : 0u, a.r1);
+    } else {
+      (void)hipFuncSetAttribute((const void*)k_p1_scatter<VT, PACKED, NT, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      k_p1_scatter<VT, PACKED, NT, false><<<sp.G1, NT, lds, s>>>(
+          a.keys, (const VT*)a.vals, a.g, sp, a.counts1, a.mask_values, a.filter, a.fp_salt,
+          fp_late ? 1u : 0u, a.r1);
+    }
   };
   auto scatter1_v = [&](auto nt) {
     switch (a.vbytes) {
