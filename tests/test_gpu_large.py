@@ -17,7 +17,9 @@ r = 8), the 1B-key filter builds (2^18 ranges, r = 16 and r = 1) and the
       sections of the export equals the library's.
 - 200,000 structures: every member's export equals the oracle's structure of
   its own keys (the oracle runs on a thread pool: its C calls release the
-  interpreter lock)."""
+  interpreter lock).
+- two 300M-key structures in one batch: each member's export equals its
+  standalone build."""
 import concurrent.futures as cf
 import os
 
@@ -164,6 +166,28 @@ def test_billion_key_filter(big, r):
                           big["lut"], big["m"], h.layer_keys(1))
     _check_chain(h, e, r, big["op"])
     h.free()
+
+
+def test_batch_of_two_large_filters(big):
+    """A batch of two 300M-key structures: each spans more than 128 level-1
+    bins, so the batched sort takes its larger tiles with the per-key
+    structure walk. Every member's export equals its standalone build (whose
+    sort is checked against the oracle above at 1B keys), and it finds its
+    keys."""
+    burr = _burr()
+    half = 300_000_000
+    keys = big["keys_dev"][:2 * half]
+    params = burr.Params(ranges=RANGES, filter_mode=1)
+    print("[large] batch of two 300M-key filters", flush=True)
+    b = burr.build_batch(keys, None, [0, half, 2 * half], [16, 16], params)
+    for i in range(2):
+        part = keys[i * half:(i + 1) * half]
+        h = burr.build(part, None, 16, params)
+        assert b.member(i).export() == h.export(), f"member {i}"
+        h.free()
+        for lo in range(0, half, CHUNK):
+            assert bool(b.member(i).contains(part[lo:lo + CHUNK]).all()), f"member {i} keys {lo}"
+    b.free()
 
 
 def test_hundred_million_key_retrieval():
