@@ -248,6 +248,33 @@ uint64_t sort_counts2_words(const SortPlan& sp) {
   return nds * sp.Hc + nds * hb + nds + 1;  // counts per (row, sub-bin), block prefixes, sub-bin starts
 }
 
+// LDS counter a[d] += 1 for every calling lane; returns the value before
+// this lane's increment (lanes in lane order). When all calling lanes of the
+// wave count the same digit - consecutive keys of one small structure of a
+// batch fall into one bin or sub-bin - one atomic adds for the whole wave:
+// 64 atomics on one address would be applied one after another.
+__device__ inline uint32_t lds_count(uint32_t* a, uint32_t d) {
+  const uint64_t m = __builtin_amdgcn_ballot_w64(true);
+  const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+  if (__builtin_amdgcn_ballot_w64(d == d0) == m) {
+    const uint32_t rank =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    uint32_t old = 0;
+    if (rank == 0) old = atomicAdd(&a[d0], (uint32_t)__popcll(m));
+    return __builtin_amdgcn_readfirstlane(old) + rank;
+  }
+  return atomicAdd(&a[d], 1u);
+}
+// lds_count for the keys of a layer of several structures (BATCH), the
+// plain atomic for one structure, whose keys spread over every digit
+template <bool BATCH>
+__device__ inline uint32_t key_count(uint32_t* a, uint32_t d) {
+  if constexpr (BATCH)
+    return lds_count(a, d);
+  else
+    return atomicAdd(&a[d], 1u);
+}
+
 // Threads walk their keys in increasing index order: the structure of the
 // first key is found by binary search, later ones by stepping forward.
 struct KeyWalk {
@@ -297,6 +324,72 @@ template <>
 struct WalkOf<true> {
   using T = OneWalk;
   __device__ static OneWalk make(const LayerGeom& g, uint64_t) { return OneWalk(g); }
+};
+
+// The geometry of the structures a workgroup's keys [lo, hi) belong to,
+// staged in LDS when there are at most kWalkCache of them: in a batch of
+// small structures a thread crosses a structure every few keys, and a
+// crossing then costs LDS reads instead of a round trip to HBM.
+constexpr uint32_t kWalkCache = 512;
+__host__ __device__ constexpr size_t walk_cache_bytes() { return (size_t)kWalkCache * 28 + 16; }
+struct WalkCache {
+  uint64_t *end, *span, *bb;  // per cached structure: first key of the next, span, first bucket
+  uint32_t *r, *jr;           // value bits; jr[0..1]: first structure, count
+};
+// mem: 16-byte aligned LDS block of walk_cache_bytes(). Called by every
+// thread; false (the same for all) if the structures do not fit.
+template <int NT>
+__device__ inline bool fill_walk_cache(WalkCache& c, uint32_t* mem, const LayerGeom& g,
+                                       uint64_t lo, uint64_t hi) {
+  c.end = reinterpret_cast<uint64_t*>(mem);
+  c.span = c.end + kWalkCache;
+  c.bb = c.span + kWalkCache;
+  c.r = reinterpret_cast<uint32_t*>(c.bb + kWalkCache);
+  c.jr = c.r + kWalkCache;
+  if (threadIdx.x == 0) {
+    const uint32_t j0 = find_struct(g.key_off, g.J, lo);
+    c.jr[0] = j0;
+    c.jr[1] = find_struct(g.key_off, g.J, hi - 1) - j0 + 1;
+  }
+  __syncthreads();
+  const uint32_t j0 = c.jr[0], n = c.jr[1];
+  if (n > kWalkCache) return false;
+  for (uint32_t t = threadIdx.x; t < n; t += NT) {
+    c.end[t] = g.key_off[j0 + t + 1];
+    c.span[t] = g.span[j0 + t];
+    c.bb[t] = g.bucket_base[j0 + t];
+    c.r[t] = g.rbits[j0 + t];
+  }
+  __syncthreads();
+  return true;
+}
+struct CachedWalk {
+  const WalkCache& c;
+  uint32_t k;  // cached structure of the current key
+  uint64_t end, span, bb;
+  uint32_t r;
+  // i: the thread's first key, in [lo, hi) of the cache or past hi
+  __device__ CachedWalk(const WalkCache& cache, uint64_t i) : c(cache) {
+    uint32_t a = 0, b = c.jr[1] - 1;  // first k with end[k] > i (the last if none)
+    while (a < b) {
+      const uint32_t mid = (a + b) >> 1;
+      if (c.end[mid] > i) b = mid; else a = mid + 1;
+    }
+    k = a;
+    load();
+  }
+  __device__ void load() {
+    end = c.end[k];
+    span = c.span[k];
+    bb = c.bb[k];
+    r = c.r[k];
+  }
+  __device__ void advance(const LayerGeom&, uint64_t i) {
+    while (i >= end) {
+      ++k;
+      load();
+    }
+  }
 };
 
 // Level-1 bin of a global slot and the slot's offset within the bin. A bin
@@ -352,13 +445,13 @@ template <bool ONE>
 __global__ __launch_bounds__(kPartThreads) void k_p1_hist(const uint64_t* __restrict__ keys,
                                                           LayerGeom g, SortPlan sp,
                                                           uint32_t* __restrict__ counts) {
-  extern __shared__ uint32_t hist[];
+  extern __shared__ __align__(16) uint32_t hist[];  // nb1 counters, then (batches) the walk cache
   for (uint32_t i = threadIdx.x; i < sp.nb1; i += kPartThreads) hist[i] = 0;
   __syncthreads();
   const uint64_t lo = (uint64_t)blockIdx.x * sp.per_group;
   const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
   const BinSplit bs(sp);
-  auto w = WalkOf<ONE>::make(g, lo + threadIdx.x);
+  auto run = [&](auto& w) {
   for (uint64_t t0 = lo; t0 < hi; t0 += kHistPer * kPartThreads) {
     // all of a thread's loads are issued before the first is used (past
     // the end, the last key is read again and not counted)
@@ -375,8 +468,22 @@ __global__ __launch_bounds__(kPartThreads) void k_p1_hist(const uint64_t* __rest
         w.advance(g, i);
         const uint64_t slot = 64 * w.bb + start_of(kk[k], g.salt_s, w.span);
         uint32_t in_bin;
-        atomicAdd(&hist[bs.bin(slot, in_bin)], 1u);
+        key_count<!ONE>(hist, bs.bin(slot, in_bin));
       }
+    }
+  }
+  };
+  if constexpr (ONE) {
+    OneWalk w(g);
+    run(w);
+  } else {
+    WalkCache wc;
+    if (lo < hi && fill_walk_cache<kPartThreads>(wc, hist + ((sp.nb1 + 3) & ~3u), g, lo, hi)) {
+      CachedWalk w(wc, lo + threadIdx.x);
+      run(w);
+    } else {
+      KeyWalk w(g, lo + threadIdx.x);
+      run(w);
     }
   }
   __syncthreads();
@@ -391,10 +498,10 @@ __global__ __launch_bounds__(kCountThreads) void k_p1_count(const uint64_t* __re
                                                             LayerGeom g, SortPlan sp,
                                                             uint32_t* __restrict__ counts1,
                                                             uint32_t* __restrict__ counts2t) {
-  extern __shared__ uint32_t sm[];
+  extern __shared__ __align__(16) uint32_t sm[];
   const uint32_t nds = sp.nb1 * sp.S;
   uint32_t* h2 = sm;        // per (bin, sub-bin)
-  uint32_t* h1 = sm + nds;  // per (bin, slice)
+  uint32_t* h1 = sm + nds;  // per (bin, slice); then (batches) the walk cache
   for (uint32_t i = threadIdx.x; i < nds + sp.nb1 * sp.cc; i += kCountThreads) sm[i] = 0;
   __syncthreads();
   const BinSplit bs(sp);
@@ -404,7 +511,7 @@ __global__ __launch_bounds__(kCountThreads) void k_p1_count(const uint64_t* __re
     const uint64_t lo = w * sp.per_group;
     const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
     if (lo >= hi) break;
-    auto kw = WalkOf<ONE>::make(g, lo + threadIdx.x);
+    auto run = [&](auto& kw) {
     for (uint64_t t0 = lo; t0 < hi; t0 += kHistPer * kCountThreads) {
       uint64_t kk[kHistPer];  // all loads issued before the first is used
 #pragma unroll
@@ -421,9 +528,24 @@ __global__ __launch_bounds__(kCountThreads) void k_p1_count(const uint64_t* __re
           uint32_t in_bin;
           const uint32_t d = bs.bin(slot, in_bin);
           const uint32_t sb = in_bin / kSubSlots;
-          atomicAdd(&h2[d * sp.S + sb], 1u);
-          atomicAdd(&h1[d * sp.cc + wl], 1u);
+          key_count<!ONE>(h2, d * sp.S + sb);
+          key_count<!ONE>(h1, d * sp.cc + wl);
         }
+      }
+    }
+    };
+    if constexpr (ONE) {
+      OneWalk kw(g);
+      run(kw);
+    } else {
+      __syncthreads();  // the previous slice's walk is done with the cache
+      WalkCache wc;
+      if (fill_walk_cache<kCountThreads>(wc, sm + ((nds + sp.nb1 * sp.cc + 3) & ~3u), g, lo, hi)) {
+        CachedWalk kw(wc, lo + threadIdx.x);
+        run(kw);
+      } else {
+        KeyWalk kw(g, lo + threadIdx.x);
+        run(kw);
       }
     }
   }
@@ -576,27 +698,20 @@ struct PartLds {
 };
 
 // Level 1, pass 2: hash, mask or fingerprint the value, write tile runs per bin.
-template <typename VT, bool PACKED, int NT, bool ONE>
-__global__ __launch_bounds__(NT) void k_p1_scatter(
-    const uint64_t* __restrict__ keys, const VT* __restrict__ vals, LayerGeom g, SortPlan sp,
-    const uint32_t* __restrict__ offs, uint32_t mask_values, uint32_t filter, uint64_t fp_salt,
-    uint32_t fp_late, void* __restrict__ out_raw) {
-  using R = typename PRec<PACKED>::T;
-  extern __shared__ __align__(16) uint32_t sm[];
+// Level 1, pass 2, the tiles of a workgroup's keys [lo, hi) (W: how a
+// thread finds the structure of its keys)
+template <typename VT, bool PACKED, int NT, bool ONE, class W,
+          class R = typename PRec<PACKED>::T>
+__device__ __forceinline__ void p1_tiles(const uint64_t* __restrict__ keys,
+                                         const VT* __restrict__ vals, const LayerGeom& g,
+                                         const SortPlan& sp, PartLds<NT, kPartPer, R>& L,
+                                         uint64_t lo, uint64_t hi, uint32_t mask_values,
+                                         uint32_t filter, uint64_t fp_salt, uint32_t fp_late,
+                                         R* __restrict__ out, W& w) {
   constexpr int PER = kPartPer;
-  const bool no_vals = filter && (mask_values || fp_late);  // values not read
-  PartLds<NT, PER, R> L(sm, sp.nb1);
   constexpr uint32_t T1 = NT * PER;
-  R* out = reinterpret_cast<R*>(out_raw);
-  for (uint32_t d = threadIdx.x; d < sp.nb1; d += NT) {
-    L.cur[d] = offs[(size_t)d * sp.G1 + blockIdx.x];
-    L.toff[d] = 0;
-  }
-  __syncthreads();
-  const uint64_t lo = (uint64_t)blockIdx.x * sp.per_group;
-  const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
+  const bool no_vals = filter && (mask_values || fp_late);  // values not read
   const BinSplit bs(sp);
-  auto w = WalkOf<ONE>::make(g, lo + threadIdx.x);
   for (uint64_t t0 = lo; t0 < hi; t0 += T1) {
     R rec[PER];
     uint32_t dr[PER];
@@ -631,12 +746,48 @@ __global__ __launch_bounds__(NT) void k_p1_scatter(
         uint32_t in_bin;
         const uint32_t d = bs.bin(slot, in_bin);
         rec[k] = PRec<PACKED>::make(key, in_bin, v);
-        dr[k] = d << kRankBits | atomicAdd(&L.toff[d], 1u);
+        dr[k] = d << kRankBits | key_count<!ONE>(L.toff, d);
       }
     }
     const uint32_t ntile = (uint32_t)(hi - t0 < T1 ? hi - t0 : T1);
     __syncthreads();
     tile_write<NT, PER, R>(rec, dr, sp.nb1, L.cur, L.toff, L.stage, L.sdig, L.wsum, ntile, out);
+  }
+}
+
+template <typename VT, bool PACKED, int NT, bool ONE>
+__global__ __launch_bounds__(NT) void k_p1_scatter(
+    const uint64_t* __restrict__ keys, const VT* __restrict__ vals, LayerGeom g, SortPlan sp,
+    const uint32_t* __restrict__ offs, uint32_t mask_values, uint32_t filter, uint64_t fp_salt,
+    uint32_t fp_late, void* __restrict__ out_raw) {
+  using R = typename PRec<PACKED>::T;
+  extern __shared__ __align__(16) uint32_t sm[];
+  constexpr int PER = kPartPer;
+  PartLds<NT, PER, R> L(sm, sp.nb1);
+  R* out = reinterpret_cast<R*>(out_raw);
+  for (uint32_t d = threadIdx.x; d < sp.nb1; d += NT) {
+    L.cur[d] = offs[(size_t)d * sp.G1 + blockIdx.x];
+    L.toff[d] = 0;
+  }
+  __syncthreads();
+  const uint64_t lo = (uint64_t)blockIdx.x * sp.per_group;
+  const uint64_t hi = lo + sp.per_group < g.nkeys ? lo + sp.per_group : g.nkeys;
+  if constexpr (ONE) {
+    OneWalk w(g);
+    p1_tiles<VT, PACKED, NT, ONE>(keys, vals, g, sp, L, lo, hi, mask_values, filter, fp_salt,
+                                  fp_late, out, w);
+  } else {  // the walk cache after the tile's LDS
+    WalkCache wc;
+    uint32_t* cmem = sm + (uint32_t)((part_lds_bytes<NT, PER>(sp.nb1, sizeof(R)) + 15) / 16 * 4);
+    if (lo < hi && fill_walk_cache<NT>(wc, cmem, g, lo, hi)) {
+      CachedWalk w(wc, lo + threadIdx.x);
+      p1_tiles<VT, PACKED, NT, ONE>(keys, vals, g, sp, L, lo, hi, mask_values, filter, fp_salt,
+                                    fp_late, out, w);
+    } else {
+      KeyWalk w(g, lo + threadIdx.x);
+      p1_tiles<VT, PACKED, NT, ONE>(keys, vals, g, sp, L, lo, hi, mask_values, filter, fp_salt,
+                                    fp_late, out, w);
+    }
   }
 }
 
@@ -727,7 +878,7 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_hist(const void* __restric
       if (PACKED) sl[k] &= 0xffffffu;
 #pragma unroll
     for (int k = 0; k < kHistPer; ++k)
-      if (t0 + threadIdx.x + k * kPart2Threads < ch.hi) atomicAdd(&hist[sl[k] / kSubSlots], 1u);
+      if (t0 + threadIdx.x + k * kPart2Threads < ch.hi) lds_count(hist, sl[k] / kSubSlots);
   }
   __syncthreads();
   const uint32_t nc = nch[ch.b];
@@ -790,7 +941,7 @@ __global__ __launch_bounds__(kPart2Threads) void k_p2_scatter(
       dr[k] = kNoDigit;
       if (i < ch.hi) {
         const uint32_t d = PRec<PACKED>::slot(rec[k]) / kSubSlots;
-        dr[k] = d << kRankBits | atomicAdd(&L.toff[d], 1u);
+        dr[k] = d << kRankBits | lds_count(L.toff, d);
       }
     }
     const uint32_t ntile = ch.hi - t0 < T2 ? ch.hi - t0 : T2;
@@ -999,15 +1150,20 @@ hipError_t sort_layer_t(const SortArgs& a, bool fp_late, hipStream_t s) {
       (void)hipFuncSetAttribute((const void*)k_p1_count<true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       k_p1_count<true><<<sp.Hc, kCountThreads, lds, s>>>(a.keys, a.g, sp, a.counts1, a.counts2);
-    } else {
+    } else {  // + the walk cache
+      const size_t ldsw = (lds + 15) / 16 * 16 + walk_cache_bytes();
       (void)hipFuncSetAttribute((const void*)k_p1_count<false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      k_p1_count<false><<<sp.Hc, kCountThreads, lds, s>>>(a.keys, a.g, sp, a.counts1, a.counts2);
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsw);
+      k_p1_count<false><<<sp.Hc, kCountThreads, ldsw, s>>>(a.keys, a.g, sp, a.counts1,
+                                                           a.counts2);
     }
   } else if (a.g.J == 1) {
     k_p1_hist<true><<<sp.G1, kPartThreads, (size_t)sp.nb1 * 4, s>>>(a.keys, a.g, sp, a.counts1);
-  } else {
-    k_p1_hist<false><<<sp.G1, kPartThreads, (size_t)sp.nb1 * 4, s>>>(a.keys, a.g, sp, a.counts1);
+  } else {  // + the walk cache
+    const size_t lds = (size_t)((sp.nb1 + 3) & ~3u) * 4 + walk_cache_bytes();
+    (void)hipFuncSetAttribute((const void*)k_p1_hist<false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_p1_hist<false><<<sp.G1, kPartThreads, lds, s>>>(a.keys, a.g, sp, a.counts1);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = scan_exclusive(a.counts1, (size_t)sp.nb1 * sp.G1, a.scan_tmp, s)) != hipSuccess) return e;
@@ -1017,6 +1173,7 @@ hipError_t sort_layer_t(const SortArgs& a, bool fp_late, hipStream_t s) {
     constexpr int NT = decltype(nt)::value;
     using VT = typename decltype(vt)::type;
     const size_t lds = part_lds_bytes<NT, kPartPer>(sp.nb1, sizeof(R));
+    const size_t lds_walk = (lds + 15) / 16 * 16 + walk_cache_bytes();  // batches: + walk cache
     if (a.g.J == 1) {
       (void)hipFuncSetAttribute((const void*)k_p1_scatter<VT, PACKED, NT, true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1025,8 +1182,8 @@ hipError_t sort_layer_t(const SortArgs& a, bool fp_late, hipStream_t s) {
           fp_late ? 1u : 0u, a.r1);
     } else {
       (void)hipFuncSetAttribute((const void*)k_p1_scatter<VT, PACKED, NT, false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      k_p1_scatter<VT, PACKED, NT, false><<<sp.G1, NT, lds, s>>>(
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_walk);
+      k_p1_scatter<VT, PACKED, NT, false><<<sp.G1, NT, lds_walk, s>>>(
           a.keys, (const VT*)a.vals, a.g, sp, a.counts1, a.mask_values, a.filter, a.fp_salt,
           fp_late ? 1u : 0u, a.r1);
     }
