@@ -190,7 +190,7 @@ constexpr uint32_t kSingleLevelSubs = 128;
 constexpr uint32_t kCountThreads = 1024;
 constexpr uint32_t kCountSlicesMax = 32;
 constexpr uint32_t kChunkFused = 3800;
-constexpr uint32_t kCountWgs = 512;
+constexpr uint32_t kCountWgs = 256;  // one per CU: its counters fill most of a CU's LDS
 constexpr uint32_t kCountLdsMax = 112 * 1024;  // one counting workgroup per CU
 constexpr uint32_t kColBlock = 32;             // h per block of the prefix over h
 __host__ __device__ constexpr uint64_t count_lds_bytes(uint32_t nb1, uint32_t S, uint32_t cs) {
