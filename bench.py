@@ -375,9 +375,14 @@ def run_batched(args, dev):
                 b.free()
         return b, np.array(times) * 1e3
 
+    def table_bits(bb):  # bits per key of every member's table
+        return 8 * sum(bb.member(i).stats()["table_bytes"] for i in range(count)) / N
+
     b, ms_default = timed(lambda: burr.build_batch(keys, vals, offs, rs, params))
+    bits_default = table_bits(b)
     b.free()
     b, ms = timed(lambda: burr.build_batch_tuned(keys, vals, offs, rs, table, params))
+    bits_tuned = table_bits(b)
     # spot check: members of sampled structures retrieve their values
     ok = True
     for i in np.linspace(0, count - 1, 64).astype(int):
@@ -419,6 +424,7 @@ def run_batched(args, dev):
         "build_ms_p50": round(float(np.percentile(ms, 50)), 2),
         "build_ms_max": round(float(ms.max()), 2),
         "untuned_minbpt16_build_ms_p50": round(float(np.percentile(ms_default, 50)), 2),
+        "table_bits_per_key": {"tuned": round(bits_tuned, 4), "untuned_minbpt16": round(bits_default, 4)},
         "members_ok": ok,
         "layer0_device_ms": {k: round(st["layers"][0][k], 3) for k in
                              ("ms_sort", "ms_solve", "ms_backsub", "ms_gather")},

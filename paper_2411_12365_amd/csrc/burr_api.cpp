@@ -389,7 +389,11 @@ struct Workspace {
   uint64_t cap_m[2] = {0, 0};
   hipStream_t side = nullptr;  // back-substitution (default priority, non-blocking)
   std::vector<hipEvent_t> evs;  // a build's timing and ordering events, kept for the next
-  uint8_t* code8 = nullptr;
+  // per-bucket codes of a BuRR layer, one buffer per row set: a layer's
+  // codes are packed on the side stream before its back-substitution,
+  // while the next layer's insertion writes the other buffer
+  uint8_t* codes8[2] = {nullptr, nullptr};
+  uint64_t cap_codes[2] = {0, 0};
   uint32_t *bump = nullptr, *bstart = nullptr, *scan_tmp = nullptr;
   uint32_t* pcount = nullptr;  // 1+-bit thresholds: popcounts of the bit words, scanned
   uint64_t cap_pc = 0;
@@ -541,10 +545,15 @@ struct Workspace {
     cap_scan = need;
     return alloc(scan_tmp, need);
   }
+  bool reserve_codes(uint64_t B, int set) {
+    if (B <= cap_codes[set] && codes8[set]) return true;
+    cap_codes[set] = B;
+    return alloc(codes8[set], B + 1);
+  }
   bool reserve_buckets(uint64_t B) {
     if (B <= cap_B && bump) return reserve_scan(B + 1);
     cap_B = B;
-    return alloc(code8, B + 1) && alloc(bump, B + 1) && alloc(bstart, B + 1) &&
+    return alloc(bump, B + 1) && alloc(bstart, B + 1) &&
            reserve_scan(B + 1);
   }
   bool reserve_sort(const SortPlan& sp) {
@@ -935,6 +944,8 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     int set = 0;
     LayerGeom g{};
     uint64_t* W = nullptr;
+    uint64_t ncode = 0;         // 2-bit codes to pack first (0: packed already)
+    uint64_t* codes = nullptr;
   } pend;
   // after: an event of the build's stream the back-substitution also waits
   // for (the next layer's sort done), or null
@@ -945,6 +956,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     HIP_TRY(hipStreamWaitEvent(side, e[2], 0));
     if (after) HIP_TRY(hipStreamWaitEvent(side, after, 0));
     HIP_TRY(hipEventRecord(e[3], side));
+    if (pend.ncode) HIP_TRY(pack_codes(ws.codes8[pend.set], pend.g, pend.ncode, pend.codes, side));
     HIP_TRY(back_substitute(ws.rowsC[pend.set], ws.rowsV[pend.set], pend.g, pend.W, side));
     HIP_TRY(hipEventRecord(e[4], side));
     return BURR_OK;
@@ -1002,7 +1014,8 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     if (li >= 2) HIP_TRY(hipStreamWaitEvent(s, bs_end(li - 2), 0));
     int rc = upload_table(ws, t, g, s, set);
     if (rc != BURR_OK) return rc;
-    if (!ws.reserve_slots(g.m, set) || !ws.reserve_buckets(g.nbuckets) || !ws.reserve_structs(g.J))
+    if (!ws.reserve_slots(g.m, set) || !ws.reserve_buckets(g.nbuckets) ||
+        !ws.reserve_codes(g.nbuckets, set) || !ws.reserve_structs(g.J))
       return set_error(BURR_E_NOMEM);
     LS.codes = (uint64_t*)b->alloc_table(t.code_base.back() * 8);
     LS.W = (uint64_t*)b->alloc_table(t.word_base.back() * 8);
@@ -1039,7 +1052,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     sa.rowsC = ws.rowsC[set];
     sa.rowsV = ws.rowsV[set];
     sa.occ = ws.occ[set];
-    sa.code8 = ws.code8;
+    sa.code8 = ws.codes8[set];
     sa.bump = ws.bump;
     sa.fail = ws.fail;
     sa.steps = ws.steps;
@@ -1058,12 +1071,16 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     pend.set = set;
     pend.g = g;
     pend.W = LS.W;
-    // codes now: the next layer's insertion rewrites code8
+    pend.ncode = 0;
+    pend.codes = LS.codes;
+    // 2-bit codes are packed with the back-substitution (side stream; the
+    // next layer's insertion writes the other code buffer); 1+-bit
+    // thresholds now, as their packing shares the build stream's scan buffers
     if (p.threshold_mode == 1)
-      HIP_TRY(pack_thresholds(ws.code8, g, t.code_base.back(), LS.codes, ws.pcount, ws.scan_tmp,
-                              LS.thr, LS.rank, LS.kcount, s));
+      HIP_TRY(pack_thresholds(ws.codes8[set], g, t.code_base.back(), LS.codes, ws.pcount,
+                              ws.scan_tmp, LS.thr, LS.rank, LS.kcount, s));
     else
-      HIP_TRY(pack_codes(ws.code8, g, t.code_base.back(), LS.codes, s));
+      pend.ncode = t.code_base.back();
 
     // per-structure bump counts (an exclusive scan of the per-bucket counts)
     // go to the host first: they are all the next layer's planning needs, so
@@ -1382,7 +1399,7 @@ uint64_t burr_workspace_bytes(uint64_t n, uint32_t rmax, uint32_t count, const b
   bytes += 44 * std::max<uint64_t>(n, 1);              // next keys/values, sort intermediates
   bytes += 16 * (n + B + 1);                           // item stream
   bytes += 12 * m + 8 * (B + 1);                       // rows and occupancy
-  bytes += 9 * (B + 1) + 4 * ((B + 2047) / 2048) * 2048 + 4 * (B + 64);  // codes, counts, scans
+  bytes += 10 * (B + 1) + 4 * ((B + 2047) / 2048) * 2048 + 4 * (B + 64);  // codes (2 sets), counts, scans
   bytes += 8 * (7ull * (count + 1) + 8);               // per-structure tables
   bytes += 36ull * 64 * (mf / 64 / 4 + count);         // final-layer segments
   if (staged) bytes += (8 + (rmax <= 8 ? 1 : rmax <= 16 ? 2 : 4)) * n;
