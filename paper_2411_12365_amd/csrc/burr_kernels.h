@@ -101,9 +101,13 @@ hipError_t solve_layer(const SolveArgs& a, hipStream_t s);
 // W[word_base[j] + k*r_j + col]. Free slots hold row 0 and value 0 (as every
 // released block does). bnd (optional, 64 u32 per range): solution values of
 // the 63 slots after each range's end (final-layer segments, whose rows
-// cross segment ends).
+// cross segment ends). max_waves (0: one wave per NG ranges): the grid's
+// width, but at least a quarter of the full grid (a long back-substitution
+// held to a few waves would outlast the work it overlaps); its waves then
+// take the ranges in turn.
 hipError_t back_substitute(const uint64_t* rowsC, const uint32_t* rowsV, const LayerGeom& g,
-                           uint64_t* W, hipStream_t s, const uint32_t* bnd = nullptr);
+                           uint64_t* W, hipStream_t s, const uint32_t* bnd = nullptr,
+                           uint32_t max_waves = 0);
 
 // code8[B] -> packed 2-bit code words of every structure
 hipError_t pack_codes(const uint8_t* code8, const LayerGeom& g, uint64_t ncode_words,

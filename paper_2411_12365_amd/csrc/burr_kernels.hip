@@ -1988,7 +1988,11 @@ __global__ __launch_bounds__(64) void k_backsub(const uint64_t* __restrict__ row
   __shared__ uint64_t sc[2][NG][65];  // rows shifted right by 1 (bit 0 is the pivot)
   __shared__ uint32_t sv[2][NG][65];
   const uint32_t lane = threadIdx.x, grp = lane / RG, col = lane % RG;
-  const uint64_t rho = (uint64_t)blockIdx.x * NG + grp;
+  // a wave takes NG ranges at a time, the grid's waves in turn (the grid may
+  // be narrower than the ranges: a back-substitution beside other layers'
+  // work is given a bounded share of the device)
+  for (uint64_t rho0 = (uint64_t)blockIdx.x * NG; rho0 < g.nranges; rho0 += (uint64_t)gridDim.x * NG) {
+  const uint64_t rho = rho0 + grp;
   const bool valid = rho < g.nranges;
   uint32_t r = 0;
   uint64_t fb = 0, lb = 0, wb = 0, bb = 0;
@@ -2042,18 +2046,25 @@ __global__ __launch_bounds__(64) void k_backsub(const uint64_t* __restrict__ row
       if (col < r) W[wb + (k - bb) * r + col] = win;
     }
   }
+  __syncthreads();  // the next ranges reuse the LDS blocks
+  }
 #undef BURR_BS_LOAD
 }
 
 hipError_t back_substitute(const uint64_t* rowsC, const uint32_t* rowsV, const LayerGeom& g,
-                           uint64_t* W, hipStream_t s, const uint32_t* bnd) {
+                           uint64_t* W, hipStream_t s, const uint32_t* bnd, uint32_t max_waves) {
   if (g.nranges == 0) return hipSuccess;
+  auto grid = [&](uint64_t per_wave) {  // at least a quarter of the full grid
+    const uint64_t w = (g.nranges + per_wave - 1) / per_wave;
+    const uint64_t cap = max_waves > w / 4 ? max_waves : w / 4;
+    return (unsigned)(max_waves && w > cap ? cap : w);
+  };
   if (g.r <= 8)
-    k_backsub<8><<<(unsigned)((g.nranges + 7) / 8), 64, 0, s>>>(rowsC, rowsV, g, W, bnd);
+    k_backsub<8><<<grid(8), 64, 0, s>>>(rowsC, rowsV, g, W, bnd);
   else if (g.r <= 16)
-    k_backsub<16><<<(unsigned)((g.nranges + 3) / 4), 64, 0, s>>>(rowsC, rowsV, g, W, bnd);
+    k_backsub<16><<<grid(4), 64, 0, s>>>(rowsC, rowsV, g, W, bnd);
   else
-    k_backsub<32><<<(unsigned)((g.nranges + 1) / 2), 64, 0, s>>>(rowsC, rowsV, g, W, bnd);
+    k_backsub<32><<<grid(2), 64, 0, s>>>(rowsC, rowsV, g, W, bnd);
   return hipGetLastError();
 }
 
