@@ -107,6 +107,65 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(uint32_t* data, size_
     if (base + k < n) data[base + k] += add;
 }
 
+// The same with the tile sums not yet scanned: each workgroup adds up the
+// sums of the tiles before it (at most kScanAddTiles of them, read from L2),
+// which saves the launch of a scan of the sums
+constexpr size_t kScanAddTiles = 2048;
+__global__ __launch_bounds__(kScanThreads) void k_scan_add_raw(uint32_t* data, size_t n,
+                                                                const uint32_t* sums) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  uint32_t part = 0;
+  for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kScanThreads) part += sums[t];
+  for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
+  if ((threadIdx.x & 63u) == 0) wsum[threadIdx.x >> 6] = part;
+  __syncthreads();
+  uint32_t add = 0;
+#pragma unroll
+  for (int w = 0; w < kScanThreads / 64; ++w) add += wsum[w];
+  const size_t base = (size_t)blockIdx.x * kScanTile;
+  for (size_t k = threadIdx.x; k < kScanTile; k += kScanThreads)
+    if (base + k < n) data[base + k] += add;
+}
+
+// One workgroup scans up to kScanOneMax words (one launch instead of two
+// or three for the small scans): the words move between HBM and LDS
+// coalesced, and each thread scans kScanOnePer consecutive words in LDS
+// (word i at i + i/32, so that the threads' strided reads hit distinct banks)
+// around one block-wide scan of the thread totals.
+constexpr int kScanOneThreads = 1024;
+constexpr int kScanOnePer = 32;
+constexpr size_t kScanOneMax = (size_t)kScanOneThreads * kScanOnePer;
+constexpr size_t kScanOneLds = (kScanOneMax + kScanOneMax / 32) * 4;
+__global__ __launch_bounds__(kScanOneThreads) void k_scan_one(uint32_t* data, size_t n) {
+  __shared__ uint32_t wsum[kScanOneThreads / 64];
+  __shared__ uint32_t total;
+  extern __shared__ uint32_t buf[];
+  const uint32_t nn = (uint32_t)n;
+#pragma unroll 8
+  for (uint32_t k = 0; k < (uint32_t)kScanOnePer; ++k) {
+    const uint32_t i = k * kScanOneThreads + threadIdx.x;
+    buf[i + i / 32] = i < nn ? data[i] : 0u;
+  }
+  __syncthreads();
+  const uint32_t base = threadIdx.x * kScanOnePer;
+  uint32_t tot = 0;
+#pragma unroll 8
+  for (uint32_t k = 0; k < (uint32_t)kScanOnePer; ++k) tot += buf[base + k + (base + k) / 32];
+  uint32_t run = block_exclusive_scan<kScanOneThreads>(tot, wsum, &total);
+#pragma unroll 8
+  for (uint32_t k = 0; k < (uint32_t)kScanOnePer; ++k) {
+    const uint32_t i = base + k, x = buf[i + i / 32];
+    buf[i + i / 32] = run;
+    run += x;
+  }
+  __syncthreads();
+#pragma unroll 8
+  for (uint32_t k = 0; k < (uint32_t)kScanOnePer; ++k) {
+    const uint32_t i = k * kScanOneThreads + threadIdx.x;
+    if (i < nn) data[i] = buf[i + i / 32];
+  }
+}
+
 size_t scan_tmp_words(size_t n) {
   size_t w = 0;
   while (n > kScanTile) {
@@ -120,6 +179,12 @@ hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s
   if (n == 0) return hipSuccess;
   size_t tiles = (n + kScanTile - 1) / kScanTile;
   const bool vec = reinterpret_cast<uintptr_t>(data) % 16 == 0;
+  if (tiles > 1 && n <= kScanOneMax) {
+    (void)hipFuncSetAttribute((const void*)k_scan_one, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)kScanOneLds);
+    k_scan_one<<<1, kScanOneThreads, kScanOneLds, s>>>(data, n);
+    return hipGetLastError();
+  }
   if (tiles == 1) {
     if (vec)
       k_scan_tile<true><<<1, kScanThreads, 0, s>>>(data, n, nullptr);
@@ -133,6 +198,10 @@ hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s
     k_scan_tile<false><<<(unsigned)tiles, kScanThreads, 0, s>>>(data, n, tmp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (tiles <= kScanAddTiles) {  // the tile sums are added up where they are used
+    k_scan_add_raw<<<(unsigned)tiles, kScanThreads, 0, s>>>(data, n, tmp);
+    return hipGetLastError();
+  }
   e = scan_exclusive(tmp, tiles, tmp + tiles, s);
   if (e != hipSuccess) return e;
   k_scan_add<<<(unsigned)tiles, kScanThreads, 0, s>>>(data, n, tmp);
