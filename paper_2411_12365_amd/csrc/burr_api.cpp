@@ -50,6 +50,10 @@ constexpr int kRowSets = kBurrSets + 1;
 // and does not hold back their short launches behind a full grid (measured
 // at 100M keys: 5.35 ms of device time against 5.37 with a full grid and
 // 5.39 with one wave per SIMD)
+#ifndef BURR_EARLY_BACKSUB_J
+#define BURR_EARLY_BACKSUB_J 4096
+#endif
+constexpr uint32_t kEarlyBacksubStructs = BURR_EARLY_BACKSUB_J;
 constexpr uint32_t kSideBacksubWaves = 2048;
 // item indices (one per key plus one per bucket) are 32-bit
 constexpr uint64_t kMaxKeys = 0xf0000000ull;
@@ -625,7 +629,11 @@ int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s, int
   // the pinned staging is reused only after the stream has passed this copy
   // (the host waits for each layer's results, which follow it on the stream)
   uint64_t* h = reinterpret_cast<uint64_t*>(ws.host);
-  memset(h, 0, words * 8);
+  // only the words no copy below fills are cleared: the last word of the
+  // span run, the odd half word after rbits and the trailing pad word
+  h[2 * (J + 1) - 1] = 0;
+  h[8 * (J + 1) + J / 2] = 0;
+  h[words - 1] = 0;
   memcpy(h, t.key_off.data(), (J + 1) * 8);
   memcpy(h + (J + 1), t.span.data(), J * 8);
   memcpy(h + 2 * (J + 1), t.bucket_base.data(), (J + 1) * 8);
@@ -842,11 +850,12 @@ struct WsLease {
 // deeper layers at the bump-rate bound, plus the final layer.
 uint64_t batch_table_estimate(const burr_batch* b, const std::vector<uint64_t>& off) {
   uint64_t words = 0;
+  const LayerPlanner planner(b->p);
   for (size_t i = 0; i < b->members.size(); ++i) {
     const uint64_t n = off[i + 1] - off[i];
     if (!n) continue;
     uint64_t m, R;
-    plan_layer(b->p, n, &m, &R);
+    planner.plan(n, b->members[i].minbpt, &m, &R);
     const uint64_t B = m / 64;
     words += B * b->members[i].r + (B + 31) / 32;
     // 1+-bit: thresholds (a byte per bucket at most), rank directory, count
@@ -1109,6 +1118,10 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     HIP_TRY(hipEventRecord(el[5], s));
     HIP_TRY(gather_bumped(ws.rec, ws.bstart, ws.bump, g.nbuckets, ws.keysA, ws.valsA, s));
     HIP_TRY(hipEventRecord(el[6], s));
+    if (g.J >= kEarlyBacksubStructs) {
+      rc = launch_backsub(el[6]);
+      if (rc != BURR_OK) return rc;
+    }
     nlayers = li + 1;
     HOST_LAP(hc, "launch", li);
     HIP_TRY(hipEventSynchronize(el[5]));
