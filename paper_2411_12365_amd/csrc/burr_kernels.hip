@@ -2380,10 +2380,11 @@ hipError_t final_merge(const FinalArgs& a, uint64_t max_segments, hipStream_t s)
 // values selected by a 63-bit dependence word X. Lane b < 63 carries bit b
 // of X through a 64-bit window (bit k = X[i+1+k] bit b; past the segment end
 // X[end+k] is the unit word e_k), lane c < r carries column c of z0; the
-// first 63 slots' words are assembled with ballots.
+// first 63 slots' words are assembled with ballots. Lane t holds row and
+// value of slot t of the current block, and every step takes the slot's
+// row and value from it with v_readlane (scalar results), so the steps wait
+// for no memory round trip (through LDS, each step waited for two).
 __global__ __launch_bounds__(64) void k_final_partial(FinalArgs a) {
-  __shared__ uint64_t sc[2][64];  // rows shifted right by 1
-  __shared__ uint32_t sv[2][64];
   const LayerGeom g = a.g;
   const uint32_t lane = threadIdx.x;
   const uint64_t p = blockIdx.x;
@@ -2404,35 +2405,50 @@ __global__ __launch_bounds__(64) void k_final_partial(FinalArgs a) {
     pc = a.rowsC[(k - 1) * 64 + lane];
     pv = a.rowsV[(k - 1) * 64 + lane];
   }
-  for (uint32_t buf = 0; k-- > kb; buf ^= 1u) {
-    sc[buf][lane] = pc >> 1;
-    sv[buf][lane] = pv;
-    __syncthreads();
+  const uint32_t vsh = lane < 32 ? lane : 31u;  // lanes >= 32 carry no value column
+  const uint32_t vmask = lane < 32 ? 1u : 0u;
+  // words of the first 63 slots: lane t keeps slot start+t's, stored at the end
+  uint64_t myX = 0;
+  uint32_t myZ = 0;
+  while (k-- > kb) {
+    const uint64_t cc = pc >> 1;  // rows without their leading bit
+    const uint32_t clo = (uint32_t)cc, chi = (uint32_t)(cc >> 32), cv = pv;
     if (k > kb) {
       pc = a.rowsC[(k - 1) * 64 + lane];
       pv = a.rowsV[(k - 1) * 64 + lane];
     }
-    const bool head = k * 64 - start < 63;  // the block holds some of the first 63 slots
-#pragma unroll 8
-    for (int tt = 63; tt >= 0; --tt) {
-      const uint64_t C = sc[buf][tt];
-      const uint32_t vbit = lane < 32 ? (sv[buf][tt] >> lane) : 0u;
-      const uint32_t x1 = ((uint32_t)C & (uint32_t)wx) ^ ((uint32_t)(C >> 32) & (uint32_t)(wx >> 32));
-      const uint32_t x2 = ((uint32_t)C & (uint32_t)wz) ^ ((uint32_t)(C >> 32) & (uint32_t)(wz >> 32));
-      const uint64_t xb = (uint32_t)__popc(x1) & 1u;
-      const uint64_t zb = ((uint32_t)__popc(x2) + vbit) & 1u;
+    auto step = [&](int tt, uint64_t& xb, uint64_t& zb) {
+      const uint32_t Clo = __builtin_amdgcn_readlane(clo, tt);
+      const uint32_t Chi = __builtin_amdgcn_readlane(chi, tt);
+      const uint32_t vbit = (__builtin_amdgcn_readlane(cv, tt) >> vsh) & vmask;
+      const uint32_t x1 = (Clo & (uint32_t)wx) ^ (Chi & (uint32_t)(wx >> 32));
+      const uint32_t x2 = (Clo & (uint32_t)wz) ^ (Chi & (uint32_t)(wz >> 32));
+      xb = (uint32_t)__popc(x1) & 1u;
+      zb = ((uint32_t)__popc(x2) + vbit) & 1u;
       wx = (wx << 1) | xb;
       wz = (wz << 1) | zb;
-      const uint64_t i = k * 64 + (uint64_t)tt;
-      if (head && i - start < 63) {
+    };
+    if (k > kb) {  // start and end are multiples of 64: only block kb holds the first slots
+#pragma unroll 16
+      for (int tt = 63; tt >= 0; --tt) {
+        uint64_t xb, zb;
+        step(tt, xb, zb);
+      }
+    } else {
+#pragma unroll 16
+      for (int tt = 63; tt >= 0; --tt) {
+        uint64_t xb, zb;
+        step(tt, xb, zb);
         const uint64_t X = __ballot(xb != 0) & 0x7fffffffffffffffull;
-        const uint64_t Z = __ballot(zb != 0) & zmask;
-        if (lane == 0) {
-          a.xfirst[p * 64 + (i - start)] = X;
-          a.z0first[p * 64 + (i - start)] = (uint32_t)Z;
-        }
+        const uint32_t Z = (uint32_t)(__ballot(zb != 0) & zmask);
+        myX = (uint32_t)tt == lane ? X : myX;
+        myZ = (uint32_t)tt == lane ? Z : myZ;
       }
     }
+  }
+  if (lane < 63) {
+    a.xfirst[p * 64 + lane] = myX;
+    a.z0first[p * 64 + lane] = myZ;
   }
 }
 
