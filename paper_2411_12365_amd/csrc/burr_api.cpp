@@ -666,7 +666,7 @@ int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s, int
 // Sorts one layer's keys by (bucket, chunk) into the item stream ws.rec and ws.bstart.
 int run_sort(Workspace& ws, const uint64_t* keys, const void* vals, uint32_t vbytes,
              bool first_layer, bool filter, uint64_t fp_salt, const LayerGeom& g,
-             hipStream_t s) {
+             hipStream_t s, const SortClear& clear) {
   SortArgs a{};
   a.keys = keys;
   a.vals = vals;
@@ -689,6 +689,7 @@ int run_sort(Workspace& ws, const uint64_t* keys, const void* vals, uint32_t vby
   a.r2 = ws.p2;
   a.out_rec = ws.rec;
   a.bstart = ws.bstart;
+  a.clear = clear;
   HIP_TRY(sort_layer(a, s));
   return BURR_OK;
 }
@@ -729,10 +730,12 @@ int final_attempt(burr_batch* b, Workspace& ws, int set, const std::vector<uint3
   if (!ws.reserve_slots(g.m, set) || !ws.reserve_buckets(g.nbuckets) ||
       !ws.reserve_structs(g.J) || !ws.reserve_segments(g.nranges))
     return set_error(BURR_E_NOMEM);
-  rc = run_sort(ws, keys, vals, vbytes, first_layer, p.filter_mode != 0, mix64(~p.seed), g, s);
+  // the sort also clears the failure flags and the segments' spill occupancy
+  const SortClear clear{{ws.res, reinterpret_cast<uint32_t*>(ws.spill_occ)},
+                        {ws.results_words(g.J), 2 * g.nranges}};
+  rc = run_sort(ws, keys, vals, vbytes, first_layer, p.filter_mode != 0, mix64(~p.seed), g, s,
+                clear);
   if (rc != BURR_OK) return rc;
-  HIP_TRY(hipMemsetAsync(ws.res, 0, ws.results_words(g.J) * 4, s));
-  HIP_TRY(hipMemsetAsync(ws.spill_occ, 0, g.nranges * 8, s));
   SolveArgs sa{};
   sa.rec = ws.rec;
   sa.bstart = ws.bstart;
@@ -1066,7 +1069,12 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
       HIP_TRY(hipMemcpyAsync(LS.keys, cur_keys, g.nkeys * 8, hipMemcpyDeviceToDevice, s));
     }
     HIP_TRY(hipEventRecord(el[0], s));
-    rc = run_sort(ws, cur_keys, cur_vals, cur_vbytes, first, p.filter_mode != 0, fp_salt, g, s);
+    // the sort also clears the insertion's results (failure flags, step
+    // counter) and the last entry of the bump counts, which the scan after
+    // the insertion reads
+    const SortClear clear{{ws.res, ws.bump + g.nbuckets}, {ws.results_words(g.J), 1}};
+    rc = run_sort(ws, cur_keys, cur_vals, cur_vbytes, first, p.filter_mode != 0, fp_salt, g, s,
+                  clear);
     if (rc != BURR_OK) return rc;
     if (cuts) {  // range ends chosen from the sorted buckets (kept with the tables)
       HIP_TRY(choose_cuts(ws.rec, ws.bstart, g, LS.rfirst, s));
@@ -1086,7 +1094,6 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     sa.steps = ws.steps;
     sa.diag = ws.diag;
     sa.nrec = (uint32_t)(g.nkeys + g.nbuckets);
-    HIP_TRY(hipMemsetAsync(ws.res, 0, ws.results_words(g.J) * 4, s));
     HIP_TRY(hipEventRecord(el[1], s));
     HIP_TRY(solve_layer(sa, s));
     HIP_TRY(hipEventRecord(el[2], s));
@@ -1115,7 +1122,6 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     // the host plans and launches it while back-substitution and the gather
     // of the bumped keys still run (the next layer's keys stay grouped by
     // structure in structure order)
-    HIP_TRY(hipMemsetAsync(ws.bump + g.nbuckets, 0, 4, s));
     HIP_TRY(scan_exclusive(ws.bump, g.nbuckets + 1, ws.scan_tmp, s));
     HIP_TRY(struct_offsets(ws.bump, g, ws.soff, s));
     HIP_TRY(hipMemcpyAsync(ws.hres, ws.res, ws.results_words(g.J) * 4, hipMemcpyDeviceToHost, s));

@@ -41,6 +41,16 @@ SortPlan plan_sort(uint64_t nkeys, uint64_t nbuckets, uint32_t nstructs);
 // u32 words of counts2 a plan needs
 uint64_t sort_counts2_words(const SortPlan& sp);
 
+// Words that the launches after a sort need zeroed (the insertion's step
+// counter and failure flags, the bump-count scan's last entry, the final
+// layer's spill occupancy): the sort's level-3 kernel, which every sort ends
+// with, clears them, so no memset launch of their own sits on the build's
+// critical path. Unused entries have n = 0.
+struct SortClear {
+  uint32_t* p[2];
+  uint64_t n[2];
+};
+
 struct SortArgs {
   const uint64_t* keys;   // input keys (g.nkeys), structure j at g.key_off[j]
   const void* vals;       // input values or nullptr (filter fingerprints)
@@ -61,6 +71,7 @@ struct SortArgs {
   void* r2;               // the same, level 2 output
   Rec* out_rec;           // item stream (nkeys + nbuckets)
   uint32_t* bstart;       // B + 1 bucket start offsets
+  SortClear clear;        // zeroed by the last sort kernel
 };
 hipError_t sort_layer(const SortArgs& a, hipStream_t s);
 

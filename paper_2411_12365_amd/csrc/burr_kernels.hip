@@ -1057,7 +1057,8 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const void* __restrict__
                                                         const uint32_t* __restrict__ sstart,
                                                         Rec* __restrict__ items,
                                                         uint32_t* __restrict__ bstart,
-                                                        uint64_t fp_salt, uint32_t fp_bits) {
+                                                        uint64_t fp_salt, uint32_t fp_bits,
+                                                        SortClear cl) {
   __shared__ uint32_t maxoff[kSubBuckets];
   __shared__ uint32_t nzero[kSubBuckets];
   __shared__ uint32_t wsum[kL3Threads / 64 + 2];
@@ -1082,6 +1083,11 @@ __global__ __launch_bounds__(kL3Threads) void k_p3_sort(const void* __restrict__
     maxoff[i] = 0;
     nzero[i] = 0;
   }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+    for (uint64_t i = (uint64_t)sb * kL3Threads + threadIdx.x; i < cl.n[c];
+         i += (uint64_t)gridDim.x * kL3Threads)
+      cl.p[c][i] = 0;
   __syncthreads();
   // the block is assembled in LDS when it fits; then every record is read
   // once, into registers, and its rank inside its digit comes from the
@@ -1296,12 +1302,12 @@ hipError_t sort_layer_t(const SortArgs& a, bool fp_late, hipStream_t s) {
       (void)hipFuncSetAttribute((const void*)k_p3_sort<PACKED, 64>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3_lds_bytes(64));
       k_p3_sort<PACKED, 64><<<sp.nsub, kL3Threads, l3_lds_bytes(64), s>>>(
-          in, a.g, sp, starts, a.out_rec, a.bstart, a.fp_salt, fp_late ? a.g.r : 0u);
+          in, a.g, sp, starts, a.out_rec, a.bstart, a.fp_salt, fp_late ? a.g.r : 0u, a.clear);
     } else {
       (void)hipFuncSetAttribute((const void*)k_p3_sort<PACKED, 3>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3_lds_bytes(3));
       k_p3_sort<PACKED, 3><<<sp.nsub, kL3Threads, l3_lds_bytes(3), s>>>(
-          in, a.g, sp, starts, a.out_rec, a.bstart, a.fp_salt, fp_late ? a.g.r : 0u);
+          in, a.g, sp, starts, a.out_rec, a.bstart, a.fp_salt, fp_late ? a.g.r : 0u, a.clear);
     }
     return hipGetLastError();
   };
