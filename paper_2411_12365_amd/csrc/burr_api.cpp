@@ -10,13 +10,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <functional>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/burr.h"
@@ -96,6 +100,82 @@ void keep_pool_memory(int dev) {
   done[dev] = true;
 }
 
+// A few host threads for the per-structure loops of large batches (the
+// tables of hundreds of thousands of structures are planned, copied and
+// read back per layer, and a single core's memory bandwidth made that
+// milliseconds per layer). Created on first use and kept for the life of
+// the process: the threads are detached and the pool is never destroyed, so
+// no static destructor waits for them at exit.
+class Workers {
+ public:
+  static Workers& get() {
+    static Workers* w = new Workers();
+    return *w;
+  }
+  uint32_t size() const { return nthreads_ + 1; }
+  // fn(k) for every k in [0, n), on the workers and the calling thread; one
+  // job at a time (concurrent callers take turns). fn must not throw.
+  void run(uint32_t n, const std::function<void(uint32_t)>& fn) {
+    if (nthreads_ == 0 || n <= 1) {
+      for (uint32_t k = 0; k < n; ++k) fn(k);
+      return;
+    }
+    std::lock_guard<std::mutex> one(run_mu_);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      job_ = &fn;
+      njob_ = n;
+      next_.store(0);
+      ++gen_;
+    }
+    start_.notify_all();
+    for (uint32_t k; (k = next_.fetch_add(1)) < n;) fn(k);
+    // every task is claimed; wait for the workers still running one
+    std::unique_lock<std::mutex> lk(mu_);
+    done_.wait(lk, [&] { return busy_ == 0; });
+    job_ = nullptr;
+  }
+
+ private:
+  Workers() {
+    const unsigned hw = std::thread::hardware_concurrency();
+    nthreads_ = hw > 1 ? std::min(hw, 8u) - 1 : 0u;
+    for (uint32_t i = 0; i < nthreads_; ++i) std::thread([this] { loop(); }).detach();
+  }
+  void loop() {
+    uint64_t seen = 0;
+    std::unique_lock<std::mutex> lk(mu_);
+    for (;;) {
+      // a worker that wakes after its job ended (job_ reset) waits for the next
+      start_.wait(lk, [&] { return gen_ != seen && job_ != nullptr; });
+      seen = gen_;
+      const std::function<void(uint32_t)>* f = job_;
+      const uint32_t n = njob_;
+      ++busy_;
+      lk.unlock();
+      for (uint32_t k; (k = next_.fetch_add(1)) < n;) (*f)(k);
+      lk.lock();
+      if (--busy_ == 0) done_.notify_all();
+    }
+  }
+  std::mutex run_mu_, mu_;
+  std::condition_variable start_, done_;
+  const std::function<void(uint32_t)>* job_ = nullptr;  // guarded by mu_
+  uint32_t njob_ = 0, busy_ = 0;                         // guarded by mu_
+  uint64_t gen_ = 0;                                     // guarded by mu_
+  std::atomic<uint32_t> next_{0};
+  uint32_t nthreads_ = 0;
+};
+
+// Loops over at least this many structures run on the workers, in chunks
+// of at least kParallelChunk.
+constexpr size_t kParallelStructs = 32768;
+constexpr size_t kParallelChunk = 8192;
+size_t parallel_chunks(size_t n) {
+  if (n < kParallelStructs) return 1;
+  return std::min<size_t>(4 * Workers::get().size(), n / kParallelChunk);
+}
+
 // Host copy of a layer's per-structure table (see LayerGeom).
 struct Table {
   std::vector<uint64_t> key_off{0}, span, bucket_base{0}, range_base{0}, word_base{0},
@@ -111,7 +191,7 @@ struct Table {
     rbits.reserve(J);
   }
   // the whole table at once: geo(i, &n, &m, &R, &r) gives structure i's keys,
-  // slots, ranges and value bits
+  // slots, ranges and value bits (called from several threads for large J)
   template <class Geo>
   void fill(size_t J, Geo geo) {
     key_off.resize(J + 1);
@@ -123,36 +203,94 @@ struct Table {
     thr_base.resize(J + 1);
     rank_base.resize(J + 1);
     rbits.resize(J);
-    uint64_t ko = 0, bb = 0, rb = 0, wb = 0, cb = 0, tb = 0, kb = 0;
-    for (size_t i = 0; i < J; ++i) {
-      uint64_t n, m, R;
-      uint32_t r;
-      geo(i, &n, &m, &R, &r);
-      const uint64_t B = m / 64;
-      key_off[i] = ko;
-      span[i] = m - kWidth + 1;
-      bucket_base[i] = bb;
-      range_base[i] = rb;
-      word_base[i] = wb;
-      code_base[i] = cb;
-      thr_base[i] = tb;
-      rank_base[i] = kb;
-      rbits[i] = r;
-      ko += n;
-      bb += B;
-      rb += R;
-      wb += B * r;
-      cb += code_words(B);
-      tb += B;
-      kb += (code_words(B) + 7) / 8;
+    const size_t nch = parallel_chunks(J);
+    if (nch == 1) {  // one pass
+      uint64_t ko = 0, bb = 0, rb = 0, wb = 0, cb = 0, tb = 0, kb = 0;
+      for (size_t i = 0; i < J; ++i) {
+        uint64_t n, m, R;
+        uint32_t r;
+        geo(i, &n, &m, &R, &r);
+        const uint64_t B = m / 64;
+        key_off[i] = ko;
+        span[i] = m - kWidth + 1;
+        bucket_base[i] = bb;
+        range_base[i] = rb;
+        word_base[i] = wb;
+        code_base[i] = cb;
+        thr_base[i] = tb;
+        rank_base[i] = kb;
+        rbits[i] = r;
+        ko += n;
+        bb += B;
+        rb += R;
+        wb += B * r;
+        cb += code_words(B);
+        tb += B;
+        kb += (code_words(B) + 7) / 8;
+      }
+      key_off[J] = ko;
+      bucket_base[J] = bb;
+      range_base[J] = rb;
+      word_base[J] = wb;
+      code_base[J] = cb;
+      thr_base[J] = tb;
+      rank_base[J] = kb;
+      return;
     }
-    key_off[J] = ko;
-    bucket_base[J] = bb;
-    range_base[J] = rb;
-    word_base[J] = wb;
-    code_base[J] = cb;
-    thr_base[J] = tb;
-    rank_base[J] = kb;
+    // in chunks on the host workers: pass 1 stores every structure's own
+    // sizes and sums them per chunk, pass 2 turns them into running offsets
+    // (key_off, bucket_base, range_base, word_base, code_base, thr_base,
+    // rank_base)
+    uint64_t* const base[7] = {key_off.data(),  bucket_base.data(), range_base.data(),
+                               word_base.data(), code_base.data(),   thr_base.data(),
+                               rank_base.data()};
+    std::vector<uint64_t> csum(7 * (nch + 1), 0);
+    auto lo_of = [&](size_t c) { return J * c / nch; };
+    Workers::get().run((uint32_t)nch, [&](uint32_t c) {
+      uint64_t sn = 0, sB = 0, sR = 0, sW = 0, sC = 0, sK = 0;
+      uint64_t *const ko = key_off.data(), *const bb = bucket_base.data(),
+                      *const rb = range_base.data(), *const wb = word_base.data(),
+                      *const cb = code_base.data(), *const tb = thr_base.data(),
+                      *const kb = rank_base.data(), *const sp = span.data();
+      uint32_t* const rr = rbits.data();
+      for (size_t i = lo_of(c); i < lo_of(c + 1); ++i) {
+        uint64_t n, m, R;
+        uint32_t r;
+        geo(i, &n, &m, &R, &r);
+        const uint64_t B = m / 64, cw = code_words(B);
+        ko[i] = n;
+        bb[i] = B;
+        rb[i] = R;
+        wb[i] = B * r;
+        cb[i] = cw;
+        tb[i] = B;
+        kb[i] = (cw + 7) / 8;
+        sp[i] = m - kWidth + 1;
+        rr[i] = r;
+        sn += n;
+        sB += B;
+        sR += R;
+        sW += B * r;
+        sC += cw;
+        sK += (cw + 7) / 8;
+      }
+      const uint64_t sum[7] = {sn, sB, sR, sW, sC, sB, sK};
+      for (int k = 0; k < 7; ++k) csum[7 * (c + 1) + k] = sum[k];
+    });
+    for (size_t c = 1; c <= nch; ++c)  // chunk sums to chunk offsets
+      for (int k = 0; k < 7; ++k) csum[7 * c + k] += csum[7 * (c - 1) + k];
+    Workers::get().run((uint32_t)nch, [&](uint32_t c) {
+      for (int k = 0; k < 7; ++k) {
+        uint64_t run = csum[7 * c + k];
+        uint64_t* const a = base[k];
+        for (size_t i = lo_of(c); i < lo_of(c + 1); ++i) {
+          const uint64_t v = a[i];
+          a[i] = run;
+          run += v;
+        }
+      }
+    });
+    for (int k = 0; k < 7; ++k) base[k][J] = csum[7 * nch + k];
   }
   // next structure: n keys, m slots, R ranges (final layer: segments), r value bits
   void add(uint64_t n, uint64_t m, uint64_t R, uint32_t r) {
@@ -635,15 +773,34 @@ int upload_table(Workspace& ws, const Table& t, LayerGeom& g, hipStream_t s, int
   h[2 * (J + 1) - 1] = 0;
   h[8 * (J + 1) + J / 2] = 0;
   h[words - 1] = 0;
-  memcpy(h, t.key_off.data(), (J + 1) * 8);
-  memcpy(h + (J + 1), t.span.data(), J * 8);
-  memcpy(h + 2 * (J + 1), t.bucket_base.data(), (J + 1) * 8);
-  memcpy(h + 3 * (J + 1), t.range_base.data(), (J + 1) * 8);
-  memcpy(h + 4 * (J + 1), t.word_base.data(), (J + 1) * 8);
-  memcpy(h + 5 * (J + 1), t.code_base.data(), (J + 1) * 8);
-  memcpy(h + 6 * (J + 1), t.thr_base.data(), (J + 1) * 8);
-  memcpy(h + 7 * (J + 1), t.rank_base.data(), (J + 1) * 8);
-  memcpy(h + 8 * (J + 1), t.rbits.data(), J * 4);
+  struct Piece {
+    void* dst;
+    const void* src;
+    size_t bytes;
+  };
+  const Piece parts[9] = {
+      {h, t.key_off.data(), (J + 1) * 8},
+      {h + (J + 1), t.span.data(), J * 8},
+      {h + 2 * (J + 1), t.bucket_base.data(), (J + 1) * 8},
+      {h + 3 * (J + 1), t.range_base.data(), (J + 1) * 8},
+      {h + 4 * (J + 1), t.word_base.data(), (J + 1) * 8},
+      {h + 5 * (J + 1), t.code_base.data(), (J + 1) * 8},
+      {h + 6 * (J + 1), t.thr_base.data(), (J + 1) * 8},
+      {h + 7 * (J + 1), t.rank_base.data(), (J + 1) * 8},
+      {h + 8 * (J + 1), t.rbits.data(), J * 4},
+  };
+  // large tables: each array in pieces, copied by the host workers
+  const size_t nch = parallel_chunks(J);
+  if (nch == 1) {
+    for (const Piece& c : parts) memcpy(c.dst, c.src, c.bytes);
+  } else {
+    Workers::get().run((uint32_t)(9 * nch), [&](uint32_t k) {
+      const Piece& c = parts[k / nch];
+      const size_t i = k % nch, lo = c.bytes * i / nch / 8 * 8,
+                   hi = i + 1 == nch ? c.bytes : c.bytes * (i + 1) / nch / 8 * 8;
+      memcpy((char*)c.dst + lo, (const char*)c.src + lo, hi - lo);
+    });
+  }
   HIP_TRY(hipMemcpyAsync(tab, h, words * 8, hipMemcpyHostToDevice, s));
   g.key_off = tab;
   g.span = tab + (J + 1);
@@ -850,23 +1007,31 @@ struct WsLease {
   }
 };
 
-// Device bytes the tables of a batch are expected to need: layer 0 exactly,
-// deeper layers at the bump-rate bound, plus the final layer.
+// Device bytes the tables of a batch are expected to need, from its layer-0
+// table: layer 0 exactly (solution words, and at most one 2-bit code word per
+// 32 buckets plus one per structure), deeper layers at the bump-rate bound,
+// plus the final layer; 1+-bit thresholds add at most a byte per bucket, the
+// rank directory and a count; cut points half a word per range.
+uint64_t batch_table_estimate(const burr_params& p, const Table& t) {
+  const uint64_t J = t.J(), B = t.bucket_base.back();
+  uint64_t words = t.word_base.back() + B / 32 + J;
+  if (p.threshold_mode == 1) words += B / 8 + B / 1024 + 4 * J;
+  if (p.cut_strategy) words += t.range_base.back() / 2 + J;
+  return words * 8 * 116 / 100 + 4096ull * (p.layers + 2);
+}
+
+// The same from the members' sizes, for a batch that builds no BuRR layer
+// (no layers, or no keys).
 uint64_t batch_table_estimate(const burr_batch* b, const std::vector<uint64_t>& off) {
-  uint64_t words = 0;
+  Table t;
+  t.thr_mode = b->p.threshold_mode;
   const LayerPlanner planner(b->p);
-  for (size_t i = 0; i < b->members.size(); ++i) {
-    const uint64_t n = off[i + 1] - off[i];
-    if (!n) continue;
-    uint64_t m, R;
-    planner.plan(n, b->members[i].minbpt, &m, &R);
-    const uint64_t B = m / 64;
-    words += B * b->members[i].r + (B + 31) / 32;
-    // 1+-bit: thresholds (a byte per bucket at most), rank directory, count
-    if (b->p.threshold_mode == 1) words += B / 8 + (B + 63) / 64 / 16 + 3;
-    if (b->p.cut_strategy) words += R / 2 + 1;  // cut points
-  }
-  return words * 8 * 116 / 100 + 4096ull * (b->p.layers + 2);
+  t.fill(b->members.size(), [&](size_t i, uint64_t* n, uint64_t* m, uint64_t* R, uint32_t* r) {
+    *n = off[i + 1] - off[i];
+    *r = b->members[i].r;
+    planner.plan(*n, b->members[i].minbpt, m, R);
+  });
+  return batch_table_estimate(b->p, t);
 }
 
 // Host vectors of freed batches (layer tables, member lists, member
@@ -937,13 +1102,14 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     wsp = lease->ws;
   }
   Workspace& ws = *wsp;
-  if (!b->arena) {  // scratch builds bring the caller's table memory
-    b->arena_cap = batch_table_estimate(b, off);
-    HOST_LAP(hc, "estimate", 0u);
+  // the table arena (scratch builds bring the caller's table memory): sized
+  // from the layer-0 table once it is planned, below
+  auto make_arena = [&](uint64_t bytes) {
+    b->arena_cap = bytes;
     b->arena = (uint8_t*)b->alloc(b->arena_cap);
-    if (!b->arena) return set_error(BURR_E_NOMEM);
     b->table_bytes = b->arena_cap;
-  }
+    return b->arena != nullptr;
+  };
   // events: [0] start, 7 per layer, then the final layer's start and end
   hipEvent_t* const ev = ws.events(3 + 7 * (size_t)p.layers);
   if (!ev) return set_error(BURR_E_DEVICE);
@@ -1029,6 +1195,8 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
       *r = mb.r;
       planner.plan(*n, mb.minbpt, m, R);
     });
+    HOST_LAP(hc, "fill", li);
+    if (!b->arena && !make_arena(batch_table_estimate(p, t))) return set_error(BURR_E_NOMEM);
     LayerGeom g{};
     g.salt_s = mix64(p.seed ^ (2ull * li + 1ull));
     g.salt_c = mix64(p.seed ^ (2ull * li + 2ull));
@@ -1148,28 +1316,52 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
               (unsigned long long)st[2], (unsigned long long)st[3]);
     }
 #endif
-    for (uint32_t k = 0; k < g.J; ++k)
-      if (fails[k]) {
-        fprintf(stderr, "burr: internal error %u in the insertion kernel, layer %u\n", fails[k],
-                li);
+    LS.steps = steps;
+    // bump counts and the members that go on (in chunks on the host workers
+    // for large layers): pass 1 counts them per chunk, pass 2 lists them
+    const size_t NA = active.size();
+    LS.bumped.resize(NA);
+    const size_t nrc = parallel_chunks(NA);
+    std::vector<uint64_t> cnext(nrc + 1, 0), cfail(nrc, ~0ull);
+    auto rlo = [&](size_t c) { return NA * c / nrc; };
+    auto pass1 = [&](uint32_t c) {
+      uint64_t k = 0;
+      for (size_t a = rlo(c); a < rlo(c + 1); ++a) {
+        if (fails[a] && cfail[c] == ~0ull) cfail[c] = a;
+        const uint32_t nb = soff[a + 1] - soff[a];
+        LS.bumped[a] = nb;
+        b->members[active[a]].built = li + 1;
+        k += nb != 0;
+      }
+      cnext[c + 1] = k;
+    };
+    if (nrc == 1)
+      pass1(0);
+    else
+      Workers::get().run((uint32_t)nrc, pass1);
+    for (size_t c = 0; c < nrc; ++c)
+      if (cfail[c] != ~0ull) {
+        fprintf(stderr, "burr: internal error %u in the insertion kernel, layer %u\n",
+                fails[cfail[c]], li);
         print_diag(ws.diag);
         return set_error(BURR_E_DEVICE);
       }
-    LS.steps = steps;
-
-    next_active.clear();
-    next_n.clear();
-    LS.bumped.resize(active.size());
-    LS.ids.clear();
-    for (size_t a = 0; a < active.size(); ++a) {
-      const uint32_t nb = soff[a + 1] - soff[a];
-      LS.bumped[a] = nb;
-      b->members[active[a]].built = li + 1;
-      if (nb) {
-        next_active.push_back(active[a]);
-        next_n.push_back(nb);
-      }
-    }
+    for (size_t c = 1; c <= nrc; ++c) cnext[c] += cnext[c - 1];
+    next_active.resize(cnext[nrc]);
+    next_n.resize(cnext[nrc]);
+    auto pass2 = [&](uint32_t c) {
+      uint64_t k = cnext[c];
+      for (size_t a = rlo(c); a < rlo(c + 1); ++a)
+        if (LS.bumped[a]) {
+          next_active[k] = active[a];
+          next_n[k] = LS.bumped[a];
+          ++k;
+        }
+    };
+    if (nrc == 1)
+      pass2(0);
+    else
+      Workers::get().run((uint32_t)nrc, pass2);
     LS.ids.assign(active.begin(), active.end());
     LS.t = std::move(t);
     active.swap(next_active);
@@ -1194,6 +1386,7 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     HIP_TRY(hipMemcpyAsync(kk, cur_keys, fin_off.back() * 8, hipMemcpyDeviceToDevice, s));
     for (size_t a = 0; a < active.size(); ++a) b->members[active[a]].fin_keys = kk + fin_off[a];
   }
+  if (!b->arena && !make_arena(batch_table_estimate(b, off))) return set_error(BURR_E_NOMEM);
   // the final layer's table and rows go to a set of their own
   const int fset = kBurrSets;
   {  // the last BuRR layer's back-substitution overlaps the final layer
