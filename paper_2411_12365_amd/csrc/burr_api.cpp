@@ -546,6 +546,11 @@ struct Workspace {
   uint64_t cap_m[kRowSets] = {};
   hipStream_t side = nullptr;  // back-substitution (default priority, non-blocking)
   std::vector<hipEvent_t> evs;  // a build's timing and ordering events, kept for the next
+  // host lists of the members with keys in the current and the next layer
+  // and their key counts, kept for the next build (fresh allocations of
+  // that size cost page faults on every build)
+  std::vector<uint32_t> h_active, h_next_active;
+  std::vector<uint64_t> h_cur_n, h_next_n;
   // per-bucket codes of a BuRR layer, one buffer per row set: a layer's
   // codes are packed on the side stream before its back-substitution,
   // while the next layer's insertion writes the other buffer
@@ -1164,15 +1169,19 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   HIP_TRY(hipEventRecord(ev[0], s));
 
   // members with keys in the current layer, in key order, and their key counts
-  std::vector<uint32_t> active;
-  std::vector<uint64_t> cur_n;
+  std::vector<uint32_t>& active = ws.h_active;
+  std::vector<uint64_t>& cur_n = ws.h_cur_n;
+  std::vector<uint32_t>& next_active = ws.h_next_active;
+  std::vector<uint64_t>& next_n = ws.h_next_n;
+  active.clear();
+  cur_n.clear();
+  active.reserve(M);
+  cur_n.reserve(M);
   for (uint32_t i = 0; i < M; ++i)
     if (off[i + 1] > off[i]) {
       active.push_back(i);
       cur_n.push_back(off[i + 1] - off[i]);
     }
-  std::vector<uint32_t> next_active;  // reused across layers
-  std::vector<uint64_t> next_n;
   next_active.reserve(active.size());
   next_n.reserve(active.size());
   const uint64_t* cur_keys = keys;
