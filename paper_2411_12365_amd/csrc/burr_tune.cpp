@@ -65,9 +65,11 @@ double time_batch(const uint64_t* keys, const void* vals, const std::vector<uint
 // Tuning on a mix of structure sizes: coordinate descent over the classes,
 // starting from p->minbpt everywhere; a class takes another candidate if the
 // whole mixed batch builds more than 3 % faster with it, or if its tables are
-// smaller while it stays within 3 % of the fastest time seen and of the
-// untuned batch's time (space counts where time is a draw, as in the paper's
-// Fig. 4 trade-off; the 3 % margin is above the timing noise of the repeats).
+// smaller by at least the fraction of time it costs, while it stays within
+// 3 % of the fastest time seen and of the untuned batch's time (space counts
+// where time is a draw, as in the paper's Fig. 4 trade-off, but a slower
+// candidate has to save as large a share of space as it costs in time; the 3 %
+// margin is above the timing noise of the repeats).
 int tune_mix(const burr_params* p, uint32_t r, const uint64_t* sizes, uint64_t nsizes,
              const uint64_t* n_max, uint32_t nclasses, const uint32_t* candidates,
              uint32_t ncandidates, uint32_t reps, burr_tune_entry* out) {
@@ -110,7 +112,10 @@ int tune_mix(const burr_params* p, uint32_t r, const uint64_t* sizes, uint64_t n
       const double t = time_batch(in.keys, in.vals, off, rs, p, table, reps, &b2, &rc);
       if (rc != BURR_OK) return burr_set_error(rc);
       const bool faster = t < best_t * 0.97;
-      const bool smaller = b2 < best_bits && t <= fastest * 1.03 && t <= untuned * 1.03;
+      const double cost = (t - best_t) / best_t;            // time added (< 0: saved)
+      const double saved = (best_bits - b2) / best_bits;    // space saved
+      const bool smaller = saved > 0 && saved >= cost && t <= fastest * 1.03 &&
+                           t <= untuned * 1.03;
       if (faster || smaller) {
         best = candidates[k];
         best_t = t;
