@@ -1449,8 +1449,10 @@ __device__ inline void solve_diag(uint64_t* d, uint32_t code, uint64_t rho, uint
 // ---------------------------------------------------------------------------
 // Solve: one wave per range, the lanes insert a bucket's records together
 // ---------------------------------------------------------------------------
-// The range's rows live in a ring of 128 slots in LDS shared by the wave
-// (bucket q touches slots [64q, 64q+126]). A pass inserts a set of records of
+// The range's rows live in a window of 128 slots in LDS shared by the wave:
+// bucket q's slots [64q, 64q+126] sit at window slots [0, 126], and after
+// the bucket its first 64 slots are published and the upper half moves
+// down (it is bucket q+1's first half). A pass inserts a set of records of
 // the current bucket: lanes take records from the staged bucket, and every
 // lane repeats one elimination step against the ring - XOR with the row at
 // its leading slot and shift - until its row reduces to zero or reaches an
@@ -1597,13 +1599,13 @@ struct SolveStats {};
 // (row 0, value 0) a step leaves the lane's row, value and position
 // unchanged (its row keeps bit 0, so the shift is 0), and the state of lanes
 // that finished is not used again.
-// A lane's position is kept as the byte offset of its slot within the ring
-// (8 (i mod 128) for slot i), which addresses the slot's row and value; a
-// step advances it with one shift-add and one mask. Bucket q's rows lie in
-// slots [64 q, 64 q + 126], so a row ending in the other ring half than
-// bucket q's own has crossed into bucket q+1: when q is the range's last
-// bucket and there is no spill buffer (last_half set), claiming it would be
-// an error.
+// A lane's position is kept as the byte offset of its slot within the
+// window (8 (i - 64 q) for slot i), which addresses the slot's row and
+// value; a step advances it with one shift-add (with a wrapping ring it also
+// took a mask, one more instruction on every step's dependent chain). A row
+// ending in the window's upper half has crossed into bucket q+1: when q is
+// the range's last bucket and there is no spill buffer (last_half set),
+// claiming it would be an error.
 // With 64 lanes per range, r0, r1 and next are wave-uniform (scalar), so the
 // record hand-out costs no vector instructions once the records are taken.
 //
@@ -1635,12 +1637,12 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
       m |= G.ballot(R.c[h * 64 + k * LANES + G.lane] != 0) << (k * LANES);
     before[h] = m;
   }
-  // byte offset of a slot within the ring, opaque to the compiler: with a
-  // known mask it merges the steps' masked shift-adds into longer sums
-  uint32_t kMask;
-  asm("s_mov_b32 %0, %1" : "=s"(kMask) : "i"((kRing - 1) * 8));
+  // Bucket q's first slot is the ring's first (after each bucket the ring's
+  // upper half moves down), so a kept row's slot is at most 126 and a step
+  // needs no wrap-around. Lanes whose state is no longer used (finished, or
+  // a FAST pass about to stop) may walk past the ring: they only read, and
+  // LDS reads past the workgroup's allocation return 0.
   constexpr uint32_t kHalf = 64u * 8u;  // byte size of a ring half (rows)
-  const uint32_t base = (q & 1u) * kHalf;        // byte offset of bucket q's first slot
   bool active = false, conflict = false, err = false, hung = false, special = false;
   uint64_t c = 0;
   uint32_t v = 0, ib = 0;  // ib: byte offset of the lane's slot
@@ -1663,7 +1665,7 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
           c = row_of((uint64_t)r.x | ((uint64_t)r.y << 32), a.g);
         }
         v = r.z;
-        ib = ((r.w & 63u) << 3) + base;
+        ib = (r.w & 63u) << 3;
         active = true;
       }
       const uint32_t nfree = (uint32_t)__popcll(freem);
@@ -1703,7 +1705,10 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
       }
       c = cx >> (j & 63u);
       v = vx;
-      ib = (ib + (j << 3)) & kMask;
+      ib += j << 3;
+      // opaque to the compiler, which would otherwise sum the steps' shifts
+      // first and add them to the start (two dependent adds per step)
+      asm("" : "+v"(ib));
     }
     // the last step read an empty slot: the lane stayed on it (at byte offset off)
     const bool at_empty = active && row == 0;
@@ -1714,7 +1719,7 @@ __device__ inline uint32_t wave_pass(WaveRing<LANES>& R, const Grp<LANES>& G,
       }
     }
     if (at_empty) {
-      if (!FAST && last_half && ((off ^ base) & kHalf)) {
+      if (!FAST && last_half && off >= kHalf) {
         active = false;  // unreachable: a kept row crossing the range end
         err = true;
       } else {
@@ -1764,10 +1769,22 @@ __device__ inline void release_half(WaveRing<LANES>& R, const Grp<LANES>& G, uin
   if (G.lane == 0) *occw = word;
 }
 
+// Moves the ring's upper half to its lower half (after the lower half was
+// published) and clears the upper half. Within one wave LDS operations
+// complete in order, so the moves read the upper half before it is cleared
+// and write the lower half after release_half read it.
 template <int LANES>
-__device__ inline void clear_half(WaveRing<LANES>& R, const Grp<LANES>& G, uint32_t hb) {
+__device__ inline void shift_down(WaveRing<LANES>& R, const Grp<LANES>& G) {
 #pragma unroll
-  for (uint32_t k = 0; k < 64 / LANES; ++k) ring_clear(R, hb + k * LANES + G.lane);
+  for (uint32_t k = 0; k < 64 / LANES; ++k) {
+    const uint32_t t = k * LANES + G.lane;
+    uint64_t row;
+    uint32_t val;
+    ring_read(R, 64 + t, row, val);
+    R.c[t] = row;
+    R.v[t] = val;
+    ring_clear(R, 64 + t);
+  }
 }
 
 // 8 waves per SIMD: the kernel then fits 64 VGPRs (no spills), and the
@@ -1990,20 +2007,17 @@ __global__ __launch_bounds__(64, 8) void k_solve_wave(SolveArgs a) {
       a.bump[beta] = count - kept;
     }
     if (q + 1 < nq && !failed) {
-      // bucket q+1's upper slots reuse the ring half of bucket q's first 64
-      // slots, which no later bucket changes: publish its rows, clear them
-      const uint32_t hb = (q & 1u) * 64u;
-      release_half(R, G, hb, a.rowsC + beta * 64, a.rowsV + beta * 64, a.occ + beta);
-      clear_half(R, G, hb);
+      // bucket q's first 64 slots, which no later bucket changes: publish
+      // their rows; bucket q+1 starts at the ring's base
+      release_half(R, G, 0, a.rowsC + beta * 64, a.rowsV + beta * 64, a.occ + beta);
+      shift_down(R, G);
     }
   }
   if (nq && !failed) {
-    const uint32_t hl = ((nq - 1) & 1u) * 64u;
     const uint64_t beta = fb + nq - 1;
-    release_half(R, G, hl, a.rowsC + beta * 64, a.rowsV + beta * 64, a.occ + beta);
+    release_half(R, G, 0, a.rowsC + beta * 64, a.rowsV + beta * 64, a.occ + beta);
     if (a.spill_occ) {  // rows past the segment end (final layer)
-      release_half(R, G, 64u - hl, a.spillC + rho * 64, a.spillV + rho * 64,
-                   a.spill_occ + rho);
+      release_half(R, G, 64, a.spillC + rho * 64, a.spillV + rho * 64, a.spill_occ + rho);
     }
   }
   if (a.steps) {
