@@ -20,29 +20,35 @@
 namespace burr {
 
 // ---------------------------------------------------------------------------
-// Block-wide exclusive scan (wave scan with cross-lane shuffles + LDS totals)
+// Block-wide exclusive scan (DPP wave scan + LDS totals)
 // ---------------------------------------------------------------------------
+// Inclusive sum over a wave's 64 lanes with DPP moves, which read a
+// neighbour lane's register within the VALU instruction (no LDS crossbar
+// round trip as with __shfl_up): a Hillis-Steele scan inside each row of 16
+// lanes (row_shr 1, 2, 4, 8; lanes shifted past their row's start add 0),
+// then row 0's total into row 1 and row 2's into row 3 (row_bcast:15), and
+// rows 0-1's total into rows 2-3 (row_bcast:31). Every lane must be active.
+__device__ inline uint32_t wave_inclusive_sum(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
+}
+
 template <int NT>
 __device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t* wsum, uint32_t* total) {
   constexpr int NW = NT / 64;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wid = threadIdx.x >> 6;
-  uint32_t inc = x;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t y = __shfl_up(inc, d, 64);
-    if (lane >= (uint32_t)d) inc += y;
-  }
+  const uint32_t inc = wave_inclusive_sum(x);
   if (lane == 63) wsum[wid] = inc;
   __syncthreads();
   if (wid == 0) {
-    uint32_t w = lane < (uint32_t)NW ? wsum[lane] : 0u;
-    uint32_t wi = w;
-#pragma unroll
-    for (int d = 1; d < NW; d <<= 1) {
-      uint32_t y = __shfl_up(wi, d, 64);
-      if (lane >= (uint32_t)d) wi += y;
-    }
+    const uint32_t w = lane < (uint32_t)NW ? wsum[lane] : 0u;
+    const uint32_t wi = wave_inclusive_sum(w);
     if (lane < (uint32_t)NW) wsum[lane] = wi - w;
     if (lane == (uint32_t)NW - 1 && total) *total = wi;
   }
