@@ -224,9 +224,9 @@ hipError_t scan_exclusive(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t s
 // level 3: one workgroup per sub-bin (64 buckets) orders its records by
 //          (bucket, chunk) in LDS and writes headers and records as one block
 // Intermediate records (16 B): key, value | slot within the bin << 32.
-// 4 records per thread: level 1 takes 82 VGPRs (5 waves per SIMD; with its
-// loads issued together it is faster than at 70 VGPRs and 7 waves, and held
-// to 80 VGPRs it is slower), level 2 takes 48 (8 waves per SIMD). A level
+// 4 records per thread: level 1 takes 46 VGPRs for a single structure and
+// 66-68 for a batch (8 and 7 waves per SIMD), level 2 takes 38 (8 waves per
+// SIMD). A level
 // with more than kBigTileDigits digits has tiles of twice as many records,
 // so that a tile still gives each digit a run of about 16 or more: level 1
 // with twice the threads (at 8 records per thread it would take over 128
@@ -2887,6 +2887,10 @@ hipError_t query(const QueryPlan& plan, const uint64_t* keys, uint64_t n, void* 
     k_query<uint8_t, 8, false><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
   else if (out_bytes == 1 && plan.r == 1)
     k_query<uint8_t, 1, false><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
+  else if (out_bytes == 1 && plan.r == 16 && al)  // membership answers of a 16-bit filter
+    k_query<uint8_t, 16, true><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
+  else if (out_bytes == 1 && plan.r == 16)
+    k_query<uint8_t, 16, false><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
   else if (out_bytes == 1)
     k_query<uint8_t, 0, false><<<blocks, 256, 0, s>>>(plan, keys, n, (uint8_t*)out, contains, fp_salt);
   else if (out_bytes == 2 && plan.r == 16 && al)

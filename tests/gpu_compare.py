@@ -36,5 +36,12 @@ def check_handle(h, ref, keys, filt=False, n_queries=20000, layer_keys=True):
     got = h.query(to_dev(q)).cpu().numpy()
     assert np.array_equal(got, ref.query(q))
     if filt:
+        # membership answers: the stored value equals the key's fingerprint,
+        # for members (always) and non-members (false positives) alike
+        import oracle
         cont = h.contains(to_dev(q)).cpu().numpy()
         assert cont[: min(n, n_queries)].all()
+        want = ref.query(q)
+        fps = np.array([oracle.fingerprint(int(k), ref.r, ref.params.seed) for k in q],
+                       dtype=want.dtype)
+        assert np.array_equal(cont.astype(bool), want == fps)
