@@ -2202,8 +2202,11 @@ constexpr uint32_t kMergeWin = 1024;  // slots of the right group staged in LDS
 // 0). Rows whose walk leaves the window are finished one by one in global
 // memory afterwards.
 __global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
-  __shared__ uint64_t wc[kMergeWin + 1];  // + a zero slot for walks past the window
-  __shared__ uint32_t wv[kMergeWin + 1];
+  // + 64 zero slots after the window: a walk that leaves the window stops at
+  // the first of them (a row keeps bit 0, so a step at an empty slot does
+  // not move), and the steps need no clamp
+  __shared__ uint64_t wc[kMergeWin + 64];
+  __shared__ uint32_t wv[kMergeWin + 64];
   __shared__ uint64_t oc_[64];
   __shared__ uint32_t ov_[64], oi_[64];
   const LayerGeom g = a.g;
@@ -2254,10 +2257,8 @@ __global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
       wc[64 * blk + lane] = occd ? lrow[blk] : 0ull;
       wv[64 * blk + lane] = occd ? lval[blk] : 0u;  // empty slots: row 0, value 0
     }
-  if (lane == 0) {
-    wc[kMergeWin] = 0;
-    wv[kMergeWin] = 0;
-  }
+  wc[64 * nblk + lane] = 0;  // the 64 slots after the window
+  wv[64 * nblk + lane] = 0;
   __syncthreads();
   // parallel phase
   const uint64_t pend = a.spill_occ[lastL];
@@ -2273,14 +2274,15 @@ __global__ __launch_bounds__(64) void k_merge(FinalArgs a, uint32_t G) {
       break;
     }
     // unmasked steps as in the insertion kernel; a walk that leaves the
-    // window reads the zero slot past it from then on, which holds it in place
+    // window stops on the zero slots after it (lanes whose row reduced to
+    // zero may walk on past them: they only read, and their state is not
+    // used again)
     bool conflict = false;
     uint64_t row = 0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const uint32_t ii = i < win ? i : kMergeWin;
-      row = wc[ii];
-      const uint32_t rv = wv[ii];
+      row = wc[i];
+      const uint32_t rv = wv[i];
       const uint64_t cx = c ^ row;
       const uint32_t vx = v ^ rv;
       const bool nz = cx != 0;  // else redundant (vx = 0) or inconsistent
