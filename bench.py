@@ -364,24 +364,31 @@ def run_batched(args, dev):
     t_tune = time.perf_counter() - t0
     print(f"# batched: {count} structures, {N} keys", file=sys.stderr, flush=True)
 
-    def timed(build):
-        build().free()
-        times = []
+    def timed(builds):
+        # the builds alternate, so that no order or warm-up effect favours one
+        for build in builds:
+            build().free()
+        times = [[] for _ in builds]
+        last = [None] * len(builds)
         for k in range(args.batch_steps):
-            t0 = time.perf_counter()
-            b = build()
-            times.append(time.perf_counter() - t0)
-            if k + 1 < args.batch_steps:
-                b.free()
-        return b, np.array(times) * 1e3
+            for j, build in enumerate(builds):
+                t0 = time.perf_counter()
+                bb = build()
+                times[j].append(time.perf_counter() - t0)
+                if k + 1 < args.batch_steps:
+                    bb.free()
+                else:
+                    last[j] = bb
+        return last, [np.array(t) * 1e3 for t in times]
 
     def table_bits(bb):  # bits per key of every member's table
         return 8 * sum(bb.member(i).stats()["table_bytes"] for i in range(count)) / N
 
-    b, ms_default = timed(lambda: burr.build_batch(keys, vals, offs, rs, params))
-    bits_default = table_bits(b)
-    b.free()
-    b, ms = timed(lambda: burr.build_batch_tuned(keys, vals, offs, rs, table, params))
+    (b_default, b), (ms_default, ms) = timed(
+        [lambda: burr.build_batch(keys, vals, offs, rs, params),
+         lambda: burr.build_batch_tuned(keys, vals, offs, rs, table, params)])
+    bits_default = table_bits(b_default)
+    b_default.free()
     bits_tuned = table_bits(b)
     # spot check: members of sampled structures retrieve their values
     ok = True
