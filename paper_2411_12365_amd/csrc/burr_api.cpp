@@ -551,6 +551,7 @@ struct Workspace {
   // that size cost page faults on every build)
   std::vector<uint32_t> h_active, h_next_active;
   std::vector<uint64_t> h_cur_n, h_next_n;
+  std::vector<uint64_t> h_rm;  // per member: minbpt << 32 | value bits (compact for planning)
   // per-bucket codes of a BuRR layer, one buffer per row set: a layer's
   // codes are packed on the side stream before its back-substitution,
   // while the next layer's insertion writes the other buffer
@@ -1095,8 +1096,6 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   hipStream_t s = b->stream;
   const uint64_t fp_salt = mix64(~p.seed);
   const uint32_t M = (uint32_t)b->members.size();
-  uint32_t rmax = 1;
-  for (const Member& mb : b->members) rmax = std::max(rmax, mb.r);
   // the workspace: the caller's (scratch builds), else one from the cache
   // or made for this build
   std::unique_ptr<WsLease> lease;
@@ -1107,6 +1106,15 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     wsp = lease->ws;
   }
   Workspace& ws = *wsp;
+  // the members' value bits and range split, compact: the layer tables are
+  // planned from them (the Member records are 72 bytes apart)
+  uint32_t rmax = 1;
+  ws.h_rm.resize(M);
+  for (uint32_t i = 0; i < M; ++i) {
+    const Member& mb = b->members[i];
+    rmax = std::max(rmax, mb.r);
+    ws.h_rm[i] = (uint64_t)mb.minbpt << 32 | mb.r;
+  }
   // the table arena (scratch builds bring the caller's table memory): sized
   // from the layer-0 table once it is planned, below
   auto make_arena = [&](uint64_t bytes) {
@@ -1173,15 +1181,21 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
   std::vector<uint64_t>& cur_n = ws.h_cur_n;
   std::vector<uint32_t>& next_active = ws.h_next_active;
   std::vector<uint64_t>& next_n = ws.h_next_n;
-  active.clear();
-  cur_n.clear();
-  active.reserve(M);
-  cur_n.reserve(M);
-  for (uint32_t i = 0; i < M; ++i)
-    if (off[i + 1] > off[i]) {
-      active.push_back(i);
-      cur_n.push_back(off[i + 1] - off[i]);
+  {  // stored by index (push_back reloads the vector's end on every element)
+    active.resize(M);
+    cur_n.resize(M);
+    uint32_t* const pa = active.data();
+    uint64_t* const pn = cur_n.data();
+    uint32_t k = 0;
+    for (uint32_t i = 0; i < M; ++i) {
+      const uint64_t n = off[i + 1] - off[i];
+      pa[k] = i;
+      pn[k] = n;
+      k += n != 0 ? 1u : 0u;
     }
+    active.resize(k);
+    cur_n.resize(k);
+  }
   next_active.reserve(active.size());
   next_n.reserve(active.size());
   const uint64_t* cur_keys = keys;
@@ -1198,11 +1212,12 @@ int build_batch(burr_batch* b, const uint64_t* keys, const void* values,
     take_host(LS, active.size());
     Table t = std::move(LS.t);
     t.thr_mode = p.threshold_mode;
+    const uint64_t* const rm = ws.h_rm.data();
     t.fill(active.size(), [&](size_t a, uint64_t* n, uint64_t* m, uint64_t* R, uint32_t* r) {
-      const Member& mb = b->members[active[a]];
+      const uint64_t x = rm[active[a]];
       *n = cur_n[a];
-      *r = mb.r;
-      planner.plan(*n, mb.minbpt, m, R);
+      *r = (uint32_t)x;
+      planner.plan(*n, (uint32_t)(x >> 32), m, R);
     });
     HOST_LAP(hc, "fill", li);
     if (!b->arena && !make_arena(batch_table_estimate(p, t))) return set_error(BURR_E_NOMEM);
