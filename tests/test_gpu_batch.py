@@ -125,6 +125,43 @@ def test_member_handles_do_not_free_the_batch():
     b.free()
 
 
+def test_tuned_batch_long_table():
+    # more than 32 size classes: the class lookup takes its binary search
+    burr = _burr()
+    table = [dict(n_max=150 * (k + 1), minbpt=2 + (k % 7)) for k in range(40)]
+    sizes = [1, 149, 150, 151, 300, 301, 2999, 3000, 4500, 5999, 6000, 6001, 9000]
+    rs = [8, 3, 8, 1, 8, 2, 8, 8, 5, 16, 3, 8, 2]
+    kw = dict(ranges=1 << 10)
+    keys, vals, offs = _make(sizes, rs, 71)
+    print(f"[batch] tuned, {len(table)} classes", flush=True)
+    b = burr.build_batch_tuned(to_dev(keys), to_dev(vals), offs, rs, table,
+                               burr.Params(flags=burr.BURR_FLAG_KEEP_LAYER_KEYS, **kw))
+    for i, n in enumerate(sizes):
+        cls = next((e for e in table if e["n_max"] >= n), table[-1])
+        mk, ref = _member_ref(keys, vals, offs, rs, i, dict(kw, minbpt=cls["minbpt"]))
+        check_handle(b.member(i), ref, mk, n_queries=500)
+    b.free()
+
+
+def test_many_small_structures_every_member():
+    # 40,000 structures: the host plans a layer of 32,768 or more structures
+    # in chunks on its worker threads (table, upload copies, bump counts);
+    # every member's export must equal the oracle's
+    burr = _burr()
+    rng = np.random.default_rng(81)
+    count = 40_000
+    sizes = np.clip(np.rint(rng.lognormal(np.log(60), 0.8, count)), 1, 400).astype(np.int64)
+    rs = [int(x) for x in rng.integers(1, 9, size=count)]
+    kw = dict(ranges=1 << 10)
+    keys, vals, offs = _make(sizes, rs, 83)
+    print(f"[batch] {count} structures, {int(offs[-1])} keys", flush=True)
+    b = burr.build_batch(to_dev(keys), to_dev(vals), offs, rs, burr.Params(**kw))
+    for i in range(count):
+        mk, ref = _member_ref(keys, vals, offs, rs, i, kw)
+        assert b.member(i).export() == ref.export(), f"member {i}"
+    b.free()
+
+
 def test_tuned_batch_uses_each_members_size_class():
     # members of different size classes get different minimum buckets per
     # range; each must equal the oracle's structure built with that value
