@@ -139,8 +139,17 @@ class Workers {
  private:
   Workers() {
     const unsigned hw = std::thread::hardware_concurrency();
-    nthreads_ = hw > 1 ? std::min(hw, 8u) - 1 : 0u;
-    for (uint32_t i = 0; i < nthreads_; ++i) std::thread([this] { loop(); }).detach();
+    const uint32_t want = hw > 1 ? std::min(hw, 8u) - 1 : 0u;
+    // a thread that cannot be created leaves the pool smaller (the caller
+    // runs every task itself when there is none)
+    for (uint32_t i = 0; i < want; ++i) {
+      try {
+        std::thread([this] { loop(); }).detach();
+      } catch (...) {
+        break;
+      }
+      ++nthreads_;
+    }
   }
   void loop() {
     uint64_t seen = 0;
